@@ -1,0 +1,151 @@
+/*
+ * nuance_mi355x.h -- C ABI of the MI355X (gfx950) transit-search hot path.
+ *
+ * The method is nuance (Garcia et al., arXiv:2402.06835): a linear search
+ * that fits, at every trial epoch and duration, a box transit plus a linear
+ * trend by generalised least squares under a fixed Gaussian-process
+ * covariance (Section 2.2, Eqs. 5-6), followed by a periodic search that
+ * combines those single events over a period x phase grid with a common
+ * depth (Section 2.3, Eq. 8 with the estimates of Eq. B4) and reports the
+ * periodogram Q(P) = depth/sigma at the best phase and duration (Section
+ * 2.4, Eq. 9).
+ *
+ * Conventions for every entry point:
+ *  - No C++ exception crosses this boundary. Every call returns a nu_status;
+ *    nu_ctx_last_error() gives a message for the last non-OK status.
+ *  - Pointers named *_host are host memory; every other array pointer is
+ *    DEVICE memory on the context's device, owned by the caller, and must
+ *    stay valid until the enqueued work has finished.
+ *  - All device work is enqueued on the context's stream (the caller's, e.g.
+ *    torch.cuda.current_stream().cuda_stream). Only nu_gp_factor synchronises
+ *    that stream (once, to report a non-positive-definite covariance).
+ *  - Argument errors are detected on the host before any launch and return
+ *    NU_ERR_ARG with nothing enqueued.
+ *  - One context per host thread; calls that share a context are not
+ *    thread-safe.
+ */
+#ifndef NUANCE_MI355X_H
+#define NUANCE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NU_OK = 0,
+  NU_ERR_ARG = 1,         /* invalid argument; nothing was enqueued */
+  NU_ERR_NOT_PD = 2,      /* covariance not positive definite (pivot reported) */
+  NU_ERR_OOM = 3,         /* device allocation failed */
+  NU_ERR_DEVICE = 4,      /* a HIP call or kernel launch failed */
+  NU_ERR_UNSUPPORTED = 5  /* valid request this build does not implement */
+} nu_status;
+
+/* Arithmetic of the bulk whitening solve of the linear search. The Cholesky
+ * factor, the trend fit, the cell normal equations and the periodic search
+ * are FP64 in every mode. */
+typedef enum {
+  NU_FP64 = 0,
+  NU_FP32_REFINE = 1,
+  NU_BF16X3_REFINE = 2
+} nu_precision;
+
+/* SHO covariance of Appendix A plus white noise on the diagonal (Section 1.1):
+ *   k(tau) = amp^2 exp(-omega tau / 2Q) * { 1 + omega tau                 (Q = 1/2)
+ *                                           cosh(f x) + sinh(f x) / f     (Q < 1/2)
+ *                                           cos(g x) + sin(g x) / g       (Q > 1/2) }
+ * with x = omega tau / 2Q, f = sqrt(1 - 4Q^2), g = sqrt(4Q^2 - 1), and
+ *   K[n][m] = k(|t_n - t_m|) + sigma_w^2 delta_nm.
+ * Units: omega in radians per time unit of t. Requires amp >= 0, omega > 0,
+ * q > 0, sigma_w >= 0, all finite. */
+typedef struct {
+  double amp;
+  double omega;
+  double q;
+  double sigma_w;
+} nu_sho;
+
+typedef struct nu_ctx nu_ctx;
+typedef struct nu_factor nu_factor;
+
+/* Context: device, stream, growable workspace, optional kernel timing.
+ * stream == NULL means the device's null stream. */
+nu_status nu_ctx_create(int device, void* stream, nu_ctx** out);
+void nu_ctx_destroy(nu_ctx* ctx);
+nu_status nu_ctx_set_stream(nu_ctx* ctx, void* stream);
+const char* nu_ctx_last_error(const nu_ctx* ctx);
+
+/* Kernel timing with HIP events recorded on the context's stream around
+ * every launch of the library's kernels, accumulated per kernel name.
+ * work_units is the algorithmic work the library attributes to the
+ * launches (flops for the dense kernels, bytes for the fold). Reading the
+ * entries synchronises the stream. */
+nu_status nu_ctx_enable_timing(nu_ctx* ctx, int enable);
+nu_status nu_ctx_timing_reset(nu_ctx* ctx);
+int nu_ctx_timing_count(nu_ctx* ctx);
+nu_status nu_ctx_timing_entry(nu_ctx* ctx, int index, const char** name_host, int64_t* launches_host,
+                              double* total_ms_host, double* work_units_host);
+
+/* (1) GP factor (Appendix A covariance; Eq. 5's ln|Sigma|).
+ * t: device, n doubles, strictly increasing. Builds K on the device, factors
+ * it as K = L L^T in FP64 (blocked, right-looking), and returns a factor
+ * object owning L and the workspace of the later solves (about 2 n^2 + n^2/4
+ * doubles of device memory, n rounded up to 128). Synchronises the stream
+ * once. On NU_ERR_NOT_PD, *fail_pivot_host is the first failing pivot and
+ * no factor is returned. logdet_host (ln|K|) and fail_pivot_host may be NULL. */
+nu_status nu_gp_factor(nu_ctx* ctx, const double* t, int64_t n, const nu_sho* theta, nu_factor** out,
+                       double* logdet_host, int64_t* fail_pivot_host);
+void nu_factor_destroy(nu_factor* factor);
+int64_t nu_factor_n(const nu_factor* factor);
+
+/* (2) Linear search (Section 2.2, Eqs. 5-6).
+ * f: device, n doubles (n = nu_factor_n). A: device, n x m1 column-major
+ * (column c at A + c*n), 0 <= m1 <= 7; may be NULL when m1 == 0.
+ * lattice: device, n int64, lattice[0] == 0 and strictly increasing: sample
+ * s sits at epoch slot lattice[s] (time t_first + lattice[s] * dt).
+ * n_epochs == lattice[n-1] + 1 epoch slots are searched. dur_samples_host:
+ * host, n_d box lengths in slots, 1 <= value <= 1024, 1 <= n_d <= 16.
+ * The box of cell (j, i) is -1 on samples whose slot lies in
+ * [i - floor(d_j/2), i - floor(d_j/2) + d_j) and 0 elsewhere.
+ * Outputs (device, row-major [n_d][n_epochs]): depth (GLS depth of the box),
+ * var (its variance, the MM element of (X^T K^-1 X)^-1), dll (log-likelihood
+ * gain over the trend-only fit, 0.5 depth^2 / var), valid (1/0). Invalid
+ * cells (empty box, or box collinear with the trend): depth = 0,
+ * var = +inf, dll = 0, valid = 0.
+ * null_out: device, 3 doubles or NULL: ln L_0 (Eq. 5 of the trend-only
+ * fit), chi2_0 and ln|K|.
+ * prec selects the arithmetic of the bulk whitening solve. */
+nu_status nu_linear_search(nu_ctx* ctx, nu_factor* factor, const double* f, const double* A, int m1,
+                           const int64_t* lattice, int64_t n_epochs, const int32_t* dur_samples_host, int n_d,
+                           nu_precision prec, double* depth, double* var, double* dll, uint8_t* valid,
+                           double* null_out);
+
+/* (3) Periodic search (Sections 2.3-2.4, Eqs. 8, 9, B4).
+ * depth/var/dll/valid: device, [n_d][n_epochs] as produced by (2).
+ * periods: device, n_p doubles in the time unit of dt (dt > 0).
+ * For period P, p = P / dt; phases m = 0 .. ceil(p) - 1 (slot units from the
+ * first sample); events k >= 0 at slot position m + k p, linearly
+ * interpolated between slots floor and floor+1 (a single slot when k p is
+ * an integer); an event needs its slot(s) inside the grid and valid.
+ * Events are combined per (m, j) with Eq. B4's depth and sigma^2, and
+ *   lnP = sum dll_k - 1/2 sum [ s (ln var_k - ln(sigma^2 + var_k))
+ *                              + (depth_k - depth)^2 / (var_k + sigma^2) ]
+ * with s = log_term_sign (+1: the sign printed in Eq. 8; -1: the sign of the
+ * derivation in Appendix B). The first maximum over (m outer, j inner)
+ * gives per period: q_snr = depth/sigma, best_phase m, best_dur j,
+ * best_depth, best_sigma, best_lnp. A period without any event has
+ * q_snr = 0, best_phase = best_dur = -1, best_lnp = -inf.
+ * best_period_index: device, 1 int64 or NULL: the first period of largest
+ * q_snr (-1 if n_p == 0 is impossible; n_p >= 1 is required). */
+nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var, const double* dll,
+                             const uint8_t* valid, int n_d, int64_t n_epochs, double dt, const double* periods,
+                             int64_t n_p, int log_term_sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,
+                             double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period_index);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUANCE_MI355X_H */

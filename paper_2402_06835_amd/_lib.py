@@ -1,0 +1,70 @@
+"""ctypes declarations of the C ABI in include/nuance_mi355x.h.
+
+The shared library is built in-tree by ``paper_2402_06835_amd.build``. There
+is no fallback: if the library is missing or fails to load, every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnuance_mi355x.so")
+
+c_int, c_int32, c_int64, c_double, c_void_p, c_char_p = (
+    ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_char_p)
+P = ctypes.POINTER
+
+NU_OK, NU_ERR_ARG, NU_ERR_NOT_PD, NU_ERR_OOM, NU_ERR_DEVICE, NU_ERR_UNSUPPORTED = range(6)
+STATUS_NAMES = {0: "NU_OK", 1: "NU_ERR_ARG", 2: "NU_ERR_NOT_PD", 3: "NU_ERR_OOM", 4: "NU_ERR_DEVICE",
+                5: "NU_ERR_UNSUPPORTED"}
+PRECISIONS = {"fp64": 0, "fp32_refine": 1, "bf16x3_refine": 2}
+
+
+class NuSho(ctypes.Structure):
+    _fields_ = [("amp", c_double), ("omega", c_double), ("q", c_double), ("sigma_w", c_double)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "nu_ctx_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
+    "nu_ctx_destroy": (None, [c_void_p]),
+    "nu_ctx_set_stream": (c_int, [c_void_p, c_void_p]),
+    "nu_ctx_last_error": (c_char_p, [c_void_p]),
+    "nu_ctx_enable_timing": (c_int, [c_void_p, c_int]),
+    "nu_ctx_timing_reset": (c_int, [c_void_p]),
+    "nu_ctx_timing_count": (c_int, [c_void_p]),
+    "nu_ctx_timing_entry": (c_int, [c_void_p, c_int, P(c_char_p), P(c_int64), P(c_double), P(c_double)]),
+    "nu_gp_factor": (c_int, [c_void_p, c_void_p, c_int64, P(NuSho), P(c_void_p), P(c_double), P(c_int64)]),
+    "nu_factor_destroy": (None, [c_void_p]),
+    "nu_factor_n": (c_int64, [c_void_p]),
+    "nu_linear_search": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int64, P(c_int32), c_int,
+                                 c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "nu_periodic_search": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int64, c_double,
+                                   c_void_p, c_int64, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p]),
+}
+
+_LIB = None
+
+
+class NuanceError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library (once). Raises if it is not built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run python -m paper_2402_06835_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB

@@ -1,0 +1,287 @@
+"""Python binding of the transit-search library (argument marshalling only).
+
+Functional layer with the C ABI's names (``Context``, ``gp_factor``,
+``linear_search``, ``periodic_search``) over torch device tensors, plus a
+``Nuance`` object shaped like the paper's interface (Section 2.5):
+``Nuance(time, flux, gp=..., X=...)``, ``.linear_search(t0s, Ds)``,
+``.periodic_search(periods)`` with ``.best`` and ``.Q_snr``.
+
+Every step of the search runs in the HIP library; this module only checks
+and converts arguments, allocates outputs with torch and passes pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from ._lib import NU_OK, PRECISIONS, NuanceError, NuSho, lib
+
+
+def _check(ctx_ptr, status: int):
+    if status != NU_OK:
+        msg = lib().nu_ctx_last_error(ctx_ptr)
+        raise NuanceError(status, msg.decode() if msg else "")
+
+
+def _dev_tensor(x, dtype, device) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        t = x.to(device=device, dtype=dtype)
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=device)
+    return t.contiguous()
+
+
+@dataclass
+class SHO:
+    """SHO covariance (Appendix A) + white noise: amp = sigma, omega, Q, sigma_w."""
+
+    amp: float
+    omega: float
+    q: float
+    sigma_w: float = 0.0
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "SHO":
+        return cls(float(d["amp"]), float(d["omega"]), float(d["q"]), float(d["sigma_w"]))
+
+    def c(self) -> NuSho:
+        return NuSho(self.amp, self.omega, self.q, self.sigma_w)
+
+
+class Context:
+    """Library context bound to one device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the transit-search library runs on the device only")
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        p = ctypes.c_void_p()
+        st = lib().nu_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(p))
+        if st != NU_OK:
+            raise NuanceError(st, "nu_ctx_create failed")
+        self.ptr = p
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().nu_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def enable_timing(self, on: bool = True):
+        _check(self.ptr, lib().nu_ctx_enable_timing(self.ptr, int(on)))
+
+    def reset_timing(self):
+        _check(self.ptr, lib().nu_ctx_timing_reset(self.ptr))
+
+    def timings(self) -> dict:
+        """{kernel name: {"launches", "ms", "work"}} accumulated since the last reset."""
+        out = {}
+        n = lib().nu_ctx_timing_count(self.ptr)
+        for i in range(n):
+            name = ctypes.c_char_p()
+            launches = ctypes.c_int64()
+            ms = ctypes.c_double()
+            work = ctypes.c_double()
+            _check(self.ptr, lib().nu_ctx_timing_entry(self.ptr, i, ctypes.byref(name), ctypes.byref(launches),
+                                                       ctypes.byref(ms), ctypes.byref(work)))
+            out[name.value.decode()] = {"launches": launches.value, "ms": ms.value, "work": work.value}
+        return out
+
+
+class Factor:
+    """Device Cholesky factor of K (and, once a search ran, its inverse)."""
+
+    def __init__(self, ptr, n: int, logdet: float):
+        self.ptr = ptr
+        self.n = n
+        self.logdet = logdet
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().nu_factor_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gp_factor(ctx: Context, t, theta) -> Factor:
+    """K = k_SHO + sigma_w^2 I built and factored on the device (one stream sync)."""
+    t_dev = _dev_tensor(t, torch.float64, ctx.device)
+    sho = theta if isinstance(theta, SHO) else SHO.from_dict(theta)
+    p = ctypes.c_void_p()
+    logdet = ctypes.c_double()
+    pivot = ctypes.c_int64(-1)
+    c = sho.c()
+    st = lib().nu_gp_factor(ctx.ptr, ctypes.c_void_p(t_dev.data_ptr()), t_dev.numel(), ctypes.byref(c),
+                            ctypes.byref(p), ctypes.byref(logdet), ctypes.byref(pivot))
+    if st != NU_OK:
+        msg = lib().nu_ctx_last_error(ctx.ptr).decode()
+        err = NuanceError(st, msg)
+        err.pivot = pivot.value
+        raise err
+    return Factor(p, t_dev.numel(), logdet.value)
+
+
+def linear_search(ctx: Context, factor: Factor, f, A, lattice, n_epochs: int, durations,
+                  precision: str = "fp64") -> dict:
+    """Single-event GLS fits over every (duration, epoch slot) cell.
+
+    f: (N,), A: (N, m1) trend design or None, lattice: (N,) int64 slot of each
+    sample (lattice[0] == 0, strictly increasing), durations: box lengths in
+    slots. Returns device tensors depth, var, dll (float64) and valid (uint8),
+    shaped (n_d, n_epochs), and ``null`` = [ln L_0, chi2_0, ln|K|].
+    """
+    dev = ctx.device
+    f_d = _dev_tensor(f, torch.float64, dev)
+    n = f_d.numel()
+    if A is None:
+        m1 = 0
+        A_d = None
+    else:
+        A_t = A if isinstance(A, torch.Tensor) else torch.as_tensor(np.asarray(A, dtype=np.float64))
+        if A_t.ndim == 1:
+            A_t = A_t[:, None]
+        if A_t.shape[0] != n:
+            raise ValueError("A must be (N, m1)")
+        m1 = int(A_t.shape[1])
+        A_d = A_t.to(device=dev, dtype=torch.float64).t().contiguous()  # column-major N x m1
+    lat = _dev_tensor(lattice, torch.int64, dev)
+    if lat.numel() != n:
+        raise ValueError("lattice must have N entries")
+    durs = np.ascontiguousarray(np.asarray(durations, dtype=np.int32))
+    n_d = int(durs.size)
+    shape = (n_d, int(n_epochs))
+    depth = torch.empty(shape, dtype=torch.float64, device=dev)
+    var = torch.empty(shape, dtype=torch.float64, device=dev)
+    dll = torch.empty(shape, dtype=torch.float64, device=dev)
+    valid = torch.empty(shape, dtype=torch.uint8, device=dev)
+    null = torch.empty(3, dtype=torch.float64, device=dev)
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+    st = lib().nu_linear_search(
+        ctx.ptr, factor.ptr, ctypes.c_void_p(f_d.data_ptr()),
+        ctypes.c_void_p(A_d.data_ptr() if A_d is not None else 0), m1, ctypes.c_void_p(lat.data_ptr()),
+        int(n_epochs), durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d, PRECISIONS[precision],
+        ctypes.c_void_p(depth.data_ptr()), ctypes.c_void_p(var.data_ptr()), ctypes.c_void_p(dll.data_ptr()),
+        ctypes.c_void_p(valid.data_ptr()), ctypes.c_void_p(null.data_ptr()))
+    _check(ctx.ptr, st)
+    # keep the inputs alive until the enqueued work has consumed them
+    return {"depth": depth, "var": var, "dll": dll, "valid": valid, "null": null,
+            "_keep": (f_d, A_d, lat)}
+
+
+def periodic_search(ctx: Context, depth, var, dll, valid, dt: float, periods, sign: int = 1) -> dict:
+    """Fold of the single-event grid over periods x phases (Eq. 8, Eq. 9)."""
+    dev = ctx.device
+    depth = _dev_tensor(depth, torch.float64, dev)
+    var = _dev_tensor(var, torch.float64, dev)
+    dll = _dev_tensor(dll, torch.float64, dev)
+    valid = _dev_tensor(valid, torch.uint8, dev)
+    if not (depth.shape == var.shape == dll.shape == valid.shape) or depth.ndim != 2:
+        raise ValueError("depth, var, dll, valid must share one (n_d, n_epochs) shape")
+    per = _dev_tensor(periods, torch.float64, dev)
+    n_d, n_t = depth.shape
+    n_p = per.numel()
+    out = {
+        "q_snr": torch.empty(n_p, dtype=torch.float64, device=dev),
+        "best_phase": torch.empty(n_p, dtype=torch.int64, device=dev),
+        "best_dur": torch.empty(n_p, dtype=torch.int32, device=dev),
+        "best_depth": torch.empty(n_p, dtype=torch.float64, device=dev),
+        "best_sigma": torch.empty(n_p, dtype=torch.float64, device=dev),
+        "best_lnp": torch.empty(n_p, dtype=torch.float64, device=dev),
+        "best_index": torch.empty(1, dtype=torch.int64, device=dev),
+    }
+    st = lib().nu_periodic_search(
+        ctx.ptr, ctypes.c_void_p(depth.data_ptr()), ctypes.c_void_p(var.data_ptr()),
+        ctypes.c_void_p(dll.data_ptr()), ctypes.c_void_p(valid.data_ptr()), n_d, n_t, float(dt),
+        ctypes.c_void_p(per.data_ptr()), n_p, int(sign),
+        *[ctypes.c_void_p(out[k].data_ptr()) for k in ("q_snr", "best_phase", "best_dur", "best_depth",
+                                                       "best_sigma", "best_lnp", "best_index")])
+    _check(ctx.ptr, st)
+    out["_keep"] = (depth, var, dll, valid, per)
+    return out
+
+
+# ---------------------------------------------------------------------------
+class SearchResult:
+    """Periodogram and best candidate of a periodic search (host arrays)."""
+
+    def __init__(self, periods, raw: dict, t_first: float, dt: float, durations_slots):
+        self.periods = np.asarray(periods, dtype=np.float64)
+        self.Q_snr = raw["q_snr"].cpu().numpy()
+        self.best_phase = raw["best_phase"].cpu().numpy()
+        self.best_dur = raw["best_dur"].cpu().numpy()
+        self.depth = raw["best_depth"].cpu().numpy()
+        self.sigma = raw["best_sigma"].cpu().numpy()
+        self.lnp = raw["best_lnp"].cpu().numpy()
+        i = int(raw["best_index"].cpu().item())
+        self.best_index = i
+        if i >= 0:
+            j = int(self.best_dur[i])
+            self.best = (float(self.periods[i]), t_first + float(self.best_phase[i]) * dt,
+                         float(durations_slots[j]) * dt, float(self.depth[i]), float(self.sigma[i]))
+        else:
+            self.best = None
+
+
+class Nuance:
+    """The paper's search object: ``Nuance(time, flux, gp=SHO(...), X=X)``.
+
+    ``time`` must sit on a regular lattice of cadence ``dt`` (gaps allowed);
+    epochs are all lattice slots from the first to the last sample.
+    """
+
+    def __init__(self, time, flux, gp: SHO, X=None, dt: Optional[float] = None, device: int = 0):
+        t = np.asarray(time, dtype=np.float64)
+        if t.ndim != 1 or t.size < 2 or not np.all(np.diff(t) > 0):
+            raise ValueError("time must be strictly increasing with at least two samples")
+        self.dt = float(np.min(np.diff(t))) if dt is None else float(dt)
+        lat = np.rint((t - t[0]) / self.dt).astype(np.int64)
+        if np.max(np.abs(t - t[0] - lat * self.dt)) > 1e-6 * self.dt or np.any(np.diff(lat) <= 0):
+            raise ValueError("time is not on a regular lattice of cadence dt")
+        self.t_first = float(t[0])
+        self.lattice = lat
+        self.n_epochs = int(lat[-1]) + 1
+        self.flux = np.asarray(flux, dtype=np.float64)
+        self.X = None if X is None else np.asarray(X, dtype=np.float64)
+        self.ctx = Context(device)
+        self.factor = gp_factor(self.ctx, t, gp)
+        self._ls = None
+        self._dur_slots = None
+
+    def linear_search(self, t0s=None, Ds=(0.04,), precision: str = "fp64") -> dict:
+        if t0s is not None and np.asarray(t0s).size not in (self.lattice.size, self.n_epochs):
+            raise ValueError("epochs are the lattice slots of the time array")
+        slots = np.rint(np.asarray(Ds, dtype=np.float64) / self.dt).astype(np.int32)
+        if np.any(slots < 1):
+            raise ValueError("durations must be at least one cadence")
+        self._dur_slots = slots
+        self._ls = linear_search(self.ctx, self.factor, self.flux, self.X, self.lattice, self.n_epochs, slots,
+                                 precision)
+        return self._ls
+
+    def periodic_search(self, periods, sign: int = 1) -> SearchResult:
+        if self._ls is None:
+            raise RuntimeError("run linear_search first")
+        periods = np.asarray(periods, dtype=np.float64)
+        if np.any(~np.isfinite(periods)) or np.any(periods < self.dt):
+            raise ValueError("periods must be finite and at least one cadence")
+        ls = self._ls
+        raw = periodic_search(self.ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], self.dt, periods, sign)
+        return SearchResult(periods, raw, self.t_first, self.dt, self._dur_slots)

@@ -1,0 +1,580 @@
+// C ABI of the transit-search library: argument validation, context and
+// factor objects, launch schedules of the blocked factorisation, kernel
+// timing. No exception crosses the boundary.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+using namespace nu;
+
+namespace nu {
+
+nu_status set_error(nu_ctx* ctx, nu_status st, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return st;
+}
+
+nu_status check_hip(nu_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return NU_OK;
+  return set_error(ctx, e == hipErrorOutOfMemory ? NU_ERR_OOM : NU_ERR_DEVICE,
+                   std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st) {
+  *st = NU_OK;
+  if (bytes <= ctx->ws_bytes) return ctx->ws;
+  // the old buffer may still be in use by enqueued work
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess && ctx->ws) e = hipFree(ctx->ws);
+  ctx->ws = nullptr;
+  ctx->ws_bytes = 0;
+  if (e == hipSuccess) e = hipMalloc(&ctx->ws, bytes);
+  if (e != hipSuccess) {
+    *st = check_hip(ctx, e, "workspace allocation");
+    ctx->ws = nullptr;
+    return nullptr;
+  }
+  ctx->ws_bytes = bytes;
+  return ctx->ws;
+}
+
+void timing_begin(nu_ctx* ctx, const char* /*name*/, hipEvent_t* start) {
+  *start = nullptr;
+  if (!ctx->timing) return;
+  if (ctx->free_events.empty()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return;
+    ctx->free_events.push_back(ev);
+  }
+  *start = ctx->free_events.back();
+  ctx->free_events.pop_back();
+  hipEventRecord(*start, ctx->stream);
+}
+
+void timing_end(nu_ctx* ctx, const char* name, hipEvent_t start, double work) {
+  if (!ctx->timing || !start) return;
+  hipEvent_t stop;
+  if (ctx->free_events.empty()) {
+    if (hipEventCreate(&stop) != hipSuccess) return;
+  } else {
+    stop = ctx->free_events.back();
+    ctx->free_events.pop_back();
+  }
+  hipEventRecord(stop, ctx->stream);
+  ctx->pending.push_back({name, start, stop, work});
+}
+
+}  // namespace nu
+
+namespace {
+
+static void resolve_timing(nu_ctx* ctx) {
+  if (ctx->pending.empty()) return;
+  hipStreamSynchronize(ctx->stream);
+  for (auto& p : ctx->pending) {
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, p.start, p.stop);
+    auto it = ctx->timings.find(p.name);
+    if (it == ctx->timings.end()) {
+      ctx->timing_names.push_back(p.name);
+      it = ctx->timings.emplace(p.name, nu_timing_slot{}).first;
+    }
+    it->second.launches += 1;
+    it->second.ms += ms;
+    it->second.work += p.work;
+    ctx->free_events.push_back(p.start);
+    ctx->free_events.push_back(p.stop);
+  }
+  ctx->pending.clear();
+}
+
+struct Timed {
+  nu_ctx* ctx;
+  const char* name;
+  double work;
+  hipEvent_t start;
+  Timed(nu_ctx* c, const char* n, double w) : ctx(c), name(n), work(w) { timing_begin(c, n, &start); }
+  ~Timed() { timing_end(ctx, name, start, work); }
+};
+
+static int tiles_of(const GemmProblem& g) {
+  const int tm = g.M / TB, tn = g.N / TB;
+  return (g.flags & G_C_LOWER_TILES) ? tm * (tm + 1) / 2 : tm * tn;
+}
+
+// useful flops of a problem (zeros of triangular operands not counted)
+static double useful_flops(const GemmProblem& g) {
+  const double M = g.M, N = g.N, K = g.K;
+  if (g.flags & G_C_LOWER_TILES) return M * (M + 1) * K;  // 2 K per lower element
+  if (g.flags & (G_B_LOWER | G_B_UPPER)) return M * N * (N + 1);  // triangular N x N right factor
+  if (g.flags & G_A_LOWER) return N * M * (M + 1);               // triangular M x M left factor
+  if (g.flags & G_BT && g.K == TB && g.N == TB) return M * N * (K + 1);  // panel: triangular X_kk^T
+  return 2.0 * M * N * K;
+}
+
+struct Range {
+  int first = 0, count = 0, tiles = 0;
+  double flops = 0.0;
+};
+
+// append one launch's problems, numbering tiles from 0 within the launch
+static Range add_launch(std::vector<GemmProblem>& sched, std::vector<GemmProblem> probs) {
+  Range r;
+  r.first = (int)sched.size();
+  r.count = (int)probs.size();
+  int t = 0;
+  for (auto& p : probs) {
+    p.tiles_n = p.N / TB;
+    p.tile_begin = t;
+    p.tile_count = tiles_of(p);
+    t += p.tile_count;
+    r.flops += useful_flops(p);
+    sched.push_back(p);
+  }
+  r.tiles = t;
+  return r;
+}
+
+static GemmProblem prob(const double* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc, int M,
+                        int N, int K, int flags, double alpha, double beta) {
+  GemmProblem g{};
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.flags = flags;
+  g.alpha = alpha;
+  g.beta = beta;
+  return g;
+}
+
+struct Node {
+  int a, mid, b;
+};
+
+static void build_tree(int a, int b, int depth, std::vector<std::vector<Node>>& levels) {
+  if (b - a < 2) return;
+  const int mid = a + (b - a + 1) / 2;
+  if ((int)levels.size() <= depth) levels.resize(depth + 1);
+  levels[depth].push_back({a, mid, b});
+  build_tree(a, mid, depth + 1, levels);
+  build_tree(mid, b, depth + 1, levels);
+}
+
+struct FactorPlan {
+  std::vector<GemmProblem> sched;
+  std::vector<Range> panel, syrk, t1, t2;  // t1/t2 deepest level first
+  size_t t_elems = 0;
+};
+
+static void plan_factor(nu_factor* F, FactorPlan& plan) {
+  const int64_t np = F->np;
+  const int nblk = (int)(np / TB);
+  for (int k = 0; k + 1 < nblk; ++k) {
+    const int64_t off = (int64_t)k * TB;
+    const int rest = (int)(np - off - TB);
+    double* panel = F->L + (off + TB) * np + off;
+    const double* xkk = F->X + off * np + off;
+    plan.panel.push_back(add_launch(plan.sched, {prob(panel, np, xkk, np, panel, np, rest, TB, TB, G_BT, 1.0, 0.0)}));
+    plan.syrk.push_back(add_launch(
+        plan.sched, {prob(panel, np, panel, np, panel + TB, np, rest, rest, TB, G_BT | G_C_LOWER_TILES, -1.0, 1.0)}));
+  }
+  std::vector<std::vector<Node>> levels;
+  build_tree(0, nblk, 0, levels);
+  size_t tmax = 0;
+  for (int d = (int)levels.size() - 1; d >= 0; --d) {
+    std::vector<GemmProblem> p1, p2;
+    size_t off_t = 0;
+    for (const Node& nd : levels[d]) {
+      const int64_t a0 = (int64_t)nd.a * TB, m0 = (int64_t)nd.mid * TB;
+      const int na = (nd.mid - nd.a) * TB, nc = (nd.b - nd.mid) * TB;
+      double* T = F->T + off_t;
+      // T = L21 X_A
+      p1.push_back(prob(F->L + m0 * np + a0, np, F->X + a0 * np + a0, np, T, na, nc, na, na, G_B_LOWER, 1.0, 0.0));
+      // X21 = -X_C T
+      p2.push_back(prob(F->X + m0 * np + m0, np, T, na, F->X + m0 * np + a0, np, nc, na, nc, G_A_LOWER, -1.0, 0.0));
+      off_t += (size_t)na * nc;
+    }
+    tmax = std::max(tmax, off_t);
+    plan.t1.push_back(add_launch(plan.sched, p1));
+    plan.t2.push_back(add_launch(plan.sched, p2));
+  }
+  plan.t_elems = tmax;
+}
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+static nu_status launch_range(nu_ctx* ctx, const nu_factor* F, const Range& r, const char* name) {
+  Timed tm(ctx, name, r.flops);
+  return check_hip(ctx, launch_gemm(ctx->stream, F->probs + r.first, r.count, r.tiles), name);
+}
+
+struct FactorExtra {
+  FactorPlan plan;
+};
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+nu_status nu_ctx_create(int device, void* stream, nu_ctx** out) {
+  if (!out) return NU_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return NU_ERR_DEVICE;
+  if (device < 0 || device >= ndev) return NU_ERR_ARG;
+  nu_ctx* ctx = new (std::nothrow) nu_ctx();
+  if (!ctx) return NU_ERR_OOM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete ctx;
+    return NU_ERR_DEVICE;
+  }
+  *out = ctx;
+  return NU_OK;
+}
+
+void nu_ctx_destroy(nu_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) hipFree(ctx->ws);
+  for (auto& p : ctx->pending) {
+    hipEventDestroy(p.start);
+    hipEventDestroy(p.stop);
+  }
+  for (auto e : ctx->free_events) hipEventDestroy(e);
+  delete ctx;
+}
+
+nu_status nu_ctx_set_stream(nu_ctx* ctx, void* stream) {
+  if (!ctx) return NU_ERR_ARG;
+  ctx->stream = (hipStream_t)stream;
+  return NU_OK;
+}
+
+const char* nu_ctx_last_error(const nu_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+nu_status nu_ctx_enable_timing(nu_ctx* ctx, int enable) {
+  if (!ctx) return NU_ERR_ARG;
+  ctx->timing = enable != 0;
+  return NU_OK;
+}
+
+nu_status nu_ctx_timing_reset(nu_ctx* ctx) {
+  if (!ctx) return NU_ERR_ARG;
+  resolve_timing(ctx);
+  ctx->timings.clear();
+  ctx->timing_names.clear();
+  return NU_OK;
+}
+
+int nu_ctx_timing_count(nu_ctx* ctx) {
+  if (!ctx) return 0;
+  resolve_timing(ctx);
+  return (int)ctx->timing_names.size();
+}
+
+nu_status nu_ctx_timing_entry(nu_ctx* ctx, int index, const char** name_host, int64_t* launches_host,
+                              double* total_ms_host, double* work_units_host) {
+  if (!ctx) return NU_ERR_ARG;
+  resolve_timing(ctx);
+  if (index < 0 || index >= (int)ctx->timing_names.size())
+    return set_error(ctx, NU_ERR_ARG, "timing index out of range");
+  const std::string& nm = ctx->timing_names[index];
+  const nu_timing_slot& s = ctx->timings[nm];
+  if (name_host) *name_host = nm.c_str();
+  if (launches_host) *launches_host = s.launches;
+  if (total_ms_host) *total_ms_host = s.ms;
+  if (work_units_host) *work_units_host = s.work;
+  return NU_OK;
+}
+
+// ---------------------------------------------------------------------------
+nu_status nu_gp_factor(nu_ctx* ctx, const double* t, int64_t n, const nu_sho* theta, nu_factor** out,
+                       double* logdet_host, int64_t* fail_pivot_host) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!t || !theta || !out) return set_error(ctx, NU_ERR_ARG, "gp_factor: null argument");
+  *out = nullptr;
+  if (fail_pivot_host) *fail_pivot_host = -1;
+  if (n < 1 || n > (int64_t)1 << 17) return set_error(ctx, NU_ERR_ARG, "gp_factor: n must be in [1, 131072]");
+  const nu_sho th = *theta;
+  if (!(std::isfinite(th.amp) && th.amp >= 0.0) || !finite_pos(th.omega) || !finite_pos(th.q) ||
+      !(std::isfinite(th.sigma_w) && th.sigma_w >= 0.0))
+    return set_error(ctx, NU_ERR_ARG, "gp_factor: need finite amp >= 0, omega > 0, q > 0, sigma_w >= 0");
+  nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+
+  nu_factor* F = new (std::nothrow) nu_factor();
+  if (!F) return set_error(ctx, NU_ERR_OOM, "gp_factor: host allocation");
+  F->device = ctx->device;
+  F->n = n;
+  F->np = round_up(n, TB);
+  const int64_t np = F->np;
+  const int nblk = (int)(np / TB);
+  auto fail = [&](nu_status s) {
+    nu_factor_destroy(F);
+    return s;
+  };
+  st = check_hip(ctx, hipMalloc(&F->L, (size_t)np * np * sizeof(double)), "alloc L");
+  if (st != NU_OK) return fail(st);
+  st = check_hip(ctx, hipMalloc(&F->X, (size_t)np * np * sizeof(double)), "alloc X");
+  if (st != NU_OK) return fail(st);
+  FactorPlan plan;
+  F->T = nullptr;
+  plan_factor(F, plan);  // T offsets are relative to F->T == nullptr until allocated
+  F->t_elems = std::max<size_t>(plan.t_elems, 1);
+  st = check_hip(ctx, hipMalloc(&F->T, F->t_elems * sizeof(double)), "alloc T");
+  if (st != NU_OK) return fail(st);
+  // rebuild with the real T base
+  plan = FactorPlan();
+  plan_factor(F, plan);
+  // small: [0, nblk) logdet parts, [nblk] logdet, [nblk+1] status (int64)
+  st = check_hip(ctx, hipMalloc(&F->small, (size_t)(nblk + 4) * sizeof(double)), "alloc small");
+  if (st != NU_OK) return fail(st);
+  st = check_hip(ctx, hipMalloc(&F->nullfit, sizeof(NullFit)), "alloc nullfit");
+  if (st != NU_OK) return fail(st);
+  st = check_hip(ctx, hipMalloc(&F->probs, std::max<size_t>(plan.sched.size(), 1) * sizeof(GemmProblem)),
+                 "alloc schedule");
+  if (st != NU_OK) return fail(st);
+  F->sched = plan.sched;
+  auto to_pairs = [](const std::vector<Range>& rs, std::vector<std::pair<int, int>>& out, std::vector<int>& tiles) {
+    out.clear();
+    for (auto& r : rs) {
+      out.push_back({r.first, r.count});
+      tiles.push_back(r.tiles);
+    }
+  };
+  F->sched_tiles.clear();
+  to_pairs(plan.panel, F->chol_panel, F->sched_tiles);
+  to_pairs(plan.syrk, F->chol_syrk, F->sched_tiles);
+  to_pairs(plan.t1, F->trtri_t1, F->sched_tiles);
+  to_pairs(plan.t2, F->trtri_t2, F->sched_tiles);
+  if (!plan.sched.empty()) {
+    st = check_hip(ctx, hipMemcpy(F->probs, plan.sched.data(), plan.sched.size() * sizeof(GemmProblem),
+                                  hipMemcpyHostToDevice),
+                   "upload schedule");
+    if (st != NU_OK) return fail(st);
+  }
+  double* parts = F->small;
+  double* logdet_dev = F->small + nblk;
+  int64_t* status = reinterpret_cast<int64_t*>(F->small + nblk + 1);
+  st = check_hip(ctx, launch_fill_i64(ctx->stream, status, -1), "status init");
+  if (st != NU_OK) return fail(st);
+  {
+    Timed tm(ctx, "kbuild", (double)n * (double)(n + 1) / 2.0);
+    st = check_hip(ctx, launch_kbuild(ctx->stream, t, n, np, th, F->L), "kbuild");
+  }
+  if (st != NU_OK) return fail(st);
+  for (int k = 0; k < nblk; ++k) {
+    {
+      Timed tm(ctx, "potrf_diag", (double)TB * TB * TB * 2.0 / 3.0);
+      st = check_hip(ctx, launch_potrf_diag(ctx->stream, F->L, np, (int64_t)k * TB, k, parts, status, F->X, np),
+                     "potrf_diag");
+    }
+    if (st != NU_OK) return fail(st);
+    if (k + 1 < nblk) {
+      st = launch_range(ctx, F, plan.panel[k], "gemm_f64");
+      if (st != NU_OK) return fail(st);
+      st = launch_range(ctx, F, plan.syrk[k], "gemm_f64");
+      if (st != NU_OK) return fail(st);
+    }
+  }
+  st = check_hip(ctx, launch_logdet_reduce(ctx->stream, parts, nblk, logdet_dev), "logdet");
+  if (st != NU_OK) return fail(st);
+  struct {
+    double logdet;
+    int64_t status;
+  } hostv{};
+  st = check_hip(ctx, hipMemcpyAsync(&hostv.logdet, logdet_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+                 "read logdet");
+  if (st == NU_OK)
+    st = check_hip(ctx, hipMemcpyAsync(&hostv.status, status, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream),
+                   "read status");
+  if (st == NU_OK) st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "gp_factor sync");
+  if (st != NU_OK) return fail(st);
+  if (hostv.status >= 0) {
+    if (fail_pivot_host) *fail_pivot_host = hostv.status;
+    nu_factor_destroy(F);
+    return set_error(ctx, NU_ERR_NOT_PD,
+                     "gp_factor: covariance not positive definite at pivot " + std::to_string(hostv.status));
+  }
+  F->logdet = hostv.logdet;
+  if (logdet_host) *logdet_host = hostv.logdet;
+  // keep the plan ranges for the triangular inverse
+  F->inverse_ready = false;
+  *out = F;
+  return NU_OK;
+}
+
+void nu_factor_destroy(nu_factor* F) {
+  if (!F) return;
+  hipSetDevice(F->device);
+  hipDeviceSynchronize();
+  if (F->L) hipFree(F->L);
+  if (F->X) hipFree(F->X);
+  if (F->T) hipFree(F->T);
+  if (F->small) hipFree(F->small);
+  if (F->nullfit) hipFree(F->nullfit);
+  if (F->probs) hipFree(F->probs);
+  delete F;
+}
+
+int64_t nu_factor_n(const nu_factor* F) { return F ? F->n : -1; }
+
+// ---------------------------------------------------------------------------
+nu_status nu_linear_search(nu_ctx* ctx, nu_factor* F, const double* f, const double* A, int m1,
+                           const int64_t* lattice, int64_t n_epochs, const int32_t* dur_samples_host, int n_d,
+                           nu_precision prec, double* depth, double* var, double* dll, uint8_t* valid,
+                           double* null_out) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!F || !f || !lattice || !dur_samples_host || !depth || !var || !dll || !valid)
+    return set_error(ctx, NU_ERR_ARG, "linear_search: null argument");
+  if (F->device != ctx->device) return set_error(ctx, NU_ERR_ARG, "linear_search: factor on another device");
+  if (m1 < 0 || m1 > MAX_M1) return set_error(ctx, NU_ERR_ARG, "linear_search: m1 must be in [0, 7]");
+  if (m1 > 0 && !A) return set_error(ctx, NU_ERR_ARG, "linear_search: A is NULL with m1 > 0");
+  if (F->n < m1 + 1) return set_error(ctx, NU_ERR_ARG, "linear_search: need n >= m1 + 1");
+  if (n_d < 1 || n_d > MAX_ND) return set_error(ctx, NU_ERR_ARG, "linear_search: n_d must be in [1, 16]");
+  if (n_epochs < 1 || n_epochs > ((int64_t)1 << 31))
+    return set_error(ctx, NU_ERR_ARG, "linear_search: n_epochs must be in [1, 2^31]");
+  if (n_epochs < F->n) return set_error(ctx, NU_ERR_ARG, "linear_search: n_epochs must be >= n (strict lattice)");
+  int dmax = 0;
+  for (int j = 0; j < n_d; ++j) {
+    if (dur_samples_host[j] < 1 || dur_samples_host[j] > MAX_DUR)
+      return set_error(ctx, NU_ERR_ARG, "linear_search: durations must be in [1, 1024] slots");
+    dmax = std::max(dmax, (int)dur_samples_host[j]);
+  }
+  if (prec != NU_FP64) return set_error(ctx, NU_ERR_UNSUPPORTED, "linear_search: only NU_FP64 in this build");
+  nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+  const int64_t n = F->n, np = F->np;
+
+  // triangular inverse X = L^-1, bottom-up over the block tree (cached in the factor)
+  if (!F->inverse_ready) {
+    const int nlev = (int)F->trtri_t1.size();
+    for (int l = 0; l < nlev; ++l) {
+      Range r1, r2;
+      r1.first = F->trtri_t1[l].first;
+      r1.count = F->trtri_t1[l].second;
+      r2.first = F->trtri_t2[l].first;
+      r2.count = F->trtri_t2[l].second;
+      r1.tiles = r2.tiles = 0;
+      r1.flops = r2.flops = 0.0;
+      for (int i = 0; i < r1.count; ++i) {
+        r1.tiles += F->sched[r1.first + i].tile_count;
+        r1.flops += useful_flops(F->sched[r1.first + i]);
+      }
+      for (int i = 0; i < r2.count; ++i) {
+        r2.tiles += F->sched[r2.first + i].tile_count;
+        r2.flops += useful_flops(F->sched[r2.first + i]);
+      }
+      st = launch_range(ctx, F, r1, "gemm_f64");
+      if (st != NU_OK) return st;
+      st = launch_range(ctx, F, r2, "gemm_f64");
+      if (st != NU_OK) return st;
+    }
+    F->inverse_ready = true;
+  }
+
+  // workspace: Y, Z (np x 8), xtv partials, q partials
+  const int xrc = 1024;
+  const int xchunks = (int)((n + xrc - 1) / xrc);
+  const int qrc = 2048;
+  const int qchunks = (int)((n + qrc - 1) / qrc);
+  const size_t yz = (size_t)np * YCOLS;
+  const size_t need = (2 * yz + (size_t)xchunks * yz + (size_t)qchunks * n_d * n_epochs) * sizeof(double);
+  double* ws = (double*)ctx_workspace(ctx, need, &st);
+  if (!ws) return st;
+  double* Y = ws;
+  double* Z = Y + yz;
+  double* xpart = Z + yz;
+  double* qpart = xpart + (size_t)xchunks * yz;
+  const double* logdet_dev = F->small + (np / TB);
+
+  {
+    Timed tm(ctx, "xv_rows", (double)n * (double)(n + 1) / 2.0 * 8.0);
+    st = check_hip(ctx, launch_xv_rows(ctx->stream, F->X, np, n, A, m1, f, Y), "xv_rows");
+  }
+  if (st != NU_OK) return st;
+  {
+    Timed tm(ctx, "null_solve", 0.0);
+    st = check_hip(ctx, launch_null_solve(ctx->stream, Y, n, m1, logdet_dev, F->nullfit, null_out), "null_solve");
+  }
+  if (st != NU_OK) return st;
+  {
+    Timed tm(ctx, "xtv_cols", (double)n * (double)(n + 1) / 2.0 * 8.0);
+    st = check_hip(ctx, launch_xtv_cols(ctx->stream, F->X, np, n, np, Y, m1 + 1, xpart, xrc, xchunks, Z),
+                   "xtv_cols");
+  }
+  if (st != NU_OK) return st;
+  // ascending durations (nested boxes) with their caller indices
+  std::vector<int32_t> order(n_d);
+  for (int j = 0; j < n_d; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return dur_samples_host[a] < dur_samples_host[b]; });
+  std::vector<int32_t> sorted(2 * n_d);
+  for (int k = 0; k < n_d; ++k) {
+    sorted[k] = dur_samples_host[order[k]];
+    sorted[n_d + k] = order[k];
+  }
+  {
+    Timed tm(ctx, "q_partial", 0.0);
+    st = check_hip(ctx, launch_q_partial(ctx->stream, F->X, np, n, lattice, n_epochs, sorted.data(), n_d, dmax, qrc,
+                                         qchunks, qpart),
+                   "q_partial");
+  }
+  if (st != NU_OK) return st;
+  {
+    Timed tm(ctx, "cell_epilogue", 0.0);
+    st = check_hip(ctx, launch_cell_epilogue(ctx->stream, qpart, qchunks, lattice, n, n_epochs, dur_samples_host,
+                                             nullptr, n_d, Z, m1, F->nullfit, depth, var, dll, valid),
+                   "cell_epilogue");
+  }
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var, const double* dll,
+                             const uint8_t* valid, int n_d, int64_t n_epochs, double dt, const double* periods,
+                             int64_t n_p, int log_term_sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,
+                             double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period_index) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!depth || !var || !dll || !valid || !periods || !q_snr || !best_phase || !best_dur || !best_depth ||
+      !best_sigma || !best_lnp)
+    return set_error(ctx, NU_ERR_ARG, "periodic_search: null argument");
+  if (n_d < 1 || n_d > MAX_ND) return set_error(ctx, NU_ERR_ARG, "periodic_search: n_d must be in [1, 16]");
+  if (n_epochs < 1 || n_epochs > ((int64_t)1 << 31))
+    return set_error(ctx, NU_ERR_ARG, "periodic_search: n_epochs must be in [1, 2^31]");
+  if (!finite_pos(dt)) return set_error(ctx, NU_ERR_ARG, "periodic_search: dt must be finite and > 0");
+  if (n_p < 1 || n_p > ((int64_t)1 << 31) - 1)
+    return set_error(ctx, NU_ERR_ARG, "periodic_search: n_p must be in [1, 2^31)");
+  if (log_term_sign != 1 && log_term_sign != -1)
+    return set_error(ctx, NU_ERR_ARG, "periodic_search: log_term_sign must be +1 or -1");
+  nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+  {
+    // algorithmic bytes: 24 per event visit (depth, var, dll of one interpolated event), n_d * n_epochs per period
+    Timed tm(ctx, "fold", 24.0 * (double)n_d * (double)n_epochs * (double)n_p);
+    st = check_hip(ctx, launch_fold(ctx->stream, depth, var, dll, valid, n_d, n_epochs, dt, periods, n_p,
+                                    log_term_sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp),
+                   "fold");
+  }
+  if (st != NU_OK) return st;
+  if (best_period_index) {
+    Timed tm(ctx, "best_period", 0.0);
+    st = check_hip(ctx, launch_best_period(ctx->stream, q_snr, n_p, best_period_index), "best_period");
+  }
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Grouped FP64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// One launch runs a list of problems C = alpha * op(A) op(B) + beta * C; each
+// workgroup owns one 128 x 128 output tile of one problem. 256 threads = 4
+// waves in a 2 x 2 arrangement, each wave a 64 x 64 sub-tile held as 4 x 4
+// MFMA accumulators (16 x 16 each). The k loop stages 16-deep slices of A and
+// op(B) through LDS (k-major, double buffered; one barrier per slice).
+//
+// This is the dense contraction of the factorisation: the trailing updates
+// and panels of the blocked Cholesky, and both products of every level of the
+// triangular inverse X = L^-1 that whitens the box design of the linear search.
+#include "internal.hpp"
+
+namespace nu {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int GBM = TB, GBN = TB, GBK = 16;
+constexpr int LPAD = 4;
+
+__device__ __forceinline__ void tile_of(const GemmProblem& P, int local, int& tm, int& tn) {
+  if (P.flags & G_C_LOWER_TILES) {
+    int r = (int)((sqrt(8.0 * (double)local + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= local) ++r;
+    while (r * (r + 1) / 2 > local) --r;
+    tm = r;
+    tn = local - r * (r + 1) / 2;
+  } else {
+    tm = local / P.tiles_n;
+    tn = local - tm * P.tiles_n;
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmProblem* __restrict__ probs, int nprob) {
+  __shared__ double As[2][GBK][GBM + LPAD];
+  __shared__ double Bs[2][GBK][GBN + LPAD];
+
+  const int tile = blockIdx.x;
+  int p = 0;
+  for (int i = 1; i < nprob; ++i)
+    if (tile >= probs[i].tile_begin) p = i;
+  const GemmProblem P = probs[p];
+  int tm, tn;
+  tile_of(P, tile - P.tile_begin, tm, tn);
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  int kb = 0, ke = P.K;
+  if (P.flags & G_A_LOWER) ke = min(ke, m0 + GBM);
+  if (P.flags & G_B_LOWER) kb = max(kb, n0);
+  if (P.flags & G_B_UPPER) ke = min(ke, n0 + GBN);
+  const int nk = ke > kb ? (ke - kb) / GBK : 0;
+  const bool bt = (P.flags & G_BT) != 0;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  // global -> register staging: "row-major M x K -> [k][m]" pattern for A (and B^T)
+  const int ar = tid >> 1, akh = (tid & 1) * 8;
+  // "row-major K x N -> [k][n]" pattern for B
+  const int bk = tid >> 4, bnc = (tid & 15) * 8;
+
+  const double* Ap = P.A + (int64_t)(m0 + ar) * P.lda + akh;
+  const double* Bp = bt ? P.B + (int64_t)(n0 + ar) * P.ldb + akh : P.B + (int64_t)bk * P.ldb + n0 + bnc;
+
+  double ra[8], rb[8];
+  auto gload = [&](int k0) {
+    const double2* a2 = reinterpret_cast<const double2*>(Ap + k0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double2 v = a2[i];
+      ra[2 * i] = v.x;
+      ra[2 * i + 1] = v.y;
+    }
+    const double2* b2 = bt ? reinterpret_cast<const double2*>(Bp + k0)
+                           : reinterpret_cast<const double2*>(Bp + (int64_t)k0 * P.ldb);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double2 v = b2[i];
+      rb[2 * i] = v.x;
+      rb[2 * i + 1] = v.y;
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) As[buf][akh + i][ar] = ra[i];
+    if (bt) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[buf][akh + i][ar] = rb[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[buf][bk][bnc + i] = rb[i];
+    }
+  };
+
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  if (nk > 0) {
+    gload(kb);
+    lstore(0);
+    __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+      const int buf = it & 1;
+      if (it + 1 < nk) gload(kb + (it + 1) * GBK);
+#pragma unroll
+      for (int kk = 0; kk < GBK / 4; ++kk) {
+        double a[4], b[4];
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) a[mi] = As[buf][kk * 4 + lk][wm + mi * 16 + lr];
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) b[ni] = Bs[buf][kk * 4 + lk][wn + ni * 16 + lr];
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 4; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+      }
+      if (it + 1 < nk) lstore(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // epilogue: lane holds rows 4*(lane/16) + i, column lane % 16 of each 16 x 16 block
+  const double alpha = P.alpha, beta = P.beta;
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = m0 + wm + mi * 16 + lk * 4 + i;
+        const int col = n0 + wn + ni * 16 + lr;
+        double* c = P.C + (int64_t)row * P.ldc + col;
+        double v = alpha * acc[mi][ni][i];
+        if (beta != 0.0) v = fma(beta, *c, v);
+        *c = v;
+      }
+}
+
+hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles) {
+  if (total_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)total_tiles), dim3(256), 0, s, dprobs, nprob);
+  return hipGetLastError();
+}
+
+}  // namespace nu

@@ -1,0 +1,152 @@
+// Internal declarations shared by the HIP sources of the transit-search library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "nuance_mi355x.h"
+
+namespace nu {
+
+// Tile edge of the dense factorisation: matrices are padded to a multiple of
+// TB (identity on the padded diagonal), every GEMM problem is a multiple of
+// TB in M and N, and the diagonal blocks factored in LDS are TB x TB.
+constexpr int TB = 128;
+constexpr int MAX_M1 = 7;        // trend columns
+constexpr int YCOLS = 8;         // row stride of the whitened [A | f] panel
+constexpr int MAX_ND = 16;       // durations per search
+constexpr int MAX_DUR = 1024;    // samples per box
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// One C = alpha * op(A) * op(B) + beta * C problem of a grouped launch.
+// All matrices are row-major. A is M x K (lda), op(B) is K x N: B itself is
+// K x N (ldb) or, with G_BT, N x K (ldb). Triangular flags restrict the
+// k-range per output tile to where the triangular operand is non-zero; the
+// zero entries inside that range must be stored zeros.
+enum GemmFlags : int {
+  G_BT = 1,             // B stored transposed (N x K)
+  G_A_LOWER = 2,        // A lower triangular: k < m0 + TB
+  G_B_LOWER = 4,        // op(B) lower triangular: k >= n0
+  G_B_UPPER = 8,        // op(B) upper triangular: k < n0 + TB
+  G_C_LOWER_TILES = 16  // only tiles with row block >= column block
+};
+
+struct GemmProblem {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t lda, ldb, ldc;
+  int M, N, K;
+  int flags;
+  double alpha, beta;
+  int tiles_n;
+  int tile_begin;
+  int tile_count;
+  int pad_;
+};
+
+struct NullFit {
+  double G0chol[MAX_M1 * MAX_M1];  // lower Cholesky factor of A^T K^-1 A
+  double w0[MAX_M1];
+  double chi2_0;
+  double lnl0;
+  double logdet;
+  int ok;
+  int pad_;
+};
+
+}  // namespace nu
+
+struct nu_timing_slot {
+  int64_t launches = 0;
+  double ms = 0.0;
+  double work = 0.0;
+};
+
+struct nu_pending_event {
+  std::string name;
+  hipEvent_t start, stop;
+  double work;
+};
+
+struct nu_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  // growable device workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // kernel timing
+  bool timing = false;
+  std::vector<nu_pending_event> pending;
+  std::vector<hipEvent_t> free_events;
+  std::map<std::string, nu_timing_slot> timings;
+  std::vector<std::string> timing_names;
+};
+
+struct nu_factor {
+  int device = 0;
+  int64_t n = 0;    // samples
+  int64_t np = 0;   // padded to a multiple of TB
+  double* L = nullptr;       // np x np row-major; lower triangle = Cholesky factor
+  double* X = nullptr;       // np x np row-major; lower triangle = L^-1 (diagonal blocks at factor time)
+  double* T = nullptr;       // workspace of the triangular-inverse levels
+  size_t t_elems = 0;
+  double* small = nullptr;   // logdet parts, status etc.
+  nu::GemmProblem* probs = nullptr;  // device copy of the schedule
+  std::vector<nu::GemmProblem> sched;  // host copy
+  // schedule ranges
+  std::vector<std::pair<int, int>> chol_panel;  // per step: (first problem, count)
+  std::vector<std::pair<int, int>> chol_syrk;
+  std::vector<std::pair<int, int>> trtri_t1;    // per level (deepest first)
+  std::vector<std::pair<int, int>> trtri_t2;
+  std::vector<int> sched_tiles;                 // tiles per launch range (parallel to the ranges above)
+  double logdet = 0.0;
+  bool inverse_ready = false;
+  nu::NullFit* nullfit = nullptr;
+};
+
+namespace nu {
+
+// error helpers (capi.cpp)
+nu_status set_error(nu_ctx* ctx, nu_status st, const std::string& msg);
+nu_status check_hip(nu_ctx* ctx, hipError_t e, const char* what);
+void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st);
+
+// kernel timing (capi.cpp)
+void timing_begin(nu_ctx* ctx, const char* name, hipEvent_t* start);
+void timing_end(nu_ctx* ctx, const char* name, hipEvent_t start, double work);
+
+// launchers (*.hip)
+hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho& th, double* K);
+hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles);
+hipError_t launch_potrf_diag(hipStream_t s, double* L, int64_t ld, int64_t off, int step, double* logdet_parts,
+                             int64_t* status, double* Xdiag, int64_t ldx);
+hipError_t launch_fill_i64(hipStream_t s, int64_t* p, int64_t v);
+hipError_t launch_logdet_reduce(hipStream_t s, const double* parts, int nparts, double* out);
+
+hipError_t launch_xv_rows(hipStream_t s, const double* X, int64_t ldx, int64_t n, const double* A, int m1,
+                          const double* f, double* Y);
+hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const double* logdet, NullFit* nf,
+                             double* null_out);
+hipError_t launch_xtv_cols(hipStream_t s, const double* X, int64_t ldx, int64_t n, int64_t np, const double* Y,
+                           int nv, double* partial, int rowchunk, int nchunks, double* Z);
+hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t n, const int64_t* lattice,
+                            int64_t n_epochs, const int32_t* dur_sorted, int n_d, int dmax, int rowchunk,
+                            int nchunks, double* qpart);
+hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks, const int64_t* lattice, int64_t n,
+                                int64_t n_epochs, const int32_t* dur, const int32_t* dur_rank, int n_d,
+                                const double* Z, int m1, const NullFit* nf, double* depth, double* var, double* dll,
+                                uint8_t* valid);
+hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, const double* dll,
+                       const uint8_t* valid, int n_d, int64_t n_epochs, double dt, const double* periods, int64_t n_p,
+                       int sign, double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth,
+                       double* best_sigma, double* best_lnp);
+hipError_t launch_best_period(hipStream_t s, const double* q_snr, int64_t n_p, int64_t* out);
+
+}  // namespace nu

@@ -1,0 +1,418 @@
+// Linear search (Section 2.2, Eqs. 5-6) on top of the factor K = L L^T and the
+// triangular inverse X = L^-1.
+//
+// For the cell (duration j, epoch slot i) the design is X_ij = [A | b] with
+// b = -1 on the box samples [lo, hi). With G0 = A^T K^-1 A, the Schur
+// complement of the trend block gives the box coefficient of Eq. 6 exactly:
+//   q = b^T K^-1 b = ||L^-1 b||^2 = sum_n (sum_{m in [lo,hi)} X[n][m])^2
+//   g = A^T K^-1 b = -sum_{n in [lo,hi)} (K^-1 A)[n]
+//   h = b^T K^-1 r0 = -sum_{n in [lo,hi)} (K^-1 r0)[n],   r0 = f - A w0
+//   S = q - g^T G0^-1 g,  depth = h / S,  var = 1 / S,  dll = h^2 / (2 S)
+// where w0 is the trend-only fit and dll = ln L_ij - ln L_0 (Eq. 5).
+//
+// Kernels, in launch order:
+//   xv_rows       Y = X [A | f]           (whitened trend and flux; one wave per row)
+//   null_solve    trend-only GLS, r~0 = f~ - A~ w0, chi2_0, ln L_0
+//   xtv_cols      Z = X^T [A~ | r~0] = [K^-1 A | K^-1 r0]   (row-chunk partials + reduce)
+//   q_partial     per cell, sum over a row chunk of the squared box window sums of X
+//   cell_epilogue per cell: g, h from window sums of Z, Schur complement, outputs
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace nu {
+
+struct DurList {
+  int n;
+  int d[MAX_ND];     // box lengths in slots (ascending for q_partial, caller order for the epilogue)
+  int perm[MAX_ND];  // q_partial: caller index of the k-th ascending duration
+};
+
+__device__ __forceinline__ int64_t lower_bound_i64(const int64_t* __restrict__ a, int64_t n, int64_t v) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void xv_rows_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
+                                                      const double* __restrict__ A, int m1,
+                                                      const double* __restrict__ f, double* __restrict__ Y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double acc[YCOLS];
+#pragma unroll
+  for (int c = 0; c < YCOLS; ++c) acc[c] = 0.0;
+  const double* xr = X + row * ldx;
+  for (int64_t m = lane; m <= row; m += 64) {
+    const double x = xr[m];
+#pragma unroll
+    for (int c = 0; c < MAX_M1; ++c)
+      if (c < m1) acc[c] = fma(x, A[c * n + m], acc[c]);
+    acc[YCOLS - 1] = fma(x, f[m], acc[YCOLS - 1]);
+  }
+#pragma unroll
+  for (int c = 0; c < YCOLS; ++c) acc[c] = wave_sum(acc[c]);
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < MAX_M1; ++c)
+      if (c < m1) Y[row * YCOLS + c] = acc[c];
+    Y[row * YCOLS + m1] = acc[YCOLS - 1];
+  }
+}
+
+hipError_t launch_xv_rows(hipStream_t s, const double* X, int64_t ldx, int64_t n, const double* A, int m1,
+                          const double* f, double* Y) {
+  hipLaunchKernelGGL(xv_rows_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, ldx, n, A, m1, f, Y);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide sum of one double per thread; fixed order (wave butterflies, then
+// the four wave totals in order). All threads get the result.
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(256) void null_solve_kernel(double* __restrict__ Y, int64_t n, int m1,
+                                                         const double* __restrict__ logdet, NullFit* __restrict__ nf,
+                                                         double* __restrict__ null_out) {
+  __shared__ double red[4];
+  __shared__ double S[MAX_M1 + 1][MAX_M1 + 1];
+  __shared__ double w0s[MAX_M1];
+  __shared__ int ok_s;
+  const int tid = threadIdx.x;
+  const int nv = m1 + 1;
+  for (int a = 0; a < nv; ++a)
+    for (int b = a; b < nv; ++b) {
+      double acc = 0.0;
+      for (int64_t r = tid; r < n; r += 256) acc = fma(Y[r * YCOLS + a], Y[r * YCOLS + b], acc);
+      acc = block_sum(acc, red);
+      if (tid == 0) S[a][b] = S[b][a] = acc;
+    }
+  __syncthreads();
+  if (tid == 0) {
+    // Cholesky of G0 = A~^T A~ and w0 = G0^-1 A~^T f~
+    double Lg[MAX_M1][MAX_M1];
+    int ok = 1;
+    for (int i = 0; i < m1; ++i)
+      for (int j = 0; j <= i; ++j) {
+        double v = S[i][j];
+        for (int k = 0; k < j; ++k) v -= Lg[i][k] * Lg[j][k];
+        if (i == j) {
+          if (!(v > 0.0)) ok = 0;
+          Lg[i][i] = sqrt(v);
+        } else {
+          Lg[i][j] = v / Lg[j][j];
+        }
+      }
+    double y[MAX_M1];
+    for (int i = 0; i < m1; ++i) {
+      double v = S[i][m1];
+      for (int k = 0; k < i; ++k) v -= Lg[i][k] * y[k];
+      y[i] = v / Lg[i][i];
+    }
+    for (int i = m1 - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < m1; ++k) v -= Lg[k][i] * w0s[k];
+      w0s[i] = v / Lg[i][i];
+    }
+    for (int i = 0; i < MAX_M1; ++i)
+      for (int j = 0; j < MAX_M1; ++j) nf->G0chol[i * MAX_M1 + j] = (i < m1 && j <= i) ? Lg[i][j] : 0.0;
+    for (int i = 0; i < m1; ++i) nf->w0[i] = w0s[i];
+    nf->ok = ok;
+    ok_s = ok;
+  }
+  __syncthreads();
+  // r~0 = f~ - A~ w0 (overwrites the f~ column), chi2_0 = ||r~0||^2
+  double acc = 0.0;
+  for (int64_t r = tid; r < n; r += 256) {
+    double v = Y[r * YCOLS + m1];
+    for (int a = 0; a < m1; ++a) v -= Y[r * YCOLS + a] * w0s[a];
+    Y[r * YCOLS + m1] = v;
+    acc = fma(v, v, acc);
+  }
+  acc = block_sum(acc, red);
+  if (tid == 0) {
+    const double ld = *logdet;
+    const double lnl0 = -0.5 * acc - 0.5 * ld - 0.5 * (double)n * log(2.0 * M_PI);
+    nf->chi2_0 = acc;
+    nf->lnl0 = lnl0;
+    nf->logdet = ld;
+    if (null_out) {
+      null_out[0] = ok_s ? lnl0 : NAN;
+      null_out[1] = acc;
+      null_out[2] = ld;
+    }
+  }
+}
+
+hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const double* logdet, NullFit* nf,
+                             double* null_out) {
+  hipLaunchKernelGGL(null_solve_kernel, dim3(1), dim3(256), 0, s, Y, n, m1, logdet, nf, null_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Z[m][c] = sum_{n >= m} X[n][m] Y[n][c], c < nv. Workgroup = 256 columns x a
+// chunk of rows; partials per chunk, then a fixed-order reduction.
+__global__ __launch_bounds__(256) void xtv_cols_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
+                                                       int64_t np, const double* __restrict__ Y, int nv,
+                                                       int rowchunk, double* __restrict__ partial) {
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= np) return;
+  const int chunk = blockIdx.y;
+  const int64_t r0 = (int64_t)chunk * rowchunk;
+  const int64_t r1 = min(n, r0 + rowchunk);
+  double acc[YCOLS];
+#pragma unroll
+  for (int c = 0; c < YCOLS; ++c) acc[c] = 0.0;
+  const int64_t c0 = (int64_t)blockIdx.x * 256;
+  if (m < n) {
+    for (int64_t r = max(r0, c0); r < r1; ++r) {
+      const double x = (m <= r) ? X[r * ldx + m] : 0.0;
+      const double* yr = Y + r * YCOLS;
+#pragma unroll
+      for (int c = 0; c < YCOLS; ++c)
+        if (c < nv) acc[c] = fma(x, yr[c], acc[c]);
+    }
+  }
+  double* out = partial + ((int64_t)chunk * np + m) * YCOLS;
+#pragma unroll
+  for (int c = 0; c < YCOLS; ++c) out[c] = acc[c];
+}
+
+__global__ __launch_bounds__(256) void xtv_reduce_kernel(const double* __restrict__ partial, int64_t np,
+                                                         int nchunks, double* __restrict__ Z) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= np * YCOLS) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * np * YCOLS + e];
+  Z[e] = s;
+}
+
+hipError_t launch_xtv_cols(hipStream_t s, const double* X, int64_t ldx, int64_t n, int64_t np, const double* Y,
+                           int nv, double* partial, int rowchunk, int nchunks, double* Z) {
+  hipLaunchKernelGGL(xtv_cols_kernel, dim3((unsigned)(np / 256 + (np % 256 ? 1 : 0)), (unsigned)nchunks),
+                     dim3(256), 0, s, X, ldx, n, np, Y, nv, rowchunk, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = np * YCOLS;
+  hipLaunchKernelGGL(xtv_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, np, nchunks,
+                     Z);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// q partial sums. Workgroup = 256 consecutive epoch slots (one per thread) x
+// one chunk of rows. The union of the boxes of the slots spans the sample
+// segment [seg_lo, seg_hi); R rows of X restricted to it are staged in LDS
+// (entries above the diagonal read as 0), and every thread forms the window
+// sums of its boxes. Boxes of one slot are nested in the duration, so the
+// ascending durations extend the previous window on both sides: each X entry
+// of the largest box is added once per row.
+constexpr int QCH = 256;
+
+__global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
+                                                        const int64_t* __restrict__ lattice, int64_t n_epochs,
+                                                        DurList dl, int wmax, int qr, int rowchunk,
+                                                        double* __restrict__ qpart) {
+  extern __shared__ double rows[];  // qr x wmax
+  __shared__ int64_t red_lo[4], red_hi[4];
+  const int tid = threadIdx.x;
+  const int64_t slot = (int64_t)blockIdx.x * QCH + tid;
+  const int chunk = blockIdx.y;
+  const bool active = slot < n_epochs;
+  int64_t lo[MAX_ND], hi[MAX_ND];
+  int64_t my_lo = INT64_MAX, my_hi = INT64_MIN;
+#pragma unroll
+  for (int k = 0; k < MAX_ND; ++k) {
+    lo[k] = hi[k] = 0;
+    if (k < dl.n && active) {
+      const int64_t a = slot - dl.d[k] / 2;
+      lo[k] = lower_bound_i64(lattice, n, a);
+      hi[k] = lower_bound_i64(lattice, n, a + dl.d[k]);
+      my_lo = min(my_lo, lo[k]);
+      my_hi = max(my_hi, hi[k]);
+    }
+  }
+  // workgroup min / max
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    my_lo = min(my_lo, (int64_t)__shfl_xor(my_lo, off, 64));
+    my_hi = max(my_hi, (int64_t)__shfl_xor(my_hi, off, 64));
+  }
+  if ((tid & 63) == 0) {
+    red_lo[tid >> 6] = my_lo;
+    red_hi[tid >> 6] = my_hi;
+  }
+  __syncthreads();
+  const int64_t seg_lo = min(min(red_lo[0], red_lo[1]), min(red_lo[2], red_lo[3]));
+  const int64_t seg_hi = max(max(red_hi[0], red_hi[1]), max(red_hi[2], red_hi[3]));
+  const int64_t r0 = (int64_t)chunk * rowchunk;
+  const int64_t rstart = max(r0, seg_lo);
+  const int64_t rend = min(n, r0 + rowchunk);
+  const int W = (seg_hi > seg_lo) ? (int)(seg_hi - seg_lo) : 0;
+
+  double q[MAX_ND];
+#pragma unroll
+  for (int k = 0; k < MAX_ND; ++k) q[k] = 0.0;
+  int rl[MAX_ND], rh[MAX_ND];
+#pragma unroll
+  for (int k = 0; k < MAX_ND; ++k) {
+    rl[k] = (int)(lo[k] - seg_lo);
+    rh[k] = (int)(hi[k] - seg_lo);
+  }
+
+  if (W > 0 && W <= wmax) {
+    for (int64_t nb = rstart; nb < rend; nb += qr) {
+      for (int rr = 0; rr < qr; ++rr) {
+        const int64_t r = nb + rr;
+        for (int w = tid; w < W; w += 256) {
+          const int64_t m = seg_lo + w;
+          rows[rr * wmax + w] = (r < rend && m <= r) ? X[r * ldx + m] : 0.0;
+        }
+      }
+      __syncthreads();
+      if (active) {
+        for (int rr = 0; rr < qr; ++rr) {
+          const double* row = rows + rr * wmax;
+          double s = 0.0;
+#pragma unroll
+          for (int k = 0; k < MAX_ND; ++k) {
+            if (k < dl.n) {
+              if (k == 0) {
+                for (int m = rl[0]; m < rh[0]; ++m) s += row[m];
+              } else {
+                for (int m = rl[k]; m < rl[k - 1]; ++m) s += row[m];
+                for (int m = rh[k - 1]; m < rh[k]; ++m) s += row[m];
+              }
+              q[k] = fma(s, s, q[k]);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < MAX_ND; ++k)
+      if (k < dl.n) qpart[((int64_t)chunk * dl.n + dl.perm[k]) * n_epochs + slot] = q[k];
+  }
+}
+
+hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t n, const int64_t* lattice,
+                            int64_t n_epochs, const int32_t* dur_sorted, int n_d, int dmax, int rowchunk,
+                            int nchunks, double* qpart) {
+  // dur_sorted: host array [2 * n_d]: ascending durations, then their caller indices
+  DurList dl{};
+  dl.n = n_d;
+  for (int k = 0; k < n_d; ++k) {
+    dl.d[k] = dur_sorted[k];
+    dl.perm[k] = dur_sorted[n_d + k];
+  }
+  const int wmax = QCH + dmax;
+  // rows staged per pass: at most 8, within 64 KB of LDS
+  const int qr = std::max(1, std::min(8, (int)(65536 / ((size_t)wmax * sizeof(double)))));
+  const size_t shm = (size_t)qr * wmax * sizeof(double);
+  hipLaunchKernelGGL(q_partial_kernel, dim3((unsigned)((n_epochs + QCH - 1) / QCH), (unsigned)nchunks), dim3(256),
+                     shm, s, X, ldx, n, lattice, n_epochs, dl, wmax, qr, rowchunk, qpart);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __restrict__ qpart, int nchunks,
+                                                            const int64_t* __restrict__ lattice, int64_t n,
+                                                            int64_t n_epochs, DurList dl,
+                                                            const double* __restrict__ Z, int m1,
+                                                            const NullFit* __restrict__ nf, double* __restrict__ depth,
+                                                            double* __restrict__ var, double* __restrict__ dll,
+                                                            uint8_t* __restrict__ valid) {
+  const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (cell >= (int64_t)dl.n * n_epochs) return;
+  const int j = (int)(cell / n_epochs);
+  const int64_t i = cell - (int64_t)j * n_epochs;
+  double q = 0.0;
+  for (int c = 0; c < nchunks; ++c) q += qpart[((int64_t)c * dl.n + j) * n_epochs + i];
+  const int d = dl.d[j];
+  const int64_t a = i - d / 2;
+  const int64_t lo = lower_bound_i64(lattice, n, a);
+  const int64_t hi = lower_bound_i64(lattice, n, a + d);
+  bool ok = (hi > lo) && nf->ok;
+  double h = 0.0, g[MAX_M1];
+#pragma unroll
+  for (int c = 0; c < MAX_M1; ++c) g[c] = 0.0;
+  if (ok) {
+    for (int64_t r = lo; r < hi; ++r) {
+      const double* zr = Z + r * YCOLS;
+#pragma unroll
+      for (int c = 0; c < MAX_M1; ++c)
+        if (c < m1) g[c] -= zr[c];
+      h -= zr[m1];
+    }
+  }
+  // S = q - g^T G0^-1 g via y = chol(G0)^-1 g
+  double gg = 0.0, y[MAX_M1];
+#pragma unroll
+  for (int r = 0; r < MAX_M1; ++r) {
+    if (r < m1) {
+      double v = g[r];
+#pragma unroll
+      for (int k = 0; k < MAX_M1; ++k)
+        if (k < r) v -= nf->G0chol[r * MAX_M1 + k] * y[k];
+      y[r] = v / nf->G0chol[r * MAX_M1 + r];
+      gg = fma(y[r], y[r], gg);
+    } else {
+      y[r] = 0.0;
+    }
+  }
+  const double S = q - gg;
+  ok = ok && (S > 0.0) && isfinite(S) && isfinite(h);
+  const int64_t o = (int64_t)j * n_epochs + i;
+  if (ok) {
+    const double dep = h / S;
+    depth[o] = dep;
+    var[o] = 1.0 / S;
+    dll[o] = 0.5 * h * dep;
+    valid[o] = 1;
+  } else {
+    depth[o] = 0.0;
+    var[o] = INFINITY;
+    dll[o] = 0.0;
+    valid[o] = 0;
+  }
+}
+
+hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks, const int64_t* lattice, int64_t n,
+                                int64_t n_epochs, const int32_t* dur, const int32_t* /*dur_rank*/, int n_d,
+                                const double* Z, int m1, const NullFit* nf, double* depth, double* var, double* dll,
+                                uint8_t* valid) {
+  DurList dl{};
+  dl.n = n_d;
+  for (int k = 0; k < n_d; ++k) {
+    dl.d[k] = dur[k];
+    dl.perm[k] = k;
+  }
+  const int64_t cells = (int64_t)n_d * n_epochs;
+  hipLaunchKernelGGL(cell_epilogue_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, qpart, nchunks,
+                     lattice, n, n_epochs, dl, Z, m1, nf, depth, var, dll, valid);
+  return hipGetLastError();
+}
+
+}  // namespace nu

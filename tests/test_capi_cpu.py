@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports
+every function include/nuance_mi355x.h declares, and the binding validates
+its arguments before calling into the library."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nuance_mi355x.h")
+
+
+@pytest.fixture(scope="module")
+def libpath():
+    from paper_2402_06835_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2402_06835_amd import build
+        build.build()
+    return _lib.LIB_PATH
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nu_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_three_entry_points():
+    names = declared_functions()
+    for n in ("nu_gp_factor", "nu_linear_search", "nu_periodic_search"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(libpath):
+    out = subprocess.run(["nm", "-D", "--defined-only", libpath], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\s[TW]\s+(\S+)$", out, flags=re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+
+
+def test_library_loads_and_binding_declares_every_symbol(libpath):
+    from paper_2402_06835_amd import _lib
+    L = _lib.lib()
+    for n in declared_functions():
+        assert hasattr(L, n)
+        assert n in _lib.SIGNATURES, f"binding lacks {n}"
+
+
+def test_null_context_is_rejected_without_a_gpu(libpath):
+    import ctypes
+    from paper_2402_06835_amd import _lib
+    L = _lib.lib()
+    # every entry point validates its context before touching the device
+    assert L.nu_gp_factor(None, None, 0, None, None, None, None) == _lib.NU_ERR_ARG
+    assert L.nu_linear_search(None, None, None, None, 0, None, 0, None, 0, 0, None, None, None, None,
+                              None) == _lib.NU_ERR_ARG
+    assert L.nu_periodic_search(None, None, None, None, None, 0, 0, 0.0, None, 0, 1, None, None, None, None,
+                                None, None, None) == _lib.NU_ERR_ARG
+    assert L.nu_ctx_create(0, None, None) == _lib.NU_ERR_ARG
+    assert L.nu_ctx_last_error(None) == b"null context"
+    assert L.nu_factor_n(None) == -1
+
+
+def test_nuance_rejects_off_lattice_time():
+    from paper_2402_06835_amd import api
+    t = np.array([0.0, 1.0, 2.5, 3.0])
+    with pytest.raises((ValueError, RuntimeError)):
+        api.Nuance(t, np.zeros(4), api.SHO(0.01, 3.0, 5.0, 1e-3), dt=1.0)
