@@ -124,7 +124,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmProblem* __r
     }
   }
 
-  // epilogue: lane holds rows 4*(lane/16) + i, column lane % 16 of each 16 x 16 block
+  // epilogue: item i of a lane is row lane/16 + 4 i, column lane % 16 of each
+  // 16 x 16 block (the f64 accumulator layout, measured on gfx950)
   const double alpha = P.alpha, beta = P.beta;
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmProblem* __r
     for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = m0 + wm + mi * 16 + lk * 4 + i;
+        const int row = m0 + wm + mi * 16 + lk + 4 * i;
         const int col = n0 + wn + ni * 16 + lr;
         double* c = P.C + (int64_t)row * P.ldc + col;
         double v = alpha * acc[mi][ni][i];
