@@ -1,0 +1,185 @@
+"""Benchmark of the transit-search hot path on one MI355X.
+
+One step = the whole hot path over one light curve already resident in HBM:
+gp_factor (covariance build + FP64 Cholesky) -> linear_search (triangular
+inverse, trend fit, every (epoch, duration) box fit) -> periodic_search (fold
+over all periods, best period). Workload: the TESS-sector-shaped curve
+(N = 18000 samples at 2-min cadence with a 1-d gap, 18720 epoch slots,
+10 durations of 9..90 samples, 20000 periods in [0.3, 13] d), synthetic and
+seeded.
+
+Prints one JSON line: value = valid (t0, D) fits per second of whole-step
+wall time (plus light curves per second), the roofline of the dominant
+kernel from HIP events recorded by the library around its launches inside
+the timed region, and the CPU oracle timed on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAKS = {"f64_mfma_tflops": 78.6, "hbm_gbs": 8000.0}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    from synth import config1, config2
+    return {"tess-sector": config2, "plain-1440": config1}[name]()
+
+
+def run_step(api, ctx, dev_in, w, precision):
+    fac = api.gp_factor(ctx, dev_in["t"], w.theta)
+    ls = api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations,
+                           precision)
+    ps = api.periodic_search(ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], w.dt, dev_in["periods"])
+    return fac, ls, ps
+
+
+def cpu_baseline(w, n_valid: int, budget_cells: int = 192, budget_periods: int = 4):
+    """The oracle on a bounded sample of the same workload, scaled to whole-step fits/s."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import gp as ogp, linear as olin, periodic as oper
+
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    log(f"cpu baseline: oracle K build + Cholesky at N={w.n} ({threads} BLAS threads)")
+    t0 = time.perf_counter()
+    K = ogp.covariance(w.t, w.theta)
+    L = ogp.cholesky(K)
+    del K
+    t_factor = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    n_d, n_t = w.durations.size, w.n_epochs
+    cells = [(int(rng.integers(n_d)), int(rng.integers(n_t))) for _ in range(budget_cells)]
+    log(f"cpu baseline: oracle GLS on {budget_cells} sampled cells")
+    t0 = time.perf_counter()
+    olin.linear_search(w.f, w.A, L, w.lattice, w.durations, cells=cells)
+    t_cells = time.perf_counter() - t0
+    # the fold needs the single-event grid; a synthetic one of the full shape costs the same
+    depth = rng.normal(2e-4, 3e-4, (n_d, n_t))
+    var = rng.uniform(4e-8, 1.2e-7, (n_d, n_t))
+    dll = 0.5 * depth ** 2 / var
+    valid = np.ones((n_d, n_t), dtype=np.uint8)
+    pidx = np.linspace(0, w.periods.size - 1, budget_periods).astype(int)
+    log(f"cpu baseline: oracle fold on {budget_periods} sampled periods")
+    t0 = time.perf_counter()
+    oper.periodic_search(depth, var, dll, valid, w.dt, w.periods[pidx])
+    t_fold = time.perf_counter() - t0
+    total = t_factor + t_cells / budget_cells * (n_d * n_t) + t_fold / budget_periods * w.periods.size
+    return {
+        "value": n_valid / total, "unit": "(t0,D) fits/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"K build + Cholesky of the full N={w.n} covariance ({t_factor:.1f} s), GLS of {budget_cells} "
+                   f"random cells ({t_cells:.1f} s), fold of {budget_periods} periods ({t_fold:.1f} s); "
+                   f"extrapolated to {n_d * n_t} cells and {w.periods.size} periods = {total:.0f} s per curve"),
+        "seconds_per_curve": total,
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="tess-sector", choices=["tess-sector", "plain-1440"])
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); curves shard across GPUs with no "
+              "communication but multi-GPU runs are not part of this build", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2402_06835_amd import _lib, api
+
+    _lib.lib()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda", 0)
+    log(f"workload {args.workload}: generating")
+    w = workload(args.workload)
+    dev_in = {
+        "t": torch.as_tensor(w.t, device=dev), "f": torch.as_tensor(w.f, device=dev),
+        "A": torch.as_tensor(w.A, device=dev), "lattice": torch.as_tensor(w.lattice, device=dev),
+        "periods": torch.as_tensor(w.periods, device=dev),
+    }
+    ctx = api.Context(0)
+    for i in range(args.warmup):
+        run_step(api, ctx, dev_in, w, args.precision)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    ctx.enable_timing(True)
+    ctx.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    keep = None
+    for i in range(args.steps):
+        keep = run_step(api, ctx, dev_in, w, args.precision)
+        log(f"step {i + 1}/{args.steps} enqueued")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timings = ctx.timings()
+    ctx.enable_timing(False)
+    fac, ls, ps = keep
+    n_valid = int(ls["valid"].sum().item())
+    best = int(ps["best_index"].item())
+    ms_step = elapsed / args.steps * 1e3
+    fits_per_s = n_valid * args.steps / elapsed
+    curves_per_s = args.steps / elapsed
+
+    # dominant kernel by accumulated time
+    dom = max(timings.items(), key=lambda kv: kv[1]["ms"])
+    name, tk = dom
+    roof = None
+    if name == "gemm_f64":
+        achieved = tk["work"] / (tk["ms"] * 1e-3) / 1e12
+        roof = {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAKS["f64_mfma_tflops"],
+                "unit": "TFLOP/s", "frac": achieved / PEAKS["f64_mfma_tflops"], "traffic": None,
+                "launches": tk["launches"], "avg_launch_ms": tk["ms"] / tk["launches"],
+                "work_per_launch": tk["work"] / tk["launches"], "work_unit": "flop (algorithmic)"}
+    else:
+        achieved = tk["work"] / (tk["ms"] * 1e-3) / 1e9
+        roof = {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+                "frac": achieved / PEAKS["hbm_gbs"], "traffic": None, "launches": tk["launches"],
+                "avg_launch_ms": tk["ms"] / tk["launches"], "work_per_launch": tk["work"] / tk["launches"],
+                "work_unit": "byte (algorithmic)"}
+    kernels = {k: {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps} for k, v in timings.items()}
+    log(f"{args.steps} steps in {elapsed:.3f} s: {fits_per_s:.4g} fits/s, {curves_per_s:.4g} curves/s; "
+        f"best period {w.periods[best] if best >= 0 else None}")
+    out = {
+        "metric": "(t0,D) GLS fits/s and light curves/s at Δll err ≤1e-6 vs FP64",
+        "value": fits_per_s, "unit": "(t0,D) fits/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else args.precision, "data": "synthetic",
+        "config": {"workload": w.name, "n_samples": w.n, "n_epochs": w.n_epochs,
+                   "n_durations": int(w.durations.size), "n_periods": int(w.periods.size),
+                   "valid_cells": n_valid, "precision": args.precision},
+        "light_curves_per_s": curves_per_s,
+        "roofline": roof,
+        "kernels": kernels,
+        "best_period_days": float(w.periods[best]) if best >= 0 else None,
+        "injected_period_days": w.injection["period"] if w.injection else None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, n_valid)
+        out["cpu_baseline"]["unit"] = out["unit"]
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
