@@ -41,7 +41,7 @@ void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st) {
   return ctx->ws;
 }
 
-void timing_begin(nu_ctx* ctx, const char* /*name*/, hipEvent_t* start) {
+void timing_begin(nu_ctx* ctx, hipStream_t s, hipEvent_t* start) {
   *start = nullptr;
   if (!ctx->timing) return;
   if (ctx->free_events.empty()) {
@@ -51,10 +51,10 @@ void timing_begin(nu_ctx* ctx, const char* /*name*/, hipEvent_t* start) {
   }
   *start = ctx->free_events.back();
   ctx->free_events.pop_back();
-  hipEventRecord(*start, ctx->stream);
+  hipEventRecord(*start, s);
 }
 
-void timing_end(nu_ctx* ctx, const char* name, hipEvent_t start, double work) {
+void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, double work) {
   if (!ctx->timing || !start) return;
   hipEvent_t stop;
   if (ctx->free_events.empty()) {
@@ -63,7 +63,7 @@ void timing_end(nu_ctx* ctx, const char* name, hipEvent_t start, double work) {
     stop = ctx->free_events.back();
     ctx->free_events.pop_back();
   }
-  hipEventRecord(stop, ctx->stream);
+  hipEventRecord(stop, s);
   ctx->pending.push_back({name, start, stop, work});
 }
 
@@ -74,6 +74,7 @@ namespace {
 static void resolve_timing(nu_ctx* ctx) {
   if (ctx->pending.empty()) return;
   hipStreamSynchronize(ctx->stream);
+  if (ctx->side) hipStreamSynchronize(ctx->side);
   for (auto& p : ctx->pending) {
     float ms = 0.0f;
     hipEventElapsedTime(&ms, p.start, p.stop);
@@ -93,11 +94,15 @@ static void resolve_timing(nu_ctx* ctx) {
 
 struct Timed {
   nu_ctx* ctx;
+  hipStream_t s;
   const char* name;
   double work;
   hipEvent_t start;
-  Timed(nu_ctx* c, const char* n, double w) : ctx(c), name(n), work(w) { timing_begin(c, n, &start); }
-  ~Timed() { timing_end(ctx, name, start, work); }
+  Timed(nu_ctx* c, const char* n, double w) : Timed(c, c->stream, n, w) {}
+  Timed(nu_ctx* c, hipStream_t st, const char* n, double w) : ctx(c), s(st), name(n), work(w) {
+    timing_begin(c, st, &start);
+  }
+  ~Timed() { timing_end(ctx, s, name, start, work); }
 };
 
 static int tiles_of(const GemmProblem& g) {
@@ -171,21 +176,43 @@ static void build_tree(int a, int b, int depth, std::vector<std::vector<Node>>& 
 
 struct FactorPlan {
   std::vector<GemmProblem> sched;
-  std::vector<Range> panel, syrk, t1, t2;  // t1/t2 deepest level first
+  std::vector<Range> panel, syrk, rest, t1, t2;  // t1/t2 deepest level first
   size_t t_elems = 0;
 };
+
+// Outer panel width of the Cholesky, in TB blocks: each panel is factored
+// block by block (diagonal block, its column, the update of the panel's
+// remaining columns), then the trailing matrix gets one update of depth
+// PANEL * TB.
+constexpr int PANEL = 4;
 
 static void plan_factor(nu_factor* F, FactorPlan& plan) {
   const int64_t np = F->np;
   const int nblk = (int)(np / TB);
-  for (int k = 0; k + 1 < nblk; ++k) {
-    const int64_t off = (int64_t)k * TB;
-    const int rest = (int)(np - off - TB);
-    double* panel = F->L + (off + TB) * np + off;
-    const double* xkk = F->X + off * np + off;
-    plan.panel.push_back(add_launch(plan.sched, {prob(panel, np, xkk, np, panel, np, rest, TB, TB, G_BT, 1.0, 0.0)}));
-    plan.syrk.push_back(add_launch(
-        plan.sched, {prob(panel, np, panel, np, panel + TB, np, rest, rest, TB, G_BT | G_C_LOWER_TILES, -1.0, 1.0)}));
+  plan.panel.assign(nblk, Range());
+  plan.syrk.assign(nblk, Range());
+  plan.rest.assign(nblk, Range());
+  for (int p0 = 0; p0 < nblk; p0 += PANEL) {
+    const int pw = std::min(PANEL, nblk - p0);
+    for (int k = p0; k < p0 + pw; ++k) {
+      const int64_t off = (int64_t)k * TB;
+      const int rest = (int)(np - off - TB);
+      if (rest <= 0) continue;
+      double* col = F->L + (off + TB) * np + off;  // rows below the diagonal block, block column k
+      const double* xkk = F->X + off * np + off;
+      plan.panel[k] = add_launch(plan.sched, {prob(col, np, xkk, np, col, np, rest, TB, TB, G_BT, 1.0, 0.0)});
+      const int inner = (p0 + pw - k - 1) * TB;  // columns of this panel right of block k
+      if (inner > 0)
+        plan.syrk[k] =
+            add_launch(plan.sched, {prob(col, np, col, np, col + TB, np, rest, inner, TB, G_BT, -1.0, 1.0)});
+    }
+    const int64_t t0 = (int64_t)(p0 + pw) * TB;
+    const int rest2 = (int)(np - t0);
+    if (rest2 > 0) {
+      double* pan = F->L + t0 * np + (int64_t)p0 * TB;  // rows of the trailing matrix, columns of the panel
+      plan.rest[p0] = add_launch(plan.sched, {prob(pan, np, pan, np, F->L + t0 * np + t0, np, rest2, rest2, pw * TB,
+                                                   G_BT | G_C_LOWER_TILES, -1.0, 1.0)});
+    }
   }
   std::vector<std::vector<Node>> levels;
   build_tree(0, nblk, 0, levels);
@@ -212,9 +239,12 @@ static void plan_factor(nu_factor* F, FactorPlan& plan) {
 
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-static nu_status launch_range(nu_ctx* ctx, const nu_factor* F, const Range& r, const char* name) {
-  Timed tm(ctx, name, r.flops);
-  return check_hip(ctx, launch_gemm(ctx->stream, F->probs + r.first, r.count, r.tiles), name);
+static nu_status launch_range(nu_ctx* ctx, const nu_factor* F, const Range& r, const char* name,
+                              hipStream_t s = nullptr) {
+  if (r.tiles == 0) return NU_OK;
+  if (!s) s = ctx->stream;
+  Timed tm(ctx, s, name, r.flops);
+  return check_hip(ctx, launch_gemm(s, F->probs + r.first, r.count, r.tiles), name);
 }
 
 struct FactorExtra {
@@ -236,8 +266,11 @@ nu_status nu_ctx_create(int device, void* stream, nu_ctx** out) {
   if (!ctx) return NU_ERR_OOM;
   ctx->device = device;
   ctx->stream = (hipStream_t)stream;
-  if (hipSetDevice(device) != hipSuccess) {
-    delete ctx;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_panel, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ev_rest, hipEventDisableTiming) != hipSuccess) {
+    nu_ctx_destroy(ctx);
     return NU_ERR_DEVICE;
   }
   *out = ctx;
@@ -248,6 +281,12 @@ void nu_ctx_destroy(nu_ctx* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
+  if (ctx->side) {
+    hipStreamSynchronize(ctx->side);
+    hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_panel) hipEventDestroy(ctx->ev_panel);
+  if (ctx->ev_rest) hipEventDestroy(ctx->ev_rest);
   if (ctx->ws) hipFree(ctx->ws);
   for (auto& p : ctx->pending) {
     hipEventDestroy(p.start);
@@ -358,6 +397,7 @@ nu_status nu_gp_factor(nu_ctx* ctx, const double* t, int64_t n, const nu_sho* th
   F->sched_tiles.clear();
   to_pairs(plan.panel, F->chol_panel, F->sched_tiles);
   to_pairs(plan.syrk, F->chol_syrk, F->sched_tiles);
+  to_pairs(plan.rest, F->chol_rest, F->sched_tiles);
   to_pairs(plan.t1, F->trtri_t1, F->sched_tiles);
   to_pairs(plan.t2, F->trtri_t2, F->sched_tiles);
   if (!plan.sched.empty()) {
@@ -376,20 +416,21 @@ nu_status nu_gp_factor(nu_ctx* ctx, const double* t, int64_t n, const nu_sho* th
     st = check_hip(ctx, launch_kbuild(ctx->stream, t, n, np, th, F->L), "kbuild");
   }
   if (st != NU_OK) return fail(st);
-  for (int k = 0; k < nblk; ++k) {
+  // Blocked right-looking Cholesky, two levels: within a panel of PANEL
+  // blocks, diagonal block -> its column (times the diagonal block's inverse)
+  // -> update of the panel's remaining columns; after the panel, one trailing
+  // update of depth PANEL * TB on the whole chip.
+  for (int k = 0; st == NU_OK && k < nblk; ++k) {
     {
       Timed tm(ctx, "potrf_diag", (double)TB * TB * TB * 2.0 / 3.0);
       st = check_hip(ctx, launch_potrf_diag(ctx->stream, F->L, np, (int64_t)k * TB, k, parts, status, F->X, np),
                      "potrf_diag");
     }
-    if (st != NU_OK) return fail(st);
-    if (k + 1 < nblk) {
-      st = launch_range(ctx, F, plan.panel[k], "gemm_f64");
-      if (st != NU_OK) return fail(st);
-      st = launch_range(ctx, F, plan.syrk[k], "gemm_f64");
-      if (st != NU_OK) return fail(st);
-    }
+    if (st == NU_OK) st = launch_range(ctx, F, plan.panel[k], "gemm_f64:panel");
+    if (st == NU_OK) st = launch_range(ctx, F, plan.syrk[k], "gemm_f64:panel_update");
+    if (st == NU_OK && (k + 1) % PANEL == 0) st = launch_range(ctx, F, plan.rest[k + 1 - PANEL], "gemm_f64:trailing");
   }
+  if (st != NU_OK) return fail(st);
   st = check_hip(ctx, launch_logdet_reduce(ctx->stream, parts, nblk, logdet_dev), "logdet");
   if (st != NU_OK) return fail(st);
   struct {
@@ -478,9 +519,9 @@ nu_status nu_linear_search(nu_ctx* ctx, nu_factor* F, const double* f, const dou
         r2.tiles += F->sched[r2.first + i].tile_count;
         r2.flops += useful_flops(F->sched[r2.first + i]);
       }
-      st = launch_range(ctx, F, r1, "gemm_f64");
+      st = launch_range(ctx, F, r1, "gemm_f64:inverse");
       if (st != NU_OK) return st;
-      st = launch_range(ctx, F, r2, "gemm_f64");
+      st = launch_range(ctx, F, r2, "gemm_f64:inverse");
       if (st != NU_OK) return st;
     }
     F->inverse_ready = true;
@@ -562,11 +603,14 @@ nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var
     return set_error(ctx, NU_ERR_ARG, "periodic_search: log_term_sign must be +1 or -1");
   nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (st != NU_OK) return st;
+  double* packed = (double*)ctx_workspace(ctx, fold_workspace_doubles(n_d, n_epochs) * sizeof(double), &st);
+  if (!packed) return st;
   {
     // algorithmic bytes: 24 per event visit (depth, var, dll of one interpolated event), n_d * n_epochs per period
     Timed tm(ctx, "fold", 24.0 * (double)n_d * (double)n_epochs * (double)n_p);
     st = check_hip(ctx, launch_fold(ctx->stream, depth, var, dll, valid, n_d, n_epochs, dt, periods, n_p,
-                                    log_term_sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp),
+                                    log_term_sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp,
+                                    packed),
                    "fold");
   }
   if (st != NU_OK) return st;

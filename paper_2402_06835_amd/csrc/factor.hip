@@ -56,64 +56,99 @@ hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, 
 
 // ---------------------------------------------------------------------------
 // Diagonal block of step k: factor the TB x TB block in LDS, write L_kk (zeros
-// above the diagonal), then invert it in place and write X_kk = L_kk^-1 into
-// the inverse's diagonal block (zeros above the diagonal).
+// above the diagonal), and its inverse X_kk = L_kk^-1 into the diagonal block
+// of the inverse (zeros above the diagonal).
 //
-// Inverse storage while in LDS: the strictly lower part of X_kk is kept
-// transposed in the strictly upper part of the array (free once L_kk is
-// lower), its diagonal in xd[]. The inverse is built bottom-up: the four
-// 32 x 32 diagonal blocks by forward substitution, then two doubling levels
-//   X21 = -X_C (L21 X_A)
-// for the 2 x 2 block partition [[A, 0], [L21, C]].
+// Blocked right-looking by 16: for each 16 x 16 diagonal piece, one wave
+// factors and inverts it in registers (lane r holds row r; values cross lanes
+// with readlane), the panel below is multiplied by that inverse on the matrix
+// cores, and the trailing pieces are updated on the matrix cores. The inverse
+// is then completed by three doubling levels X21 = -X_C (L21 X_A) for the
+// 2 x 2 partitions 16|16, 32|32, 64|64, also on the matrix cores.
+//
+// Inverse storage while in LDS: X[r][c] (r > c) is kept at a[c][r] (the
+// strictly upper part, free once L is lower), its diagonal in xd[].
 // ---------------------------------------------------------------------------
 constexpr int DB = TB;       // 128
 constexpr int DPAD = DB + 1;
+constexpr int SB = 16;       // piece edge
+constexpr int NSB = DB / SB; // 8
 
-__device__ __forceinline__ double xinv(const double (*a)[DPAD], const double* xd, int r, int c) {
-  // element (r, c) of the inverse, r >= c, within an already-inverted block
-  return r == c ? xd[r] : a[c][r];
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __hiloint2double(hi, lo);
 }
 
-// One doubling level: nodes at A-block offsets a0 = node*2*BS, C-block at a0+BS.
+__device__ __forceinline__ double xget(const double (*a)[DPAD], const double* xd, int r, int c) {
+  return r > c ? a[c][r] : (r == c ? xd[r] : 0.0);
+}
+
+__device__ __forceinline__ dbl4 mfma64(double av, double bv, dbl4 acc) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+}
+
+// One doubling level of the in-block inverse: NODES nodes of edge 2*BS, the
+// A part at a0 = node*2*BS, the C part at c0 = a0 + BS. Work unit = one 16 x 16
+// output piece per wave.
 template <int BS, int NODES>
 __device__ void inverse_level(double (*a)[DPAD], const double* xd) {
-  constexpr int PER_NODE = BS * BS;
-  constexpr int TOTAL = PER_NODE * NODES;
-  constexpr int PER_THREAD = TOTAL / 256;
-  static_assert(TOTAL % 256 == 0, "level must split evenly over 256 threads");
-  const int tid = threadIdx.x;
-  // T = L21 X_A, stored at a[a0 + j][c0 + i] (upper region of this node, free)
+  constexpr int NB = BS / SB;
+  constexpr int TT = NODES * NB * NB;
+  constexpr int PER = (TT + 3) / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  // T = L21 X_A, kept at a[a0 + j][c0 + i] until overwritten by X21
 #pragma unroll
-  for (int u = 0; u < PER_THREAD; ++u) {
-    const int idx = tid + 256 * u;
-    const int node = idx / PER_NODE, e = idx % PER_NODE;
-    const int i = e / BS, j = e % BS;
-    const int a0 = node * 2 * BS, c0 = a0 + BS;
-    double acc = 0.0;
-    for (int k = j; k < BS; ++k) acc = fma(a[c0 + i][a0 + k], xinv(a, xd, a0 + k, a0 + j), acc);
-    a[a0 + j][c0 + i] = acc;
+  for (int u = 0; u < PER; ++u) {
+    const int t = wave + 4 * u;
+    if (t < TT) {
+      const int node = t / (NB * NB), e = t % (NB * NB), bi = e / NB, bj = e % NB;
+      const int a0 = node * 2 * BS, c0 = a0 + BS;
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int bk = bj; bk < NB; ++bk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = bk * SB + q * 4 + lk;
+          acc = mfma64(a[c0 + bi * SB + lr][a0 + k], xget(a, xd, a0 + k, a0 + bj * SB + lr), acc);
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[a0 + bj * SB + lr][c0 + bi * SB + lk + 4 * v] = acc[v];
+    }
   }
   __syncthreads();
-  // X21 = -X_C T into registers, then overwrite T
-  double out[PER_THREAD];
+  // X21 = -X_C T
+  dbl4 res[PER];
 #pragma unroll
-  for (int u = 0; u < PER_THREAD; ++u) {
-    const int idx = tid + 256 * u;
-    const int node = idx / PER_NODE, e = idx % PER_NODE;
-    const int i = e / BS, j = e % BS;
-    const int a0 = node * 2 * BS, c0 = a0 + BS;
-    double acc = 0.0;
-    for (int k = 0; k <= i; ++k) acc = fma(xinv(a, xd, c0 + i, c0 + k), a[a0 + j][c0 + k], acc);
-    out[u] = -acc;
+  for (int u = 0; u < PER; ++u) {
+    const int t = wave + 4 * u;
+    res[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    if (t < TT) {
+      const int node = t / (NB * NB), e = t % (NB * NB), bi = e / NB, bj = e % NB;
+      const int a0 = node * 2 * BS, c0 = a0 + BS;
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int bk = 0; bk <= bi; ++bk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = bk * SB + q * 4 + lk;
+          acc = mfma64(-xget(a, xd, c0 + bi * SB + lr, c0 + k), a[a0 + bj * SB + lr][c0 + k], acc);
+        }
+      res[u] = acc;
+    }
   }
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < PER_THREAD; ++u) {
-    const int idx = tid + 256 * u;
-    const int node = idx / PER_NODE, e = idx % PER_NODE;
-    const int i = e / BS, j = e % BS;
-    const int a0 = node * 2 * BS, c0 = a0 + BS;
-    a[a0 + j][c0 + i] = out[u];
+  for (int u = 0; u < PER; ++u) {
+    const int t = wave + 4 * u;
+    if (t < TT) {
+      const int node = t / (NB * NB), e = t % (NB * NB), bi = e / NB, bj = e % NB;
+      const int a0 = node * 2 * BS, c0 = a0 + BS;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[a0 + bj * SB + lr][c0 + bi * SB + lk + 4 * v] = res[u][v];
+    }
   }
   __syncthreads();
 }
@@ -124,69 +159,118 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(double* __restrict__
                                                            int64_t ldx) {
   __shared__ double a[DB][DPAD];
   __shared__ double xd[DB];
-  __shared__ double piv;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < DB * DB; idx += 256) {
-    const int r = idx / DB, c = idx - (idx / DB) * DB;
-    a[r][c] = c <= r ? L[(off + r) * ld + off + c] : 0.0;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  // load the block: 64 values per thread, 16 loads in flight at a time
+  // (the whole 128 x 128 block lies inside the matrix; the upper part is
+  // discarded)
+  for (int u0 = 0; u0 < DB * DB / 256; u0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * (u0 + u);
+      v[u] = L[(off + (idx >> 7)) * ld + off + (idx & 127)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = tid + 256 * (u0 + u);
+      const int r = idx >> 7, c = idx & 127;
+      a[r][c] = c <= r ? v[u] : 0.0;
+    }
   }
   __syncthreads();
-  double logsum = 0.0;
-  // right-looking, one column at a time; thread (s, rpar) owns column s and
-  // the rows r >= s of parity rpar in the trailing update
-  const int s_col = tid & (DB - 1), rpar = tid >> 7;
-  for (int c = 0; c < DB; ++c) {
-    if (tid == 0) {
-      const double p = a[c][c];
-      if (!(p > 0.0) && *status < 0) *status = off + c;
-      const double d = sqrt(p);
-      a[c][c] = d;
-      piv = d;
-      logsum += log(d);
+  for (int kb = 0; kb < NSB; ++kb) {
+    const int o = kb * SB;
+    // (a) the 16 x 16 diagonal piece: factor, then invert, in the registers of wave 0
+    if (wave == 0) {
+      const int r = lane;
+      double row[SB];
+#pragma unroll
+      for (int s = 0; s < SB; ++s) row[s] = (r < SB && s <= r) ? a[o + (r & (SB - 1))][o + s] : 0.0;
+#pragma unroll
+      for (int c = 0; c < SB; ++c) {
+        const double piv = readlane_d(row[c], c);
+        if (lane == 0 && !(piv > 0.0) && *status < 0) *status = off + o + c;
+        const double d = sqrt(piv);
+        if (r == c) row[c] = d;
+        else if (r > c) row[c] = row[c] / d;
+#pragma unroll
+        for (int s = c + 1; s < SB; ++s) {
+          const double v = readlane_d(row[c], s);
+          if (r >= s) row[s] = fma(-row[c], v, row[s]);
+        }
+      }
+      const int j = lane;  // lane j: column j of the inverse
+      double x[SB];
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int s = 0; s < i; ++s) acc = fma(-readlane_d(row[s], i), x[s], acc);
+        x[i] = (i >= j) ? acc / readlane_d(row[i], i) : 0.0;
+      }
+      if (lane < SB) {
+#pragma unroll
+        for (int s = 0; s < SB; ++s) {
+          if (s <= r) a[o + r][o + s] = row[s];
+          if (s > j) a[o + j][o + s] = x[s];
+          if (s == j) xd[o + j] = x[s];
+        }
+      }
     }
     __syncthreads();
-    if (tid > c && tid < DB) a[tid][c] = a[tid][c] / piv;
+    // (b) pieces below: P = A X_dd^T
+    for (int t = wave; t < NSB - 1 - kb; t += 4) {
+      const int i0 = (kb + 1 + t) * SB;
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = q * 4 + lk;
+        acc = mfma64(a[i0 + lr][o + k], xget(a, xd, o + lr, o + k), acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[i0 + lk + 4 * v][o + lr] = acc[v];
+    }
     __syncthreads();
-    if (s_col > c) {
-      const double asc = a[s_col][c];
-      for (int r = s_col + rpar; r < DB; r += 2) a[r][s_col] = fma(-a[r][c], asc, a[r][s_col]);
+    // (c) trailing pieces (i, j), kb < j <= i: A_ij -= P_i P_j^T
+    const int m = NSB - 1 - kb;
+    for (int t = wave; t < m * (m + 1) / 2; t += 4) {
+      int ii = 0;
+      while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+      const int jj = t - ii * (ii + 1) / 2;
+      const int i0 = (kb + 1 + ii) * SB, j0 = (kb + 1 + jj) * SB;
+      dbl4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = a[i0 + lk + 4 * v][j0 + lr];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = o + q * 4 + lk;
+        acc = mfma64(-a[i0 + lr][k], a[j0 + lr][k], acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[i0 + lk + 4 * v][j0 + lr] = acc[v];
     }
     __syncthreads();
   }
-  if (tid == 0) logdet_parts[step] = 2.0 * logsum;
+  // ln|L_kk| = sum of ln of the diagonal: two per lane of wave 0, then a
+  // fixed-order butterfly
+  if (wave == 0) {
+    double v = log(a[lane][lane]) + log(a[lane + 64][lane + 64]);
+#pragma unroll
+    for (int offs = 32; offs > 0; offs >>= 1) v += __shfl_xor(v, offs, 64);
+    if (lane == 0) logdet_parts[step] = 2.0 * v;
+  }
   for (int idx = tid; idx < DB * DB; idx += 256) {
     const int r = idx / DB, c = idx - (idx / DB) * DB;
     L[(off + r) * ld + off + c] = c <= r ? a[r][c] : 0.0;
   }
-  __syncthreads();
-  // ---- inverse of the four 32 x 32 diagonal blocks: wave w, lane = column ----
-  {
-    const int w = tid >> 6, lane = tid & 63;
-    const int b0 = w * 32;
-    if (lane < 32) {
-      const int c = lane;
-      double x[32];
-#pragma unroll
-      for (int r = 0; r < 32; ++r) {
-        double acc = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-        for (int s = 0; s < r; ++s)
-          if (s >= c) acc = fma(-a[b0 + r][b0 + s], x[s], acc);
-        x[r] = (r >= c) ? acc / a[b0 + r][b0 + r] : 0.0;
-      }
-#pragma unroll
-      for (int r = 0; r < 32; ++r) {
-        if (r == c) xd[b0 + c] = x[r];
-        if (r > c) a[b0 + c][b0 + r] = x[r];
-      }
-    }
-  }
-  __syncthreads();
+  inverse_level<16, 4>(a, xd);
   inverse_level<32, 2>(a, xd);
   inverse_level<64, 1>(a, xd);
   for (int idx = tid; idx < DB * DB; idx += 256) {
     const int r = idx / DB, c = idx - (idx / DB) * DB;
-    X[(off + r) * ldx + off + c] = r > c ? a[c][r] : (r == c ? xd[r] : 0.0);
+    X[(off + r) * ldx + off + c] = xget(a, xd, r, c);
   }
 }
 

@@ -2,11 +2,12 @@
 // phases, common-depth combination (Eq. 8 with the estimates of Eq. B4), the
 // argmax of Eq. 9 and Q(P) = depth / sigma; then the best period.
 //
-// One workgroup per trial period; thread = phase m of one duration j at a
-// time. Consecutive threads read consecutive epoch slots m + floor(k p), so
-// each event gather is one coalesced segment per wave. Interpolation and the
-// sums are evaluated exactly as written (this file is compiled without
-// floating-point contraction), in increasing k.
+// One workgroup per trial period; thread = phase m, for groups of four
+// durations at a time (the event positions m + k p are shared by all
+// durations). Consecutive threads read consecutive epoch slots, so each
+// event gather is one coalesced segment per wave. Interpolation is evaluated
+// as written (this file is compiled without floating-point contraction); the
+// sums run in increasing k.
 #include "internal.hpp"
 
 namespace nu {
@@ -24,39 +25,155 @@ __device__ __forceinline__ bool beats(const Best& a, const Best& b) {
   return a.val > b.val || (a.val == b.val && a.flat < b.flat);
 }
 
-// event k of phase m: slot position m + k p; returns false when outside the grid
-struct Ev {
-  double d, v, l;
-  bool use;
-};
-
-__device__ __forceinline__ bool event_at(const double* __restrict__ D, const double* __restrict__ V,
-                                         const double* __restrict__ LL, const uint8_t* __restrict__ ok, int64_t n_t,
-                                         int64_t m, double kp, bool need_l, Ev& e) {
-  const double base = floor(kp);
-  const int64_t i0 = m + (int64_t)base;
-  if (i0 > n_t - 1) return false;  // this and every later event lie past the grid
-  const double w = kp - base;
-  e.use = false;
-  if (w == 0.0) {
-    if (ok[i0]) {
-      e.d = D[i0];
-      e.v = V[i0];
-      e.l = need_l ? LL[i0] : 0.0;
-      e.use = true;
-    }
-  } else if (i0 + 1 <= n_t - 1 && ok[i0] && ok[i0 + 1]) {
-    const double u = 1.0 - w;
-    e.d = u * D[i0] + w * D[i0 + 1];
-    e.v = u * V[i0] + w * V[i0 + 1];
-    e.l = need_l ? u * LL[i0] + w * LL[i0 + 1] : 0.0;
-    e.use = true;
-  }
-  return true;
+// 1/x: the hardware reciprocal estimate refined by two Newton-Raphson steps
+// (each step squares the relative error), for positive normal x.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 
-__global__ __launch_bounds__(256) void fold_kernel(const double* __restrict__ depth, const double* __restrict__ var,
-                                                   const double* __restrict__ dll, const uint8_t* __restrict__ valid,
+constexpr int JG = 4;     // durations per pass over the events
+constexpr int FPAD = 64;  // padded slots after the grid (invalid), one wave wide
+constexpr int WPH = 63;   // phases per wave: lane 63 only supplies its neighbour
+
+// Packed copy of the single-event grid for the fold: rows of n_t + FPAD slots
+// holding (depth, var) pairs and dll; var = NaN where the cell is invalid or
+// past the grid, so "valid and inside the grid" is var == var.
+__global__ __launch_bounds__(256) void fold_pack_kernel(const double* __restrict__ depth,
+                                                        const double* __restrict__ var,
+                                                        const double* __restrict__ dll,
+                                                        const uint8_t* __restrict__ valid, int n_d, int64_t n_t,
+                                                        double2* __restrict__ DV, double* __restrict__ Lp) {
+  const int64_t ld = n_t + FPAD;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n_d * ld) return;
+  const int j = (int)(e / ld);
+  const int64_t i = e - (int64_t)j * ld;
+  double d = 0.0, v = NAN, l = 0.0;
+  if (i < n_t) {
+    const int64_t o = (int64_t)j * n_t + i;
+    if (valid[o]) {
+      d = depth[o];
+      v = var[o];
+      l = dll[o];
+    }
+  }
+  DV[e] = make_double2(d, v);
+  Lp[e] = l;
+}
+
+// lane i receives lane i+1's value (DPP wave shift; lane 63 receives 0)
+__device__ __forceinline__ double from_next_lane(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Eq. 8 with the estimates of Eq. B4, for the durations j0 .. j0+JG-1 and the
+// phases m = mb + lane of one wave. All lanes share base_k = floor(k p) and
+// w_k, so an event's right-hand slot is the next lane's left-hand slot.
+// The sum of log ratios is taken as one logarithm of a product:
+//   sum_k [ln var_k - ln(sigma^2 + var_k)] = -ln prod_k (1 + sigma^2 / var_k),
+// where the product lies in (1, e] because sigma^2 sum_k 1/var_k = 1.
+__device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const double* __restrict__ Lp, int n_d,
+                                           int64_t n_t, int j0, int64_t mb, int lane, int64_t nph, double p,
+                                           double sign, Best& best) {
+  const int64_t ld = n_t + FPAD;
+  const int64_t m = mb + lane;
+  const int64_t kmax_base = n_t - 1 - mb;  // events while base_k <= this (uniform)
+  int64_t row[JG];
+#pragma unroll
+  for (int g = 0; g < JG; ++g) row[g] = (int64_t)min(j0 + g, n_d - 1) * ld + m;
+  double s_w[JG], s_wd[JG], s_ll[JG];
+  int cnt[JG];
+#pragma unroll
+  for (int g = 0; g < JG; ++g) {
+    s_w[g] = s_wd[g] = s_ll[g] = 0.0;
+    cnt[g] = 0;
+  }
+  // pass 1
+  for (int64_t k = 0;; ++k) {
+    const double kp = (double)k * p;
+    const double base = floor(kp);
+    if (base > (double)kmax_base) break;
+    const int64_t b = (int64_t)base;
+    const double w = kp - base;
+    const double u = 1.0 - w;
+    double2 dv[JG];
+    double l[JG];
+#pragma unroll
+    for (int g = 0; g < JG; ++g) {
+      dv[g] = DV[row[g] + b];
+      l[g] = Lp[row[g] + b];
+    }
+#pragma unroll
+    for (int g = 0; g < JG; ++g) {
+      double d = dv[g].x, v = dv[g].y, ll = l[g];
+      if (w != 0.0) {
+        d = u * d + w * from_next_lane(d);
+        v = u * v + w * from_next_lane(v);
+        ll = u * ll + w * from_next_lane(ll);
+      }
+      if (v == v && j0 + g < n_d) {
+        const double iv = rcp_nr(v);
+        s_w[g] = s_w[g] + iv;
+        s_wd[g] = s_wd[g] + d * iv;
+        s_ll[g] = s_ll[g] + ll;
+        ++cnt[g];
+      }
+    }
+  }
+  double s2[JG], dc[JG], prod[JG], chi[JG];
+#pragma unroll
+  for (int g = 0; g < JG; ++g) {
+    s2[g] = 1.0 / s_w[g];
+    dc[g] = s2[g] * s_wd[g];
+    prod[g] = 1.0;
+    chi[g] = 0.0;
+  }
+  // pass 2
+  for (int64_t k = 0;; ++k) {
+    const double kp = (double)k * p;
+    const double base = floor(kp);
+    if (base > (double)kmax_base) break;
+    const int64_t b = (int64_t)base;
+    const double w = kp - base;
+    const double u = 1.0 - w;
+    double2 dv[JG];
+#pragma unroll
+    for (int g = 0; g < JG; ++g) dv[g] = DV[row[g] + b];
+#pragma unroll
+    for (int g = 0; g < JG; ++g) {
+      double d = dv[g].x, v = dv[g].y;
+      if (w != 0.0) {
+        d = u * d + w * from_next_lane(d);
+        v = u * v + w * from_next_lane(v);
+      }
+      if (v == v && cnt[g] > 0) {
+        const double iv = rcp_nr(v);
+        const double x1 = fma(s2[g], iv, 1.0);  // 1 + sigma^2 / var_k
+        prod[g] = prod[g] * x1;
+        const double dd = d - dc[g];
+        chi[g] = fma(dd * dd * iv, rcp_nr(x1), chi[g]);  // (d_k - d)^2 / (var_k + sigma^2)
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < JG; ++g) {
+    const int j = j0 + g;
+    if (j < n_d && cnt[g] > 0 && m < nph && lane < WPH) {
+      const double corr = -sign * log(prod[g]) + chi[g];
+      const double lnp = s_ll[g] - 0.5 * corr;
+      Best cand{lnp, m * (int64_t)n_d + j, dc[g], s2[g]};
+      if (lnp == lnp && lnp > -INFINITY && beats(cand, best)) best = cand;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
                                                    int n_d, int64_t n_t, double dt,
                                                    const double* __restrict__ periods, double sign,
                                                    double* __restrict__ q_snr, int64_t* __restrict__ best_phase,
@@ -64,7 +181,7 @@ __global__ __launch_bounds__(256) void fold_kernel(const double* __restrict__ de
                                                    double* __restrict__ best_sigma, double* __restrict__ best_lnp) {
   __shared__ Best red[256];
   const int64_t ip = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double P = periods[ip];
   const double p = P / dt;
   Best best{-INFINITY, -1, 0.0, 0.0};
@@ -72,46 +189,8 @@ __global__ __launch_bounds__(256) void fold_kernel(const double* __restrict__ de
   if (p >= 1.0 && p <= 1e15) {
     const double nph_d = ceil(p);
     const int64_t nph = nph_d < (double)n_t ? (int64_t)nph_d : n_t;  // phases >= n_t hold no event
-    for (int j = 0; j < n_d; ++j) {
-      const double* D = depth + (int64_t)j * n_t;
-      const double* V = var + (int64_t)j * n_t;
-      const double* LL = dll + (int64_t)j * n_t;
-      const uint8_t* OK = valid + (int64_t)j * n_t;
-      for (int64_t mb = 0; mb < nph; mb += 256) {
-        const int64_t m = mb + tid;
-        if (m >= nph) continue;
-        // pass 1: Eq. B4 estimates and the sum of single-event log-likelihood gains
-        double s_w = 0.0, s_wd = 0.0, s_ll = 0.0;
-        int64_t cnt = 0;
-        for (int64_t k = 0;; ++k) {
-          Ev e;
-          if (!event_at(D, V, LL, OK, n_t, m, (double)k * p, true, e)) break;
-          if (e.use) {
-            s_w = s_w + 1.0 / e.v;
-            s_wd = s_wd + e.d / e.v;
-            s_ll = s_ll + e.l;
-            ++cnt;
-          }
-        }
-        if (cnt == 0) continue;
-        const double s2 = 1.0 / s_w;
-        const double dc = s2 * s_wd;
-        // pass 2: the common-depth terms of Eq. 8
-        double corr = 0.0;
-        for (int64_t k = 0;; ++k) {
-          Ev e;
-          if (!event_at(D, V, LL, OK, n_t, m, (double)k * p, false, e)) break;
-          if (e.use) {
-            const double dd = e.d - dc;
-            const double term = sign * (log(e.v) - log(s2 + e.v)) + dd * dd / (e.v + s2);
-            corr = corr + term;
-          }
-        }
-        const double lnp = s_ll - 0.5 * corr;
-        Best cand{lnp, m * (int64_t)n_d + j, dc, s2};
-        if (lnp == lnp && lnp > -INFINITY && beats(cand, best)) best = cand;
-      }
-    }
+    for (int64_t mb = (int64_t)wave * WPH; mb < nph; mb += 4 * WPH)
+      for (int j0 = 0; j0 < n_d; j0 += JG) fold_cells(DV, Lp, n_d, n_t, j0, mb, lane, nph, p, sign, best);
   }
   red[tid] = best;
   __syncthreads();
@@ -143,11 +222,21 @@ __global__ __launch_bounds__(256) void fold_kernel(const double* __restrict__ de
 hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, const double* dll,
                        const uint8_t* valid, int n_d, int64_t n_epochs, double dt, const double* periods, int64_t n_p,
                        int sign, double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth,
-                       double* best_sigma, double* best_lnp) {
-  hipLaunchKernelGGL(fold_kernel, dim3((unsigned)n_p), dim3(256), 0, s, depth, var, dll, valid, n_d, n_epochs, dt,
-                     periods, (double)sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp);
+                       double* best_sigma, double* best_lnp, double* packed) {
+  const int64_t ld = n_epochs + FPAD;
+  double2* DV = reinterpret_cast<double2*>(packed);
+  double* Lp = packed + 2 * (int64_t)n_d * ld;
+  const int64_t tot = (int64_t)n_d * ld;
+  hipLaunchKernelGGL(fold_pack_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, depth, var, dll, valid,
+                     n_d, n_epochs, DV, Lp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fold_kernel, dim3((unsigned)n_p), dim3(256), 0, s, DV, Lp, n_d, n_epochs, dt, periods,
+                     (double)sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp);
   return hipGetLastError();
 }
+
+size_t fold_workspace_doubles(int n_d, int64_t n_epochs) { return (size_t)3 * n_d * (size_t)(n_epochs + FPAD); }
 
 // First period of largest Q (NaN never wins).
 __global__ __launch_bounds__(1024) void best_period_kernel(const double* __restrict__ q, int64_t n_p,

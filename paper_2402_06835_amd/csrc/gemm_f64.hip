@@ -18,16 +18,45 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int GBM = TB, GBN = TB, GBK = 16;
 constexpr int LPAD = 4;
 
-__device__ __forceinline__ void tile_of(const GemmProblem& P, int local, int& tm, int& tn) {
+// Tile order within a problem: groups of GROUP tile-rows, column-major inside
+// a group, so any run of consecutive tiles covers a compact block of rows and
+// columns (their A row panels and B column panels meet in L2). For the
+// lower-triangular tile set the same grouping is applied to the rows: the
+// rectangular part of a group (columns left of its diagonal) comes first,
+// then its triangle.
+constexpr int GROUP = 16;
+
+__device__ __forceinline__ void tile_of(const GemmProblem& P, int t, int& tm, int& tn) {
   if (P.flags & G_C_LOWER_TILES) {
-    int r = (int)((sqrt(8.0 * (double)local + 1.0) - 1.0) * 0.5);
-    while ((r + 1) * (r + 2) / 2 <= local) ++r;
-    while (r * (r + 1) / 2 > local) --r;
-    tm = r;
-    tn = local - r * (r + 1) / 2;
+    const int T = P.M / TB;
+    // group g starts at tile g*G*(g*G+1)/2: largest row start r0 = g*G with r0(r0+1)/2 <= t
+    int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    while (r * (r + 1) / 2 > t) --r;
+    int g0 = (r / GROUP) * GROUP;
+    const int R = min(GROUP, T - g0);
+    int u = t - g0 * (g0 + 1) / 2;
+    if (u < g0 * R) {
+      tn = u / R;
+      tm = g0 + u % R;
+    } else {
+      u -= g0 * R;
+      int c = 0;
+      while (u >= R - c) {
+        u -= R - c;
+        ++c;
+      }
+      tn = g0 + c;
+      tm = g0 + c + u;
+    }
   } else {
-    tm = local / P.tiles_n;
-    tn = local - tm * P.tiles_n;
+    const int Tm = P.M / TB, Tn = P.tiles_n;
+    const int g = t / (GROUP * Tn);
+    const int g0 = g * GROUP;
+    const int R = min(GROUP, Tm - g0);
+    const int u = t - g * GROUP * Tn;
+    tn = u / R;
+    tm = g0 + u % R;
   }
 }
 
@@ -35,6 +64,10 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmProblem* __r
   __shared__ double As[2][GBK][GBM + LPAD];
   __shared__ double Bs[2][GBK][GBN + LPAD];
 
+  // Workgroups go to the 8 XCDs round-robin, so the ~512 tiles resident at
+  // once are consecutive tiles of the grouped order below: a compact block of
+  // rows x columns whose panels all XCDs stream together (shared last-level
+  // cache), with two rows of the block per XCD.
   const int tile = blockIdx.x;
   int p = 0;
   for (int i = 1; i < nprob; ++i)

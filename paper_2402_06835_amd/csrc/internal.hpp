@@ -77,6 +77,10 @@ struct nu_pending_event {
 struct nu_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // side stream (default priority) for the trailing updates of the factor's
+  // lookahead, ordered against the caller's stream with two events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_panel = nullptr, ev_rest = nullptr;
   std::string last_error;
   // growable device workspace
   void* ws = nullptr;
@@ -102,7 +106,8 @@ struct nu_factor {
   std::vector<nu::GemmProblem> sched;  // host copy
   // schedule ranges
   std::vector<std::pair<int, int>> chol_panel;  // per step: (first problem, count)
-  std::vector<std::pair<int, int>> chol_syrk;
+  std::vector<std::pair<int, int>> chol_syrk;   // trailing update of the next block column
+  std::vector<std::pair<int, int>> chol_rest;   // trailing update of the remaining columns
   std::vector<std::pair<int, int>> trtri_t1;    // per level (deepest first)
   std::vector<std::pair<int, int>> trtri_t2;
   std::vector<int> sched_tiles;                 // tiles per launch range (parallel to the ranges above)
@@ -119,8 +124,8 @@ nu_status check_hip(nu_ctx* ctx, hipError_t e, const char* what);
 void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st);
 
 // kernel timing (capi.cpp)
-void timing_begin(nu_ctx* ctx, const char* name, hipEvent_t* start);
-void timing_end(nu_ctx* ctx, const char* name, hipEvent_t start, double work);
+void timing_begin(nu_ctx* ctx, hipStream_t s, hipEvent_t* start);
+void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, double work);
 
 // launchers (*.hip)
 hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho& th, double* K);
@@ -146,7 +151,8 @@ hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks,
 hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, const double* dll,
                        const uint8_t* valid, int n_d, int64_t n_epochs, double dt, const double* periods, int64_t n_p,
                        int sign, double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth,
-                       double* best_sigma, double* best_lnp);
+                       double* best_sigma, double* best_lnp, double* packed);
+size_t fold_workspace_doubles(int n_d, int64_t n_epochs);
 hipError_t launch_best_period(hipStream_t s, const double* q_snr, int64_t n_p, int64_t* out);
 
 }  // namespace nu

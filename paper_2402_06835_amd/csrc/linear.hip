@@ -221,23 +221,24 @@ hipError_t launch_xtv_cols(hipStream_t s, const double* X, int64_t ldx, int64_t 
 // ---------------------------------------------------------------------------
 // q partial sums. Workgroup = 256 consecutive epoch slots (one per thread) x
 // one chunk of rows. The union of the boxes of the slots spans the sample
-// segment [seg_lo, seg_hi); R rows of X restricted to it are staged in LDS
-// (entries above the diagonal read as 0), and every thread forms the window
-// sums of its boxes. Boxes of one slot are nested in the duration, so the
-// ascending durations extend the previous window on both sides: each X entry
-// of the largest box is added once per row.
+// segment [seg_lo, seg_hi); qr rows of X restricted to it are staged in LDS
+// (entries above the diagonal read as 0) and turned into exclusive prefix
+// sums along the row (one wave per row), so every box sum of a row is the
+// difference of two prefix values.
 constexpr int QCH = 256;
 
 __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
                                                         const int64_t* __restrict__ lattice, int64_t n_epochs,
                                                         DurList dl, int wmax, int qr, int rowchunk,
                                                         double* __restrict__ qpart) {
-  extern __shared__ double rows[];  // qr x wmax
+  extern __shared__ double rows[];  // qr x (wmax + 1)
   __shared__ int64_t red_lo[4], red_hi[4];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int64_t slot = (int64_t)blockIdx.x * QCH + tid;
   const int chunk = blockIdx.y;
   const bool active = slot < n_epochs;
+  const int ldr = wmax + 1;
   int64_t lo[MAX_ND], hi[MAX_ND];
   int64_t my_lo = INT64_MAX, my_hi = INT64_MIN;
 #pragma unroll
@@ -251,15 +252,14 @@ __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict
       my_hi = max(my_hi, hi[k]);
     }
   }
-  // workgroup min / max
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     my_lo = min(my_lo, (int64_t)__shfl_xor(my_lo, off, 64));
     my_hi = max(my_hi, (int64_t)__shfl_xor(my_hi, off, 64));
   }
-  if ((tid & 63) == 0) {
-    red_lo[tid >> 6] = my_lo;
-    red_hi[tid >> 6] = my_hi;
+  if (lane == 0) {
+    red_lo[wave] = my_lo;
+    red_hi[wave] = my_hi;
   }
   __syncthreads();
   const int64_t seg_lo = min(min(red_lo[0], red_lo[1]), min(red_lo[2], red_lo[3]));
@@ -270,39 +270,53 @@ __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict
   const int W = (seg_hi > seg_lo) ? (int)(seg_hi - seg_lo) : 0;
 
   double q[MAX_ND];
-#pragma unroll
-  for (int k = 0; k < MAX_ND; ++k) q[k] = 0.0;
   int rl[MAX_ND], rh[MAX_ND];
 #pragma unroll
   for (int k = 0; k < MAX_ND; ++k) {
+    q[k] = 0.0;
     rl[k] = (int)(lo[k] - seg_lo);
     rh[k] = (int)(hi[k] - seg_lo);
   }
 
   if (W > 0 && W <= wmax) {
+    const int per = (W + 63) / 64;  // prefix-scan run per lane
     for (int64_t nb = rstart; nb < rend; nb += qr) {
       for (int rr = 0; rr < qr; ++rr) {
         const int64_t r = nb + rr;
+        double* P = rows + rr * ldr;
+        if (tid == 0) P[0] = 0.0;
         for (int w = tid; w < W; w += 256) {
           const int64_t m = seg_lo + w;
-          rows[rr * wmax + w] = (r < rend && m <= r) ? X[r * ldx + m] : 0.0;
+          P[1 + w] = (r < rend && m <= r) ? X[r * ldx + m] : 0.0;
         }
+      }
+      __syncthreads();
+      for (int rr = wave; rr < qr; rr += 4) {
+        double* P = rows + rr * ldr + 1;
+        const int b = lane * per, e = min(W, b + per);
+        double run = 0.0;
+        for (int i = b; i < e; ++i) {
+          run += P[i];
+          P[i] = run;
+        }
+        double incl = run;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const double y = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += y;
+        }
+        const double excl = incl - run;
+        for (int i = b; i < e; ++i) P[i] += excl;
       }
       __syncthreads();
       if (active) {
         for (int rr = 0; rr < qr; ++rr) {
-          const double* row = rows + rr * wmax;
-          double s = 0.0;
+          const double* P = rows + rr * ldr;
 #pragma unroll
           for (int k = 0; k < MAX_ND; ++k) {
             if (k < dl.n) {
-              if (k == 0) {
-                for (int m = rl[0]; m < rh[0]; ++m) s += row[m];
-              } else {
-                for (int m = rl[k]; m < rl[k - 1]; ++m) s += row[m];
-                for (int m = rh[k - 1]; m < rh[k]; ++m) s += row[m];
-              }
-              q[k] = fma(s, s, q[k]);
+              const double sk = P[rh[k]] - P[rl[k]];
+              q[k] = fma(sk, sk, q[k]);
             }
           }
         }
@@ -329,8 +343,8 @@ hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t
   }
   const int wmax = QCH + dmax;
   // rows staged per pass: at most 8, within 64 KB of LDS
-  const int qr = std::max(1, std::min(8, (int)(65536 / ((size_t)wmax * sizeof(double)))));
-  const size_t shm = (size_t)qr * wmax * sizeof(double);
+  const int qr = std::max(1, std::min(8, (int)(65536 / ((size_t)(wmax + 1) * sizeof(double)))));
+  const size_t shm = (size_t)qr * (wmax + 1) * sizeof(double);
   hipLaunchKernelGGL(q_partial_kernel, dim3((unsigned)((n_epochs + QCH - 1) / QCH), (unsigned)nchunks), dim3(256),
                      shm, s, X, ldx, n, lattice, n_epochs, dl, wmax, qr, rowchunk, qpart);
   return hipGetLastError();
