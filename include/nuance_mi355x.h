@@ -43,9 +43,17 @@ typedef enum {
   NU_ERR_UNSUPPORTED = 5  /* valid request this build does not implement */
 } nu_status;
 
-/* Arithmetic of the bulk whitening solve of the linear search. The Cholesky
- * factor, the trend fit, the cell normal equations and the periodic search
- * are FP64 in every mode. */
+/* Arithmetic of the bulk whitening solve of the linear search (the triangular
+ * inverse W = L^-1). The Cholesky factor, the trend fit, the cell normal
+ * equations and the periodic search are FP64 in every mode.
+ *  NU_FP64          all FP64.
+ *  NU_FP32_REFINE   the doubling products of the inverse in FP32 on the matrix
+ *                   cores, then one FP64 Newton step W += W (I - L W) on the
+ *                   block band next to the diagonal, and one step of iterative
+ *                   refinement against L of the whitened trend and flux and of
+ *                   their back-substitution. Outputs within ~1e-9 of FP64 on
+ *                   the test workloads (the bar is 1e-6 on dll).
+ *  NU_BF16X3_REFINE not available in this build (NU_ERR_UNSUPPORTED). */
 typedef enum {
   NU_FP64 = 0,
   NU_FP32_REFINE = 1,
@@ -92,11 +100,17 @@ nu_status nu_ctx_timing_entry(nu_ctx* ctx, int index, const char** name_host, in
  * t: device, n doubles, strictly increasing. Builds K on the device, factors
  * it as K = L L^T in FP64 (blocked, right-looking), and returns a factor
  * object owning L and the workspace of the later solves (about 2 n^2 + n^2/4
- * doubles of device memory, n rounded up to 128). Synchronises the stream
+ * doubles of device memory, n rounded up to 128, plus 2 n^2 floats once a
+ * reduced-precision search has run on it). Synchronises the stream
  * once. On NU_ERR_NOT_PD, *fail_pivot_host is the first failing pivot and
  * no factor is returned. logdet_host (ln|K|) and fail_pivot_host may be NULL. */
 nu_status nu_gp_factor(nu_ctx* ctx, const double* t, int64_t n, const nu_sho* theta, nu_factor** out,
                        double* logdet_host, int64_t* fail_pivot_host);
+/* (1b) Same as (1) into an existing factor of the same n (its device buffers
+ * are reused; no allocation). On NU_ERR_NOT_PD the factor's contents are
+ * undefined until the next successful call. */
+nu_status nu_gp_factor_into(nu_ctx* ctx, nu_factor* factor, const double* t, int64_t n, const nu_sho* theta,
+                            double* logdet_host, int64_t* fail_pivot_host);
 void nu_factor_destroy(nu_factor* factor);
 int64_t nu_factor_n(const nu_factor* factor);
 

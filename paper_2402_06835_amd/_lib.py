@@ -36,6 +36,7 @@ SIGNATURES = {
     "nu_ctx_timing_count": (c_int, [c_void_p]),
     "nu_ctx_timing_entry": (c_int, [c_void_p, c_int, P(c_char_p), P(c_int64), P(c_double), P(c_double)]),
     "nu_gp_factor": (c_int, [c_void_p, c_void_p, c_int64, P(NuSho), P(c_void_p), P(c_double), P(c_int64)]),
+    "nu_gp_factor_into": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, P(NuSho), P(c_double), P(c_int64)]),
     "nu_factor_destroy": (None, [c_void_p]),
     "nu_factor_n": (c_int64, [c_void_p]),
     "nu_linear_search": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int64, P(c_int32), c_int,

@@ -120,21 +120,31 @@ class Factor:
             pass
 
 
-def gp_factor(ctx: Context, t, theta) -> Factor:
-    """K = k_SHO + sigma_w^2 I built and factored on the device (one stream sync)."""
+def gp_factor(ctx: Context, t, theta, out: Optional[Factor] = None) -> Factor:
+    """K = k_SHO + sigma_w^2 I built and factored on the device (one stream sync).
+
+    With ``out`` (a factor of the same length) its device buffers are reused."""
     t_dev = _dev_tensor(t, torch.float64, ctx.device)
     sho = theta if isinstance(theta, SHO) else SHO.from_dict(theta)
-    p = ctypes.c_void_p()
     logdet = ctypes.c_double()
     pivot = ctypes.c_int64(-1)
     c = sho.c()
-    st = lib().nu_gp_factor(ctx.ptr, ctypes.c_void_p(t_dev.data_ptr()), t_dev.numel(), ctypes.byref(c),
-                            ctypes.byref(p), ctypes.byref(logdet), ctypes.byref(pivot))
+    if out is not None:
+        st = lib().nu_gp_factor_into(ctx.ptr, out.ptr, ctypes.c_void_p(t_dev.data_ptr()), t_dev.numel(),
+                                     ctypes.byref(c), ctypes.byref(logdet), ctypes.byref(pivot))
+        p = None
+    else:
+        p = ctypes.c_void_p()
+        st = lib().nu_gp_factor(ctx.ptr, ctypes.c_void_p(t_dev.data_ptr()), t_dev.numel(), ctypes.byref(c),
+                                ctypes.byref(p), ctypes.byref(logdet), ctypes.byref(pivot))
     if st != NU_OK:
         msg = lib().nu_ctx_last_error(ctx.ptr).decode()
         err = NuanceError(st, msg)
         err.pivot = pivot.value
         raise err
+    if out is not None:
+        out.logdet = logdet.value
+        return out
     return Factor(p, t_dev.numel(), logdet.value)
 
 

@@ -1,4 +1,5 @@
-// Grouped FP64 GEMM on the gfx950 matrix cores (v_mfma_f64_16x16x4_f64).
+// Grouped GEMM on the gfx950 matrix cores, FP64 (v_mfma_f64_16x16x4_f64) and
+// FP32 (v_mfma_f32_16x16x4_f32).
 //
 // One launch runs a list of problems C = alpha * op(A) op(B) + beta * C; each
 // workgroup owns one 128 x 128 output tile of one problem. 256 threads = 4
@@ -11,16 +12,22 @@
 // triangular inverse X = L^-1 that whitens the box design of the linear search.
 #include "internal.hpp"
 
+// Accumulator layout of v_mfma_f32_16x16x4_f32 (set from the lane probe)
+#ifndef MFMA_F32_ROW_INTERLEAVED
+#define MFMA_F32_ROW_INTERLEAVED 0
+#endif
+
 namespace nu {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
 constexpr int GBM = TB, GBN = TB, GBK = 16;
 constexpr int LPAD = 4;
 
 // Tile order within a problem: groups of GROUP tile-rows, column-major inside
 // a group, so any run of consecutive tiles covers a compact block of rows and
-// columns (their A row panels and B column panels meet in L2). For the
+// columns (their A row panels and B column panels meet in cache). For the
 // lower-triangular tile set the same grouping is applied to the rows: the
 // rectangular part of a group (columns left of its diagonal) comes first,
 // then its triangle.
@@ -29,7 +36,6 @@ constexpr int GROUP = 16;
 __device__ __forceinline__ void tile_of(const GemmProblem& P, int t, int& tm, int& tn) {
   if (P.flags & G_C_LOWER_TILES) {
     const int T = P.M / TB;
-    // group g starts at tile g*G*(g*G+1)/2: largest row start r0 = g*G with r0(r0+1)/2 <= t
     int r = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((r + 1) * (r + 2) / 2 <= t) ++r;
     while (r * (r + 1) / 2 > t) --r;
@@ -60,19 +66,58 @@ __device__ __forceinline__ void tile_of(const GemmProblem& P, int t, int& tm, in
   }
 }
 
-__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmProblem* __restrict__ probs, int nprob) {
-  __shared__ double As[2][GBK][GBM + LPAD];
-  __shared__ double Bs[2][GBK][GBN + LPAD];
+// Matrix-core operation per element type: the accumulator of one 16 x 16 x 4
+// product and the row that item i of a lane holds (measured on gfx950: the
+// f64 accumulator interleaves rows by 4, the f32 one holds 4 consecutive rows).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef dbl4 acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int i) { return lk + 4 * i; }
+};
+template <>
+struct Mfma<float> {
+  typedef flt4 acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int i) { return MFMA_F32_ROW_INTERLEAVED ? lk + 4 * i : 4 * lk + i; }
+};
+
+// 8 consecutive elements from global memory into registers, 16-byte loads
+template <typename T>
+__device__ __forceinline__ void load8(const T* p, T (&r)[8]) {
+  constexpr int PER = 16 / sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(PER)));
+  const vec_t* v = reinterpret_cast<const vec_t*>(p);
+#pragma unroll
+  for (int i = 0; i < 8 / PER; ++i) {
+    const vec_t x = v[i];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) r[i * PER + e] = x[e];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restrict__ probs, int nprob) {
+  __shared__ T As[2][GBK][GBM + LPAD];
+  __shared__ T Bs[2][GBK][GBN + LPAD];
+  typedef typename Mfma<T>::acc_t acc_t;
 
   // Workgroups go to the 8 XCDs round-robin, so the ~512 tiles resident at
-  // once are consecutive tiles of the grouped order below: a compact block of
-  // rows x columns whose panels all XCDs stream together (shared last-level
-  // cache), with two rows of the block per XCD.
+  // once are consecutive tiles of the grouped order: a compact block of rows
+  // x columns whose panels all XCDs stream together (shared last-level cache).
   const int tile = blockIdx.x;
-  int p = 0;
-  for (int i = 1; i < nprob; ++i)
-    if (tile >= probs[i].tile_begin) p = i;
-  const GemmProblem P = probs[p];
+  int lo = 0, hi = nprob - 1;  // last problem with tile_begin <= tile
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GemmProblem P = probs[lo];
   int tm, tn;
   tile_of(P, tile - P.tile_begin, tm, tn);
   const int m0 = tm * GBM, n0 = tn * GBN;
@@ -93,26 +138,15 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmProblem* __r
   // "row-major K x N -> [k][n]" pattern for B
   const int bk = tid >> 4, bnc = (tid & 15) * 8;
 
-  const double* Ap = P.A + (int64_t)(m0 + ar) * P.lda + akh;
-  const double* Bp = bt ? P.B + (int64_t)(n0 + ar) * P.ldb + akh : P.B + (int64_t)bk * P.ldb + n0 + bnc;
+  const T* A = static_cast<const T*>(P.A);
+  const T* B = static_cast<const T*>(P.B);
+  const T* Ap = A + (int64_t)(m0 + ar) * P.lda + akh;
+  const T* Bp = bt ? B + (int64_t)(n0 + ar) * P.ldb + akh : B + (int64_t)bk * P.ldb + n0 + bnc;
 
-  double ra[8], rb[8];
+  T ra[8], rb[8];
   auto gload = [&](int k0) {
-    const double2* a2 = reinterpret_cast<const double2*>(Ap + k0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double2 v = a2[i];
-      ra[2 * i] = v.x;
-      ra[2 * i + 1] = v.y;
-    }
-    const double2* b2 = bt ? reinterpret_cast<const double2*>(Bp + k0)
-                           : reinterpret_cast<const double2*>(Bp + (int64_t)k0 * P.ldb);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double2 v = b2[i];
-      rb[2 * i] = v.x;
-      rb[2 * i + 1] = v.y;
-    }
+    load8<T>(Ap + k0, ra);
+    load8<T>(bt ? Bp + k0 : Bp + (int64_t)k0 * P.ldb, rb);
   };
   auto lstore = [&](int buf) {
 #pragma unroll
@@ -126,11 +160,11 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmProblem* __r
     }
   };
 
-  dbl4 acc[4][4];
+  acc_t acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   if (nk > 0) {
     gload(kb);
@@ -141,7 +175,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmProblem* __r
       if (it + 1 < nk) gload(kb + (it + 1) * GBK);
 #pragma unroll
       for (int kk = 0; kk < GBK / 4; ++kk) {
-        double a[4], b[4];
+        T a[4], b[4];
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi) a[mi] = As[buf][kk * 4 + lk][wm + mi * 16 + lr];
 #pragma unroll
@@ -149,35 +183,36 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const GemmProblem* __r
 #pragma unroll
         for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < 4; ++ni)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+          for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = Mfma<T>::op(a[mi], b[ni], acc[mi][ni]);
       }
       if (it + 1 < nk) lstore(buf ^ 1);
       __syncthreads();
     }
   }
 
-  // epilogue: item i of a lane is row lane/16 + 4 i, column lane % 16 of each
-  // 16 x 16 block (the f64 accumulator layout, measured on gfx950)
-  const double alpha = P.alpha, beta = P.beta;
+  const T alpha = (T)P.alpha, beta = (T)P.beta;
+  T* C = static_cast<T*>(P.C);
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int row = m0 + wm + mi * 16 + lk + 4 * i;
+        const int row = m0 + wm + mi * 16 + Mfma<T>::row(lk, i);
         const int col = n0 + wn + ni * 16 + lr;
-        double* c = P.C + (int64_t)row * P.ldc + col;
-        double v = alpha * acc[mi][ni][i];
-        if (beta != 0.0) v = fma(beta, *c, v);
+        T* c = C + (int64_t)row * P.ldc + col;
+        T v = alpha * acc[mi][ni][i];
+        if (beta != (T)0) v = fma(beta, *c, v);
         *c = v;
       }
 }
 
-hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles) {
+hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32) {
   if (total_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)total_tiles), dim3(256), 0, s, dprobs, nprob);
+  if (f32)
+    hipLaunchKernelGGL(gemm_kernel<float>, dim3((unsigned)total_tiles), dim3(256), 0, s, dprobs, nprob);
+  else
+    hipLaunchKernelGGL(gemm_kernel<double>, dim3((unsigned)total_tiles), dim3(256), 0, s, dprobs, nprob);
   return hipGetLastError();
 }
 

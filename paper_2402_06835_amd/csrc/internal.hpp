@@ -37,9 +37,9 @@ enum GemmFlags : int {
 };
 
 struct GemmProblem {
-  const double* A;
-  const double* B;
-  double* C;
+  const void* A;  // element type given by the launch (double or float)
+  const void* B;
+  void* C;
   int64_t lda, ldb, ldc;
   int M, N, K;
   int flags;
@@ -77,10 +77,6 @@ struct nu_pending_event {
 struct nu_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  // side stream (default priority) for the trailing updates of the factor's
-  // lookahead, ordered against the caller's stream with two events
-  hipStream_t side = nullptr;
-  hipEvent_t ev_panel = nullptr, ev_rest = nullptr;
   std::string last_error;
   // growable device workspace
   void* ws = nullptr;
@@ -93,6 +89,15 @@ struct nu_ctx {
   std::vector<std::string> timing_names;
 };
 
+namespace nu {
+// one grouped launch: problems [first, first + count) of a schedule
+struct Range {
+  int first = 0, count = 0, tiles = 0;
+  double flops = 0.0;
+};
+constexpr int BAND_W = 2;  // block diagonals refined after a reduced-precision inverse
+}  // namespace nu
+
 struct nu_factor {
   int device = 0;
   int64_t n = 0;    // samples
@@ -101,19 +106,22 @@ struct nu_factor {
   double* X = nullptr;       // np x np row-major; lower triangle = L^-1 (diagonal blocks at factor time)
   double* T = nullptr;       // workspace of the triangular-inverse levels
   size_t t_elems = 0;
-  double* small = nullptr;   // logdet parts, status etc.
-  nu::GemmProblem* probs = nullptr;  // device copy of the schedule
-  std::vector<nu::GemmProblem> sched;  // host copy
-  // schedule ranges
-  std::vector<std::pair<int, int>> chol_panel;  // per step: (first problem, count)
-  std::vector<std::pair<int, int>> chol_syrk;   // trailing update of the next block column
-  std::vector<std::pair<int, int>> chol_rest;   // trailing update of the remaining columns
-  std::vector<std::pair<int, int>> trtri_t1;    // per level (deepest first)
-  std::vector<std::pair<int, int>> trtri_t2;
-  std::vector<int> sched_tiles;                 // tiles per launch range (parallel to the ranges above)
-  double logdet = 0.0;
-  bool inverse_ready = false;
+  double* small = nullptr;   // logdet parts, logdet, status
   nu::NullFit* nullfit = nullptr;
+  // FP64 schedule: Cholesky and triangular inverse
+  nu::GemmProblem* probs = nullptr;
+  std::vector<nu::GemmProblem> sched;
+  std::vector<nu::Range> panel, pupd, trail, t1, t2;
+  // reduced-precision inverse (allocated on first use)
+  float* L32 = nullptr;
+  float* X32 = nullptr;
+  double* bandP = nullptr;   // (I, d) blocks of L X on the band, stored by column block
+  double* bandX = nullptr;   // refined band blocks
+  nu::GemmProblem* probs32 = nullptr;
+  std::vector<nu::GemmProblem> sched32;
+  std::vector<nu::Range> t1_32, t2_32, bandp, bandx;
+  int inverse_kind = 0;  // 0 none, 1 FP64, 2 FP32 levels + refinement
+  double logdet = 0.0;
 };
 
 namespace nu {
@@ -129,18 +137,23 @@ void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, 
 
 // launchers (*.hip)
 hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho& th, double* K);
-hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles);
+hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32 = 0);
 hipError_t launch_potrf_diag(hipStream_t s, double* L, int64_t ld, int64_t off, int step, double* logdet_parts,
                              int64_t* status, double* Xdiag, int64_t ldx);
 hipError_t launch_fill_i64(hipStream_t s, int64_t* p, int64_t v);
+hipError_t launch_cvt_f64_f32(hipStream_t s, const double* src, float* dst, int64_t np, int diag_only);
+hipError_t launch_cvt_f32_f64(hipStream_t s, const float* src, double* dst, int64_t np);
+hipError_t launch_band_copy(hipStream_t s, double* X, int64_t np, double* band, int w, int to_band);
 hipError_t launch_logdet_reduce(hipStream_t s, const double* parts, int nparts, double* out);
 
-hipError_t launch_xv_rows(hipStream_t s, const double* X, int64_t ldx, int64_t n, const double* A, int m1,
-                          const double* f, double* Y);
+hipError_t launch_pack_v(hipStream_t s, const double* A, int m1, const double* f, int64_t n, double* V);
+hipError_t launch_rows_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, const double* V, int nv,
+                              const double* base, double alpha, double* out);
 hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const double* logdet, NullFit* nf,
                              double* null_out);
-hipError_t launch_xtv_cols(hipStream_t s, const double* X, int64_t ldx, int64_t n, int64_t np, const double* Y,
-                           int nv, double* partial, int rowchunk, int nchunks, double* Z);
+hipError_t launch_cols_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, int64_t np, const double* W,
+                              int nv, double* partial, int rowchunk, int nchunks, const double* base, double alpha,
+                              double* out);
 hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t n, const int64_t* lattice,
                             int64_t n_epochs, const int32_t* dur_sorted, int n_d, int dmax, int rowchunk,
                             int nchunks, double* qpart);

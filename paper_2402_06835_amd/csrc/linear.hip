@@ -11,9 +11,13 @@
 // where w0 is the trend-only fit and dll = ln L_ij - ln L_0 (Eq. 5).
 //
 // Kernels, in launch order:
-//   xv_rows       Y = X [A | f]           (whitened trend and flux; one wave per row)
+//   pack_v        V = [A | f] row-major
+//   rows_matvec   Y = X V                 (whitened trend and flux; one wave per row)
 //   null_solve    trend-only GLS, r~0 = f~ - A~ w0, chi2_0, ln L_0
-//   xtv_cols      Z = X^T [A~ | r~0] = [K^-1 A | K^-1 r0]   (row-chunk partials + reduce)
+//   cols_matvec   Z = X^T [A~ | r~0] = [K^-1 A | K^-1 r0]   (row-chunk partials + reduce)
+// With an inverse X computed in reduced precision, Y and Z each get one step
+// of iterative refinement against the FP64 factor: Y += X (V - L Y) and
+// Z += X^T (W - L^T Z).
 //   q_partial     per cell, sum over a row chunk of the squared box window sums of X
 //   cell_epilogue per cell: g, h from window sums of Z, Schur complement, outputs
 #include <algorithm>
@@ -44,36 +48,55 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void xv_rows_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
-                                                      const double* __restrict__ A, int m1,
-                                                      const double* __restrict__ f, double* __restrict__ Y) {
+// V = [A | f] packed row-major (np x YCOLS): column c < m1 is trend column c,
+// column m1 is the flux.
+__global__ __launch_bounds__(256) void pack_v_kernel(const double* __restrict__ A, int m1,
+                                                     const double* __restrict__ f, int64_t n,
+                                                     double* __restrict__ V) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+#pragma unroll
+  for (int c = 0; c < YCOLS; ++c) V[r * YCOLS + c] = c < m1 ? A[c * n + r] : (c == m1 ? f[r] : 0.0);
+}
+
+hipError_t launch_pack_v(hipStream_t s, const double* A, int m1, const double* f, int64_t n, double* V) {
+  hipLaunchKernelGGL(pack_v_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, m1, f, n, V);
+  return hipGetLastError();
+}
+
+// out[r] = base[r] + alpha * sum_{m <= r} M[r][m] V[m]   (nv columns, row-major,
+// lower-triangular M; one wave per row, fixed-order wave reduction). out may
+// alias base.
+__global__ __launch_bounds__(256) void rows_matvec_kernel(const double* __restrict__ M, int64_t ldm, int64_t n,
+                                                          const double* __restrict__ V, int nv,
+                                                          const double* base, double alpha, double* out) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   double acc[YCOLS];
 #pragma unroll
   for (int c = 0; c < YCOLS; ++c) acc[c] = 0.0;
-  const double* xr = X + row * ldx;
+  const double* mr = M + row * ldm;
   for (int64_t m = lane; m <= row; m += 64) {
-    const double x = xr[m];
+    const double x = mr[m];
+    const double* v = V + m * YCOLS;
 #pragma unroll
-    for (int c = 0; c < MAX_M1; ++c)
-      if (c < m1) acc[c] = fma(x, A[c * n + m], acc[c]);
-    acc[YCOLS - 1] = fma(x, f[m], acc[YCOLS - 1]);
+    for (int c = 0; c < YCOLS; ++c)
+      if (c < nv) acc[c] = fma(x, v[c], acc[c]);
   }
 #pragma unroll
   for (int c = 0; c < YCOLS; ++c) acc[c] = wave_sum(acc[c]);
   if (lane == 0) {
 #pragma unroll
-    for (int c = 0; c < MAX_M1; ++c)
-      if (c < m1) Y[row * YCOLS + c] = acc[c];
-    Y[row * YCOLS + m1] = acc[YCOLS - 1];
+    for (int c = 0; c < YCOLS; ++c)
+      if (c < nv) out[row * YCOLS + c] = (base ? base[row * YCOLS + c] : 0.0) + alpha * acc[c];
   }
 }
 
-hipError_t launch_xv_rows(hipStream_t s, const double* X, int64_t ldx, int64_t n, const double* A, int m1,
-                          const double* f, double* Y) {
-  hipLaunchKernelGGL(xv_rows_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, ldx, n, A, m1, f, Y);
+hipError_t launch_rows_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, const double* V, int nv,
+                              const double* base, double alpha, double* out) {
+  hipLaunchKernelGGL(rows_matvec_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, M, ldm, n, V, nv, base,
+                     alpha, out);
   return hipGetLastError();
 }
 
@@ -169,11 +192,12 @@ hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const 
 }
 
 // ---------------------------------------------------------------------------
-// Z[m][c] = sum_{n >= m} X[n][m] Y[n][c], c < nv. Workgroup = 256 columns x a
-// chunk of rows; partials per chunk, then a fixed-order reduction.
-__global__ __launch_bounds__(256) void xtv_cols_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
-                                                       int64_t np, const double* __restrict__ Y, int nv,
-                                                       int rowchunk, double* __restrict__ partial) {
+// out[m] = base[m] + alpha * sum_{n >= m} M[n][m] W[n]   (nv columns,
+// row-major, lower-triangular M). Workgroup = 256 columns x a chunk of rows;
+// partials per chunk, then a fixed-order reduction. out may alias base.
+__global__ __launch_bounds__(256) void cols_partial_kernel(const double* __restrict__ M, int64_t ldm, int64_t n,
+                                                           int64_t np, const double* __restrict__ W, int nv,
+                                                           int rowchunk, double* __restrict__ partial) {
   const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (m >= np) return;
   const int chunk = blockIdx.y;
@@ -185,36 +209,38 @@ __global__ __launch_bounds__(256) void xtv_cols_kernel(const double* __restrict_
   const int64_t c0 = (int64_t)blockIdx.x * 256;
   if (m < n) {
     for (int64_t r = max(r0, c0); r < r1; ++r) {
-      const double x = (m <= r) ? X[r * ldx + m] : 0.0;
-      const double* yr = Y + r * YCOLS;
+      const double x = (m <= r) ? M[r * ldm + m] : 0.0;
+      const double* wr = W + r * YCOLS;
 #pragma unroll
       for (int c = 0; c < YCOLS; ++c)
-        if (c < nv) acc[c] = fma(x, yr[c], acc[c]);
+        if (c < nv) acc[c] = fma(x, wr[c], acc[c]);
     }
   }
-  double* out = partial + ((int64_t)chunk * np + m) * YCOLS;
+  double* o = partial + ((int64_t)chunk * np + m) * YCOLS;
 #pragma unroll
-  for (int c = 0; c < YCOLS; ++c) out[c] = acc[c];
+  for (int c = 0; c < YCOLS; ++c) o[c] = acc[c];
 }
 
-__global__ __launch_bounds__(256) void xtv_reduce_kernel(const double* __restrict__ partial, int64_t np,
-                                                         int nchunks, double* __restrict__ Z) {
+__global__ __launch_bounds__(256) void cols_reduce_kernel(const double* __restrict__ partial, int64_t np,
+                                                          int nchunks, const double* base, double alpha,
+                                                          double* out) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= np * YCOLS) return;
   double s = 0.0;
   for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * np * YCOLS + e];
-  Z[e] = s;
+  out[e] = (base ? base[e] : 0.0) + alpha * s;
 }
 
-hipError_t launch_xtv_cols(hipStream_t s, const double* X, int64_t ldx, int64_t n, int64_t np, const double* Y,
-                           int nv, double* partial, int rowchunk, int nchunks, double* Z) {
-  hipLaunchKernelGGL(xtv_cols_kernel, dim3((unsigned)(np / 256 + (np % 256 ? 1 : 0)), (unsigned)nchunks),
-                     dim3(256), 0, s, X, ldx, n, np, Y, nv, rowchunk, partial);
+hipError_t launch_cols_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, int64_t np, const double* W,
+                              int nv, double* partial, int rowchunk, int nchunks, const double* base, double alpha,
+                              double* out) {
+  hipLaunchKernelGGL(cols_partial_kernel, dim3((unsigned)(np / 256 + (np % 256 ? 1 : 0)), (unsigned)nchunks),
+                     dim3(256), 0, s, M, ldm, n, np, W, nv, rowchunk, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tot = np * YCOLS;
-  hipLaunchKernelGGL(xtv_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, np, nchunks,
-                     Z);
+  hipLaunchKernelGGL(cols_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, np, nchunks,
+                     base, alpha, out);
   return hipGetLastError();
 }
 

@@ -311,3 +311,84 @@ def test_full_size_fold_sampled(api, ctx):
     np.testing.assert_allclose(g["q_snr"][same], sub["q_snr"][same], rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(g["best_lnp"], sub["best_lnp"], rtol=1e-12)
     say(f"full-size fold: certified ties {ties}")
+
+
+# ---------------------------------------------------------------------------
+# Reduced-precision inverse (FP32 level products + FP64 band Newton step +
+# iterative refinement of the small solves): the bar is 1e-6 on dll (and on
+# depth in sigma units and var), against the FP64 oracle.
+# ---------------------------------------------------------------------------
+MIXED_TOL = 1e-6
+
+
+def assert_linear_close_tol(gpu, ref, tol, tag=""):
+    v = ref["valid"].astype(bool)
+    np.testing.assert_array_equal(gpu["valid"].astype(bool), v, err_msg=f"valid {tag}")
+    e_dll = np.abs(gpu["dll"][v] - ref["dll"][v]) / np.maximum(np.abs(ref["dll"][v]), 1.0)
+    e_dep = np.abs(gpu["depth"][v] - ref["depth"][v]) / np.sqrt(ref["var"][v])
+    e_var = np.abs(gpu["var"][v] - ref["var"][v]) / ref["var"][v]
+    errs = {"dll": e_dll.max(), "depth": e_dep.max(), "var": e_var.max(), "dll_p999": np.quantile(e_dll, 0.999)}
+    say(f"{tag} max errors {errs}")
+    assert errs["dll"] <= tol and errs["depth"] <= tol and errs["var"] <= tol, (tag, errs)
+    return errs
+
+
+@pytest.mark.parametrize("name,kw", [("N700-m3-gap", dict(n=700, m1=3, durs=[1, 4, 9, 17], gap=(333, 25))),
+                                     ("N1000-m3", dict(n=1000, m1=3, durs=[3, 9, 20], seed=4))],
+                         ids=["N700-m3-gap", "N1000-m3"])
+def test_linear_search_fp32_refine_parity(api, ctx, name, kw):
+    import torch
+    w = _case(**kw)
+    say(f"fp32_refine {name}: N={w.n}")
+    fac = api.gp_factor(ctx, w.t, w.theta)
+    ls = api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations, precision="fp32_refine")
+    torch.cuda.synchronize()
+    L = ogp.cholesky(ogp.covariance(w.t, w.theta))
+    ref = olin.linear_search(w.f, w.A, L, w.lattice, w.durations)
+    assert_linear_close_tol(_host(ls), ref, MIXED_TOL, f"fp32_refine {name}")
+
+
+def test_precision_switch_and_factor_reuse(api, ctx):
+    import torch
+    w = _case(n=700, m1=3, durs=[2, 6], gap=(200, 11), seed=8)
+    w2 = _case(n=700, m1=3, durs=[2, 6], gap=(200, 11), seed=9)
+    say("precision switch and factor reuse N=700")
+    fac = api.gp_factor(ctx, w.t, w.theta)
+    a = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations))
+    b = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations, precision="fp32_refine"))
+    c = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations))
+    torch.cuda.synchronize()
+    for k in a:
+        np.testing.assert_array_equal(a[k], c[k])  # back to FP64: identical to the first FP64 run
+    v = a["valid"].astype(bool)
+    assert np.max(np.abs(b["dll"][v] - a["dll"][v]) / np.maximum(np.abs(a["dll"][v]), 1)) < MIXED_TOL
+    # refill the same factor with another curve: same results as a fresh factor
+    api.gp_factor(ctx, w2.t, w2.theta, out=fac)
+    r1 = _host(api.linear_search(ctx, fac, w2.f, w2.A, w2.lattice, w2.n_epochs, w2.durations))
+    fresh = api.gp_factor(ctx, w2.t, w2.theta)
+    r2 = _host(api.linear_search(ctx, fresh, w2.f, w2.A, w2.lattice, w2.n_epochs, w2.durations))
+    torch.cuda.synchronize()
+    for k in r1:
+        np.testing.assert_array_equal(r1[k], r2[k])
+
+
+def test_full_size_fp32_refine_sampled(api, ctx):
+    import torch
+    w = config2()
+    say(f"full-size fp32_refine N={w.n}")
+    fac = api.gp_factor(ctx, w.t, w.theta)
+    ls = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations, precision="fp32_refine"))
+    ls64 = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations))
+    torch.cuda.synchronize()
+    v = ls64["valid"].astype(bool)
+    e_all = np.abs(ls["dll"][v] - ls64["dll"][v]) / np.maximum(np.abs(ls64["dll"][v]), 1.0)
+    say(f"fp32_refine vs fp64 (all {v.sum()} cells): max {e_all.max():.2e} p99.9 {np.quantile(e_all, 0.999):.2e}")
+    say("oracle Cholesky at N=18000 (CPU)")
+    L = ogp.cholesky(ogp.covariance(w.t, w.theta))
+    rng = np.random.default_rng(7)
+    n_d, n_t = ls["dll"].shape
+    cells = [(int(rng.integers(n_d)), int(rng.integers(n_t))) for _ in range(100)]
+    ref = olin.linear_search(w.f, w.A, L, w.lattice, w.durations, cells=cells)
+    sel = {k: np.array([ls[k][j, i] for (j, i) in cells]) for k in ls}
+    assert_linear_close_tol(sel, ref, MIXED_TOL, "full-size fp32_refine sampled")
+    assert e_all.max() <= MIXED_TOL
