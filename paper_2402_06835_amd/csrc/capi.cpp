@@ -100,10 +100,15 @@ struct Timed {
   ~Timed() { timing_end(ctx, ctx->stream, name, start, work); }
 };
 
-int tiles_of(const GemmProblem& g) {
-  const int tm = g.M / TB, tn = g.N / TB;
+int tiles_of(const GemmProblem& g, int tile) {
+  const int tm = g.M / tile, tn = g.N / tile;
   return (g.flags & G_C_LOWER_TILES) ? tm * (tm + 1) / 2 : tm * tn;
 }
+
+// Launches with fewer 128 x 128 tiles than one round of workgroups on the chip
+// (256 CUs x 2) use 64 x 64 tiles instead: four times the workgroups, each a
+// quarter of the work.
+constexpr int SMALL_LAUNCH_TILES = 512;
 
 // useful flops of a problem (zeros of triangular operands not counted)
 double useful_flops(const GemmProblem& g) {
@@ -120,11 +125,14 @@ Range add_launch(std::vector<GemmProblem>& sched, std::vector<GemmProblem> probs
   Range r;
   r.first = (int)sched.size();
   r.count = (int)probs.size();
+  int big = 0;
+  for (auto& p : probs) big += tiles_of(p, TB);
+  r.tile = big < SMALL_LAUNCH_TILES ? 64 : TB;
   int t = 0;
   for (auto& p : probs) {
-    p.tiles_n = p.N / TB;
+    p.tiles_n = p.N / r.tile;
     p.tile_begin = t;
-    p.tile_count = tiles_of(p);
+    p.tile_count = tiles_of(p, r.tile);
     t += p.tile_count;
     r.flops += useful_flops(p);
     sched.push_back(p);
@@ -271,7 +279,7 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 nu_status launch_range(nu_ctx* ctx, const GemmProblem* dprobs, const Range& r, const char* name, int f32 = 0) {
   if (r.tiles == 0) return NU_OK;
   Timed tm(ctx, name, r.flops);
-  return check_hip(ctx, launch_gemm(ctx->stream, dprobs + r.first, r.count, r.tiles, f32), name);
+  return check_hip(ctx, launch_gemm(ctx->stream, dprobs + r.first, r.count, r.tiles, f32, r.tile), name);
 }
 
 nu_status upload(nu_ctx* ctx, GemmProblem** dst, const std::vector<GemmProblem>& src) {

@@ -59,12 +59,13 @@ hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, 
 // above the diagonal), and its inverse X_kk = L_kk^-1 into the diagonal block
 // of the inverse (zeros above the diagonal).
 //
-// Blocked right-looking by 16: for each 16 x 16 diagonal piece, one wave
-// factors and inverts it in registers (lane r holds row r; values cross lanes
-// with readlane), the panel below is multiplied by that inverse on the matrix
-// cores, and the trailing pieces are updated on the matrix cores. The inverse
-// is then completed by three doubling levels X21 = -X_C (L21 X_A) for the
-// 2 x 2 partitions 16|16, 32|32, 64|64, also on the matrix cores.
+// Blocked right-looking by 16: each 16 x 16 diagonal piece is factored by all
+// threads with one barrier per column, the rows below it are solved against
+// it by substitution (one row per thread), and the trailing pieces are
+// updated on the matrix cores. The inverse starts from the eight piece
+// inverses (forward substitution, one column per lane) and is completed by
+// three doubling levels X21 = -X_C (L21 X_A) for the 2 x 2 partitions 16|16,
+// 32|32, 64|64, also on the matrix cores.
 //
 // Inverse storage while in LDS: X[r][c] (r > c) is kept at a[c][r] (the
 // strictly upper part, free once L is lower), its diagonal in xd[].
@@ -75,13 +76,6 @@ constexpr int SB = 16;       // piece edge
 constexpr int NSB = DB / SB; // 8
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const long long x = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffLL), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
-  return __hiloint2double(hi, lo);
-}
 
 __device__ __forceinline__ double xget(const double (*a)[DPAD], const double* xd, int r, int c) {
   return r > c ? a[c][r] : (r == c ? xd[r] : 0.0);
@@ -159,6 +153,7 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(double* __restrict__
                                                            int64_t ldx) {
   __shared__ double a[DB][DPAD];
   __shared__ double xd[DB];
+  __shared__ double rdg[DB];  // 1 / L_cc
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -180,60 +175,50 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(double* __restrict__
     }
   }
   __syncthreads();
+  const int pr = tid >> 4, ps = tid & 15;  // (row, column) of a 16 x 16 piece owned by this thread
   for (int kb = 0; kb < NSB; ++kb) {
     const int o = kb * SB;
-    // (a) the 16 x 16 diagonal piece: factor, then invert, in the registers of wave 0
-    if (wave == 0) {
-      const int r = lane;
-      double row[SB];
-#pragma unroll
-      for (int s = 0; s < SB; ++s) row[s] = (r < SB && s <= r) ? a[o + (r & (SB - 1))][o + s] : 0.0;
-#pragma unroll
-      for (int c = 0; c < SB; ++c) {
-        const double piv = readlane_d(row[c], c);
-        if (lane == 0 && !(piv > 0.0) && *status < 0) *status = off + o + c;
-        const double d = sqrt(piv);
-        if (r == c) row[c] = d;
-        else if (r > c) row[c] = row[c] / d;
-#pragma unroll
-        for (int s = c + 1; s < SB; ++s) {
-          const double v = readlane_d(row[c], s);
-          if (r >= s) row[s] = fma(-row[c], v, row[s]);
+    // (a) factor the 16 x 16 diagonal piece, one barrier per column: the
+    // update of column c's trailing entries uses the unscaled column,
+    //   a_rs -= a_rc a_sc / p,  p = a_cc  (entries with s > c only),
+    // while column c - 1 is scaled by 1/sqrt of its pivot (neither phase
+    // touches what the other reads); column 15 is scaled after the loop.
+    double pprev = 1.0;
+    for (int c = 0; c <= SB; ++c) {
+      if (c > 0 && tid < SB && tid >= c - 1) {
+        const double d = sqrt(pprev);
+        if (tid == c - 1) {
+          if (!(pprev > 0.0) && *status < 0) *status = off + o + c - 1;
+          rdg[o + c - 1] = 1.0 / d;
         }
+        a[o + tid][o + c - 1] = (tid == c - 1) ? d : a[o + tid][o + c - 1] / d;
       }
-      const int j = lane;  // lane j: column j of the inverse
+      if (c < SB) {
+        const double p = a[o + c][o + c];
+        const double rp = 1.0 / p;
+        if (ps > c && ps <= pr)
+          a[o + pr][o + ps] = fma(-a[o + pr][o + c] * rp, a[o + ps][o + c], a[o + pr][o + ps]);
+        pprev = p;
+      }
+      __syncthreads();
+    }
+    // (b) rows below the piece: solve x L_dd^T = a_row by substitution
+    const int nrow = DB - o - SB;
+    if (tid < nrow) {
+      const int r = o + SB + tid;
       double x[SB];
 #pragma unroll
-      for (int i = 0; i < SB; ++i) {
-        double acc = (i == j) ? 1.0 : 0.0;
+      for (int c = 0; c < SB; ++c) {
+        double acc = a[r][o + c];
 #pragma unroll
-        for (int s = 0; s < i; ++s) acc = fma(-readlane_d(row[s], i), x[s], acc);
-        x[i] = (i >= j) ? acc / readlane_d(row[i], i) : 0.0;
+        for (int s2 = 0; s2 < c; ++s2) acc = fma(-x[s2], a[o + c][o + s2], acc);
+        x[c] = acc * rdg[o + c];
       }
-      if (lane < SB) {
 #pragma unroll
-        for (int s = 0; s < SB; ++s) {
-          if (s <= r) a[o + r][o + s] = row[s];
-          if (s > j) a[o + j][o + s] = x[s];
-          if (s == j) xd[o + j] = x[s];
-        }
-      }
+      for (int c = 0; c < SB; ++c) a[r][o + c] = x[c];
     }
     __syncthreads();
-    // (b) pieces below: P = A X_dd^T
-    for (int t = wave; t < NSB - 1 - kb; t += 4) {
-      const int i0 = (kb + 1 + t) * SB;
-      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k = q * 4 + lk;
-        acc = mfma64(a[i0 + lr][o + k], xget(a, xd, o + lr, o + k), acc);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) a[i0 + lk + 4 * v][o + lr] = acc[v];
-    }
-    __syncthreads();
-    // (c) trailing pieces (i, j), kb < j <= i: A_ij -= P_i P_j^T
+    // (c) trailing pieces (i, j), kb < j <= i: A_ij -= P_i P_j^T on the matrix cores
     const int m = NSB - 1 - kb;
     for (int t = wave; t < m * (m + 1) / 2; t += 4) {
       int ii = 0;
@@ -265,6 +250,29 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(double* __restrict__
     const int r = idx / DB, c = idx - (idx / DB) * DB;
     L[(off + r) * ld + off + c] = c <= r ? a[r][c] : 0.0;
   }
+  // inverses of the eight 16 x 16 diagonal pieces: wave w takes pieces w and
+  // w + 4, lane j < 16 forms column j by forward substitution
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int o = (wave + 4 * h) * SB;
+    if (lane < SB) {
+      const int j = lane;
+      double x[SB];
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int s2 = 0; s2 < i; ++s2) acc = fma(-a[o + i][o + s2], x[s2], acc);
+        x[i] = (i >= j) ? acc * rdg[o + i] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < SB; ++i) {
+        if (i > j) a[o + j][o + i] = x[i];
+        if (i == j) xd[o + j] = x[i];
+      }
+    }
+  }
+  __syncthreads();
   inverse_level<16, 4>(a, xd);
   inverse_level<32, 2>(a, xd);
   inverse_level<64, 1>(a, xd);

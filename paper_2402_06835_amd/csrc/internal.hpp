@@ -12,7 +12,7 @@
 
 namespace nu {
 
-// Tile edge of the dense factorisation: matrices are padded to a multiple of
+// Block edge of the dense factorisation: matrices are padded to a multiple of
 // TB (identity on the padded diagonal), every GEMM problem is a multiple of
 // TB in M and N, and the diagonal blocks factored in LDS are TB x TB.
 constexpr int TB = 128;
@@ -93,6 +93,7 @@ namespace nu {
 // one grouped launch: problems [first, first + count) of a schedule
 struct Range {
   int first = 0, count = 0, tiles = 0;
+  int tile = TB;  // output tile edge of the launch (128 or 64)
   double flops = 0.0;
 };
 constexpr int BAND_W = 2;  // block diagonals refined after a reduced-precision inverse
@@ -137,7 +138,7 @@ void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, 
 
 // launchers (*.hip)
 hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho& th, double* K);
-hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32 = 0);
+hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32, int tile);
 hipError_t launch_potrf_diag(hipStream_t s, double* L, int64_t ld, int64_t off, int step, double* logdet_parts,
                              int64_t* status, double* Xdiag, int64_t ldx);
 hipError_t launch_fill_i64(hipStream_t s, int64_t* p, int64_t v);
