@@ -158,6 +158,74 @@ nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var
                              int64_t n_p, int log_term_sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,
                              double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period_index);
 
+/* (4) Batch search of light curves of uneven length: (1), (2) and (3) for
+ * every curve of the batch (Sections 2.2-2.4 per curve).
+ * Curve c owns samples [sample_off_host[c], sample_off_host[c+1]) of t, f and
+ * lattice (device; its lattice starts at 0 as in (2)), trend columns at
+ * A + m1 * sample_off_host[c] (column-major n_c x m1, as in (2)), and epoch
+ * slots [epoch_off_host[c], epoch_off_host[c+1]); both offset arrays are host,
+ * n_curves + 1 entries, starting at 0. theta_host and dt_host: host, one per
+ * curve. Durations, periods (device, n_p), precision and log_term_sign are
+ * shared by all curves.
+ * Outputs (device): depth/var/dll/valid of curve c at n_d * epoch_off[c],
+ * laid out [n_d][n_epochs_c] as in (2); null_out (3 per curve, may be NULL);
+ * the per-period arrays of (3) at c * n_p; best_period_index (one per curve,
+ * may be NULL). logdet_host and fail_pivot_host (host, one per curve, may be
+ * NULL): ln|K| and -1 or the failing pivot.
+ * The curves are processed longest first in waves whose factors fit in
+ * memory_budget_bytes of device memory (0: 90 % of the free memory); each
+ * dense stage of a wave is one launch over all its curves. The call
+ * synchronises the stream once per wave. A curve whose covariance is not
+ * positive definite gets invalid cells and no event at any period; the call
+ * then finishes the other curves and returns NU_ERR_NOT_PD. A single curve
+ * larger than the budget gives NU_ERR_OOM before any work. */
+nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_host, const int64_t* epoch_off_host,
+                          const double* t, const double* f, const double* A, int m1, const int64_t* lattice,
+                          const nu_sho* theta_host, const double* dt_host, const int32_t* dur_samples_host, int n_d,
+                          const double* periods, int64_t n_p, nu_precision prec, int log_term_sign,
+                          size_t memory_budget_bytes, double* depth, double* var, double* dll, uint8_t* valid,
+                          double* null_out, double* q_snr, int64_t* best_phase, int32_t* best_dur,
+                          double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period_index,
+                          double* logdet_host, int64_t* fail_pivot_host);
+
+/* (5) Captured graph of the whole search of one light curve: K build,
+ * Cholesky, inverse, linear search, periodic search and best period, as
+ * (1)-(3) with the same arguments, recorded once into a HIP graph bound to
+ * these device buffers. Each nu_graph_launch replays it on the context's
+ * stream and reads the current contents of t, f, A, lattice, periods and
+ * theta_dev (device, one nu_sho: the caller may rewrite it between launches,
+ * in stream order). No synchronisation: status_dev (device, one int64)
+ * receives -1 or the failing pivot of that launch; after a failing pivot the
+ * outputs of that launch are meaningless. The graph owns its factor and
+ * workspace (created here, before the capture); launches of one graph must
+ * not overlap. theta_dev is not validated: it must satisfy (1)'s bounds. */
+typedef struct nu_graph nu_graph;
+nu_status nu_graph_create(nu_ctx* ctx, const double* t, int64_t n, const nu_sho* theta_dev, const double* f,
+                          const double* A, int m1, const int64_t* lattice, int64_t n_epochs,
+                          const int32_t* dur_samples_host, int n_d, nu_precision prec, double dt,
+                          const double* periods, int64_t n_p, int log_term_sign, double* depth, double* var,
+                          double* dll, uint8_t* valid, double* null_out, double* q_snr, int64_t* best_phase,
+                          int32_t* best_dur, double* best_depth, double* best_sigma, double* best_lnp,
+                          int64_t* best_period_index, int64_t* status_dev, nu_graph** out);
+nu_status nu_graph_launch(nu_ctx* ctx, nu_graph* graph);
+void nu_graph_destroy(nu_graph* graph);
+
+/* (6) Tile policy of the dense launches. Launch classes: 0 Cholesky panel,
+ * 1 panel update, 2 trailing update, 3 FP64 inverse levels, 4 FP32 inverse
+ * levels, 5 band Newton step. A launch of a class takes 64 x 64 output tiles
+ * when it has fewer 128 x 128 tiles than the class threshold (default 512),
+ * else 128 x 128. The choice changes speed only: every output element sums
+ * the same products in the same order either way, so results are bitwise
+ * identical. nu_ctx_autotune times the factorisation and inverse of a
+ * synthetic covariance of size n (128 <= n <= 131072) under six thresholds
+ * per class, keeps the fastest per class in the context, and restores the
+ * caller's timing state; schedules built afterwards (new factors, batches,
+ * graphs) use it. It synchronises the stream and allocates about 2.5 n^2
+ * doubles while it runs. */
+nu_status nu_ctx_autotune(nu_ctx* ctx, int64_t n, nu_precision prec);
+nu_status nu_ctx_get_tuning(const nu_ctx* ctx, int launch_class, int* small_below_host);
+nu_status nu_ctx_set_tuning(nu_ctx* ctx, int launch_class, int small_below);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,7 +44,24 @@ SIGNATURES = {
     "nu_periodic_search": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int64, c_double,
                                    c_void_p, c_int64, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p]),
+    "nu_search_batch": (c_int, [c_void_p, c_int, P(c_int64), P(c_int64), c_void_p, c_void_p, c_void_p, c_int,
+                                c_void_p, P(NuSho), P(c_double), P(c_int32), c_int, c_void_p, c_int64, c_int, c_int,
+                                ctypes.c_size_t, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(c_double),
+                                P(c_int64)]),
+    "nu_graph_create": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int, c_void_p,
+                                c_int64, P(c_int32), c_int, c_int, c_double, c_void_p, c_int64, c_int, c_void_p,
+                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_void_p, c_void_p, c_void_p, P(c_void_p)]),
+    "nu_graph_launch": (c_int, [c_void_p, c_void_p]),
+    "nu_graph_destroy": (None, [c_void_p]),
+    "nu_ctx_autotune": (c_int, [c_void_p, c_int64, c_int]),
+    "nu_ctx_get_tuning": (c_int, [c_void_p, c_int, P(c_int)]),
+    "nu_ctx_set_tuning": (c_int, [c_void_p, c_int, c_int]),
 }
+
+# launch classes of the tile policy (include/nuance_mi355x.h, entry point 6)
+TUNE_CLASSES = ("panel", "panel_update", "trailing", "inverse_fp64", "inverse_fp32", "band")
 
 _LIB = None
 

@@ -18,7 +18,7 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import NU_OK, PRECISIONS, NuanceError, NuSho, lib
+from ._lib import NU_ERR_NOT_PD, NU_OK, PRECISIONS, TUNE_CLASSES, NuanceError, NuSho, lib
 
 
 def _check(ctx_ptr, status: int):
@@ -98,6 +98,25 @@ class Context:
                                                        ctypes.byref(ms), ctypes.byref(work)))
             out[name.value.decode()] = {"launches": launches.value, "ms": ms.value, "work": work.value}
         return out
+
+
+    # tile policy of the dense launches (entry point 6 of the C ABI)
+    def autotune(self, n: int, precision: str = "fp64") -> dict:
+        """Time six tile thresholds per launch class on a synthetic covariance of size n; keep the fastest."""
+        _check(self.ptr, lib().nu_ctx_autotune(self.ptr, int(n), PRECISIONS[precision]))
+        return self.tuning()
+
+    def tuning(self) -> dict:
+        out = {}
+        for i, name in enumerate(TUNE_CLASSES):
+            v = ctypes.c_int()
+            _check(self.ptr, lib().nu_ctx_get_tuning(self.ptr, i, ctypes.byref(v)))
+            out[name] = v.value
+        return out
+
+    def set_tuning(self, **thresholds):
+        for name, v in thresholds.items():
+            _check(self.ptr, lib().nu_ctx_set_tuning(self.ptr, TUNE_CLASSES.index(name), int(v)))
 
 
 class Factor:
@@ -226,6 +245,175 @@ def periodic_search(ctx: Context, depth, var, dll, valid, dt: float, periods, si
     _check(ctx.ptr, st)
     out["_keep"] = (depth, var, dll, valid, per)
     return out
+
+
+_PERIOD_KEYS = ("q_snr", "best_phase", "best_dur", "best_depth", "best_sigma", "best_lnp")
+_PERIOD_DTYPES = (torch.float64, torch.int64, torch.int32, torch.float64, torch.float64, torch.float64)
+
+
+def _trend_colmajor(A, n, dev):
+    if A is None:
+        return 0, None
+    A_t = A if isinstance(A, torch.Tensor) else torch.as_tensor(np.asarray(A, dtype=np.float64))
+    if A_t.ndim == 1:
+        A_t = A_t[:, None]
+    if A_t.shape[0] != n:
+        raise ValueError("A must be (N, m1)")
+    return int(A_t.shape[1]), A_t.to(device=dev, dtype=torch.float64).t().contiguous()
+
+
+def search_batch(ctx: Context, curves, durations, periods, precision: str = "fp32_refine", sign: int = 1,
+                 memory_budget: int = 0, raise_not_pd: bool = True) -> dict:
+    """Linear + periodic search of a batch of light curves of uneven length.
+
+    curves: list of dicts with t, f, A (N x m1 or None; the same m1 for all),
+    lattice (int64 slots, starting at 0), n_epochs, theta (SHO) and dt.
+    Returns the concatenated device outputs and, per curve, views:
+    ``cells[c]`` (depth, var, dll, valid shaped (n_d, n_epochs_c)) and
+    ``periods[c]`` (the per-period arrays), plus host ``logdet``,
+    ``fail_pivot`` and the device ``best_index`` (one per curve).
+    """
+    dev = ctx.device
+    nc = len(curves)
+    if nc < 1:
+        raise ValueError("empty batch")
+    ns = [int(np.asarray(c["lattice"]).size) for c in curves]
+    nes = [int(c["n_epochs"]) for c in curves]
+    soff = np.zeros(nc + 1, dtype=np.int64)
+    soff[1:] = np.cumsum(ns)
+    eoff = np.zeros(nc + 1, dtype=np.int64)
+    eoff[1:] = np.cumsum(nes)
+    m1s = set()
+    cols = []
+    for c, n in zip(curves, ns):
+        m1, Ac = _trend_colmajor(c.get("A"), n, torch.device("cpu"))
+        m1s.add(m1)
+        cols.append(Ac)
+    if len(m1s) != 1:
+        raise ValueError("every curve needs the same number of trend columns")
+    m1 = m1s.pop()
+    t = _dev_tensor(np.concatenate([np.asarray(c["t"], dtype=np.float64) for c in curves]), torch.float64, dev)
+    f = _dev_tensor(np.concatenate([np.asarray(c["f"], dtype=np.float64) for c in curves]), torch.float64, dev)
+    lat = _dev_tensor(np.concatenate([np.asarray(c["lattice"], dtype=np.int64) for c in curves]), torch.int64, dev)
+    A = torch.cat([a.reshape(-1) for a in cols]).to(dev) if m1 > 0 else None
+    thetas = (NuSho * nc)(*[(c["theta"] if isinstance(c["theta"], SHO) else SHO.from_dict(c["theta"])).c()
+                            for c in curves])
+    dts = np.ascontiguousarray([float(c["dt"]) for c in curves], dtype=np.float64)
+    durs = np.ascontiguousarray(np.asarray(durations, dtype=np.int32))
+    n_d = int(durs.size)
+    per = _dev_tensor(periods, torch.float64, dev)
+    n_p = per.numel()
+    cells = n_d * int(eoff[-1])
+    out = {k: torch.empty(cells, dtype=dt_, device=dev)
+           for k, dt_ in (("depth", torch.float64), ("var", torch.float64), ("dll", torch.float64),
+                          ("valid", torch.uint8))}
+    out["null"] = torch.empty((nc, 3), dtype=torch.float64, device=dev)
+    for k, dt_ in zip(_PERIOD_KEYS, _PERIOD_DTYPES):
+        out[k] = torch.empty((nc, n_p), dtype=dt_, device=dev)
+    out["best_index"] = torch.empty(nc, dtype=torch.int64, device=dev)
+    logdet = np.zeros(nc, dtype=np.float64)
+    pivot = np.full(nc, -1, dtype=np.int64)
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    st = lib().nu_search_batch(
+        ctx.ptr, nc, soff.ctypes.data_as(P64), eoff.ctypes.data_as(P64), ctypes.c_void_p(t.data_ptr()),
+        ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(A.data_ptr() if A is not None else 0), m1,
+        ctypes.c_void_p(lat.data_ptr()), thetas, dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d, ctypes.c_void_p(per.data_ptr()), n_p,
+        PRECISIONS[precision], int(sign), int(memory_budget),
+        *[ctypes.c_void_p(out[k].data_ptr()) for k in ("depth", "var", "dll", "valid", "null")],
+        *[ctypes.c_void_p(out[k].data_ptr()) for k in _PERIOD_KEYS],
+        ctypes.c_void_p(out["best_index"].data_ptr()),
+        logdet.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), pivot.ctypes.data_as(P64))
+    if st != NU_OK and not (st == NU_ERR_NOT_PD and not raise_not_pd):
+        _check(ctx.ptr, st)
+    out["logdet"] = logdet
+    out["fail_pivot"] = pivot
+    out["cells"] = [{k: out[k][n_d * int(eoff[c]):n_d * int(eoff[c + 1])].view(n_d, nes[c])
+                     for k in ("depth", "var", "dll", "valid")} for c in range(nc)]
+    out["periods"] = [{k: out[k][c] for k in _PERIOD_KEYS} for c in range(nc)]
+    out["_keep"] = (t, f, lat, A, per)
+    return out
+
+
+class Graph:
+    """Captured graph of the whole search of one light curve (entry point 5).
+
+    The graph is bound to device buffers owned by this object: write new
+    inputs with ``set_inputs`` (same shapes) and ``launch()`` replays factor,
+    inverse, linear and periodic search on the context's stream without any
+    synchronisation; ``status`` holds -1 or the failing pivot of the launch.
+    """
+
+    def __init__(self, ctx: Context, t, f, A, lattice, n_epochs: int, durations, theta, dt: float, periods,
+                 precision: str = "fp64", sign: int = 1):
+        dev = ctx.device
+        self.ctx = ctx
+        self.t = _dev_tensor(t, torch.float64, dev)
+        n = self.t.numel()
+        self.f = _dev_tensor(f, torch.float64, dev)
+        self.m1, self.A = _trend_colmajor(A, n, dev)
+        self.lattice = _dev_tensor(lattice, torch.int64, dev)
+        self.periods = _dev_tensor(periods, torch.float64, dev)
+        self.theta = torch.empty(4, dtype=torch.float64, device=dev)
+        self.status = torch.empty(1, dtype=torch.int64, device=dev)
+        self.set_inputs(theta=theta)
+        self.durs = np.ascontiguousarray(np.asarray(durations, dtype=np.int32))
+        n_d = int(self.durs.size)
+        shape = (n_d, int(n_epochs))
+        self.out = {"depth": torch.empty(shape, dtype=torch.float64, device=dev),
+                    "var": torch.empty(shape, dtype=torch.float64, device=dev),
+                    "dll": torch.empty(shape, dtype=torch.float64, device=dev),
+                    "valid": torch.empty(shape, dtype=torch.uint8, device=dev),
+                    "null": torch.empty(3, dtype=torch.float64, device=dev),
+                    "best_index": torch.empty(1, dtype=torch.int64, device=dev)}
+        n_p = self.periods.numel()
+        for k, dt_ in zip(_PERIOD_KEYS, _PERIOD_DTYPES):
+            self.out[k] = torch.empty(n_p, dtype=dt_, device=dev)
+        p = ctypes.c_void_p()
+        st = lib().nu_graph_create(
+            ctx.ptr, ctypes.c_void_p(self.t.data_ptr()), n, ctypes.c_void_p(self.theta.data_ptr()),
+            ctypes.c_void_p(self.f.data_ptr()), ctypes.c_void_p(self.A.data_ptr() if self.A is not None else 0),
+            self.m1, ctypes.c_void_p(self.lattice.data_ptr()), int(n_epochs),
+            self.durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d, PRECISIONS[precision], float(dt),
+            ctypes.c_void_p(self.periods.data_ptr()), n_p, int(sign),
+            *[ctypes.c_void_p(self.out[k].data_ptr()) for k in ("depth", "var", "dll", "valid", "null")],
+            *[ctypes.c_void_p(self.out[k].data_ptr()) for k in _PERIOD_KEYS],
+            ctypes.c_void_p(self.out["best_index"].data_ptr()), ctypes.c_void_p(self.status.data_ptr()),
+            ctypes.byref(p))
+        _check(ctx.ptr, st)
+        self.ptr = p
+
+    def set_inputs(self, theta=None, f=None, A=None, t=None):
+        """Overwrite bound inputs in place (stream-ordered copies)."""
+        if theta is not None:
+            sho = theta if isinstance(theta, SHO) else SHO.from_dict(theta)
+            self.theta.copy_(torch.tensor([sho.amp, sho.omega, sho.q, sho.sigma_w], dtype=torch.float64))
+        if f is not None:
+            self.f.copy_(_dev_tensor(f, torch.float64, self.f.device))
+        if A is not None:
+            m1, Ac = _trend_colmajor(A, self.t.numel(), self.t.device)
+            if m1 != self.m1:
+                raise ValueError("A must keep its shape")
+            self.A.copy_(Ac)
+        if t is not None:
+            self.t.copy_(_dev_tensor(t, torch.float64, self.t.device))
+
+    def launch(self) -> dict:
+        _check(self.ctx.ptr, lib().nu_graph_launch(self.ctx.ptr, self.ptr))
+        return self.out
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().nu_graph_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnuance_mi355x.so")
 
-SOURCES = ["factor.hip", "gemm.hip", "linear.hip", "fold.hip", "precision.hip", "capi.cpp"]
+SOURCES = ["factor.hip", "gemm.hip", "linear.hip", "fold.hip", "precision.hip", "engine.cpp", "capi.cpp", "batch.cpp"]
 ARCH = os.environ.get("NU_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -1,0 +1,582 @@
+// Execution engine shared by the single-curve entry points, the batch search
+// and the captured graphs: factor allocation, launch schedules of the blocked
+// Cholesky and of the triangular inverse for one or more factors at once, and
+// the enqueue sequences of the factorisation, the inverse, the linear search
+// and the periodic search. Nothing here synchronises except run_factor when
+// asked to read the statuses back.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace nu {
+
+namespace {
+
+int tiles_of(const GemmProblem& g, int tile) {
+  const int tm = g.M / tile, tn = g.N / tile;
+  return (g.flags & G_C_LOWER_TILES) ? tm * (tm + 1) / 2 : tm * tn;
+}
+
+// useful flops of a problem (zeros of triangular operands not counted)
+double useful_flops(const GemmProblem& g) {
+  const double M = g.M, N = g.N, K = g.K;
+  if (g.flags & G_C_LOWER_TILES) return M * (M + 1) * K;          // 2 K per lower element
+  if (g.flags & (G_B_LOWER | G_B_UPPER)) return M * N * (N + 1);  // triangular N x N right factor
+  if (g.flags & G_A_LOWER) return N * M * (M + 1);                // triangular M x M left factor
+  if ((g.flags & G_BT) && g.K == TB && g.N == TB) return M * N * (K + 1);  // panel: triangular X_kk^T
+  return 2.0 * M * N * K;
+}
+
+// Append one launch's problems, numbering tiles from 0 within the launch. A
+// launch with fewer 128 x 128 tiles than small_below uses 64 x 64 tiles (four
+// times the workgroups, each a quarter of the work).
+Range add_launch(std::vector<GemmProblem>& sched, std::vector<GemmProblem> probs, int small_below) {
+  Range r;
+  if (probs.empty()) return r;
+  r.first = (int)sched.size();
+  r.count = (int)probs.size();
+  int big = 0;
+  for (auto& p : probs) big += tiles_of(p, TB);
+  r.tile = big < small_below ? 64 : TB;
+  int t = 0;
+  for (auto& p : probs) {
+    p.tiles_n = p.N / r.tile;
+    p.tile_begin = t;
+    p.tile_count = tiles_of(p, r.tile);
+    t += p.tile_count;
+    r.flops += useful_flops(p);
+    sched.push_back(p);
+  }
+  r.tiles = t;
+  return r;
+}
+
+// element (row, col) of a row-major matrix with leading dimension ld and element size es
+inline const void* at(const void* base, int64_t row, int64_t col, int64_t ld, size_t es) {
+  return static_cast<const char*>(base) + (size_t)(row * ld + col) * es;
+}
+inline void* at(void* base, int64_t row, int64_t col, int64_t ld, size_t es) {
+  return static_cast<char*>(base) + (size_t)(row * ld + col) * es;
+}
+
+GemmProblem prob(const void* A, int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, int M, int N, int K,
+                 int flags, double alpha, double beta) {
+  GemmProblem g{};
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.flags = flags;
+  g.alpha = alpha;
+  g.beta = beta;
+  return g;
+}
+
+struct Node {
+  int a, mid, b;
+};
+
+void build_tree(int a, int b, int depth, std::vector<std::vector<Node>>& levels) {
+  if (b - a < 2) return;
+  const int mid = a + (b - a + 1) / 2;
+  if ((int)levels.size() <= depth) levels.resize(depth + 1);
+  levels[depth].push_back({a, mid, b});
+  build_tree(a, mid, depth + 1, levels);
+  build_tree(mid, b, depth + 1, levels);
+}
+
+// levels of the inverse tree in execution order (deepest first)
+std::vector<std::vector<Node>> inverse_levels(int nblk) {
+  std::vector<std::vector<Node>> levels;
+  build_tree(0, nblk, 0, levels);
+  std::reverse(levels.begin(), levels.end());
+  return levels;
+}
+
+// Outer panel width of the Cholesky, in TB blocks: each panel is factored
+// block by block (diagonal block, its column, the update of the panel's
+// remaining columns), then the trailing matrix gets one update of depth
+// PANEL * TB.
+constexpr int PANEL = 4;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Schedules
+
+void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P) {
+  int steps = 0;
+  for (auto* F : Fs) steps = std::max(steps, F->nblk);
+  P.panel.assign(steps, Range());
+  P.pupd.assign(steps, Range());
+  P.trail.assign(steps, Range());
+  P.job_first.assign(steps, 0);
+  P.job_count.assign(steps, 0);
+  const size_t es = sizeof(double);
+  for (int k = 0; k < steps; ++k) {
+    P.job_first[k] = (int)P.jobs.size();
+    std::vector<GemmProblem> pan, pup, tr;
+    for (auto* F : Fs) {
+      if (k >= F->nblk) continue;
+      const int64_t np = F->np;
+      const int64_t off = (int64_t)k * TB;
+      P.jobs.push_back(PotrfJob{F->L, F->X, F->parts(), F->status_dev(), np, off, k, 0});
+      const int p0 = k / PANEL * PANEL;
+      const int pw = std::min(PANEL, F->nblk - p0);
+      const int rest = (int)(np - off - TB);
+      if (rest > 0) {
+        void* col = at(F->L, off + TB, off, np, es);  // rows below the diagonal block, block column k
+        const void* xkk = at(F->X, off, off, np, es);
+        pan.push_back(prob(col, np, xkk, np, col, np, rest, TB, TB, G_BT, 1.0, 0.0));
+        const int inner = (p0 + pw - k - 1) * TB;  // columns of this panel right of block k
+        if (inner > 0)
+          pup.push_back(prob(col, np, col, np, at(col, 0, TB, np, es), np, rest, inner, TB, G_BT, -1.0, 1.0));
+      }
+      if (k == p0 + pw - 1) {  // last block of the panel: update the trailing matrix
+        const int64_t t0 = (int64_t)(p0 + pw) * TB;
+        const int rest2 = (int)(np - t0);
+        if (rest2 > 0) {
+          const void* pn = at(F->L, t0, (int64_t)p0 * TB, np, es);  // trailing rows, panel columns
+          tr.push_back(prob(pn, np, pn, np, at(F->L, t0, t0, np, es), np, rest2, rest2, pw * TB,
+                            G_BT | G_C_LOWER_TILES, -1.0, 1.0));
+        }
+      }
+    }
+    P.job_count[k] = (int)P.jobs.size() - P.job_first[k];
+    P.panel[k] = add_launch(P.sched, pan, tu.small_below[TC_PANEL]);
+    P.pupd[k] = add_launch(P.sched, pup, tu.small_below[TC_PUPD]);
+    P.trail[k] = add_launch(P.sched, tr, tu.small_below[TC_TRAIL]);
+  }
+}
+
+// Triangular inverse X = L^-1, bottom-up over a binary tree of the TB blocks:
+// for the node [[A, 0], [L21, C]], T = L21 X_A then X21 = -X_C T. Leaves are
+// the diagonal-block inverses. Level e of every factor runs in one launch.
+void plan_inverse(const std::vector<nu_factor*>& Fs, bool f32, const Tuning& tu, Plan& P) {
+  std::vector<std::vector<std::vector<Node>>> lv(Fs.size());
+  size_t nlev = 0;
+  for (size_t i = 0; i < Fs.size(); ++i) {
+    lv[i] = inverse_levels(Fs[i]->nblk);
+    nlev = std::max(nlev, lv[i].size());
+  }
+  const size_t es = f32 ? sizeof(float) : sizeof(double);
+  const int cls = f32 ? TC_INV32 : TC_INV64;
+  P.t1.clear();
+  P.t2.clear();
+  for (size_t e = 0; e < nlev; ++e) {
+    std::vector<GemmProblem> p1, p2;
+    for (size_t i = 0; i < Fs.size(); ++i) {
+      if (e >= lv[i].size()) continue;
+      nu_factor* F = Fs[i];
+      const int64_t np = F->np;
+      const void* L = f32 ? (const void*)F->L32 : (const void*)F->L;
+      void* X = f32 ? (void*)F->X32 : (void*)F->X;
+      size_t off_t = 0;
+      for (const Node& nd : lv[i][e]) {
+        const int64_t a0 = (int64_t)nd.a * TB, m0 = (int64_t)nd.mid * TB;
+        const int na = (nd.mid - nd.a) * TB, nc = (nd.b - nd.mid) * TB;
+        void* Tn = at(F->T, 0, (int64_t)off_t, 0, es);
+        p1.push_back(prob(at(L, m0, a0, np, es), np, at(X, a0, a0, np, es), np, Tn, na, nc, na, na, G_B_LOWER, 1.0,
+                          0.0));
+        p2.push_back(prob(at(X, m0, m0, np, es), np, Tn, na, at(X, m0, a0, np, es), np, nc, na, nc, G_A_LOWER, -1.0,
+                          0.0));
+        off_t += (size_t)na * nc;
+      }
+    }
+    P.t1.push_back(add_launch(P.sched, p1, tu.small_below[cls]));
+    P.t2.push_back(add_launch(P.sched, p2, tu.small_below[cls]));
+  }
+}
+
+size_t inverse_t_elems(int nblk) {
+  size_t tmax = 1;
+  for (const auto& level : inverse_levels(nblk)) {
+    size_t s = 0;
+    for (const Node& nd : level) s += (size_t)(nd.mid - nd.a) * TB * (size_t)(nd.b - nd.mid) * TB;
+    tmax = std::max(tmax, s);
+  }
+  return tmax;
+}
+
+// One Newton step X1 = 2 X - X (L X) on the blocks within BAND_W of the
+// diagonal, FP64: P(I, J) = sum_{K=J..I} L(I, K) X(K, J) for I - J <= w, stored
+// by column block (the blocks P(J..J+w, J) stacked), then
+// X1(I, J) = 2 X(I, J) - sum_{K=J..I} X(I, K) P(K, J) for 1 <= I - J <= w, into
+// the band buffer (which holds X(I, J) on entry).
+void plan_band(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P) {
+  const int w = BAND_W;
+  const size_t es = sizeof(double);
+  const int64_t bs = (int64_t)TB * TB;
+  std::vector<GemmProblem> pp, px;
+  for (nu_factor* F : Fs) {
+    const int64_t np = F->np;
+    for (int I = 0; I < F->nblk; ++I)
+      for (int d = 0; d <= w && d <= I; ++d) {
+        const int J = I - d;
+        pp.push_back(prob(at(F->L, (int64_t)I * TB, (int64_t)J * TB, np, es), np,
+                          at(F->X, (int64_t)J * TB, (int64_t)J * TB, np, es), np,
+                          F->bandP + ((int64_t)J * (w + 1) + d) * bs, TB, TB, TB, (d + 1) * TB, 0, 1.0, 0.0));
+        if (d >= 1)
+          px.push_back(prob(at(F->X, (int64_t)I * TB, (int64_t)J * TB, np, es), np,
+                            F->bandP + (int64_t)J * (w + 1) * bs, TB, F->bandX + ((int64_t)I * (w + 1) + d) * bs,
+                            TB, TB, TB, (d + 1) * TB, 0, -1.0, 2.0));
+      }
+  }
+  P.bandp = add_launch(P.sched, pp, tu.small_below[TC_BAND]);
+  P.bandx = add_launch(P.sched, px, tu.small_below[TC_BAND]);
+}
+
+nu_status plan_upload(nu_ctx* ctx, Plan& P) {
+  nu_status st = check_hip(ctx, hipMalloc(&P.dprobs, std::max<size_t>(P.sched.size(), 1) * sizeof(GemmProblem)),
+                           "alloc schedule");
+  if (st == NU_OK && !P.sched.empty())
+    st = check_hip(ctx, hipMemcpy(P.dprobs, P.sched.data(), P.sched.size() * sizeof(GemmProblem),
+                                  hipMemcpyHostToDevice), "upload schedule");
+  if (st == NU_OK)
+    st = check_hip(ctx, hipMalloc(&P.djobs, std::max<size_t>(P.jobs.size(), 1) * sizeof(PotrfJob)), "alloc jobs");
+  if (st == NU_OK && !P.jobs.empty())
+    st = check_hip(ctx, hipMemcpy(P.djobs, P.jobs.data(), P.jobs.size() * sizeof(PotrfJob), hipMemcpyHostToDevice),
+                   "upload jobs");
+  if (st == NU_OK) P.built = true;
+  return st;
+}
+
+void plan_release(Plan& P) {
+  if (P.dprobs) hipFree(P.dprobs);
+  if (P.djobs) hipFree(P.djobs);
+  P = Plan();
+}
+
+// ---------------------------------------------------------------------------
+// Factors
+
+size_t factor_bytes(int64_t n, bool mixed) {
+  const int64_t np = round_up(n, TB);
+  const int nblk = (int)(np / TB);
+  size_t b = 2 * (size_t)np * np * sizeof(double) + inverse_t_elems(nblk) * sizeof(double) +
+             (size_t)(nblk + FACTOR_SMALL_EXTRA) * sizeof(double) + sizeof(NullFit);
+  if (mixed) b += 2 * (size_t)np * np * sizeof(float) + 2 * (size_t)nblk * (BAND_W + 1) * TB * TB * sizeof(double);
+  return b;
+}
+
+nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out) {
+  *out = nullptr;
+  nu_factor* F = new (std::nothrow) nu_factor();
+  if (!F) return set_error(ctx, NU_ERR_OOM, "factor: host allocation");
+  F->device = ctx->device;
+  F->n = n;
+  F->np = round_up(n, TB);
+  F->nblk = (int)(F->np / TB);
+  const int64_t np = F->np;
+  F->t_elems = inverse_t_elems(F->nblk);
+  nu_status st = check_hip(ctx, hipMalloc(&F->L, (size_t)np * np * sizeof(double)), "alloc L");
+  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->X, (size_t)np * np * sizeof(double)), "alloc X");
+  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->T, F->t_elems * sizeof(double)), "alloc T");
+  if (st == NU_OK)
+    st = check_hip(ctx, hipMalloc(&F->small, (size_t)(F->nblk + FACTOR_SMALL_EXTRA) * sizeof(double)),
+                   "alloc small");
+  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->nullfit, sizeof(NullFit)), "alloc nullfit");
+  if (st == NU_OK && own_plan) {
+    std::vector<nu_factor*> one{F};
+    plan_cholesky(one, ctx->tuning, F->plan64);
+    plan_inverse(one, false, ctx->tuning, F->plan64);
+    st = plan_upload(ctx, F->plan64);
+  }
+  if (st != NU_OK) {
+    factor_free(F);
+    return st;
+  }
+  *out = F;
+  return NU_OK;
+}
+
+// allocations of the reduced-precision inverse (first use only)
+nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F) {
+  if (F->L32) return NU_OK;
+  const int64_t np = F->np;
+  const size_t band_elems = (size_t)F->nblk * (BAND_W + 1) * TB * TB;
+  nu_status st = check_hip(ctx, hipMalloc(&F->L32, (size_t)np * np * sizeof(float)), "alloc L32");
+  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->X32, (size_t)np * np * sizeof(float)), "alloc X32");
+  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->bandP, band_elems * sizeof(double)), "alloc band");
+  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->bandX, band_elems * sizeof(double)), "alloc band");
+  return st;
+}
+
+// the factor's own reduced-precision schedule (the FP32 level products reuse
+// the FP64 T workspace: the same element count fits)
+nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F) {
+  if (F->plan32.built) return NU_OK;
+  nu_status st = alloc_mixed(ctx, F);
+  if (st != NU_OK) return st;
+  std::vector<nu_factor*> one{F};
+  plan_inverse(one, true, ctx->tuning, F->plan32);
+  plan_band(one, ctx->tuning, F->plan32);
+  return plan_upload(ctx, F->plan32);
+}
+
+void factor_free(nu_factor* F) {
+  if (!F) return;
+  hipSetDevice(F->device);
+  hipDeviceSynchronize();
+  void* bufs[] = {F->L, F->X, F->T, F->small, F->nullfit, F->L32, F->X32, F->bandP, F->bandX};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  plan_release(F->plan64);
+  plan_release(F->plan32);
+  delete F;
+}
+
+// ---------------------------------------------------------------------------
+// Enqueue sequences
+
+nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int f32) {
+  if (r.tiles == 0) return NU_OK;
+  Timed tm(ctx, name, r.flops);
+  return check_hip(ctx, launch_gemm(ctx->stream, P.dprobs + r.first, r.count, r.tiles, f32, r.tile), name);
+}
+
+nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P,
+                     const std::vector<const double*>& ts, const std::vector<const nu_sho*>& theta_dev) {
+  nu_status st = NU_OK;
+  for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i) {
+    nu_factor* F = Fs[i];
+    F->inverse_kind = 0;
+    st = check_hip(ctx, launch_fill_i64(ctx->stream, F->status_dev(), -1), "status init");
+    if (st == NU_OK) {
+      Timed tm(ctx, "kbuild", (double)F->n * (double)(F->n + 1) / 2.0);
+      st = check_hip(ctx, launch_kbuild(ctx->stream, ts[i], F->n, F->np, theta_dev[i], F->L), "kbuild");
+    }
+  }
+  // Blocked right-looking Cholesky, two levels: within a panel of PANEL
+  // blocks, diagonal block -> its column (times the diagonal block's inverse)
+  // -> update of the panel's remaining columns; after the panel, one trailing
+  // update of depth PANEL * TB on the whole chip.
+  const int steps = (int)P.job_first.size();
+  for (int k = 0; st == NU_OK && k < steps; ++k) {
+    {
+      Timed tm(ctx, "potrf_diag", (double)P.job_count[k] * TB * TB * TB * 2.0 / 3.0);
+      st = check_hip(ctx, launch_potrf_diag(ctx->stream, P.djobs + P.job_first[k], P.job_count[k]), "potrf_diag");
+    }
+    if (st == NU_OK) st = launch_range(ctx, P, P.panel[k], "gemm_f64:panel", 0);
+    if (st == NU_OK) st = launch_range(ctx, P, P.pupd[k], "gemm_f64:panel_update", 0);
+    if (st == NU_OK) st = launch_range(ctx, P, P.trail[k], "gemm_f64:trailing", 0);
+  }
+  for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i)
+    st = check_hip(ctx, launch_logdet_reduce(ctx->stream, Fs[i]->parts(), Fs[i]->nblk, Fs[i]->logdet_dev()),
+                   "logdet");
+  return st;
+}
+
+nu_status read_factor_status(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, std::vector<int64_t>& status) {
+  std::vector<double> host(2 * Fs.size());
+  nu_status st = NU_OK;
+  for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i)
+    st = check_hip(ctx, hipMemcpyAsync(&host[2 * i], Fs[i]->logdet_dev(), 2 * sizeof(double),
+                                       hipMemcpyDeviceToHost, ctx->stream),
+                   "read logdet and status");
+  if (st == NU_OK) st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "gp_factor sync");
+  if (st != NU_OK) return st;
+  status.resize(Fs.size());
+  for (size_t i = 0; i < Fs.size(); ++i) {
+    Fs[i]->logdet = host[2 * i];
+    std::memcpy(&status[i], &host[2 * i + 1], sizeof(int64_t));
+  }
+  return NU_OK;
+}
+
+nu_status run_inverse_fp64(nu_ctx* ctx, const Plan& P) {
+  nu_status st = NU_OK;
+  for (size_t l = 0; st == NU_OK && l < P.t1.size(); ++l) {
+    st = launch_range(ctx, P, P.t1[l], "gemm_f64:inverse", 0);
+    if (st == NU_OK) st = launch_range(ctx, P, P.t2[l], "gemm_f64:inverse", 0);
+  }
+  return st;
+}
+
+// FP32 doubling levels, then one FP64 Newton step on the blocks within
+// BAND_W of the diagonal. P holds the FP32 levels and the band products of
+// every factor in Fs (their mixed buffers allocated).
+nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P) {
+  nu_status st = NU_OK;
+  for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i) {
+    nu_factor* F = Fs[i];
+    Timed tm(ctx, "convert", 0.0);
+    st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->L, F->L32, F->np, 0), "convert L");
+    if (st == NU_OK) st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->X, F->X32, F->np, 1), "convert X diag");
+  }
+  for (size_t l = 0; st == NU_OK && l < P.t1.size(); ++l) {
+    st = launch_range(ctx, P, P.t1[l], "gemm_f32:inverse", 1);
+    if (st == NU_OK) st = launch_range(ctx, P, P.t2[l], "gemm_f32:inverse", 1);
+  }
+  for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i) {
+    nu_factor* F = Fs[i];
+    {
+      Timed tm(ctx, "convert", 0.0);
+      st = check_hip(ctx, launch_cvt_f32_f64(ctx->stream, F->X32, F->X, F->np), "convert X");
+    }
+    if (st == NU_OK) st = check_hip(ctx, launch_band_copy(ctx->stream, F->X, F->np, F->bandX, BAND_W, 1), "band copy");
+  }
+  if (st == NU_OK) st = launch_range(ctx, P, P.bandp, "gemm_f64:band", 0);
+  if (st == NU_OK) st = launch_range(ctx, P, P.bandx, "gemm_f64:band", 0);
+  for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i)
+    st = check_hip(ctx, launch_band_copy(ctx->stream, Fs[i]->X, Fs[i]->np, Fs[i]->bandX, BAND_W, 0), "band copy");
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// Linear search of one factor (the inverse of the requested kind in place)
+
+namespace {
+constexpr int XRC = 1024;  // rows per partial of the transposed products
+constexpr int QRC = 2048;  // rows per partial of the box sums of squares
+}  // namespace
+
+size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs) {
+  const int64_t np = round_up(n, TB);
+  const size_t xchunks = (size_t)((n + XRC - 1) / XRC), qchunks = (size_t)((n + QRC - 1) / QRC);
+  const size_t yz = (size_t)np * YCOLS;
+  return (5 * yz + xchunks * yz + qchunks * (size_t)n_d * (size_t)n_epochs) * sizeof(double);
+}
+
+nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double* A, int m1, const int64_t* lattice,
+                          int64_t n_epochs, const int32_t* dur_samples_host, int n_d, nu_precision prec,
+                          const void* depth, const void* var, const void* dll, const void* valid) {
+  if (!f || !lattice || !dur_samples_host || !depth || !var || !dll || !valid)
+    return set_error(ctx, NU_ERR_ARG, "linear_search: null argument");
+  if (m1 < 0 || m1 > MAX_M1) return set_error(ctx, NU_ERR_ARG, "linear_search: m1 must be in [0, 7]");
+  if (m1 > 0 && !A) return set_error(ctx, NU_ERR_ARG, "linear_search: A is NULL with m1 > 0");
+  if (n < m1 + 1) return set_error(ctx, NU_ERR_ARG, "linear_search: need n >= m1 + 1");
+  if (n_d < 1 || n_d > MAX_ND) return set_error(ctx, NU_ERR_ARG, "linear_search: n_d must be in [1, 16]");
+  if (n_epochs < 1 || n_epochs > ((int64_t)1 << 31))
+    return set_error(ctx, NU_ERR_ARG, "linear_search: n_epochs must be in [1, 2^31]");
+  if (n_epochs < n) return set_error(ctx, NU_ERR_ARG, "linear_search: n_epochs must be >= n (strict lattice)");
+  for (int j = 0; j < n_d; ++j)
+    if (dur_samples_host[j] < 1 || dur_samples_host[j] > MAX_DUR)
+      return set_error(ctx, NU_ERR_ARG, "linear_search: durations must be in [1, 1024] slots");
+  if (prec != NU_FP64 && prec != NU_FP32_REFINE)
+    return set_error(ctx, NU_ERR_UNSUPPORTED, "linear_search: precision not available in this build");
+  return NU_OK;
+}
+
+nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A, int m1, const int64_t* lattice,
+                     int64_t n_epochs, const int32_t* dur_samples_host, int n_d, bool mixed, double* depth,
+                     double* var, double* dll, uint8_t* valid, double* null_out, double* ws) {
+  const int64_t n = F->n, np = F->np;
+  const int xchunks = (int)((n + XRC - 1) / XRC);
+  const int qchunks = (int)((n + QRC - 1) / QRC);
+  const size_t yz = (size_t)np * YCOLS;
+  double* V = ws;
+  double* Y = V + yz;
+  double* R = Y + yz;
+  double* Z = R + yz;
+  double* Rz = Z + yz;
+  double* xpart = Rz + yz;
+  double* qpart = xpart + (size_t)xchunks * yz;
+  const int nv = m1 + 1;
+  const double gemv_bytes = (double)n * (double)(n + 1) / 2.0 * 8.0;
+  int dmax = 0;
+  for (int j = 0; j < n_d; ++j) dmax = std::max(dmax, (int)dur_samples_host[j]);
+
+  nu_status st = check_hip(ctx, launch_pack_v(ctx->stream, A, m1, f, n, V), "pack_v");
+  if (st != NU_OK) return st;
+  {
+    // Y = X V, refined once against L when X is the mixed inverse
+    Timed tm(ctx, "rows_matvec", gemv_bytes * (mixed ? 3 : 1));
+    st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->X, np, n, V, nv, nullptr, 1.0, Y), "rows_matvec");
+    if (mixed && st == NU_OK)
+      st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->L, np, n, Y, nv, V, -1.0, R), "rows_matvec");
+    if (mixed && st == NU_OK)
+      st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->X, np, n, R, nv, Y, 1.0, Y), "rows_matvec");
+  }
+  if (st != NU_OK) return st;
+  {
+    Timed tm(ctx, "null_solve", 0.0);
+    st = check_hip(ctx, launch_null_solve(ctx->stream, Y, n, m1, F->logdet_dev(), F->nullfit, null_out),
+                   "null_solve");
+  }
+  if (st != NU_OK) return st;
+  {
+    // Z = X^T [A~ | r~0], refined once against L^T when X is the mixed inverse
+    Timed tm(ctx, "cols_matvec", gemv_bytes * (mixed ? 3 : 1));
+    st = check_hip(ctx, launch_cols_matvec(ctx->stream, F->X, np, n, np, Y, nv, xpart, XRC, xchunks, nullptr, 1.0, Z),
+                   "cols_matvec");
+    if (mixed && st == NU_OK)
+      st = check_hip(ctx, launch_cols_matvec(ctx->stream, F->L, np, n, np, Z, nv, xpart, XRC, xchunks, Y, -1.0, Rz),
+                     "cols_matvec");
+    if (mixed && st == NU_OK)
+      st = check_hip(ctx, launch_cols_matvec(ctx->stream, F->X, np, n, np, Rz, nv, xpart, XRC, xchunks, Z, 1.0, Z),
+                     "cols_matvec");
+  }
+  if (st != NU_OK) return st;
+  // ascending durations (nested boxes) with their caller indices
+  std::vector<int32_t> order(n_d);
+  for (int j = 0; j < n_d; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return dur_samples_host[a] < dur_samples_host[b]; });
+  std::vector<int32_t> sorted(2 * n_d);
+  for (int k = 0; k < n_d; ++k) {
+    sorted[k] = dur_samples_host[order[k]];
+    sorted[n_d + k] = order[k];
+  }
+  {
+    Timed tm(ctx, "q_partial", 0.0);
+    st = check_hip(ctx, launch_q_partial(ctx->stream, F->X, np, n, lattice, n_epochs, sorted.data(), n_d, dmax, QRC,
+                                         qchunks, qpart),
+                   "q_partial");
+  }
+  if (st != NU_OK) return st;
+  {
+    Timed tm(ctx, "cell_epilogue", 0.0);
+    st = check_hip(ctx, launch_cell_epilogue(ctx->stream, qpart, qchunks, lattice, n, n_epochs, dur_samples_host,
+                                             nullptr, n_d, Z, m1, F->nullfit, depth, var, dll, valid),
+                   "cell_epilogue");
+  }
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// Periodic search
+
+size_t periodic_ws_bytes(int n_d, int64_t n_epochs) { return fold_workspace_doubles(n_d, n_epochs) * sizeof(double); }
+
+nu_status validate_periodic(nu_ctx* ctx, int n_d, int64_t n_epochs, double dt, int64_t n_p, int log_term_sign) {
+  if (n_d < 1 || n_d > MAX_ND) return set_error(ctx, NU_ERR_ARG, "periodic_search: n_d must be in [1, 16]");
+  if (n_epochs < 1 || n_epochs > ((int64_t)1 << 31))
+    return set_error(ctx, NU_ERR_ARG, "periodic_search: n_epochs must be in [1, 2^31]");
+  if (!(std::isfinite(dt) && dt > 0.0))
+    return set_error(ctx, NU_ERR_ARG, "periodic_search: dt must be finite and > 0");
+  if (n_p < 1 || n_p > ((int64_t)1 << 31) - 1)
+    return set_error(ctx, NU_ERR_ARG, "periodic_search: n_p must be in [1, 2^31)");
+  if (log_term_sign != 1 && log_term_sign != -1)
+    return set_error(ctx, NU_ERR_ARG, "periodic_search: log_term_sign must be +1 or -1");
+  return NU_OK;
+}
+
+nu_status run_periodic(nu_ctx* ctx, const double* depth, const double* var, const double* dll, const uint8_t* valid,
+                       int n_d, int64_t n_epochs, double dt, const double* periods, int64_t n_p, int log_term_sign,
+                       double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth, double* best_sigma,
+                       double* best_lnp, int64_t* best_period_index, double* ws) {
+  nu_status st;
+  {
+    // algorithmic bytes: 24 per event visit (depth, var, dll of one interpolated event), n_d * n_epochs per period
+    Timed tm(ctx, "fold", 24.0 * (double)n_d * (double)n_epochs * (double)n_p);
+    st = check_hip(ctx, launch_fold(ctx->stream, depth, var, dll, valid, n_d, n_epochs, dt, periods, n_p,
+                                    log_term_sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp, ws),
+                   "fold");
+  }
+  if (st == NU_OK && best_period_index) {
+    Timed tm(ctx, "best_period", 0.0);
+    st = check_hip(ctx, launch_best_period(ctx->stream, q_snr, n_p, best_period_index), "best_period");
+  }
+  return st;
+}
+
+}  // namespace nu

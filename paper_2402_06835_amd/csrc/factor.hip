@@ -3,6 +3,8 @@
 //
 // K[n][m] = k_SHO(|t_n - t_m|) + sigma_w^2 delta_nm with the SHO covariance of
 // Appendix A; ln|K| = 2 sum ln L_nn enters Eq. 5.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace nu {
@@ -25,10 +27,10 @@ __device__ __forceinline__ double sho_cov(double tau, double amp, double omega, 
 // Lower triangle of K, padded: rows/columns n >= N hold the identity.
 // Grid: (np/64, np/64) blocks of 64 x 64; upper blocks exit at once.
 __global__ __launch_bounds__(256) void kbuild_kernel(const double* __restrict__ t, int64_t n, int64_t np,
-                                                     double amp, double omega, double q, double s2w,
-                                                     double* __restrict__ K) {
+                                                     const nu_sho* __restrict__ th, double* __restrict__ K) {
   const int64_t br = blockIdx.y, bc = blockIdx.x;
   if (bc > br) return;
+  const double amp = th->amp, omega = th->omega, q = th->q, s2w = th->sigma_w * th->sigma_w;
   const int64_t r0 = br * 64, c0 = bc * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 columns x 4 rows per pass
   const int64_t col = c0 + tx;
@@ -47,10 +49,10 @@ __global__ __launch_bounds__(256) void kbuild_kernel(const double* __restrict__ 
   }
 }
 
-hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho& th, double* K) {
+// theta is read from device memory, so a captured graph picks up new values
+hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho* th_dev, double* K) {
   dim3 grid((unsigned)(np / 64), (unsigned)(np / 64));
-  hipLaunchKernelGGL(kbuild_kernel, grid, dim3(256), 0, s, t, n, np, th.amp, th.omega, th.q,
-                     th.sigma_w * th.sigma_w, K);
+  hipLaunchKernelGGL(kbuild_kernel, grid, dim3(256), 0, s, t, n, np, th_dev, K);
   return hipGetLastError();
 }
 
@@ -147,10 +149,12 @@ __device__ void inverse_level(double (*a)[DPAD], const double* xd) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256, 1) void potrf_diag_kernel(double* __restrict__ L, int64_t ld, int64_t off,
-                                                           int step, double* __restrict__ logdet_parts,
-                                                           int64_t* __restrict__ status, double* __restrict__ X,
-                                                           int64_t ldx) {
+__global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __restrict__ jobs) {
+  const PotrfJob J = jobs[blockIdx.x];
+  double* __restrict__ L = J.L;
+  double* __restrict__ X = J.X;
+  int64_t* __restrict__ status = J.status;
+  const int64_t ld = J.ld, ldx = J.ld, off = J.off;
   __shared__ double a[DB][DPAD];
   __shared__ double xd[DB];
   __shared__ double rdg[DB];  // 1 / L_cc
@@ -244,7 +248,7 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(double* __restrict__
     double v = log(a[lane][lane]) + log(a[lane + 64][lane + 64]);
 #pragma unroll
     for (int offs = 32; offs > 0; offs >>= 1) v += __shfl_xor(v, offs, 64);
-    if (lane == 0) logdet_parts[step] = 2.0 * v;
+    if (lane == 0) J.parts[J.step] = 2.0 * v;
   }
   for (int idx = tid; idx < DB * DB; idx += 256) {
     const int r = idx / DB, c = idx - (idx / DB) * DB;
@@ -282,10 +286,10 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(double* __restrict__
   }
 }
 
-hipError_t launch_potrf_diag(hipStream_t s, double* L, int64_t ld, int64_t off, int step, double* logdet_parts,
-                             int64_t* status, double* Xdiag, int64_t ldx) {
-  hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, L, ld, off, step, logdet_parts, status, Xdiag,
-                     ldx);
+// one workgroup per job (one diagonal block per factor of a batch)
+hipError_t launch_potrf_diag(hipStream_t s, const PotrfJob* jobs, int njobs) {
+  if (njobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(potrf_diag_kernel, dim3((unsigned)njobs), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 
@@ -295,6 +299,60 @@ __global__ void fill_i64_kernel(int64_t* __restrict__ p, int64_t v) {
 
 hipError_t launch_fill_i64(hipStream_t s, int64_t* p, int64_t v) {
   hipLaunchKernelGGL(fill_i64_kernel, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+__global__ void copy_i64_kernel(const int64_t* __restrict__ src, int64_t* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+hipError_t launch_copy_i64(hipStream_t s, const int64_t* src, int64_t* dst) {
+  hipLaunchKernelGGL(copy_i64_kernel, dim3(1), dim3(64), 0, s, src, dst);
+  return hipGetLastError();
+}
+
+// outputs of a light curve whose covariance could not be factored: every
+// cell invalid (depth 0, var +inf, dll 0) and no event at any period
+__global__ void fill_invalid_cells_kernel(int64_t count, double* __restrict__ depth, double* __restrict__ var,
+                                          double* __restrict__ dll, uint8_t* __restrict__ valid) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    depth[i] = 0.0;
+    var[i] = INFINITY;
+    dll[i] = 0.0;
+    valid[i] = 0;
+  }
+}
+
+hipError_t launch_fill_invalid_cells(hipStream_t s, int64_t count, double* depth, double* var, double* dll,
+                                     uint8_t* valid) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_invalid_cells_kernel, dim3((unsigned)blocks), dim3(256), 0, s, count, depth, var, dll,
+                     valid);
+  return hipGetLastError();
+}
+
+__global__ void fill_no_event_kernel(int64_t n_p, double* __restrict__ q_snr, int64_t* __restrict__ best_phase,
+                                     int32_t* __restrict__ best_dur, double* __restrict__ best_depth,
+                                     double* __restrict__ best_sigma, double* __restrict__ best_lnp,
+                                     int64_t* __restrict__ best_period) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0 && best_period) *best_period = -1;
+  for (int64_t i = i0; i < n_p; i += (int64_t)gridDim.x * blockDim.x) {
+    q_snr[i] = 0.0;
+    best_phase[i] = -1;
+    best_dur[i] = -1;
+    best_depth[i] = 0.0;
+    best_sigma[i] = 0.0;
+    best_lnp[i] = -INFINITY;
+  }
+}
+
+hipError_t launch_fill_no_event(hipStream_t s, int64_t n_p, double* q_snr, int64_t* best_phase, int32_t* best_dur,
+                                double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period) {
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n_p + 255) / 256, 4096));
+  hipLaunchKernelGGL(fill_no_event_kernel, dim3((unsigned)blocks), dim3(256), 0, s, n_p, q_snr, best_phase, best_dur,
+                     best_depth, best_sigma, best_lnp, best_period);
   return hipGetLastError();
 }
 

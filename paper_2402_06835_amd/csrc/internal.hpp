@@ -50,6 +50,13 @@ struct GemmProblem {
   int pad_;
 };
 
+// Launch classes of the dense schedule. Each class takes 64 x 64 output tiles
+// when a launch has fewer 128 x 128 tiles than its threshold.
+enum TuneClass { TC_PANEL = 0, TC_PUPD, TC_TRAIL, TC_INV64, TC_INV32, TC_BAND, TC_COUNT };
+struct Tuning {
+  int small_below[TC_COUNT] = {512, 512, 512, 512, 512, 512};
+};
+
 struct NullFit {
   double G0chol[MAX_M1 * MAX_M1];  // lower Cholesky factor of A^T K^-1 A
   double w0[MAX_M1];
@@ -87,6 +94,8 @@ struct nu_ctx {
   std::vector<hipEvent_t> free_events;
   std::map<std::string, nu_timing_slot> timings;
   std::vector<std::string> timing_names;
+  // tile policy of the dense launches (set by the autotuner)
+  nu::Tuning tuning;
 };
 
 namespace nu {
@@ -97,33 +106,64 @@ struct Range {
   double flops = 0.0;
 };
 constexpr int BAND_W = 2;  // block diagonals refined after a reduced-precision inverse
+
+// One diagonal block of the blocked Cholesky (one workgroup of a launch).
+struct PotrfJob {
+  double* L;            // the factor, row-major, leading dimension ld
+  double* X;            // the inverse, same layout
+  double* parts;        // per-step ln|L_kk| terms
+  int64_t* status;      // first failing pivot, or -1
+  int64_t ld;
+  int64_t off;          // row and column of the block's first element
+  int step;             // block index
+  int pad_;
+};
+
+// Schedule of the dense work of one or more factors run together: grouped
+// GEMM launches whose problem lists span every factor, and the diagonal
+// blocks of each Cholesky step as one launch of one workgroup per factor.
+struct Plan {
+  std::vector<GemmProblem> sched;
+  GemmProblem* dprobs = nullptr;
+  std::vector<PotrfJob> jobs;
+  PotrfJob* djobs = nullptr;
+  std::vector<int> job_first, job_count;  // per Cholesky step
+  std::vector<Range> panel, pupd, trail;  // per Cholesky step (trail: launched after the step)
+  std::vector<Range> t1, t2;              // per inverse level, deepest first
+  Range bandp, bandx;
+  bool built = false;
+};
+void plan_release(Plan& P);
+
 }  // namespace nu
 
 struct nu_factor {
   int device = 0;
   int64_t n = 0;    // samples
   int64_t np = 0;   // padded to a multiple of TB
+  int nblk = 0;     // np / TB
   double* L = nullptr;       // np x np row-major; lower triangle = Cholesky factor
   double* X = nullptr;       // np x np row-major; lower triangle = L^-1 (diagonal blocks at factor time)
   double* T = nullptr;       // workspace of the triangular-inverse levels
   size_t t_elems = 0;
-  double* small = nullptr;   // logdet parts, logdet, status
+  double* small = nullptr;   // [nblk] logdet parts, logdet, status (int64), theta (4), spare
   nu::NullFit* nullfit = nullptr;
-  // FP64 schedule: Cholesky and triangular inverse
-  nu::GemmProblem* probs = nullptr;
-  std::vector<nu::GemmProblem> sched;
-  std::vector<nu::Range> panel, pupd, trail, t1, t2;
+  nu_sho theta_host{};       // source of the theta upload of the last factorisation
+  nu::Plan plan64;           // Cholesky + FP64 inverse
   // reduced-precision inverse (allocated on first use)
   float* L32 = nullptr;
   float* X32 = nullptr;
   double* bandP = nullptr;   // (I, d) blocks of L X on the band, stored by column block
   double* bandX = nullptr;   // refined band blocks
-  nu::GemmProblem* probs32 = nullptr;
-  std::vector<nu::GemmProblem> sched32;
-  std::vector<nu::Range> t1_32, t2_32, bandp, bandx;
+  nu::Plan plan32;           // FP32 inverse + FP64 band step
   int inverse_kind = 0;  // 0 none, 1 FP64, 2 FP32 levels + refinement
   double logdet = 0.0;
+  double* parts() const { return small; }
+  double* logdet_dev() const { return small + nblk; }
+  int64_t* status_dev() const { return reinterpret_cast<int64_t*>(small + nblk + 1); }
+  nu_sho* theta_dev() const { return reinterpret_cast<nu_sho*>(small + nblk + 2); }
 };
+constexpr int FACTOR_SMALL_EXTRA = 8;  // doubles of `small` after the per-block parts
 
 namespace nu {
 
@@ -132,15 +172,60 @@ nu_status set_error(nu_ctx* ctx, nu_status st, const std::string& msg);
 nu_status check_hip(nu_ctx* ctx, hipError_t e, const char* what);
 void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st);
 
-// kernel timing (capi.cpp)
+// kernel timing (capi.cpp): events on the context's stream around a launch
 void timing_begin(nu_ctx* ctx, hipStream_t s, hipEvent_t* start);
 void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, double work);
+void resolve_timing(nu_ctx* ctx);  // synchronises the stream, folds pending events into the totals
+struct Timed {
+  nu_ctx* ctx;
+  const char* name;
+  double work;
+  hipEvent_t start;
+  Timed(nu_ctx* c, const char* n, double w) : ctx(c), name(n), work(w) { timing_begin(c, c->stream, &start); }
+  ~Timed() { timing_end(ctx, ctx->stream, name, start, work); }
+};
+
+// engine (engine.cpp)
+void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P);
+void plan_inverse(const std::vector<nu_factor*>& Fs, bool f32, const Tuning& tu, Plan& P);
+void plan_band(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P);
+size_t inverse_t_elems(int nblk);
+nu_status plan_upload(nu_ctx* ctx, Plan& P);
+size_t factor_bytes(int64_t n, bool mixed);
+nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out);
+nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F);
+nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F);
+void factor_free(nu_factor* F);
+nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int f32);
+nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P,
+                     const std::vector<const double*>& ts, const std::vector<const nu_sho*>& theta_dev);
+nu_status read_factor_status(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, std::vector<int64_t>& status);
+nu_status run_inverse_fp64(nu_ctx* ctx, const Plan& P);
+nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P);
+size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs);
+nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double* A, int m1, const int64_t* lattice,
+                          int64_t n_epochs, const int32_t* dur_samples_host, int n_d, nu_precision prec,
+                          const void* depth, const void* var, const void* dll, const void* valid);
+nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A, int m1, const int64_t* lattice,
+                     int64_t n_epochs, const int32_t* dur_samples_host, int n_d, bool mixed, double* depth,
+                     double* var, double* dll, uint8_t* valid, double* null_out, double* ws);
+size_t periodic_ws_bytes(int n_d, int64_t n_epochs);
+nu_status validate_periodic(nu_ctx* ctx, int n_d, int64_t n_epochs, double dt, int64_t n_p, int log_term_sign);
+nu_status run_periodic(nu_ctx* ctx, const double* depth, const double* var, const double* dll, const uint8_t* valid,
+                       int n_d, int64_t n_epochs, double dt, const double* periods, int64_t n_p, int log_term_sign,
+                       double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth, double* best_sigma,
+                       double* best_lnp, int64_t* best_period_index, double* ws);
+nu_status validate_theta(nu_ctx* ctx, const nu_sho* theta);
 
 // launchers (*.hip)
-hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho& th, double* K);
+hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho* th_dev, double* K);
 hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32, int tile);
-hipError_t launch_potrf_diag(hipStream_t s, double* L, int64_t ld, int64_t off, int step, double* logdet_parts,
-                             int64_t* status, double* Xdiag, int64_t ldx);
+hipError_t launch_potrf_diag(hipStream_t s, const PotrfJob* jobs, int njobs);
+hipError_t launch_copy_i64(hipStream_t s, const int64_t* src, int64_t* dst);
+hipError_t launch_fill_invalid_cells(hipStream_t s, int64_t count, double* depth, double* var, double* dll,
+                                     uint8_t* valid);
+hipError_t launch_fill_no_event(hipStream_t s, int64_t n_p, double* q_snr, int64_t* best_phase, int32_t* best_dur,
+                                double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period);
 hipError_t launch_fill_i64(hipStream_t s, int64_t* p, int64_t v);
 hipError_t launch_cvt_f64_f32(hipStream_t s, const double* src, float* dst, int64_t np, int diag_only);
 hipError_t launch_cvt_f32_f64(hipStream_t s, const float* src, double* dst, int64_t np);

@@ -48,6 +48,25 @@ def test_library_loads_and_binding_declares_every_symbol(libpath):
         assert n in _lib.SIGNATURES, f"binding lacks {n}"
 
 
+def declared_arity():
+    """Number of parameters of every function the header declares."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(nu_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", src):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_arity_matches_the_header():
+    from paper_2402_06835_amd import _lib
+    arity = declared_arity()
+    assert set(arity) == set(declared_functions())
+    for name, n in arity.items():
+        assert len(_lib.SIGNATURES[name][1]) == n, name
+
+
 def test_null_context_is_rejected_without_a_gpu(libpath):
     import ctypes
     from paper_2402_06835_amd import _lib
@@ -58,6 +77,23 @@ def test_null_context_is_rejected_without_a_gpu(libpath):
                               None) == _lib.NU_ERR_ARG
     assert L.nu_periodic_search(None, None, None, None, None, 0, 0, 0.0, None, 0, 1, None, None, None, None,
                                 None, None, None) == _lib.NU_ERR_ARG
+    def zeros(name):
+        # NULL for pointers, 0 for integers and doubles
+        out = []
+        for t in _lib.SIGNATURES[name][1]:
+            if t in (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t):
+                out.append(0)
+            elif t is ctypes.c_double:
+                out.append(0.0)
+            else:
+                out.append(None)
+        return out
+
+    assert L.nu_search_batch(*zeros("nu_search_batch")) == _lib.NU_ERR_ARG
+    assert L.nu_graph_create(*zeros("nu_graph_create")) == _lib.NU_ERR_ARG
+    assert L.nu_graph_launch(None, None) == _lib.NU_ERR_ARG
+    assert L.nu_ctx_autotune(None, 1024, 0) == _lib.NU_ERR_ARG
+    assert L.nu_ctx_set_tuning(None, 0, 0) == _lib.NU_ERR_ARG
     assert L.nu_ctx_create(0, None, None) == _lib.NU_ERR_ARG
     assert L.nu_ctx_last_error(None) == b"null context"
     assert L.nu_factor_n(None) == -1

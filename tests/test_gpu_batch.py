@@ -1,0 +1,241 @@
+"""GPU: batch search of uneven light curves, captured graphs and the tile
+policy, all through the C ABI.
+
+The batch and the graph run the same kernels as the single-curve calls, on
+the same per-curve problems, so their outputs must equal the single-curve
+outputs bit for bit (those are parity-tested against the oracle elsewhere);
+two curves are also compared with the oracle directly. The tile policy only
+changes the shape of the output tiles: every element sums the same products
+in the same order, so a search under forced 64 x 64 tiles must equal one
+under forced 128 x 128 tiles bit for bit.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle import gp as ogp, linear as olin
+from synth import make_workload, sho_omega_from_rotation
+
+pytestmark = pytest.mark.gpu
+
+CELL_KEYS = ("depth", "var", "dll", "valid")
+PERIOD_KEYS = ("q_snr", "best_phase", "best_dur", "best_depth", "best_sigma", "best_lnp")
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    from paper_2402_06835_amd import _lib, api as a
+    _lib.lib()
+    assert torch.cuda.is_available()
+    return a
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0)
+
+
+DURS = [1, 4, 9, 17]
+PERIODS = np.linspace(0.3, 2.0, 60)
+DT = 10 / 1440
+
+
+def _curve(n, seed, prot, gap=None):
+    th = {"amp": 0.01, "omega": sho_omega_from_rotation(prot, 5.0), "q": 5.0, "sigma_w": 1e-3}
+    w = make_workload(f"batch-N{n}-s{seed}", seed, n, DT, th, DURS, PERIODS, gaps=[gap] if gap else [],
+                      injection={"depth": 2e-3, "period": 0.61, "t0": 0.13, "duration": 0.05})
+    return w
+
+
+def _curves():
+    # uneven lengths: several tiles, ragged tails, one gap, one curve shorter than a tile
+    return [_curve(700, 11, 1.2, gap=(333, 25)), _curve(300, 12, 0.8), _curve(1000, 13, 1.6),
+            _curve(129, 14, 1.0), _curve(515, 15, 0.5)]
+
+
+def _as_batch_input(w):
+    return {"t": w.t, "f": w.f, "A": w.A, "lattice": w.lattice, "n_epochs": w.n_epochs, "theta": w.theta,
+            "dt": DT}
+
+
+def _single(api, ctx, w, precision):
+    import torch
+    fac = api.gp_factor(ctx, w.t, w.theta)
+    ls = api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, DURS, precision)
+    ps = api.periodic_search(ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], DT, PERIODS)
+    torch.cuda.synchronize()
+    out = {k: ls[k].cpu().numpy() for k in CELL_KEYS}
+    out.update({k: ps[k].cpu().numpy() for k in PERIOD_KEYS})
+    out["null"] = ls["null"].cpu().numpy()
+    out["best_index"] = int(ps["best_index"].cpu().item())
+    out["logdet"] = fac.logdet
+    fac.close()
+    return out
+
+
+def _assert_same(a, b, tag):
+    for k in CELL_KEYS + PERIOD_KEYS + ("null",):
+        np.testing.assert_array_equal(np.asarray(a[k]), np.asarray(b[k]), err_msg=f"{tag}: {k}")
+    assert a["best_index"] == b["best_index"], tag
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_batch_equals_single_curve_calls(api, ctx, precision):
+    import torch
+    ws = _curves()
+    say(f"batch of {len(ws)} curves, N={[w.n for w in ws]}, {precision}")
+    res = api.search_batch(ctx, [_as_batch_input(w) for w in ws], DURS, PERIODS, precision=precision)
+    torch.cuda.synchronize()
+    assert np.all(res["fail_pivot"] == -1)
+    best = res["best_index"].cpu().numpy()
+    for c, w in enumerate(ws):
+        single = _single(api, ctx, w, precision)
+        got = {k: res["cells"][c][k].cpu().numpy() for k in CELL_KEYS}
+        got.update({k: res["periods"][c][k].cpu().numpy() for k in PERIOD_KEYS})
+        got["null"] = res["null"][c].cpu().numpy()
+        got["best_index"] = int(best[c])
+        _assert_same(got, single, f"curve {c} N={w.n}")
+        assert res["logdet"][c] == single["logdet"]
+
+
+def test_batch_against_oracle(api, ctx):
+    import torch
+    ws = [_curve(300, 21, 0.9), _curve(129, 22, 1.3, gap=(60, 4))]
+    say("batch of 2 curves vs the oracle, fp64")
+    res = api.search_batch(ctx, [_as_batch_input(w) for w in ws], DURS, PERIODS, precision="fp64")
+    torch.cuda.synchronize()
+    for c, w in enumerate(ws):
+        L = ogp.cholesky(ogp.covariance(w.t, w.theta))
+        ref = olin.linear_search(w.f, w.A, L, w.lattice, DURS)
+        got = {k: res["cells"][c][k].cpu().numpy() for k in CELL_KEYS}
+        v = ref["valid"].astype(bool)
+        np.testing.assert_array_equal(got["valid"].astype(bool), v)
+        e = np.abs(got["dll"][v] - ref["dll"][v]) / np.maximum(np.abs(ref["dll"][v]), 1.0)
+        assert e.max() <= 1e-9
+        assert res["logdet"][c] == pytest.approx(ref["logdet"], rel=1e-12)
+
+
+def test_batch_waves_under_a_small_budget(api, ctx):
+    import torch
+    ws = _curves()
+    say("batch split into waves by a small memory budget")
+    one = api.search_batch(ctx, [_as_batch_input(w) for w in ws], DURS, PERIODS, precision="fp64")
+    # room for the largest factor (N=1000: at most 2.25 * 1024^2 doubles) and a little more: several waves
+    budget = 20 << 20
+    many = api.search_batch(ctx, [_as_batch_input(w) for w in ws], DURS, PERIODS, precision="fp64",
+                            memory_budget=budget)
+    torch.cuda.synchronize()
+    for k in CELL_KEYS + PERIOD_KEYS + ("null", "best_index"):
+        np.testing.assert_array_equal(one[k].cpu().numpy(), many[k].cpu().numpy(), err_msg=k)
+
+
+def test_batch_budget_too_small_is_oom(api, ctx):
+    from paper_2402_06835_amd._lib import NU_ERR_OOM, NuanceError
+    ws = _curves()[:2]
+    say("batch with a budget below one factor")
+    with pytest.raises(NuanceError) as ei:
+        api.search_batch(ctx, [_as_batch_input(w) for w in ws], DURS, PERIODS, precision="fp64",
+                         memory_budget=1024)
+    assert ei.value.status == NU_ERR_OOM
+
+
+def test_batch_not_positive_definite_curve(api, ctx):
+    import torch
+    from paper_2402_06835_amd._lib import NU_ERR_NOT_PD, NuanceError
+    ws = [_curve(300, 31, 0.9), _curve(200, 32, 1.1), _curve(150, 33, 0.7)]
+    ws[1].theta = {"amp": 0.0, "omega": 3.0, "q": 5.0, "sigma_w": 0.0}  # K = 0: first pivot fails
+    say("batch with a zero covariance in the middle")
+    with pytest.raises(NuanceError) as ei:
+        api.search_batch(ctx, [_as_batch_input(w) for w in ws], DURS, PERIODS, precision="fp64")
+    assert ei.value.status == NU_ERR_NOT_PD
+    res = api.search_batch(ctx, [_as_batch_input(w) for w in ws], DURS, PERIODS, precision="fp64",
+                           raise_not_pd=False)
+    torch.cuda.synchronize()
+    assert list(res["fail_pivot"]) == [-1, 0, -1]
+    bad = res["cells"][1]
+    assert not bad["valid"].any().item() and bool(torch.isinf(bad["var"]).all().item())
+    assert bool((res["periods"][1]["best_phase"] == -1).all().item())
+    assert int(res["best_index"][1].item()) == -1
+    for c in (0, 2):
+        single = _single(api, ctx, ws[c], "fp64")
+        np.testing.assert_array_equal(res["cells"][c]["dll"].cpu().numpy(), single["dll"])
+        np.testing.assert_array_equal(res["periods"][c]["q_snr"].cpu().numpy(), single["q_snr"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_graph_replays_match_eager(api, ctx, precision):
+    import torch
+    w = _curve(700, 41, 1.2, gap=(333, 25))
+    say(f"graph N=700, {precision}: three replays with new theta and flux")
+    g = api.Graph(ctx, w.t, w.f, w.A, w.lattice, w.n_epochs, DURS, w.theta, DT, PERIODS, precision=precision)
+    rng = np.random.default_rng(5)
+    for rep in range(3):
+        theta = dict(w.theta)
+        theta["amp"] = w.theta["amp"] * (1.0 + 0.3 * rep)
+        theta["sigma_w"] = w.theta["sigma_w"] * (1.0 + 0.2 * rep)
+        f = w.f + 1e-4 * rng.standard_normal(w.n)
+        g.set_inputs(theta=theta, f=f)
+        out = g.launch()
+        torch.cuda.synchronize()
+        assert int(g.status.item()) == -1
+        got = {k: out[k].cpu().numpy() for k in CELL_KEYS + PERIOD_KEYS + ("null",)}
+        got["best_index"] = int(out["best_index"].item())
+        # eager run of the same inputs between replays
+        w2 = copy.copy(w)
+        w2.theta, w2.f = theta, f
+        _assert_same(got, _single(api, ctx, w2, precision), f"replay {rep}")
+    g.close()
+
+
+def test_graph_reports_not_pd_without_sync(api, ctx):
+    import torch
+    w = _curve(300, 42, 1.0)
+    say("graph with a zero covariance on the second launch")
+    g = api.Graph(ctx, w.t, w.f, w.A, w.lattice, w.n_epochs, DURS, w.theta, DT, PERIODS)
+    g.launch()
+    torch.cuda.synchronize()
+    assert int(g.status.item()) == -1
+    g.set_inputs(theta={"amp": 0.0, "omega": 3.0, "q": 5.0, "sigma_w": 0.0})
+    g.launch()
+    torch.cuda.synchronize()
+    assert int(g.status.item()) == 0
+    g.set_inputs(theta=w.theta)
+    out = g.launch()
+    torch.cuda.synchronize()
+    assert int(g.status.item()) == -1
+    np.testing.assert_array_equal(out["dll"].cpu().numpy(), _single(api, ctx, w, "fp64")["dll"])
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_tile_policy_does_not_change_results(api, ctx, precision):
+    from paper_2402_06835_amd._lib import TUNE_CLASSES
+    w = _curve(1000, 51, 1.3, gap=(400, 30))
+    say(f"tile policy: all 128 vs all 64, N=1000, {precision}")
+    c = api.Context(0)
+    c.set_tuning(**{k: 0 for k in TUNE_CLASSES})
+    big = _single(api, c, w, precision)
+    c.set_tuning(**{k: 1 << 30 for k in TUNE_CLASSES})
+    small = _single(api, c, w, precision)
+    _assert_same(big, small, "64 vs 128 tiles")
+    assert big["logdet"] == small["logdet"]
+    c.close()
+
+
+def test_autotune_keeps_results(api, ctx):
+    w = _curve(700, 61, 1.1)
+    say("autotune at n=2048, fp32_refine")
+    c = api.Context(0)
+    before = _single(api, c, w, "fp32_refine")
+    tuned = c.autotune(2048, "fp32_refine")
+    say(f"tuned thresholds {tuned}")
+    assert set(tuned.values()) <= {0, 256, 512, 1024, 2048, 1 << 30}
+    after = _single(api, c, w, "fp32_refine")
+    _assert_same(before, after, "autotuned")
+    c.close()
