@@ -13,6 +13,15 @@ wall time (plus light curves per second), the roofline of the dominant
 kernel from HIP events recorded by the library around its launches inside
 the timed region, and the CPU oracle timed on a bounded sample of the same
 workload.
+
+Default precision: FP32_REFINE (FP64 Cholesky, FP32 inverse products with an
+FP64 band Newton step and one refinement step), the fastest path that meets
+the 1e-6 dll bar; its dll error against the FP64 path on the same curve is
+measured after the timed region and reported. Other modes:
+  --mode graph          the same step as one captured-graph launch
+  --workload batch-64   64 curves of 4000..20000 samples in one batch call per step
+                        (--mode loop: the same curves through the single-curve calls)
+  --autotune            tile policy tuned on the device before warming up
 """
 from __future__ import annotations
 
@@ -88,13 +97,176 @@ def cpu_baseline(w, n_valid: int, budget_cells: int = 192, budget_periods: int =
     }
 
 
+def roofline_of(timings):
+    """Dominant kernel (by accumulated time) and its achieved rate against the MI355X peak."""
+    merged = {}
+    for k, v in timings.items():
+        base = k.split(":")[0]
+        m = merged.setdefault(base, {"launches": 0, "ms": 0.0, "work": 0.0})
+        for f in m:
+            m[f] += v[f]
+    name, tk = max(merged.items(), key=lambda kv: kv[1]["ms"])
+    common = {"kernel": name, "traffic": None, "launches": tk["launches"], "avg_launch_ms": tk["ms"] / tk["launches"],
+              "work_per_launch": tk["work"] / tk["launches"]}
+    if name.startswith("gemm_"):
+        achieved = tk["work"] / (tk["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAKS[name], "unit": "TFLOP/s",
+                "frac": achieved / PEAKS[name], "work_unit": "flop (algorithmic)"}
+    else:
+        achieved = tk["work"] / (tk["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+                "frac": achieved / PEAKS["hbm_gbs"], "work_unit": "byte (algorithmic)"}
+    roof.update(common)
+    gemms = {k: {"tflops": v["work"] / (v["ms"] * 1e-3) / 1e12, "ms": v["ms"]}
+             for k, v in merged.items() if k.startswith("gemm_")}
+    return roof, gemms
+
+
+def dll_error(dll, dll_ref, valid_ref):
+    import torch
+    v = valid_ref.bool()
+    ref = dll_ref[v]
+    err = (dll[v] - ref).abs() / ref.abs().clamp(min=1.0)
+    return {"max": float(err.max().item()), "p999": float(torch.quantile(err.float(), 0.999).item())}
+
+
+def bench_batch(args, api, ctx, torch):
+    """The uneven 64-curve batch in one batch call per step."""
+    from synth import config3
+    t0 = time.perf_counter()
+    ws = config3()
+    log(f"batch of {len(ws)} curves generated in {time.perf_counter() - t0:.1f} s; N from "
+        f"{min(w.n for w in ws)} to {max(w.n for w in ws)}")
+    curves = [{"t": w.t, "f": w.f, "A": w.A, "lattice": w.lattice, "n_epochs": w.n_epochs, "theta": w.theta,
+               "dt": w.dt} for w in ws]
+    durs, periods = ws[0].durations, ws[0].periods
+    batch = api.prepare_batch(ctx, curves)
+    per = torch.as_tensor(periods, device=ctx.device)
+    dev_in = [{"t": torch.as_tensor(w.t, device=ctx.device), "f": torch.as_tensor(w.f, device=ctx.device),
+               "A": torch.as_tensor(w.A, device=ctx.device), "lattice": torch.as_tensor(w.lattice, device=ctx.device),
+               "periods": per} for w in ws] if args.mode == "loop" else None
+
+    def one_step():
+        if dev_in is None:
+            return api.search_batch(ctx, batch, durs, per, precision=args.precision)
+        # the same curves one by one through the single-curve entry points
+        valid = []
+        for w, d in zip(ws, dev_in):
+            fac, ls, _ = run_step(api, ctx, d, w, args.precision)
+            valid.append(ls["valid"].reshape(-1))
+            fac.close()
+        return {"valid": torch.cat(valid)}
+
+    for i in range(max(args.warmup, 1)):
+        res = one_step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    ctx.enable_timing(True)
+    ctx.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = one_step()
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timings = ctx.timings()
+    ctx.enable_timing(False)
+    n_valid = int(res["valid"].sum().item())
+    if dev_in is not None:
+        log(f"{args.steps} loops of {len(ws)} single-curve searches in {elapsed:.3f} s: "
+            f"{n_valid * args.steps / elapsed:.4g} fits/s, {len(ws) * args.steps / elapsed:.4g} curves/s")
+        cfg = {"workload": "uneven-batch-64x(4000..20000)", "n_curves": len(ws), "valid_cells": n_valid,
+               "precision": args.precision, "mode": "loop of single-curve calls"}
+        return elapsed, n_valid, len(ws), timings, None, cfg, {}
+    dll_err = None
+    if args.precision != "fp64":
+        ref = api.search_batch(ctx, batch, durs, per, precision="fp64")
+        dll_err = dll_error(res["dll"], ref["dll"], ref["valid"])
+        log(f"dll error vs fp64: {dll_err}")
+    best = res["best_index"].cpu().numpy()
+    found = sum(1 for c, w in enumerate(ws) if w.injection and best[c] >= 0 and
+                abs(periods[best[c]] - w.injection["period"]) < 0.01 * w.injection["period"])
+    n_inj = sum(1 for w in ws if w.injection)
+    log(f"{args.steps} batches in {elapsed:.3f} s: {n_valid * args.steps / elapsed:.4g} fits/s, "
+        f"{len(ws) * args.steps / elapsed:.4g} curves/s; injected periods recovered {found}/{n_inj}")
+    cfg = {"workload": "uneven-batch-64x(4000..20000)", "n_curves": len(ws),
+           "n_samples_total": int(sum(w.n for w in ws)), "n_durations": int(len(durs)),
+           "n_periods": int(len(periods)), "valid_cells": n_valid, "precision": args.precision,
+           "mode": "batch call"}
+    return elapsed, n_valid, len(ws), timings, dll_err, cfg, {"injected_recovered": f"{found}/{n_inj}"}
+
+
+def bench_curve(args, api, ctx, torch):
+    """One TESS-sector-shaped curve per step (eager calls, or one captured-graph launch)."""
+    w = workload(args.workload)
+    dev = ctx.device
+    dev_in = {
+        "t": torch.as_tensor(w.t, device=dev), "f": torch.as_tensor(w.f, device=dev),
+        "A": torch.as_tensor(w.A, device=dev), "lattice": torch.as_tensor(w.lattice, device=dev),
+        "periods": torch.as_tensor(w.periods, device=dev),
+    }
+    fac = None
+    g = None
+    if args.mode == "graph":
+        g = api.Graph(ctx, dev_in["t"], dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations,
+                      w.theta, w.dt, dev_in["periods"], precision=args.precision)
+    for i in range(max(args.warmup, 1)):
+        if g is None:
+            fac, _, _ = run_step(api, ctx, dev_in, w, args.precision, fac)
+        else:
+            g.launch()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    ctx.enable_timing(g is None)
+    ctx.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    keep = None
+    for i in range(args.steps):
+        # one curve per step; the factor's device buffers are reused across curves of one length
+        if g is None:
+            keep = run_step(api, ctx, dev_in, w, args.precision, fac)
+        else:
+            g.launch()
+        log(f"step {i + 1}/{args.steps} enqueued")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timings = ctx.timings()
+    ctx.enable_timing(False)
+    if g is None:
+        fac, ls, ps = keep
+        valid, dll, best = ls["valid"], ls["dll"], int(ps["best_index"].item())
+    else:
+        assert int(g.status.item()) == -1
+        valid, dll, best = g.out["valid"], g.out["dll"], int(g.out["best_index"].item())
+        fac = api.gp_factor(ctx, dev_in["t"], w.theta)
+    n_valid = int(valid.sum().item())
+    dll_err = None
+    if args.precision != "fp64":
+        # accuracy of this precision against the FP64 path on the same curve (outside the timed region)
+        ls64 = api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations)
+        dll_err = dll_error(dll, ls64["dll"], ls64["valid"])
+        log(f"dll error vs fp64: {dll_err}")
+    log(f"{args.steps} steps in {elapsed:.3f} s: {n_valid * args.steps / elapsed:.4g} fits/s, "
+        f"{args.steps / elapsed:.4g} curves/s; best period {w.periods[best] if best >= 0 else None}")
+    cfg = {"workload": w.name, "n_samples": w.n, "n_epochs": w.n_epochs, "n_durations": int(w.durations.size),
+           "n_periods": int(w.periods.size), "valid_cells": n_valid, "precision": args.precision,
+           "mode": args.mode}
+    extra = {"best_period_days": float(w.periods[best]) if best >= 0 else None,
+             "injected_period_days": w.injection["period"] if w.injection else None}
+    return elapsed, n_valid, 1, timings, dll_err, cfg, extra, w
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="tess-sector", choices=["tess-sector", "plain-1440"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refine"])
+    ap.add_argument("--workload", default="tess-sector", choices=["tess-sector", "plain-1440", "batch-64"])
+    ap.add_argument("--precision", default="fp32_refine", choices=["fp64", "fp32_refine"])
+    ap.add_argument("--mode", default="eager", choices=["eager", "graph", "loop"])
+    ap.add_argument("--autotune", action="store_true", help="tune the tile policy before warming up")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -102,101 +274,47 @@ def main(argv=None):
               "communication but multi-GPU runs are not part of this build", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     from paper_2402_06835_amd import _lib, api
 
     _lib.lib()
     assert torch.cuda.is_available(), "bench needs a GPU"
-    dev = torch.device("cuda", 0)
-    log(f"workload {args.workload}: generating")
-    w = workload(args.workload)
-    dev_in = {
-        "t": torch.as_tensor(w.t, device=dev), "f": torch.as_tensor(w.f, device=dev),
-        "A": torch.as_tensor(w.A, device=dev), "lattice": torch.as_tensor(w.lattice, device=dev),
-        "periods": torch.as_tensor(w.periods, device=dev),
-    }
+    log(f"workload {args.workload}, precision {args.precision}, mode {args.mode}")
     ctx = api.Context(0)
-    fac = None
-    for i in range(max(args.warmup, 1)):
-        fac, _, _ = run_step(api, ctx, dev_in, w, args.precision, fac)
-        torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{args.warmup} done")
-    ctx.enable_timing(True)
-    ctx.reset_timing()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    keep = None
-    for i in range(args.steps):
-        # one curve per step; the factor's device buffers are reused across curves of one length
-        keep = run_step(api, ctx, dev_in, w, args.precision, fac)
-        log(f"step {i + 1}/{args.steps} enqueued")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    timings = ctx.timings()
-    ctx.enable_timing(False)
-    fac, ls, ps = keep
-    n_valid = int(ls["valid"].sum().item())
-    best = int(ps["best_index"].item())
-    ms_step = elapsed / args.steps * 1e3
-    fits_per_s = n_valid * args.steps / elapsed
-    curves_per_s = args.steps / elapsed
-
-    # kernels by accumulated time; the grouped FP64 GEMM is one kernel whose
-    # launches are recorded per role (panel, next column, trailing, inverse)
-    merged = {}
-    for k, v in timings.items():
-        base = k.split(":")[0]
-        m = merged.setdefault(base, {"launches": 0, "ms": 0.0, "work": 0.0})
-        for f in m:
-            m[f] += v[f]
-    dom = max(merged.items(), key=lambda kv: kv[1]["ms"])
-    name, tk = dom
-    roof = None
-    if name.startswith("gemm_"):
-        achieved = tk["work"] / (tk["ms"] * 1e-3) / 1e12
-        roof = {"kernel": name, "bound": "mfma", "achieved": achieved, "peak": PEAKS[name],
-                "unit": "TFLOP/s", "frac": achieved / PEAKS[name], "traffic": None,
-                "launches": tk["launches"], "avg_launch_ms": tk["ms"] / tk["launches"],
-                "work_per_launch": tk["work"] / tk["launches"], "work_unit": "flop (algorithmic)"}
+    tuning = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuning = ctx.autotune(18000 if args.workload != "plain-1440" else 1440, args.precision)
+        log(f"autotuned in {time.perf_counter() - t0:.1f} s: {tuning}")
+    w = None
+    if args.workload == "batch-64":
+        if args.mode == "graph":
+            raise SystemExit("the batch runs through its own entry point (--mode eager, or loop)")
+        elapsed, n_valid, curves, timings, dll_err, cfg, extra = bench_batch(args, api, ctx, torch)
     else:
-        achieved = tk["work"] / (tk["ms"] * 1e-3) / 1e9
-        roof = {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
-                "frac": achieved / PEAKS["hbm_gbs"], "traffic": None, "launches": tk["launches"],
-                "avg_launch_ms": tk["ms"] / tk["launches"], "work_per_launch": tk["work"] / tk["launches"],
-                "work_unit": "byte (algorithmic)"}
+        if args.mode == "loop":
+            raise SystemExit("--mode loop compares against the batch (--workload batch-64)")
+        elapsed, n_valid, curves, timings, dll_err, cfg, extra, w = bench_curve(args, api, ctx, torch)
+    roof, gemms = (roofline_of(timings) if timings else (None, None))
     kernels = {k: {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps} for k, v in timings.items()}
-    gemms = {k: {"tflops": v["work"] / (v["ms"] * 1e-3) / 1e12, "ms_per_step": v["ms"] / args.steps}
-             for k, v in merged.items() if k.startswith("gemm_")}
-    dll_err = None
-    if args.precision != "fp64":
-        # accuracy of this precision against the FP64 path on the same curve (outside the timed region)
-        ls64 = api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations)
-        v = ls64["valid"].bool()
-        ref = ls64["dll"][v]
-        err = (ls["dll"][v] - ref).abs() / ref.abs().clamp(min=1.0)
-        dll_err = {"max": float(err.max().item()), "p999": float(torch.quantile(err.float(), 0.999).item())}
-        log(f"dll error vs fp64: {dll_err}")
-    log(f"{args.steps} steps in {elapsed:.3f} s: {fits_per_s:.4g} fits/s, {curves_per_s:.4g} curves/s; "
-        f"best period {w.periods[best] if best >= 0 else None}")
     out = {
         "metric": "(t0,D) GLS fits/s and light curves/s at Δll err ≤1e-6 vs FP64",
-        "value": fits_per_s, "unit": "(t0,D) fits/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else args.precision, "data": "synthetic",
-        "config": {"workload": w.name, "n_samples": w.n, "n_epochs": w.n_epochs,
-                   "n_durations": int(w.durations.size), "n_periods": int(w.periods.size),
-                   "valid_cells": n_valid, "precision": args.precision},
-        "light_curves_per_s": curves_per_s,
+        "value": n_valid * args.steps / elapsed, "unit": "(t0,D) fits/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
+        "config": cfg,
+        "light_curves_per_s": curves * args.steps / elapsed,
         "dll_err_vs_fp64": dll_err,
-        "gemm_by_type": gemms,
+        "gemm_by_type": {k: {"tflops": v["tflops"], "ms_per_step": v["ms"] / args.steps} for k, v in gemms.items()}
+        if gemms else None,
         "roofline": roof,
         "kernels": kernels,
-        "best_period_days": float(w.periods[best]) if best >= 0 else None,
-        "injected_period_days": w.injection["period"] if w.injection else None,
+        "tuning": tuning,
     }
-    if not args.no_cpu_baseline:
+    out.update(extra)
+    if not args.no_cpu_baseline and w is not None:
         out["cpu_baseline"] = cpu_baseline(w, n_valid)
         out["cpu_baseline"]["unit"] = out["unit"]
     print(json.dumps(out), flush=True)

@@ -262,16 +262,11 @@ def _trend_colmajor(A, n, dev):
     return int(A_t.shape[1]), A_t.to(device=dev, dtype=torch.float64).t().contiguous()
 
 
-def search_batch(ctx: Context, curves, durations, periods, precision: str = "fp32_refine", sign: int = 1,
-                 memory_budget: int = 0, raise_not_pd: bool = True) -> dict:
-    """Linear + periodic search of a batch of light curves of uneven length.
+def prepare_batch(ctx: Context, curves) -> dict:
+    """Concatenate a batch of light curves into device arrays (done once, outside any timing).
 
     curves: list of dicts with t, f, A (N x m1 or None; the same m1 for all),
-    lattice (int64 slots, starting at 0), n_epochs, theta (SHO) and dt.
-    Returns the concatenated device outputs and, per curve, views:
-    ``cells[c]`` (depth, var, dll, valid shaped (n_d, n_epochs_c)) and
-    ``periods[c]`` (the per-period arrays), plus host ``logdet``,
-    ``fail_pivot`` and the device ``best_index`` (one per curve).
+    lattice (int64 slots, starting at 0), n_epochs, theta (SHO or dict) and dt.
     """
     dev = ctx.device
     nc = len(curves)
@@ -292,13 +287,32 @@ def search_batch(ctx: Context, curves, durations, periods, precision: str = "fp3
     if len(m1s) != 1:
         raise ValueError("every curve needs the same number of trend columns")
     m1 = m1s.pop()
-    t = _dev_tensor(np.concatenate([np.asarray(c["t"], dtype=np.float64) for c in curves]), torch.float64, dev)
-    f = _dev_tensor(np.concatenate([np.asarray(c["f"], dtype=np.float64) for c in curves]), torch.float64, dev)
-    lat = _dev_tensor(np.concatenate([np.asarray(c["lattice"], dtype=np.int64) for c in curves]), torch.int64, dev)
-    A = torch.cat([a.reshape(-1) for a in cols]).to(dev) if m1 > 0 else None
-    thetas = (NuSho * nc)(*[(c["theta"] if isinstance(c["theta"], SHO) else SHO.from_dict(c["theta"])).c()
-                            for c in curves])
-    dts = np.ascontiguousarray([float(c["dt"]) for c in curves], dtype=np.float64)
+    return {
+        "n_curves": nc, "n_epochs": nes, "sample_off": soff, "epoch_off": eoff, "m1": m1,
+        "t": _dev_tensor(np.concatenate([np.asarray(c["t"], dtype=np.float64) for c in curves]), torch.float64, dev),
+        "f": _dev_tensor(np.concatenate([np.asarray(c["f"], dtype=np.float64) for c in curves]), torch.float64, dev),
+        "lattice": _dev_tensor(np.concatenate([np.asarray(c["lattice"], dtype=np.int64) for c in curves]),
+                               torch.int64, dev),
+        "A": torch.cat([a.reshape(-1) for a in cols]).to(dev) if m1 > 0 else None,
+        "theta": (NuSho * nc)(*[(c["theta"] if isinstance(c["theta"], SHO) else SHO.from_dict(c["theta"])).c()
+                                for c in curves]),
+        "dt": np.ascontiguousarray([float(c["dt"]) for c in curves], dtype=np.float64),
+    }
+
+
+def search_batch(ctx: Context, curves, durations, periods, precision: str = "fp32_refine", sign: int = 1,
+                 memory_budget: int = 0, raise_not_pd: bool = True) -> dict:
+    """Linear + periodic search of a batch of light curves of uneven length (entry point 4).
+
+    curves: a list of curve dicts (see ``prepare_batch``) or a prepared batch.
+    Returns the concatenated device outputs and, per curve, views:
+    ``cells[c]`` (depth, var, dll, valid shaped (n_d, n_epochs_c)) and
+    ``periods[c]`` (the per-period arrays), plus host ``logdet``,
+    ``fail_pivot`` and the device ``best_index`` (one per curve).
+    """
+    dev = ctx.device
+    b = curves if isinstance(curves, dict) else prepare_batch(ctx, curves)
+    nc, nes, soff, eoff = b["n_curves"], b["n_epochs"], b["sample_off"], b["epoch_off"]
     durs = np.ascontiguousarray(np.asarray(durations, dtype=np.int32))
     n_d = int(durs.size)
     per = _dev_tensor(periods, torch.float64, dev)
@@ -316,10 +330,11 @@ def search_batch(ctx: Context, curves, durations, periods, precision: str = "fp3
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
     P64 = ctypes.POINTER(ctypes.c_int64)
+    A = b["A"]
     st = lib().nu_search_batch(
-        ctx.ptr, nc, soff.ctypes.data_as(P64), eoff.ctypes.data_as(P64), ctypes.c_void_p(t.data_ptr()),
-        ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(A.data_ptr() if A is not None else 0), m1,
-        ctypes.c_void_p(lat.data_ptr()), thetas, dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        ctx.ptr, nc, soff.ctypes.data_as(P64), eoff.ctypes.data_as(P64), ctypes.c_void_p(b["t"].data_ptr()),
+        ctypes.c_void_p(b["f"].data_ptr()), ctypes.c_void_p(A.data_ptr() if A is not None else 0), b["m1"],
+        ctypes.c_void_p(b["lattice"].data_ptr()), b["theta"], b["dt"].ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
         durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d, ctypes.c_void_p(per.data_ptr()), n_p,
         PRECISIONS[precision], int(sign), int(memory_budget),
         *[ctypes.c_void_p(out[k].data_ptr()) for k in ("depth", "var", "dll", "valid", "null")],
@@ -333,7 +348,7 @@ def search_batch(ctx: Context, curves, durations, periods, precision: str = "fp3
     out["cells"] = [{k: out[k][n_d * int(eoff[c]):n_d * int(eoff[c + 1])].view(n_d, nes[c])
                      for k in ("depth", "var", "dll", "valid")} for c in range(nc)]
     out["periods"] = [{k: out[k][c] for k in _PERIOD_KEYS} for c in range(nc)]
-    out["_keep"] = (t, f, lat, A, per)
+    out["_keep"] = (b, per)
     return out
 
 

@@ -15,9 +15,9 @@ namespace nu {
 
 namespace {
 
-int tiles_of(const GemmProblem& g, int tile) {
-  const int tm = g.M / tile, tn = g.N / tile;
-  return (g.flags & G_C_LOWER_TILES) ? tm * (tm + 1) / 2 : tm * tn;
+int tiles_of(const GemmProblem& g, int tm, int tn) {
+  const int rm = g.M / tm, rn = g.N / tn;
+  return (g.flags & G_C_LOWER_TILES) ? rm * (rm + 1) / 2 : rm * rn;
 }
 
 // useful flops of a problem (zeros of triangular operands not counted)
@@ -32,20 +32,28 @@ double useful_flops(const GemmProblem& g) {
 
 // Append one launch's problems, numbering tiles from 0 within the launch. A
 // launch with fewer 128 x 128 tiles than small_below uses 64 x 64 tiles (four
-// times the workgroups, each a quarter of the work).
+// times the workgroups, each a quarter of the work), or 64 x 128 tiles when
+// its problems write C over A (N = 128 there: each tile keeps whole rows).
 Range add_launch(std::vector<GemmProblem>& sched, std::vector<GemmProblem> probs, int small_below) {
   Range r;
   if (probs.empty()) return r;
   r.first = (int)sched.size();
   r.count = (int)probs.size();
   int big = 0;
-  for (auto& p : probs) big += tiles_of(p, TB);
-  r.tile = big < small_below ? 64 : TB;
+  bool inplace = false;
+  for (auto& p : probs) {
+    big += tiles_of(p, TB, TB);
+    inplace = inplace || (p.flags & G_C_IS_A);
+  }
+  if (big < small_below) {
+    r.tile_m = 64;
+    r.tile_n = inplace ? TB : 64;
+  }
   int t = 0;
   for (auto& p : probs) {
-    p.tiles_n = p.N / r.tile;
+    p.tiles_n = p.N / r.tile_n;
     p.tile_begin = t;
-    p.tile_count = tiles_of(p, r.tile);
+    p.tile_count = tiles_of(p, r.tile_m, r.tile_n);
     t += p.tile_count;
     r.flops += useful_flops(p);
     sched.push_back(p);
@@ -135,7 +143,7 @@ void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P)
       if (rest > 0) {
         void* col = at(F->L, off + TB, off, np, es);  // rows below the diagonal block, block column k
         const void* xkk = at(F->X, off, off, np, es);
-        pan.push_back(prob(col, np, xkk, np, col, np, rest, TB, TB, G_BT, 1.0, 0.0));
+        pan.push_back(prob(col, np, xkk, np, col, np, rest, TB, TB, G_BT | G_C_IS_A, 1.0, 0.0));
         const int inner = (p0 + pw - k - 1) * TB;  // columns of this panel right of block k
         if (inner > 0)
           pup.push_back(prob(col, np, col, np, at(col, 0, TB, np, es), np, rest, inner, TB, G_BT, -1.0, 1.0));
@@ -340,7 +348,8 @@ void factor_free(nu_factor* F) {
 nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int f32) {
   if (r.tiles == 0) return NU_OK;
   Timed tm(ctx, name, r.flops);
-  return check_hip(ctx, launch_gemm(ctx->stream, P.dprobs + r.first, r.count, r.tiles, f32, r.tile), name);
+  return check_hip(ctx, launch_gemm(ctx->stream, P.dprobs + r.first, r.count, r.tiles, f32, r.tile_m, r.tile_n),
+                   name);
 }
 
 nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P,

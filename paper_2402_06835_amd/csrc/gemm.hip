@@ -2,11 +2,16 @@
 // FP32 (v_mfma_f32_16x16x4_f32).
 //
 // One launch runs a list of problems C = alpha * op(A) op(B) + beta * C; each
-// workgroup owns one 128 x 128 (or, for launches with few tiles, 64 x 64)
-// output tile of one problem. 256 threads = 4 waves in a 2 x 2 arrangement,
-// each wave a 64 x 64 (32 x 32) sub-tile held as 4 x 4 (2 x 2) MFMA
-// accumulators of 16 x 16. The k loop stages 16-deep slices of A and op(B)
-// through LDS (k-major, double buffered; one barrier per slice).
+// workgroup owns one 128 x 128 output tile of one problem (or, for launches
+// with few tiles, 64 x 64, or 64 x 128 where C aliases A). 256 threads = 4
+// waves in a 2 x 2 arrangement, each wave a quarter of the tile held as 16 x 16
+// MFMA accumulators. The k loop stages 16-deep slices of A and op(B) through
+// LDS (k-major, double buffered; one barrier per slice).
+//
+// A problem may write C over its own A (the Cholesky panel, times the inverse
+// of the diagonal block) only if every tile spans all N columns: a tile reads
+// whole rows of A, and another tile of the same rows must not overwrite them
+// while it does.
 //
 // This is the dense contraction of the factorisation: the trailing updates
 // and panels of the blocked Cholesky, and both products of every level of the
@@ -104,14 +109,14 @@ __device__ __forceinline__ void loadE(const T* p, T (&r)[E]) {
   }
 }
 
-// BM x BM output tile per workgroup (BM = 128 or 64), 4 waves in a 2 x 2
-// arrangement of (BM/2) x (BM/2) sub-tiles.
-template <typename T, int BM>
+// BM x BN output tile per workgroup ((128, 128), (64, 64) or (64, 128)),
+// 4 waves in a 2 x 2 arrangement of (BM/2) x (BN/2) sub-tiles.
+template <typename T, int BM, int BN>
 __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restrict__ probs, int nprob) {
-  constexpr int BN = BM;
-  constexpr int E = BM * GBK / 256;  // elements per thread per operand slice
-  constexpr int WT = BM / 2;         // wave sub-tile edge
-  constexpr int NB = WT / 16;        // MFMA blocks per wave sub-tile edge
+  constexpr int EA = BM * GBK / 256;  // elements per thread of an A slice
+  constexpr int EB = BN * GBK / 256;  // elements per thread of a B slice
+  constexpr int NBM = BM / 32;        // MFMA blocks per wave sub-tile, rows
+  constexpr int NBN = BN / 32;        // and columns
   __shared__ T As[2][GBK][BM + LPAD];
   __shared__ T Bs[2][GBK][BN + LPAD];
   typedef typename Mfma<T>::acc_t acc_t;
@@ -138,41 +143,42 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * WT, wn = (wave & 1) * WT;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
   const int lr = lane & 15, lk = lane >> 4;
 
   // global -> register staging: "row-major M x K -> [k][m]" pattern for A (and B^T)
-  const int ar = tid / (GBK / E), akh = (tid % (GBK / E)) * E;
+  const int ar = tid / (GBK / EA), akh = (tid % (GBK / EA)) * EA;
+  const int br = tid / (GBK / EB), bkh = (tid % (GBK / EB)) * EB;
   // "row-major K x N -> [k][n]" pattern for B
-  const int bk = tid / (BN / E), bnc = (tid % (BN / E)) * E;
+  const int bk = tid / (BN / EB), bnc = (tid % (BN / EB)) * EB;
 
   const T* A = static_cast<const T*>(P.A);
   const T* B = static_cast<const T*>(P.B);
   const T* Ap = A + (int64_t)(m0 + ar) * P.lda + akh;
-  const T* Bp = bt ? B + (int64_t)(n0 + ar) * P.ldb + akh : B + (int64_t)bk * P.ldb + n0 + bnc;
+  const T* Bp = bt ? B + (int64_t)(n0 + br) * P.ldb + bkh : B + (int64_t)bk * P.ldb + n0 + bnc;
 
-  T ra[E], rb[E];
+  T ra[EA], rb[EB];
   auto gload = [&](int k0) {
-    loadE<T, E>(Ap + k0, ra);
-    loadE<T, E>(bt ? Bp + k0 : Bp + (int64_t)k0 * P.ldb, rb);
+    loadE<T, EA>(Ap + k0, ra);
+    loadE<T, EB>(bt ? Bp + k0 : Bp + (int64_t)k0 * P.ldb, rb);
   };
   auto lstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) As[buf][akh + i][ar] = ra[i];
+    for (int i = 0; i < EA; ++i) As[buf][akh + i][ar] = ra[i];
     if (bt) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) Bs[buf][akh + i][ar] = rb[i];
+      for (int i = 0; i < EB; ++i) Bs[buf][bkh + i][br] = rb[i];
     } else {
 #pragma unroll
-      for (int i = 0; i < E; ++i) Bs[buf][bk][bnc + i] = rb[i];
+      for (int i = 0; i < EB; ++i) Bs[buf][bk][bnc + i] = rb[i];
     }
   };
 
-  acc_t acc[NB][NB];
+  acc_t acc[NBM][NBN];
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
+  for (int i = 0; i < NBM; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    for (int j = 0; j < NBN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   if (nk > 0) {
     gload(kb);
@@ -183,15 +189,15 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
       if (it + 1 < nk) gload(kb + (it + 1) * GBK);
 #pragma unroll
       for (int kk = 0; kk < GBK / 4; ++kk) {
-        T a[NB], b[NB];
+        T a[NBM], b[NBN];
 #pragma unroll
-        for (int mi = 0; mi < NB; ++mi) a[mi] = As[buf][kk * 4 + lk][wm + mi * 16 + lr];
+        for (int mi = 0; mi < NBM; ++mi) a[mi] = As[buf][kk * 4 + lk][wm + mi * 16 + lr];
 #pragma unroll
-        for (int ni = 0; ni < NB; ++ni) b[ni] = Bs[buf][kk * 4 + lk][wn + ni * 16 + lr];
+        for (int ni = 0; ni < NBN; ++ni) b[ni] = Bs[buf][kk * 4 + lk][wn + ni * 16 + lr];
 #pragma unroll
-        for (int mi = 0; mi < NB; ++mi)
+        for (int mi = 0; mi < NBM; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < NB; ++ni) acc[mi][ni] = Mfma<T>::op(a[mi], b[ni], acc[mi][ni]);
+          for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = Mfma<T>::op(a[mi], b[ni], acc[mi][ni]);
       }
       if (it + 1 < nk) lstore(buf ^ 1);
       __syncthreads();
@@ -201,9 +207,9 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
   const T alpha = (T)P.alpha, beta = (T)P.beta;
   T* C = static_cast<T*>(P.C);
 #pragma unroll
-  for (int mi = 0; mi < NB; ++mi)
+  for (int mi = 0; mi < NBM; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < NB; ++ni)
+    for (int ni = 0; ni < NBN; ++ni)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = m0 + wm + mi * 16 + Mfma<T>::row(lk, i);
@@ -215,16 +221,22 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
       }
 }
 
-hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32, int tile) {
+template <typename T>
+void launch_typed(hipStream_t s, const GemmProblem* dprobs, int nprob, dim3 g, int tm, int tn) {
+  const dim3 b(256);
+  if (tm == 64 && tn == 64) hipLaunchKernelGGL((gemm_kernel<T, 64, 64>), g, b, 0, s, dprobs, nprob);
+  else if (tm == 64) hipLaunchKernelGGL((gemm_kernel<T, 64, 128>), g, b, 0, s, dprobs, nprob);
+  else hipLaunchKernelGGL((gemm_kernel<T, 128, 128>), g, b, 0, s, dprobs, nprob);
+}
+
+hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32, int tile_m,
+                       int tile_n) {
   if (total_tiles <= 0) return hipSuccess;
-  const dim3 g((unsigned)total_tiles), b(256);
-  if (f32) {
-    if (tile == 64) hipLaunchKernelGGL((gemm_kernel<float, 64>), g, b, 0, s, dprobs, nprob);
-    else hipLaunchKernelGGL((gemm_kernel<float, 128>), g, b, 0, s, dprobs, nprob);
-  } else {
-    if (tile == 64) hipLaunchKernelGGL((gemm_kernel<double, 64>), g, b, 0, s, dprobs, nprob);
-    else hipLaunchKernelGGL((gemm_kernel<double, 128>), g, b, 0, s, dprobs, nprob);
-  }
+  if (!((tile_m == 128 && tile_n == 128) || (tile_m == 64 && (tile_n == 64 || tile_n == 128))))
+    return hipErrorInvalidValue;
+  const dim3 g((unsigned)total_tiles);
+  if (f32) launch_typed<float>(s, dprobs, nprob, g, tile_m, tile_n);
+  else launch_typed<double>(s, dprobs, nprob, g, tile_m, tile_n);
   return hipGetLastError();
 }
 

@@ -33,7 +33,8 @@ enum GemmFlags : int {
   G_A_LOWER = 2,        // A lower triangular: k < m0 + TB
   G_B_LOWER = 4,        // op(B) lower triangular: k >= n0
   G_B_UPPER = 8,        // op(B) upper triangular: k < n0 + TB
-  G_C_LOWER_TILES = 16  // only tiles with row block >= column block
+  G_C_LOWER_TILES = 16,  // only tiles with row block >= column block (square tiles)
+  G_C_IS_A = 32          // C overwrites A's rows: every tile must span all N columns
 };
 
 struct GemmProblem {
@@ -102,7 +103,7 @@ namespace nu {
 // one grouped launch: problems [first, first + count) of a schedule
 struct Range {
   int first = 0, count = 0, tiles = 0;
-  int tile = TB;  // output tile edge of the launch (128 or 64)
+  int tile_m = TB, tile_n = TB;  // output tile of the launch: 128 x 128, 64 x 64 or 64 x 128
   double flops = 0.0;
 };
 constexpr int BAND_W = 2;  // block diagonals refined after a reduced-precision inverse
@@ -219,7 +220,8 @@ nu_status validate_theta(nu_ctx* ctx, const nu_sho* theta);
 
 // launchers (*.hip)
 hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho* th_dev, double* K);
-hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32, int tile);
+hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32, int tile_m,
+                       int tile_n);
 hipError_t launch_potrf_diag(hipStream_t s, const PotrfJob* jobs, int njobs);
 hipError_t launch_copy_i64(hipStream_t s, const int64_t* src, int64_t* dst);
 hipError_t launch_fill_invalid_cells(hipStream_t s, int64_t count, double* depth, double* var, double* dll,

@@ -239,3 +239,23 @@ def test_autotune_keeps_results(api, ctx):
     after = _single(api, c, w, "fp32_refine")
     _assert_same(before, after, "autotuned")
     c.close()
+
+
+def test_batch_many_curves_under_load(api, ctx):
+    """Regression: a loaded batch (many merged tiles per launch, late steps with few curves left) gives
+    every curve exactly its single-curve result; an in-place panel product split across tiles of the
+    same rows once made this fail at random."""
+    import torch
+    rng = np.random.default_rng(77)
+    ns = [int(n) for n in rng.integers(2500, 6000, size=16)]
+    ws = [_curve(n, 100 + i, float(rng.uniform(0.3, 2.0))) for i, n in enumerate(ns)]
+    say(f"loaded batch of {len(ws)} curves, N={ns}, fp64, small budget (several waves)")
+    budget = 3 * (6000 + 128) ** 2 * 8 * 3
+    res = api.search_batch(ctx, [_as_batch_input(w) for w in ws], DURS, PERIODS, precision="fp64",
+                           memory_budget=budget)
+    torch.cuda.synchronize()
+    assert np.all(res["fail_pivot"] == -1)
+    for c, w in enumerate(ws):
+        single = _single(api, ctx, w, "fp64")
+        np.testing.assert_array_equal(res["cells"][c]["dll"].cpu().numpy(), single["dll"], err_msg=f"curve {c}")
+        assert res["logdet"][c] == single["logdet"]
