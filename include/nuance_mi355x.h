@@ -83,6 +83,9 @@ typedef struct nu_factor nu_factor;
 nu_status nu_ctx_create(int device, void* stream, nu_ctx** out);
 void nu_ctx_destroy(nu_ctx* ctx);
 nu_status nu_ctx_set_stream(nu_ctx* ctx, void* stream);
+/* Frees the device memory the context keeps between calls: the search
+ * workspace and the arena of the batch factors (4). Synchronises the stream. */
+nu_status nu_ctx_release_memory(nu_ctx* ctx);
 const char* nu_ctx_last_error(const nu_ctx* ctx);
 
 /* Kernel timing with HIP events recorded on the context's stream around
@@ -173,9 +176,12 @@ nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var
  * may be NULL). logdet_host and fail_pivot_host (host, one per curve, may be
  * NULL): ln|K| and -1 or the failing pivot.
  * The curves are processed longest first in waves whose factors fit in
- * memory_budget_bytes of device memory (0: 90 % of the free memory); each
- * dense stage of a wave is one launch over all its curves. The call
- * synchronises the stream once per wave. A curve whose covariance is not
+ * memory_budget_bytes of device memory (0: 90 % of the free memory counting
+ * the arena the context already holds as free); each dense stage of a wave is one launch
+ * over all its curves. The factors live in a device arena of the size of the
+ * largest wave, which the context keeps for later calls (released by
+ * nu_ctx_release_memory or nu_ctx_destroy). The call synchronises the stream
+ * once per wave and once before it returns. A curve whose covariance is not
  * positive definite gets invalid cells and no event at any period; the call
  * then finishes the other curves and returns NU_ERR_NOT_PD. A single curve
  * larger than the budget gives NU_ERR_OOM before any work. */

@@ -79,6 +79,10 @@ class Context:
         except Exception:
             pass
 
+    def release_memory(self):
+        """Free the device memory the context keeps between calls (workspace, batch arena)."""
+        _check(self.ptr, lib().nu_ctx_release_memory(self.ptr))
+
     def enable_timing(self, on: bool = True):
         _check(self.ptr, lib().nu_ctx_enable_timing(self.ptr, int(on)))
 

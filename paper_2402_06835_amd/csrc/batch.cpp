@@ -2,7 +2,9 @@
 // whole single-curve search, and the tile autotuner.
 //
 // Batch: the curves are ordered by length (longest first) and cut into waves
-// whose factors fit the device-memory budget. Within a wave every dense stage
+// whose factors fit the device-memory budget; the factors of a wave are carved
+// from one device arena that the context keeps for later calls (allocating
+// and freeing hundreds of GB per call costs seconds). Within a wave every dense stage
 // is one launch for all curves: the diagonal blocks of Cholesky step k are
 // one launch of one workgroup per curve that has a block k, and the panel,
 // panel-update, trailing and inverse-level products of all curves form the
@@ -87,12 +89,13 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
   double* ws = (double*)ctx_workspace(ctx, ws_need, &st);
   if (!ws) return st;
 
+  // the budget counts the arena this context already holds as available
   size_t budget = memory_budget_bytes;
   if (budget == 0) {
     size_t free_b = 0, total_b = 0;
     st = check_hip(ctx, hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
     if (st != NU_OK) return st;
-    budget = free_b / 10 * 9;
+    budget = (free_b + ctx->arena_bytes) / 10 * 9;
   }
 
   // longest curves first, cut into waves that fit the budget
@@ -115,25 +118,45 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
     waves.back().push_back(c);
     used += need;
   }
+  size_t arena_need = 0;
+  for (const auto& wave : waves) {
+    size_t b = 0;
+    for (int c : wave) b += factor_bytes(sample_off_host[c + 1] - sample_off_host[c], mixed);
+    arena_need = std::max(arena_need, b);
+  }
+  char* arena = nullptr;
+  {
+    HostTimed ht(ctx, "batch_arena");
+    arena = (char*)ctx_arena(ctx, arena_need, &st);
+  }
+  if (!arena) return st;
 
   int n_failed = 0;
   int first_failed = -1;
   for (const auto& wave : waves) {
     std::vector<nu_factor*> Fs;
-    for (int c : wave) {
-      nu_factor* F = nullptr;
-      st = factor_alloc(ctx, sample_off_host[c + 1] - sample_off_host[c], false, &F);
-      if (st != NU_OK) return fail_batch(ctx, Fs, nullptr, nullptr, st);
-      Fs.push_back(F);
-      F->theta_host = theta_host[c];
-      st = check_hip(ctx, hipMemcpyAsync(F->theta_dev(), &F->theta_host, sizeof(nu_sho), hipMemcpyHostToDevice,
-                                         ctx->stream),
-                     "upload theta");
-      if (st != NU_OK) return fail_batch(ctx, Fs, nullptr, nullptr, st);
+    {
+      HostTimed ht(ctx, "batch_place");
+      char* cursor = arena;
+      for (int c : wave) {
+        nu_factor* F = nullptr;
+        st = factor_place(ctx, sample_off_host[c + 1] - sample_off_host[c], mixed, &cursor, &F);
+        if (st != NU_OK) break;
+        Fs.push_back(F);
+        F->theta_host = theta_host[c];
+        st = check_hip(ctx, hipMemcpyAsync(F->theta_dev(), &F->theta_host, sizeof(nu_sho), hipMemcpyHostToDevice,
+                                           ctx->stream),
+                       "upload theta");
+        if (st != NU_OK) break;
+      }
     }
+    if (st != NU_OK) return fail_batch(ctx, Fs, nullptr, nullptr, st);
     Plan P, Q;
-    plan_cholesky(Fs, ctx->tuning, P);
-    st = plan_upload(ctx, P);
+    {
+      HostTimed ht(ctx, "batch_plan");
+      plan_cholesky(Fs, ctx->tuning, P);
+      st = plan_upload(ctx, P);
+    }
     std::vector<const double*> ts;
     std::vector<const nu_sho*> th;
     for (size_t i = 0; i < wave.size(); ++i) {
@@ -142,7 +165,10 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
     }
     if (st == NU_OK) st = run_factor(ctx, Fs, P, ts, th);
     std::vector<int64_t> status;
-    if (st == NU_OK) st = read_factor_status(ctx, Fs, status);
+    if (st == NU_OK) {
+      HostTimed ht(ctx, "batch_factor_wait");
+      st = read_factor_status(ctx, Fs, status);
+    }
     if (st != NU_OK) return fail_batch(ctx, Fs, &P, &Q, st);
 
     std::vector<nu_factor*> ok;
@@ -158,9 +184,8 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
       }
     }
     if (!ok.empty()) {
+      HostTimed ht(ctx, "batch_inverse_setup");
       if (mixed) {
-        for (nu_factor* F : ok)
-          if (st == NU_OK) st = alloc_mixed(ctx, F);
         if (st == NU_OK) {
           plan_inverse(ok, true, ctx->tuning, Q);
           plan_band(ok, ctx->tuning, Q);
@@ -202,7 +227,11 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
                           periods, n_p, log_term_sign, qs, bp, bd, bdep, bsig, blnp, bpi, ws);
     }
     // the factors go before the next wave is allocated
-    nu_status st2 = fail_batch(ctx, Fs, &P, &Q, st);
+    nu_status st2;
+    {
+      HostTimed ht(ctx, "batch_wait_free");
+      st2 = fail_batch(ctx, Fs, &P, &Q, st);
+    }
     if (st2 != NU_OK) return st2;
   }
   if (n_failed > 0)

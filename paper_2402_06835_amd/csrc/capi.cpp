@@ -2,6 +2,7 @@
 // validation, context and factor objects, kernel timing. The schedules and
 // enqueue sequences live in the engine. No exception crosses the boundary.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -41,6 +42,23 @@ void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st) {
   return ctx->ws;
 }
 
+void* ctx_arena(nu_ctx* ctx, size_t bytes, nu_status* st) {
+  *st = NU_OK;
+  if (bytes <= ctx->arena_bytes) return ctx->arena;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess && ctx->arena) e = hipFree(ctx->arena);
+  ctx->arena = nullptr;
+  ctx->arena_bytes = 0;
+  if (e == hipSuccess) e = hipMalloc(&ctx->arena, bytes);
+  if (e != hipSuccess) {
+    *st = check_hip(ctx, e, "arena allocation");
+    ctx->arena = nullptr;
+    return nullptr;
+  }
+  ctx->arena_bytes = bytes;
+  return ctx->arena;
+}
+
 void timing_begin(nu_ctx* ctx, hipStream_t s, hipEvent_t* start) {
   *start = nullptr;
   if (!ctx->timing) return;
@@ -65,6 +83,24 @@ void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, 
   }
   hipEventRecord(stop, s);
   ctx->pending.push_back({name, start, stop, work});
+}
+
+static double wall_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+HostTimed::HostTimed(nu_ctx* c, const char* n) : ctx(c), name(n), t0(c->timing ? wall_ms() : 0.0) {}
+
+HostTimed::~HostTimed() {
+  if (!ctx->timing) return;
+  const std::string key = std::string("host:") + name;
+  auto it = ctx->timings.find(key);
+  if (it == ctx->timings.end()) {
+    ctx->timing_names.push_back(key);
+    it = ctx->timings.emplace(key, nu_timing_slot{}).first;
+  }
+  it->second.launches += 1;
+  it->second.ms += wall_ms() - t0;
 }
 
 void resolve_timing(nu_ctx* ctx) {
@@ -149,12 +185,25 @@ void nu_ctx_destroy(nu_ctx* ctx) {
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
   if (ctx->ws) hipFree(ctx->ws);
+  if (ctx->arena) hipFree(ctx->arena);
   for (auto& p : ctx->pending) {
     hipEventDestroy(p.start);
     hipEventDestroy(p.stop);
   }
   for (auto e : ctx->free_events) hipEventDestroy(e);
   delete ctx;
+}
+
+nu_status nu_ctx_release_memory(nu_ctx* ctx) {
+  if (!ctx) return NU_ERR_ARG;
+  nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st == NU_OK) st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "release sync");
+  if (st != NU_OK) return st;
+  if (ctx->ws) hipFree(ctx->ws);
+  if (ctx->arena) hipFree(ctx->arena);
+  ctx->ws = ctx->arena = nullptr;
+  ctx->ws_bytes = ctx->arena_bytes = 0;
+  return NU_OK;
 }
 
 nu_status nu_ctx_set_stream(nu_ctx* ctx, void* stream) {

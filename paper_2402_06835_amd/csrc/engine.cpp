@@ -266,25 +266,47 @@ void plan_release(Plan& P) {
 // ---------------------------------------------------------------------------
 // Factors
 
-size_t factor_bytes(int64_t n, bool mixed) {
+namespace {
+constexpr size_t ARENA_ALIGN = 256;
+size_t aligned(size_t b) { return (b + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN; }
+
+// device bytes of each buffer of a factor of n samples, in carving order
+std::vector<size_t> factor_buffer_bytes(int64_t n, bool mixed) {
   const int64_t np = round_up(n, TB);
   const int nblk = (int)(np / TB);
-  size_t b = 2 * (size_t)np * np * sizeof(double) + inverse_t_elems(nblk) * sizeof(double) +
-             (size_t)(nblk + FACTOR_SMALL_EXTRA) * sizeof(double) + sizeof(NullFit);
-  if (mixed) b += 2 * (size_t)np * np * sizeof(float) + 2 * (size_t)nblk * (BAND_W + 1) * TB * TB * sizeof(double);
+  std::vector<size_t> b = {(size_t)np * np * sizeof(double), (size_t)np * np * sizeof(double),
+                           inverse_t_elems(nblk) * sizeof(double),
+                           (size_t)(nblk + FACTOR_SMALL_EXTRA) * sizeof(double), sizeof(NullFit)};
+  if (mixed) {
+    const size_t band = (size_t)nblk * (BAND_W + 1) * TB * TB * sizeof(double);
+    b.insert(b.end(), {(size_t)np * np * sizeof(float), (size_t)np * np * sizeof(float), band, band});
+  }
   return b;
 }
 
-nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out) {
-  *out = nullptr;
+nu_factor* new_factor(nu_ctx* ctx, int64_t n) {
   nu_factor* F = new (std::nothrow) nu_factor();
-  if (!F) return set_error(ctx, NU_ERR_OOM, "factor: host allocation");
+  if (!F) return nullptr;
   F->device = ctx->device;
   F->n = n;
   F->np = round_up(n, TB);
   F->nblk = (int)(F->np / TB);
-  const int64_t np = F->np;
   F->t_elems = inverse_t_elems(F->nblk);
+  return F;
+}
+}  // namespace
+
+size_t factor_bytes(int64_t n, bool mixed) {
+  size_t s = 0;
+  for (size_t b : factor_buffer_bytes(n, mixed)) s += aligned(b);
+  return s;
+}
+
+nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out) {
+  *out = nullptr;
+  nu_factor* F = new_factor(ctx, n);
+  if (!F) return set_error(ctx, NU_ERR_OOM, "factor: host allocation");
+  const int64_t np = F->np;
   nu_status st = check_hip(ctx, hipMalloc(&F->L, (size_t)np * np * sizeof(double)), "alloc L");
   if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->X, (size_t)np * np * sizeof(double)), "alloc X");
   if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->T, F->t_elems * sizeof(double)), "alloc T");
@@ -301,6 +323,25 @@ nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out) {
   if (st != NU_OK) {
     factor_free(F);
     return st;
+  }
+  *out = F;
+  return NU_OK;
+}
+
+// A factor whose buffers (and, if mixed, its reduced-precision buffers) are
+// carved from caller-owned device memory at *cursor (factor_bytes(n, mixed)
+// bytes, 256-byte aligned); the factor does not free them.
+nu_status factor_place(nu_ctx* ctx, int64_t n, bool mixed, char** cursor, nu_factor** out) {
+  *out = nullptr;
+  nu_factor* F = new_factor(ctx, n);
+  if (!F) return set_error(ctx, NU_ERR_OOM, "factor: host allocation");
+  F->owns_memory = false;
+  const std::vector<size_t> sz = factor_buffer_bytes(n, mixed);
+  void** slots[] = {(void**)&F->L,  (void**)&F->X,   (void**)&F->T,     (void**)&F->small, (void**)&F->nullfit,
+                    (void**)&F->L32, (void**)&F->X32, (void**)&F->bandP, (void**)&F->bandX};
+  for (size_t i = 0; i < sz.size(); ++i) {
+    *slots[i] = *cursor;
+    *cursor += aligned(sz[i]);
   }
   *out = F;
   return NU_OK;
@@ -335,8 +376,9 @@ void factor_free(nu_factor* F) {
   hipSetDevice(F->device);
   hipDeviceSynchronize();
   void* bufs[] = {F->L, F->X, F->T, F->small, F->nullfit, F->L32, F->X32, F->bandP, F->bandX};
-  for (void* b : bufs)
-    if (b) hipFree(b);
+  if (F->owns_memory)
+    for (void* b : bufs)
+      if (b) hipFree(b);
   plan_release(F->plan64);
   plan_release(F->plan32);
   delete F;

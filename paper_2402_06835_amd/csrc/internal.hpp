@@ -86,9 +86,12 @@ struct nu_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
-  // growable device workspace
+  // growable device workspace of the searches
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // device arena of the batch factors, kept between calls
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
   // kernel timing
   bool timing = false;
   std::vector<nu_pending_event> pending;
@@ -159,6 +162,7 @@ struct nu_factor {
   nu::Plan plan32;           // FP32 inverse + FP64 band step
   int inverse_kind = 0;  // 0 none, 1 FP64, 2 FP32 levels + refinement
   double logdet = 0.0;
+  bool owns_memory = true;   // false: buffers carved from the context's arena
   double* parts() const { return small; }
   double* logdet_dev() const { return small + nblk; }
   int64_t* status_dev() const { return reinterpret_cast<int64_t*>(small + nblk + 1); }
@@ -186,6 +190,16 @@ struct Timed {
   ~Timed() { timing_end(ctx, ctx->stream, name, start, work); }
 };
 
+// Host wall time of a phase of a call (allocation, planning, waits, frees),
+// accumulated under "host:<name>" when timing is on.
+struct HostTimed {
+  nu_ctx* ctx;
+  const char* name;
+  double t0;
+  HostTimed(nu_ctx* c, const char* n);
+  ~HostTimed();
+};
+
 // engine (engine.cpp)
 void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P);
 void plan_inverse(const std::vector<nu_factor*>& Fs, bool f32, const Tuning& tu, Plan& P);
@@ -194,6 +208,8 @@ size_t inverse_t_elems(int nblk);
 nu_status plan_upload(nu_ctx* ctx, Plan& P);
 size_t factor_bytes(int64_t n, bool mixed);
 nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out);
+nu_status factor_place(nu_ctx* ctx, int64_t n, bool mixed, char** cursor, nu_factor** out);
+void* ctx_arena(nu_ctx* ctx, size_t bytes, nu_status* st);
 nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F);
 nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F);
 void factor_free(nu_factor* F);
