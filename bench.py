@@ -101,6 +101,8 @@ def roofline_of(timings):
     """Dominant kernel (by accumulated time) and its achieved rate against the MI355X peak."""
     merged = {}
     for k, v in timings.items():
+        if k.startswith("host:"):  # host-side phases, not kernels
+            continue
         base = k.split(":")[0]
         m = merged.setdefault(base, {"launches": 0, "ms": 0.0, "work": 0.0})
         for f in m:
@@ -120,6 +122,27 @@ def roofline_of(timings):
     gemms = {k: {"tflops": v["work"] / (v["ms"] * 1e-3) / 1e12, "ms": v["ms"]}
              for k, v in merged.items() if k.startswith("gemm_")}
     return roof, gemms
+
+
+# the kernel and the schedule of its launches
+TRAFFIC_SOURCES = ["paper_2402_06835_amd/csrc/gemm.hip", "paper_2402_06835_amd/csrc/engine.cpp"]
+
+
+def measured_traffic(roof, workload, precision):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, if it was taken on
+    this workload, precision and the current kernel sources (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{roof['kernel']}_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if rec.get("sources_sha256") != h.hexdigest():
+        log(f"traffic record {os.path.basename(path)} predates the current kernel sources: traffic = null")
+        return None
+    return rec["bytes_per_launch"]
 
 
 def dll_error(dll, dll_ref, valid_ref):
@@ -180,7 +203,7 @@ def bench_batch(args, api, ctx, torch):
                "precision": args.precision, "mode": "loop of single-curve calls"}
         return elapsed, n_valid, len(ws), timings, None, cfg, {}
     dll_err = None
-    if args.precision != "fp64":
+    if args.precision != "fp64" and not args.no_dll_check:
         ref = api.search_batch(ctx, batch, durs, per, precision="fp64")
         dll_err = dll_error(res["dll"], ref["dll"], ref["valid"])
         log(f"dll error vs fp64: {dll_err}")
@@ -243,7 +266,7 @@ def bench_curve(args, api, ctx, torch):
         fac = api.gp_factor(ctx, dev_in["t"], w.theta)
     n_valid = int(valid.sum().item())
     dll_err = None
-    if args.precision != "fp64":
+    if args.precision != "fp64" and not args.no_dll_check:
         # accuracy of this precision against the FP64 path on the same curve (outside the timed region)
         ls64 = api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations)
         dll_err = dll_error(dll, ls64["dll"], ls64["valid"])
@@ -268,6 +291,12 @@ def main(argv=None):
     ap.add_argument("--mode", default="eager", choices=["eager", "graph", "loop"])
     ap.add_argument("--autotune", action="store_true", help="tune the tile policy before warming up")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dll-check", action="store_true",
+                    help="skip the FP64 reference search that measures the dll error of a reduced precision "
+                         "(keeps a profiled run to the timed kernels)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the workload, one plain device copy of this many MiB (a kernel of known "
+                         "traffic, to scale hardware byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); curves shard across GPUs with no "
@@ -281,6 +310,15 @@ def main(argv=None):
     _lib.lib()
     assert torch.cuda.is_available(), "bench needs a GPU"
     log(f"workload {args.workload}, precision {args.precision}, mode {args.mode}")
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
     ctx = api.Context(0)
     tuning = None
     if args.autotune:
@@ -297,6 +335,8 @@ def main(argv=None):
             raise SystemExit("--mode loop compares against the batch (--workload batch-64)")
         elapsed, n_valid, curves, timings, dll_err, cfg, extra, w = bench_curve(args, api, ctx, torch)
     roof, gemms = (roofline_of(timings) if timings else (None, None))
+    if roof is not None:
+        roof["traffic"] = measured_traffic(roof, args.workload, args.precision)
     kernels = {k: {"launches": v["launches"], "ms_per_step": v["ms"] / args.steps} for k, v in timings.items()}
     out = {
         "metric": "(t0,D) GLS fits/s and light curves/s at Δll err ≤1e-6 vs FP64",
