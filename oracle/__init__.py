@@ -18,6 +18,14 @@ Contents (each function cites the passage it follows):
                        the linear-search grid onto phases, the common-depth
                        combination of Eq. 8 with the estimates of Eq. B4,
                        the argmax of Eq. 9 and Q(P) = depth/sigma.
+* ``oracle.learned``   The hyperparameter fit the search needs first (Section
+                       3.2: maximum likelihood with the trend solved
+                       linearly) and the learned warm start for it: the
+                       counter-based random numbers and GP sampler of the
+                       training data, the CNN input, the network with its
+                       gradient and Adam, the trend-profiled likelihood by
+                       dense Cholesky and by Kalman filter, the plain
+                       Lomb-Scargle start and BFGS.
 
 Readings of passages where the paper is silent or inconsistent are listed
 in each module header. Parity unpinned (no worked numbers in the paper):
