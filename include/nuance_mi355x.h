@@ -232,6 +232,89 @@ nu_status nu_ctx_autotune(nu_ctx* ctx, int64_t n, nu_precision prec);
 nu_status nu_ctx_get_tuning(const nu_ctx* ctx, int launch_class, int* small_below_host);
 nu_status nu_ctx_set_tuning(nu_ctx* ctx, int launch_class, int small_below);
 
+/* ---------------------------------------------------------------------------
+ * (7) The hyperparameter fit the search needs first, and its learned warm
+ * start. The paper fits the GP hyperparameters of each curve by maximum
+ * likelihood with the trend solved linearly (Section 3.2); the likelihood is
+ * Eq. 5 of the trend-only model. Here the fit runs in the coordinates
+ * x = (ln amp, ln P_rot, ln Q, ln sigma_w), with omega = 4 pi Q / (P_rot
+ * sqrt(4Q^2 - 1)) for Q > 1/2 (2 pi / P_rot otherwise). The warm start is a 1D
+ * CNN trained on curves drawn from the GP itself.
+ * --------------------------------------------------------------------------- */
+
+/* (7a) Training curves from the SHO process plus white noise on a unit
+ * baseline: f_n = 1 + g(t_n) + sigma_w e_n, g by the exact discretisation of
+ * the oscillator's state-space model, random numbers from Philox-4x32-10
+ * (Salmon et al. 2011) keyed by seed, counter (sample index, curve index low,
+ * high word, stream: 0 process noise, 1 white noise, 2 initial state, 3
+ * hyperparameters), uniforms (k + 1/2) 2^-52 from the top 26 bits of two words,
+ * Box-Muller normals. Curve c has index curve_base + c. t: device, n >= 2,
+ * strictly increasing, shared by all curves. theta: device, n_curves, or NULL
+ * to draw each curve's hyperparameters from the training prior (log-uniform:
+ * amp [0.005, 0.03], P_rot [0.3, 2] time units, Q [1, 100], sigma_w [3e-4,
+ * 3e-3]). Outputs (device, each may be NULL): flux [n_curves][n]; input
+ * [n_curves][n_bins] (n_bins <= 512): 100 (m_b / median - 1) of the bin means
+ * m_b over n_bins equal time bins (bin floor((t - t_0)/(t_{n-1} - t_0) n_bins),
+ * the last sample in the last bin; median over non-empty bins; empty bins 0);
+ * target [n_curves][4]: the standardised logs of (amp, P_rot, Q, sigma_w)
+ * under the prior; theta_out [n_curves]. */
+nu_status nu_gp_sample(nu_ctx* ctx, const double* t, int64_t n, int n_curves, const nu_sho* theta, uint64_t seed,
+                       uint64_t curve_base, int n_bins, double* flux, float* input, float* target,
+                       nu_sho* theta_out);
+
+/* (7b) -ln L_0 (Eq. 5 of the trend-only model, the trend profiled) for
+ * n_curves x n_eval (curve, theta) pairs, by the Kalman filter of the SHO
+ * state-space model: its innovations whiten [A | f] and ln|K| is the sum of
+ * their log variances (exact, O(N) per pair). sample_off: DEVICE, n_curves + 1
+ * offsets; t, f: device; A: device, curve c's n_c x m1 column-major block at
+ * A + m1 * sample_off[c] (as in (4)); theta: device [n_curves][n_eval]; nll:
+ * device [n_curves][n_eval] (+inf when the trend Gram is singular). */
+nu_status nu_gp_nll(nu_ctx* ctx, int n_curves, const int64_t* sample_off, const double* t, const double* f,
+                    const double* A, int m1, const nu_sho* theta, int n_eval, double* nll);
+
+/* (7c) The plain start (fallback of the learned one): P_rot = the first
+ * maximum of the Lomb-Scargle power of f - mean(f) over prot_grid (device,
+ * n_grid trial periods), amp = std(f), Q = 5, sigma_w = rms of the second
+ * differences / sqrt(6). sample_off: DEVICE, n_curves + 1. x0: device
+ * [n_curves][4] in fit coordinates. */
+nu_status nu_plain_init(nu_ctx* ctx, int n_curves, const int64_t* sample_off, const double* t, const double* f,
+                        const double* prot_grid, int n_grid, double* x0);
+
+/* (7d) Maximum-likelihood fit by BFGS of all curves in lockstep: gradients by
+ * central differences (step 1e-4 in x), Armijo backtracking, coordinates
+ * clamped to wide bounds; one likelihood launch (7b) per gradient or line-
+ * search trial for all curves. sample_off_host: HOST, n_curves + 1. x0_host,
+ * x_host: host [n_curves][4]. Stops per curve when every |gradient| <= gtol,
+ * the step no longer decreases the likelihood, or after max_iter iterations.
+ * nll_host, n_eval_host (likelihood evaluations used), iters_host: host, may
+ * be NULL. Synchronises the stream at every step. */
+nu_status nu_fit_hyper(nu_ctx* ctx, int n_curves, const int64_t* sample_off_host, const double* t, const double* f,
+                       const double* A, int m1, const double* x0_host, int max_iter, double gtol, double* x_host,
+                       double* nll_host, int32_t* n_eval_host, int32_t* iters_host);
+
+/* (7e) The CNN: input 512 values; four convolutions of width 7, stride 2,
+ * zero padding 3, 64 channels, ReLU; global average pool; linear head to 4
+ * outputs (the standardised logs of amp, P_rot, Q, sigma_w). Parameters flat,
+ * FP32: (W1 [64][1][7], b1, W2..W4 [64][64][7], b2..b4, Wh [4][64], bh),
+ * nu_cnn_param_count() values. half_precision != 0: the convolutions run on
+ * the matrix cores in FP16 (weights and activations rounded to FP16, FP32
+ * accumulation, FP32 master weights); 0: FP32 products. Adam (beta 0.9,
+ * 0.999, eps 1e-8) on the mean squared error. All arrays device except
+ * params_host; input [batch][512], target and out [batch][4], grad
+ * [param_count], loss one float; x_log (may be NULL) [batch][4] receives the
+ * outputs in fit coordinates. */
+typedef struct nu_cnn nu_cnn;
+int64_t nu_cnn_param_count(void);
+nu_status nu_cnn_create(nu_ctx* ctx, int half_precision, int max_batch, nu_cnn** out);
+void nu_cnn_destroy(nu_cnn* model);
+nu_status nu_cnn_set_params(nu_ctx* ctx, nu_cnn* model, const float* params_host);
+nu_status nu_cnn_get_params(nu_ctx* ctx, nu_cnn* model, float* params_host);
+nu_status nu_cnn_forward(nu_ctx* ctx, nu_cnn* model, const float* input, int batch, float* out, double* x_log);
+nu_status nu_cnn_gradient(nu_ctx* ctx, nu_cnn* model, const float* input, const float* target, int batch,
+                          float* grad, float* loss);
+nu_status nu_cnn_train_step(nu_ctx* ctx, nu_cnn* model, const float* input, const float* target, int batch, float lr,
+                            float* loss);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,20 @@ SIGNATURES = {
     "nu_ctx_autotune": (c_int, [c_void_p, c_int64, c_int]),
     "nu_ctx_get_tuning": (c_int, [c_void_p, c_int, P(c_int)]),
     "nu_ctx_set_tuning": (c_int, [c_void_p, c_int, c_int]),
+    "nu_gp_sample": (c_int, [c_void_p, c_void_p, c_int64, c_int, c_void_p, ctypes.c_uint64, ctypes.c_uint64, c_int,
+                             c_void_p, c_void_p, c_void_p, c_void_p]),
+    "nu_gp_nll": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int, c_void_p]),
+    "nu_plain_init": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    "nu_fit_hyper": (c_int, [c_void_p, c_int, P(c_int64), c_void_p, c_void_p, c_void_p, c_int, P(c_double), c_int,
+                             c_double, P(c_double), P(c_double), P(c_int32), P(c_int32)]),
+    "nu_cnn_param_count": (c_int64, []),
+    "nu_cnn_create": (c_int, [c_void_p, c_int, c_int, P(c_void_p)]),
+    "nu_cnn_destroy": (None, [c_void_p]),
+    "nu_cnn_set_params": (c_int, [c_void_p, c_void_p, P(ctypes.c_float)]),
+    "nu_cnn_get_params": (c_int, [c_void_p, c_void_p, P(ctypes.c_float)]),
+    "nu_cnn_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
+    "nu_cnn_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
+    "nu_cnn_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p]),
 }
 
 # launch classes of the tile policy (include/nuance_mi355x.h, entry point 6)

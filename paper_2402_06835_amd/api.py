@@ -436,6 +436,163 @@ class Graph:
 
 
 # ---------------------------------------------------------------------------
+# The hyperparameter fit and its learned warm start (entry point 7)
+
+PRIOR = {"amp": (0.005, 0.03), "prot": (0.3, 2.0), "q": (1.0, 100.0), "sigma_w": (3e-4, 3e-3)}
+
+
+def _sho_rows(thetas, dev) -> torch.Tensor:
+    """(k, 4) float64 device rows (amp, omega, q, sigma_w) = k nu_sho structs."""
+    if isinstance(thetas, torch.Tensor):
+        return thetas.to(device=dev, dtype=torch.float64).reshape(-1, 4).contiguous()
+    rows = []
+    for th in thetas:
+        sho = th if isinstance(th, SHO) else SHO.from_dict(th)
+        rows.append([sho.amp, sho.omega, sho.q, sho.sigma_w])
+    return torch.tensor(rows, dtype=torch.float64, device=dev)
+
+
+def gp_sample(ctx: Context, t, n_curves: int, theta=None, seed: int = 0, curve_base: int = 0, n_bins: int = 512,
+              flux: bool = False, inputs: bool = True) -> dict:
+    """Curves from the SHO process + white noise (7a): theta None draws from the training prior."""
+    dev = ctx.device
+    t_d = _dev_tensor(t, torch.float64, dev)
+    n = t_d.numel()
+    th = None if theta is None else _sho_rows(theta, dev)
+    out = {"theta": torch.empty((n_curves, 4), dtype=torch.float64, device=dev),
+           "target": torch.empty((n_curves, 4), dtype=torch.float32, device=dev)}
+    if flux:
+        out["flux"] = torch.empty((n_curves, n), dtype=torch.float64, device=dev)
+    if inputs:
+        out["input"] = torch.empty((n_curves, n_bins), dtype=torch.float32, device=dev)
+
+    def ptr(k):
+        return ctypes.c_void_p(out[k].data_ptr()) if k in out else ctypes.c_void_p(0)
+
+    st = lib().nu_gp_sample(ctx.ptr, ctypes.c_void_p(t_d.data_ptr()), n, int(n_curves),
+                            ctypes.c_void_p(th.data_ptr() if th is not None else 0), int(seed), int(curve_base),
+                            int(n_bins), ptr("flux"), ptr("input"), ptr("target"), ptr("theta"))
+    _check(ctx.ptr, st)
+    out["_keep"] = (t_d, th)
+    return out
+
+
+def gp_nll(ctx: Context, batch: dict, thetas, n_eval: int = 1) -> torch.Tensor:
+    """-ln L_0 (7b) of curve c at thetas[c * n_eval + e]; batch from ``prepare_batch``."""
+    dev = ctx.device
+    th = _sho_rows(thetas, dev)
+    nc = batch["n_curves"]
+    if th.shape[0] != nc * n_eval:
+        raise ValueError("need n_curves * n_eval thetas")
+    off = torch.as_tensor(batch["sample_off"], device=dev)
+    nll = torch.empty((nc, n_eval), dtype=torch.float64, device=dev)
+    A = batch["A"]
+    st = lib().nu_gp_nll(ctx.ptr, nc, ctypes.c_void_p(off.data_ptr()), ctypes.c_void_p(batch["t"].data_ptr()),
+                         ctypes.c_void_p(batch["f"].data_ptr()), ctypes.c_void_p(A.data_ptr() if A is not None else 0),
+                         batch["m1"], ctypes.c_void_p(th.data_ptr()), int(n_eval), ctypes.c_void_p(nll.data_ptr()))
+    _check(ctx.ptr, st)
+    torch.cuda.synchronize(dev)
+    return nll
+
+
+def plain_init(ctx: Context, batch: dict, prot_grid) -> torch.Tensor:
+    """The plain start (7c): (n_curves, 4) fit coordinates ln(amp, P_rot, Q, sigma_w)."""
+    dev = ctx.device
+    grid = _dev_tensor(prot_grid, torch.float64, dev)
+    off = torch.as_tensor(batch["sample_off"], device=dev)
+    x0 = torch.empty((batch["n_curves"], 4), dtype=torch.float64, device=dev)
+    st = lib().nu_plain_init(ctx.ptr, batch["n_curves"], ctypes.c_void_p(off.data_ptr()),
+                             ctypes.c_void_p(batch["t"].data_ptr()), ctypes.c_void_p(batch["f"].data_ptr()),
+                             ctypes.c_void_p(grid.data_ptr()), grid.numel(), ctypes.c_void_p(x0.data_ptr()))
+    _check(ctx.ptr, st)
+    torch.cuda.synchronize(dev)
+    return x0
+
+
+def fit_hyper(ctx: Context, batch: dict, x0, max_iter: int = 100, gtol: float = 1e-2) -> dict:
+    """BFGS maximum-likelihood fit (7d) from x0 (n_curves, 4) in fit coordinates."""
+    nc = batch["n_curves"]
+    x0h = np.ascontiguousarray(x0.cpu().numpy() if isinstance(x0, torch.Tensor) else np.asarray(x0),
+                               dtype=np.float64).reshape(nc, 4)
+    x = np.zeros((nc, 4))
+    nll = np.zeros(nc)
+    nev = np.zeros(nc, dtype=np.int32)
+    its = np.zeros(nc, dtype=np.int32)
+    A = batch["A"]
+    PD = ctypes.POINTER(ctypes.c_double)
+    PI = ctypes.POINTER(ctypes.c_int32)
+    st = lib().nu_fit_hyper(ctx.ptr, nc, batch["sample_off"].ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            ctypes.c_void_p(batch["t"].data_ptr()), ctypes.c_void_p(batch["f"].data_ptr()),
+                            ctypes.c_void_p(A.data_ptr() if A is not None else 0), batch["m1"],
+                            x0h.ctypes.data_as(PD), int(max_iter), float(gtol), x.ctypes.data_as(PD),
+                            nll.ctypes.data_as(PD), nev.ctypes.data_as(PI), its.ctypes.data_as(PI))
+    _check(ctx.ptr, st)
+    return {"x": x, "nll": nll, "n_eval": nev, "iters": its}
+
+
+class CNN:
+    """The warm-start network (7e) with its parameters, Adam state and activations on the device."""
+
+    def __init__(self, ctx: Context, half: bool = True, max_batch: int = 256, params=None):
+        self.ctx = ctx
+        self.max_batch = max_batch
+        p = ctypes.c_void_p()
+        _check(ctx.ptr, lib().nu_cnn_create(ctx.ptr, int(half), int(max_batch), ctypes.byref(p)))
+        self.ptr = p
+        self.n_params = int(lib().nu_cnn_param_count())
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if a.size != self.n_params:
+            raise ValueError(f"need {self.n_params} parameters")
+        _check(self.ctx.ptr, lib().nu_cnn_set_params(self.ctx.ptr, self.ptr,
+                                                     a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.n_params, dtype=np.float32)
+        _check(self.ctx.ptr, lib().nu_cnn_get_params(self.ctx.ptr, self.ptr,
+                                                     a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return a
+
+    def forward(self, inputs: torch.Tensor):
+        """Outputs (batch, 4) standardised, and the same in fit coordinates (float64)."""
+        b = inputs.shape[0]
+        out = torch.empty((b, 4), dtype=torch.float32, device=self.ctx.device)
+        xlog = torch.empty((b, 4), dtype=torch.float64, device=self.ctx.device)
+        _check(self.ctx.ptr, lib().nu_cnn_forward(self.ctx.ptr, self.ptr, ctypes.c_void_p(inputs.data_ptr()), b,
+                                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(xlog.data_ptr())))
+        return out, xlog
+
+    def gradient(self, inputs: torch.Tensor, targets: torch.Tensor):
+        b = inputs.shape[0]
+        g = torch.empty(self.n_params, dtype=torch.float32, device=self.ctx.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.ctx.device)
+        _check(self.ctx.ptr, lib().nu_cnn_gradient(self.ctx.ptr, self.ptr, ctypes.c_void_p(inputs.data_ptr()),
+                                                   ctypes.c_void_p(targets.data_ptr()), b,
+                                                   ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(loss.data_ptr())))
+        return g, loss
+
+    def train_step(self, inputs: torch.Tensor, targets: torch.Tensor, lr: float = 1e-3, loss=None):
+        b = inputs.shape[0]
+        _check(self.ctx.ptr, lib().nu_cnn_train_step(self.ctx.ptr, self.ptr, ctypes.c_void_p(inputs.data_ptr()),
+                                                     ctypes.c_void_p(targets.data_ptr()), b, float(lr),
+                                                     ctypes.c_void_p(loss.data_ptr() if loss is not None else 0)))
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().nu_cnn_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
 class SearchResult:
     """Periodogram and best candidate of a periodic search (host arrays)."""
 

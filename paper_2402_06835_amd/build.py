@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnuance_mi355x.so")
 
-SOURCES = ["factor.hip", "gemm.hip", "linear.hip", "fold.hip", "precision.hip", "engine.cpp", "capi.cpp", "batch.cpp"]
+SOURCES = ["factor.hip", "gemm.hip", "linear.hip", "fold.hip", "precision.hip", "engine.cpp", "capi.cpp", "batch.cpp", "learned.hip",
+           "learned_api.cpp"]
 ARCH = os.environ.get("NU_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-ffp-contract=off",
