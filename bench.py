@@ -22,6 +22,8 @@ measured after the timed region and reported. Other modes:
   --workload batch-64   64 curves of 4000..20000 samples in one batch call per step
                         (--mode loop: the same curves through the single-curve calls)
   --autotune            tile policy tuned on the device before warming up
+  --workload learned    the learned warm start: GP sampling, CNN training, and BFGS fits of 256
+                        held-out curves from the plain and from the learned start
 """
 from __future__ import annotations
 
@@ -220,6 +222,86 @@ def bench_batch(args, api, ctx, torch):
     return elapsed, n_valid, len(ws), timings, dll_err, cfg, {"injected_recovered": f"{found}/{n_inj}"}
 
 
+def bench_learned(args, api, ctx, torch):
+    """The learned warm start at the TESS-sector shape: 100000 training curves drawn from the
+    GP on the device, the CNN trained on them, then 256 held-out curves fitted by BFGS from the
+    plain start and from the learned one (the judge: the best optimum of those and the true start)."""
+    import numpy as np
+    dt = 2 / 1440
+    t = np.arange(18000) * dt
+    t[9000:] += 720 * dt
+    ntr, bs, nev = 100000, 256, 256
+    X = torch.empty((ntr, 512), dtype=torch.float32, device=ctx.device)
+    Y = torch.empty((ntr, 4), dtype=torch.float32, device=ctx.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for base in range(0, ntr, 8192):
+        k = min(8192, ntr - base)
+        d = api.gp_sample(ctx, t, k, theta=None, seed=5_000_000, curve_base=base)
+        X[base:base + k] = d["input"]
+        Y[base:base + k] = d["target"]
+    torch.cuda.synchronize()
+    t_sample = time.perf_counter() - t0
+    log(f"sampled {ntr} curves of N=18000 in {t_sample:.2f} s")
+    m = api.CNN(ctx, half=True, max_batch=bs, seed=1)
+    steps = ntr // bs
+    loss = torch.empty(1, dtype=torch.float32, device=ctx.device)
+    ctx.enable_timing(True)
+    ctx.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ep in range(args.epochs):
+        lr = 2e-3 * 0.5 ** (ep // 4)
+        for s in range(steps):
+            j = ((s + 37 * ep) % steps) * bs
+            m.train_step(X[j:j + bs], Y[j:j + bs], lr=lr, loss=loss)
+        log(f"epoch {ep + 1}/{args.epochs}: loss of the last batch {loss.item():.4f}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    train_timings = ctx.timings()
+    d = api.gp_sample(ctx, t, nev, theta=None, seed=6000, curve_base=0, flux=True)
+    th = d["theta"].cpu().numpy()
+    prot = 4 * np.pi * th[:, 2] / (th[:, 1] * np.sqrt(4 * th[:, 2] ** 2 - 1))
+    x_true = np.log(np.column_stack([th[:, 0], prot, th[:, 2], th[:, 3]]))
+    x = (t - t.mean()) / (np.ptp(t) / 2)
+    A1 = np.concatenate([np.stack([np.ones_like(x), x, x * x])] * nev).reshape(-1)
+    batch = {"n_curves": nev, "sample_off": np.arange(nev + 1, dtype=np.int64) * t.size,
+             "t": torch.as_tensor(np.tile(t, nev), device=ctx.device), "f": d["flux"].reshape(-1).contiguous(),
+             "A": torch.as_tensor(A1, device=ctx.device), "m1": 3}
+    grid = np.exp(np.linspace(math.log(0.1), math.log(5.0), 1000))
+    ctx.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x_plain = api.plain_init(ctx, batch, grid)
+    t_plain_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x_learned = m.warm_start(d["input"], x_plain)
+    torch.cuda.synchronize()
+    t_infer = time.perf_counter() - t0
+    fits, t_fit = {}, {}
+    for k, x0 in (("plain", x_plain), ("learned", x_learned), ("truth", x_true)):
+        t0 = time.perf_counter()
+        fits[k] = api.fit_hyper(ctx, batch, x0, max_iter=300, gtol=1e-3)
+        t_fit[k] = time.perf_counter() - t0
+        log(f"fit from the {k} start: {t_fit[k]:.2f} s, {fits[k]['n_eval'].mean():.1f} likelihood evaluations per curve")
+    timings = ctx.timings()
+    ctx.enable_timing(False)
+    best = np.min(np.stack([f["nll"] for f in fits.values()]), axis=0)
+    summary = {}
+    for k in ("plain", "learned"):
+        gap = fits[k]["nll"] - best
+        x0 = (x_plain if k == "plain" else x_learned).cpu().numpy()
+        summary[k] = {"success_rate": float(np.mean(gap < 0.1)), "mean_evaluations": float(fits[k]["n_eval"].mean()),
+                      "fit_seconds": t_fit[k], "curves_per_s": nev / t_fit[k],
+                      "median_abs_log_error_at_start": np.median(np.abs(x0 - x_true), axis=0).round(4).tolist()}
+    cfg = {"workload": "learned-warm-start-tess-sector", "train_curves": ntr, "epochs": args.epochs,
+           "batch": bs, "eval_curves": nev, "n_samples": int(t.size), "precision": "cnn fp16/fp32, fit fp64"}
+    extra = {"sampler_curves_per_s": ntr / t_sample, "train_samples_per_s": ntr * args.epochs / t_train,
+             "train_seconds": t_train, "plain_start_seconds": t_plain_init, "learned_start_seconds": t_infer,
+             "fit": summary, "train_kernels": {k: v["ms"] for k, v in train_timings.items()}}
+    return t_fit["learned"], nev, nev, timings, None, cfg, extra
+
+
 def bench_curve(args, api, ctx, torch):
     """One TESS-sector-shaped curve per step (eager calls, or one captured-graph launch)."""
     w = workload(args.workload)
@@ -286,7 +368,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="tess-sector", choices=["tess-sector", "plain-1440", "batch-64"])
+    ap.add_argument("--workload", default="tess-sector",
+                    choices=["tess-sector", "plain-1440", "batch-64", "learned"])
+    ap.add_argument("--epochs", type=int, default=12, help="training epochs of the learned workload")
     ap.add_argument("--precision", default="fp32_refine", choices=["fp64", "fp32_refine"])
     ap.add_argument("--mode", default="eager", choices=["eager", "graph", "loop"])
     ap.add_argument("--autotune", action="store_true", help="tune the tile policy before warming up")
@@ -326,6 +410,16 @@ def main(argv=None):
         tuning = ctx.autotune(18000 if args.workload != "plain-1440" else 1440, args.precision)
         log(f"autotuned in {time.perf_counter() - t0:.1f} s: {tuning}")
     w = None
+    if args.workload == "learned":
+        elapsed, n_valid, curves, timings, dll_err, cfg, extra = bench_learned(args, api, ctx, torch)
+        out = {"metric": "ML hyperparameter fits/s from the learned warm start", "value": n_valid / elapsed,
+               "unit": "curves/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": elapsed * 1e3,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16+f32 (cnn), f64 (fit)",
+               "data": "synthetic", "config": cfg, "roofline": None,
+               "kernels": {k: {"launches": v["launches"], "ms": v["ms"]} for k, v in timings.items()}}
+        out.update(extra)
+        print(json.dumps(out), flush=True)
+        return 0
     if args.workload == "batch-64":
         if args.mode == "graph":
             raise SystemExit("the batch runs through its own entry point (--mode eager, or loop)")

@@ -308,8 +308,17 @@ int64_t nu_cnn_param_count(void);
 nu_status nu_cnn_create(nu_ctx* ctx, int half_precision, int max_batch, nu_cnn** out);
 void nu_cnn_destroy(nu_cnn* model);
 nu_status nu_cnn_set_params(nu_ctx* ctx, nu_cnn* model, const float* params_host);
+/* He-uniform weights (U(-sqrt(6/fan_in), sqrt(6/fan_in)), uniforms from
+ * Philox with counter = parameter index, stream 4), zero biases, fresh Adam. */
+nu_status nu_cnn_init(nu_ctx* ctx, nu_cnn* model, uint64_t seed);
 nu_status nu_cnn_get_params(nu_ctx* ctx, nu_cnn* model, float* params_host);
 nu_status nu_cnn_forward(nu_ctx* ctx, nu_cnn* model, const float* input, int batch, float* out, double* x_log);
+/* (7f) The learned warm start of the fit (7d): the network's amp, P_rot and Q
+ * with sigma_w from the plain start x_plain (device [batch][4], from (7c)): the
+ * binned input averages the white noise away, the second differences of the
+ * full curve measure it. x_out: device [batch][4] fit coordinates. */
+nu_status nu_warm_start(nu_ctx* ctx, nu_cnn* model, const float* input, int batch, const double* x_plain,
+                        double* x_out);
 nu_status nu_cnn_gradient(nu_ctx* ctx, nu_cnn* model, const float* input, const float* target, int batch,
                           float* grad, float* loss);
 nu_status nu_cnn_train_step(nu_ctx* ctx, nu_cnn* model, const float* input, const float* target, int batch, float lr,

@@ -70,7 +70,9 @@ SIGNATURES = {
     "nu_cnn_destroy": (None, [c_void_p]),
     "nu_cnn_set_params": (c_int, [c_void_p, c_void_p, P(ctypes.c_float)]),
     "nu_cnn_get_params": (c_int, [c_void_p, c_void_p, P(ctypes.c_float)]),
+    "nu_cnn_init": (c_int, [c_void_p, c_void_p, ctypes.c_uint64]),
     "nu_cnn_forward": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
+    "nu_warm_start": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "nu_cnn_gradient": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "nu_cnn_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float, c_void_p]),
 }

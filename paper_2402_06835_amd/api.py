@@ -533,7 +533,7 @@ def fit_hyper(ctx: Context, batch: dict, x0, max_iter: int = 100, gtol: float = 
 class CNN:
     """The warm-start network (7e) with its parameters, Adam state and activations on the device."""
 
-    def __init__(self, ctx: Context, half: bool = True, max_batch: int = 256, params=None):
+    def __init__(self, ctx: Context, half: bool = True, max_batch: int = 256, params=None, seed: int = 0):
         self.ctx = ctx
         self.max_batch = max_batch
         p = ctypes.c_void_p()
@@ -542,6 +542,8 @@ class CNN:
         self.n_params = int(lib().nu_cnn_param_count())
         if params is not None:
             self.set_params(params)
+        else:
+            _check(ctx.ptr, lib().nu_cnn_init(ctx.ptr, self.ptr, int(seed)))
 
     def set_params(self, params):
         a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
@@ -564,6 +566,15 @@ class CNN:
         _check(self.ctx.ptr, lib().nu_cnn_forward(self.ctx.ptr, self.ptr, ctypes.c_void_p(inputs.data_ptr()), b,
                                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(xlog.data_ptr())))
         return out, xlog
+
+    def warm_start(self, inputs: torch.Tensor, x_plain: torch.Tensor) -> torch.Tensor:
+        """Fit coordinates (batch, 4): the network's amp, P_rot, Q and the plain start's sigma_w (7f)."""
+        b = inputs.shape[0]
+        x = torch.empty((b, 4), dtype=torch.float64, device=self.ctx.device)
+        xp = x_plain.to(device=self.ctx.device, dtype=torch.float64).contiguous()
+        _check(self.ctx.ptr, lib().nu_warm_start(self.ctx.ptr, self.ptr, ctypes.c_void_p(inputs.data_ptr()), b,
+                                                 ctypes.c_void_p(xp.data_ptr()), ctypes.c_void_p(x.data_ptr())))
+        return x
 
     def gradient(self, inputs: torch.Tensor, targets: torch.Tensor):
         b = inputs.shape[0]

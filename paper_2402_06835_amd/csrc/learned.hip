@@ -905,19 +905,45 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, _Float
   if (p16) p16[i] = (_Float16)pi;
 }
 
+// He-uniform weights, zero biases: parameter i of a weight block with fan-in F
+// is U(-sqrt(6/F), sqrt(6/F)), the uniform from Philox (counter i, stream 4)
+__global__ __launch_bounds__(256) void cnn_init_kernel(float* __restrict__ p, int64_t n, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  int fan = 0;
+  for (int l = 0; l < CNN_LAYERS; ++l)
+    if (i >= cnn_w_offset(l) && i < cnn_b_offset(l)) fan = (l == 0 ? 1 : CNN_CH) * CNN_KW;
+  if (i >= cnn_head_w() && i < cnn_head_b()) fan = CNN_CH;
+  if (fan == 0) {
+    p[i] = 0.f;
+    return;
+  }
+  const U4 w = draw((uint64_t)i, 0, 4, seed);
+  const double u = uniform01(w.v[0], w.v[1]);
+  p[i] = (float)((2.0 * u - 1.0) * sqrt(6.0 / fan));
+}
+
+hipError_t launch_cnn_init(hipStream_t s, float* p, int64_t n, uint64_t seed) {
+  hipLaunchKernelGGL(cnn_init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, seed);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void to_half_kernel(const float* __restrict__ p, _Float16* __restrict__ p16,
                                                       int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) p16[i] = (_Float16)p[i];
 }
 
-// standardised outputs -> fit coordinates (ln amp, ln P_rot, ln Q, ln sigma_w)
-__global__ void outputs_to_log_kernel(const float* __restrict__ y, int batch, double* __restrict__ x) {
+// standardised outputs -> fit coordinates (ln amp, ln P_rot, ln Q, ln sigma_w); with x_plain,
+// ln sigma_w is taken from it (the white noise is averaged out of the binned input, the
+// second differences of the full curve measure it directly)
+__global__ void outputs_to_log_kernel(const float* __restrict__ y, int batch, const double* __restrict__ x_plain,
+                                      double* __restrict__ x) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= batch * CNN_OUT) return;
   const int k = i % CNN_OUT;
   const double lo = log(prior_lo(k)), hi = log(prior_hi(k));
-  x[i] = 0.5 * (lo + hi) + (hi - lo) / sqrt(12.0) * (double)y[i];
+  x[i] = (x_plain && k == 3) ? x_plain[i] : 0.5 * (lo + hi) + (hi - lo) / sqrt(12.0) * (double)y[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1021,9 +1047,9 @@ hipError_t launch_to_half(hipStream_t s, const float* p, _Float16* p16, int64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_outputs_to_log(hipStream_t s, const float* y, int batch, double* x) {
+hipError_t launch_outputs_to_log(hipStream_t s, const float* y, int batch, const double* x_plain, double* x) {
   hipLaunchKernelGGL(outputs_to_log_kernel, dim3((unsigned)((batch * CNN_OUT + 255) / 256)), dim3(256), 0, s, y,
-                     batch, x);
+                     batch, x_plain, x);
   return hipGetLastError();
 }
 

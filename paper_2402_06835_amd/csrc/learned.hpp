@@ -26,13 +26,15 @@ constexpr int CNN_IN = 512, CNN_CH = 64, CNN_KW = 7, CNN_LAYERS = 4, CNN_OUT = 4
 constexpr int CNN_WCHUNK = 8;  // samples per partial of the weight gradient
 
 // flat parameter layout: (W1, b1, ..., W4, b4, Wh, bh), W of layer l is [64][c_in * 7]
-inline int64_t cnn_w_offset(int l) {
+__host__ __device__ inline int64_t cnn_w_offset(int l) {
   return l == 0 ? 0 : (int64_t)CNN_CH * CNN_KW + CNN_CH + (int64_t)(l - 1) * (CNN_CH * CNN_CH * CNN_KW + CNN_CH);
 }
-inline int64_t cnn_b_offset(int l) { return cnn_w_offset(l) + (int64_t)CNN_CH * (l == 0 ? 1 : CNN_CH) * CNN_KW; }
-inline int64_t cnn_head_w() { return cnn_b_offset(CNN_LAYERS - 1) + CNN_CH; }
-inline int64_t cnn_head_b() { return cnn_head_w() + (int64_t)CNN_OUT * CNN_CH; }
-inline int64_t cnn_param_count() { return cnn_head_b() + CNN_OUT; }
+__host__ __device__ inline int64_t cnn_b_offset(int l) {
+  return cnn_w_offset(l) + (int64_t)CNN_CH * (l == 0 ? 1 : CNN_CH) * CNN_KW;
+}
+__host__ __device__ inline int64_t cnn_head_w() { return cnn_b_offset(CNN_LAYERS - 1) + CNN_CH; }
+__host__ __device__ inline int64_t cnn_head_b() { return cnn_head_w() + (int64_t)CNN_OUT * CNN_CH; }
+__host__ __device__ inline int64_t cnn_param_count() { return cnn_head_b() + CNN_OUT; }
 
 // activations and scratch of one batch
 struct CnnBuffers {
@@ -59,6 +61,7 @@ hipError_t launch_cnn_backward(hipStream_t s, const CnnBuffers& B, const float* 
 hipError_t launch_adam(hipStream_t s, float* p, _Float16* p16, const float* g, float* m, float* v, int64_t n, float lr,
                        float b1, float b2, float eps, float c1, float c2);
 hipError_t launch_to_half(hipStream_t s, const float* p, _Float16* p16, int64_t n);
-hipError_t launch_outputs_to_log(hipStream_t s, const float* y, int batch, double* x);
+hipError_t launch_cnn_init(hipStream_t s, float* p, int64_t n, uint64_t seed);
+hipError_t launch_outputs_to_log(hipStream_t s, const float* y, int batch, const double* x_plain, double* x);
 
 }  // namespace nu

@@ -393,6 +393,18 @@ nu_status nu_cnn_set_params(nu_ctx* ctx, nu_cnn* M, const float* params_host) {
   return st;
 }
 
+nu_status nu_cnn_init(nu_ctx* ctx, nu_cnn* M, uint64_t seed) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!M) return set_error(ctx, NU_ERR_ARG, "cnn_init: null model");
+  nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st == NU_OK) st = check_hip(ctx, launch_cnn_init(ctx->stream, M->p, M->n, seed), "cnn init");
+  if (st == NU_OK) st = check_hip(ctx, launch_to_half(ctx->stream, M->p, M->p16, M->n), "to half");
+  if (st == NU_OK) st = check_hip(ctx, hipMemsetAsync(M->m, 0, (size_t)M->n * 4, ctx->stream), "clear m");
+  if (st == NU_OK) st = check_hip(ctx, hipMemsetAsync(M->v, 0, (size_t)M->n * 4, ctx->stream), "clear v");
+  M->step = 0;
+  return st;
+}
+
 nu_status nu_cnn_get_params(nu_ctx* ctx, nu_cnn* M, float* params_host) {
   if (!ctx) return NU_ERR_ARG;
   if (!M || !params_host) return set_error(ctx, NU_ERR_ARG, "cnn_get_params: null argument");
@@ -421,7 +433,23 @@ nu_status nu_cnn_forward(nu_ctx* ctx, nu_cnn* M, const float* input, int batch, 
     Timed tm(ctx, "cnn_forward", 0.0);
     st = check_hip(ctx, launch_cnn_forward(ctx->stream, M->buf, M->p, M->p16, M->half, input, batch, o), "cnn fwd");
   }
-  if (st == NU_OK && x_log) st = check_hip(ctx, launch_outputs_to_log(ctx->stream, o, batch, x_log), "to log");
+  if (st == NU_OK && x_log)
+    st = check_hip(ctx, launch_outputs_to_log(ctx->stream, o, batch, nullptr, x_log), "to log");
+  return st;
+}
+
+nu_status nu_warm_start(nu_ctx* ctx, nu_cnn* M, const float* input, int batch, const double* x_plain,
+                        double* x_out) {
+  nu_status st = cnn_check(ctx, M, input, batch, "warm_start");
+  if (st != NU_OK) return st;
+  if (!x_plain || !x_out) return set_error(ctx, NU_ERR_ARG, "warm_start: null argument");
+  {
+    Timed tm(ctx, "cnn_forward", 0.0);
+    st = check_hip(ctx, launch_cnn_forward(ctx->stream, M->buf, M->p, M->p16, M->half, input, batch, M->buf.out),
+                   "cnn fwd");
+  }
+  if (st == NU_OK)
+    st = check_hip(ctx, launch_outputs_to_log(ctx->stream, M->buf.out, batch, x_plain, x_out), "warm start");
   return st;
 }
 

@@ -251,3 +251,67 @@ def test_cnn_training_reduces_the_loss(api, ctx):
     say(f"mean loss of the first 10 steps {first / 10:.4f}, of the last 10 {last / 10:.4f}")
     assert last / 10 < 0.7 * first / 10
     m.close()
+
+
+def test_learned_warm_start_gain(api, ctx):
+    """What the trained network gains over the plain start, at the TESS-sector shape:
+    the network is trained on the GPU on 100000 curves drawn from the GP, then both
+    starts seed the same BFGS fit on 128 held-out curves. The judge is the best optimum
+    found from the plain, learned and true starts."""
+    import torch
+    dt = 2 / 1440
+    t = np.arange(18000) * dt
+    t[9000:] += 720 * dt
+    say("learned warm start: sample 100000 curves N=18000, train 12 epochs, fit 128 held-out curves")
+    ntr, bs = 100000, 256
+    X = torch.empty((ntr, 512), dtype=torch.float32, device="cuda")
+    Y = torch.empty((ntr, 4), dtype=torch.float32, device="cuda")
+    for base in range(0, ntr, 8192):
+        k = min(8192, ntr - base)
+        d = api.gp_sample(ctx, t, k, theta=None, seed=5_000_000, curve_base=base)
+        X[base:base + k] = d["input"]
+        Y[base:base + k] = d["target"]
+    m = api.CNN(ctx, half=True, max_batch=bs, seed=1)
+    steps = ntr // bs
+    for ep in range(12):
+        lr = 2e-3 * 0.5 ** (ep // 4)
+        for s in range(steps):
+            j = ((s + 37 * ep) % steps) * bs  # a different order each epoch, deterministic
+            m.train_step(X[j:j + bs], Y[j:j + bs], lr=lr)
+    torch.cuda.synchronize()
+    nev = 128
+    d = api.gp_sample(ctx, t, nev, theta=None, seed=6000, curve_base=0, flux=True)
+    th = d["theta"].cpu().numpy()
+    prot = 4 * np.pi * th[:, 2] / (th[:, 1] * np.sqrt(4 * th[:, 2] ** 2 - 1))
+    x_true = np.log(np.column_stack([th[:, 0], prot, th[:, 2], th[:, 3]]))
+    x = (t - t.mean()) / (np.ptp(t) / 2)
+    A1 = np.concatenate([np.stack([np.ones_like(x), x, x * x])] * nev).reshape(-1)
+    batch = {"n_curves": nev, "sample_off": np.arange(nev + 1, dtype=np.int64) * t.size,
+             "t": torch.as_tensor(np.tile(t, nev), device="cuda"), "f": d["flux"].reshape(-1).contiguous(),
+             "A": torch.as_tensor(A1, device="cuda"), "m1": 3}
+    grid = np.exp(np.linspace(math.log(0.1), math.log(5.0), 1000))
+    x_plain = api.plain_init(ctx, batch, grid)
+    x_learned = m.warm_start(d["input"], x_plain)
+    starts = {"plain": x_plain.cpu().numpy(), "learned": x_learned.cpu().numpy(), "truth": x_true}
+    fits = {k: api.fit_hyper(ctx, batch, v, max_iter=300, gtol=1e-3) for k, v in starts.items()}
+    best = np.min(np.stack([f["nll"] for f in fits.values()]), axis=0)
+
+    def start_gap(x0):
+        rows = []
+        for r in x0:
+            amp, p_rot, q, sw = np.exp(r)
+            rows.append([amp, ol.omega_from_rotation(p_rot, q), q, sw])
+        return api.gp_nll(ctx, batch, torch.as_tensor(np.array(rows), device="cuda")).cpu().numpy()[:, 0] - best
+
+    stats = {}
+    for k in ("plain", "learned"):
+        gap = fits[k]["nll"] - best
+        stats[k] = {"success": float(np.mean(gap < 0.1)), "evals": float(fits[k]["n_eval"].mean()),
+                    "start_gap": float(np.median(start_gap(starts[k]))),
+                    "q_err": float(np.median(np.abs(starts[k][:, 2] - x_true[:, 2])))}
+        say(f"{k}: {stats[k]}")
+    assert stats["learned"]["success"] >= stats["plain"]["success"]
+    assert stats["learned"]["start_gap"] < stats["plain"]["start_gap"] / 5
+    assert stats["learned"]["q_err"] < stats["plain"]["q_err"] / 2
+    assert stats["learned"]["evals"] < 0.95 * stats["plain"]["evals"]
+    m.close()
