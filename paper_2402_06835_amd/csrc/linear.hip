@@ -65,38 +65,73 @@ hipError_t launch_pack_v(hipStream_t s, const double* A, int m1, const double* f
 }
 
 // out[r] = base[r] + alpha * sum_{m <= r} M[r][m] V[m]   (nv columns, row-major,
-// lower-triangular M; one wave per row, fixed-order wave reduction). out may
-// alias base.
+// lower-triangular M; entries above the diagonal are never read). A wave owns
+// RPW consecutive rows and streams 64-column chunks of V once for all of them
+// (each lane: one column of the chunk, its nv values of V, and one element of
+// every row), so V leaves L2 once per RPW rows; fixed-order wave reductions at
+// the end. out may alias base.
+constexpr int RPW = 8;
+
+template <int NV>
 __global__ __launch_bounds__(256) void rows_matvec_kernel(const double* __restrict__ M, int64_t ldm, int64_t n,
-                                                          const double* __restrict__ V, int nv,
-                                                          const double* base, double alpha, double* out) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+                                                          const double* __restrict__ V, const double* base,
+                                                          double alpha, double* out) {
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
   const int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  double acc[YCOLS];
+  if (r0 >= n) return;
+  const int rows = (int)min((int64_t)RPW, n - r0);
+  const int64_t rlast = r0 + rows - 1;
+  double acc[RPW][NV];
 #pragma unroll
-  for (int c = 0; c < YCOLS; ++c) acc[c] = 0.0;
-  const double* mr = M + row * ldm;
-  for (int64_t m = lane; m <= row; m += 64) {
-    const double x = mr[m];
-    const double* v = V + m * YCOLS;
+  for (int i = 0; i < RPW; ++i)
 #pragma unroll
-    for (int c = 0; c < YCOLS; ++c)
-      if (c < nv) acc[c] = fma(x, v[c], acc[c]);
+    for (int c = 0; c < NV; ++c) acc[i][c] = 0.0;
+  for (int64_t m0 = 0; m0 <= rlast; m0 += 64) {
+    const int64_t m = m0 + lane;
+    double v[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] = m <= rlast ? V[m * YCOLS + c] : 0.0;
+    double x[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) x[i] = (i < rows && m <= r0 + i) ? M[(r0 + i) * ldm + m] : 0.0;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+      for (int c = 0; c < NV; ++c) acc[i][c] = fma(x[i], v[c], acc[i][c]);
   }
 #pragma unroll
-  for (int c = 0; c < YCOLS; ++c) acc[c] = wave_sum(acc[c]);
-  if (lane == 0) {
+  for (int i = 0; i < RPW; ++i)
 #pragma unroll
-    for (int c = 0; c < YCOLS; ++c)
-      if (c < nv) out[row * YCOLS + c] = (base ? base[row * YCOLS + c] : 0.0) + alpha * acc[c];
+    for (int c = 0; c < NV; ++c) acc[i][c] = wave_sum(acc[i][c]);
+  // lane i * 8 + c writes row r0 + i, column c
+  const int wi = lane >> 3, wc = lane & 7;
+  double mine = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < NV; ++c)
+      if (i == wi && c == wc) mine = acc[i][c];
+  if (wi < rows && wc < NV) {
+    const int64_t o = (r0 + wi) * YCOLS + wc;
+    out[o] = (base ? base[o] : 0.0) + alpha * mine;
   }
 }
 
 hipError_t launch_rows_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, const double* V, int nv,
                               const double* base, double alpha, double* out) {
-  hipLaunchKernelGGL(rows_matvec_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, M, ldm, n, V, nv, base,
-                     alpha, out);
+  const int64_t waves = (n + RPW - 1) / RPW;
+  const dim3 g((unsigned)((waves + 3) / 4)), b(256);
+  switch (nv) {
+    case 1: hipLaunchKernelGGL(rows_matvec_kernel<1>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
+    case 2: hipLaunchKernelGGL(rows_matvec_kernel<2>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
+    case 3: hipLaunchKernelGGL(rows_matvec_kernel<3>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
+    case 4: hipLaunchKernelGGL(rows_matvec_kernel<4>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
+    case 5: hipLaunchKernelGGL(rows_matvec_kernel<5>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
+    case 6: hipLaunchKernelGGL(rows_matvec_kernel<6>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
+    case 7: hipLaunchKernelGGL(rows_matvec_kernel<7>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
+    case 8: hipLaunchKernelGGL(rows_matvec_kernel<8>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -208,7 +243,21 @@ __global__ __launch_bounds__(256) void cols_partial_kernel(const double* __restr
   for (int c = 0; c < YCOLS; ++c) acc[c] = 0.0;
   const int64_t c0 = (int64_t)blockIdx.x * 256;
   if (m < n) {
-    for (int64_t r = max(r0, c0); r < r1; ++r) {
+    // eight rows per step: eight independent loads in flight per thread
+    int64_t r = max(r0, c0);
+    for (; r + 8 <= r1; r += 8) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = (m <= r + u) ? M[(r + u) * ldm + m] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double* wr = W + (r + u) * YCOLS;
+#pragma unroll
+        for (int c = 0; c < YCOLS; ++c)
+          if (c < nv) acc[c] = fma(x[u], wr[c], acc[c]);
+      }
+    }
+    for (; r < r1; ++r) {
       const double x = (m <= r) ? M[r * ldm + m] : 0.0;
       const double* wr = W + r * YCOLS;
 #pragma unroll
