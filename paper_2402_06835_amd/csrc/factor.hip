@@ -62,7 +62,7 @@ hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, 
 // of the inverse (zeros above the diagonal).
 //
 // Blocked right-looking by 16: each 16 x 16 diagonal piece is factored by all
-// threads with one barrier per column, the rows below it are solved against
+// threads with one barrier per pair of columns, the rows below it are solved against
 // it by substitution (one row per thread), and the trailing pieces are
 // updated on the matrix cores. The inverse starts from the eight piece
 // inverses (forward substitution, one column per lane) and is completed by
@@ -78,6 +78,15 @@ constexpr int SB = 16;       // piece edge
 constexpr int NSB = DB / SB; // 8
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// 1/x: the hardware estimate and two Newton-Raphson steps
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 
 __device__ __forceinline__ double xget(const double (*a)[DPAD], const double* xd, int r, int c) {
   return r > c ? a[c][r] : (r == c ? xd[r] : 0.0);
@@ -182,27 +191,44 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __re
   const int pr = tid >> 4, ps = tid & 15;  // (row, column) of a 16 x 16 piece owned by this thread
   for (int kb = 0; kb < NSB; ++kb) {
     const int o = kb * SB;
-    // (a) factor the 16 x 16 diagonal piece, one barrier per column: the
-    // update of column c's trailing entries uses the unscaled column,
-    //   a_rs -= a_rc a_sc / p,  p = a_cc  (entries with s > c only),
-    // while column c - 1 is scaled by 1/sqrt of its pivot (neither phase
-    // touches what the other reads); column 15 is scaled after the loop.
-    double pprev = 1.0;
-    for (int c = 0; c <= SB; ++c) {
-      if (c > 0 && tid < SB && tid >= c - 1) {
-        const double d = sqrt(pprev);
-        if (tid == c - 1) {
-          if (!(pprev > 0.0) && *status < 0) *status = off + o + c - 1;
-          rdg[o + c - 1] = 1.0 / d;
+    // (a) factor the 16 x 16 diagonal piece two columns per barrier: with the
+    // unscaled pivot block P = [[p00, p01], [p01, p11]] of columns c, c+1,
+    //   a_rs -= [a_rc, a_r,c+1] P^-1 [a_sc, a_s,c+1]^T   (s > c+1, r >= s),
+    // while the previous pair is scaled into L (neither phase touches what the
+    // other reads): L_rc = a_rc / sqrt(p00), and with the Schur complement
+    // z = p11 - p01^2 / p00, L_r,c+1 = (a_r,c+1 - a_rc p01 / p00) / sqrt(z).
+    // The last pair is scaled after the loop.
+    double q00 = 1.0, q01 = 0.0, q11 = 1.0;  // pivot block of the previous pair
+    for (int c = 0; c <= SB; c += 2) {
+      if (c > 0 && tid < SB && tid >= c - 2) {
+        const int r = tid, c0 = c - 2;
+        const double rd0 = rcp_nr(sqrt(q00));
+        const double z = q11 - q01 * q01 * rcp_nr(q00);
+        const double rd1 = rcp_nr(sqrt(z));
+        if (r == c0) {
+          if (!(q00 > 0.0) && *status < 0) *status = off + o + c0;
+          else if (!(z > 0.0) && *status < 0) *status = off + o + c0 + 1;
+          rdg[o + c0] = rd0;
+          rdg[o + c0 + 1] = rd1;
         }
-        a[o + tid][o + c - 1] = (tid == c - 1) ? d : a[o + tid][o + c - 1] / d;
+        const double ar0 = a[o + r][o + c0];
+        a[o + r][o + c0] = (r == c0) ? sqrt(q00) : ar0 * rd0;
+        if (r > c0) {
+          const double ar1 = a[o + r][o + c0 + 1];
+          a[o + r][o + c0 + 1] = (r == c0 + 1) ? sqrt(z) : (ar1 - ar0 * q01 * rcp_nr(q00)) * rd1;
+        }
       }
       if (c < SB) {
-        const double p = a[o + c][o + c];
-        const double rp = 1.0 / p;
-        if (ps > c && ps <= pr)
-          a[o + pr][o + ps] = fma(-a[o + pr][o + c] * rp, a[o + ps][o + c], a[o + pr][o + ps]);
-        pprev = p;
+        const double p00 = a[o + c][o + c], p01 = a[o + c + 1][o + c], p11 = a[o + c + 1][o + c + 1];
+        const double rdet = rcp_nr(p00 * p11 - p01 * p01);
+        if (ps > c + 1 && ps <= pr) {
+          const double r0 = a[o + pr][o + c], r1 = a[o + pr][o + c + 1];
+          const double u = (r0 * p11 - r1 * p01) * rdet, v = (r1 * p00 - r0 * p01) * rdet;
+          a[o + pr][o + ps] = fma(-u, a[o + ps][o + c], fma(-v, a[o + ps][o + c + 1], a[o + pr][o + ps]));
+        }
+        q00 = p00;
+        q01 = p01;
+        q11 = p11;
       }
       __syncthreads();
     }
