@@ -35,7 +35,6 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 
-constexpr int JG = 4;     // durations per pass over the events
 constexpr int FPAD = 64;  // padded slots after the grid (invalid), one wave wide
 constexpr int WPH = 63;   // phases per wave: lane 63 only supplies its neighbour
 
@@ -78,6 +77,7 @@ __device__ __forceinline__ double from_next_lane(double x) {
 // The sum of log ratios is taken as one logarithm of a product:
 //   sum_k [ln var_k - ln(sigma^2 + var_k)] = -ln prod_k (1 + sigma^2 / var_k),
 // where the product lies in (1, e] because sigma^2 sum_k 1/var_k = 1.
+template <int JG>  // durations per pass over the events
 __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const double* __restrict__ Lp, int n_d,
                                            int64_t n_t, int j0, int64_t mb, int lane, int64_t nph, double p,
                                            double sign, Best& best) {
@@ -173,6 +173,7 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
   }
 }
 
+template <int JG>
 __global__ __launch_bounds__(256) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
                                                    int n_d, int64_t n_t, double dt,
                                                    const double* __restrict__ periods, double sign,
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(256) void fold_kernel(const double2* __restrict__ D
     const double nph_d = ceil(p);
     const int64_t nph = nph_d < (double)n_t ? (int64_t)nph_d : n_t;  // phases >= n_t hold no event
     for (int64_t mb = (int64_t)wave * WPH; mb < nph; mb += 4 * WPH)
-      for (int j0 = 0; j0 < n_d; j0 += JG) fold_cells(DV, Lp, n_d, n_t, j0, mb, lane, nph, p, sign, best);
+      for (int j0 = 0; j0 < n_d; j0 += JG) fold_cells<JG>(DV, Lp, n_d, n_t, j0, mb, lane, nph, p, sign, best);
   }
   red[tid] = best;
   __syncthreads();
@@ -231,8 +232,14 @@ hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, co
                      n_d, n_epochs, DV, Lp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fold_kernel, dim3((unsigned)n_p), dim3(256), 0, s, DV, Lp, n_d, n_epochs, dt, periods,
-                     (double)sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp);
+  // durations per pass: 5 when that pads fewer cells than 4 (10 durations: 10 rather than 12)
+  const int pad4 = (n_d + 3) / 4 * 4, pad5 = (n_d + 4) / 5 * 5;
+  if (pad5 < pad4)
+    hipLaunchKernelGGL(fold_kernel<5>, dim3((unsigned)n_p), dim3(256), 0, s, DV, Lp, n_d, n_epochs, dt, periods,
+                       (double)sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp);
+  else
+    hipLaunchKernelGGL(fold_kernel<4>, dim3((unsigned)n_p), dim3(256), 0, s, DV, Lp, n_d, n_epochs, dt, periods,
+                       (double)sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp);
   return hipGetLastError();
 }
 
