@@ -38,7 +38,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAKS = {"gemm_f64": 78.6, "gemm_f32": 157.3, "hbm_gbs": 8000.0}
+# gemm_bf16x3 counts each product once (FP32-equivalent flops); it takes three BF16 products at the
+# 2.5 PFLOP/s dense BF16 peak
+PEAKS = {"gemm_f64": 78.6, "gemm_f32": 157.3, "gemm_bf16x3": 2500.0 / 3, "hbm_gbs": 8000.0}
 
 
 def log(msg):
@@ -371,7 +373,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="tess-sector",
                     choices=["tess-sector", "plain-1440", "batch-64", "learned"])
     ap.add_argument("--epochs", type=int, default=12, help="training epochs of the learned workload")
-    ap.add_argument("--precision", default="fp32_refine", choices=["fp64", "fp32_refine"])
+    ap.add_argument("--precision", default="fp32_refine", choices=["fp64", "fp32_refine", "bf16x3_refine"])
     ap.add_argument("--mode", default="eager", choices=["eager", "graph", "loop"])
     ap.add_argument("--autotune", action="store_true", help="tune the tile policy before warming up")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -437,7 +439,7 @@ def main(argv=None):
         "value": n_valid * args.steps / elapsed, "unit": "(t0,D) fits/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f64+f32", "data": "synthetic",
+        "dtype": {"fp64": "f64", "fp32_refine": "f64+f32", "bf16x3_refine": "f64+bf16x3"}[args.precision], "data": "synthetic",
         "config": cfg,
         "light_curves_per_s": curves * args.steps / elapsed,
         "dll_err_vs_fp64": dll_err,

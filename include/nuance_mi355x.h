@@ -53,7 +53,13 @@ typedef enum {
  *                   refinement against L of the whitened trend and flux and of
  *                   their back-substitution. Outputs within ~1e-9 of FP64 on
  *                   the test workloads (the bar is 1e-6 on dll).
- *  NU_BF16X3_REFINE not available in this build (NU_ERR_UNSUPPORTED). */
+ *  NU_BF16X3_REFINE the doubling products as split BF16 products on the
+ *                   matrix cores: each FP32 operand held as hi + lo BF16
+ *                   halves, three products (lo*hi, hi*lo, hi*hi) with FP32
+ *                   accumulation; the same FP64 Newton step on a band of 8
+ *                   block diagonals (FP32_REFINE: 2) and the same refinement
+ *                   of the small solves. The factor then holds wider band
+ *                   buffers: 2 x 9 x 128 n doubles (FP32_REFINE: 2 x 3 x 128 n). */
 typedef enum {
   NU_FP64 = 0,
   NU_FP32_REFINE = 1,
@@ -218,8 +224,9 @@ void nu_graph_destroy(nu_graph* graph);
 
 /* (6) Tile policy of the dense launches. Launch classes: 0 Cholesky panel,
  * 1 panel update, 2 trailing update, 3 FP64 inverse levels, 4 FP32 inverse
- * levels, 5 band Newton step. A launch of a class takes 64 x 64 output tiles
- * when it has fewer 128 x 128 tiles than the class threshold (default 512),
+ * levels, 5 band Newton step, 6 split-BF16 inverse levels. A launch of a
+ * class takes 64 x 64 output tiles when it has fewer 128 x 128 tiles than the
+ * class threshold (default 512),
  * else 128 x 128. The choice changes speed only: every output element sums
  * the same products in the same order either way, so results are bitwise
  * identical. nu_ctx_autotune times the factorisation and inverse of a

@@ -78,7 +78,7 @@ SIGNATURES = {
 }
 
 # launch classes of the tile policy (include/nuance_mi355x.h, entry point 6)
-TUNE_CLASSES = ("panel", "panel_update", "trailing", "inverse_fp64", "inverse_fp32", "band")
+TUNE_CLASSES = ("panel", "panel_update", "trailing", "inverse_fp64", "inverse_fp32", "band", "inverse_bf16x3")
 
 _LIB = None
 

@@ -40,7 +40,8 @@ nu_status fail_batch(nu_ctx* ctx, std::vector<nu_factor*>& Fs, Plan* P, Plan* Q,
 
 const char* class_timing_name(int c) {
   static const char* names[TC_COUNT] = {"gemm_f64:panel",   "gemm_f64:panel_update", "gemm_f64:trailing",
-                                        "gemm_f64:inverse", "gemm_f32:inverse",      "gemm_f64:band"};
+                                        "gemm_f64:inverse", "gemm_f32:inverse",      "gemm_f64:band",
+                                        "gemm_bf16x3:inverse"};
   return names[c];
 }
 
@@ -77,7 +78,7 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
   }
   nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (st != NU_OK) return st;
-  const bool mixed = prec == NU_FP32_REFINE;
+  const bool mixed = prec != NU_FP64;
 
   // shared workspace of the per-curve searches, sized for the largest curve
   size_t ws_need = 0;
@@ -107,7 +108,7 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
   std::vector<std::vector<int>> waves;
   size_t used = 0;
   for (int c : order) {
-    const size_t need = factor_bytes(sample_off_host[c + 1] - sample_off_host[c], mixed);
+    const size_t need = factor_bytes(sample_off_host[c + 1] - sample_off_host[c], prec);
     if (need > budget)
       return set_error(ctx, NU_ERR_OOM, "search_batch: curve " + std::to_string(c) +
                                             " does not fit the device-memory budget");
@@ -121,7 +122,7 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
   size_t arena_need = 0;
   for (const auto& wave : waves) {
     size_t b = 0;
-    for (int c : wave) b += factor_bytes(sample_off_host[c + 1] - sample_off_host[c], mixed);
+    for (int c : wave) b += factor_bytes(sample_off_host[c + 1] - sample_off_host[c], prec);
     arena_need = std::max(arena_need, b);
   }
   char* arena = nullptr;
@@ -140,7 +141,7 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
       char* cursor = arena;
       for (int c : wave) {
         nu_factor* F = nullptr;
-        st = factor_place(ctx, sample_off_host[c + 1] - sample_off_host[c], mixed, &cursor, &F);
+        st = factor_place(ctx, sample_off_host[c + 1] - sample_off_host[c], prec, &cursor, &F);
         if (st != NU_OK) break;
         Fs.push_back(F);
         F->theta_host = theta_host[c];
@@ -187,13 +188,13 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
       HostTimed ht(ctx, "batch_inverse_setup");
       if (mixed) {
         if (st == NU_OK) {
-          plan_inverse(ok, true, ctx->tuning, Q);
-          plan_band(ok, ctx->tuning, Q);
+          plan_inverse(ok, gemm_kind_of(prec), ctx->tuning, Q);
+          plan_band(ok, band_width(prec), ctx->tuning, Q);
           st = plan_upload(ctx, Q);
         }
-        if (st == NU_OK) st = run_inverse_mixed(ctx, ok, Q);
+        if (st == NU_OK) st = run_inverse_mixed(ctx, ok, Q, prec);
       } else {
-        plan_inverse(ok, false, ctx->tuning, Q);
+        plan_inverse(ok, GK_F64, ctx->tuning, Q);
         st = plan_upload(ctx, Q);
         if (st == NU_OK) st = run_inverse_fp64(ctx, Q);
       }
@@ -261,7 +262,7 @@ nu_status nu_graph_create(nu_ctx* ctx, const double* t, int64_t n, const nu_sho*
   if (st != NU_OK) return st;
   st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (st != NU_OK) return st;
-  const bool mixed = prec == NU_FP32_REFINE;
+  const bool mixed = prec != NU_FP64;
 
   nu_graph* g = new (std::nothrow) nu_graph();
   if (!g) return set_error(ctx, NU_ERR_OOM, "graph_create: host allocation");
@@ -272,7 +273,7 @@ nu_status nu_graph_create(nu_ctx* ctx, const double* t, int64_t n, const nu_sho*
   };
   // every allocation happens before the capture
   st = factor_alloc(ctx, n, true, &g->F);
-  if (st == NU_OK && mixed) st = ensure_plan32(ctx, g->F);
+  if (st == NU_OK && mixed) st = ensure_plan32(ctx, g->F, prec);
   if (st == NU_OK)
     st = check_hip(ctx, hipMalloc(&g->ws, std::max(linear_ws_bytes(n, n_d, n_epochs), periodic_ws_bytes(n_d, n_epochs))),
                    "alloc graph workspace");
@@ -291,7 +292,7 @@ nu_status nu_graph_create(nu_ctx* ctx, const double* t, int64_t n, const nu_sho*
     std::vector<nu_factor*> one{F};
     nu_status cst = run_factor(ctx, one, F->plan64, {t}, {theta_dev});
     if (cst == NU_OK) cst = check_hip(ctx, launch_copy_i64(cs, F->status_dev(), status_dev), "status copy");
-    if (cst == NU_OK) cst = mixed ? run_inverse_mixed(ctx, one, F->plan32) : run_inverse_fp64(ctx, F->plan64);
+    if (cst == NU_OK) cst = mixed ? run_inverse_mixed(ctx, one, F->plan32, prec) : run_inverse_fp64(ctx, F->plan64);
     if (cst == NU_OK)
       cst = run_linear(ctx, F, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, mixed, depth, var, dll, valid,
                        null_out, g->ws);
@@ -340,7 +341,7 @@ nu_status nu_ctx_get_tuning(const nu_ctx* ctx, int launch_class, int* small_belo
 nu_status nu_ctx_set_tuning(nu_ctx* ctx, int launch_class, int small_below) {
   if (!ctx) return NU_ERR_ARG;
   if (launch_class < 0 || launch_class >= TC_COUNT || small_below < 0)
-    return set_error(ctx, NU_ERR_ARG, "set_tuning: class in [0, 6) and threshold >= 0 required");
+    return set_error(ctx, NU_ERR_ARG, "set_tuning: class in [0, 7) and threshold >= 0 required");
   ctx->tuning.small_below[launch_class] = small_below;
   return NU_OK;
 }
@@ -348,11 +349,11 @@ nu_status nu_ctx_set_tuning(nu_ctx* ctx, int launch_class, int small_below) {
 nu_status nu_ctx_autotune(nu_ctx* ctx, int64_t n, nu_precision prec) {
   if (!ctx) return NU_ERR_ARG;
   if (n < TB || n > (int64_t)1 << 17) return set_error(ctx, NU_ERR_ARG, "autotune: n must be in [128, 131072]");
-  if (prec != NU_FP64 && prec != NU_FP32_REFINE)
-    return set_error(ctx, NU_ERR_UNSUPPORTED, "autotune: precision not available in this build");
+  if (prec != NU_FP64 && prec != NU_FP32_REFINE && prec != NU_BF16X3_REFINE)
+    return set_error(ctx, NU_ERR_ARG, "autotune: unknown precision");
   nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (st != NU_OK) return st;
-  const bool mixed = prec == NU_FP32_REFINE;
+  const bool mixed = prec != NU_FP64;
   // a well-conditioned synthetic covariance on a unit-spaced grid
   std::vector<double> th(n);
   for (int64_t i = 0; i < n; ++i) th[i] = (double)i;
@@ -361,7 +362,7 @@ nu_status nu_ctx_autotune(nu_ctx* ctx, int64_t n, nu_precision prec) {
   st = check_hip(ctx, hipMalloc(&t_dev, n * sizeof(double)), "autotune alloc");
   if (st == NU_OK) st = check_hip(ctx, hipMemcpy(t_dev, th.data(), n * sizeof(double), hipMemcpyHostToDevice), "copy");
   if (st == NU_OK) st = factor_alloc(ctx, n, false, &F);
-  if (st == NU_OK && mixed) st = alloc_mixed(ctx, F);
+  if (st == NU_OK && mixed) st = alloc_mixed(ctx, F, prec);
   if (st == NU_OK) {
     F->theta_host = nu_sho{1.0, 0.3, 2.0, 0.5};
     st = check_hip(ctx, hipMemcpy(F->theta_dev(), &F->theta_host, sizeof(nu_sho), hipMemcpyHostToDevice), "copy");
@@ -386,11 +387,11 @@ nu_status nu_ctx_autotune(nu_ctx* ctx, int64_t n, nu_precision prec) {
     for (int c = 0; c < TC_COUNT; ++c) tu.small_below[c] = cand;
     Plan P, Q;
     plan_cholesky(one, tu, P);
-    plan_inverse(one, false, tu, P);
+    plan_inverse(one, GK_F64, tu, P);
     st = plan_upload(ctx, P);
     if (st == NU_OK && mixed) {
-      plan_inverse(one, true, tu, Q);
-      plan_band(one, tu, Q);
+      plan_inverse(one, gemm_kind_of(prec), tu, Q);
+      plan_band(one, band_width(prec), tu, Q);
       st = plan_upload(ctx, Q);
     }
     for (int rep = 0; st == NU_OK && rep < 2; ++rep) {  // the second repetition is the one kept
@@ -399,7 +400,7 @@ nu_status nu_ctx_autotune(nu_ctx* ctx, int64_t n, nu_precision prec) {
       ctx->timing = true;
       st = run_factor(ctx, one, P, {t_dev}, {F->theta_dev()});
       if (st == NU_OK) st = run_inverse_fp64(ctx, P);
-      if (st == NU_OK && mixed) st = run_inverse_mixed(ctx, one, Q);
+      if (st == NU_OK && mixed) st = run_inverse_mixed(ctx, one, Q, prec);
       resolve_timing(ctx);
       ctx->timing = false;
     }

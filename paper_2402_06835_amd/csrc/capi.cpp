@@ -304,14 +304,14 @@ nu_status nu_linear_search(nu_ctx* ctx, nu_factor* F, const double* f, const dou
   if (st != NU_OK) return st;
   st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (st != NU_OK) return st;
-  const bool mixed = prec == NU_FP32_REFINE;
+  const bool mixed = prec != NU_FP64;
 
   // triangular inverse X = L^-1 (kept in the factor for further searches)
-  const int want = mixed ? 2 : 1;
+  const int want = 1 + (int)prec;
   if (F->inverse_kind != want) {
     if (mixed) {
-      st = ensure_plan32(ctx, F);
-      if (st == NU_OK) st = run_inverse_mixed(ctx, {F}, F->plan32);
+      st = ensure_plan32(ctx, F, prec);
+      if (st == NU_OK) st = run_inverse_mixed(ctx, {F}, F->plan32, prec);
     } else {
       st = run_inverse_fp64(ctx, F->plan64);
     }

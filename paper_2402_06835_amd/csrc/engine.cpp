@@ -168,7 +168,8 @@ void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P)
 // Triangular inverse X = L^-1, bottom-up over a binary tree of the TB blocks:
 // for the node [[A, 0], [L21, C]], T = L21 X_A then X21 = -X_C T. Leaves are
 // the diagonal-block inverses. Level e of every factor runs in one launch.
-void plan_inverse(const std::vector<nu_factor*>& Fs, bool f32, const Tuning& tu, Plan& P) {
+void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu, Plan& P) {
+  const bool f32 = kind != GK_F64;  // the split-BF16 products run on the FP32 copies
   std::vector<std::vector<std::vector<Node>>> lv(Fs.size());
   size_t nlev = 0;
   for (size_t i = 0; i < Fs.size(); ++i) {
@@ -176,7 +177,7 @@ void plan_inverse(const std::vector<nu_factor*>& Fs, bool f32, const Tuning& tu,
     nlev = std::max(nlev, lv[i].size());
   }
   const size_t es = f32 ? sizeof(float) : sizeof(double);
-  const int cls = f32 ? TC_INV32 : TC_INV64;
+  const int cls = kind == GK_F64 ? TC_INV64 : kind == GK_F32 ? TC_INV32 : TC_INVB;
   P.t1.clear();
   P.t2.clear();
   for (size_t e = 0; e < nlev; ++e) {
@@ -214,13 +215,12 @@ size_t inverse_t_elems(int nblk) {
   return tmax;
 }
 
-// One Newton step X1 = 2 X - X (L X) on the blocks within BAND_W of the
+// One Newton step X1 = 2 X - X (L X) on the blocks within w of the
 // diagonal, FP64: P(I, J) = sum_{K=J..I} L(I, K) X(K, J) for I - J <= w, stored
 // by column block (the blocks P(J..J+w, J) stacked), then
 // X1(I, J) = 2 X(I, J) - sum_{K=J..I} X(I, K) P(K, J) for 1 <= I - J <= w, into
 // the band buffer (which holds X(I, J) on entry).
-void plan_band(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P) {
-  const int w = BAND_W;
+void plan_band(const std::vector<nu_factor*>& Fs, int w, const Tuning& tu, Plan& P) {
   const size_t es = sizeof(double);
   const int64_t bs = (int64_t)TB * TB;
   std::vector<GemmProblem> pp, px;
@@ -271,14 +271,15 @@ constexpr size_t ARENA_ALIGN = 256;
 size_t aligned(size_t b) { return (b + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN; }
 
 // device bytes of each buffer of a factor of n samples, in carving order
-std::vector<size_t> factor_buffer_bytes(int64_t n, bool mixed) {
+// (prec != NU_FP64: with the reduced-precision buffers, band sized for prec)
+std::vector<size_t> factor_buffer_bytes(int64_t n, int prec) {
   const int64_t np = round_up(n, TB);
   const int nblk = (int)(np / TB);
   std::vector<size_t> b = {(size_t)np * np * sizeof(double), (size_t)np * np * sizeof(double),
                            inverse_t_elems(nblk) * sizeof(double),
                            (size_t)(nblk + FACTOR_SMALL_EXTRA) * sizeof(double), sizeof(NullFit)};
-  if (mixed) {
-    const size_t band = (size_t)nblk * (BAND_W + 1) * TB * TB * sizeof(double);
+  if (prec != NU_FP64) {
+    const size_t band = (size_t)nblk * (band_width(prec) + 1) * TB * TB * sizeof(double);
     b.insert(b.end(), {(size_t)np * np * sizeof(float), (size_t)np * np * sizeof(float), band, band});
   }
   return b;
@@ -296,9 +297,9 @@ nu_factor* new_factor(nu_ctx* ctx, int64_t n) {
 }
 }  // namespace
 
-size_t factor_bytes(int64_t n, bool mixed) {
+size_t factor_bytes(int64_t n, int prec) {
   size_t s = 0;
-  for (size_t b : factor_buffer_bytes(n, mixed)) s += aligned(b);
+  for (size_t b : factor_buffer_bytes(n, prec)) s += aligned(b);
   return s;
 }
 
@@ -317,7 +318,7 @@ nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out) {
   if (st == NU_OK && own_plan) {
     std::vector<nu_factor*> one{F};
     plan_cholesky(one, ctx->tuning, F->plan64);
-    plan_inverse(one, false, ctx->tuning, F->plan64);
+    plan_inverse(one, GK_F64, ctx->tuning, F->plan64);
     st = plan_upload(ctx, F->plan64);
   }
   if (st != NU_OK) {
@@ -328,15 +329,16 @@ nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out) {
   return NU_OK;
 }
 
-// A factor whose buffers (and, if mixed, its reduced-precision buffers) are
-// carved from caller-owned device memory at *cursor (factor_bytes(n, mixed)
+// A factor whose buffers (and, for prec != NU_FP64, its reduced-precision buffers) are
+// carved from caller-owned device memory at *cursor (factor_bytes(n, prec)
 // bytes, 256-byte aligned); the factor does not free them.
-nu_status factor_place(nu_ctx* ctx, int64_t n, bool mixed, char** cursor, nu_factor** out) {
+nu_status factor_place(nu_ctx* ctx, int64_t n, int prec, char** cursor, nu_factor** out) {
   *out = nullptr;
   nu_factor* F = new_factor(ctx, n);
   if (!F) return set_error(ctx, NU_ERR_OOM, "factor: host allocation");
   F->owns_memory = false;
-  const std::vector<size_t> sz = factor_buffer_bytes(n, mixed);
+  const std::vector<size_t> sz = factor_buffer_bytes(n, prec);
+  if (prec != NU_FP64) F->band_w = band_width(prec);
   void** slots[] = {(void**)&F->L,  (void**)&F->X,   (void**)&F->T,     (void**)&F->small, (void**)&F->nullfit,
                     (void**)&F->L32, (void**)&F->X32, (void**)&F->bandP, (void**)&F->bandX};
   for (size_t i = 0; i < sz.size(); ++i) {
@@ -347,28 +349,49 @@ nu_status factor_place(nu_ctx* ctx, int64_t n, bool mixed, char** cursor, nu_fac
   return NU_OK;
 }
 
-// allocations of the reduced-precision inverse (first use only)
-nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F) {
-  if (F->L32) return NU_OK;
+// allocations of the reduced-precision inverse of precision prec (first use,
+// and the band buffers again when a wider band is asked for)
+nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F, int prec) {
+  const int w = band_width(prec);
+  if (F->L32 && F->band_w >= w) return NU_OK;
+  if (!F->owns_memory) return set_error(ctx, NU_ERR_ARG, "factor: placed without the reduced-precision buffers");
   const int64_t np = F->np;
-  const size_t band_elems = (size_t)F->nblk * (BAND_W + 1) * TB * TB;
-  nu_status st = check_hip(ctx, hipMalloc(&F->L32, (size_t)np * np * sizeof(float)), "alloc L32");
-  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->X32, (size_t)np * np * sizeof(float)), "alloc X32");
+  nu_status st = NU_OK;
+  if (!F->L32) {
+    st = check_hip(ctx, hipMalloc(&F->L32, (size_t)np * np * sizeof(float)), "alloc L32");
+    if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->X32, (size_t)np * np * sizeof(float)), "alloc X32");
+  }
+  if (st == NU_OK && F->bandP) {
+    st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "band realloc sync");
+    hipFree(F->bandP);
+    hipFree(F->bandX);
+    F->bandP = F->bandX = nullptr;
+    F->band_w = 0;
+  }
+  const size_t band_elems = (size_t)F->nblk * (w + 1) * TB * TB;
   if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->bandP, band_elems * sizeof(double)), "alloc band");
   if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->bandX, band_elems * sizeof(double)), "alloc band");
+  if (st == NU_OK) F->band_w = w;
   return st;
 }
 
-// the factor's own reduced-precision schedule (the FP32 level products reuse
-// the FP64 T workspace: the same element count fits)
-nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F) {
-  if (F->plan32.built) return NU_OK;
-  nu_status st = alloc_mixed(ctx, F);
+// the factor's own reduced-precision schedule for precision prec (the FP32
+// level products reuse the FP64 T workspace: the same element count fits)
+nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F, int prec) {
+  if (F->plan32.built && F->plan32_prec == prec) return NU_OK;
+  nu_status st = alloc_mixed(ctx, F, prec);
   if (st != NU_OK) return st;
+  if (F->plan32.built) {
+    st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "plan rebuild sync");
+    if (st != NU_OK) return st;
+    plan_release(F->plan32);
+  }
   std::vector<nu_factor*> one{F};
-  plan_inverse(one, true, ctx->tuning, F->plan32);
-  plan_band(one, ctx->tuning, F->plan32);
-  return plan_upload(ctx, F->plan32);
+  plan_inverse(one, gemm_kind_of(prec), ctx->tuning, F->plan32);
+  plan_band(one, band_width(prec), ctx->tuning, F->plan32);
+  st = plan_upload(ctx, F->plan32);
+  if (st == NU_OK) F->plan32_prec = prec;
+  return st;
 }
 
 void factor_free(nu_factor* F) {
@@ -387,10 +410,10 @@ void factor_free(nu_factor* F) {
 // ---------------------------------------------------------------------------
 // Enqueue sequences
 
-nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int f32) {
+nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int kind) {
   if (r.tiles == 0) return NU_OK;
   Timed tm(ctx, name, r.flops);
-  return check_hip(ctx, launch_gemm(ctx->stream, P.dprobs + r.first, r.count, r.tiles, f32, r.tile_m, r.tile_n),
+  return check_hip(ctx, launch_gemm(ctx->stream, P.dprobs + r.first, r.count, r.tiles, kind, r.tile_m, r.tile_n),
                    name);
 }
 
@@ -416,9 +439,9 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
       Timed tm(ctx, "potrf_diag", (double)P.job_count[k] * TB * TB * TB * 2.0 / 3.0);
       st = check_hip(ctx, launch_potrf_diag(ctx->stream, P.djobs + P.job_first[k], P.job_count[k]), "potrf_diag");
     }
-    if (st == NU_OK) st = launch_range(ctx, P, P.panel[k], "gemm_f64:panel", 0);
-    if (st == NU_OK) st = launch_range(ctx, P, P.pupd[k], "gemm_f64:panel_update", 0);
-    if (st == NU_OK) st = launch_range(ctx, P, P.trail[k], "gemm_f64:trailing", 0);
+    if (st == NU_OK) st = launch_range(ctx, P, P.panel[k], "gemm_f64:panel", GK_F64);
+    if (st == NU_OK) st = launch_range(ctx, P, P.pupd[k], "gemm_f64:panel_update", GK_F64);
+    if (st == NU_OK) st = launch_range(ctx, P, P.trail[k], "gemm_f64:trailing", GK_F64);
   }
   for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i)
     st = check_hip(ctx, launch_logdet_reduce(ctx->stream, Fs[i]->parts(), Fs[i]->nblk, Fs[i]->logdet_dev()),
@@ -446,26 +469,31 @@ nu_status read_factor_status(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, std
 nu_status run_inverse_fp64(nu_ctx* ctx, const Plan& P) {
   nu_status st = NU_OK;
   for (size_t l = 0; st == NU_OK && l < P.t1.size(); ++l) {
-    st = launch_range(ctx, P, P.t1[l], "gemm_f64:inverse", 0);
-    if (st == NU_OK) st = launch_range(ctx, P, P.t2[l], "gemm_f64:inverse", 0);
+    st = launch_range(ctx, P, P.t1[l], "gemm_f64:inverse", GK_F64);
+    if (st == NU_OK) st = launch_range(ctx, P, P.t2[l], "gemm_f64:inverse", GK_F64);
   }
   return st;
 }
 
-// FP32 doubling levels, then one FP64 Newton step on the blocks within
-// BAND_W of the diagonal. P holds the FP32 levels and the band products of
-// every factor in Fs (their mixed buffers allocated).
-nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P) {
+// Reduced-precision doubling levels (FP32, or split BF16 for
+// NU_BF16X3_REFINE), then one FP64 Newton step on the blocks within the
+// precision's band width of the diagonal. P holds the levels and the band
+// products of every factor in Fs (their reduced-precision buffers allocated
+// for prec).
+nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P, int prec) {
+  const int kind = gemm_kind_of(prec), w = band_width(prec);
+  const char* level_name = kind == GK_BF16X3 ? "gemm_bf16x3:inverse" : "gemm_f32:inverse";
   nu_status st = NU_OK;
   for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i) {
     nu_factor* F = Fs[i];
+    if (F->band_w < w) return set_error(ctx, NU_ERR_ARG, "inverse: band buffers narrower than the precision needs");
     Timed tm(ctx, "convert", 0.0);
     st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->L, F->L32, F->np, 0), "convert L");
     if (st == NU_OK) st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->X, F->X32, F->np, 1), "convert X diag");
   }
   for (size_t l = 0; st == NU_OK && l < P.t1.size(); ++l) {
-    st = launch_range(ctx, P, P.t1[l], "gemm_f32:inverse", 1);
-    if (st == NU_OK) st = launch_range(ctx, P, P.t2[l], "gemm_f32:inverse", 1);
+    st = launch_range(ctx, P, P.t1[l], level_name, kind);
+    if (st == NU_OK) st = launch_range(ctx, P, P.t2[l], level_name, kind);
   }
   for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i) {
     nu_factor* F = Fs[i];
@@ -473,12 +501,12 @@ nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, cons
       Timed tm(ctx, "convert", 0.0);
       st = check_hip(ctx, launch_cvt_f32_f64(ctx->stream, F->X32, F->X, F->np), "convert X");
     }
-    if (st == NU_OK) st = check_hip(ctx, launch_band_copy(ctx->stream, F->X, F->np, F->bandX, BAND_W, 1), "band copy");
+    if (st == NU_OK) st = check_hip(ctx, launch_band_copy(ctx->stream, F->X, F->np, F->bandX, w, 1), "band copy");
   }
-  if (st == NU_OK) st = launch_range(ctx, P, P.bandp, "gemm_f64:band", 0);
-  if (st == NU_OK) st = launch_range(ctx, P, P.bandx, "gemm_f64:band", 0);
+  if (st == NU_OK) st = launch_range(ctx, P, P.bandp, "gemm_f64:band", GK_F64);
+  if (st == NU_OK) st = launch_range(ctx, P, P.bandx, "gemm_f64:band", GK_F64);
   for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i)
-    st = check_hip(ctx, launch_band_copy(ctx->stream, Fs[i]->X, Fs[i]->np, Fs[i]->bandX, BAND_W, 0), "band copy");
+    st = check_hip(ctx, launch_band_copy(ctx->stream, Fs[i]->X, Fs[i]->np, Fs[i]->bandX, w, 0), "band copy");
   return st;
 }
 
@@ -512,8 +540,8 @@ nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double*
   for (int j = 0; j < n_d; ++j)
     if (dur_samples_host[j] < 1 || dur_samples_host[j] > MAX_DUR)
       return set_error(ctx, NU_ERR_ARG, "linear_search: durations must be in [1, 1024] slots");
-  if (prec != NU_FP64 && prec != NU_FP32_REFINE)
-    return set_error(ctx, NU_ERR_UNSUPPORTED, "linear_search: precision not available in this build");
+  if (prec != NU_FP64 && prec != NU_FP32_REFINE && prec != NU_BF16X3_REFINE)
+    return set_error(ctx, NU_ERR_ARG, "linear_search: unknown precision");
   return NU_OK;
 }
 

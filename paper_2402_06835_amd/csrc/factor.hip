@@ -160,9 +160,9 @@ __device__ void inverse_level(double (*a)[DPAD], const double* xd) {
 
 __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __restrict__ jobs) {
   const PotrfJob J = jobs[blockIdx.x];
-  double* __restrict__ L = J.L;
-  double* __restrict__ X = J.X;
-  int64_t* __restrict__ status = J.status;
+  NU_GLOBAL double* __restrict__ L = (NU_GLOBAL double*)J.L;
+  NU_GLOBAL double* __restrict__ X = (NU_GLOBAL double*)J.X;
+  NU_GLOBAL int64_t* __restrict__ status = (NU_GLOBAL int64_t*)J.status;
   const int64_t ld = J.ld, ldx = J.ld, off = J.off;
   __shared__ double a[DB][DPAD];
   __shared__ double xd[DB];
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __re
     double v = log(a[lane][lane]) + log(a[lane + 64][lane + 64]);
 #pragma unroll
     for (int offs = 32; offs > 0; offs >>= 1) v += __shfl_xor(v, offs, 64);
-    if (lane == 0) J.parts[J.step] = 2.0 * v;
+    if (lane == 0) ((NU_GLOBAL double*)J.parts)[J.step] = 2.0 * v;
   }
   for (int idx = tid; idx < DB * DB; idx += 256) {
     const int r = idx / DB, c = idx - (idx / DB) * DB;

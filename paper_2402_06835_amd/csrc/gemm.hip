@@ -1,5 +1,6 @@
-// Grouped GEMM on the gfx950 matrix cores, FP64 (v_mfma_f64_16x16x4_f64) and
-// FP32 (v_mfma_f32_16x16x4_f32).
+// Grouped GEMM on the gfx950 matrix cores, FP64 (v_mfma_f64_16x16x4_f64),
+// FP32 (v_mfma_f32_16x16x4_f32) and split BF16 (v_mfma_f32_16x16x32_bf16 on
+// FP32 data, see gemm_bf16x3_kernel).
 //
 // One launch runs a list of problems C = alpha * op(A) op(B) + beta * C; each
 // workgroup owns one 128 x 128 output tile of one problem (or, for launches
@@ -27,6 +28,7 @@ namespace nu {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef float flt2 __attribute__((ext_vector_type(2)));
 
 constexpr int GBK = 16;
 constexpr int LPAD = 4;
@@ -97,10 +99,10 @@ struct Mfma<float> {
 
 // E consecutive elements from global memory into registers, 16-byte loads
 template <typename T, int E>
-__device__ __forceinline__ void loadE(const T* p, T (&r)[E]) {
+__device__ __forceinline__ void loadE(const NU_GLOBAL T* p, T (&r)[E]) {
   constexpr int PER = 16 / sizeof(T);
   typedef T vec_t __attribute__((ext_vector_type(PER)));
-  const vec_t* v = reinterpret_cast<const vec_t*>(p);
+  const NU_GLOBAL vec_t* v = reinterpret_cast<const NU_GLOBAL vec_t*>(p);
 #pragma unroll
   for (int i = 0; i < E / PER; ++i) {
     const vec_t x = v[i];
@@ -152,10 +154,10 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
   // "row-major K x N -> [k][n]" pattern for B
   const int bk = tid / (BN / EB), bnc = (tid % (BN / EB)) * EB;
 
-  const T* A = static_cast<const T*>(P.A);
-  const T* B = static_cast<const T*>(P.B);
-  const T* Ap = A + (int64_t)(m0 + ar) * P.lda + akh;
-  const T* Bp = bt ? B + (int64_t)(n0 + br) * P.ldb + bkh : B + (int64_t)bk * P.ldb + n0 + bnc;
+  const NU_GLOBAL T* A = (const NU_GLOBAL T*)P.A;
+  const NU_GLOBAL T* B = (const NU_GLOBAL T*)P.B;
+  const NU_GLOBAL T* Ap = A + (int64_t)(m0 + ar) * P.lda + akh;
+  const NU_GLOBAL T* Bp = bt ? B + (int64_t)(n0 + br) * P.ldb + bkh : B + (int64_t)bk * P.ldb + n0 + bnc;
 
   T ra[EA], rb[EB];
   auto gload = [&](int k0) {
@@ -205,20 +207,207 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
   }
 
   const T alpha = (T)P.alpha, beta = (T)P.beta;
-  T* C = static_cast<T*>(P.C);
+  NU_GLOBAL T* C = (NU_GLOBAL T*)P.C + (int64_t)(m0 + wm) * P.ldc + n0 + wn + lr;
+  auto cptr = [&](int mi, int ni, int i) { return C + (int64_t)(mi * 16 + Mfma<T>::row(lk, i)) * P.ldc + ni * 16; };
+  if (beta != (T)0) {
+    // the loads of C of a row block all in flight before its stores (a store
+    // could alias a later load as far as the compiler knows, which would
+    // otherwise serialise every load behind the previous store)
 #pragma unroll
-  for (int mi = 0; mi < NBM; ++mi)
+    for (int mi = 0; mi < NBM; ++mi) {
+      T cv[NBN][4];
 #pragma unroll
-    for (int ni = 0; ni < NBN; ++ni)
+      for (int ni = 0; ni < NBN; ++ni)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = m0 + wm + mi * 16 + Mfma<T>::row(lk, i);
-        const int col = n0 + wn + ni * 16 + lr;
-        T* c = C + (int64_t)row * P.ldc + col;
-        T v = alpha * acc[mi][ni][i];
-        if (beta != (T)0) v = fma(beta, *c, v);
-        *c = v;
+        for (int i = 0; i < 4; ++i) cv[ni][i] = *cptr(mi, ni, i);
+#pragma unroll
+      for (int ni = 0; ni < NBN; ++ni)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) *cptr(mi, ni, i) = fma(beta, cv[ni][i], alpha * acc[mi][ni][i]);
+    }
+  } else {
+#pragma unroll
+    for (int mi = 0; mi < NBM; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < NBN; ++ni)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) *cptr(mi, ni, i) = alpha * acc[mi][ni][i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split BF16 products with FP32 accumulation. Every FP32 operand x is held as
+// hi + lo, hi = x rounded to BF16 and lo = (x - hi) rounded to BF16 (x - hi is
+// exact in FP32), which carries 16 of x's 24 significand bits; a product is
+// taken as lo_a hi_b + hi_a lo_b + hi_a hi_b, leaving out lo_a lo_b (2^-16
+// relative). One v_mfma_f32_16x16x32_bf16 covers 32 k at the BF16 rate, so
+// the three products cost about a fifth of the FP32 matrix-core time of
+// v_mfma_f32_16x16x4_f32. The relative error per product is ~2^-16 instead of
+// 2^-24; the triangular inverse built this way gets a wider FP64 band step.
+//
+// Operands are FP32 in memory (A row-major M x K, B row-major K x N; no G_BT
+// and no G_C_IS_A), split once while a slice is staged: LDS holds the hi and
+// lo halves k-contiguous per row of A and per column of B, so each lane
+// fetches its 8 k of a 16 x 16 x 32 operand with one 16-byte read (row stride
+// 80 bytes: the 16 rows of a quarter-wave fall on disjoint banks). A and B
+// take k in the same lane order, which is all the product needs.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int SBK = 32;        // k depth of a slice: one MFMA
+constexpr int SROW = SBK + 8;  // LDS row stride in BF16 elements
+
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(x[e] - (float)h);
+  }
+}
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const GemmProblem* __restrict__ probs, int nprob) {
+  constexpr int NBM = BM / 32, NBN = BN / 32;  // MFMA blocks per wave sub-tile
+  constexpr int EA = BM * SBK / 256;           // A elements per thread and slice: one row segment
+  constexpr int APR = SBK / EA;                // threads per A row
+  constexpr int NBC = BN / 64;                 // B columns per thread (8 k each)
+  constexpr int BCT = BN / NBC;                // threads across the B columns
+  static_assert(EA % 8 == 0 && 256 / BCT * 8 == SBK, "staging layout");
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][SROW];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][SROW];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][SROW];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN][SROW];
+
+  const int tile = blockIdx.x;
+  int lo_p = 0, hi_p = nprob - 1;  // last problem with tile_begin <= tile
+  while (lo_p < hi_p) {
+    const int mid = (lo_p + hi_p + 1) >> 1;
+    if (probs[mid].tile_begin <= tile) lo_p = mid; else hi_p = mid - 1;
+  }
+  const GemmProblem P = probs[lo_p];
+  int tm, tn;
+  tile_of<BM>(P, tile - P.tile_begin, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  int kb = 0, ke = P.K;
+  if (P.flags & G_A_LOWER) ke = min(ke, m0 + BM);
+  if (P.flags & G_B_LOWER) kb = max(kb, n0);
+  if (P.flags & G_B_UPPER) ke = min(ke, n0 + BN);
+  const int nk = ke > kb ? (ke - kb) / SBK : 0;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int lr = lane & 15, lg = lane >> 4;
+
+  const int ar = tid / APR, ak = (tid % APR) * EA;         // A: one row, EA consecutive k
+  const int bc = (tid % BCT) * NBC, bk = (tid / BCT) * 8;  // B: NBC columns, 8 consecutive k
+  const NU_GLOBAL float* Ap = (const NU_GLOBAL float*)P.A + (int64_t)(m0 + ar) * P.lda + ak;
+  const NU_GLOBAL float* Bp = (const NU_GLOBAL float*)P.B + (int64_t)bk * P.ldb + n0 + bc;
+
+  float ra[EA], rb[NBC][8];
+  auto gload = [&](int k0) {
+    loadE<float, EA>(Ap + k0, ra);
+    const NU_GLOBAL float* b = Bp + (int64_t)k0 * P.ldb;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if constexpr (NBC == 2) {
+        const flt2 v = *reinterpret_cast<const NU_GLOBAL flt2*>(b + (int64_t)r * P.ldb);
+        rb[0][r] = v[0];
+        rb[1][r] = v[1];
+      } else {
+        rb[0][r] = b[(int64_t)r * P.ldb];
       }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < EA / 8; ++h) {
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = ra[h * 8 + e];
+      bf16x8 vh, vl;
+      split8(x, vh, vl);
+      *reinterpret_cast<bf16x8*>(&Ah[buf][ar][ak + h * 8]) = vh;
+      *reinterpret_cast<bf16x8*>(&Al[buf][ar][ak + h * 8]) = vl;
+    }
+#pragma unroll
+    for (int c = 0; c < NBC; ++c) {
+      bf16x8 vh, vl;
+      split8(rb[c], vh, vl);
+      *reinterpret_cast<bf16x8*>(&Bh[buf][bc + c][bk]) = vh;
+      *reinterpret_cast<bf16x8*>(&Bl[buf][bc + c][bk]) = vl;
+    }
+  };
+
+  flt4 acc[NBM][NBN];
+#pragma unroll
+  for (int i = 0; i < NBM; ++i)
+#pragma unroll
+    for (int j = 0; j < NBN; ++j) acc[i][j] = flt4{0, 0, 0, 0};
+
+  if (nk > 0) {
+    gload(kb);
+    lstore(0);
+    __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+      const int buf = it & 1;
+      if (it + 1 < nk) gload(kb + (it + 1) * SBK);
+      bf16x8 ah[NBM], al[NBM], bh[NBN], bl[NBN];
+#pragma unroll
+      for (int mi = 0; mi < NBM; ++mi) {
+        ah[mi] = *reinterpret_cast<const bf16x8*>(&Ah[buf][wm + mi * 16 + lr][lg * 8]);
+        al[mi] = *reinterpret_cast<const bf16x8*>(&Al[buf][wm + mi * 16 + lr][lg * 8]);
+      }
+#pragma unroll
+      for (int ni = 0; ni < NBN; ++ni) {
+        bh[ni] = *reinterpret_cast<const bf16x8*>(&Bh[buf][wn + ni * 16 + lr][lg * 8]);
+        bl[ni] = *reinterpret_cast<const bf16x8*>(&Bl[buf][wn + ni * 16 + lr][lg * 8]);
+      }
+      // small terms first; each pass is NBM * NBN independent accumulations
+#pragma unroll
+      for (int mi = 0; mi < NBM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < NBN; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+      for (int mi = 0; mi < NBM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < NBN; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+      for (int mi = 0; mi < NBM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < NBN; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+      if (it + 1 < nk) lstore(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  // accumulator of a 16 x 16 block: lane (lr, lg) holds column lr, rows 4 lg .. 4 lg + 3
+  const float alpha = (float)P.alpha, beta = (float)P.beta;
+  NU_GLOBAL float* C = (NU_GLOBAL float*)P.C + (int64_t)(m0 + wm) * P.ldc + n0 + wn + lr;
+  auto cptr = [&](int mi, int ni, int i) { return C + (int64_t)(mi * 16 + 4 * lg + i) * P.ldc + ni * 16; };
+  if (beta != 0.0f) {
+#pragma unroll
+    for (int mi = 0; mi < NBM; ++mi) {
+      float cv[NBN][4];
+#pragma unroll
+      for (int ni = 0; ni < NBN; ++ni)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) cv[ni][i] = *cptr(mi, ni, i);
+#pragma unroll
+      for (int ni = 0; ni < NBN; ++ni)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) *cptr(mi, ni, i) = fmaf(beta, cv[ni][i], alpha * acc[mi][ni][i]);
+    }
+  } else {
+#pragma unroll
+    for (int mi = 0; mi < NBM; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < NBN; ++ni)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) *cptr(mi, ni, i) = alpha * acc[mi][ni][i];
+  }
 }
 
 template <typename T>
@@ -229,14 +418,23 @@ void launch_typed(hipStream_t s, const GemmProblem* dprobs, int nprob, dim3 g, i
   else hipLaunchKernelGGL((gemm_kernel<T, 128, 128>), g, b, 0, s, dprobs, nprob);
 }
 
-hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32, int tile_m,
+hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int kind, int tile_m,
                        int tile_n) {
   if (total_tiles <= 0) return hipSuccess;
   if (!((tile_m == 128 && tile_n == 128) || (tile_m == 64 && (tile_n == 64 || tile_n == 128))))
     return hipErrorInvalidValue;
-  const dim3 g((unsigned)total_tiles);
-  if (f32) launch_typed<float>(s, dprobs, nprob, g, tile_m, tile_n);
-  else launch_typed<double>(s, dprobs, nprob, g, tile_m, tile_n);
+  const dim3 g((unsigned)total_tiles), b(256);
+  switch (kind) {
+    case GK_F64: launch_typed<double>(s, dprobs, nprob, g, tile_m, tile_n); break;
+    case GK_F32: launch_typed<float>(s, dprobs, nprob, g, tile_m, tile_n); break;
+    case GK_BF16X3:
+      // square tiles only (64 x 128 serves the in-place panels, which this kind never runs)
+      if (tile_m != tile_n) return hipErrorInvalidValue;
+      if (tile_m == 64) hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 64>), g, b, 0, s, dprobs, nprob);
+      else hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128>), g, b, 0, s, dprobs, nprob);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

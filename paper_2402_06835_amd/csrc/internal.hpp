@@ -16,6 +16,13 @@ namespace nu {
 // TB (identity on the padded diagonal), every GEMM problem is a multiple of
 // TB in M and N, and the diagonal blocks factored in LDS are TB x TB.
 constexpr int TB = 128;
+
+// Device pointers read out of a problem or job record are generic (flat)
+// pointers to the compiler, and a flat load also counts against the LDS wait
+// counter: every wait for an LDS read in a k loop would then wait for the
+// global loads of the next slice too. Kernels cast such pointers to the global
+// address space, which gives global_load / global_store.
+#define NU_GLOBAL __attribute__((address_space(1)))
 constexpr int MAX_M1 = 7;        // trend columns
 constexpr int YCOLS = 8;         // row stride of the whitened [A | f] panel
 constexpr int MAX_ND = 16;       // durations per search
@@ -53,10 +60,24 @@ struct GemmProblem {
 
 // Launch classes of the dense schedule. Each class takes 64 x 64 output tiles
 // when a launch has fewer 128 x 128 tiles than its threshold.
-enum TuneClass { TC_PANEL = 0, TC_PUPD, TC_TRAIL, TC_INV64, TC_INV32, TC_BAND, TC_COUNT };
+enum TuneClass { TC_PANEL = 0, TC_PUPD, TC_TRAIL, TC_INV64, TC_INV32, TC_BAND, TC_INVB, TC_COUNT };
 struct Tuning {
-  int small_below[TC_COUNT] = {512, 512, 512, 512, 512, 512};
+  int small_below[TC_COUNT] = {512, 512, 512, 512, 512, 512, 512};
 };
+
+// Arithmetic of a grouped GEMM launch: FP64, FP32, or split BF16 products on
+// FP32 data (hi + lo halves, three products, FP32 accumulation).
+enum GemmKind { GK_F64 = 0, GK_F32 = 1, GK_BF16X3 = 2 };
+
+// Block diagonals refined in FP64 after a reduced-precision inverse: the
+// split-BF16 products leave ~2^-16 relative error where FP32 leaves 2^-24, so
+// more of the near-diagonal weight of the box sums is restored in FP64.
+constexpr int BAND_W_F32 = 2;
+constexpr int BAND_W_BF16X3 = 8;
+inline int band_width(int prec) { return prec == NU_BF16X3_REFINE ? BAND_W_BF16X3 : BAND_W_F32; }
+inline int gemm_kind_of(int prec) {
+  return prec == NU_BF16X3_REFINE ? GK_BF16X3 : prec == NU_FP32_REFINE ? GK_F32 : GK_F64;
+}
 
 struct NullFit {
   double G0chol[MAX_M1 * MAX_M1];  // lower Cholesky factor of A^T K^-1 A
@@ -109,7 +130,6 @@ struct Range {
   int tile_m = TB, tile_n = TB;  // output tile of the launch: 128 x 128, 64 x 64 or 64 x 128
   double flops = 0.0;
 };
-constexpr int BAND_W = 2;  // block diagonals refined after a reduced-precision inverse
 
 // One diagonal block of the blocked Cholesky (one workgroup of a launch).
 struct PotrfJob {
@@ -159,8 +179,10 @@ struct nu_factor {
   float* X32 = nullptr;
   double* bandP = nullptr;   // (I, d) blocks of L X on the band, stored by column block
   double* bandX = nullptr;   // refined band blocks
-  nu::Plan plan32;           // FP32 inverse + FP64 band step
-  int inverse_kind = 0;  // 0 none, 1 FP64, 2 FP32 levels + refinement
+  int band_w = 0;            // widest band the band buffers hold
+  nu::Plan plan32;           // reduced-precision inverse + FP64 band step
+  int plan32_prec = 0;       // the nu_precision plan32 was built for
+  int inverse_kind = 0;  // 0 none, else 1 + the nu_precision X was formed in
   double logdet = 0.0;
   bool owns_memory = true;   // false: buffers carved from the context's arena
   double* parts() const { return small; }
@@ -202,23 +224,23 @@ struct HostTimed {
 
 // engine (engine.cpp)
 void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P);
-void plan_inverse(const std::vector<nu_factor*>& Fs, bool f32, const Tuning& tu, Plan& P);
-void plan_band(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P);
+void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu, Plan& P);
+void plan_band(const std::vector<nu_factor*>& Fs, int w, const Tuning& tu, Plan& P);
 size_t inverse_t_elems(int nblk);
 nu_status plan_upload(nu_ctx* ctx, Plan& P);
-size_t factor_bytes(int64_t n, bool mixed);
+size_t factor_bytes(int64_t n, int prec);
 nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out);
-nu_status factor_place(nu_ctx* ctx, int64_t n, bool mixed, char** cursor, nu_factor** out);
+nu_status factor_place(nu_ctx* ctx, int64_t n, int prec, char** cursor, nu_factor** out);
 void* ctx_arena(nu_ctx* ctx, size_t bytes, nu_status* st);
-nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F);
-nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F);
+nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F, int prec);
+nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F, int prec);
 void factor_free(nu_factor* F);
-nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int f32);
+nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int kind);
 nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P,
                      const std::vector<const double*>& ts, const std::vector<const nu_sho*>& theta_dev);
 nu_status read_factor_status(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, std::vector<int64_t>& status);
 nu_status run_inverse_fp64(nu_ctx* ctx, const Plan& P);
-nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P);
+nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P, int prec);
 size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs);
 nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double* A, int m1, const int64_t* lattice,
                           int64_t n_epochs, const int32_t* dur_samples_host, int n_d, nu_precision prec,
@@ -236,7 +258,7 @@ nu_status validate_theta(nu_ctx* ctx, const nu_sho* theta);
 
 // launchers (*.hip)
 hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho* th_dev, double* K);
-hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int f32, int tile_m,
+hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int kind, int tile_m,
                        int tile_n);
 hipError_t launch_potrf_diag(hipStream_t s, const PotrfJob* jobs, int njobs);
 hipError_t launch_copy_i64(hipStream_t s, const int64_t* src, int64_t* dst);

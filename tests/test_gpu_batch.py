@@ -85,7 +85,7 @@ def _assert_same(a, b, tag):
     assert a["best_index"] == b["best_index"], tag
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "bf16x3_refine"])
 def test_batch_equals_single_curve_calls(api, ctx, precision):
     import torch
     ws = _curves()
@@ -168,7 +168,7 @@ def test_batch_not_positive_definite_curve(api, ctx):
         np.testing.assert_array_equal(res["periods"][c]["q_snr"].cpu().numpy(), single["q_snr"])
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "bf16x3_refine"])
 def test_graph_replays_match_eager(api, ctx, precision):
     import torch
     w = _curve(700, 41, 1.2, gap=(333, 25))
@@ -213,7 +213,7 @@ def test_graph_reports_not_pd_without_sync(api, ctx):
     g.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "bf16x3_refine"])
 def test_tile_policy_does_not_change_results(api, ctx, precision):
     from paper_2402_06835_amd._lib import TUNE_CLASSES
     w = _curve(1000, 51, 1.3, gap=(400, 30))

@@ -333,19 +333,21 @@ def assert_linear_close_tol(gpu, ref, tol, tag=""):
     return errs
 
 
+@pytest.mark.parametrize("precision", ["fp32_refine", "bf16x3_refine"])
 @pytest.mark.parametrize("name,kw", [("N700-m3-gap", dict(n=700, m1=3, durs=[1, 4, 9, 17], gap=(333, 25))),
-                                     ("N1000-m3", dict(n=1000, m1=3, durs=[3, 9, 20], seed=4))],
-                         ids=["N700-m3-gap", "N1000-m3"])
-def test_linear_search_fp32_refine_parity(api, ctx, name, kw):
+                                     ("N1000-m3", dict(n=1000, m1=3, durs=[3, 9, 20], seed=4)),
+                                     ("N2300-m2-gap", dict(n=2300, m1=2, durs=[5, 30, 90], gap=(1500, 120), seed=6))],
+                         ids=["N700-m3-gap", "N1000-m3", "N2300-m2-gap"])
+def test_linear_search_reduced_precision_parity(api, ctx, name, kw, precision):
     import torch
     w = _case(**kw)
-    say(f"fp32_refine {name}: N={w.n}")
+    say(f"{precision} {name}: N={w.n}")
     fac = api.gp_factor(ctx, w.t, w.theta)
-    ls = api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations, precision="fp32_refine")
+    ls = api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations, precision=precision)
     torch.cuda.synchronize()
     L = ogp.cholesky(ogp.covariance(w.t, w.theta))
     ref = olin.linear_search(w.f, w.A, L, w.lattice, w.durations)
-    assert_linear_close_tol(_host(ls), ref, MIXED_TOL, f"fp32_refine {name}")
+    assert_linear_close_tol(_host(ls), ref, MIXED_TOL, f"{precision} {name}")
 
 
 def test_precision_switch_and_factor_reuse(api, ctx):
@@ -357,11 +359,15 @@ def test_precision_switch_and_factor_reuse(api, ctx):
     a = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations))
     b = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations, precision="fp32_refine"))
     c = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations))
+    d = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations, precision="bf16x3_refine"))
+    e = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations, precision="fp32_refine"))
     torch.cuda.synchronize()
     for k in a:
         np.testing.assert_array_equal(a[k], c[k])  # back to FP64: identical to the first FP64 run
+        np.testing.assert_array_equal(b[k], e[k])  # FP32 after BF16 (wider band kept): identical
     v = a["valid"].astype(bool)
-    assert np.max(np.abs(b["dll"][v] - a["dll"][v]) / np.maximum(np.abs(a["dll"][v]), 1)) < MIXED_TOL
+    for r in (b, d):
+        assert np.max(np.abs(r["dll"][v] - a["dll"][v]) / np.maximum(np.abs(a["dll"][v]), 1)) < MIXED_TOL
     # refill the same factor with another curve: same results as a fresh factor
     api.gp_factor(ctx, w2.t, w2.theta, out=fac)
     r1 = _host(api.linear_search(ctx, fac, w2.f, w2.A, w2.lattice, w2.n_epochs, w2.durations))
@@ -372,23 +378,29 @@ def test_precision_switch_and_factor_reuse(api, ctx):
         np.testing.assert_array_equal(r1[k], r2[k])
 
 
-def test_full_size_fp32_refine_sampled(api, ctx):
+def test_full_size_reduced_precision_sampled(api, ctx):
     import torch
     w = config2()
-    say(f"full-size fp32_refine N={w.n}")
+    say(f"full-size reduced precision N={w.n}")
     fac = api.gp_factor(ctx, w.t, w.theta)
-    ls = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations, precision="fp32_refine"))
     ls64 = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations))
+    got = {}
+    for prec in ("fp32_refine", "bf16x3_refine"):
+        got[prec] = _host(api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations, precision=prec))
     torch.cuda.synchronize()
     v = ls64["valid"].astype(bool)
-    e_all = np.abs(ls["dll"][v] - ls64["dll"][v]) / np.maximum(np.abs(ls64["dll"][v]), 1.0)
-    say(f"fp32_refine vs fp64 (all {v.sum()} cells): max {e_all.max():.2e} p99.9 {np.quantile(e_all, 0.999):.2e}")
+    e_all = {}
+    for prec, ls in got.items():
+        e_all[prec] = np.abs(ls["dll"][v] - ls64["dll"][v]) / np.maximum(np.abs(ls64["dll"][v]), 1.0)
+        say(f"{prec} vs fp64 (all {v.sum()} cells): max {e_all[prec].max():.2e} "
+            f"p99.9 {np.quantile(e_all[prec], 0.999):.2e}")
     say("oracle Cholesky at N=18000 (CPU)")
     L = ogp.cholesky(ogp.covariance(w.t, w.theta))
     rng = np.random.default_rng(7)
-    n_d, n_t = ls["dll"].shape
+    n_d, n_t = ls64["dll"].shape
     cells = [(int(rng.integers(n_d)), int(rng.integers(n_t))) for _ in range(100)]
     ref = olin.linear_search(w.f, w.A, L, w.lattice, w.durations, cells=cells)
-    sel = {k: np.array([ls[k][j, i] for (j, i) in cells]) for k in ls}
-    assert_linear_close_tol(sel, ref, MIXED_TOL, "full-size fp32_refine sampled")
-    assert e_all.max() <= MIXED_TOL
+    for prec, ls in got.items():
+        sel = {k: np.array([ls[k][j, i] for (j, i) in cells]) for k in ls}
+        assert_linear_close_tol(sel, ref, MIXED_TOL, f"full-size {prec} sampled")
+        assert e_all[prec].max() <= MIXED_TOL, prec
