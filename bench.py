@@ -149,12 +149,33 @@ def measured_traffic(roof, workload, precision):
     return rec["bytes_per_launch"]
 
 
-def dll_error(dll, dll_ref, valid_ref):
+def _stats(err):
     import torch
-    v = valid_ref.bool()
-    ref = dll_ref[v]
-    err = (dll[v] - ref).abs() / ref.abs().clamp(min=1.0)
-    return {"max": float(err.max().item()), "p999": float(torch.quantile(err.float(), 0.999).item())}
+    if err.numel() == 0:
+        return {"max": 0.0, "p999": 0.0}
+    e = err.float()
+    if e.numel() > 1 << 24:  # quantile's input limit
+        e = e[torch.randperm(e.numel(), device=e.device)[:1 << 24]]
+    return {"max": float(err.max().item()), "p999": float(torch.quantile(e, 0.999).item())}
+
+
+def output_errors(got, ref):
+    """Per-output error of a reduced-precision search against the FP64 path on the same inputs:
+    dll relative to max(|dll|, 1), depth in units of its FP64 sigma, var relative, the per-period
+    SNR relative to max(|SNR|, 1), and how many per-period best (phase, duration) picks agree."""
+    import torch
+    v = ref["valid"].bool()
+    out = {"dll": _stats((got["dll"][v] - ref["dll"][v]).abs() / ref["dll"][v].abs().clamp(min=1.0)),
+           "depth": _stats((got["depth"][v] - ref["depth"][v]).abs() / ref["var"][v].sqrt()),
+           "var": _stats((got["var"][v] - ref["var"][v]).abs() / ref["var"][v])}
+    out["valid_same"] = bool(torch.equal(got["valid"], ref["valid"]))
+    if "q_snr" in ref:
+        ok = ref["best_phase"] >= 0
+        q, qr = got["q_snr"][ok], ref["q_snr"][ok]
+        out["q_snr"] = _stats((q - qr).abs() / qr.abs().clamp(min=1.0))
+        same = (got["best_phase"][ok] == ref["best_phase"][ok]) & (got["best_dur"][ok] == ref["best_dur"][ok])
+        out["best_cell_same"] = f"{int(same.sum().item())}/{int(ok.sum().item())}"
+    return out
 
 
 def bench_batch(args, api, ctx, torch):
@@ -209,8 +230,8 @@ def bench_batch(args, api, ctx, torch):
     dll_err = None
     if args.precision != "fp64" and not args.no_dll_check:
         ref = api.search_batch(ctx, batch, durs, per, precision="fp64")
-        dll_err = dll_error(res["dll"], ref["dll"], ref["valid"])
-        log(f"dll error vs fp64: {dll_err}")
+        dll_err = output_errors(res, ref)
+        log(f"errors vs fp64: {dll_err}")
     best = res["best_index"].cpu().numpy()
     found = sum(1 for c, w in enumerate(ws) if w.injection and best[c] >= 0 and
                 abs(periods[best[c]] - w.injection["period"]) < 0.01 * w.injection["period"])
@@ -343,18 +364,23 @@ def bench_curve(args, api, ctx, torch):
     ctx.enable_timing(False)
     if g is None:
         fac, ls, ps = keep
-        valid, dll, best = ls["valid"], ls["dll"], int(ps["best_index"].item())
+        got = dict(ls)
+        got.update(ps)
     else:
         assert int(g.status.item()) == -1
-        valid, dll, best = g.out["valid"], g.out["dll"], int(g.out["best_index"].item())
+        got = g.out
         fac = api.gp_factor(ctx, dev_in["t"], w.theta)
+    valid, best = got["valid"], int(got["best_index"].item())
     n_valid = int(valid.sum().item())
     dll_err = None
     if args.precision != "fp64" and not args.no_dll_check:
         # accuracy of this precision against the FP64 path on the same curve (outside the timed region)
-        ls64 = api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations)
-        dll_err = dll_error(dll, ls64["dll"], ls64["valid"])
-        log(f"dll error vs fp64: {dll_err}")
+        ref = dict(api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs,
+                                     w.durations))
+        ref.update(api.periodic_search(ctx, ref["depth"], ref["var"], ref["dll"], ref["valid"], w.dt,
+                                       dev_in["periods"]))
+        dll_err = output_errors(got, ref)
+        log(f"errors vs fp64: {dll_err}")
     log(f"{args.steps} steps in {elapsed:.3f} s: {n_valid * args.steps / elapsed:.4g} fits/s, "
         f"{args.steps / elapsed:.4g} curves/s; best period {w.periods[best] if best >= 0 else None}")
     cfg = {"workload": w.name, "n_samples": w.n, "n_epochs": w.n_epochs, "n_durations": int(w.durations.size),
@@ -442,7 +468,7 @@ def main(argv=None):
         "dtype": {"fp64": "f64", "fp32_refine": "f64+f32", "bf16x3_refine": "f64+bf16x3"}[args.precision], "data": "synthetic",
         "config": cfg,
         "light_curves_per_s": curves * args.steps / elapsed,
-        "dll_err_vs_fp64": dll_err,
+        "errors_vs_fp64": dll_err,
         "gemm_by_type": {k: {"tflops": v["tflops"], "ms_per_step": v["ms"] / args.steps} for k, v in gemms.items()}
         if gemms else None,
         "roofline": roof,

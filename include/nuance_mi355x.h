@@ -57,9 +57,13 @@ typedef enum {
  *                   matrix cores: each FP32 operand held as hi + lo BF16
  *                   halves, three products (lo*hi, hi*lo, hi*hi) with FP32
  *                   accumulation; the same FP64 Newton step on a band of 8
- *                   block diagonals (FP32_REFINE: 2) and the same refinement
- *                   of the small solves. The factor then holds wider band
- *                   buffers: 2 x 9 x 128 n doubles (FP32_REFINE: 2 x 3 x 128 n). */
+ *                   block diagonals (FP32_REFINE: 2) and two steps of the
+ *                   refinement of the small solves (FP32_REFINE: one). The
+ *                   factor then holds wider band buffers: 2 x 9 x 128 n
+ *                   doubles (FP32_REFINE: 2 x 3 x 128 n). Outputs within
+ *                   ~1e-8 of FP64 on a TESS-sector curve, but up to a few
+ *                   1e-6 on dll for curves whose L^-1 decays slowly (strong,
+ *                   long-period variability over white noise). */
 typedef enum {
   NU_FP64 = 0,
   NU_FP32_REFINE = 1,

@@ -30,7 +30,7 @@ struct nu_graph {
 namespace {
 
 nu_status fail_batch(nu_ctx* ctx, std::vector<nu_factor*>& Fs, Plan* P, Plan* Q, nu_status st) {
-  hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
   if (P) plan_release(*P);
   if (Q) plan_release(*Q);
   for (nu_factor* F : Fs) factor_free(F);
@@ -221,7 +221,7 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
         continue;
       }
       st = run_linear(ctx, Fs[i], f + s0, m1 > 0 ? A + (int64_t)m1 * s0 : nullptr, m1, lattice + s0, ne,
-                      dur_samples_host, n_d, mixed, depth + cells, var + cells, dll + cells, valid + cells,
+                      dur_samples_host, n_d, prec, depth + cells, var + cells, dll + cells, valid + cells,
                       null_out ? null_out + 3 * (int64_t)c : nullptr, ws);
       if (st == NU_OK)
         st = run_periodic(ctx, depth + cells, var + cells, dll + cells, valid + cells, n_d, ne, dt_host[c],
@@ -294,7 +294,7 @@ nu_status nu_graph_create(nu_ctx* ctx, const double* t, int64_t n, const nu_sho*
     if (cst == NU_OK) cst = check_hip(ctx, launch_copy_i64(cs, F->status_dev(), status_dev), "status copy");
     if (cst == NU_OK) cst = mixed ? run_inverse_mixed(ctx, one, F->plan32, prec) : run_inverse_fp64(ctx, F->plan64);
     if (cst == NU_OK)
-      cst = run_linear(ctx, F, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, mixed, depth, var, dll, valid,
+      cst = run_linear(ctx, F, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, prec, depth, var, dll, valid,
                        null_out, g->ws);
     if (cst == NU_OK)
       cst = run_periodic(ctx, depth, var, dll, valid, n_d, n_epochs, dt, periods, n_p, log_term_sign, q_snr,
@@ -304,7 +304,7 @@ nu_status nu_graph_create(nu_ctx* ctx, const double* t, int64_t n, const nu_sho*
   }
   ctx->stream = saved_stream;
   ctx->timing = saved_timing;
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (st == NU_OK) st = check_hip(ctx, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0), "instantiate");
   if (st != NU_OK) return fail(st);
   *out = g;
@@ -322,11 +322,11 @@ nu_status nu_graph_launch(nu_ctx* ctx, nu_graph* g) {
 
 void nu_graph_destroy(nu_graph* g) {
   if (!g) return;
-  hipSetDevice(g->device);
-  hipDeviceSynchronize();
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
-  if (g->ws) hipFree(g->ws);
+  (void)hipSetDevice(g->device);
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->ws) (void)hipFree(g->ws);
   factor_free(g->F);
   delete g;
 }
@@ -412,7 +412,7 @@ nu_status nu_ctx_autotune(nu_ctx* ctx, int64_t n, nu_precision prec) {
           best_thr[c] = cand;
         }
       }
-    hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(ctx->stream);
     plan_release(P);
     plan_release(Q);
   }
@@ -420,7 +420,7 @@ nu_status nu_ctx_autotune(nu_ctx* ctx, int64_t n, nu_precision prec) {
   ctx->timings = saved_timings;
   ctx->timing_names = saved_names;
   factor_free(F);
-  if (t_dev) hipFree(t_dev);
+  if (t_dev) (void)hipFree(t_dev);
   if (st != NU_OK) return st;
   for (int c = 0; c < TC_COUNT; ++c) ctx->tuning.small_below[c] = best_thr[c];
   return NU_OK;

@@ -69,7 +69,7 @@ void timing_begin(nu_ctx* ctx, hipStream_t s, hipEvent_t* start) {
   }
   *start = ctx->free_events.back();
   ctx->free_events.pop_back();
-  hipEventRecord(*start, s);
+  (void)hipEventRecord(*start, s);
 }
 
 void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, double work) {
@@ -81,7 +81,7 @@ void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, 
     stop = ctx->free_events.back();
     ctx->free_events.pop_back();
   }
-  hipEventRecord(stop, s);
+  (void)hipEventRecord(stop, s);
   ctx->pending.push_back({name, start, stop, work});
 }
 
@@ -105,10 +105,10 @@ HostTimed::~HostTimed() {
 
 void resolve_timing(nu_ctx* ctx) {
   if (ctx->pending.empty()) return;
-  hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
   for (auto& p : ctx->pending) {
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, p.start, p.stop);
+    (void)hipEventElapsedTime(&ms, p.start, p.stop);
     auto it = ctx->timings.find(p.name);
     if (it == ctx->timings.end()) {
       ctx->timing_names.push_back(p.name);
@@ -182,15 +182,15 @@ nu_status nu_ctx_create(int device, void* stream, nu_ctx** out) {
 
 void nu_ctx_destroy(nu_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
-  if (ctx->ws) hipFree(ctx->ws);
-  if (ctx->arena) hipFree(ctx->arena);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->arena) (void)hipFree(ctx->arena);
   for (auto& p : ctx->pending) {
-    hipEventDestroy(p.start);
-    hipEventDestroy(p.stop);
+    (void)hipEventDestroy(p.start);
+    (void)hipEventDestroy(p.stop);
   }
-  for (auto e : ctx->free_events) hipEventDestroy(e);
+  for (auto e : ctx->free_events) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -199,8 +199,8 @@ nu_status nu_ctx_release_memory(nu_ctx* ctx) {
   nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (st == NU_OK) st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "release sync");
   if (st != NU_OK) return st;
-  if (ctx->ws) hipFree(ctx->ws);
-  if (ctx->arena) hipFree(ctx->arena);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->arena) (void)hipFree(ctx->arena);
   ctx->ws = ctx->arena = nullptr;
   ctx->ws_bytes = ctx->arena_bytes = 0;
   return NU_OK;
@@ -320,7 +320,7 @@ nu_status nu_linear_search(nu_ctx* ctx, nu_factor* F, const double* f, const dou
   }
   double* ws = (double*)ctx_workspace(ctx, linear_ws_bytes(F->n, n_d, n_epochs), &st);
   if (!ws) return st;
-  return run_linear(ctx, F, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, mixed, depth, var, dll, valid,
+  return run_linear(ctx, F, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, prec, depth, var, dll, valid,
                     null_out, ws);
 }
 

@@ -258,8 +258,8 @@ nu_status plan_upload(nu_ctx* ctx, Plan& P) {
 }
 
 void plan_release(Plan& P) {
-  if (P.dprobs) hipFree(P.dprobs);
-  if (P.djobs) hipFree(P.djobs);
+  if (P.dprobs) (void)hipFree(P.dprobs);
+  if (P.djobs) (void)hipFree(P.djobs);
   P = Plan();
 }
 
@@ -363,8 +363,8 @@ nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F, int prec) {
   }
   if (st == NU_OK && F->bandP) {
     st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "band realloc sync");
-    hipFree(F->bandP);
-    hipFree(F->bandX);
+    (void)hipFree(F->bandP);
+    (void)hipFree(F->bandX);
     F->bandP = F->bandX = nullptr;
     F->band_w = 0;
   }
@@ -396,12 +396,12 @@ nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F, int prec) {
 
 void factor_free(nu_factor* F) {
   if (!F) return;
-  hipSetDevice(F->device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(F->device);
+  (void)hipDeviceSynchronize();
   void* bufs[] = {F->L, F->X, F->T, F->small, F->nullfit, F->L32, F->X32, F->bandP, F->bandX};
   if (F->owns_memory)
     for (void* b : bufs)
-      if (b) hipFree(b);
+      if (b) (void)hipFree(b);
   plan_release(F->plan64);
   plan_release(F->plan32);
   delete F;
@@ -546,8 +546,9 @@ nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double*
 }
 
 nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A, int m1, const int64_t* lattice,
-                     int64_t n_epochs, const int32_t* dur_samples_host, int n_d, bool mixed, double* depth,
+                     int64_t n_epochs, const int32_t* dur_samples_host, int n_d, int prec, double* depth,
                      double* var, double* dll, uint8_t* valid, double* null_out, double* ws) {
+  const int steps = refine_steps(prec);
   const int64_t n = F->n, np = F->np;
   const int xchunks = (int)((n + XRC - 1) / XRC);
   const int qchunks = (int)((n + QRC - 1) / QRC);
@@ -567,13 +568,14 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
   nu_status st = check_hip(ctx, launch_pack_v(ctx->stream, A, m1, f, n, V), "pack_v");
   if (st != NU_OK) return st;
   {
-    // Y = X V, refined once against L when X is the mixed inverse
-    Timed tm(ctx, "rows_matvec", gemv_bytes * (mixed ? 3 : 1));
+    // Y = X V, refined against L when X is a reduced-precision inverse
+    Timed tm(ctx, "rows_matvec", gemv_bytes * (1 + 2 * steps));
     st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->X, np, n, V, nv, nullptr, 1.0, Y), "rows_matvec");
-    if (mixed && st == NU_OK)
+    for (int r = 0; r < steps && st == NU_OK; ++r) {
       st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->L, np, n, Y, nv, V, -1.0, R), "rows_matvec");
-    if (mixed && st == NU_OK)
-      st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->X, np, n, R, nv, Y, 1.0, Y), "rows_matvec");
+      if (st == NU_OK)
+        st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->X, np, n, R, nv, Y, 1.0, Y), "rows_matvec");
+    }
   }
   if (st != NU_OK) return st;
   {
@@ -583,16 +585,17 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
   }
   if (st != NU_OK) return st;
   {
-    // Z = X^T [A~ | r~0], refined once against L^T when X is the mixed inverse
-    Timed tm(ctx, "cols_matvec", gemv_bytes * (mixed ? 3 : 1));
+    // Z = X^T [A~ | r~0], refined against L^T when X is a reduced-precision inverse
+    Timed tm(ctx, "cols_matvec", gemv_bytes * (1 + 2 * steps));
     st = check_hip(ctx, launch_cols_matvec(ctx->stream, F->X, np, n, np, Y, nv, xpart, XRC, xchunks, nullptr, 1.0, Z),
                    "cols_matvec");
-    if (mixed && st == NU_OK)
+    for (int r = 0; r < steps && st == NU_OK; ++r) {
       st = check_hip(ctx, launch_cols_matvec(ctx->stream, F->L, np, n, np, Z, nv, xpart, XRC, xchunks, Y, -1.0, Rz),
                      "cols_matvec");
-    if (mixed && st == NU_OK)
-      st = check_hip(ctx, launch_cols_matvec(ctx->stream, F->X, np, n, np, Rz, nv, xpart, XRC, xchunks, Z, 1.0, Z),
-                     "cols_matvec");
+      if (st == NU_OK)
+        st = check_hip(ctx, launch_cols_matvec(ctx->stream, F->X, np, n, np, Rz, nv, xpart, XRC, xchunks, Z, 1.0, Z),
+                       "cols_matvec");
+    }
   }
   if (st != NU_OK) return st;
   // ascending durations (nested boxes) with their caller indices

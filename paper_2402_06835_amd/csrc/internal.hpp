@@ -75,6 +75,16 @@ enum GemmKind { GK_F64 = 0, GK_F32 = 1, GK_BF16X3 = 2 };
 constexpr int BAND_W_F32 = 2;
 constexpr int BAND_W_BF16X3 = 8;
 inline int band_width(int prec) { return prec == NU_BF16X3_REFINE ? BAND_W_BF16X3 : BAND_W_F32; }
+// Steps of iterative refinement of the whitened trend and flux (Y = X V) and
+// of their back-substitution (Z = X^T W) against the FP64 factor. Each step
+// shrinks the error by about cond(K) times the inverse's relative error, so
+// the split-BF16 inverse (2^-16) needs a second step where FP32 (2^-24) does
+// not.
+constexpr int REFINE_STEPS_F32 = 1;
+constexpr int REFINE_STEPS_BF16X3 = 2;
+inline int refine_steps(int prec) {
+  return prec == NU_BF16X3_REFINE ? REFINE_STEPS_BF16X3 : prec == NU_FP32_REFINE ? REFINE_STEPS_F32 : 0;
+}
 inline int gemm_kind_of(int prec) {
   return prec == NU_BF16X3_REFINE ? GK_BF16X3 : prec == NU_FP32_REFINE ? GK_F32 : GK_F64;
 }
@@ -246,7 +256,7 @@ nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double*
                           int64_t n_epochs, const int32_t* dur_samples_host, int n_d, nu_precision prec,
                           const void* depth, const void* var, const void* dll, const void* valid);
 nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A, int m1, const int64_t* lattice,
-                     int64_t n_epochs, const int32_t* dur_samples_host, int n_d, bool mixed, double* depth,
+                     int64_t n_epochs, const int32_t* dur_samples_host, int n_d, int prec, double* depth,
                      double* var, double* dll, uint8_t* valid, double* null_out, double* ws);
 size_t periodic_ws_bytes(int n_d, int64_t n_epochs);
 nu_status validate_periodic(nu_ctx* ctx, int n_d, int64_t n_epochs, double dt, int64_t n_p, int log_term_sign);

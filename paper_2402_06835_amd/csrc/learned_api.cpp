@@ -372,9 +372,9 @@ nu_status nu_cnn_create(nu_ctx* ctx, int half_precision, int max_batch, nu_cnn**
 
 void nu_cnn_destroy(nu_cnn* M) {
   if (!M) return;
-  hipSetDevice(M->device);
-  hipDeviceSynchronize();
-  if (M->arena) hipFree(M->arena);
+  (void)hipSetDevice(M->device);
+  (void)hipDeviceSynchronize();
+  if (M->arena) (void)hipFree(M->arena);
   delete M;
 }
 

@@ -259,3 +259,53 @@ def test_batch_many_curves_under_load(api, ctx):
         single = _single(api, ctx, w, "fp64")
         np.testing.assert_array_equal(res["cells"][c]["dll"].cpu().numpy(), single["dll"], err_msg=f"curve {c}")
         assert res["logdet"][c] == single["logdet"]
+
+
+def test_batch_split_precision_per_output_errors(api, ctx):
+    """The uneven batch with the split-BF16 inverse against the FP64 batch, output by output
+    (dll, depth in sigma units, var, per-period SNR), on curves long enough that the FP64 band
+    step does not cover them; one curve also against the oracle on sampled cells."""
+    import torch
+    dt = 2 / 1440
+    ws = []
+    for c, n in enumerate((2600, 4100, 5000)):
+        rng = np.random.default_rng(7000 + c)
+        prot = float(np.exp(rng.uniform(np.log(0.3), np.log(2.0))))
+        amp = float(np.exp(rng.uniform(np.log(0.005), np.log(0.03))))
+        th = {"amp": amp, "omega": sho_omega_from_rotation(prot, 5.0), "q": 5.0, "sigma_w": 8e-4}
+        ws.append(make_workload(f"split-N{n}", 7000 + c, n, dt, th, [15, 28, 41, 60], np.linspace(0.5, 3.0, 200),
+                                injection={"depth": 2e-3, "period": 1.3, "t0": 0.4, "duration": 40 * dt}))
+    say(f"split-BF16 batch N={[w.n for w in ws]}")
+    curves = [{"t": w.t, "f": w.f, "A": w.A, "lattice": w.lattice, "n_epochs": w.n_epochs, "theta": w.theta,
+               "dt": dt} for w in ws]
+    durs, periods = ws[0].durations, ws[0].periods
+    ref = api.search_batch(ctx, curves, durs, periods, precision="fp64")
+    got = api.search_batch(ctx, curves, durs, periods, precision="bf16x3_refine")
+    torch.cuda.synchronize()
+    v = ref["valid"].cpu().numpy().astype(bool)
+    np.testing.assert_array_equal(got["valid"].cpu().numpy().astype(bool), v)
+    g = {k: got[k].cpu().numpy() for k in ("depth", "var", "dll", "q_snr", "best_phase", "best_dur")}
+    r = {k: ref[k].cpu().numpy() for k in ("depth", "var", "dll", "q_snr", "best_phase", "best_dur")}
+    errs = {"dll": np.max(np.abs(g["dll"][v] - r["dll"][v]) / np.maximum(np.abs(r["dll"][v]), 1.0)),
+            "depth": np.max(np.abs(g["depth"][v] - r["depth"][v]) / np.sqrt(r["var"][v])),
+            "var": np.max(np.abs(g["var"][v] - r["var"][v]) / r["var"][v])}
+    ok = r["best_phase"] >= 0
+    errs["q_snr"] = np.max(np.abs(g["q_snr"][ok] - r["q_snr"][ok]) / np.maximum(np.abs(r["q_snr"][ok]), 1.0))
+    same = np.mean((g["best_phase"][ok] == r["best_phase"][ok]) & (g["best_dur"][ok] == r["best_dur"][ok]))
+    say(f"split-BF16 vs FP64 batch: {errs}, best cell agreement {same:.4f}")
+    assert max(errs.values()) <= 1e-6, errs
+    assert same >= 0.99
+    np.testing.assert_array_equal(got["best_index"].cpu().numpy(), ref["best_index"].cpu().numpy())
+    # the longest curve against the oracle on sampled cells
+    w = ws[2]
+    L = ogp.cholesky(ogp.covariance(w.t, w.theta))
+    rng = np.random.default_rng(3)
+    cells = [(int(rng.integers(len(durs))), int(rng.integers(w.n_epochs))) for _ in range(60)]
+    oref = olin.linear_search(w.f, w.A, L, w.lattice, durs, cells=cells)
+    gc = {k: got["cells"][2][k].cpu().numpy() for k in CELL_KEYS}
+    sel = {k: np.array([gc[k][j, i] for (j, i) in cells]) for k in gc}
+    vv = oref["valid"].astype(bool)
+    np.testing.assert_array_equal(sel["valid"].astype(bool), vv)
+    e = np.abs(sel["dll"][vv] - oref["dll"][vv]) / np.maximum(np.abs(oref["dll"][vv]), 1.0)
+    say(f"split-BF16 longest curve vs oracle (sampled): dll max {e.max():.2e}")
+    assert e.max() <= 1e-6
