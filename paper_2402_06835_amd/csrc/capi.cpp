@@ -184,6 +184,7 @@ void nu_ctx_destroy(nu_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  nu::destroy_factor_streams(ctx);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->arena) (void)hipFree(ctx->arena);
   for (auto& p : ctx->pending) {

@@ -125,13 +125,14 @@ void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P)
   for (auto* F : Fs) steps = std::max(steps, F->nblk);
   P.panel.assign(steps, Range());
   P.pupd.assign(steps, Range());
-  P.trail.assign(steps, Range());
+  P.next.assign(steps, Range());
+  P.rest.assign(steps, Range());
   P.job_first.assign(steps, 0);
   P.job_count.assign(steps, 0);
   const size_t es = sizeof(double);
   for (int k = 0; k < steps; ++k) {
     P.job_first[k] = (int)P.jobs.size();
-    std::vector<GemmProblem> pan, pup, tr;
+    std::vector<GemmProblem> pan, pup, nx, rs;
     for (auto* F : Fs) {
       if (k >= F->nblk) continue;
       const int64_t np = F->np;
@@ -148,20 +149,31 @@ void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P)
         if (inner > 0)
           pup.push_back(prob(col, np, col, np, at(col, 0, TB, np, es), np, rest, inner, TB, G_BT, -1.0, 1.0));
       }
-      if (k == p0 + pw - 1) {  // last block of the panel: update the trailing matrix
+      if (k == p0 + pw - 1) {
+        // last block of the panel: update the trailing matrix by the panel,
+        // first the next panel's columns (all rows below them, as a full
+        // rectangle: what lands above the diagonal there is never read),
+        // then the rest (lower tiles)
         const int64_t t0 = (int64_t)(p0 + pw) * TB;
         const int rest2 = (int)(np - t0);
         if (rest2 > 0) {
           const void* pn = at(F->L, t0, (int64_t)p0 * TB, np, es);  // trailing rows, panel columns
-          tr.push_back(prob(pn, np, pn, np, at(F->L, t0, t0, np, es), np, rest2, rest2, pw * TB,
-                            G_BT | G_C_LOWER_TILES, -1.0, 1.0));
+          const int nw = std::min(PANEL, F->nblk - (p0 + pw)) * TB;   // next panel's width
+          nx.push_back(prob(pn, np, pn, np, at(F->L, t0, t0, np, es), np, rest2, nw, pw * TB, G_BT, -1.0, 1.0));
+          const int rest3 = rest2 - nw;
+          if (rest3 > 0) {
+            const void* pr = at(F->L, t0 + nw, (int64_t)p0 * TB, np, es);
+            rs.push_back(prob(pr, np, pr, np, at(F->L, t0 + nw, t0 + nw, np, es), np, rest3, rest3, pw * TB,
+                              G_BT | G_C_LOWER_TILES, -1.0, 1.0));
+          }
         }
       }
     }
     P.job_count[k] = (int)P.jobs.size() - P.job_first[k];
     P.panel[k] = add_launch(P.sched, pan, tu.small_below[TC_PANEL]);
     P.pupd[k] = add_launch(P.sched, pup, tu.small_below[TC_PUPD]);
-    P.trail[k] = add_launch(P.sched, tr, tu.small_below[TC_TRAIL]);
+    P.next[k] = add_launch(P.sched, nx, tu.small_below[TC_TRAIL]);
+    P.rest[k] = add_launch(P.sched, rs, tu.small_below[TC_TRAIL]);
   }
 }
 
@@ -410,11 +422,53 @@ void factor_free(nu_factor* F) {
 // ---------------------------------------------------------------------------
 // Enqueue sequences
 
-nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int kind) {
+nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int kind, hipStream_t s) {
   if (r.tiles == 0) return NU_OK;
-  Timed tm(ctx, name, r.flops);
-  return check_hip(ctx, launch_gemm(ctx->stream, P.dprobs + r.first, r.count, r.tiles, kind, r.tile_m, r.tile_n),
-                   name);
+  if (!s) s = ctx->stream;
+  Timed tm(ctx, s, name, r.flops);
+  return check_hip(ctx, launch_gemm(s, P.dprobs + r.first, r.count, r.tiles, kind, r.tile_m, r.tile_n), name);
+}
+
+// Compute units the rest of a trailing update leaves to the step loop's own
+// stream, so that a diagonal-block workgroup (most of a CU's LDS) finds a
+// free CU while the update runs.
+constexpr int LOOKAHEAD_FREE_CUS = 8;
+
+nu_status ensure_factor_streams(nu_ctx* ctx) {
+  if (ctx->s_rest) return NU_OK;
+  int ncu = 0;
+  nu_status st =
+      check_hip(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device), "CU count");
+  if (st != NU_OK) return st;
+  if (ncu <= 2 * LOOKAHEAD_FREE_CUS) {  // too small to split: no lookahead
+    ctx->lookahead = false;
+    return NU_OK;
+  }
+  std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0u);
+  for (int c = LOOKAHEAD_FREE_CUS; c < ncu; ++c) mask[(size_t)c / 32] |= 1u << (c % 32);
+  st = check_hip(ctx, hipStreamCreateWithFlags(&ctx->s_fac, hipStreamNonBlocking), "step-loop stream");
+  if (st == NU_OK)
+    st = check_hip(ctx, hipExtStreamCreateWithCUMask(&ctx->s_rest, (uint32_t)mask.size(), mask.data()),
+                   "trailing-update stream");
+  hipEvent_t* evs[] = {&ctx->ev_fork, &ctx->ev_pan, &ctx->ev_rest, &ctx->ev_join};
+  for (hipEvent_t* e : evs)
+    if (st == NU_OK) st = check_hip(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming), "step-loop event");
+  if (st != NU_OK) destroy_factor_streams(ctx);
+  return st;
+}
+
+void destroy_factor_streams(nu_ctx* ctx) {
+  if (ctx->s_fac) (void)hipStreamSynchronize(ctx->s_fac);
+  if (ctx->s_rest) (void)hipStreamSynchronize(ctx->s_rest);
+  hipEvent_t* evs[] = {&ctx->ev_fork, &ctx->ev_pan, &ctx->ev_rest, &ctx->ev_join};
+  for (hipEvent_t* e : evs)
+    if (*e) {
+      (void)hipEventDestroy(*e);
+      *e = nullptr;
+    }
+  if (ctx->s_fac) (void)hipStreamDestroy(ctx->s_fac);
+  if (ctx->s_rest) (void)hipStreamDestroy(ctx->s_rest);
+  ctx->s_fac = ctx->s_rest = nullptr;
 }
 
 nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P,
@@ -433,15 +487,68 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
   // blocks, diagonal block -> its column (times the diagonal block's inverse)
   // -> update of the panel's remaining columns; after the panel, one trailing
   // update of depth PANEL * TB on the whole chip.
+  //
+  // Lookahead: the trailing update after panel p is split into the next
+  // panel's columns (on the step loop's stream sf) and the rest (on s_rest).
+  // Panel p + 1 is factored on sf while the rest of update p runs, which
+  // hides the latency-bound diagonal blocks behind the dense update. Ordering:
+  //  * rest(p) needs panel p factored (ev_pan) and follows rest(p - 1) (same stream);
+  //  * next(p) writes tiles that rest(p - 1) also writes, so sf waits for
+  //    rest(p - 1) (ev_rest) before next(p), and so before panel p + 1;
+  //  * everything else touches disjoint tiles (next(p) and panel p + 1 the
+  //    next panel's columns, rest(p) only those right of them), and both read
+  //    panel p's columns, which are final.
+  //
+  // Under stream capture the loop stays on the caller's stream: the
+  // CU-masked stream is a blocking stream, whose launches HIP orders after
+  // the null stream's pending work, and that must not enter a capture.
+  // A step whose diagonal blocks outnumber the free CUs (a batch: one block
+  // per curve) would queue them behind the update's tiles; it stays serial.
+  hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+  if (st == NU_OK) st = check_hip(ctx, hipStreamIsCapturing(ctx->stream, &capturing), "capture status");
+  int max_jobs = 0;
+  for (int c : P.job_count) max_jobs = std::max(max_jobs, c);
+  const bool want_la = ctx->lookahead && capturing == hipStreamCaptureStatusNone && max_jobs <= LOOKAHEAD_FREE_CUS;
+  if (st == NU_OK && want_la) st = ensure_factor_streams(ctx);
+  const bool la = st == NU_OK && want_la && ctx->lookahead && ctx->s_rest;
+  hipStream_t sf = ctx->stream;
+  if (la) {
+    st = check_hip(ctx, hipEventRecord(ctx->ev_fork, ctx->stream), "fork");
+    if (st == NU_OK) st = check_hip(ctx, hipStreamWaitEvent(ctx->s_fac, ctx->ev_fork, 0), "fork");
+    sf = ctx->s_fac;
+  }
+  bool rest_pending = false;
   const int steps = (int)P.job_first.size();
   for (int k = 0; st == NU_OK && k < steps; ++k) {
     {
-      Timed tm(ctx, "potrf_diag", (double)P.job_count[k] * TB * TB * TB * 2.0 / 3.0);
-      st = check_hip(ctx, launch_potrf_diag(ctx->stream, P.djobs + P.job_first[k], P.job_count[k]), "potrf_diag");
+      Timed tm(ctx, sf, "potrf_diag", (double)P.job_count[k] * TB * TB * TB * 2.0 / 3.0);
+      st = check_hip(ctx, launch_potrf_diag(sf, P.djobs + P.job_first[k], P.job_count[k]), "potrf_diag");
     }
-    if (st == NU_OK) st = launch_range(ctx, P, P.panel[k], "gemm_f64:panel", GK_F64);
-    if (st == NU_OK) st = launch_range(ctx, P, P.pupd[k], "gemm_f64:panel_update", GK_F64);
-    if (st == NU_OK) st = launch_range(ctx, P, P.trail[k], "gemm_f64:trailing", GK_F64);
+    if (st == NU_OK) st = launch_range(ctx, P, P.panel[k], "gemm_f64:panel", GK_F64, sf);
+    if (st == NU_OK) st = launch_range(ctx, P, P.pupd[k], "gemm_f64:panel_update", GK_F64, sf);
+    if (st != NU_OK || (P.next[k].tiles == 0 && P.rest[k].tiles == 0)) continue;
+    if (!la) {
+      st = launch_range(ctx, P, P.next[k], "gemm_f64:trailing", GK_F64, sf);
+      if (st == NU_OK) st = launch_range(ctx, P, P.rest[k], "gemm_f64:trailing", GK_F64, sf);
+      continue;
+    }
+    st = check_hip(ctx, hipEventRecord(ctx->ev_pan, sf), "panel event");
+    if (st == NU_OK && rest_pending) st = check_hip(ctx, hipStreamWaitEvent(sf, ctx->ev_rest, 0), "rest wait");
+    if (st == NU_OK) st = launch_range(ctx, P, P.next[k], "gemm_f64:trailing", GK_F64, sf);
+    if (st == NU_OK && P.rest[k].tiles > 0) {
+      st = check_hip(ctx, hipStreamWaitEvent(ctx->s_rest, ctx->ev_pan, 0), "panel wait");
+      if (st == NU_OK) st = launch_range(ctx, P, P.rest[k], "gemm_f64:trailing", GK_F64, ctx->s_rest);
+      if (st == NU_OK) st = check_hip(ctx, hipEventRecord(ctx->ev_rest, ctx->s_rest), "rest event");
+      rest_pending = true;
+    }
+  }
+  if (la) {
+    // join (also after an error: the caller's stream must not run ahead of s_fac and s_rest)
+    nu_status sj = NU_OK;
+    if (rest_pending) sj = check_hip(ctx, hipStreamWaitEvent(sf, ctx->ev_rest, 0), "join");
+    if (sj == NU_OK) sj = check_hip(ctx, hipEventRecord(ctx->ev_join, sf), "join");
+    if (sj == NU_OK) sj = check_hip(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "join");
+    if (st == NU_OK) st = sj;
   }
   for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i)
     st = check_hip(ctx, launch_logdet_reduce(ctx->stream, Fs[i]->parts(), Fs[i]->nblk, Fs[i]->logdet_dev()),

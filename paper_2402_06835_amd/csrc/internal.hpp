@@ -131,6 +131,12 @@ struct nu_ctx {
   std::vector<std::string> timing_names;
   // tile policy of the dense launches (set by the autotuner)
   nu::Tuning tuning;
+  // the Cholesky's step loop (created on first use): the diagonal blocks,
+  // panels and lookahead updates on s_fac; the rest of each trailing update
+  // on s_rest, which leaves LOOKAHEAD_FREE_CUS compute units to s_fac
+  hipStream_t s_fac = nullptr, s_rest = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_pan = nullptr, ev_rest = nullptr, ev_join = nullptr;
+  bool lookahead = true;
 };
 
 namespace nu {
@@ -162,7 +168,9 @@ struct Plan {
   std::vector<PotrfJob> jobs;
   PotrfJob* djobs = nullptr;
   std::vector<int> job_first, job_count;  // per Cholesky step
-  std::vector<Range> panel, pupd, trail;  // per Cholesky step (trail: launched after the step)
+  std::vector<Range> panel, pupd;        // per Cholesky step
+  std::vector<Range> next, rest;          // per step: the trailing update after a panel's last block, split
+                                          // into the next panel's columns and the rest
   std::vector<Range> t1, t2;              // per inverse level, deepest first
   Range bandp, bandx;
   bool built = false;
@@ -215,11 +223,15 @@ void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, 
 void resolve_timing(nu_ctx* ctx);  // synchronises the stream, folds pending events into the totals
 struct Timed {
   nu_ctx* ctx;
+  hipStream_t stream;
   const char* name;
   double work;
   hipEvent_t start;
-  Timed(nu_ctx* c, const char* n, double w) : ctx(c), name(n), work(w) { timing_begin(c, c->stream, &start); }
-  ~Timed() { timing_end(ctx, ctx->stream, name, start, work); }
+  Timed(nu_ctx* c, const char* n, double w) : Timed(c, c->stream, n, w) {}
+  Timed(nu_ctx* c, hipStream_t s, const char* n, double w) : ctx(c), stream(s), name(n), work(w) {
+    timing_begin(c, s, &start);
+  }
+  ~Timed() { timing_end(ctx, stream, name, start, work); }
 };
 
 // Host wall time of a phase of a call (allocation, planning, waits, frees),
@@ -245,7 +257,10 @@ void* ctx_arena(nu_ctx* ctx, size_t bytes, nu_status* st);
 nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F, int prec);
 nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F, int prec);
 void factor_free(nu_factor* F);
-nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int kind);
+nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int kind,
+                       hipStream_t s = nullptr);  // s = nullptr: the context's stream
+nu_status ensure_factor_streams(nu_ctx* ctx);
+void destroy_factor_streams(nu_ctx* ctx);
 nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P,
                      const std::vector<const double*>& ts, const std::vector<const nu_sho*>& theta_dev);
 nu_status read_factor_status(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, std::vector<int64_t>& status);

@@ -169,10 +169,13 @@ def test_batch_not_positive_definite_curve(api, ctx):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "bf16x3_refine"])
-def test_graph_replays_match_eager(api, ctx, precision):
+@pytest.mark.parametrize("n", [700, 2000])
+def test_graph_replays_match_eager(api, ctx, precision, n):
+    # N = 2000 has trailing updates beyond the next panel (the eager step loop
+    # splits them across two streams; the captured one keeps one stream)
     import torch
-    w = _curve(700, 41, 1.2, gap=(333, 25))
-    say(f"graph N=700, {precision}: three replays with new theta and flux")
+    w = _curve(n, 41, 1.2, gap=(333, 25))
+    say(f"graph N={n}, {precision}: three replays with new theta and flux")
     g = api.Graph(ctx, w.t, w.f, w.A, w.lattice, w.n_epochs, DURS, w.theta, DT, PERIODS, precision=precision)
     rng = np.random.default_rng(5)
     for rep in range(3):
