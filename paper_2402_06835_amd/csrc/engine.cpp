@@ -622,14 +622,15 @@ nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, cons
 
 namespace {
 constexpr int XRC = 1024;  // rows per partial of the transposed products
-constexpr int QRC = 2048;  // rows per partial of the box sums of squares
+constexpr int QRC = 512;   // rows per partial of the box sums of squares (one wave each: latency bound, so many)
 }  // namespace
 
 size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs) {
   const int64_t np = round_up(n, TB);
   const size_t xchunks = (size_t)((n + XRC - 1) / XRC), qchunks = (size_t)((n + QRC - 1) / QRC);
   const size_t yz = (size_t)np * YCOLS;
-  return (5 * yz + xchunks * yz + qchunks * (size_t)n_d * (size_t)n_epochs) * sizeof(double);
+  const size_t slots = ((size_t)n_epochs + 2) / 2;  // the int32 slot-count table, in doubles
+  return (5 * yz + xchunks * yz + qchunks * (size_t)n_d * (size_t)n_epochs + slots) * sizeof(double);
 }
 
 nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double* A, int m1, const int64_t* lattice,
@@ -667,6 +668,7 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
   double* Rz = Z + yz;
   double* xpart = Rz + yz;
   double* qpart = xpart + (size_t)xchunks * yz;
+  int32_t* slot_count = reinterpret_cast<int32_t*>(qpart + (size_t)qchunks * n_d * n_epochs);
   const int nv = m1 + 1;
   const double gemv_bytes = (double)n * (double)(n + 1) / 2.0 * 8.0;
   int dmax = 0;
@@ -717,15 +719,18 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
   }
   {
     Timed tm(ctx, "q_partial", 0.0);
-    st = check_hip(ctx, launch_q_partial(ctx->stream, F->X, np, n, lattice, n_epochs, sorted.data(), n_d, dmax, QRC,
-                                         qchunks, qpart),
-                   "q_partial");
+    st = check_hip(ctx, launch_slot_count(ctx->stream, lattice, n, n_epochs, slot_count), "slot_count");
+    if (st == NU_OK)
+      st = check_hip(ctx, launch_q_partial(ctx->stream, F->X, np, n, lattice, slot_count, n_epochs, sorted.data(),
+                                           n_d, dmax, QRC, qchunks, qpart),
+                     "q_partial");
   }
   if (st != NU_OK) return st;
   {
     Timed tm(ctx, "cell_epilogue", 0.0);
-    st = check_hip(ctx, launch_cell_epilogue(ctx->stream, qpart, qchunks, lattice, n, n_epochs, dur_samples_host,
-                                             nullptr, n_d, Z, m1, F->nullfit, depth, var, dll, valid),
+    st = check_hip(ctx, launch_cell_epilogue(ctx->stream, qpart, qchunks, lattice, slot_count, n, n_epochs,
+                                             dur_samples_host, nullptr, n_d, Z, m1, F->nullfit, depth, var, dll,
+                                             valid),
                    "cell_epilogue");
   }
   return st;

@@ -305,11 +305,13 @@ hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const 
 hipError_t launch_cols_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, int64_t np, const double* W,
                               int nv, double* partial, int rowchunk, int nchunks, const double* base, double alpha,
                               double* out);
+hipError_t launch_slot_count(hipStream_t s, const int64_t* lattice, int64_t n, int64_t n_epochs, int32_t* T);
 hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t n, const int64_t* lattice,
-                            int64_t n_epochs, const int32_t* dur_sorted, int n_d, int dmax, int rowchunk,
-                            int nchunks, double* qpart);
-hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks, const int64_t* lattice, int64_t n,
-                                int64_t n_epochs, const int32_t* dur, const int32_t* dur_rank, int n_d,
+                            const int32_t* T, int64_t n_epochs, const int32_t* dur_sorted, int n_d, int dmax,
+                            int rowchunk, int nchunks, double* qpart);
+hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks, const int64_t* lattice,
+                                const int32_t* T, int64_t n, int64_t n_epochs, const int32_t* dur,
+                                const int32_t* dur_rank, int n_d,
                                 const double* Z, int m1, const NullFit* nf, double* depth, double* var, double* dll,
                                 uint8_t* valid);
 hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, const double* dll,

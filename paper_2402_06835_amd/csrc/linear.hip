@@ -41,6 +41,25 @@ __device__ __forceinline__ int64_t lower_bound_i64(const int64_t* __restrict__ a
   return lo;
 }
 
+// Samples with lattice index below a: from the table T[s] = that count for
+// s in [0, n_epochs], by binary search outside it.
+__device__ __forceinline__ int64_t count_below(const int64_t* __restrict__ lattice, int64_t n,
+                                               const int32_t* __restrict__ T, int64_t n_epochs, int64_t a) {
+  return (a >= 0 && a <= n_epochs) ? (int64_t)T[a] : lower_bound_i64(lattice, n, a);
+}
+
+__global__ __launch_bounds__(256) void slot_count_kernel(const int64_t* __restrict__ lattice, int64_t n,
+                                                         int64_t n_epochs, int32_t* __restrict__ T) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s <= n_epochs) T[s] = (int32_t)lower_bound_i64(lattice, n, s);
+}
+
+hipError_t launch_slot_count(hipStream_t s, const int64_t* lattice, int64_t n, int64_t n_epochs, int32_t* T) {
+  hipLaunchKernelGGL(slot_count_kernel, dim3((unsigned)((n_epochs + 1 + 255) / 256)), dim3(256), 0, s, lattice, n,
+                     n_epochs, T);
+  return hipGetLastError();
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -294,26 +313,39 @@ hipError_t launch_cols_matvec(hipStream_t s, const double* M, int64_t ldm, int64
 }
 
 // ---------------------------------------------------------------------------
-// q partial sums. Workgroup = 256 consecutive epoch slots (one per thread) x
-// one chunk of rows. The union of the boxes of the slots spans the sample
-// segment [seg_lo, seg_hi); qr rows of X restricted to it are staged in LDS
-// (entries above the diagonal read as 0) and turned into exclusive prefix
-// sums along the row (one wave per row), so every box sum of a row is the
-// difference of two prefix values.
-constexpr int QCH = 256;
+// q partial sums. A wave owns 64 consecutive epoch slots (one per lane) and
+// one chunk of rows; the four waves of a workgroup take adjacent slot groups
+// over the same rows, so their overlapping row segments meet in cache. The
+// union of the boxes of a wave's slots spans the sample segment
+// [seg_lo, seg_hi), at most 64 + dmax samples; a row of X restricted to it
+// (entries above the diagonal read as 0) is turned into inclusive prefix sums
+// in registers, each lane holding RUN consecutive entries: a serial prefix
+// within the lane, one wave scan of the lane totals, then the lane's offset.
+// The prefix row goes to the wave's own LDS row, from which each lane takes
+// the two ends of each of its boxes: box sum = P[hi] - P[lo]. Rows go two at
+// a time (two independent scan chains), the next two rows' segments loading
+// meanwhile. No workgroup barrier:
+// the waves are independent, and LDS order within a wave needs only a
+// compiler fence.
+constexpr int QCH = 256;  // slots per workgroup (4 waves x 64)
 
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int RUN>
 __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
-                                                        const int64_t* __restrict__ lattice, int64_t n_epochs,
-                                                        DurList dl, int wmax, int qr, int rowchunk,
-                                                        double* __restrict__ qpart) {
-  extern __shared__ double rows[];  // qr x (wmax + 1)
-  __shared__ int64_t red_lo[4], red_hi[4];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int64_t slot = (int64_t)blockIdx.x * QCH + tid;
+                                                        const int64_t* __restrict__ lattice,
+                                                        const int32_t* __restrict__ T, int64_t n_epochs,
+                                                        DurList dl, int rowchunk, double* __restrict__ qpart) {
+  constexpr int SEG = 64 * RUN;  // segment capacity of a wave
+  __shared__ double prefix[4][2][SEG + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t slot = (int64_t)blockIdx.x * QCH + wave * 64 + lane;
   const int chunk = blockIdx.y;
   const bool active = slot < n_epochs;
-  const int ldr = wmax + 1;
   int64_t lo[MAX_ND], hi[MAX_ND];
   int64_t my_lo = INT64_MAX, my_hi = INT64_MIN;
 #pragma unroll
@@ -321,8 +353,8 @@ __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict
     lo[k] = hi[k] = 0;
     if (k < dl.n && active) {
       const int64_t a = slot - dl.d[k] / 2;
-      lo[k] = lower_bound_i64(lattice, n, a);
-      hi[k] = lower_bound_i64(lattice, n, a + dl.d[k]);
+      lo[k] = count_below(lattice, n, T, n_epochs, a);
+      hi[k] = count_below(lattice, n, T, n_epochs, a + dl.d[k]);
       my_lo = min(my_lo, lo[k]);
       my_hi = max(my_hi, hi[k]);
     }
@@ -332,18 +364,9 @@ __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict
     my_lo = min(my_lo, (int64_t)__shfl_xor(my_lo, off, 64));
     my_hi = max(my_hi, (int64_t)__shfl_xor(my_hi, off, 64));
   }
-  if (lane == 0) {
-    red_lo[wave] = my_lo;
-    red_hi[wave] = my_hi;
-  }
-  __syncthreads();
-  const int64_t seg_lo = min(min(red_lo[0], red_lo[1]), min(red_lo[2], red_lo[3]));
-  const int64_t seg_hi = max(max(red_hi[0], red_hi[1]), max(red_hi[2], red_hi[3]));
-  const int64_t r0 = (int64_t)chunk * rowchunk;
-  const int64_t rstart = max(r0, seg_lo);
-  const int64_t rend = min(n, r0 + rowchunk);
-  const int W = (seg_hi > seg_lo) ? (int)(seg_hi - seg_lo) : 0;
-
+  const int64_t seg_lo = my_lo, seg_hi = my_hi;  // empty wave: seg_lo > seg_hi
+  double* P0 = prefix[wave][0];
+  double* P1 = prefix[wave][1];
   double q[MAX_ND];
   int rl[MAX_ND], rh[MAX_ND];
 #pragma unroll
@@ -352,51 +375,63 @@ __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict
     rl[k] = (int)(lo[k] - seg_lo);
     rh[k] = (int)(hi[k] - seg_lo);
   }
-
-  if (W > 0 && W <= wmax) {
-    const int per = (W + 63) / 64;  // prefix-scan run per lane
-    for (int64_t nb = rstart; nb < rend; nb += qr) {
-      for (int rr = 0; rr < qr; ++rr) {
-        const int64_t r = nb + rr;
-        double* P = rows + rr * ldr;
-        if (tid == 0) P[0] = 0.0;
-        for (int w = tid; w < W; w += 256) {
-          const int64_t m = seg_lo + w;
-          P[1 + w] = (r < rend && m <= r) ? X[r * ldx + m] : 0.0;
-        }
-      }
-      __syncthreads();
-      for (int rr = wave; rr < qr; rr += 4) {
-        double* P = rows + rr * ldr + 1;
-        const int b = lane * per, e = min(W, b + per);
-        double run = 0.0;
-        for (int i = b; i < e; ++i) {
-          run += P[i];
-          P[i] = run;
-        }
-        double incl = run;
+  const int64_t r0 = max((int64_t)chunk * rowchunk, seg_lo);
+  const int64_t r1 = min(n, (int64_t)chunk * rowchunk + rowchunk);
+  if (seg_hi > seg_lo && seg_hi - seg_lo <= SEG && r0 < r1) {
+    if (lane == 0) P0[0] = P1[0] = 0.0;
+    const int64_t m0 = seg_lo + lane * RUN;  // this lane's first column
+    // row r restricted to the segment; rows at or past r1 read as 0
+    auto load_row = [&](int64_t r, double (&v)[RUN]) {
+      const double* x = X + r * ldx;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          const double y = __shfl_up(incl, off, 64);
-          if (lane >= off) incl += y;
-        }
-        const double excl = incl - run;
-        for (int i = b; i < e; ++i) P[i] += excl;
+      for (int e = 0; e < RUN; ++e) {
+        const int64_t m = m0 + e;
+        v[e] = (r < r1 && m < seg_hi && m <= r) ? x[m] : 0.0;
       }
-      __syncthreads();
+    };
+    // inclusive prefix of the segment into P[1..]
+    auto scan_store = [&](double (&v)[RUN], double* P) {
+#pragma unroll
+      for (int e = 1; e < RUN; ++e) v[e] += v[e - 1];
+      double incl = v[RUN - 1];
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const double y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+      }
+      const double excl = incl - v[RUN - 1];
+#pragma unroll
+      for (int e = 0; e < RUN; ++e) P[1 + lane * RUN + e] = v[e] + excl;
+    };
+    // two rows per pass, the next two rows' loads in flight meanwhile
+    double n0[RUN], n1[RUN];
+    load_row(r0, n0);
+    load_row(r0 + 1, n1);
+    for (int64_t r = r0; r < r1; r += 2) {
+      double v0[RUN], v1[RUN];
+#pragma unroll
+      for (int e = 0; e < RUN; ++e) {
+        v0[e] = n0[e];
+        v1[e] = n1[e];
+      }
+      if (r + 2 < r1) {
+        load_row(r + 2, n0);
+        load_row(r + 3, n1);
+      }
+      scan_store(v0, P0);
+      scan_store(v1, P1);
+      wave_lds_fence();
       if (active) {
-        for (int rr = 0; rr < qr; ++rr) {
-          const double* P = rows + rr * ldr;
 #pragma unroll
-          for (int k = 0; k < MAX_ND; ++k) {
-            if (k < dl.n) {
-              const double sk = P[rh[k]] - P[rl[k]];
-              q[k] = fma(sk, sk, q[k]);
-            }
+        for (int k = 0; k < MAX_ND; ++k)
+          if (k < dl.n) {
+            const double s0 = P0[rh[k]] - P0[rl[k]];
+            const double s1 = P1[rh[k]] - P1[rl[k]];
+            q[k] = fma(s0, s0, q[k]);
+            q[k] = fma(s1, s1, q[k]);
           }
-        }
       }
-      __syncthreads();
+      wave_lds_fence();
     }
   }
   if (active) {
@@ -407,8 +442,8 @@ __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict
 }
 
 hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t n, const int64_t* lattice,
-                            int64_t n_epochs, const int32_t* dur_sorted, int n_d, int dmax, int rowchunk,
-                            int nchunks, double* qpart) {
+                            const int32_t* T, int64_t n_epochs, const int32_t* dur_sorted, int n_d, int dmax,
+                            int rowchunk, int nchunks, double* qpart) {
   // dur_sorted: host array [2 * n_d]: ascending durations, then their caller indices
   DurList dl{};
   dl.n = n_d;
@@ -416,18 +451,22 @@ hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t
     dl.d[k] = dur_sorted[k];
     dl.perm[k] = dur_sorted[n_d + k];
   }
-  const int wmax = QCH + dmax;
-  // rows staged per pass: at most 8, within 64 KB of LDS
-  const int qr = std::max(1, std::min(8, (int)(65536 / ((size_t)(wmax + 1) * sizeof(double)))));
-  const size_t shm = (size_t)qr * (wmax + 1) * sizeof(double);
-  hipLaunchKernelGGL(q_partial_kernel, dim3((unsigned)((n_epochs + QCH - 1) / QCH), (unsigned)nchunks), dim3(256),
-                     shm, s, X, ldx, n, lattice, n_epochs, dl, wmax, qr, rowchunk, qpart);
+  // a wave's segment: at most 64 slots plus the longest box, in samples
+  const int seg = 64 + dmax;
+  const dim3 g((unsigned)((n_epochs + QCH - 1) / QCH), (unsigned)nchunks), b(256);
+  if (seg <= 64 * 2) hipLaunchKernelGGL(q_partial_kernel<2>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, rowchunk, qpart);
+  else if (seg <= 64 * 3) hipLaunchKernelGGL(q_partial_kernel<3>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, rowchunk, qpart);
+  else if (seg <= 64 * 5) hipLaunchKernelGGL(q_partial_kernel<5>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, rowchunk, qpart);
+  else if (seg <= 64 * 9) hipLaunchKernelGGL(q_partial_kernel<9>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, rowchunk, qpart);
+  else if (seg <= 64 * 17) hipLaunchKernelGGL(q_partial_kernel<17>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, rowchunk, qpart);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __restrict__ qpart, int nchunks,
-                                                            const int64_t* __restrict__ lattice, int64_t n,
+                                                            const int64_t* __restrict__ lattice,
+                                                            const int32_t* __restrict__ T, int64_t n,
                                                             int64_t n_epochs, DurList dl,
                                                             const double* __restrict__ Z, int m1,
                                                             const NullFit* __restrict__ nf, double* __restrict__ depth,
@@ -441,8 +480,8 @@ __global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __rest
   for (int c = 0; c < nchunks; ++c) q += qpart[((int64_t)c * dl.n + j) * n_epochs + i];
   const int d = dl.d[j];
   const int64_t a = i - d / 2;
-  const int64_t lo = lower_bound_i64(lattice, n, a);
-  const int64_t hi = lower_bound_i64(lattice, n, a + d);
+  const int64_t lo = count_below(lattice, n, T, n_epochs, a);
+  const int64_t hi = count_below(lattice, n, T, n_epochs, a + d);
   bool ok = (hi > lo) && nf->ok;
   double h = 0.0, g[MAX_M1];
 #pragma unroll
@@ -488,8 +527,8 @@ __global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __rest
   }
 }
 
-hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks, const int64_t* lattice, int64_t n,
-                                int64_t n_epochs, const int32_t* dur, const int32_t* /*dur_rank*/, int n_d,
+hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks, const int64_t* lattice,
+                                const int32_t* T, int64_t n, int64_t n_epochs, const int32_t* dur, const int32_t* /*dur_rank*/, int n_d,
                                 const double* Z, int m1, const NullFit* nf, double* depth, double* var, double* dll,
                                 uint8_t* valid) {
   DurList dl{};
@@ -500,7 +539,7 @@ hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks,
   }
   const int64_t cells = (int64_t)n_d * n_epochs;
   hipLaunchKernelGGL(cell_epilogue_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, qpart, nchunks,
-                     lattice, n, n_epochs, dl, Z, m1, nf, depth, var, dll, valid);
+                     lattice, T, n, n_epochs, dl, Z, m1, nf, depth, var, dll, valid);
   return hipGetLastError();
 }
 
