@@ -77,21 +77,33 @@ __device__ __forceinline__ double from_next_lane(double x) {
 // The sum of log ratios is taken as one logarithm of a product:
 //   sum_k [ln var_k - ln(sigma^2 + var_k)] = -ln prod_k (1 + sigma^2 / var_k),
 // where the product lies in (1, e] because sigma^2 sum_k 1/var_k = 1.
+//
+// Pass 2 (the chi^2 and log terms, which need the combined depth and sigma^2
+// of pass 1) is skipped for a group of durations when no cell of the wave can
+// reach the best lnP found so far for this period (thr, from any wave of the
+// workgroup). The bound, from pass-1 sums alone: with L = ln prod in [0, 1],
+//   lnP = S_ll - (-s L + chi^2) / 2 <= S_ll + [s > 0] / 2 - chi^2 / 2,
+// and, since sigma^2 <= v_min (the smallest var_k) and sum_k (d_k - D) / v_k = 0,
+//   chi^2 >= sum_k (d_k - D)^2 / (v_k (1 + sigma^2 / v_min))
+//         = (sum_k d_k^2 / v_k - D^2 S_w) / (1 + sigma^2 / v_min).
+// A skipped cell's lnP is below a value some cell reaches, so the argmax and
+// every per-period output are unchanged; a relative margin covers rounding.
 template <int JG>  // durations per pass over the events
 __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const double* __restrict__ Lp, int n_d,
                                            int64_t n_t, int j0, int64_t mb, int lane, int64_t nph, double p,
-                                           double sign, Best& best) {
+                                           double sign, double thr, Best& best) {
   const int64_t ld = n_t + FPAD;
   const int64_t m = mb + lane;
   const int64_t kmax_base = n_t - 1 - mb;  // events while base_k <= this (uniform)
   int64_t row[JG];
 #pragma unroll
   for (int g = 0; g < JG; ++g) row[g] = (int64_t)min(j0 + g, n_d - 1) * ld + m;
-  double s_w[JG], s_wd[JG], s_ll[JG];
+  double s_w[JG], s_wd[JG], s_ll[JG], s_dd[JG];
+  double vmin = INFINITY;  // over the group's durations: a smaller v_min only loosens the bound
   int cnt[JG];
 #pragma unroll
   for (int g = 0; g < JG; ++g) {
-    s_w[g] = s_wd[g] = s_ll[g] = 0.0;
+    s_w[g] = s_wd[g] = s_ll[g] = s_dd[g] = 0.0;
     cnt[g] = 0;
   }
   // pass 1
@@ -119,21 +131,36 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
       }
       if (v == v && j0 + g < n_d) {
         const double iv = rcp_nr(v);
+        const double dw = d * iv;
         s_w[g] = s_w[g] + iv;
-        s_wd[g] = s_wd[g] + d * iv;
+        s_wd[g] = s_wd[g] + dw;
+        s_dd[g] = s_dd[g] + d * dw;
         s_ll[g] = s_ll[g] + ll;
+        vmin = fmin(vmin, v);
         ++cnt[g];
       }
     }
   }
   double s2[JG], dc[JG], prod[JG], chi[JG];
+  bool need[JG];
+  bool any_need = false;
 #pragma unroll
   for (int g = 0; g < JG; ++g) {
     s2[g] = 1.0 / s_w[g];
     dc[g] = s2[g] * s_wd[g];
     prod[g] = 1.0;
     chi[g] = 0.0;
+    bool mine = false;
+    if (j0 + g < n_d && cnt[g] > 0 && m < nph && lane < WPH) {
+      const double chi_lb = fmax(s_dd[g] - dc[g] * dc[g] * s_w[g], 0.0) / (1.0 + s2[g] / vmin);
+      const double ub = s_ll[g] + (sign > 0.0 ? 0.5 : 0.0) - 0.5 * chi_lb;
+      const double margin = 1e-9 * (1.0 + fabs(s_ll[g]) + s_dd[g]);
+      mine = !(ub + margin < thr);  // NaN: evaluated
+    }
+    need[g] = __ballot(mine) != 0;
+    any_need = any_need || need[g];
   }
+  if (!any_need) return;
   // pass 2
   for (int64_t k = 0;; ++k) {
     const double kp = (double)k * p;
@@ -144,9 +171,11 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
     const double u = 1.0 - w;
     double2 dv[JG];
 #pragma unroll
-    for (int g = 0; g < JG; ++g) dv[g] = DV[row[g] + b];
+    for (int g = 0; g < JG; ++g)
+      if (need[g]) dv[g] = DV[row[g] + b];
 #pragma unroll
     for (int g = 0; g < JG; ++g) {
+      if (!need[g]) continue;
       double d = dv[g].x, v = dv[g].y;
       if (w != 0.0) {
         d = u * d + w * from_next_lane(d);
@@ -164,7 +193,7 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
 #pragma unroll
   for (int g = 0; g < JG; ++g) {
     const int j = j0 + g;
-    if (j < n_d && cnt[g] > 0 && m < nph && lane < WPH) {
+    if (need[g] && j < n_d && cnt[g] > 0 && m < nph && lane < WPH) {
       const double corr = -sign * log(prod[g]) + chi[g];
       const double lnp = s_ll[g] - 0.5 * corr;
       Best cand{lnp, m * (int64_t)n_d + j, dc[g], s2[g]};
@@ -174,15 +203,19 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
 }
 
 template <int JG>
-__global__ __launch_bounds__(256) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
+__global__ __launch_bounds__(256, 3) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
                                                    int n_d, int64_t n_t, double dt,
                                                    const double* __restrict__ periods, double sign,
                                                    double* __restrict__ q_snr, int64_t* __restrict__ best_phase,
                                                    int32_t* __restrict__ best_dur, double* __restrict__ best_depth,
                                                    double* __restrict__ best_sigma, double* __restrict__ best_lnp) {
   __shared__ Best red[256];
+  __shared__ double wave_best[4];  // best lnP found so far by each wave (only rises)
   const int64_t ip = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid < 4) wave_best[tid] = -INFINITY;
+  __syncthreads();
+  volatile double* wb = wave_best;
   const double P = periods[ip];
   const double p = P / dt;
   Best best{-INFINITY, -1, 0.0, 0.0};
@@ -191,7 +224,15 @@ __global__ __launch_bounds__(256) void fold_kernel(const double2* __restrict__ D
     const double nph_d = ceil(p);
     const int64_t nph = nph_d < (double)n_t ? (int64_t)nph_d : n_t;  // phases >= n_t hold no event
     for (int64_t mb = (int64_t)wave * WPH; mb < nph; mb += 4 * WPH)
-      for (int j0 = 0; j0 < n_d; j0 += JG) fold_cells<JG>(DV, Lp, n_d, n_t, j0, mb, lane, nph, p, sign, best);
+      for (int j0 = 0; j0 < n_d; j0 += JG) {
+        // read without synchronisation: a stale value only prunes less
+        const double thr = fmax(fmax(wb[0], wb[1]), fmax(wb[2], wb[3]));
+        fold_cells<JG>(DV, Lp, n_d, n_t, j0, mb, lane, nph, p, sign, thr, best);
+        double v = best.flat >= 0 ? best.val : -INFINITY;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+        if (lane == 0 && v > wb[wave]) wb[wave] = v;
+      }
   }
   red[tid] = best;
   __syncthreads();
