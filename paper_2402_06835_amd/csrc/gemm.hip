@@ -159,12 +159,14 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
   const NU_GLOBAL T* Ap = A + (int64_t)(m0 + ar) * P.lda + akh;
   const NU_GLOBAL T* Bp = bt ? B + (int64_t)(n0 + br) * P.ldb + bkh : B + (int64_t)bk * P.ldb + n0 + bnc;
 
-  T ra[EA], rb[EB];
-  auto gload = [&](int k0) {
+  // two register sets: the global loads of slice it + 2 are issued while
+  // slice it is computed, two slices ahead of their LDS store
+  T ra0[EA], rb0[EB], ra1[EA], rb1[EB];
+  auto gload = [&](int k0, T (&ra)[EA], T (&rb)[EB]) {
     loadE<T, EA>(Ap + k0, ra);
     loadE<T, EB>(bt ? Bp + k0 : Bp + (int64_t)k0 * P.ldb, rb);
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, const T (&ra)[EA], const T (&rb)[EB]) {
 #pragma unroll
     for (int i = 0; i < EA; ++i) As[buf][akh + i][ar] = ra[i];
     if (bt) {
@@ -182,27 +184,37 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
 #pragma unroll
     for (int j = 0; j < NBN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  if (nk > 0) {
-    gload(kb);
-    lstore(0);
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int kk = 0; kk < GBK / 4; ++kk) {
+      T a[NBM], b[NBN];
+#pragma unroll
+      for (int mi = 0; mi < NBM; ++mi) a[mi] = As[buf][kk * 4 + lk][wm + mi * 16 + lr];
+#pragma unroll
+      for (int ni = 0; ni < NBN; ++ni) b[ni] = Bs[buf][kk * 4 + lk][wn + ni * 16 + lr];
+#pragma unroll
+      for (int mi = 0; mi < NBM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = Mfma<T>::op(a[mi], b[ni], acc[mi][ni]);
+    }
+  };
+  // one slice: compute buffer it & 1 (slice it), refill the register set
+  // that held slice it with slice it + 2, store slice it + 1 from the other
+  auto step = [&](int it, T (&rac)[EA], T (&rbc)[EB], T (&ran)[EA], T (&rbn)[EB]) {
+    if (it + 2 < nk) gload(kb + (it + 2) * GBK, rac, rbc);
+    compute(it & 1);
+    if (it + 1 < nk) lstore((it + 1) & 1, ran, rbn);
     __syncthreads();
-    for (int it = 0; it < nk; ++it) {
-      const int buf = it & 1;
-      if (it + 1 < nk) gload(kb + (it + 1) * GBK);
-#pragma unroll
-      for (int kk = 0; kk < GBK / 4; ++kk) {
-        T a[NBM], b[NBN];
-#pragma unroll
-        for (int mi = 0; mi < NBM; ++mi) a[mi] = As[buf][kk * 4 + lk][wm + mi * 16 + lr];
-#pragma unroll
-        for (int ni = 0; ni < NBN; ++ni) b[ni] = Bs[buf][kk * 4 + lk][wn + ni * 16 + lr];
-#pragma unroll
-        for (int mi = 0; mi < NBM; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = Mfma<T>::op(a[mi], b[ni], acc[mi][ni]);
-      }
-      if (it + 1 < nk) lstore(buf ^ 1);
-      __syncthreads();
+  };
+
+  if (nk > 0) {
+    gload(kb, ra0, rb0);
+    if (nk > 1) gload(kb + GBK, ra1, rb1);
+    lstore(0, ra0, rb0);
+    __syncthreads();
+    for (int it = 0; it < nk; it += 2) {
+      step(it, ra0, rb0, ra1, rb1);
+      if (it + 1 < nk) step(it + 1, ra1, rb1, ra0, rb0);
     }
   }
 
