@@ -171,6 +171,21 @@ nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var
                              int64_t n_p, int log_term_sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,
                              double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period_index);
 
+/* (3b) Search for further candidates (Section 4, the search of TOI-540): mask
+ * a found candidate's transits in the linear-search outputs, in place, so
+ * that the next periodic search (3) on them skips those epochs; the linear
+ * search is not repeated.
+ * depth/var/dll/valid: device, [n_d][n_epochs] as produced by (2), modified
+ * in place. period: the candidate's period (time unit of dt, p = period / dt
+ * >= 1); phase: its best phase m in slots (0 <= m < n_epochs); half_width:
+ * its duration in slots, n_j (1 .. 1024): windows of width 2 D.
+ * Slot i is masked, for every duration, when |(i - m) - k p| < half_width for
+ * some integer k (k p rounded once to FP64); masked cells take the invalid
+ * encoding of (2): depth = 0, var = +inf, dll = 0, valid = 0.
+ * Argument errors return NU_ERR_ARG before any launch; no synchronisation. */
+nu_status nu_mask_transit(nu_ctx* ctx, double* depth, double* var, double* dll, uint8_t* valid, int n_d,
+                          int64_t n_epochs, double dt, double period, int64_t phase, int half_width);
+
 /* (4) Batch search of light curves of uneven length: (1), (2) and (3) for
  * every curve of the batch (Sections 2.2-2.4 per curve).
  * Curve c owns samples [sample_off_host[c], sample_off_host[c+1]) of t, f and

@@ -45,6 +45,8 @@ SIGNATURES = {
     "nu_periodic_search": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int64, c_double,
                                    c_void_p, c_int64, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p]),
+    "nu_mask_transit": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int64, c_double,
+                                c_double, c_int64, c_int]),
     "nu_search_batch": (c_int, [c_void_p, c_int, P(c_int64), P(c_int64), c_void_p, c_void_p, c_void_p, c_int,
                                 c_void_p, P(NuSho), P(c_double), P(c_int32), c_int, c_void_p, c_int64, c_int, c_int,
                                 ctypes.c_size_t, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

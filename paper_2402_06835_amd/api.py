@@ -304,6 +304,47 @@ def prepare_batch(ctx: Context, curves) -> dict:
     }
 
 
+def mask_transit(ctx: Context, ls: dict, dt: float, period: float, phase: int, half_width: int) -> dict:
+    """Mask a found candidate's transit windows in the linear-search outputs ``ls`` in place (entry point 3b,
+    Section 4): slots within ``half_width`` of phase + k period/dt, every duration. Returns ``ls``."""
+    depth, var, dll, valid = ls["depth"], ls["var"], ls["dll"], ls["valid"]
+    n_d, n_epochs = depth.shape
+    for x, dt_ in ((depth, torch.float64), (var, torch.float64), (dll, torch.float64), (valid, torch.uint8)):
+        if x.dtype != dt_ or not x.is_cuda or not x.is_contiguous() or tuple(x.shape) != (n_d, n_epochs):
+            raise ValueError("mask_transit: ls must hold the contiguous device outputs of linear_search")
+    _check(ctx.ptr, lib().nu_mask_transit(ctx.ptr, ctypes.c_void_p(depth.data_ptr()), ctypes.c_void_p(var.data_ptr()),
+                                          ctypes.c_void_p(dll.data_ptr()), ctypes.c_void_p(valid.data_ptr()), n_d,
+                                          n_epochs, float(dt), float(period), int(phase), int(half_width)))
+    return ls
+
+
+def search_planets(ctx: Context, ls: dict, dt: float, periods, durations, n_planets: int, sign: int = 1,
+                   copy: bool = True) -> list:
+    """Up to ``n_planets`` candidates from one linear search (Section 4): periodic search, mask the best
+    candidate's transits (windows of width 2 D), repeat. ``durations``: the box lengths in slots passed to
+    linear_search. With ``copy`` the masking works on copies of the grid, else ``ls`` is masked in place.
+    One stream synchronisation per candidate (to read its period, phase and duration)."""
+    if copy:
+        ls = {k: ls[k].clone() for k in ("depth", "var", "dll", "valid")}
+    durs = np.asarray(durations, dtype=np.int64)
+    per_host = periods.cpu().numpy() if isinstance(periods, torch.Tensor) else np.asarray(periods, dtype=np.float64)
+    found = []
+    for _ in range(int(n_planets)):
+        ps = periodic_search(ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], dt, periods, sign)
+        ip = int(ps["best_index"].item())
+        if ip < 0:
+            break
+        m = int(ps["best_phase"][ip].item())
+        if m < 0:
+            break
+        j = int(ps["best_dur"][ip].item())
+        found.append({"index": ip, "period": float(per_host[ip]), "phase": m, "dur_index": j,
+                      "snr": float(ps["q_snr"][ip].item()), "depth": float(ps["best_depth"][ip].item()),
+                      "lnp": float(ps["best_lnp"][ip].item())})
+        mask_transit(ctx, ls, dt, float(per_host[ip]), m, int(durs[j]))
+    return found
+
+
 def search_batch(ctx: Context, curves, durations, periods, precision: str = "fp32_refine", sign: int = 1,
                  memory_budget: int = 0, raise_not_pd: bool = True) -> dict:
     """Linear + periodic search of a batch of light curves of uneven length (entry point 4).
@@ -670,3 +711,16 @@ class Nuance:
         ls = self._ls
         raw = periodic_search(self.ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], self.dt, periods, sign)
         return SearchResult(periods, raw, self.t_first, self.dt, self._dur_slots)
+
+    def search_planets(self, periods, n_planets: int = 2, sign: int = 1) -> list:
+        """Several candidates from the one linear search (Section 4): each periodic search is followed by
+        masking the found transits (windows of width 2 D) in copies of the linear-search products.
+        Returns (period, t0, duration, depth, snr) per candidate."""
+        if self._ls is None:
+            raise RuntimeError("run linear_search first")
+        periods = np.asarray(periods, dtype=np.float64)
+        if np.any(~np.isfinite(periods)) or np.any(periods < self.dt):
+            raise ValueError("periods must be finite and at least one cadence")
+        found = search_planets(self.ctx, self._ls, self.dt, periods, self._dur_slots, n_planets, sign)
+        return [(c["period"], self.t_first + c["phase"] * self.dt, float(self._dur_slots[c["dur_index"]]) * self.dt,
+                 c["depth"], c["snr"]) for c in found]

@@ -326,6 +326,28 @@ nu_status nu_linear_search(nu_ctx* ctx, nu_factor* F, const double* f, const dou
 }
 
 // ---------------------------------------------------------------------------
+nu_status nu_mask_transit(nu_ctx* ctx, double* depth, double* var, double* dll, uint8_t* valid, int n_d,
+                          int64_t n_epochs, double dt, double period, int64_t phase, int half_width) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!depth || !var || !dll || !valid) return set_error(ctx, NU_ERR_ARG, "mask_transit: null argument");
+  if (n_d < 1 || n_d > MAX_ND) return set_error(ctx, NU_ERR_ARG, "mask_transit: n_d must be in [1, 16]");
+  if (n_epochs < 1 || n_epochs > ((int64_t)1 << 31))
+    return set_error(ctx, NU_ERR_ARG, "mask_transit: n_epochs must be in [1, 2^31]");
+  if (!(std::isfinite(dt) && dt > 0.0)) return set_error(ctx, NU_ERR_ARG, "mask_transit: dt must be finite and > 0");
+  const double p = period / dt;
+  if (!(std::isfinite(p) && p >= 1.0 && p <= 1e15))
+    return set_error(ctx, NU_ERR_ARG, "mask_transit: period must be at least one cadence (and finite)");
+  if (phase < 0 || phase >= n_epochs) return set_error(ctx, NU_ERR_ARG, "mask_transit: phase must be in [0, n_epochs)");
+  if (half_width < 1 || half_width > MAX_DUR)
+    return set_error(ctx, NU_ERR_ARG, "mask_transit: half_width must be in [1, 1024] slots");
+  nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+  Timed tm(ctx, "mask_transit", 0.0);
+  return check_hip(ctx, launch_mask_transit(ctx->stream, depth, var, dll, valid, n_d, n_epochs, p, phase, half_width),
+                   "mask_transit");
+}
+
+// ---------------------------------------------------------------------------
 nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var, const double* dll,
                              const uint8_t* valid, int n_d, int64_t n_epochs, double dt, const double* periods,
                              int64_t n_p, int log_term_sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,

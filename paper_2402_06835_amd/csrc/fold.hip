@@ -286,6 +286,41 @@ hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, co
 
 size_t fold_workspace_doubles(int n_d, int64_t n_epochs) { return (size_t)3 * n_d * (size_t)(n_epochs + FPAD); }
 
+// ---------------------------------------------------------------------------
+// Search for further candidates (Section 4, the search of TOI-540): the trial
+// epochs in windows of width 2 D centred on a found candidate's transits are
+// masked in the linear-search products, which the next periodic search then
+// skips. Transit k of the candidate sits at slot m + k p (any integer k), the
+// position the fold combines; slot i is masked, for every duration, when
+// |(i - m) - k p| < h for some k, evaluated with one rounding for k p (this
+// file is compiled without floating-point contraction). One thread per slot;
+// the k range covers [(i - m - h) / p, (i - m + h) / p] with a margin of one.
+__global__ __launch_bounds__(256) void mask_transit_kernel(double* __restrict__ depth, double* __restrict__ var,
+                                                           double* __restrict__ dll, uint8_t* __restrict__ valid,
+                                                           int n_d, int64_t n_t, double p, int64_t m, int h) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_t) return;
+  const double x = (double)(i - m), hd = (double)h;
+  const int64_t k_lo = (int64_t)floor((x - hd) / p) - 1, k_hi = (int64_t)ceil((x + hd) / p) + 1;
+  bool hit = false;
+  for (int64_t k = k_lo; k <= k_hi && !hit; ++k) hit = fabs(x - (double)k * p) < hd;
+  if (!hit) return;
+  for (int j = 0; j < n_d; ++j) {
+    const int64_t o = (int64_t)j * n_t + i;
+    depth[o] = 0.0;
+    var[o] = INFINITY;
+    dll[o] = 0.0;
+    valid[o] = 0;
+  }
+}
+
+hipError_t launch_mask_transit(hipStream_t s, double* depth, double* var, double* dll, uint8_t* valid, int n_d,
+                               int64_t n_t, double p, int64_t m, int h) {
+  hipLaunchKernelGGL(mask_transit_kernel, dim3((unsigned)((n_t + 255) / 256)), dim3(256), 0, s, depth, var, dll,
+                     valid, n_d, n_t, p, m, h);
+  return hipGetLastError();
+}
+
 // First period of largest Q (NaN never wins).
 __global__ __launch_bounds__(1024) void best_period_kernel(const double* __restrict__ q, int64_t n_p,
                                                            int64_t* __restrict__ out) {

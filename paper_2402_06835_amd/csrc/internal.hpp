@@ -319,6 +319,8 @@ hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, co
                        int sign, double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth,
                        double* best_sigma, double* best_lnp, double* packed);
 size_t fold_workspace_doubles(int n_d, int64_t n_epochs);
+hipError_t launch_mask_transit(hipStream_t s, double* depth, double* var, double* dll, uint8_t* valid, int n_d,
+                               int64_t n_t, double p, int64_t m, int h);
 hipError_t launch_best_period(hipStream_t s, const double* q_snr, int64_t n_p, int64_t* out);
 
 }  // namespace nu
