@@ -52,12 +52,26 @@ def workload(name: str):
     return {"tess-sector": config2, "plain-1440": config1}[name]()
 
 
-def run_step(api, ctx, dev_in, w, precision, fac=None):
+def run_step(api, ctx, dev_in, w, precision, fac=None, planets=1):
+    """gp_factor + linear_search + periodic_search; with planets > 1, the periodic search is repeated on the
+    same linear-search grid with each found candidate's transits masked (Section 4). Returns the factor,
+    the grid, the first periodic search and the candidates (None for planets == 1)."""
     fac = api.gp_factor(ctx, dev_in["t"], w.theta, out=fac)
     ls = api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations,
                            precision)
     ps = api.periodic_search(ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], w.dt, dev_in["periods"])
-    return fac, ls, ps
+    if planets <= 1:
+        return fac, ls, ps, None
+    # the first candidate comes from ps; the next ones from masked copies of the grid
+    ip = int(ps["best_index"].item())
+    cands = []
+    if ip >= 0:
+        m, j = int(ps["best_phase"][ip].item()), int(ps["best_dur"][ip].item())
+        cands.append({"period": float(w.periods[ip]), "phase": m, "dur_index": j, "snr": float(ps["q_snr"][ip].item())})
+        masked = api.mask_transit(ctx, {k: ls[k].clone() for k in ("depth", "var", "dll", "valid")}, w.dt,
+                                  float(w.periods[ip]), m, int(w.durations[j]))
+        cands += api.search_planets(ctx, masked, w.dt, dev_in["periods"], w.durations, planets - 1, copy=False)
+    return fac, ls, ps, cands
 
 
 def cpu_baseline(w, n_valid: int, budget_cells: int = 192, budget_periods: int = 4):
@@ -200,7 +214,7 @@ def bench_batch(args, api, ctx, torch):
         # the same curves one by one through the single-curve entry points
         valid = []
         for w, d in zip(ws, dev_in):
-            fac, ls, _ = run_step(api, ctx, d, w, args.precision)
+            fac, ls, _, _ = run_step(api, ctx, d, w, args.precision)
             valid.append(ls["valid"].reshape(-1))
             fac.close()
         return {"valid": torch.cat(valid)}
@@ -341,7 +355,7 @@ def bench_curve(args, api, ctx, torch):
                       w.theta, w.dt, dev_in["periods"], precision=args.precision)
     for i in range(max(args.warmup, 1)):
         if g is None:
-            fac, _, _ = run_step(api, ctx, dev_in, w, args.precision, fac)
+            fac, _, _, _ = run_step(api, ctx, dev_in, w, args.precision, fac, args.planets)
         else:
             g.launch()
         torch.cuda.synchronize()
@@ -354,7 +368,7 @@ def bench_curve(args, api, ctx, torch):
     for i in range(args.steps):
         # one curve per step; the factor's device buffers are reused across curves of one length
         if g is None:
-            keep = run_step(api, ctx, dev_in, w, args.precision, fac)
+            keep = run_step(api, ctx, dev_in, w, args.precision, fac, args.planets)
         else:
             g.launch()
         log(f"step {i + 1}/{args.steps} enqueued")
@@ -362,8 +376,9 @@ def bench_curve(args, api, ctx, torch):
     elapsed = time.perf_counter() - t0
     timings = ctx.timings()
     ctx.enable_timing(False)
+    cands = None
     if g is None:
-        fac, ls, ps = keep
+        fac, ls, ps, cands = keep
         got = dict(ls)
         got.update(ps)
     else:
@@ -388,6 +403,9 @@ def bench_curve(args, api, ctx, torch):
            "mode": args.mode}
     extra = {"best_period_days": float(w.periods[best]) if best >= 0 else None,
              "injected_period_days": w.injection["period"] if w.injection else None}
+    if args.planets > 1:
+        cfg["planets"] = args.planets
+        extra["candidates"] = cands
     return elapsed, n_valid, 1, timings, dll_err, cfg, extra, w
 
 
@@ -401,6 +419,9 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=12, help="training epochs of the learned workload")
     ap.add_argument("--precision", default="fp32_refine", choices=["fp64", "fp32_refine", "bf16x3_refine"])
     ap.add_argument("--mode", default="eager", choices=["eager", "graph", "loop"])
+    ap.add_argument("--planets", type=int, default=1,
+                    help="candidates per curve: after each periodic search the found transits are masked in the "
+                         "linear-search products and the periodic search is repeated (single-curve eager mode)")
     ap.add_argument("--autotune", action="store_true", help="tune the tile policy before warming up")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dll-check", action="store_true",
@@ -455,6 +476,8 @@ def main(argv=None):
     else:
         if args.mode == "loop":
             raise SystemExit("--mode loop compares against the batch (--workload batch-64)")
+        if args.planets > 1 and args.mode != "eager":
+            raise SystemExit("--planets applies to the eager single-curve step")
         elapsed, n_valid, curves, timings, dll_err, cfg, extra, w = bench_curve(args, api, ctx, torch)
     roof, gemms = (roofline_of(timings) if timings else (None, None))
     if roof is not None:
