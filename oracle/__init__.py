@@ -18,6 +18,8 @@ Contents (each function cites the passage it follows):
                        the linear-search grid onto phases, the common-depth
                        combination of Eq. 8 with the estimates of Eq. B4,
                        the argmax of Eq. 9 and Q(P) = depth/sigma.
+* ``oracle.segments``  The periodic search over several segments (sectors), each
+                       with its own linear search, on one global lattice.
 * ``oracle.multiplanet`` The iterative search for several candidates (Section 4):
                        mask the found candidate's transit windows in the
                        linear-search products and search again.
