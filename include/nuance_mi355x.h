@@ -171,6 +171,25 @@ nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var
                              int64_t n_p, int log_term_sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,
                              double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period_index);
 
+/* (3c) Periodic search over segments of one light curve, each with its own
+ * linear search (Sections 3.3 and 4: sectors observed apart, one GP and one
+ * linear search per sector, combined in the fold).
+ * Segment s covers the global lattice slots [seg_off_host[s],
+ * seg_off_host[s] + seg_len_host[s]) (host arrays, n_seg in 1 .. 32; ascending,
+ * at least 64 slots apart; the global slot 0 is the phase origin). Its grid,
+ * as produced by (2) for that segment, is the [n_d][seg_len_host[s]] block of
+ * depth/var/dll/valid (device) that follows the blocks of segments 0 .. s-1,
+ * i.e. the concatenated outputs of (2), or of (4) with one curve per segment.
+ * The result equals (3) on one global grid with every slot of no segment an
+ * invalid cell; phases (best_phase) are global slots. The fold skips the gaps,
+ * so its work is that of the segments. Outputs as in (3). */
+nu_status nu_periodic_search_segments(nu_ctx* ctx, const double* depth, const double* var, const double* dll,
+                                      const uint8_t* valid, int n_d, int n_seg, const int64_t* seg_len_host,
+                                      const int64_t* seg_off_host, double dt, const double* periods, int64_t n_p,
+                                      int log_term_sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,
+                                      double* best_depth, double* best_sigma, double* best_lnp,
+                                      int64_t* best_period_index);
+
 /* (3b) Search for further candidates (Section 4, the search of TOI-540): mask
  * a found candidate's transits in the linear-search outputs, in place, so
  * that the next periodic search (3) on them skips those epochs; the linear

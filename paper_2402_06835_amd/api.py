@@ -251,6 +251,59 @@ def periodic_search(ctx: Context, depth, var, dll, valid, dt: float, periods, si
     return out
 
 
+def periodic_search_segments(ctx: Context, grids, offsets, dt: float, periods, sign: int = 1) -> dict:
+    """Fold over segments of one light curve, each with its own linear search (entry point 3c).
+
+    grids: a list of per-segment linear-search outputs (dicts with depth, var, dll, valid of shape
+    (n_d, n_s)); offsets: the global lattice slot of each segment's first slot (ascending, at least 64
+    slots apart). Phases in the result are global slots."""
+    dev = ctx.device
+    if len(grids) < 1:
+        raise ValueError("need at least one segment")
+    n_d = None
+    parts = {k: [] for k in ("depth", "var", "dll", "valid")}
+    lens = []
+    for g in grids:
+        d = _dev_tensor(g["depth"], torch.float64, dev)
+        if d.ndim != 2:
+            raise ValueError("segment grids must be (n_d, n_s)")
+        n_d = d.shape[0] if n_d is None else n_d
+        if d.shape[0] != n_d:
+            raise ValueError("segments must share the durations")
+        for k, t in (("depth", torch.float64), ("var", torch.float64), ("dll", torch.float64), ("valid", torch.uint8)):
+            x = _dev_tensor(g[k], t, dev)
+            if tuple(x.shape) != tuple(d.shape):
+                raise ValueError("depth, var, dll, valid must share one shape per segment")
+            parts[k].append(x.reshape(-1))
+        lens.append(d.shape[1])
+    cat = {k: torch.cat(v).contiguous() for k, v in parts.items()}
+    lens_h = np.ascontiguousarray(lens, dtype=np.int64)
+    offs_h = np.ascontiguousarray([int(o) for o in offsets], dtype=np.int64)
+    if offs_h.size != lens_h.size:
+        raise ValueError("one offset per segment")
+    per = _dev_tensor(periods, torch.float64, dev)
+    n_p = per.numel()
+    out = {
+        "q_snr": torch.empty(n_p, dtype=torch.float64, device=dev),
+        "best_phase": torch.empty(n_p, dtype=torch.int64, device=dev),
+        "best_dur": torch.empty(n_p, dtype=torch.int32, device=dev),
+        "best_depth": torch.empty(n_p, dtype=torch.float64, device=dev),
+        "best_sigma": torch.empty(n_p, dtype=torch.float64, device=dev),
+        "best_lnp": torch.empty(n_p, dtype=torch.float64, device=dev),
+        "best_index": torch.empty(1, dtype=torch.int64, device=dev),
+    }
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    st = lib().nu_periodic_search_segments(
+        ctx.ptr, ctypes.c_void_p(cat["depth"].data_ptr()), ctypes.c_void_p(cat["var"].data_ptr()),
+        ctypes.c_void_p(cat["dll"].data_ptr()), ctypes.c_void_p(cat["valid"].data_ptr()), int(n_d), len(lens),
+        lens_h.ctypes.data_as(P64), offs_h.ctypes.data_as(P64), float(dt), ctypes.c_void_p(per.data_ptr()), n_p,
+        int(sign), *[ctypes.c_void_p(out[k].data_ptr()) for k in ("q_snr", "best_phase", "best_dur", "best_depth",
+                                                                  "best_sigma", "best_lnp", "best_index")])
+    _check(ctx.ptr, st)
+    out["_keep"] = (cat, per)
+    return out
+
+
 _PERIOD_KEYS = ("q_snr", "best_phase", "best_dur", "best_depth", "best_sigma", "best_lnp")
 _PERIOD_DTYPES = (torch.float64, torch.int64, torch.int32, torch.float64, torch.float64, torch.float64)
 

@@ -366,4 +366,48 @@ nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var
                       best_phase, best_dur, best_depth, best_sigma, best_lnp, best_period_index, ws);
 }
 
+// ---------------------------------------------------------------------------
+nu_status nu_periodic_search_segments(nu_ctx* ctx, const double* depth, const double* var, const double* dll,
+                                      const uint8_t* valid, int n_d, int n_seg, const int64_t* seg_len_host,
+                                      const int64_t* seg_off_host, double dt, const double* periods, int64_t n_p,
+                                      int log_term_sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,
+                                      double* best_depth, double* best_sigma, double* best_lnp,
+                                      int64_t* best_period_index) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!depth || !var || !dll || !valid || !periods || !q_snr || !best_phase || !best_dur || !best_depth ||
+      !best_sigma || !best_lnp || !seg_len_host || !seg_off_host)
+    return set_error(ctx, NU_ERR_ARG, "periodic_search_segments: null argument");
+  if (n_seg < 1 || n_seg > MAX_SEG)
+    return set_error(ctx, NU_ERR_ARG, "periodic_search_segments: n_seg must be in [1, 32]");
+  for (int s = 0; s < n_seg; ++s) {
+    if (seg_len_host[s] < 1 || seg_off_host[s] < 0)
+      return set_error(ctx, NU_ERR_ARG, "periodic_search_segments: segment lengths >= 1 and offsets >= 0 required");
+    if (s > 0 && seg_off_host[s] < seg_off_host[s - 1] + seg_len_host[s - 1] + 64)
+      return set_error(ctx, NU_ERR_ARG,
+                       "periodic_search_segments: segments must be ascending and at least 64 slots apart");
+  }
+  const int64_t extent = seg_off_host[n_seg - 1] + seg_len_host[n_seg - 1];
+  nu_status st = validate_periodic(ctx, n_d, extent, dt, n_p, log_term_sign);
+  if (st != NU_OK) return st;
+  st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+  double* ws =
+      (double*)ctx_workspace(ctx, fold_segments_workspace_doubles(n_d, seg_len_host, n_seg) * sizeof(double), &st);
+  if (!ws) return st;
+  int64_t cells = 0;
+  for (int s = 0; s < n_seg; ++s) cells += (int64_t)n_d * seg_len_host[s];
+  {
+    Timed tm(ctx, "fold", 24.0 * (double)cells * (double)n_p);
+    st = check_hip(ctx, launch_fold_segments(ctx->stream, depth, var, dll, valid, n_d, n_seg, seg_len_host,
+                                             seg_off_host, dt, periods, n_p, log_term_sign, q_snr, best_phase,
+                                             best_dur, best_depth, best_sigma, best_lnp, ws),
+                   "fold_segments");
+  }
+  if (st == NU_OK && best_period_index) {
+    Timed tm(ctx, "best_period", 0.0);
+    st = check_hip(ctx, launch_best_period(ctx->stream, q_snr, n_p, best_period_index), "best_period");
+  }
+  return st;
+}
+
 }  // extern "C"

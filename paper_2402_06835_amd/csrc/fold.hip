@@ -71,6 +71,36 @@ __device__ __forceinline__ double from_next_lane(double x) {
   return __hiloint2double(hi, lo);
 }
 
+// Segments of one global lattice (sectors with their own linear searches):
+// segment s covers global slots [off[s], off[s] + len[s]); the packed grid
+// holds each segment's slots at [pstart[s], pstart[s] + len[s]) of a row,
+// with FPAD invalid slots before and after every segment, and the caller's
+// grid holds segment s as an [n_d][len[s]] block at in_start[s].
+struct Segs {
+  int n;
+  int64_t off[MAX_SEG], len[MAX_SEG], pstart[MAX_SEG], in_start[MAX_SEG];
+};
+
+// Event base b of a wave (global slot mb + b for lane 0) on a segmented grid:
+// advances the segment cursor and gives the packed offset of the window in
+// *delta; or, when the 64-slot window lies in the gap before segment *seg,
+// returns false with the next k worth trying (one below the first k whose
+// window could reach the segment, to stay clear of rounding in k p).
+// Segments are at least FPAD slots apart, so a window touches one segment and
+// the lanes outside it read that segment's padding.
+__device__ __forceinline__ bool seg_event(const Segs& S, int64_t mb, int64_t b, int64_t k, double p, int& seg,
+                                          int64_t& delta, int64_t& knext) {
+  const int64_t g0 = mb + b;
+  while (seg < S.n - 1 && g0 > S.off[seg] + S.len[seg] - 1) ++seg;
+  if (g0 + 63 < S.off[seg]) {
+    const int64_t kj = (int64_t)ceil((double)(S.off[seg] - 63 - mb) / p) - 1;
+    knext = kj > k ? kj : k + 1;
+    return false;
+  }
+  delta = S.pstart[seg] - S.off[seg];
+  return true;
+}
+
 // Eq. 8 with the estimates of Eq. B4, for the durations j0 .. j0+JG-1 and the
 // phases m = mb + lane of one wave. All lanes share base_k = floor(k p) and
 // w_k, so an event's right-hand slot is the next lane's left-hand slot.
@@ -88,11 +118,10 @@ __device__ __forceinline__ double from_next_lane(double x) {
 //         = (sum_k d_k^2 / v_k - D^2 S_w) / (1 + sigma^2 / v_min).
 // A skipped cell's lnP is below a value some cell reaches, so the argmax and
 // every per-period output are unchanged; a relative margin covers rounding.
-template <int JG>  // durations per pass over the events
+template <int JG, bool SEG>  // durations per pass over the events; segmented grid
 __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const double* __restrict__ Lp, int n_d,
-                                           int64_t n_t, int j0, int64_t mb, int lane, int64_t nph, double p,
-                                           double sign, double thr, Best& best) {
-  const int64_t ld = n_t + FPAD;
+                                           int64_t n_t, int64_t ld, const Segs& S, int j0, int64_t mb, int lane,
+                                           int64_t nph, double p, double sign, double thr, Best& best) {
   const int64_t m = mb + lane;
   const int64_t kmax_base = n_t - 1 - mb;  // events while base_k <= this (uniform)
   int64_t row[JG];
@@ -107,11 +136,20 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
     cnt[g] = 0;
   }
   // pass 1
+  int seg = 0;
   for (int64_t k = 0;; ++k) {
     const double kp = (double)k * p;
     const double base = floor(kp);
     if (base > (double)kmax_base) break;
-    const int64_t b = (int64_t)base;
+    int64_t b = (int64_t)base;
+    if constexpr (SEG) {
+      int64_t delta, knext;
+      if (!seg_event(S, mb, b, k, p, seg, delta, knext)) {
+        k = knext - 1;
+        continue;
+      }
+      b += delta;
+    }
     const double w = kp - base;
     const double u = 1.0 - w;
     double2 dv[JG];
@@ -162,11 +200,20 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
   }
   if (!any_need) return;
   // pass 2
+  seg = 0;
   for (int64_t k = 0;; ++k) {
     const double kp = (double)k * p;
     const double base = floor(kp);
     if (base > (double)kmax_base) break;
-    const int64_t b = (int64_t)base;
+    int64_t b = (int64_t)base;
+    if constexpr (SEG) {
+      int64_t delta, knext;
+      if (!seg_event(S, mb, b, k, p, seg, delta, knext)) {
+        k = knext - 1;
+        continue;
+      }
+      b += delta;
+    }
     const double w = kp - base;
     const double u = 1.0 - w;
     double2 dv[JG];
@@ -202,9 +249,9 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
   }
 }
 
-template <int JG>
+template <int JG, bool SEG>
 __global__ __launch_bounds__(256, 3) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
-                                                   int n_d, int64_t n_t, double dt,
+                                                   int n_d, int64_t n_t, int64_t ld, const Segs S, double dt,
                                                    const double* __restrict__ periods, double sign,
                                                    double* __restrict__ q_snr, int64_t* __restrict__ best_phase,
                                                    int32_t* __restrict__ best_dur, double* __restrict__ best_depth,
@@ -227,7 +274,7 @@ __global__ __launch_bounds__(256, 3) void fold_kernel(const double2* __restrict_
       for (int j0 = 0; j0 < n_d; j0 += JG) {
         // read without synchronisation: a stale value only prunes less
         const double thr = fmax(fmax(wb[0], wb[1]), fmax(wb[2], wb[3]));
-        fold_cells<JG>(DV, Lp, n_d, n_t, j0, mb, lane, nph, p, sign, thr, best);
+        fold_cells<JG, SEG>(DV, Lp, n_d, n_t, ld, S, j0, mb, lane, nph, p, sign, thr, best);
         double v = best.flat >= 0 ? best.val : -INFINITY;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -261,6 +308,22 @@ __global__ __launch_bounds__(256, 3) void fold_kernel(const double2* __restrict_
   }
 }
 
+// durations per pass: 5 when that pads fewer cells than 4 (10 durations: 10 rather than 12)
+template <bool SEG>
+static hipError_t launch_fold_kernel(hipStream_t s, const double2* DV, const double* Lp, int n_d, int64_t n_t,
+                                     int64_t ld, const Segs& S, double dt, const double* periods, int64_t n_p,
+                                     int sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,
+                                     double* best_depth, double* best_sigma, double* best_lnp) {
+  const int pad4 = (n_d + 3) / 4 * 4, pad5 = (n_d + 4) / 5 * 5;
+  if (pad5 < pad4)
+    hipLaunchKernelGGL((fold_kernel<5, SEG>), dim3((unsigned)n_p), dim3(256), 0, s, DV, Lp, n_d, n_t, ld, S, dt,
+                       periods, (double)sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp);
+  else
+    hipLaunchKernelGGL((fold_kernel<4, SEG>), dim3((unsigned)n_p), dim3(256), 0, s, DV, Lp, n_d, n_t, ld, S, dt,
+                       periods, (double)sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp);
+  return hipGetLastError();
+}
+
 hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, const double* dll,
                        const uint8_t* valid, int n_d, int64_t n_epochs, double dt, const double* periods, int64_t n_p,
                        int sign, double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth,
@@ -273,15 +336,75 @@ hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, co
                      n_d, n_epochs, DV, Lp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // durations per pass: 5 when that pads fewer cells than 4 (10 durations: 10 rather than 12)
-  const int pad4 = (n_d + 3) / 4 * 4, pad5 = (n_d + 4) / 5 * 5;
-  if (pad5 < pad4)
-    hipLaunchKernelGGL(fold_kernel<5>, dim3((unsigned)n_p), dim3(256), 0, s, DV, Lp, n_d, n_epochs, dt, periods,
-                       (double)sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp);
-  else
-    hipLaunchKernelGGL(fold_kernel<4>, dim3((unsigned)n_p), dim3(256), 0, s, DV, Lp, n_d, n_epochs, dt, periods,
-                       (double)sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp);
-  return hipGetLastError();
+  return launch_fold_kernel<false>(s, DV, Lp, n_d, n_epochs, ld, Segs{}, dt, periods, n_p, sign, q_snr, best_phase,
+                                   best_dur, best_depth, best_sigma, best_lnp);
+}
+
+// Packed grid of a segmented search (layout in Segs).
+__global__ __launch_bounds__(256) void fold_pack_segments_kernel(const double* __restrict__ depth,
+                                                                 const double* __restrict__ var,
+                                                                 const double* __restrict__ dll,
+                                                                 const uint8_t* __restrict__ valid, int n_d,
+                                                                 const Segs S, int64_t ld, double2* __restrict__ DV,
+                                                                 double* __restrict__ Lp) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n_d * ld) return;
+  const int j = (int)(e / ld);
+  const int64_t pos = e - (int64_t)j * ld;
+  double d = 0.0, v = NAN, l = 0.0;
+  for (int s = 0; s < S.n; ++s)
+    if (pos >= S.pstart[s] && pos < S.pstart[s] + S.len[s]) {
+      const int64_t o = S.in_start[s] + (int64_t)j * S.len[s] + (pos - S.pstart[s]);
+      if (valid[o]) {
+        d = depth[o];
+        v = var[o];
+        l = dll[o];
+      }
+      break;
+    }
+  DV[e] = make_double2(d, v);
+  Lp[e] = l;
+}
+
+// row length of the packed grid of a segmented search
+static int64_t seg_row(const int64_t* len, int n_seg) {
+  int64_t t = FPAD;
+  for (int s = 0; s < n_seg; ++s) t += len[s] + FPAD;
+  return t;
+}
+
+size_t fold_segments_workspace_doubles(int n_d, const int64_t* len, int n_seg) {
+  return (size_t)3 * n_d * (size_t)seg_row(len, n_seg);
+}
+
+hipError_t launch_fold_segments(hipStream_t s, const double* depth, const double* var, const double* dll,
+                                const uint8_t* valid, int n_d, int n_seg, const int64_t* seg_len,
+                                const int64_t* seg_off, double dt, const double* periods, int64_t n_p, int sign,
+                                double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth,
+                                double* best_sigma, double* best_lnp, double* packed) {
+  if (n_seg < 1 || n_seg > MAX_SEG) return hipErrorInvalidValue;
+  Segs S{};
+  S.n = n_seg;
+  int64_t pstart = FPAD, in_start = 0;
+  for (int i = 0; i < n_seg; ++i) {
+    S.off[i] = seg_off[i];
+    S.len[i] = seg_len[i];
+    S.pstart[i] = pstart;
+    S.in_start[i] = in_start;
+    pstart += seg_len[i] + FPAD;
+    in_start += (int64_t)n_d * seg_len[i];
+  }
+  const int64_t ld = seg_row(seg_len, n_seg);
+  const int64_t n_t = seg_off[n_seg - 1] + seg_len[n_seg - 1];  // global extent
+  double2* DV = reinterpret_cast<double2*>(packed);
+  double* Lp = packed + 2 * (int64_t)n_d * ld;
+  const int64_t tot = (int64_t)n_d * ld;
+  hipLaunchKernelGGL(fold_pack_segments_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, depth, var, dll,
+                     valid, n_d, S, ld, DV, Lp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_fold_kernel<true>(s, DV, Lp, n_d, n_t, ld, S, dt, periods, n_p, sign, q_snr, best_phase, best_dur,
+                                  best_depth, best_sigma, best_lnp);
 }
 
 size_t fold_workspace_doubles(int n_d, int64_t n_epochs) { return (size_t)3 * n_d * (size_t)(n_epochs + FPAD); }

@@ -27,6 +27,7 @@ constexpr int MAX_M1 = 7;        // trend columns
 constexpr int YCOLS = 8;         // row stride of the whitened [A | f] panel
 constexpr int MAX_ND = 16;       // durations per search
 constexpr int MAX_DUR = 1024;    // samples per box
+constexpr int MAX_SEG = 32;      // segments of a segmented periodic search
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -319,6 +320,12 @@ hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, co
                        int sign, double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth,
                        double* best_sigma, double* best_lnp, double* packed);
 size_t fold_workspace_doubles(int n_d, int64_t n_epochs);
+size_t fold_segments_workspace_doubles(int n_d, const int64_t* len, int n_seg);
+hipError_t launch_fold_segments(hipStream_t s, const double* depth, const double* var, const double* dll,
+                                const uint8_t* valid, int n_d, int n_seg, const int64_t* seg_len,
+                                const int64_t* seg_off, double dt, const double* periods, int64_t n_p, int sign,
+                                double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth,
+                                double* best_sigma, double* best_lnp, double* packed);
 hipError_t launch_mask_transit(hipStream_t s, double* depth, double* var, double* dll, uint8_t* valid, int n_d,
                                int64_t n_t, double p, int64_t m, int h);
 hipError_t launch_best_period(hipStream_t s, const double* q_snr, int64_t n_p, int64_t* out);
