@@ -259,6 +259,64 @@ def bench_batch(args, api, ctx, torch):
     return elapsed, n_valid, len(ws), timings, dll_err, cfg, {"injected_recovered": f"{found}/{n_inj}"}
 
 
+def bench_two_sectors(args, api, ctx, torch):
+    """Two TESS-sector curves a year apart, one star: per step, each sector's gp_factor + linear_search, then
+    one segmented periodic search over both (the fold skips the year-long gap)."""
+    from synth.lightcurve import two_sectors
+    ws, offs = two_sectors()
+    dev = ctx.device
+    dev_in = [{"t": torch.as_tensor(w.t, device=dev), "f": torch.as_tensor(w.f, device=dev),
+               "A": torch.as_tensor(w.A, device=dev), "lattice": torch.as_tensor(w.lattice, device=dev)} for w in ws]
+    per = torch.as_tensor(ws[0].periods, device=dev)
+    dt, durs = ws[0].dt, ws[0].durations
+    facs = [None, None]
+
+    def one_step(precision):
+        grids = []
+        for i, (w, d) in enumerate(zip(ws, dev_in)):
+            facs[i] = api.gp_factor(ctx, d["t"], w.theta, out=facs[i])
+            grids.append(api.linear_search(ctx, facs[i], d["f"], d["A"], d["lattice"], w.n_epochs, durs, precision))
+        ps = api.periodic_search_segments(ctx, grids, offs, dt, per)
+        return grids, ps
+
+    for i in range(max(args.warmup, 1)):
+        one_step(args.precision)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    ctx.enable_timing(True)
+    ctx.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        grids, ps = one_step(args.precision)
+        log(f"step {i + 1}/{args.steps} enqueued")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timings = ctx.timings()
+    ctx.enable_timing(False)
+    n_valid = int(sum(int(g["valid"].sum().item()) for g in grids))
+    best = int(ps["best_index"].item())
+    err = None
+    if args.precision != "fp64" and not args.no_dll_check:
+        ref_grids, ref_ps = one_step("fp64")
+        got = {k: torch.cat([g[k].reshape(-1) for g in grids]) for k in ("depth", "var", "dll", "valid")}
+        ref = {k: torch.cat([g[k].reshape(-1) for g in ref_grids]) for k in ("depth", "var", "dll", "valid")}
+        got.update({k: ps[k] for k in ("q_snr", "best_phase", "best_dur")})
+        ref.update({k: ref_ps[k] for k in ("q_snr", "best_phase", "best_dur")})
+        err = output_errors(got, ref)
+        log(f"errors vs fp64: {err}")
+    p_true = ws[0].injection["period"]
+    log(f"{args.steps} steps in {elapsed:.3f} s: {n_valid * args.steps / elapsed:.4g} fits/s; best period "
+        f"{float(ws[0].periods[best]) if best >= 0 else None} (injected {p_true:.4f})")
+    cfg = {"workload": "two-tess-sectors-N2x18000-gap1yr", "sectors": 2, "n_samples": [w.n for w in ws],
+           "offsets_slots": offs, "n_durations": int(len(durs)), "n_periods": int(len(ws[0].periods)),
+           "valid_cells": n_valid, "precision": args.precision, "mode": "eager"}
+    extra = {"best_period_days": float(ws[0].periods[best]) if best >= 0 else None, "injected_period_days": p_true,
+             "best_t0_days": float(ps["best_phase"][best].item()) * dt if best >= 0 else None,
+             "injected_t0_days": float(ws[0].injection["global_t0"])}
+    return elapsed, n_valid, 2, timings, err, cfg, extra
+
+
 def bench_learned(args, api, ctx, torch):
     """The learned warm start at the TESS-sector shape: 100000 training curves drawn from the
     GP on the device, the CNN trained on them, then 256 held-out curves fitted by BFGS from the
@@ -415,7 +473,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tess-sector",
-                    choices=["tess-sector", "plain-1440", "batch-64", "learned"])
+                    choices=["tess-sector", "plain-1440", "batch-64", "learned", "two-sectors"])
     ap.add_argument("--epochs", type=int, default=12, help="training epochs of the learned workload")
     ap.add_argument("--precision", default="fp32_refine", choices=["fp64", "fp32_refine", "bf16x3_refine"])
     ap.add_argument("--mode", default="eager", choices=["eager", "graph", "loop"])
@@ -473,6 +531,10 @@ def main(argv=None):
         if args.mode == "graph":
             raise SystemExit("the batch runs through its own entry point (--mode eager, or loop)")
         elapsed, n_valid, curves, timings, dll_err, cfg, extra = bench_batch(args, api, ctx, torch)
+    elif args.workload == "two-sectors":
+        if args.mode != "eager" or args.planets > 1:
+            raise SystemExit("the two-sector search runs eager, one candidate")
+        elapsed, n_valid, curves, timings, dll_err, cfg, extra = bench_two_sectors(args, api, ctx, torch)
     else:
         if args.mode == "loop":
             raise SystemExit("--mode loop compares against the batch (--workload batch-64)")

@@ -8,6 +8,7 @@ from .lightcurve import (  # noqa: F401
     config1,
     config2,
     config3,
+    two_sectors,
     principle_e1,
     make_workload,
     lattice_box_mask,

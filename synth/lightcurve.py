@@ -232,6 +232,35 @@ def config2(seed: int = 2) -> Workload:
     return w
 
 
+def two_sectors(seed: int = 8, gap_slots: int = 262800):
+    """Two TESS-sector-shaped curves (as config2: N = 18000 at 2 min, 1-d mid-sector gap) a year apart
+    (gap_slots empty slots between them), each with its own rotation GP, and one planet through both:
+    depth 1e-3, duration 36 samples, period = the trial period of index 7402 (5.0005 d; on the grid, since
+    over a one-year baseline a period between grid points drifts the later transits out of their box),
+    first transit at global time 1234 dt. Returns the two workloads (each on its own lattice from 0, its
+    injection epoch shifted into it) and their global slot offsets."""
+    rng = np.random.default_rng(seed)
+    dt = 2 * MINUTE
+    q = 5.0
+    periods = linspace_periods(0.3, 13.0, 20000)
+    period, t0_global = float(periods[7402]), 1234 * dt
+    out, offs = [], []
+    off = 0
+    for c in range(2):
+        prot = _log_uniform(rng, 0.3, 2.0)
+        amp = _log_uniform(rng, 0.005, 0.03)
+        theta = {"amp": amp, "omega": sho_omega_from_rotation(prot, q), "q": q, "sigma_w": 8e-4}
+        inj = {"depth": 1e-3, "period": period, "duration": 36 * dt,
+               "t0": float((t0_global - off * dt) % period), "global_t0": t0_global}
+        w = make_workload(f"sector-{c}", seed * 10 + c, 18000, dt, theta, [9 * k for k in range(1, 11)],
+                          periods, gaps=[(8999, 720)], injection=inj, rng=rng)
+        w.extra["prot"] = prot
+        out.append(w)
+        offs.append(off)
+        off += int(w.n_epochs) + gap_slots
+    return out, offs
+
+
 def config3(n_curves: int = 64, base_seed: int = 3000):
     """Uneven batch: curves of N uniform in {4000..20000} samples at 2 min."""
     out = []
