@@ -86,3 +86,54 @@ def test_cholesky_textbook_flags_non_pd():
     K = np.ones((4, 4))  # rank one
     with pytest.raises(np.linalg.LinAlgError):
         gp.cholesky_textbook(K)
+
+
+# ---------------------------------------------------------------------------
+# The Section 3.2 stellar-variability kernel (sum of terms)
+
+def test_single_sho_term_is_the_sho_covariance():
+    from oracle import gp as g
+    t = np.sort(np.random.default_rng(1).uniform(0, 5, 60))
+    th = {"amp": 0.01, "omega": 3.1, "q": 4.0, "sigma_w": 1e-3}
+    a = g.covariance(t, th)
+    b = g.covariance_terms(t, {"sho": [(0.01, 3.1, 4.0)]}, 1e-3)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_rotation_terms_variance_split_and_periods():
+    from oracle import gp as g
+    sigma, P, q0, dq, f = 0.02, 1.3, 2.0, 3.0, 0.4
+    terms = g.rotation_terms(sigma, P, q0, dq, f, 0.003, 0.05, 0.005, 7.0)
+    (a1, w1, q1), (a2, w2, q2) = terms["sho"]
+    # k1(0) + k2(0) = sigma^2, split 1 : f
+    assert a1 ** 2 + a2 ** 2 == pytest.approx(sigma ** 2, rel=1e-14)
+    assert a2 ** 2 / a1 ** 2 == pytest.approx(f, rel=1e-14)
+    assert q1 == 0.5 + q0 + dq and q2 == 0.5 + q0 and w2 == 2 * w1
+    # the damped oscillation of k1 has period P: sin/cos argument g omega tau / (2 Q) = 2 pi tau / P
+    gq = np.sqrt(4 * q1 ** 2 - 1)
+    assert gq * w1 / (2 * q1) == pytest.approx(2 * np.pi / P, rel=1e-14)
+    K = g.covariance_terms(np.array([0.0]), terms, 0.001)
+    assert K[0, 0] == pytest.approx(sigma ** 2 + 0.003 ** 2 + 0.005 ** 2 + 0.001 ** 2, rel=1e-14)
+
+
+def test_exponential_term_has_a_tridiagonal_inverse():
+    # an exponential covariance on any grid is Markov (AR(1)): its precision matrix is tridiagonal,
+    # which pins exp(-|tau|/ell) against e.g. a squared exponential
+    from oracle import gp as g
+    t = np.sort(np.random.default_rng(2).uniform(0, 3, 40))
+    K = g.covariance_terms(t, {"exp": [(0.7, 0.4)]}, 0.0)
+    Pm = np.linalg.inv(K)
+    off = np.abs(np.triu(Pm, 2)).max() / np.abs(Pm).max()
+    assert off < 1e-10
+
+
+def test_rotation_covariance_is_positive_definite():
+    from oracle import gp as g
+    rng = np.random.default_rng(3)
+    t = np.arange(300) * (2 / 1440)
+    for _ in range(5):
+        terms = g.rotation_terms(rng.uniform(0.005, 0.03), rng.uniform(0.3, 3), rng.uniform(0.1, 5),
+                                 rng.uniform(0.01, 5), rng.uniform(0.05, 1), rng.uniform(1e-4, 2e-3),
+                                 rng.uniform(0.005, 0.05), rng.uniform(1e-4, 5e-3), rng.uniform(1, 20))
+        K = g.covariance_terms(t, terms, rng.uniform(3e-4, 2e-3))
+        g.cholesky(K)
