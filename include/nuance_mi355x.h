@@ -85,6 +85,25 @@ typedef struct {
   double sigma_w;
 } nu_sho;
 
+/* A GP covariance as a sum of terms: the stellar-variability kernel of
+ * Section 3.2 is k = k1 + k2 + k3 + k4 with two SHO terms (at the rotation
+ * period and half of it) and two exponential terms.
+ *   k(tau) = sum_{s < n_sho} SHO(tau; sho_amp[s], sho_omega[s], sho_q[s])   (as nu_sho)
+ *          + sum_{e < n_exp} exp_sigma[e]^2 exp(-tau / exp_ell[e]),
+ *   K[n][m] = k(|t_n - t_m|) + sigma_w^2 delta_nm.
+ * Requires 0 <= n_sho, n_exp <= 4; amp >= 0, omega > 0, q > 0, sigma >= 0,
+ * ell > 0, sigma_w >= 0, all finite. */
+typedef struct {
+  int32_t n_sho;
+  int32_t n_exp;
+  double sho_amp[4];
+  double sho_omega[4];
+  double sho_q[4];
+  double exp_sigma[4];
+  double exp_ell[4];
+  double sigma_w;
+} nu_kernel;
+
 typedef struct nu_ctx nu_ctx;
 typedef struct nu_factor nu_factor;
 
@@ -119,6 +138,13 @@ nu_status nu_ctx_timing_entry(nu_ctx* ctx, int index, const char** name_host, in
  * no factor is returned. logdet_host (ln|K|) and fail_pivot_host may be NULL. */
 nu_status nu_gp_factor(nu_ctx* ctx, const double* t, int64_t n, const nu_sho* theta, nu_factor** out,
                        double* logdet_host, int64_t* fail_pivot_host);
+
+/* (1b) GP factor of a sum-of-terms covariance (nu_kernel, e.g. the rotation
+ * kernel of Section 3.2): as (1), with K built from kernel_host. The factor
+ * then serves (2) like any other; nu_gp_factor_into with a nu_sho turns it
+ * back into a single-SHO factor. */
+nu_status nu_gp_factor_kernel(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel* kernel_host,
+                              nu_factor** out, double* logdet_host, int64_t* fail_pivot_host);
 /* (1b) Same as (1) into an existing factor of the same n (its device buffers
  * are reused; no allocation). On NU_ERR_NOT_PD the factor's contents are
  * undefined until the next successful call. */

@@ -25,6 +25,12 @@ class NuSho(ctypes.Structure):
     _fields_ = [("amp", c_double), ("omega", c_double), ("q", c_double), ("sigma_w", c_double)]
 
 
+class NuKernel(ctypes.Structure):
+    _fields_ = [("n_sho", c_int32), ("n_exp", c_int32), ("sho_amp", c_double * 4), ("sho_omega", c_double * 4),
+                ("sho_q", c_double * 4), ("exp_sigma", c_double * 4), ("exp_ell", c_double * 4),
+                ("sigma_w", c_double)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "nu_ctx_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
@@ -37,6 +43,7 @@ SIGNATURES = {
     "nu_ctx_timing_count": (c_int, [c_void_p]),
     "nu_ctx_timing_entry": (c_int, [c_void_p, c_int, P(c_char_p), P(c_int64), P(c_double), P(c_double)]),
     "nu_gp_factor": (c_int, [c_void_p, c_void_p, c_int64, P(NuSho), P(c_void_p), P(c_double), P(c_int64)]),
+    "nu_gp_factor_kernel": (c_int, [c_void_p, c_void_p, c_int64, P(NuKernel), P(c_void_p), P(c_double), P(c_int64)]),
     "nu_gp_factor_into": (c_int, [c_void_p, c_void_p, c_void_p, c_int64, P(NuSho), P(c_double), P(c_int64)]),
     "nu_factor_destroy": (None, [c_void_p]),
     "nu_factor_n": (c_int64, [c_void_p]),

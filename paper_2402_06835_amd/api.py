@@ -12,13 +12,14 @@ and converts arguments, allocates outputs with torch and passes pointers.
 from __future__ import annotations
 
 import ctypes
-from dataclasses import dataclass
+import math
+from dataclasses import dataclass, field
 from typing import Optional
 
 import numpy as np
 import torch
 
-from ._lib import NU_ERR_NOT_PD, NU_OK, PRECISIONS, TUNE_CLASSES, NuanceError, NuSho, lib
+from ._lib import NU_ERR_NOT_PD, NU_OK, PRECISIONS, TUNE_CLASSES, NuanceError, NuKernel, NuSho, lib
 
 
 def _check(ctx_ptr, status: int):
@@ -143,14 +144,66 @@ class Factor:
             pass
 
 
-def gp_factor(ctx: Context, t, theta, out: Optional[Factor] = None) -> Factor:
-    """K = k_SHO + sigma_w^2 I built and factored on the device (one stream sync).
+@dataclass
+class Kernel:
+    """A covariance as a sum of terms (entry point 1b): SHO terms (amp, omega, q), exponential terms
+    (sigma, ell): sigma^2 exp(-|tau| / ell), and sigma_w^2 on the diagonal."""
 
-    With ``out`` (a factor of the same length) its device buffers are reused."""
+    sho: list = field(default_factory=list)
+    exp: list = field(default_factory=list)
+    sigma_w: float = 0.0
+
+    def c(self) -> NuKernel:
+        if len(self.sho) > 4 or len(self.exp) > 4:
+            raise ValueError("at most 4 SHO and 4 exponential terms")
+        k = NuKernel()
+        k.n_sho, k.n_exp = len(self.sho), len(self.exp)
+        for i, (a, w, q) in enumerate(self.sho):
+            k.sho_amp[i], k.sho_omega[i], k.sho_q[i] = float(a), float(w), float(q)
+        for i, (sg, ell) in enumerate(self.exp):
+            k.exp_sigma[i], k.exp_ell[i] = float(sg), float(ell)
+        k.sigma_w = float(self.sigma_w)
+        return k
+
+
+def rotation_kernel(sigma: float, period: float, q0: float, dq: float, f: float, sigma_short: float,
+                    ell_short: float, sigma_long: float, ell_long: float, sigma_w: float) -> Kernel:
+    """The stellar-variability kernel of Section 3.2, k = k1 + k2 + k3 + k4 (8 hyperparameters, plus the
+    white-noise diagonal): SHO terms at the rotation period P and at P/2,
+        Q1 = 1/2 + Q0 + dQ, omega1 = 4 pi Q1 / (P sqrt(4 Q1^2 - 1)), S1 = sigma^2 / ((1 + f) omega1 Q1),
+        Q2 = 1/2 + Q0,      omega2 = 2 omega1,                       S2 = f sigma^2 / ((1 + f) omega2 Q2),
+    each with k(0) = S0 omega Q, and the short and long exponential terms."""
+    q1 = 0.5 + q0 + dq
+    w1 = 4.0 * math.pi * q1 / (period * math.sqrt(4.0 * q1 * q1 - 1.0))
+    s1 = sigma * sigma / ((1.0 + f) * w1 * q1)
+    q2 = 0.5 + q0
+    w2 = 2.0 * w1
+    s2 = f * sigma * sigma / ((1.0 + f) * w2 * q2)
+    return Kernel(sho=[(math.sqrt(s1 * w1 * q1), w1, q1), (math.sqrt(s2 * w2 * q2), w2, q2)],
+                  exp=[(sigma_short, ell_short), (sigma_long, ell_long)], sigma_w=sigma_w)
+
+
+def gp_factor(ctx: Context, t, theta, out: Optional[Factor] = None) -> Factor:
+    """K = k_SHO + sigma_w^2 I (``theta``: SHO or dict), or a sum of terms (``theta``: Kernel), built and
+    factored on the device (one stream sync).
+
+    With ``out`` (a factor of the same length; SHO only) its device buffers are reused."""
     t_dev = _dev_tensor(t, torch.float64, ctx.device)
-    sho = theta if isinstance(theta, SHO) else SHO.from_dict(theta)
     logdet = ctypes.c_double()
     pivot = ctypes.c_int64(-1)
+    if isinstance(theta, Kernel):
+        if out is not None:
+            raise ValueError("a sum-of-terms kernel factors into a new factor (out is for SHO refits)")
+        kc = theta.c()
+        p = ctypes.c_void_p()
+        st = lib().nu_gp_factor_kernel(ctx.ptr, ctypes.c_void_p(t_dev.data_ptr()), t_dev.numel(), ctypes.byref(kc),
+                                       ctypes.byref(p), ctypes.byref(logdet), ctypes.byref(pivot))
+        if st != NU_OK:
+            err = NuanceError(st, lib().nu_ctx_last_error(ctx.ptr).decode())
+            err.pivot = pivot.value
+            raise err
+        return Factor(p, t_dev.numel(), logdet.value)
+    sho = theta if isinstance(theta, SHO) else SHO.from_dict(theta)
     c = sho.c()
     if out is not None:
         st = lib().nu_gp_factor_into(ctx.ptr, out.ptr, ctypes.c_void_p(t_dev.data_ptr()), t_dev.numel(),

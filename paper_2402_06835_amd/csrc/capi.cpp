@@ -132,19 +132,30 @@ nu_status validate_theta(nu_ctx* ctx, const nu_sho* theta) {
   return NU_OK;
 }
 
+nu_status validate_kernel(nu_ctx* ctx, const nu_kernel* k) {
+  auto finite_pos = [](double x) { return std::isfinite(x) && x > 0.0; };
+  auto finite_nonneg = [](double x) { return std::isfinite(x) && x >= 0.0; };
+  if (k->n_sho < 0 || k->n_sho > 4 || k->n_exp < 0 || k->n_exp > 4)
+    return set_error(ctx, NU_ERR_ARG, "gp_factor_kernel: n_sho and n_exp must be in [0, 4]");
+  for (int s = 0; s < k->n_sho; ++s)
+    if (!finite_nonneg(k->sho_amp[s]) || !finite_pos(k->sho_omega[s]) || !finite_pos(k->sho_q[s]))
+      return set_error(ctx, NU_ERR_ARG, "gp_factor_kernel: SHO terms need finite amp >= 0, omega > 0, q > 0");
+  for (int e = 0; e < k->n_exp; ++e)
+    if (!finite_nonneg(k->exp_sigma[e]) || !finite_pos(k->exp_ell[e]))
+      return set_error(ctx, NU_ERR_ARG, "gp_factor_kernel: exponential terms need finite sigma >= 0, ell > 0");
+  if (!finite_nonneg(k->sigma_w)) return set_error(ctx, NU_ERR_ARG, "gp_factor_kernel: need finite sigma_w >= 0");
+  return NU_OK;
+}
+
 }  // namespace nu
 
 namespace {
 
-// theta upload, K build, blocked Cholesky, ln|K|; synchronises once for the status
-nu_status factor_compute(nu_ctx* ctx, nu_factor* F, const double* t, const nu_sho& th, double* logdet_host,
-                         int64_t* fail_pivot_host) {
-  F->theta_host = th;
-  nu_status st = check_hip(ctx, hipMemcpyAsync(F->theta_dev(), &F->theta_host, sizeof(nu_sho), hipMemcpyHostToDevice,
-                                               ctx->stream),
-                           "upload theta");
+// K build (from the uploaded theta or kernel), blocked Cholesky, ln|K|;
+// synchronises once for the status
+nu_status factor_run(nu_ctx* ctx, nu_factor* F, const double* t, double* logdet_host, int64_t* fail_pivot_host) {
   std::vector<nu_factor*> one{F};
-  if (st == NU_OK) st = run_factor(ctx, one, F->plan64, {t}, {F->theta_dev()});
+  nu_status st = run_factor(ctx, one, F->plan64, {t}, {F->theta_dev()});
   std::vector<int64_t> status;
   if (st == NU_OK) st = read_factor_status(ctx, one, status);
   if (st != NU_OK) return st;
@@ -155,6 +166,29 @@ nu_status factor_compute(nu_ctx* ctx, nu_factor* F, const double* t, const nu_sh
   }
   if (logdet_host) *logdet_host = F->logdet;
   return NU_OK;
+}
+
+nu_status factor_compute_kernel(nu_ctx* ctx, nu_factor* F, const double* t, const nu_kernel& k, double* logdet_host,
+                                int64_t* fail_pivot_host) {
+  F->general = true;
+  F->kernel_host = k;
+  nu_status st = check_hip(ctx, hipMemcpyAsync(F->kernel_dev(), &F->kernel_host, sizeof(nu_kernel),
+                                               hipMemcpyHostToDevice, ctx->stream),
+                           "upload kernel");
+  if (st != NU_OK) return st;
+  return factor_run(ctx, F, t, logdet_host, fail_pivot_host);
+}
+
+// theta upload, K build, blocked Cholesky, ln|K|; synchronises once for the status
+nu_status factor_compute(nu_ctx* ctx, nu_factor* F, const double* t, const nu_sho& th, double* logdet_host,
+                         int64_t* fail_pivot_host) {
+  F->general = false;
+  F->theta_host = th;
+  nu_status st = check_hip(ctx, hipMemcpyAsync(F->theta_dev(), &F->theta_host, sizeof(nu_sho), hipMemcpyHostToDevice,
+                                               ctx->stream),
+                           "upload theta");
+  if (st != NU_OK) return st;
+  return factor_run(ctx, F, t, logdet_host, fail_pivot_host);
 }
 
 }  // namespace
@@ -266,6 +300,29 @@ nu_status nu_gp_factor(nu_ctx* ctx, const double* t, int64_t n, const nu_sho* th
   st = factor_alloc(ctx, n, true, &F);
   if (st != NU_OK) return st;
   st = factor_compute(ctx, F, t, *theta, logdet_host, fail_pivot_host);
+  if (st != NU_OK) {
+    factor_free(F);
+    return st;
+  }
+  *out = F;
+  return NU_OK;
+}
+
+nu_status nu_gp_factor_kernel(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel* kernel_host,
+                              nu_factor** out, double* logdet_host, int64_t* fail_pivot_host) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!t || !kernel_host || !out) return set_error(ctx, NU_ERR_ARG, "gp_factor_kernel: null argument");
+  *out = nullptr;
+  if (fail_pivot_host) *fail_pivot_host = -1;
+  if (n < 1 || n > (int64_t)1 << 17) return set_error(ctx, NU_ERR_ARG, "gp_factor_kernel: n must be in [1, 131072]");
+  nu_status st = validate_kernel(ctx, kernel_host);
+  if (st != NU_OK) return st;
+  st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+  nu_factor* F = nullptr;
+  st = factor_alloc(ctx, n, true, &F);
+  if (st != NU_OK) return st;
+  st = factor_compute_kernel(ctx, F, t, *kernel_host, logdet_host, fail_pivot_host);
   if (st != NU_OK) {
     factor_free(F);
     return st;

@@ -480,7 +480,10 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
     st = check_hip(ctx, launch_fill_i64(ctx->stream, F->status_dev(), -1), "status init");
     if (st == NU_OK) {
       Timed tm(ctx, "kbuild", (double)F->n * (double)(F->n + 1) / 2.0);
-      st = check_hip(ctx, launch_kbuild(ctx->stream, ts[i], F->n, F->np, theta_dev[i], F->L), "kbuild");
+      st = check_hip(ctx,
+                     F->general ? launch_kbuild_terms(ctx->stream, ts[i], F->n, F->np, F->kernel_dev(), F->L)
+                                : launch_kbuild(ctx->stream, ts[i], F->n, F->np, theta_dev[i], F->L),
+                     "kbuild");
     }
   }
   // Blocked right-looking Cholesky, two levels: within a panel of PANEL

@@ -49,6 +49,41 @@ __global__ __launch_bounds__(256) void kbuild_kernel(const double* __restrict__ 
   }
 }
 
+// Lower triangle of K for a sum-of-terms covariance (nu_kernel), same layout.
+__global__ __launch_bounds__(256) void kbuild_terms_kernel(const double* __restrict__ t, int64_t n, int64_t np,
+                                                           const nu_kernel* __restrict__ kp, double* __restrict__ K) {
+  const int64_t br = blockIdx.y, bc = blockIdx.x;
+  if (bc > br) return;
+  const nu_kernel k = *kp;
+  const double s2w = k.sigma_w * k.sigma_w;
+  const int64_t r0 = br * 64, c0 = bc * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t col = c0 + tx;
+  const double tc = col < n ? t[col] : 0.0;
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t row = r0 + rr;
+    if (col > row) continue;
+    double v;
+    if (row < n && col < n) {
+      const double tau = fabs(t[row] - tc);
+      v = 0.0;
+      for (int s = 0; s < k.n_sho; ++s) v += sho_cov(tau, k.sho_amp[s], k.sho_omega[s], k.sho_q[s]);
+      for (int e = 0; e < k.n_exp; ++e) v += k.exp_sigma[e] * k.exp_sigma[e] * exp(-tau / k.exp_ell[e]);
+      if (row == col) v += s2w;
+    } else {
+      v = (row == col) ? 1.0 : 0.0;
+    }
+    K[row * np + col] = v;
+  }
+}
+
+hipError_t launch_kbuild_terms(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_kernel* k_dev,
+                               double* K) {
+  dim3 grid((unsigned)(np / 64), (unsigned)(np / 64));
+  hipLaunchKernelGGL(kbuild_terms_kernel, grid, dim3(256), 0, s, t, n, np, k_dev, K);
+  return hipGetLastError();
+}
+
 // theta is read from device memory, so a captured graph picks up new values
 hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho* th_dev, double* K) {
   dim3 grid((unsigned)(np / 64), (unsigned)(np / 64));

@@ -192,6 +192,8 @@ struct nu_factor {
   double* small = nullptr;   // [nblk] logdet parts, logdet, status (int64), theta (4), spare
   nu::NullFit* nullfit = nullptr;
   nu_sho theta_host{};       // source of the theta upload of the last factorisation
+  bool general = false;      // K from kernel_dev() (a nu_kernel) instead of theta_dev()
+  nu_kernel kernel_host{};   // source of the kernel upload of the last general factorisation
   nu::Plan plan64;           // Cholesky + FP64 inverse
   // reduced-precision inverse (allocated on first use)
   float* L32 = nullptr;
@@ -208,8 +210,10 @@ struct nu_factor {
   double* logdet_dev() const { return small + nblk; }
   int64_t* status_dev() const { return reinterpret_cast<int64_t*>(small + nblk + 1); }
   nu_sho* theta_dev() const { return reinterpret_cast<nu_sho*>(small + nblk + 2); }
+  nu_kernel* kernel_dev() const { return reinterpret_cast<nu_kernel*>(small + nblk + 8); }
 };
-constexpr int FACTOR_SMALL_EXTRA = 8;  // doubles of `small` after the per-block parts
+// doubles of `small` after the per-block parts: logdet, status, theta (4), spare (2), a nu_kernel
+constexpr int FACTOR_SMALL_EXTRA = 8 + (int)((sizeof(nu_kernel) + 7) / 8);
 
 namespace nu {
 
@@ -284,6 +288,9 @@ nu_status validate_theta(nu_ctx* ctx, const nu_sho* theta);
 
 // launchers (*.hip)
 hipError_t launch_kbuild(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_sho* th_dev, double* K);
+hipError_t launch_kbuild_terms(hipStream_t s, const double* t, int64_t n, int64_t np, const nu_kernel* k_dev,
+                               double* K);
+nu_status validate_kernel(nu_ctx* ctx, const nu_kernel* k);
 hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int kind, int tile_m,
                        int tile_n);
 hipError_t launch_potrf_diag(hipStream_t s, const PotrfJob* jobs, int njobs);
