@@ -43,6 +43,12 @@ if ROOT not in sys.path:
 PEAKS = {"gemm_f64": 78.6, "gemm_f32": 157.3, "gemm_bf16x3": 2500.0 / 3, "hbm_gbs": 8000.0}
 
 
+# the stellar-variability kernel of Section 3.2 at a 2-d rotation period (variance split between the modes,
+# a short and a long exponential term) with the white noise of the TESS-sector curve
+ROTATION_KERNEL = dict(sigma=1e-2, period=2.0, q0=1.0, dq=3.0, f=0.4, sigma_short=3e-4, ell_short=0.02,
+                       sigma_long=8e-4, ell_long=3.0, sigma_w=8e-4)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -52,13 +58,19 @@ def workload(name: str):
     return {"tess-sector": config2, "plain-1440": config1}[name]()
 
 
-def run_step(api, ctx, dev_in, w, precision, fac=None, planets=1):
-    """gp_factor + linear_search + periodic_search; with planets > 1, the periodic search is repeated on the
-    same linear-search grid with each found candidate's transits masked (Section 4). Returns the factor,
-    the grid, the first periodic search and the candidates (None for planets == 1)."""
-    fac = api.gp_factor(ctx, dev_in["t"], w.theta, out=fac)
-    ls = api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations,
-                           precision)
+def run_step(api, ctx, dev_in, w, precision, fac=None, planets=1, solver="dense", kernel=None):
+    """gp_factor + linear_search + periodic_search (solver "statespace": the state-space linear search, no
+    factor); with planets > 1, the periodic search is repeated on the same linear-search grid with each found
+    candidate's transits masked (Section 4). Returns the factor, the grid, the first periodic search and the
+    candidates (None for planets == 1)."""
+    if solver == "statespace":
+        ls = api.linear_search_ss(ctx, dev_in["t"], kernel, dev_in["f"], dev_in["A"], dev_in["lattice"],
+                                  w.n_epochs, w.durations, check=False)
+    else:
+        fac = api.gp_factor(ctx, dev_in["t"], w.theta if kernel is None else kernel,
+                            out=fac if kernel is None else None)
+        ls = api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations,
+                               precision)
     ps = api.periodic_search(ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], w.dt, dev_in["periods"])
     if planets <= 1:
         return fac, ls, ps, None
@@ -74,8 +86,9 @@ def run_step(api, ctx, dev_in, w, precision, fac=None, planets=1):
     return fac, ls, ps, cands
 
 
-def cpu_baseline(w, n_valid: int, budget_cells: int = 192, budget_periods: int = 4):
-    """The oracle on a bounded sample of the same workload, scaled to whole-step fits/s."""
+def cpu_baseline(w, n_valid: int, budget_cells: int = 192, budget_periods: int = 4, kernel: str = "sho"):
+    """The oracle on a bounded sample of the same workload, scaled to whole-step fits/s. The oracle is the
+    dense definition whichever solver the GPU step uses."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -84,7 +97,13 @@ def cpu_baseline(w, n_valid: int, budget_cells: int = 192, budget_periods: int =
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     log(f"cpu baseline: oracle K build + Cholesky at N={w.n} ({threads} BLAS threads)")
     t0 = time.perf_counter()
-    K = ogp.covariance(w.t, w.theta)
+    if kernel == "rotation":
+        rk = ROTATION_KERNEL
+        terms = ogp.rotation_terms(rk["sigma"], rk["period"], rk["q0"], rk["dq"], rk["f"], rk["sigma_short"],
+                                   rk["ell_short"], rk["sigma_long"], rk["ell_long"])
+        K = ogp.covariance_terms(w.t, terms, rk["sigma_w"])
+    else:
+        K = ogp.covariance(w.t, w.theta)
     L = ogp.cholesky(K)
     del K
     t_factor = time.perf_counter() - t0
@@ -408,12 +427,17 @@ def bench_curve(args, api, ctx, torch):
     }
     fac = None
     g = None
+    kernel = None
+    if args.kernel == "rotation":
+        kernel = api.rotation_kernel(**ROTATION_KERNEL)
+    elif args.solver == "statespace":
+        kernel = api.SHO.from_dict(w.theta)
     if args.mode == "graph":
         g = api.Graph(ctx, dev_in["t"], dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations,
                       w.theta, w.dt, dev_in["periods"], precision=args.precision)
     for i in range(max(args.warmup, 1)):
         if g is None:
-            fac, _, _, _ = run_step(api, ctx, dev_in, w, args.precision, fac, args.planets)
+            fac, _, _, _ = run_step(api, ctx, dev_in, w, args.precision, fac, args.planets, args.solver, kernel)
         else:
             g.launch()
         torch.cuda.synchronize()
@@ -426,7 +450,7 @@ def bench_curve(args, api, ctx, torch):
     for i in range(args.steps):
         # one curve per step; the factor's device buffers are reused across curves of one length
         if g is None:
-            keep = run_step(api, ctx, dev_in, w, args.precision, fac, args.planets)
+            keep = run_step(api, ctx, dev_in, w, args.precision, fac, args.planets, args.solver, kernel)
         else:
             g.launch()
         log(f"step {i + 1}/{args.steps} enqueued")
@@ -446,8 +470,10 @@ def bench_curve(args, api, ctx, torch):
     valid, best = got["valid"], int(got["best_index"].item())
     n_valid = int(valid.sum().item())
     dll_err = None
-    if args.precision != "fp64" and not args.no_dll_check:
-        # accuracy of this precision against the FP64 path on the same curve (outside the timed region)
+    if (args.precision != "fp64" or args.solver == "statespace") and not args.no_dll_check:
+        # accuracy of this path against the dense FP64 path on the same curve (outside the timed region)
+        if fac is None:
+            fac = api.gp_factor(ctx, dev_in["t"], w.theta if kernel is None or args.kernel != "rotation" else kernel)
         ref = dict(api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs,
                                      w.durations))
         ref.update(api.periodic_search(ctx, ref["depth"], ref["var"], ref["dll"], ref["valid"], w.dt,
@@ -457,8 +483,9 @@ def bench_curve(args, api, ctx, torch):
     log(f"{args.steps} steps in {elapsed:.3f} s: {n_valid * args.steps / elapsed:.4g} fits/s, "
         f"{args.steps / elapsed:.4g} curves/s; best period {w.periods[best] if best >= 0 else None}")
     cfg = {"workload": w.name, "n_samples": w.n, "n_epochs": w.n_epochs, "n_durations": int(w.durations.size),
-           "n_periods": int(w.periods.size), "valid_cells": n_valid, "precision": args.precision,
-           "mode": args.mode}
+           "n_periods": int(w.periods.size), "valid_cells": n_valid,
+           "precision": args.precision if args.solver == "dense" else "fp64", "mode": args.mode,
+           "solver": args.solver, "kernel": args.kernel}
     extra = {"best_period_days": float(w.periods[best]) if best >= 0 else None,
              "injected_period_days": w.injection["period"] if w.injection else None}
     if args.planets > 1:
@@ -477,6 +504,11 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=12, help="training epochs of the learned workload")
     ap.add_argument("--precision", default="fp32_refine", choices=["fp64", "fp32_refine", "bf16x3_refine"])
     ap.add_argument("--mode", default="eager", choices=["eager", "graph", "loop"])
+    ap.add_argument("--solver", default="dense", choices=["dense", "statespace"],
+                    help="linear search from the dense factor, or from the state-space (Kalman) form of the "
+                         "covariance (FP64; single-curve eager mode)")
+    ap.add_argument("--kernel", default="sho", choices=["sho", "rotation"],
+                    help="covariance: the workload's SHO, or the stellar-variability kernel of Section 3.2")
     ap.add_argument("--planets", type=int, default=1,
                     help="candidates per curve: after each periodic search the found transits are masked in the "
                          "linear-search products and the periodic search is repeated (single-curve eager mode)")
@@ -540,6 +572,8 @@ def main(argv=None):
             raise SystemExit("--mode loop compares against the batch (--workload batch-64)")
         if args.planets > 1 and args.mode != "eager":
             raise SystemExit("--planets applies to the eager single-curve step")
+        if (args.solver == "statespace" or args.kernel == "rotation") and args.mode != "eager":
+            raise SystemExit("--solver statespace and --kernel rotation run the eager single-curve step")
         elapsed, n_valid, curves, timings, dll_err, cfg, extra, w = bench_curve(args, api, ctx, torch)
     roof, gemms = (roofline_of(timings) if timings else (None, None))
     if roof is not None:
@@ -550,7 +584,8 @@ def main(argv=None):
         "value": n_valid * args.steps / elapsed, "unit": "(t0,D) fits/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32_refine": "f64+f32", "bf16x3_refine": "f64+bf16x3"}[args.precision], "data": "synthetic",
+        "dtype": "f64" if args.solver == "statespace" else
+        {"fp64": "f64", "fp32_refine": "f64+f32", "bf16x3_refine": "f64+bf16x3"}[args.precision], "data": "synthetic",
         "config": cfg,
         "light_curves_per_s": curves * args.steps / elapsed,
         "errors_vs_fp64": dll_err,
@@ -562,7 +597,7 @@ def main(argv=None):
     }
     out.update(extra)
     if not args.no_cpu_baseline and w is not None:
-        out["cpu_baseline"] = cpu_baseline(w, n_valid)
+        out["cpu_baseline"] = cpu_baseline(w, n_valid, kernel=args.kernel)
         out["cpu_baseline"]["unit"] = out["unit"]
     print(json.dumps(out), flush=True)
     return 0

@@ -175,6 +175,30 @@ nu_status nu_linear_search(nu_ctx* ctx, nu_factor* factor, const double* f, cons
                            nu_precision prec, double* depth, double* var, double* dll, uint8_t* valid,
                            double* null_out);
 
+/* (2b) Linear search of (2) without a dense factor, for a sum-of-terms
+ * covariance (Appendix A's SHO, Section 3.2's rotation kernel): the O(N J^2)
+ * quasiseparable route of the GP package the paper uses (Section 3.2,
+ * Appendix A), as the Kalman filter of the equivalent state-space model
+ * (J = 2 n_sho + n_exp states; at least one term). The filter's innovations
+ * are the Cholesky factorisation of K sample by sample, so every output is
+ * the one (2) gives with the factor of (1b) of the same kernel, up to
+ * rounding, in FP64.
+ * t: device, n doubles, non-decreasing (the sample times of K). f, A,
+ * lattice, n_epochs, dur_samples_host, the outputs and null_out as in (2).
+ * The kernel is passed by value to the device (no upload, no allocation
+ * beyond the context's workspace: about n (3 YCOLS + 8 J + J^2) doubles plus
+ * one double per cell).
+ * fail_index_host: host or NULL. Non-NULL: the call synchronises the stream
+ * once and, if an innovation variance is not positive (K not positive
+ * definite in floating point), stores the first failing sample there and
+ * returns NU_ERR_NOT_PD (else stores -1). NULL: no synchronisation; a failure
+ * then shows as ln L_0 = NaN and ln|K| = NaN in null_out and every cell
+ * invalid. */
+nu_status nu_linear_search_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel* kernel_host, const double* f,
+                              const double* A, int m1, const int64_t* lattice, int64_t n_epochs,
+                              const int32_t* dur_samples_host, int n_d, double* depth, double* var, double* dll,
+                              uint8_t* valid, double* null_out, int64_t* fail_index_host);
+
 /* (3) Periodic search (Sections 2.3-2.4, Eqs. 8, 9, B4).
  * depth/var/dll/valid: device, [n_d][n_epochs] as produced by (2).
  * periods: device, n_p doubles in the time unit of dt (dt > 0).

@@ -272,6 +272,54 @@ def linear_search(ctx: Context, factor: Factor, f, A, lattice, n_epochs: int, du
             "_keep": (f_d, A_d, lat)}
 
 
+def _as_kernel(theta) -> "Kernel":
+    if isinstance(theta, Kernel):
+        return theta
+    sho = theta if isinstance(theta, SHO) else SHO.from_dict(theta)
+    return Kernel(sho=[(sho.amp, sho.omega, sho.q)], sigma_w=sho.sigma_w)
+
+
+def linear_search_ss(ctx: Context, t, theta, f, A, lattice, n_epochs: int, durations, check: bool = True) -> dict:
+    """The linear search of ``linear_search`` from the state-space (Kalman) form of the covariance
+    (entry point 2b): no N x N factor, O(N J^2) work. ``theta``: Kernel, SHO or SHO dict.
+
+    With ``check`` the call waits for the filter and raises NU_ERR_NOT_PD (with ``.index``, the first
+    failing sample) if an innovation variance is not positive; without it nothing waits, and a failure
+    shows as NaN in ``null`` and every cell invalid."""
+    dev = ctx.device
+    kc = _as_kernel(theta).c()
+    t_d = _dev_tensor(t, torch.float64, dev)
+    f_d = _dev_tensor(f, torch.float64, dev)
+    n = f_d.numel()
+    if t_d.numel() != n:
+        raise ValueError("t and f must have the same length")
+    m1, A_d = _trend_colmajor(A, n, dev)
+    lat = _dev_tensor(lattice, torch.int64, dev)
+    if lat.numel() != n:
+        raise ValueError("lattice must have N entries")
+    durs = np.ascontiguousarray(np.asarray(durations, dtype=np.int32))
+    n_d = int(durs.size)
+    shape = (n_d, int(n_epochs))
+    depth = torch.empty(shape, dtype=torch.float64, device=dev)
+    var = torch.empty(shape, dtype=torch.float64, device=dev)
+    dll = torch.empty(shape, dtype=torch.float64, device=dev)
+    valid = torch.empty(shape, dtype=torch.uint8, device=dev)
+    null = torch.empty(3, dtype=torch.float64, device=dev)
+    fail = ctypes.c_int64(-1)
+    st = lib().nu_linear_search_ss(
+        ctx.ptr, ctypes.c_void_p(t_d.data_ptr()), n, ctypes.byref(kc), ctypes.c_void_p(f_d.data_ptr()),
+        ctypes.c_void_p(A_d.data_ptr() if A_d is not None else 0), m1, ctypes.c_void_p(lat.data_ptr()),
+        int(n_epochs), durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d, ctypes.c_void_p(depth.data_ptr()),
+        ctypes.c_void_p(var.data_ptr()), ctypes.c_void_p(dll.data_ptr()), ctypes.c_void_p(valid.data_ptr()),
+        ctypes.c_void_p(null.data_ptr()), ctypes.byref(fail) if check else None)
+    if st != NU_OK:
+        err = NuanceError(st, lib().nu_ctx_last_error(ctx.ptr).decode())
+        err.index = fail.value
+        raise err
+    return {"depth": depth, "var": var, "dll": dll, "valid": valid, "null": null,
+            "_keep": (t_d, f_d, A_d, lat)}
+
+
 def periodic_search(ctx: Context, depth, var, dll, valid, dt: float, periods, sign: int = 1) -> dict:
     """Fold of the single-event grid over periods x phases (Eq. 8, Eq. 9)."""
     dev = ctx.device
@@ -776,10 +824,16 @@ class Nuance:
     """The paper's search object: ``Nuance(time, flux, gp=SHO(...), X=X)``.
 
     ``time`` must sit on a regular lattice of cadence ``dt`` (gaps allowed);
-    epochs are all lattice slots from the first to the last sample.
+    epochs are all lattice slots from the first to the last sample. ``gp`` is
+    an SHO (or its dict) or a sum-of-terms Kernel. ``solver="statespace"``
+    runs the linear search from the state-space form of the covariance (no
+    dense factor is formed); ``"dense"`` factors K.
     """
 
-    def __init__(self, time, flux, gp: SHO, X=None, dt: Optional[float] = None, device: int = 0):
+    def __init__(self, time, flux, gp, X=None, dt: Optional[float] = None, device: int = 0,
+                 solver: str = "dense"):
+        if solver not in ("dense", "statespace"):
+            raise ValueError("solver must be 'dense' or 'statespace'")
         t = np.asarray(time, dtype=np.float64)
         if t.ndim != 1 or t.size < 2 or not np.all(np.diff(t) > 0):
             raise ValueError("time must be strictly increasing with at least two samples")
@@ -793,7 +847,10 @@ class Nuance:
         self.flux = np.asarray(flux, dtype=np.float64)
         self.X = None if X is None else np.asarray(X, dtype=np.float64)
         self.ctx = Context(device)
-        self.factor = gp_factor(self.ctx, t, gp)
+        self.solver = solver
+        self.gp = gp
+        self.time = t
+        self.factor = gp_factor(self.ctx, t, gp) if solver == "dense" else None
         self._ls = None
         self._dur_slots = None
 
@@ -804,8 +861,12 @@ class Nuance:
         if np.any(slots < 1):
             raise ValueError("durations must be at least one cadence")
         self._dur_slots = slots
-        self._ls = linear_search(self.ctx, self.factor, self.flux, self.X, self.lattice, self.n_epochs, slots,
-                                 precision)
+        if self.solver == "statespace":
+            self._ls = linear_search_ss(self.ctx, self.time, self.gp, self.flux, self.X, self.lattice,
+                                        self.n_epochs, slots)
+        else:
+            self._ls = linear_search(self.ctx, self.factor, self.flux, self.X, self.lattice, self.n_epochs, slots,
+                                     precision)
         return self._ls
 
     def periodic_search(self, periods, sign: int = 1) -> SearchResult:

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnuance_mi355x.so")
 
-SOURCES = ["factor.hip", "gemm.hip", "linear.hip", "fold.hip", "precision.hip", "engine.cpp", "capi.cpp", "batch.cpp", "learned.hip",
+SOURCES = ["factor.hip", "gemm.hip", "linear.hip", "fold.hip", "precision.hip", "statespace.hip", "engine.cpp", "ss_engine.cpp", "capi.cpp", "batch.cpp", "learned.hip",
            "learned_api.cpp"]
 ARCH = os.environ.get("NU_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

@@ -136,14 +136,14 @@ nu_status validate_kernel(nu_ctx* ctx, const nu_kernel* k) {
   auto finite_pos = [](double x) { return std::isfinite(x) && x > 0.0; };
   auto finite_nonneg = [](double x) { return std::isfinite(x) && x >= 0.0; };
   if (k->n_sho < 0 || k->n_sho > 4 || k->n_exp < 0 || k->n_exp > 4)
-    return set_error(ctx, NU_ERR_ARG, "gp_factor_kernel: n_sho and n_exp must be in [0, 4]");
+    return set_error(ctx, NU_ERR_ARG, "kernel: n_sho and n_exp must be in [0, 4]");
   for (int s = 0; s < k->n_sho; ++s)
     if (!finite_nonneg(k->sho_amp[s]) || !finite_pos(k->sho_omega[s]) || !finite_pos(k->sho_q[s]))
-      return set_error(ctx, NU_ERR_ARG, "gp_factor_kernel: SHO terms need finite amp >= 0, omega > 0, q > 0");
+      return set_error(ctx, NU_ERR_ARG, "kernel: SHO terms need finite amp >= 0, omega > 0, q > 0");
   for (int e = 0; e < k->n_exp; ++e)
     if (!finite_nonneg(k->exp_sigma[e]) || !finite_pos(k->exp_ell[e]))
-      return set_error(ctx, NU_ERR_ARG, "gp_factor_kernel: exponential terms need finite sigma >= 0, ell > 0");
-  if (!finite_nonneg(k->sigma_w)) return set_error(ctx, NU_ERR_ARG, "gp_factor_kernel: need finite sigma_w >= 0");
+      return set_error(ctx, NU_ERR_ARG, "kernel: exponential terms need finite sigma >= 0, ell > 0");
+  if (!finite_nonneg(k->sigma_w)) return set_error(ctx, NU_ERR_ARG, "kernel: need finite sigma_w >= 0");
   return NU_OK;
 }
 
@@ -380,6 +380,40 @@ nu_status nu_linear_search(nu_ctx* ctx, nu_factor* F, const double* f, const dou
   if (!ws) return st;
   return run_linear(ctx, F, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, prec, depth, var, dll, valid,
                     null_out, ws);
+}
+
+// ---------------------------------------------------------------------------
+nu_status nu_linear_search_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel* kernel_host, const double* f,
+                              const double* A, int m1, const int64_t* lattice, int64_t n_epochs,
+                              const int32_t* dur_samples_host, int n_d, double* depth, double* var, double* dll,
+                              uint8_t* valid, double* null_out, int64_t* fail_index_host) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!t || !kernel_host) return set_error(ctx, NU_ERR_ARG, "linear_search_ss: null argument");
+  nu_status st = validate_kernel(ctx, kernel_host);
+  if (st != NU_OK) return st;
+  if (kernel_host->n_sho + kernel_host->n_exp < 1)
+    return set_error(ctx, NU_ERR_ARG, "linear_search_ss: the kernel needs at least one SHO or exponential term");
+  if (n < 1 || n > ((int64_t)1 << 31)) return set_error(ctx, NU_ERR_ARG, "linear_search_ss: n must be in [1, 2^31]");
+  st = validate_linear(ctx, n, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, NU_FP64, depth, var, dll, valid);
+  if (st != NU_OK) return st;
+  st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+  double* ws = (double*)ctx_workspace(ctx, linear_ss_ws_bytes(n, *kernel_host, n_d, n_epochs), &st);
+  if (!ws) return st;
+  int64_t* status_dev = nullptr;
+  st = run_linear_ss(ctx, t, n, *kernel_host, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, depth, var, dll,
+                     valid, null_out, ws, &status_dev);
+  if (st != NU_OK || !fail_index_host) return st;
+  int64_t fail = -1;
+  st = check_hip(ctx, hipMemcpyAsync(&fail, status_dev, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream),
+                 "hipMemcpyAsync");
+  if (st == NU_OK) st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  if (st != NU_OK) return st;
+  *fail_index_host = fail;
+  if (fail >= 0)
+    return set_error(ctx, NU_ERR_NOT_PD,
+                     "linear_search_ss: innovation variance not positive at sample " + std::to_string(fail));
+  return NU_OK;
 }
 
 // ---------------------------------------------------------------------------

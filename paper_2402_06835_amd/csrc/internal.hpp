@@ -278,6 +278,11 @@ nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double*
 nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A, int m1, const int64_t* lattice,
                      int64_t n_epochs, const int32_t* dur_samples_host, int n_d, int prec, double* depth,
                      double* var, double* dll, uint8_t* valid, double* null_out, double* ws);
+size_t linear_ss_ws_bytes(int64_t n, const nu_kernel& k, int n_d, int64_t n_epochs);
+nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel& k, const double* f, const double* A,
+                        int m1, const int64_t* lattice, int64_t n_epochs, const int32_t* dur_samples_host, int n_d,
+                        double* depth, double* var, double* dll, uint8_t* valid, double* null_out, double* ws,
+                        int64_t** status_dev);
 size_t periodic_ws_bytes(int n_d, int64_t n_epochs);
 nu_status validate_periodic(nu_ctx* ctx, int n_d, int64_t n_epochs, double dt, int64_t n_p, int log_term_sign);
 nu_status run_periodic(nu_ctx* ctx, const double* depth, const double* var, const double* dll, const uint8_t* valid,
@@ -336,5 +341,31 @@ hipError_t launch_fold_segments(hipStream_t s, const double* depth, const double
 hipError_t launch_mask_transit(hipStream_t s, double* depth, double* var, double* dll, uint8_t* valid, int n_d,
                                int64_t n_t, double p, int64_t m, int h);
 hipError_t launch_best_period(hipStream_t s, const double* q_snr, int64_t n_p, int64_t* out);
+
+// State-space linear search (statespace.hip): the phases after the step
+// coefficients, each one launch on the stream.
+enum SsPhase { SS_RICCATI = 0, SS_FORWARD, SS_BACKWARD, SS_BOX };
+struct SsArgs {
+  int n_sho = 0, n_exp = 0;
+  int64_t n = 0;
+  nu_kernel kernel{};                   // by value: a kernel argument of the first phase
+  const double* step = nullptr;         // [n - 1][7 n_sho + 2 n_exp]
+  double* gain = nullptr;               // [n][1 + J]
+  double* Gm = nullptr;                 // [n + 1][J][J]
+  double* logdet = nullptr;             // 1 (NaN on failure)
+  int64_t* status = nullptr;            // first failing sample or -1
+  const double* V = nullptr;            // [n][YCOLS]
+  double* Y = nullptr;                  // [n][YCOLS]
+  double* Z = nullptr;                  // [n][YCOLS]
+  int nv = 0;
+  const int64_t* lattice = nullptr;
+  const int32_t* slot_count = nullptr;
+  int64_t n_epochs = 0;
+  const int32_t* dur_sorted = nullptr;  // host [2 n_d]: ascending durations, then their caller indices
+  int n_d = 0;
+  double* qbox = nullptr;               // [n_d][n_epochs]
+};
+hipError_t launch_ss_step(hipStream_t s, const double* t, int64_t n, const nu_kernel& k, double* step);
+hipError_t launch_ss(int phase, hipStream_t s, const SsArgs& A);
 
 }  // namespace nu

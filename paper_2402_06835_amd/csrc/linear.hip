@@ -22,31 +22,10 @@
 //   cell_epilogue per cell: g, h from window sums of Z, Schur complement, outputs
 #include <algorithm>
 
+#include "cells.hpp"
 #include "internal.hpp"
 
 namespace nu {
-
-struct DurList {
-  int n;
-  int d[MAX_ND];     // box lengths in slots (ascending for q_partial, caller order for the epilogue)
-  int perm[MAX_ND];  // q_partial: caller index of the k-th ascending duration
-};
-
-__device__ __forceinline__ int64_t lower_bound_i64(const int64_t* __restrict__ a, int64_t n, int64_t v) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (a[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-// Samples with lattice index below a: from the table T[s] = that count for
-// s in [0, n_epochs], by binary search outside it.
-__device__ __forceinline__ int64_t count_below(const int64_t* __restrict__ lattice, int64_t n,
-                                               const int32_t* __restrict__ T, int64_t n_epochs, int64_t a) {
-  return (a >= 0 && a <= n_epochs) ? (int64_t)T[a] : lower_bound_i64(lattice, n, a);
-}
 
 __global__ __launch_bounds__(256) void slot_count_kernel(const int64_t* __restrict__ lattice, int64_t n,
                                                          int64_t n_epochs, int32_t* __restrict__ T) {
@@ -212,6 +191,8 @@ __global__ __launch_bounds__(256) void null_solve_kernel(double* __restrict__ Y,
     for (int i = 0; i < MAX_M1; ++i)
       for (int j = 0; j < MAX_M1; ++j) nf->G0chol[i * MAX_M1 + j] = (i < m1 && j <= i) ? Lg[i][j] : 0.0;
     for (int i = 0; i < m1; ++i) nf->w0[i] = w0s[i];
+    // a failed factorisation leaves ln|K| non-finite: no cell is valid then
+    if (!isfinite(*logdet)) ok = 0;
     nf->ok = ok;
     ok_s = ok;
   }
@@ -328,12 +309,6 @@ hipError_t launch_cols_matvec(hipStream_t s, const double* M, int64_t ldm, int64
 // the waves are independent, and LDS order within a wave needs only a
 // compiler fence.
 constexpr int QCH = 256;  // slots per workgroup (4 waves x 64)
-
-__device__ __forceinline__ void wave_lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <int RUN>
 __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,

@@ -1,0 +1,639 @@
+// Linear search (Section 2.2, Eqs. 5-6) in O(N J^2) without a dense factor,
+// for the sum-of-terms covariances of Appendix A (SHO) and Section 3.2 (the
+// rotation kernel): the quasiseparable route of the GP package the paper
+// uses, written here as the Kalman filter of the equivalent state-space model.
+//
+// Every SHO term is the stationary response of a damped oscillator driven by
+// white noise (two states: position and velocity) and every exponential term
+// a one-state Ornstein-Uhlenbeck process, so K is the covariance of
+// y_n = H x(t_n) + w_n, with x the J-state Markov process (J = 2 n_sho +
+// n_exp, states ordered as the SHO pairs then the exponential terms), H
+// picking every position state and w white with variance sigma_w^2. Between
+// samples the state moves by Phi_{n+1} = exp(F h) and gains the process
+// noise Qd = Pinf - Phi Pinf Phi^T (h = t_{n+1} - t_n).
+//
+// The filter is the Cholesky factorisation K = L L^T taken sample by sample:
+//   S_n = H P_n H^T + sigma_w^2            (the squared pivots: ln|K| = sum ln S_n)
+//   k_n = P_n H^T / S_n,  P_{n+1} = Phi_{n+1} (P_n - k_n S_n k_n^T) Phi_{n+1}^T + Qd_{n+1},  P_0 = Pinf
+// and L^-1 v is the scaled innovation sequence
+//   z_n = (v_n - H x_n) / sqrt(S_n),  x_{n+1} = Phi_{n+1} (x_n + k_n (v_n - H x_n)),  x_0 = 0.
+// Its transpose L^-T w runs backwards with an adjoint state lambda (lambda_N = 0):
+//   mu = Phi_{n+1}^T lambda_{n+1},  u_n = w_n / sqrt(S_n) + k_n . mu,  lambda_n = mu - H^T u_n.
+// For a box b = 1 on samples [lo, hi), L^-1 b is zero before lo, follows the
+// recursion with v = 1 inside, and after hi is the free response of x_hi,
+// whose energy is x_hi^T G_hi x_hi with
+//   G_n = H^T H / S_n + M_n^T G_{n+1} M_n,  M_n = Phi_{n+1} (I - k_n H),  G_N = 0,
+// so q = b^T K^-1 b costs O(d J + J^2) per box instead of a pass over L^-1.
+//
+// Kernels, in launch order (the trend/flux packing, the trend-only fit, the
+// slot table and the per-cell Schur epilogue are the dense path's):
+//   ss_step      per sample gap: Phi and Qd of every term              (parallel)
+//   ss_riccati   S_n, k_n               (one wave; lane a keeps row a of P), then ln|K|
+//   ss_forward   Y = L^-1 [A | f]       (one lane per column)
+//   ss_backward  Z = L^-T [A~ | r~0]    (one lane per column) and G_n (one wave; lane a keeps row a)
+//   ss_box       q of every cell, one thread per box start: the boxes of all
+//                durations that start on one slot share the in-box recursion
+#include "cells.hpp"
+#include "internal.hpp"
+
+namespace nu {
+
+namespace {
+
+// Step record of one sample gap: per SHO term 7 doubles (Phi row-major
+// p00 p01 p10 p11, then Qd00 Qd01 Qd11), per exponential term 2 (phi, Qd).
+// Gain record of one sample: 1/sqrt(S_n), then k_n[J].
+template <int NS, int NE>
+struct SsLayout {
+  static constexpr int J = 2 * NS + NE;
+  static constexpr int TS = 7 * NS + 2 * NE;
+  static constexpr int GS = J + 1;
+  static constexpr bool pos(int b) { return b >= 2 * NS || (b & 1) == 0; }
+};
+
+// e^{-a h} cos(b h) and e^{-a h} sin(b h) / b of the oscillator (and their
+// limits at Q = 1/2 and their hyperbolic forms for Q < 1/2), a = omega / 2Q.
+__device__ void sho_step_coeffs(double amp, double om, double q, double h, double* c) {
+  const double a = om / (2.0 * q);
+  double eC, eS;
+  if (q == 0.5) {
+    const double e = exp(-a * h);
+    eC = e;
+    eS = e * h;
+  } else if (q > 0.5) {
+    const double b = om * sqrt(1.0 - 1.0 / (4.0 * q * q));
+    double sn, cs;
+    sincos(b * h, &sn, &cs);
+    const double e = exp(-a * h);
+    eC = e * cs;
+    eS = e * sn / b;
+  } else {
+    // b < a: e^{-ah} cosh(bh) = (e1 + e2) / 2 and e^{-ah} sinh(bh) / b =
+    // e1 (1 - e^{-2bh}) / 2b with e1 = e^{-(a-b)h}, e2 = e^{-(a+b)h}, which
+    // neither overflow at long gaps nor cancel at short ones
+    const double b = om * sqrt(1.0 / (4.0 * q * q) - 1.0);
+    const double e1 = exp(-(a - b) * h), e2 = exp(-(a + b) * h);
+    eC = 0.5 * (e1 + e2);
+    eS = -e1 * expm1(-2.0 * b * h) / (2.0 * b);
+  }
+  const double p00 = eC + a * eS, p01 = eS, p10 = -om * om * eS, p11 = eC - a * eS;
+  const double v0 = amp * amp, v1 = v0 * om * om;
+  c[0] = p00;
+  c[1] = p01;
+  c[2] = p10;
+  c[3] = p11;
+  c[4] = v0 - (p00 * p00 * v0 + p01 * p01 * v1);
+  c[5] = -(p00 * p10 * v0 + p01 * p11 * v1);
+  c[6] = v1 - (p10 * p10 * v0 + p11 * p11 * v1);
+}
+
+__global__ __launch_bounds__(256) void ss_step_kernel(const double* __restrict__ t, int64_t n, nu_kernel k,
+                                                      int ts, double* __restrict__ step) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i + 1 >= n) return;
+  const double h = t[i + 1] - t[i];
+  double* c = step + i * ts;
+  const int ns = k.n_sho, ne = k.n_exp;
+  for (int s = 0; s < ns; ++s) sho_step_coeffs(k.sho_amp[s], k.sho_omega[s], k.sho_q[s], h, c + 7 * s);
+  for (int e = 0; e < ne; ++e) {
+    const double sg = k.exp_sigma[e], ell = k.exp_ell[e];
+    c[7 * ns + 2 * e] = exp(-h / ell);
+    c[7 * ns + 2 * e + 1] = -sg * sg * expm1(-2.0 * h / ell);
+  }
+}
+
+// v of lane src in every lane (two readlanes; src uniform)
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// v of lane l ^ 1 (the partner row of an SHO pair): a DPP quad permutation
+// [1, 0, 3, 2] of both halves, no LDS round trip
+__device__ __forceinline__ double pair_swap(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, 0xb1, 0xf, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0xb1, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// 1 / sqrt(s): the hardware estimate and two Newton steps
+__device__ __forceinline__ double rsqrt_nr(double s) {
+  double r = __builtin_amdgcn_rsq(s);
+  const double h = 0.5 * s;
+  r = fma(r, fma(-h * r, r, 0.5), r);
+  return fma(r, fma(-h * r, r, 0.5), r);
+}
+
+// The sequential kernels take their per-sample records from LDS, staged one
+// chunk of CH samples ahead: at the start of a chunk the wave issues the
+// global loads of the next chunk's records (coalesced: lane l moves words l,
+// l + 64, ... of the chunk's contiguous span of W-double records) and writes
+// them to the other LDS buffer at the end of the chunk, so no load latency
+// sits on the recursion's critical path.
+constexpr int CH = 64;
+
+template <int W>
+struct Stage {
+  double r[W];
+  // records [c0, c0 + CH) of an array of nrec records
+  __device__ __forceinline__ void load(const double* __restrict__ src, int64_t c0, int64_t nrec, int lane) {
+    const int64_t first = c0 * W, end = nrec * W;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int64_t idx = first + k * 64 + lane;
+      r[k] = idx < end ? src[idx] : 0.0;
+    }
+  }
+  __device__ __forceinline__ void put(double* lds, int lane) const {
+#pragma unroll
+    for (int k = 0; k < W; ++k) lds[k * 64 + lane] = r[k];
+  }
+};
+
+// x <- Phi x for the block-diagonal transition of a step record
+template <int NS, int NE>
+__device__ __forceinline__ void apply_phi(const double* c, double* x) {
+#pragma unroll
+  for (int s2 = 0; s2 < NS; ++s2) {
+    const double u0 = x[2 * s2], u1 = x[2 * s2 + 1];
+    x[2 * s2] = c[7 * s2] * u0 + c[7 * s2 + 1] * u1;
+    x[2 * s2 + 1] = c[7 * s2 + 2] * u0 + c[7 * s2 + 3] * u1;
+  }
+#pragma unroll
+  for (int e2 = 0; e2 < NE; ++e2) x[2 * NS + e2] = c[7 * NS + 2 * e2] * x[2 * NS + e2];
+}
+
+// x <- Phi^T x
+template <int NS, int NE>
+__device__ __forceinline__ void apply_phi_t(const double* c, double* x) {
+#pragma unroll
+  for (int s2 = 0; s2 < NS; ++s2) {
+    const double l0 = x[2 * s2], l1 = x[2 * s2 + 1];
+    x[2 * s2] = c[7 * s2] * l0 + c[7 * s2 + 2] * l1;
+    x[2 * s2 + 1] = c[7 * s2 + 1] * l0 + c[7 * s2 + 3] * l1;
+  }
+#pragma unroll
+  for (int e2 = 0; e2 < NE; ++e2) x[2 * NS + e2] = c[7 * NS + 2 * e2] * x[2 * NS + e2];
+}
+
+// Lane a of the wave keeps row a of the J x J state covariance (lanes past J
+// shadow row 0 and store nothing). Per sample: the pivot S from the
+// broadcast row sums over the position columns, the rank-one update, Phi
+// from the left (the partner row of an SHO pair by a lane swap), Phi^T from
+// the right and the process noise of the lane's own block. ln|K| is summed
+// afterwards, in parallel, from the stored 1/sqrt(S_n).
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_riccati_kernel(const double* __restrict__ step, nu_kernel kp, int64_t n,
+                                                        double* __restrict__ gain, int64_t* __restrict__ status) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS, GS = Lt::GS;
+  __shared__ double st[2][CH * TS];
+  const int lane = threadIdx.x;
+  const int a = lane < J ? lane : 0;
+  const bool sho = a < 2 * NS;
+  const int s = a >> 1, r = a & 1, e = a - 2 * NS;
+  // own-block offsets in the step record: Phi(r, r), Phi(r, 1-r), Qd(r, 0), Qd(r, 1)
+  const int o_diag = sho ? 7 * s + 3 * r : 7 * NS + 2 * e;
+  const int o_off = sho ? 7 * s + 1 + r : 0;
+  const int o_q0 = sho ? 7 * s + 4 + r : 7 * NS + 2 * e + 1;
+  const int o_q1 = sho ? 7 * s + 5 + r : 0;
+  const int c0 = sho ? 2 * s : a;  // first column of the lane's own block
+  double pinf;
+  if (sho) {
+    const double amp = kp.sho_amp[s], om = kp.sho_omega[s];
+    pinf = r == 0 ? amp * amp : amp * amp * om * om;
+  } else {
+    const double sg = kp.exp_sigma[e];
+    pinf = sg * sg;
+  }
+  const double sw2 = kp.sigma_w * kp.sigma_w;
+  double P[J];
+#pragma unroll
+  for (int b = 0; b < J; ++b) P[b] = b == a ? pinf : 0.0;
+  int64_t fail = -1;
+  Stage<TS> pre;
+  pre.load(step, 0, n - 1, lane);
+  pre.put(st[0], lane);
+  wave_lds_fence();
+  const int64_t nch = (n + CH - 1) / CH;
+  for (int64_t ch = 0; ch < nch && fail < 0; ++ch) {
+    const double* cur = st[ch & 1];
+    if (ch + 1 < nch) pre.load(step, (ch + 1) * CH, n - 1, lane);
+    const int iend = (int)min((int64_t)CH, n - ch * CH);
+    for (int ii = 0; ii < iend; ++ii) {
+      const int64_t i = ch * CH + ii;
+      double ph = 0.0;
+#pragma unroll
+      for (int b = 0; b < J; ++b)
+        if (Lt::pos(b)) ph += P[b];
+      double phv[J];
+#pragma unroll
+      for (int b = 0; b < J; ++b) phv[b] = lane_bcast(ph, b);
+      double S = sw2;
+#pragma unroll
+      for (int b = 0; b < J; ++b)
+        if (Lt::pos(b)) S += phv[b];
+      if (!(S > 0.0 && S < INFINITY)) {
+        fail = i;
+        break;
+      }
+      const double rsq = rsqrt_nr(S);
+      const double rS = rsq * rsq;
+      double* g = gain + i * GS;
+      if (lane == 0) g[0] = rsq;
+      if (lane < J) g[1 + lane] = ph * rS;
+      if (i + 1 == n) break;
+      // P - P H^T H P / S
+      const double kr = ph * rS;
+#pragma unroll
+      for (int b = 0; b < J; ++b) P[b] = fma(-kr, phv[b], P[b]);
+      // Phi from the left: rows of the lane's own block
+      const double* c = cur + ii * TS;
+      const double al = c[o_diag];
+      const double be = sho ? c[o_off] : 0.0;
+      double T[J];
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        const double other = pair_swap(P[b]);
+        T[b] = al * P[b] + (sho ? be * other : 0.0);
+      }
+      // Phi^T from the right, then the process noise of the own block
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) {
+        const double p00 = c[7 * s2], p01 = c[7 * s2 + 1], p10 = c[7 * s2 + 2], p11 = c[7 * s2 + 3];
+        const double t0 = T[2 * s2], t1 = T[2 * s2 + 1];
+        P[2 * s2] = t0 * p00 + t1 * p01;
+        P[2 * s2 + 1] = t0 * p10 + t1 * p11;
+      }
+#pragma unroll
+      for (int e2 = 0; e2 < NE; ++e2) P[2 * NS + e2] = T[2 * NS + e2] * c[7 * NS + 2 * e2];
+      const double q0 = c[o_q0], q1 = sho ? c[o_q1] : 0.0;
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        if (b == c0) P[b] += q0;
+        if (sho && b == c0 + 1) P[b] += q1;
+      }
+    }
+    if (ch + 1 < nch) pre.put(st[(ch + 1) & 1], lane);
+    wave_lds_fence();
+  }
+  if (lane == 0) *status = fail;
+}
+
+// ln|K| = sum ln S_n = -2 sum ln(1/sqrt(S_n)) in a fixed order; NaN if the
+// filter failed
+__global__ __launch_bounds__(256) void ss_logdet_kernel(const double* __restrict__ gain, int gs, int64_t n,
+                                                        const int64_t* __restrict__ status,
+                                                        double* __restrict__ logdet) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc += log(gain[i * gs]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *logdet = *status >= 0 ? NAN : -2.0 * (((red[0] + red[1]) + red[2]) + red[3]);
+}
+
+// Y = L^-1 V: lane c carries the filter state of column c (lanes past the
+// last column repeat it and store nothing).
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_forward_kernel(const double* __restrict__ step,
+                                                        const double* __restrict__ gain, int64_t n,
+                                                        const double* __restrict__ V, int nv, double* __restrict__ Y) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS, GS = Lt::GS;
+  __shared__ double sv[2][CH * YCOLS], sg[2][CH * GS], ss[2][CH * TS];
+  const int lane = threadIdx.x;
+  const int col = lane < nv ? lane : nv - 1;
+  double x[J];
+#pragma unroll
+  for (int b = 0; b < J; ++b) x[b] = 0.0;
+  Stage<YCOLS> pv;
+  Stage<GS> pg;
+  Stage<TS> ps;
+  pv.load(V, 0, n, lane);
+  pg.load(gain, 0, n, lane);
+  ps.load(step, 0, n - 1, lane);
+  pv.put(sv[0], lane);
+  pg.put(sg[0], lane);
+  ps.put(ss[0], lane);
+  wave_lds_fence();
+  const int64_t nch = (n + CH - 1) / CH;
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int buf = (int)(ch & 1);
+    if (ch + 1 < nch) {
+      pv.load(V, (ch + 1) * CH, n, lane);
+      pg.load(gain, (ch + 1) * CH, n, lane);
+      ps.load(step, (ch + 1) * CH, n - 1, lane);
+    }
+    const int iend = (int)min((int64_t)CH, n - ch * CH);
+    for (int ii = 0; ii < iend; ++ii) {
+      const int64_t i = ch * CH + ii;
+      const double* g = sg[buf] + ii * GS;
+      double hx = 0.0;
+#pragma unroll
+      for (int b = 0; b < J; ++b)
+        if (Lt::pos(b)) hx += x[b];
+      const double ev = sv[buf][ii * YCOLS + col] - hx;
+      if (lane < nv) Y[i * YCOLS + lane] = ev * g[0];
+#pragma unroll
+      for (int b = 0; b < J; ++b) x[b] = fma(g[1 + b], ev, x[b]);
+      apply_phi<NS, NE>(ss[buf] + ii * TS, x);  // the last sample's record is unused padding
+    }
+    if (ch + 1 < nch) {
+      pv.put(sv[buf ^ 1], lane);
+      pg.put(sg[buf ^ 1], lane);
+      ps.put(ss[buf ^ 1], lane);
+    }
+    wave_lds_fence();
+  }
+}
+
+// Workgroup 0: Z = L^-T W (lane c carries the adjoint state of column c).
+// Workgroup 1: G_n for n = N .. 0 (lane a keeps row a), stored row-major
+// J x J per sample. The two chains are independent and run side by side;
+// both walk the chunks backwards, staging the previous chunk.
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_backward_kernel(const double* __restrict__ step,
+                                                         const double* __restrict__ gain, int64_t n,
+                                                         const double* __restrict__ W, int nv, double* __restrict__ Z,
+                                                         double* __restrict__ Gm) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS, GS = Lt::GS;
+  __shared__ double sw[2][CH * YCOLS], sg[2][CH * GS], ss[2][CH * TS];
+  const int lane = threadIdx.x;
+  const bool adj = blockIdx.x == 0;
+  const int64_t nch = (n + CH - 1) / CH;
+  Stage<YCOLS> pw;
+  Stage<GS> pg;
+  Stage<TS> ps;
+  {
+    const int64_t c0 = (nch - 1) * CH;
+    if (adj) pw.load(W, c0, n, lane);
+    pg.load(gain, c0, n, lane);
+    ps.load(step, c0, n - 1, lane);
+    if (adj) pw.put(sw[(nch - 1) & 1], lane);
+    pg.put(sg[(nch - 1) & 1], lane);
+    ps.put(ss[(nch - 1) & 1], lane);
+    wave_lds_fence();
+  }
+  if (adj) {
+    const int col = lane < nv ? lane : nv - 1;
+    double lam[J];
+#pragma unroll
+    for (int b = 0; b < J; ++b) lam[b] = 0.0;
+    for (int64_t ch = nch - 1; ch >= 0; --ch) {
+      const int buf = (int)(ch & 1);
+      if (ch > 0) {
+        pw.load(W, (ch - 1) * CH, n, lane);
+        pg.load(gain, (ch - 1) * CH, n, lane);
+        ps.load(step, (ch - 1) * CH, n - 1, lane);
+      }
+      const int iend = (int)min((int64_t)CH, n - ch * CH);
+      for (int ii = iend - 1; ii >= 0; --ii) {
+        const int64_t i = ch * CH + ii;
+        double mu[J];
+#pragma unroll
+        for (int b = 0; b < J; ++b) mu[b] = lam[b];
+        if (i + 1 < n) {
+          apply_phi_t<NS, NE>(ss[buf] + ii * TS, mu);
+        } else {
+#pragma unroll
+          for (int b = 0; b < J; ++b) mu[b] = 0.0;
+        }
+        const double* g = sg[buf] + ii * GS;
+        double u = sw[buf][ii * YCOLS + col] * g[0];
+#pragma unroll
+        for (int b = 0; b < J; ++b) u = fma(g[1 + b], mu[b], u);
+        if (lane < nv) Z[i * YCOLS + lane] = u;
+#pragma unroll
+        for (int b = 0; b < J; ++b) lam[b] = Lt::pos(b) ? mu[b] - u : mu[b];
+      }
+      if (ch > 0) {
+        pw.put(sw[buf ^ 1], lane);
+        pg.put(sg[buf ^ 1], lane);
+        ps.put(ss[buf ^ 1], lane);
+      }
+      wave_lds_fence();
+    }
+    return;
+  }
+  const int a = lane < J ? lane : 0;
+  const bool sho = a < 2 * NS;
+  const int s = a >> 1, r = a & 1, e = a - 2 * NS;
+  // Phi^T from the left: Phi(r, r) on the own row, Phi(1-r, r) on the partner row
+  const int o_diag = sho ? 7 * s + 3 * r : 7 * NS + 2 * e;
+  const int o_off = sho ? 7 * s + 2 - r : 0;
+  const bool posa = Lt::pos(a);
+  double G[J];
+#pragma unroll
+  for (int b = 0; b < J; ++b) G[b] = 0.0;
+  if (lane < J) {
+#pragma unroll
+    for (int b = 0; b < J; ++b) Gm[(n * J + lane) * J + b] = 0.0;
+  }
+  for (int64_t ch = nch - 1; ch >= 0; --ch) {
+    const int buf = (int)(ch & 1);
+    if (ch > 0) {
+      pg.load(gain, (ch - 1) * CH, n, lane);
+      ps.load(step, (ch - 1) * CH, n - 1, lane);
+    }
+    const int iend = (int)min((int64_t)CH, n - ch * CH);
+    for (int ii = iend - 1; ii >= 0; --ii) {
+      const int64_t i = ch * CH + ii;
+      double Wr[J];
+      if (i + 1 < n) {
+        const double* c = ss[buf] + ii * TS;
+        const double al = c[o_diag];
+        const double be = sho ? c[o_off] : 0.0;
+        double T[J];
+#pragma unroll
+        for (int b = 0; b < J; ++b) {
+          const double other = pair_swap(G[b]);
+          T[b] = al * G[b] + (sho ? be * other : 0.0);
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2) {
+          const double p00 = c[7 * s2], p01 = c[7 * s2 + 1], p10 = c[7 * s2 + 2], p11 = c[7 * s2 + 3];
+          const double t0 = T[2 * s2], t1 = T[2 * s2 + 1];
+          Wr[2 * s2] = t0 * p00 + t1 * p10;
+          Wr[2 * s2 + 1] = t0 * p01 + t1 * p11;
+        }
+#pragma unroll
+        for (int e2 = 0; e2 < NE; ++e2) Wr[2 * NS + e2] = T[2 * NS + e2] * c[7 * NS + 2 * e2];
+      } else {
+#pragma unroll
+        for (int b = 0; b < J; ++b) Wr[b] = 0.0;
+      }
+      const double* g = sg[buf] + ii * GS;
+      const double rS = g[0] * g[0];
+      double wk = 0.0;
+#pragma unroll
+      for (int b = 0; b < J; ++b) wk = fma(Wr[b], g[1 + b], wk);
+      double wkv[J];
+#pragma unroll
+      for (int b = 0; b < J; ++b) wkv[b] = lane_bcast(wk, b);
+      double kwk = 0.0;
+#pragma unroll
+      for (int b = 0; b < J; ++b) kwk = fma(g[1 + b], wkv[b], kwk);
+      const double corner = kwk + rS;
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        double v = Wr[b];
+        if (posa) v -= wkv[b];
+        if (Lt::pos(b)) v -= wk;
+        if (posa && Lt::pos(b)) v += corner;
+        G[b] = v;
+      }
+      if (lane < J) {
+#pragma unroll
+        for (int b = 0; b < J; ++b) Gm[(i * J + lane) * J + b] = G[b];
+      }
+    }
+    if (ch > 0) {
+      pg.put(sg[buf ^ 1], lane);
+      ps.put(ss[buf ^ 1], lane);
+    }
+    wave_lds_fence();
+  }
+}
+
+// q of every cell. Thread for box start slot a (a from -floor(dmax/2)):
+// the boxes [a, a + d_k) of the ascending durations share the recursion from
+// lo = count_below(a); at each end hi_k the tail energy x^T G_hi x is added
+// and the cell (k, a + floor(d_k/2)) written, if it is on the grid.
+template <int NS, int NE>
+__global__ __launch_bounds__(256) void ss_box_kernel(const double* __restrict__ step, const double* __restrict__ gain,
+                                                     const double* __restrict__ Gm, int64_t n,
+                                                     const int64_t* __restrict__ lattice,
+                                                     const int32_t* __restrict__ T, int64_t n_epochs, DurList dl,
+                                                     int half_max, double* __restrict__ qbox) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS, GS = Lt::GS;
+  const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x - half_max;
+  if (a >= n_epochs) return;
+  double x[J];
+#pragma unroll
+  for (int b = 0; b < J; ++b) x[b] = 0.0;
+  double q = 0.0;
+  int64_t m = count_below(lattice, n, T, n_epochs, a);
+  for (int k = 0; k < dl.n; ++k) {
+    const int64_t hk = count_below(lattice, n, T, n_epochs, a + dl.d[k]);
+    for (; m < hk; ++m) {
+      const double* g = gain + m * GS;
+      double hx = 0.0;
+#pragma unroll
+      for (int b = 0; b < J; ++b)
+        if (Lt::pos(b)) hx += x[b];
+      const double ev = 1.0 - hx;
+      const double z = ev * g[0];
+      q = fma(z, z, q);
+      if (m + 1 < n) {
+        const double* c = step + m * TS;
+        double u[J];
+#pragma unroll
+        for (int b = 0; b < J; ++b) u[b] = fma(g[1 + b], ev, x[b]);
+#pragma unroll
+        for (int s2 = 0; s2 < NS; ++s2) {
+          const double u0 = u[2 * s2], u1 = u[2 * s2 + 1];
+          x[2 * s2] = c[7 * s2] * u0 + c[7 * s2 + 1] * u1;
+          x[2 * s2 + 1] = c[7 * s2 + 2] * u0 + c[7 * s2 + 3] * u1;
+        }
+#pragma unroll
+        for (int e2 = 0; e2 < NE; ++e2) x[2 * NS + e2] = c[7 * NS + 2 * e2] * u[2 * NS + e2];
+      } else {
+#pragma unroll
+        for (int b = 0; b < J; ++b) x[b] = 0.0;
+      }
+    }
+    const double* G = Gm + hk * J * J;
+    double tail = 0.0;
+#pragma unroll
+    for (int a2 = 0; a2 < J; ++a2) {
+      double row = 0.0;
+#pragma unroll
+      for (int b = 0; b < J; ++b) row = fma(G[a2 * J + b], x[b], row);
+      tail = fma(x[a2], row, tail);
+    }
+    const int64_t i = a + dl.d[k] / 2;
+    if (i >= 0 && i < n_epochs) qbox[(int64_t)dl.perm[k] * n_epochs + i] = q + tail;
+  }
+}
+
+template <int NS, int NE>
+hipError_t launch_ss_typed(int phase, hipStream_t s, const SsArgs& A) {
+  switch (phase) {
+    case SS_RICCATI:
+      hipLaunchKernelGGL((ss_riccati_kernel<NS, NE>), dim3(1), dim3(64), 0, s, A.step, A.kernel, A.n, A.gain,
+                         A.status);
+      if (hipPeekAtLastError() != hipSuccess) break;
+      hipLaunchKernelGGL(ss_logdet_kernel, dim3(1), dim3(256), 0, s, A.gain, SsLayout<NS, NE>::GS, A.n, A.status,
+                         A.logdet);
+      break;
+    case SS_FORWARD:
+      hipLaunchKernelGGL((ss_forward_kernel<NS, NE>), dim3(1), dim3(64), 0, s, A.step, A.gain, A.n, A.V, A.nv, A.Y);
+      break;
+    case SS_BACKWARD:
+      hipLaunchKernelGGL((ss_backward_kernel<NS, NE>), dim3(2), dim3(64), 0, s, A.step, A.gain, A.n, A.Y, A.nv,
+                         A.Z, A.Gm);
+      break;
+    case SS_BOX: {
+      DurList dl{};
+      dl.n = A.n_d;
+      int dmax = 0;
+      for (int k = 0; k < A.n_d; ++k) {
+        dl.d[k] = A.dur_sorted[k];
+        dl.perm[k] = A.dur_sorted[A.n_d + k];
+        dmax = dl.d[k] > dmax ? dl.d[k] : dmax;
+      }
+      const int half = dmax / 2;
+      const int64_t threads = A.n_epochs + half;
+      hipLaunchKernelGGL((ss_box_kernel<NS, NE>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, A.step,
+                         A.gain, A.Gm, A.n, A.lattice, A.slot_count, A.n_epochs, dl, half, A.qbox);
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int NS>
+hipError_t dispatch_ne(int phase, hipStream_t s, const SsArgs& A) {
+  switch (A.n_exp) {
+    case 0:
+      if constexpr (NS > 0) return launch_ss_typed<NS, 0>(phase, s, A);
+      return hipErrorInvalidValue;
+    case 1: return launch_ss_typed<NS, 1>(phase, s, A);
+    case 2: return launch_ss_typed<NS, 2>(phase, s, A);
+    case 3: return launch_ss_typed<NS, 3>(phase, s, A);
+    case 4: return launch_ss_typed<NS, 4>(phase, s, A);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_ss_step(hipStream_t s, const double* t, int64_t n, const nu_kernel& k, double* step) {
+  if (n < 2) return hipSuccess;
+  const int ts = 7 * k.n_sho + 2 * k.n_exp;
+  hipLaunchKernelGGL(ss_step_kernel, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s, t, n, k, ts, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_ss(int phase, hipStream_t s, const SsArgs& A) {
+  switch (A.n_sho) {
+    case 0: return dispatch_ne<0>(phase, s, A);
+    case 1: return dispatch_ne<1>(phase, s, A);
+    case 2: return dispatch_ne<2>(phase, s, A);
+    case 3: return dispatch_ne<3>(phase, s, A);
+    case 4: return dispatch_ne<4>(phase, s, A);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace nu
