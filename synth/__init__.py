@@ -1,4 +1,5 @@
-"""Seeded synthetic inputs for the transit search (light curves, grids).
+"""Seeded synthetic inputs for the transit search (light curves, grids,
+single-event shapes in ``synth.templates``).
 
 Serves the oracle, the tests and the benchmark alike. Holds none of the
 search's arithmetic; see ``synth.lightcurve`` for how curves are drawn.
