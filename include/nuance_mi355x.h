@@ -185,6 +185,7 @@ nu_status nu_linear_search(nu_ctx* ctx, nu_factor* factor, const double* f, cons
  * rounding, in FP64.
  * t: device, n doubles, non-decreasing (the sample times of K). f, A,
  * lattice, n_epochs, dur_samples_host, the outputs and null_out as in (2).
+ * shapes_host: NULL for boxes, or template shapes as in (2c).
  * The kernel is passed by value to the device (no upload, no allocation
  * beyond the context's workspace: about n (3 YCOLS + 8 J + J^2) doubles plus
  * one double per cell).
@@ -196,8 +197,24 @@ nu_status nu_linear_search(nu_ctx* ctx, nu_factor* factor, const double* f, cons
  * invalid. */
 nu_status nu_linear_search_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel* kernel_host, const double* f,
                               const double* A, int m1, const int64_t* lattice, int64_t n_epochs,
-                              const int32_t* dur_samples_host, int n_d, double* depth, double* var, double* dll,
-                              uint8_t* valid, double* null_out, int64_t* fail_index_host);
+                              const int32_t* dur_samples_host, int n_d, const double* shapes_host, double* depth,
+                              double* var, double* dll, uint8_t* valid, double* null_out, int64_t* fail_index_host);
+
+/* (2c) Linear search with a non-box base model in the last column of the
+ * design (Section 5, prospects: limb-darkened transits, exocomets, flares):
+ * as (2), with the box of duration j replaced by its shape. shapes_host:
+ * host, the n_d shapes concatenated in the caller's duration order, shape j
+ * holding dur_samples_host[j] finite values (one per lattice slot of the
+ * window), at most 2048 values together; copied before the call returns.
+ * The last column of cell (j, i) is -shape_j[l - a] on samples whose slot l
+ * lies in [a, a + d_j), a = i - floor(d_j/2), and 0 elsewhere; depth is the
+ * coefficient of the shape (the unit shape gives (2)'s outputs). The same
+ * shapes_host argument of (2b) (NULL there means boxes) gives the
+ * state-space version of this search. */
+nu_status nu_linear_search_template(nu_ctx* ctx, nu_factor* factor, const double* f, const double* A, int m1,
+                                    const int64_t* lattice, int64_t n_epochs, const int32_t* dur_samples_host,
+                                    int n_d, const double* shapes_host, nu_precision prec, double* depth,
+                                    double* var, double* dll, uint8_t* valid, double* null_out);
 
 /* (3) Periodic search (Sections 2.3-2.4, Eqs. 8, 9, B4).
  * depth/var/dll/valid: device, [n_d][n_epochs] as produced by (2).

@@ -50,8 +50,11 @@ SIGNATURES = {
     "nu_linear_search": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int64, P(c_int32), c_int,
                                  c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "nu_linear_search_ss": (c_int, [c_void_p, c_void_p, c_int64, P(NuKernel), c_void_p, c_void_p, c_int, c_void_p,
-                                    c_int64, P(c_int32), c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                                    P(c_int64)]),
+                                    c_int64, P(c_int32), c_int, P(c_double), c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, P(c_int64)]),
+    "nu_linear_search_template": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_int64,
+                                          P(c_int32), c_int, P(c_double), c_int, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p]),
     "nu_periodic_search": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int64, c_double,
                                    c_void_p, c_int64, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p]),

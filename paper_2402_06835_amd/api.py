@@ -224,14 +224,31 @@ def gp_factor(ctx: Context, t, theta, out: Optional[Factor] = None) -> Factor:
     return Factor(p, t_dev.numel(), logdet.value)
 
 
+def _shapes_arg(shapes, durs):
+    """Concatenated template shapes (one per duration, d_j values each) as a contiguous host array, or None."""
+    if shapes is None:
+        return None
+    if len(shapes) != durs.size:
+        raise ValueError("one shape per duration")
+    parts = [np.asarray(s, dtype=np.float64).reshape(-1) for s in shapes]
+    for p_, d in zip(parts, durs):
+        if p_.size != int(d):
+            raise ValueError("shape j must hold durations[j] values (one per slot of the window)")
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
 def linear_search(ctx: Context, factor: Factor, f, A, lattice, n_epochs: int, durations,
-                  precision: str = "fp64") -> dict:
+                  precision: str = "fp64", shapes=None) -> dict:
     """Single-event GLS fits over every (duration, epoch slot) cell.
 
     f: (N,), A: (N, m1) trend design or None, lattice: (N,) int64 slot of each
     sample (lattice[0] == 0, strictly increasing), durations: box lengths in
     slots. Returns device tensors depth, var, dll (float64) and valid (uint8),
     shaped (n_d, n_epochs), and ``null`` = [ln L_0, chi2_0, ln|K|].
+
+    ``shapes``: one shape per duration (``durations[j]`` values, one per slot of
+    the window) in place of the box (entry point 2c): limb-darkened transits,
+    exocomets, any single-event base model.
     """
     dev = ctx.device
     f_d = _dev_tensor(f, torch.float64, dev)
@@ -260,12 +277,22 @@ def linear_search(ctx: Context, factor: Factor, f, A, lattice, n_epochs: int, du
     null = torch.empty(3, dtype=torch.float64, device=dev)
     if precision not in PRECISIONS:
         raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
-    st = lib().nu_linear_search(
-        ctx.ptr, factor.ptr, ctypes.c_void_p(f_d.data_ptr()),
-        ctypes.c_void_p(A_d.data_ptr() if A_d is not None else 0), m1, ctypes.c_void_p(lat.data_ptr()),
-        int(n_epochs), durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d, PRECISIONS[precision],
-        ctypes.c_void_p(depth.data_ptr()), ctypes.c_void_p(var.data_ptr()), ctypes.c_void_p(dll.data_ptr()),
-        ctypes.c_void_p(valid.data_ptr()), ctypes.c_void_p(null.data_ptr()))
+    shp = _shapes_arg(shapes, durs)
+    if shp is None:
+        st = lib().nu_linear_search(
+            ctx.ptr, factor.ptr, ctypes.c_void_p(f_d.data_ptr()),
+            ctypes.c_void_p(A_d.data_ptr() if A_d is not None else 0), m1, ctypes.c_void_p(lat.data_ptr()),
+            int(n_epochs), durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d, PRECISIONS[precision],
+            ctypes.c_void_p(depth.data_ptr()), ctypes.c_void_p(var.data_ptr()), ctypes.c_void_p(dll.data_ptr()),
+            ctypes.c_void_p(valid.data_ptr()), ctypes.c_void_p(null.data_ptr()))
+    else:
+        st = lib().nu_linear_search_template(
+            ctx.ptr, factor.ptr, ctypes.c_void_p(f_d.data_ptr()),
+            ctypes.c_void_p(A_d.data_ptr() if A_d is not None else 0), m1, ctypes.c_void_p(lat.data_ptr()),
+            int(n_epochs), durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d,
+            shp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), PRECISIONS[precision],
+            ctypes.c_void_p(depth.data_ptr()), ctypes.c_void_p(var.data_ptr()), ctypes.c_void_p(dll.data_ptr()),
+            ctypes.c_void_p(valid.data_ptr()), ctypes.c_void_p(null.data_ptr()))
     _check(ctx.ptr, st)
     # keep the inputs alive until the enqueued work has consumed them
     return {"depth": depth, "var": var, "dll": dll, "valid": valid, "null": null,
@@ -279,13 +306,14 @@ def _as_kernel(theta) -> "Kernel":
     return Kernel(sho=[(sho.amp, sho.omega, sho.q)], sigma_w=sho.sigma_w)
 
 
-def linear_search_ss(ctx: Context, t, theta, f, A, lattice, n_epochs: int, durations, check: bool = True) -> dict:
+def linear_search_ss(ctx: Context, t, theta, f, A, lattice, n_epochs: int, durations, check: bool = True,
+                     shapes=None) -> dict:
     """The linear search of ``linear_search`` from the state-space (Kalman) form of the covariance
     (entry point 2b): no N x N factor, O(N J^2) work. ``theta``: Kernel, SHO or SHO dict.
 
     With ``check`` the call waits for the filter and raises NU_ERR_NOT_PD (with ``.index``, the first
     failing sample) if an innovation variance is not positive; without it nothing waits, and a failure
-    shows as NaN in ``null`` and every cell invalid."""
+    shows as NaN in ``null`` and every cell invalid. ``shapes`` as in ``linear_search``."""
     dev = ctx.device
     kc = _as_kernel(theta).c()
     t_d = _dev_tensor(t, torch.float64, dev)
@@ -306,10 +334,13 @@ def linear_search_ss(ctx: Context, t, theta, f, A, lattice, n_epochs: int, durat
     valid = torch.empty(shape, dtype=torch.uint8, device=dev)
     null = torch.empty(3, dtype=torch.float64, device=dev)
     fail = ctypes.c_int64(-1)
+    shp = _shapes_arg(shapes, durs)
     st = lib().nu_linear_search_ss(
         ctx.ptr, ctypes.c_void_p(t_d.data_ptr()), n, ctypes.byref(kc), ctypes.c_void_p(f_d.data_ptr()),
         ctypes.c_void_p(A_d.data_ptr() if A_d is not None else 0), m1, ctypes.c_void_p(lat.data_ptr()),
-        int(n_epochs), durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d, ctypes.c_void_p(depth.data_ptr()),
+        int(n_epochs), durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d,
+        shp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if shp is not None else None,
+        ctypes.c_void_p(depth.data_ptr()),
         ctypes.c_void_p(var.data_ptr()), ctypes.c_void_p(dll.data_ptr()), ctypes.c_void_p(valid.data_ptr()),
         ctypes.c_void_p(null.data_ptr()), ctypes.byref(fail) if check else None)
     if st != NU_OK:
@@ -854,19 +885,22 @@ class Nuance:
         self._ls = None
         self._dur_slots = None
 
-    def linear_search(self, t0s=None, Ds=(0.04,), precision: str = "fp64") -> dict:
+    def linear_search(self, t0s=None, Ds=(0.04,), precision: str = "fp64", template=None) -> dict:
+        """Single-event fits on every epoch slot for the durations ``Ds`` (time units). ``template``: None for
+        boxes, or a function of the window length in slots returning the shape (one value per slot)."""
         if t0s is not None and np.asarray(t0s).size not in (self.lattice.size, self.n_epochs):
             raise ValueError("epochs are the lattice slots of the time array")
         slots = np.rint(np.asarray(Ds, dtype=np.float64) / self.dt).astype(np.int32)
         if np.any(slots < 1):
             raise ValueError("durations must be at least one cadence")
         self._dur_slots = slots
+        shapes = None if template is None else [np.asarray(template(int(d)), dtype=np.float64) for d in slots]
         if self.solver == "statespace":
             self._ls = linear_search_ss(self.ctx, self.time, self.gp, self.flux, self.X, self.lattice,
-                                        self.n_epochs, slots)
+                                        self.n_epochs, slots, shapes=shapes)
         else:
             self._ls = linear_search(self.ctx, self.factor, self.flux, self.X, self.lattice, self.n_epochs, slots,
-                                     precision)
+                                     precision, shapes=shapes)
         return self._ls
 
     def periodic_search(self, periods, sign: int = 1) -> SearchResult:

@@ -42,6 +42,41 @@ void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st) {
   return ctx->ws;
 }
 
+nu_status ctx_upload(nu_ctx* ctx, const void* host, size_t bytes, void* dev) {
+  if (bytes == 0) return NU_OK;
+  // the previous copy out of the staging buffer must be done before it is overwritten
+  if (ctx->pinned_ev) {
+    nu_status st = check_hip(ctx, hipEventSynchronize(ctx->pinned_ev), "upload wait");
+    if (st != NU_OK) return st;
+  } else {
+    nu_status st = check_hip(ctx, hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming), "upload event");
+    if (st != NU_OK) return st;
+  }
+  if (bytes > ctx->pinned_bytes) {
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    nu_status st = check_hip(ctx, hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault), "pinned staging");
+    if (st != NU_OK) return st;
+    ctx->pinned_bytes = bytes;
+  }
+  std::memcpy(ctx->pinned, host, bytes);
+  nu_status st = check_hip(ctx, hipMemcpyAsync(dev, ctx->pinned, bytes, hipMemcpyHostToDevice, ctx->stream),
+                           "upload");
+  if (st == NU_OK) st = check_hip(ctx, hipEventRecord(ctx->pinned_ev, ctx->stream), "upload event");
+  return st;
+}
+
+nu_status validate_shapes(nu_ctx* ctx, const double* shapes_host, const int32_t* dur_samples_host, int n_d) {
+  int64_t total = 0;
+  for (int j = 0; j < n_d; ++j) total += dur_samples_host[j];
+  if (total > MAX_SHAPE)
+    return set_error(ctx, NU_ERR_ARG, "template search: the shapes together may hold at most 2048 values");
+  for (int64_t k = 0; k < total; ++k)
+    if (!std::isfinite(shapes_host[k])) return set_error(ctx, NU_ERR_ARG, "template search: shape values must be finite");
+  return NU_OK;
+}
+
 void* ctx_arena(nu_ctx* ctx, size_t bytes, nu_status* st) {
   *st = NU_OK;
   if (bytes <= ctx->arena_bytes) return ctx->arena;
@@ -221,6 +256,8 @@ void nu_ctx_destroy(nu_ctx* ctx) {
   nu::destroy_factor_streams(ctx);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->arena) (void)hipFree(ctx->arena);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->pinned_ev) (void)hipEventDestroy(ctx->pinned_ev);
   for (auto& p : ctx->pending) {
     (void)hipEventDestroy(p.start);
     (void)hipEventDestroy(p.stop);
@@ -383,10 +420,42 @@ nu_status nu_linear_search(nu_ctx* ctx, nu_factor* F, const double* f, const dou
 }
 
 // ---------------------------------------------------------------------------
+nu_status nu_linear_search_template(nu_ctx* ctx, nu_factor* F, const double* f, const double* A, int m1,
+                                    const int64_t* lattice, int64_t n_epochs, const int32_t* dur_samples_host,
+                                    int n_d, const double* shapes_host, nu_precision prec, double* depth,
+                                    double* var, double* dll, uint8_t* valid, double* null_out) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!F || !shapes_host) return set_error(ctx, NU_ERR_ARG, "linear_search_template: null argument");
+  if (F->device != ctx->device) return set_error(ctx, NU_ERR_ARG, "linear_search_template: factor on another device");
+  nu_status st = validate_linear(ctx, F->n, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, prec, depth, var,
+                                 dll, valid);
+  if (st == NU_OK) st = validate_shapes(ctx, shapes_host, dur_samples_host, n_d);
+  if (st != NU_OK) return st;
+  st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+  const bool mixed = prec != NU_FP64;
+  const int want = 1 + (int)prec;
+  if (F->inverse_kind != want) {
+    if (mixed) {
+      st = ensure_plan32(ctx, F, prec);
+      if (st == NU_OK) st = run_inverse_mixed(ctx, {F}, F->plan32, prec);
+    } else {
+      st = run_inverse_fp64(ctx, F->plan64);
+    }
+    if (st != NU_OK) return st;
+    F->inverse_kind = want;
+  }
+  double* ws = (double*)ctx_workspace(ctx, linear_ws_bytes(F->n, n_d, n_epochs), &st);
+  if (!ws) return st;
+  return run_linear(ctx, F, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, prec, depth, var, dll, valid,
+                    null_out, ws, shapes_host);
+}
+
+// ---------------------------------------------------------------------------
 nu_status nu_linear_search_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel* kernel_host, const double* f,
                               const double* A, int m1, const int64_t* lattice, int64_t n_epochs,
-                              const int32_t* dur_samples_host, int n_d, double* depth, double* var, double* dll,
-                              uint8_t* valid, double* null_out, int64_t* fail_index_host) {
+                              const int32_t* dur_samples_host, int n_d, const double* shapes_host, double* depth,
+                              double* var, double* dll, uint8_t* valid, double* null_out, int64_t* fail_index_host) {
   if (!ctx) return NU_ERR_ARG;
   if (!t || !kernel_host) return set_error(ctx, NU_ERR_ARG, "linear_search_ss: null argument");
   nu_status st = validate_kernel(ctx, kernel_host);
@@ -395,14 +464,15 @@ nu_status nu_linear_search_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_
     return set_error(ctx, NU_ERR_ARG, "linear_search_ss: the kernel needs at least one SHO or exponential term");
   if (n < 1 || n > ((int64_t)1 << 31)) return set_error(ctx, NU_ERR_ARG, "linear_search_ss: n must be in [1, 2^31]");
   st = validate_linear(ctx, n, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, NU_FP64, depth, var, dll, valid);
+  if (st == NU_OK && shapes_host) st = validate_shapes(ctx, shapes_host, dur_samples_host, n_d);
   if (st != NU_OK) return st;
   st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (st != NU_OK) return st;
   double* ws = (double*)ctx_workspace(ctx, linear_ss_ws_bytes(n, *kernel_host, n_d, n_epochs), &st);
   if (!ws) return st;
   int64_t* status_dev = nullptr;
-  st = run_linear_ss(ctx, t, n, *kernel_host, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, depth, var, dll,
-                     valid, null_out, ws, &status_dev);
+  st = run_linear_ss(ctx, t, n, *kernel_host, f, A, m1, lattice, n_epochs, dur_samples_host, n_d, shapes_host, depth,
+                     var, dll, valid, null_out, ws, &status_dev);
   if (st != NU_OK || !fail_index_host) return st;
   int64_t fail = -1;
   st = check_hip(ctx, hipMemcpyAsync(&fail, status_dev, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream),

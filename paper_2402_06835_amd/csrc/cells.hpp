@@ -14,6 +14,7 @@ struct DurList {
   int n;
   int d[MAX_ND];     // box lengths in slots (ascending for the q kernels, caller order for the epilogue)
   int perm[MAX_ND];  // q kernels: caller index of the k-th ascending duration
+  int off[MAX_ND];   // template searches: offset of the duration's shape in the concatenated shapes
 };
 
 __device__ __forceinline__ int64_t lower_bound_i64(const int64_t* __restrict__ a, int64_t n, int64_t v) {

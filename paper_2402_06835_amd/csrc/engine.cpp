@@ -633,7 +633,8 @@ size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs) {
   const size_t xchunks = (size_t)((n + XRC - 1) / XRC), qchunks = (size_t)((n + QRC - 1) / QRC);
   const size_t yz = (size_t)np * YCOLS;
   const size_t slots = ((size_t)n_epochs + 2) / 2;  // the int32 slot-count table, in doubles
-  return (5 * yz + xchunks * yz + qchunks * (size_t)n_d * (size_t)n_epochs + slots) * sizeof(double);
+  // template shapes after the slot table
+  return (5 * yz + xchunks * yz + qchunks * (size_t)n_d * (size_t)n_epochs + slots + MAX_SHAPE) * sizeof(double);
 }
 
 nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double* A, int m1, const int64_t* lattice,
@@ -658,7 +659,8 @@ nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double*
 
 nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A, int m1, const int64_t* lattice,
                      int64_t n_epochs, const int32_t* dur_samples_host, int n_d, int prec, double* depth,
-                     double* var, double* dll, uint8_t* valid, double* null_out, double* ws) {
+                     double* var, double* dll, uint8_t* valid, double* null_out, double* ws,
+                     const double* shapes_host) {
   const int steps = refine_steps(prec);
   const int64_t n = F->n, np = F->np;
   const int xchunks = (int)((n + XRC - 1) / XRC);
@@ -672,12 +674,20 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
   double* xpart = Rz + yz;
   double* qpart = xpart + (size_t)xchunks * yz;
   int32_t* slot_count = reinterpret_cast<int32_t*>(qpart + (size_t)qchunks * n_d * n_epochs);
+  double* shapes = qpart + (size_t)qchunks * n_d * n_epochs + ((size_t)n_epochs + 2) / 2;
   const int nv = m1 + 1;
   const double gemv_bytes = (double)n * (double)(n + 1) / 2.0 * 8.0;
   int dmax = 0;
   for (int j = 0; j < n_d; ++j) dmax = std::max(dmax, (int)dur_samples_host[j]);
 
-  nu_status st = check_hip(ctx, launch_pack_v(ctx->stream, A, m1, f, n, V), "pack_v");
+  nu_status st = NU_OK;
+  if (shapes_host) {
+    size_t total = 0;
+    for (int j = 0; j < n_d; ++j) total += (size_t)dur_samples_host[j];
+    st = ctx_upload(ctx, shapes_host, total * sizeof(double), shapes);
+    if (st != NU_OK) return st;
+  }
+  st = check_hip(ctx, launch_pack_v(ctx->stream, A, m1, f, n, V), "pack_v");
   if (st != NU_OK) return st;
   {
     // Y = X V, refined against L when X is a reduced-precision inverse
@@ -720,7 +730,14 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
     sorted[k] = dur_samples_host[order[k]];
     sorted[n_d + k] = order[k];
   }
-  {
+  if (shapes_host) {
+    Timed tm(ctx, "q_template", 0.0);
+    st = check_hip(ctx, launch_slot_count(ctx->stream, lattice, n, n_epochs, slot_count), "slot_count");
+    if (st == NU_OK)
+      st = check_hip(ctx, launch_q_template(ctx->stream, F->X, np, n, lattice, slot_count, n_epochs, sorted.data(),
+                                            dur_samples_host, n_d, shapes, dmax, QRC, qchunks, qpart),
+                     "q_template");
+  } else {
     Timed tm(ctx, "q_partial", 0.0);
     st = check_hip(ctx, launch_slot_count(ctx->stream, lattice, n, n_epochs, slot_count), "slot_count");
     if (st == NU_OK)
@@ -732,8 +749,8 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
   {
     Timed tm(ctx, "cell_epilogue", 0.0);
     st = check_hip(ctx, launch_cell_epilogue(ctx->stream, qpart, qchunks, lattice, slot_count, n, n_epochs,
-                                             dur_samples_host, nullptr, n_d, Z, m1, F->nullfit, depth, var, dll,
-                                             valid),
+                                             dur_samples_host, n_d, Z, m1, F->nullfit, depth, var, dll, valid,
+                                             shapes_host ? shapes : nullptr),
                    "cell_epilogue");
   }
   return st;

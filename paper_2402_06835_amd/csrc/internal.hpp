@@ -28,6 +28,7 @@ constexpr int YCOLS = 8;         // row stride of the whitened [A | f] panel
 constexpr int MAX_ND = 16;       // durations per search
 constexpr int MAX_DUR = 1024;    // samples per box
 constexpr int MAX_SEG = 32;      // segments of a segmented periodic search
+constexpr int MAX_SHAPE = 2048;  // values of all shapes of a template search together
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -138,6 +139,11 @@ struct nu_ctx {
   hipStream_t s_fac = nullptr, s_rest = nullptr;
   hipEvent_t ev_fork = nullptr, ev_pan = nullptr, ev_rest = nullptr, ev_join = nullptr;
   bool lookahead = true;
+  // pinned host staging of small host-to-device uploads (template shapes); the
+  // event marks the last copy out of it
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t pinned_ev = nullptr;
 };
 
 namespace nu {
@@ -221,6 +227,10 @@ namespace nu {
 nu_status set_error(nu_ctx* ctx, nu_status st, const std::string& msg);
 nu_status check_hip(nu_ctx* ctx, hipError_t e, const char* what);
 void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st);
+// host -> device copy on the context's stream through the pinned staging buffer
+nu_status ctx_upload(nu_ctx* ctx, const void* host, size_t bytes, void* dev);
+// template shapes: validates n_d shapes of dur_samples_host[j] values each (finite, total <= MAX_SHAPE)
+nu_status validate_shapes(nu_ctx* ctx, const double* shapes_host, const int32_t* dur_samples_host, int n_d);
 
 // kernel timing (capi.cpp): events on the context's stream around a launch
 void timing_begin(nu_ctx* ctx, hipStream_t s, hipEvent_t* start);
@@ -275,14 +285,16 @@ size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs);
 nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double* A, int m1, const int64_t* lattice,
                           int64_t n_epochs, const int32_t* dur_samples_host, int n_d, nu_precision prec,
                           const void* depth, const void* var, const void* dll, const void* valid);
+// shapes_host: NULL for boxes, else the concatenated template shapes (caller order; copied into ws)
 nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A, int m1, const int64_t* lattice,
                      int64_t n_epochs, const int32_t* dur_samples_host, int n_d, int prec, double* depth,
-                     double* var, double* dll, uint8_t* valid, double* null_out, double* ws);
+                     double* var, double* dll, uint8_t* valid, double* null_out, double* ws,
+                     const double* shapes_host = nullptr);
 size_t linear_ss_ws_bytes(int64_t n, const nu_kernel& k, int n_d, int64_t n_epochs);
 nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel& k, const double* f, const double* A,
                         int m1, const int64_t* lattice, int64_t n_epochs, const int32_t* dur_samples_host, int n_d,
-                        double* depth, double* var, double* dll, uint8_t* valid, double* null_out, double* ws,
-                        int64_t** status_dev);
+                        const double* shapes_host, double* depth, double* var, double* dll, uint8_t* valid,
+                        double* null_out, double* ws, int64_t** status_dev);
 size_t periodic_ws_bytes(int n_d, int64_t n_epochs);
 nu_status validate_periodic(nu_ctx* ctx, int n_d, int64_t n_epochs, double dt, int64_t n_p, int log_term_sign);
 nu_status run_periodic(nu_ctx* ctx, const double* depth, const double* var, const double* dll, const uint8_t* valid,
@@ -322,11 +334,15 @@ hipError_t launch_slot_count(hipStream_t s, const int64_t* lattice, int64_t n, i
 hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t n, const int64_t* lattice,
                             const int32_t* T, int64_t n_epochs, const int32_t* dur_sorted, int n_d, int dmax,
                             int rowchunk, int nchunks, double* qpart);
+// shapes: NULL for boxes, else the concatenated template shapes on the device (caller order)
 hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks, const int64_t* lattice,
-                                const int32_t* T, int64_t n, int64_t n_epochs, const int32_t* dur,
-                                const int32_t* dur_rank, int n_d,
+                                const int32_t* T, int64_t n, int64_t n_epochs, const int32_t* dur, int n_d,
                                 const double* Z, int m1, const NullFit* nf, double* depth, double* var, double* dll,
-                                uint8_t* valid);
+                                uint8_t* valid, const double* shapes = nullptr);
+// q of template cells from the rows of X (shapes on the device, caller order; dur_sorted as for q_partial)
+hipError_t launch_q_template(hipStream_t s, const double* X, int64_t ldx, int64_t n, const int64_t* lattice,
+                             const int32_t* T, int64_t n_epochs, const int32_t* dur_sorted, const int32_t* dur,
+                             int n_d, const double* shapes, int dmax, int rowchunk, int nchunks, double* qpart);
 hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, const double* dll,
                        const uint8_t* valid, int n_d, int64_t n_epochs, double dt, const double* periods, int64_t n_p,
                        int sign, double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth,
@@ -344,7 +360,7 @@ hipError_t launch_best_period(hipStream_t s, const double* q_snr, int64_t n_p, i
 
 // State-space linear search (statespace.hip): the phases after the step
 // coefficients, each one launch on the stream.
-enum SsPhase { SS_RICCATI = 0, SS_FORWARD, SS_BACKWARD, SS_BOX };
+enum SsPhase { SS_RICCATI = 0, SS_FORWARD, SS_BACKWARD, SS_BOX, SS_TEMPLATE };
 struct SsArgs {
   int n_sho = 0, n_exp = 0;
   int64_t n = 0;
@@ -362,7 +378,9 @@ struct SsArgs {
   const int32_t* slot_count = nullptr;
   int64_t n_epochs = 0;
   const int32_t* dur_sorted = nullptr;  // host [2 n_d]: ascending durations, then their caller indices
+  const int32_t* dur = nullptr;         // host [n_d], caller order
   int n_d = 0;
+  const double* shapes = nullptr;       // device, concatenated template shapes (caller order), or NULL: boxes
   double* qbox = nullptr;               // [n_d][n_epochs]
 };
 hipError_t launch_ss_step(hipStream_t s, const double* t, int64_t n, const nu_kernel& k, double* step);

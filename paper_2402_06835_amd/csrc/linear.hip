@@ -439,14 +439,20 @@ hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t
 }
 
 // ---------------------------------------------------------------------------
+// Per cell: q from the partial sums, g = A^T K^-1 b and h = b^T K^-1 r0 as
+// (weighted) window sums of Z, the Schur complement of the trend block, and
+// the outputs. With TPL the box is the duration's shape: sample r of the
+// window weighs shapes[off_j + lattice[r] - a].
+template <bool TPL>
 __global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __restrict__ qpart, int nchunks,
                                                             const int64_t* __restrict__ lattice,
                                                             const int32_t* __restrict__ T, int64_t n,
                                                             int64_t n_epochs, DurList dl,
                                                             const double* __restrict__ Z, int m1,
-                                                            const NullFit* __restrict__ nf, double* __restrict__ depth,
-                                                            double* __restrict__ var, double* __restrict__ dll,
-                                                            uint8_t* __restrict__ valid) {
+                                                            const NullFit* __restrict__ nf,
+                                                            const double* __restrict__ shapes,
+                                                            double* __restrict__ depth, double* __restrict__ var,
+                                                            double* __restrict__ dll, uint8_t* __restrict__ valid) {
   const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (cell >= (int64_t)dl.n * n_epochs) return;
   const int j = (int)(cell / n_epochs);
@@ -464,10 +470,11 @@ __global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __rest
   if (ok) {
     for (int64_t r = lo; r < hi; ++r) {
       const double* zr = Z + r * YCOLS;
+      const double wgt = TPL ? shapes[dl.off[j] + (int)(lattice[r] - a)] : 1.0;
 #pragma unroll
       for (int c = 0; c < MAX_M1; ++c)
-        if (c < m1) g[c] -= zr[c];
-      h -= zr[m1];
+        if (c < m1) g[c] = fma(-wgt, zr[c], g[c]);
+      h = fma(-wgt, zr[m1], h);
     }
   }
   // S = q - g^T G0^-1 g via y = chol(G0)^-1 g
@@ -503,18 +510,134 @@ __global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __rest
 }
 
 hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks, const int64_t* lattice,
-                                const int32_t* T, int64_t n, int64_t n_epochs, const int32_t* dur, const int32_t* /*dur_rank*/, int n_d,
+                                const int32_t* T, int64_t n, int64_t n_epochs, const int32_t* dur, int n_d,
                                 const double* Z, int m1, const NullFit* nf, double* depth, double* var, double* dll,
-                                uint8_t* valid) {
+                                uint8_t* valid, const double* shapes) {
   DurList dl{};
   dl.n = n_d;
+  int off = 0;
   for (int k = 0; k < n_d; ++k) {
     dl.d[k] = dur[k];
     dl.perm[k] = k;
+    dl.off[k] = off;
+    off += dur[k];
   }
   const int64_t cells = (int64_t)n_d * n_epochs;
-  hipLaunchKernelGGL(cell_epilogue_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, qpart, nchunks,
-                     lattice, T, n, n_epochs, dl, Z, m1, nf, depth, var, dll, valid);
+  const dim3 g((unsigned)((cells + 255) / 256)), b(256);
+  if (shapes)
+    hipLaunchKernelGGL(cell_epilogue_kernel<true>, g, b, 0, s, qpart, nchunks, lattice, T, n, n_epochs, dl, Z, m1,
+                       nf, shapes, depth, var, dll, valid);
+  else
+    hipLaunchKernelGGL(cell_epilogue_kernel<false>, g, b, 0, s, qpart, nchunks, lattice, T, n, n_epochs, dl, Z, m1,
+                       nf, shapes, depth, var, dll, valid);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// q of template cells: q = sum_r (sum_m X[r][m] b_m)^2 with b the shape of the
+// cell on its window. As in q_partial, a wave owns 64 consecutive epoch slots
+// and one chunk of rows; here a row is laid out by lattice slot in the wave's
+// LDS row (zeros on slots without a sample), so a cell's window is a
+// contiguous run of it and the shape value at window offset k is the same for
+// every lane: each lane takes, per duration, the dot product of its window
+// with the shape (staged once per workgroup in LDS). The span of slots a
+// wave's windows cover is 64 + dmax; RUN slots per lane.
+template <int RUN>
+__global__ __launch_bounds__(256) void q_template_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
+                                                         const int64_t* __restrict__ lattice,
+                                                         const int32_t* __restrict__ T, int64_t n_epochs, DurList dl,
+                                                         const double* __restrict__ shapes, int shape_total,
+                                                         int half_max, int rowchunk, double* __restrict__ qpart) {
+  constexpr int SPAN = 64 * RUN;
+  __shared__ double sh[MAX_SHAPE];
+  __shared__ double row[4][SPAN];
+  for (int t = threadIdx.x; t < shape_total; t += 256) sh[t] = shapes[t];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t s0 = (int64_t)blockIdx.x * QCH + wave * 64;  // first slot of the wave
+  const int64_t slot = s0 + lane;
+  const int chunk = blockIdx.y;
+  const bool active = slot < n_epochs;
+  const int64_t base = s0 - half_max;  // slot of row position 0
+  // the sample (if any) on each of the lane's RUN slots
+  int64_t msamp[RUN];
+  int64_t my_lo = INT64_MAX, my_hi = INT64_MIN;
+#pragma unroll
+  for (int e = 0; e < RUN; ++e) {
+    const int64_t sl = base + lane * RUN + e;
+    const int64_t m = count_below(lattice, n, T, n_epochs, sl);
+    const bool present = m < n && lattice[m] == sl;
+    msamp[e] = present ? m : -1;
+    if (present) {
+      my_lo = min(my_lo, m);
+      my_hi = max(my_hi, m + 1);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    my_lo = min(my_lo, (int64_t)__shfl_xor(my_lo, off, 64));
+    my_hi = max(my_hi, (int64_t)__shfl_xor(my_hi, off, 64));
+  }
+  double* P = row[wave];
+  double q[MAX_ND];
+#pragma unroll
+  for (int k = 0; k < MAX_ND; ++k) q[k] = 0.0;
+  const int64_t r0 = max((int64_t)chunk * rowchunk, my_lo);
+  const int64_t r1 = min(n, (int64_t)chunk * rowchunk + rowchunk);
+  if (my_hi > my_lo) {
+    for (int64_t r = r0; r < r1; ++r) {
+      const double* x = X + r * ldx;
+#pragma unroll
+      for (int e = 0; e < RUN; ++e) {
+        const int64_t m = msamp[e];
+        P[lane * RUN + e] = (m >= 0 && m <= r) ? x[m] : 0.0;
+      }
+      wave_lds_fence();
+      if (active) {
+        for (int k = 0; k < dl.n; ++k) {
+          const int d = dl.d[k];
+          const double* shp = sh + dl.off[k];
+          const double* win = P + (slot - d / 2 - base);
+          double acc = 0.0;
+          for (int kk = 0; kk < d; ++kk) acc = fma(shp[kk], win[kk], acc);
+          q[k] = fma(acc, acc, q[k]);
+        }
+      }
+      wave_lds_fence();
+    }
+  }
+  if (active) {
+    for (int k = 0; k < dl.n; ++k) qpart[((int64_t)chunk * dl.n + dl.perm[k]) * n_epochs + slot] = q[k];
+  }
+}
+
+hipError_t launch_q_template(hipStream_t s, const double* X, int64_t ldx, int64_t n, const int64_t* lattice,
+                             const int32_t* T, int64_t n_epochs, const int32_t* dur_sorted, const int32_t* dur,
+                             int n_d, const double* shapes, int dmax, int rowchunk, int nchunks, double* qpart) {
+  // dur_sorted: host [2 n_d]: ascending durations, then their caller indices; dur: caller order
+  int offs[MAX_ND];
+  int total = 0;
+  for (int k = 0; k < n_d; ++k) {
+    offs[k] = total;
+    total += dur[k];
+  }
+  if (total > MAX_SHAPE) return hipErrorInvalidValue;
+  DurList dl{};
+  dl.n = n_d;
+  for (int k = 0; k < n_d; ++k) {
+    dl.d[k] = dur_sorted[k];
+    dl.perm[k] = dur_sorted[n_d + k];
+    dl.off[k] = offs[dl.perm[k]];
+  }
+  const int span = 64 + dmax;
+  const int half = dmax / 2;
+  const dim3 g((unsigned)((n_epochs + QCH - 1) / QCH), (unsigned)nchunks), b(256);
+  if (span <= 64 * 2) hipLaunchKernelGGL(q_template_kernel<2>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart);
+  else if (span <= 64 * 3) hipLaunchKernelGGL(q_template_kernel<3>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart);
+  else if (span <= 64 * 5) hipLaunchKernelGGL(q_template_kernel<5>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart);
+  else if (span <= 64 * 9) hipLaunchKernelGGL(q_template_kernel<9>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart);
+  else if (span <= 64 * 17) hipLaunchKernelGGL(q_template_kernel<17>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ namespace nu {
 
 namespace {
 struct SsWs {
-  double *V, *Y, *Z, *step, *gain, *Gm, *qbox, *logdet;
+  double *V, *Y, *Z, *step, *gain, *Gm, *qbox, *shapes, *logdet;
   int64_t* status;
   NullFit* nf;
   int32_t* slot_count;
@@ -34,6 +34,7 @@ size_t ss_layout(int64_t n, int J, int ts, int n_d, int64_t n_epochs, double* ba
   l.gain = take((size_t)n * (J + 1));
   l.Gm = take((size_t)(n + 1) * J * J);
   l.qbox = take((size_t)n_d * n_epochs);
+  l.shapes = take(MAX_SHAPE);
   l.logdet = take(2);
   l.status = reinterpret_cast<int64_t*>(l.logdet + 1);
   l.nf = reinterpret_cast<NullFit*>(take((sizeof(NullFit) + 7) / 8));
@@ -49,8 +50,8 @@ size_t linear_ss_ws_bytes(int64_t n, const nu_kernel& k, int n_d, int64_t n_epoc
 
 nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel& k, const double* f, const double* A,
                         int m1, const int64_t* lattice, int64_t n_epochs, const int32_t* dur_samples_host, int n_d,
-                        double* depth, double* var, double* dll, uint8_t* valid, double* null_out, double* ws,
-                        int64_t** status_dev) {
+                        const double* shapes_host, double* depth, double* var, double* dll, uint8_t* valid,
+                        double* null_out, double* ws, int64_t** status_dev) {
   const int J = 2 * k.n_sho + k.n_exp, ts = 7 * k.n_sho + 2 * k.n_exp;
   SsWs w{};
   ss_layout(n, J, ts, n_d, n_epochs, ws, &w);
@@ -73,6 +74,8 @@ nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel
   a.slot_count = w.slot_count;
   a.n_epochs = n_epochs;
   a.n_d = n_d;
+  a.dur = dur_samples_host;
+  a.shapes = shapes_host ? w.shapes : nullptr;
   a.qbox = w.qbox;
   // ascending durations (the boxes of one start are nested) with their caller indices
   std::vector<int32_t> order(n_d);
@@ -85,7 +88,14 @@ nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel
     sorted[n_d + j] = order[j];
   }
   a.dur_sorted = sorted.data();
-  nu_status st = check_hip(ctx, launch_pack_v(ctx->stream, A, m1, f, n, w.V), "pack_v");
+  nu_status st = NU_OK;
+  if (shapes_host) {
+    size_t total = 0;
+    for (int j = 0; j < n_d; ++j) total += (size_t)dur_samples_host[j];
+    st = ctx_upload(ctx, shapes_host, total * sizeof(double), w.shapes);
+    if (st != NU_OK) return st;
+  }
+  st = check_hip(ctx, launch_pack_v(ctx->stream, A, m1, f, n, w.V), "pack_v");
   if (st != NU_OK) return st;
   {
     Timed tm(ctx, "ss_step", 0.0);
@@ -115,12 +125,14 @@ nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel
   {
     Timed tm(ctx, "ss_box", 0.0);
     st = check_hip(ctx, launch_slot_count(ctx->stream, lattice, n, n_epochs, w.slot_count), "slot_count");
-    if (st == NU_OK) st = check_hip(ctx, launch_ss(SS_BOX, ctx->stream, a), "ss_box");
+    if (st == NU_OK)
+      st = check_hip(ctx, launch_ss(shapes_host ? SS_TEMPLATE : SS_BOX, ctx->stream, a),
+                     shapes_host ? "ss_template" : "ss_box");
   }
   if (st != NU_OK) return st;
   Timed tm(ctx, "cell_epilogue", 0.0);
   return check_hip(ctx, launch_cell_epilogue(ctx->stream, w.qbox, 1, lattice, w.slot_count, n, n_epochs,
-                                             dur_samples_host, nullptr, n_d, w.Z, m1, w.nf, depth, var, dll, valid),
+                                             dur_samples_host, n_d, w.Z, m1, w.nf, depth, var, dll, valid, a.shapes),
                    "cell_epilogue");
 }
 

@@ -33,6 +33,8 @@
 //   ss_backward  Z = L^-T [A~ | r~0]    (one lane per column) and G_n (one wave; lane a keeps row a)
 //   ss_box       q of every cell, one thread per box start: the boxes of all
 //                durations that start on one slot share the in-box recursion
+//   ss_template  q of every cell of a template search (a shape in place of the
+//                box), one thread per cell
 #include "cells.hpp"
 #include "internal.hpp"
 
@@ -564,6 +566,61 @@ __global__ __launch_bounds__(256) void ss_box_kernel(const double* __restrict__ 
   }
 }
 
+// q of template cells: one thread per cell (the windows of different
+// durations no longer share their recursion, the shape values differ). The
+// in-window recursion takes v = the shape value of each sample's slot.
+template <int NS, int NE>
+__global__ __launch_bounds__(256) void ss_template_kernel(const double* __restrict__ step,
+                                                          const double* __restrict__ gain,
+                                                          const double* __restrict__ Gm, int64_t n,
+                                                          const int64_t* __restrict__ lattice,
+                                                          const int32_t* __restrict__ T, int64_t n_epochs, DurList dl,
+                                                          const double* __restrict__ shapes,
+                                                          double* __restrict__ qbox) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS, GS = Lt::GS;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n_epochs) return;
+  const int d = dl.d[j];
+  const double* shp = shapes + dl.off[j];
+  const int64_t a = i - d / 2;
+  const int64_t lo = count_below(lattice, n, T, n_epochs, a);
+  const int64_t hi = count_below(lattice, n, T, n_epochs, a + d);
+  double x[J];
+#pragma unroll
+  for (int b = 0; b < J; ++b) x[b] = 0.0;
+  double q = 0.0;
+  for (int64_t m = lo; m < hi; ++m) {
+    const double* g = gain + m * GS;
+    double hx = 0.0;
+#pragma unroll
+    for (int b = 0; b < J; ++b)
+      if (Lt::pos(b)) hx += x[b];
+    const double ev = shp[lattice[m] - a] - hx;
+    const double z = ev * g[0];
+    q = fma(z, z, q);
+    if (m + 1 < n) {
+#pragma unroll
+      for (int b = 0; b < J; ++b) x[b] = fma(g[1 + b], ev, x[b]);
+      apply_phi<NS, NE>(step + m * TS, x);
+    } else {
+#pragma unroll
+      for (int b = 0; b < J; ++b) x[b] = 0.0;
+    }
+  }
+  const double* G = Gm + hi * J * J;
+  double tail = 0.0;
+#pragma unroll
+  for (int a2 = 0; a2 < J; ++a2) {
+    double rw = 0.0;
+#pragma unroll
+    for (int b = 0; b < J; ++b) rw = fma(G[a2 * J + b], x[b], rw);
+    tail = fma(x[a2], rw, tail);
+  }
+  qbox[(int64_t)j * n_epochs + i] = q + tail;
+}
+
 template <int NS, int NE>
 hipError_t launch_ss_typed(int phase, hipStream_t s, const SsArgs& A) {
   switch (phase) {
@@ -594,6 +651,21 @@ hipError_t launch_ss_typed(int phase, hipStream_t s, const SsArgs& A) {
       const int64_t threads = A.n_epochs + half;
       hipLaunchKernelGGL((ss_box_kernel<NS, NE>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, A.step,
                          A.gain, A.Gm, A.n, A.lattice, A.slot_count, A.n_epochs, dl, half, A.qbox);
+      break;
+    }
+    case SS_TEMPLATE: {
+      DurList dl{};
+      dl.n = A.n_d;
+      int off = 0;
+      for (int k = 0; k < A.n_d; ++k) {
+        dl.d[k] = A.dur[k];
+        dl.perm[k] = k;
+        dl.off[k] = off;
+        off += A.dur[k];
+      }
+      hipLaunchKernelGGL((ss_template_kernel<NS, NE>), dim3((unsigned)((A.n_epochs + 255) / 256), (unsigned)A.n_d),
+                         dim3(256), 0, s, A.step, A.gain, A.Gm, A.n, A.lattice, A.slot_count, A.n_epochs, dl,
+                         A.shapes, A.qbox);
       break;
     }
     default:
