@@ -58,19 +58,19 @@ def workload(name: str):
     return {"tess-sector": config2, "plain-1440": config1}[name]()
 
 
-def run_step(api, ctx, dev_in, w, precision, fac=None, planets=1, solver="dense", kernel=None):
+def run_step(api, ctx, dev_in, w, precision, fac=None, planets=1, solver="dense", kernel=None, shapes=None):
     """gp_factor + linear_search + periodic_search (solver "statespace": the state-space linear search, no
     factor); with planets > 1, the periodic search is repeated on the same linear-search grid with each found
     candidate's transits masked (Section 4). Returns the factor, the grid, the first periodic search and the
     candidates (None for planets == 1)."""
     if solver == "statespace":
         ls = api.linear_search_ss(ctx, dev_in["t"], kernel, dev_in["f"], dev_in["A"], dev_in["lattice"],
-                                  w.n_epochs, w.durations, check=False)
+                                  w.n_epochs, w.durations, check=False, shapes=shapes)
     else:
         fac = api.gp_factor(ctx, dev_in["t"], w.theta if kernel is None else kernel,
                             out=fac if kernel is None else None)
         ls = api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations,
-                               precision)
+                               precision, shapes=shapes)
     ps = api.periodic_search(ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], w.dt, dev_in["periods"])
     if planets <= 1:
         return fac, ls, ps, None
@@ -86,13 +86,14 @@ def run_step(api, ctx, dev_in, w, precision, fac=None, planets=1, solver="dense"
     return fac, ls, ps, cands
 
 
-def cpu_baseline(w, n_valid: int, budget_cells: int = 192, budget_periods: int = 4, kernel: str = "sho"):
+def cpu_baseline(w, n_valid: int, budget_cells: int = 192, budget_periods: int = 4, kernel: str = "sho",
+                 shapes=None):
     """The oracle on a bounded sample of the same workload, scaled to whole-step fits/s. The oracle is the
     dense definition whichever solver the GPU step uses."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
-    from oracle import gp as ogp, linear as olin, periodic as oper
+    from oracle import gp as ogp, linear as olin, periodic as oper, templates as otpl
 
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     log(f"cpu baseline: oracle K build + Cholesky at N={w.n} ({threads} BLAS threads)")
@@ -112,7 +113,10 @@ def cpu_baseline(w, n_valid: int, budget_cells: int = 192, budget_periods: int =
     cells = [(int(rng.integers(n_d)), int(rng.integers(n_t))) for _ in range(budget_cells)]
     log(f"cpu baseline: oracle GLS on {budget_cells} sampled cells")
     t0 = time.perf_counter()
-    olin.linear_search(w.f, w.A, L, w.lattice, w.durations, cells=cells)
+    if shapes is None:
+        olin.linear_search(w.f, w.A, L, w.lattice, w.durations, cells=cells)
+    else:
+        otpl.linear_search_template(w.f, w.A, L, w.lattice, shapes, cells=cells)
     t_cells = time.perf_counter() - t0
     # the fold needs the single-event grid; a synthetic one of the full shape costs the same
     depth = rng.normal(2e-4, 3e-4, (n_d, n_t))
@@ -428,6 +432,10 @@ def bench_curve(args, api, ctx, torch):
     fac = None
     g = None
     kernel = None
+    shapes = None
+    if args.template != "box":
+        from synth import templates as stpl
+        shapes = stpl.shapes_for(args.template, w.durations)
     if args.kernel == "rotation":
         kernel = api.rotation_kernel(**ROTATION_KERNEL)
     elif args.solver == "statespace":
@@ -437,7 +445,8 @@ def bench_curve(args, api, ctx, torch):
                       w.theta, w.dt, dev_in["periods"], precision=args.precision)
     for i in range(max(args.warmup, 1)):
         if g is None:
-            fac, _, _, _ = run_step(api, ctx, dev_in, w, args.precision, fac, args.planets, args.solver, kernel)
+            fac, _, _, _ = run_step(api, ctx, dev_in, w, args.precision, fac, args.planets, args.solver, kernel,
+                                    shapes)
         else:
             g.launch()
         torch.cuda.synchronize()
@@ -450,7 +459,7 @@ def bench_curve(args, api, ctx, torch):
     for i in range(args.steps):
         # one curve per step; the factor's device buffers are reused across curves of one length
         if g is None:
-            keep = run_step(api, ctx, dev_in, w, args.precision, fac, args.planets, args.solver, kernel)
+            keep = run_step(api, ctx, dev_in, w, args.precision, fac, args.planets, args.solver, kernel, shapes)
         else:
             g.launch()
         log(f"step {i + 1}/{args.steps} enqueued")
@@ -475,7 +484,7 @@ def bench_curve(args, api, ctx, torch):
         if fac is None:
             fac = api.gp_factor(ctx, dev_in["t"], w.theta if kernel is None or args.kernel != "rotation" else kernel)
         ref = dict(api.linear_search(ctx, fac, dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs,
-                                     w.durations))
+                                     w.durations, shapes=shapes))
         ref.update(api.periodic_search(ctx, ref["depth"], ref["var"], ref["dll"], ref["valid"], w.dt,
                                        dev_in["periods"]))
         dll_err = output_errors(got, ref)
@@ -485,7 +494,7 @@ def bench_curve(args, api, ctx, torch):
     cfg = {"workload": w.name, "n_samples": w.n, "n_epochs": w.n_epochs, "n_durations": int(w.durations.size),
            "n_periods": int(w.periods.size), "valid_cells": n_valid,
            "precision": args.precision if args.solver == "dense" else "fp64", "mode": args.mode,
-           "solver": args.solver, "kernel": args.kernel}
+           "solver": args.solver, "kernel": args.kernel, "template": args.template}
     extra = {"best_period_days": float(w.periods[best]) if best >= 0 else None,
              "injected_period_days": w.injection["period"] if w.injection else None}
     if args.planets > 1:
@@ -507,6 +516,8 @@ def main(argv=None):
     ap.add_argument("--solver", default="dense", choices=["dense", "statespace"],
                     help="linear search from the dense factor, or from the state-space (Kalman) form of the "
                          "covariance (FP64; single-curve eager mode)")
+    ap.add_argument("--template", default="box", choices=["box", "limb_darkened", "exocomet"],
+                    help="single-event base model in the last column of the design (Section 5 prospects)")
     ap.add_argument("--kernel", default="sho", choices=["sho", "rotation"],
                     help="covariance: the workload's SHO, or the stellar-variability kernel of Section 3.2")
     ap.add_argument("--planets", type=int, default=1,
@@ -572,8 +583,9 @@ def main(argv=None):
             raise SystemExit("--mode loop compares against the batch (--workload batch-64)")
         if args.planets > 1 and args.mode != "eager":
             raise SystemExit("--planets applies to the eager single-curve step")
-        if (args.solver == "statespace" or args.kernel == "rotation") and args.mode != "eager":
-            raise SystemExit("--solver statespace and --kernel rotation run the eager single-curve step")
+        if (args.solver == "statespace" or args.kernel == "rotation" or args.template != "box") and \
+                args.mode != "eager":
+            raise SystemExit("--solver statespace, --kernel rotation and --template run the eager single-curve step")
         elapsed, n_valid, curves, timings, dll_err, cfg, extra, w = bench_curve(args, api, ctx, torch)
     roof, gemms = (roofline_of(timings) if timings else (None, None))
     if roof is not None:
@@ -597,7 +609,11 @@ def main(argv=None):
     }
     out.update(extra)
     if not args.no_cpu_baseline and w is not None:
-        out["cpu_baseline"] = cpu_baseline(w, n_valid, kernel=args.kernel)
+        shapes = None
+        if args.template != "box":
+            from synth import templates as stpl
+            shapes = stpl.shapes_for(args.template, w.durations)
+        out["cpu_baseline"] = cpu_baseline(w, n_valid, kernel=args.kernel, shapes=shapes)
         out["cpu_baseline"]["unit"] = out["unit"]
     print(json.dumps(out), flush=True)
     return 0
