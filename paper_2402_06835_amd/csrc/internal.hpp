@@ -360,7 +360,11 @@ hipError_t launch_best_period(hipStream_t s, const double* q_snr, int64_t n_p, i
 
 // State-space linear search (statespace.hip): the phases after the step
 // coefficients, each one launch on the stream.
-enum SsPhase { SS_RICCATI = 0, SS_FORWARD, SS_BACKWARD, SS_BOX, SS_TEMPLATE };
+enum SsPhase {
+  SS_RICCATI = 0, SS_FORWARD, SS_BACKWARD, SS_BOX, SS_TEMPLATE,
+  // the chunked (parallel-in-time) forms of the first three
+  SS_PAR_RICCATI, SS_PAR_FORWARD, SS_PAR_BACKWARD
+};
 struct SsArgs {
   int n_sho = 0, n_exp = 0;
   int64_t n = 0;
@@ -382,7 +386,12 @@ struct SsArgs {
   int n_d = 0;
   const double* shapes = nullptr;       // device, concatenated template shapes (caller order), or NULL: boxes
   double* qbox = nullptr;               // [n_d][n_epochs]
+  double* chunk = nullptr;              // chunked path: ss_chunk_ws_doubles(n, J) doubles
 };
+// the chunked path: its workspace, and whether it applies to a kernel (at most
+// 6 states, sigma_w > 0, every term of positive variance)
+size_t ss_chunk_ws_doubles(int64_t n, int J);
+bool ss_chunked_applies(const nu_kernel& k);
 hipError_t launch_ss_step(hipStream_t s, const double* t, int64_t n, const nu_kernel& k, double* step);
 hipError_t launch_ss(int phase, hipStream_t s, const SsArgs& A);
 

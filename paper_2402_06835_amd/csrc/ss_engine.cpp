@@ -12,7 +12,7 @@ namespace nu {
 
 namespace {
 struct SsWs {
-  double *V, *Y, *Z, *step, *gain, *Gm, *qbox, *shapes, *logdet;
+  double *V, *Y, *Z, *step, *gain, *Gm, *qbox, *shapes, *chunk, *logdet;
   int64_t* status;
   NullFit* nf;
   int32_t* slot_count;
@@ -35,6 +35,7 @@ size_t ss_layout(int64_t n, int J, int ts, int n_d, int64_t n_epochs, double* ba
   l.Gm = take((size_t)(n + 1) * J * J);
   l.qbox = take((size_t)n_d * n_epochs);
   l.shapes = take(MAX_SHAPE);
+  l.chunk = take(ss_chunk_ws_doubles(n, J));
   l.logdet = take(2);
   l.status = reinterpret_cast<int64_t*>(l.logdet + 1);
   l.nf = reinterpret_cast<NullFit*>(take((sizeof(NullFit) + 7) / 8));
@@ -77,6 +78,8 @@ nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel
   a.dur = dur_samples_host;
   a.shapes = shapes_host ? w.shapes : nullptr;
   a.qbox = w.qbox;
+  a.chunk = w.chunk;
+  const bool chunked = ss_chunked_applies(k);
   // ascending durations (the boxes of one start are nested) with their caller indices
   std::vector<int32_t> order(n_d);
   for (int j = 0; j < n_d; ++j) order[j] = j;
@@ -104,12 +107,12 @@ nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel
   if (st != NU_OK) return st;
   {
     Timed tm(ctx, "ss_riccati", 0.0);
-    st = check_hip(ctx, launch_ss(SS_RICCATI, ctx->stream, a), "ss_riccati");
+    st = check_hip(ctx, launch_ss(chunked ? SS_PAR_RICCATI : SS_RICCATI, ctx->stream, a), "ss_riccati");
   }
   if (st != NU_OK) return st;
   {
     Timed tm(ctx, "ss_forward", 0.0);
-    st = check_hip(ctx, launch_ss(SS_FORWARD, ctx->stream, a), "ss_forward");
+    st = check_hip(ctx, launch_ss(chunked ? SS_PAR_FORWARD : SS_FORWARD, ctx->stream, a), "ss_forward");
   }
   if (st != NU_OK) return st;
   {
@@ -119,7 +122,7 @@ nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel
   if (st != NU_OK) return st;
   {
     Timed tm(ctx, "ss_backward", 0.0);
-    st = check_hip(ctx, launch_ss(SS_BACKWARD, ctx->stream, a), "ss_backward");
+    st = check_hip(ctx, launch_ss(chunked ? SS_PAR_BACKWARD : SS_BACKWARD, ctx->stream, a), "ss_backward");
   }
   if (st != NU_OK) return st;
   {

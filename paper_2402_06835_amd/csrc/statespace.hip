@@ -286,10 +286,11 @@ __global__ __launch_bounds__(64) void ss_riccati_kernel(const double* __restrict
 }
 
 // ln|K| = sum ln S_n = -2 sum ln(1/sqrt(S_n)) in a fixed order; NaN if the
-// filter failed
+// filter failed. With failmin (the chunked filter's smallest failing sample,
+// n if none) the status is written here from it.
 __global__ __launch_bounds__(256) void ss_logdet_kernel(const double* __restrict__ gain, int gs, int64_t n,
-                                                        const int64_t* __restrict__ status,
-                                                        double* __restrict__ logdet) {
+                                                        const unsigned long long* __restrict__ failmin,
+                                                        int64_t* __restrict__ status, double* __restrict__ logdet) {
   __shared__ double red[4];
   double acc = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) acc += log(gain[i * gs]);
@@ -297,7 +298,14 @@ __global__ __launch_bounds__(256) void ss_logdet_kernel(const double* __restrict
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) *logdet = *status >= 0 ? NAN : -2.0 * (((red[0] + red[1]) + red[2]) + red[3]);
+  if (threadIdx.x == 0) {
+    int64_t st = *status;
+    if (failmin) {
+      st = *failmin < (unsigned long long)n ? (int64_t)*failmin : -1;
+      *status = st;
+    }
+    *logdet = st >= 0 ? NAN : -2.0 * (((red[0] + red[1]) + red[2]) + red[3]);
+  }
 }
 
 // Y = L^-1 V: lane c carries the filter state of column c (lanes past the
@@ -621,6 +629,762 @@ __global__ __launch_bounds__(256) void ss_template_kernel(const double* __restri
   qbox[(int64_t)j * n_epochs + i] = q + tail;
 }
 
+// ---------------------------------------------------------------------------
+// Chunked (parallel-in-time) form of the three recursions, for kernels of at
+// most 6 states with white noise (sigma_w > 0) and every term of positive
+// variance. The samples split into chunks of CL; one thread owns a chunk
+// (J x J matrices in registers).
+//
+// Riccati. With R = sigma_w^2, one sample maps the predicted covariance as
+// P -> Phi (P^-1 + h h^T / R)^-1 Phi^T + Qd, and maps of the form
+// P -> A (P^-1 + Jm)^-1 A^T + C compose into the same form: applying
+// (A2, C2, J2) after (A1, C1, J1) gives, with W = (I + C1 J2)^-1,
+//   A = A2 W A1,  C = A2 W C1 A2^T + C2,  Jm = A1^T J2 W A1 + J1.
+// For one more sample (J2 = h h^T / R, rank one) W = I - C1 h h^T / s with
+// s = R + h^T C1 h, so a chunk composes in O(J^2) per sample:
+//   A <- Phi (A - (C h)(h^T A) / s),  C <- Phi (C - (C h)(C h)^T / s) Phi^T + Qd,
+//   Jm <- Jm + (A^T h)(A^T h)^T / s          (A^T h before the A update).
+// ss_compose builds every chunk's map; ss_carry applies them in turn from
+// Pinf, giving each chunk's true starting P, as
+//   (P^-1 + Jm)^-1 = Z Z^T,  Z = Lp Rz^-T,  P = Lp Lp^T,  I + Lp^T Jm Lp = Rz Rz^T
+// (two Cholesky factorisations, no pivoting: I + Lp^T Jm Lp has eigenvalues
+// >= 1); ss_chunk_riccati then runs the per-sample filter of each chunk from
+// its start, writing the same gain records as the sequential kernel.
+//
+// Linear recursions. With the gains known, x_{n+1} = M_n x_n + B_n v_n
+// (M_n = Phi (I - k_n h^T)), the adjoint lambda_n = M_n^T lambda_{n+1} - ...
+// and G_n = h h^T / S_n + M_n^T G_{n+1} M_n are affine in their state: each
+// chunk runs from a zero state (its local part) and carries T_c = the
+// product of its M_n (the forward pass of the unit vectors); a short
+// sequential pass over chunks gives every chunk's true boundary state
+// (x_s' = x_local + T_c x_s, lambda_s = lambda_local + T_c^T lambda_e,
+// G_s = G_local + T_c^T G_e T_c); a final pass reruns each chunk from it.
+constexpr int SS_CL = 192;       // samples per chunk
+constexpr int SS_PAR_MAXJ = 6;   // largest state of the chunked path
+
+template <int J>
+struct Mat {
+  double m[J][J];
+};
+
+// M <- Phi M (the rows of each block)
+template <int NS, int NE>
+__device__ __forceinline__ void rows_phi(const double* c, Mat<2 * NS + NE>& M) {
+  constexpr int J = 2 * NS + NE;
+#pragma unroll
+  for (int s2 = 0; s2 < NS; ++s2)
+#pragma unroll
+    for (int b = 0; b < J; ++b) {
+      const double r0 = M.m[2 * s2][b], r1 = M.m[2 * s2 + 1][b];
+      M.m[2 * s2][b] = c[7 * s2] * r0 + c[7 * s2 + 1] * r1;
+      M.m[2 * s2 + 1][b] = c[7 * s2 + 2] * r0 + c[7 * s2 + 3] * r1;
+    }
+#pragma unroll
+  for (int e2 = 0; e2 < NE; ++e2)
+#pragma unroll
+    for (int b = 0; b < J; ++b) M.m[2 * NS + e2][b] *= c[7 * NS + 2 * e2];
+}
+
+// M <- Phi^T M
+template <int NS, int NE>
+__device__ __forceinline__ void rows_phi_t(const double* c, Mat<2 * NS + NE>& M) {
+  constexpr int J = 2 * NS + NE;
+#pragma unroll
+  for (int s2 = 0; s2 < NS; ++s2)
+#pragma unroll
+    for (int b = 0; b < J; ++b) {
+      const double r0 = M.m[2 * s2][b], r1 = M.m[2 * s2 + 1][b];
+      M.m[2 * s2][b] = c[7 * s2] * r0 + c[7 * s2 + 2] * r1;
+      M.m[2 * s2 + 1][b] = c[7 * s2 + 1] * r0 + c[7 * s2 + 3] * r1;
+    }
+#pragma unroll
+  for (int e2 = 0; e2 < NE; ++e2)
+#pragma unroll
+    for (int b = 0; b < J; ++b) M.m[2 * NS + e2][b] *= c[7 * NS + 2 * e2];
+}
+
+// M <- M Phi^T
+template <int NS, int NE>
+__device__ __forceinline__ void cols_phi_t(const double* c, Mat<2 * NS + NE>& M) {
+  constexpr int J = 2 * NS + NE;
+#pragma unroll
+  for (int a = 0; a < J; ++a) {
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) {
+      const double m0 = M.m[a][2 * s2], m1 = M.m[a][2 * s2 + 1];
+      M.m[a][2 * s2] = m0 * c[7 * s2] + m1 * c[7 * s2 + 1];
+      M.m[a][2 * s2 + 1] = m0 * c[7 * s2 + 2] + m1 * c[7 * s2 + 3];
+    }
+#pragma unroll
+    for (int e2 = 0; e2 < NE; ++e2) M.m[a][2 * NS + e2] *= c[7 * NS + 2 * e2];
+  }
+}
+
+// M <- M Phi
+template <int NS, int NE>
+__device__ __forceinline__ void cols_phi(const double* c, Mat<2 * NS + NE>& M) {
+  constexpr int J = 2 * NS + NE;
+#pragma unroll
+  for (int a = 0; a < J; ++a) {
+#pragma unroll
+    for (int s2 = 0; s2 < NS; ++s2) {
+      const double m0 = M.m[a][2 * s2], m1 = M.m[a][2 * s2 + 1];
+      M.m[a][2 * s2] = m0 * c[7 * s2] + m1 * c[7 * s2 + 2];
+      M.m[a][2 * s2 + 1] = m0 * c[7 * s2 + 1] + m1 * c[7 * s2 + 3];
+    }
+#pragma unroll
+    for (int e2 = 0; e2 < NE; ++e2) M.m[a][2 * NS + e2] *= c[7 * NS + 2 * e2];
+  }
+}
+
+// M += Qd on the block diagonal
+template <int NS, int NE>
+__device__ __forceinline__ void add_qd(const double* c, Mat<2 * NS + NE>& M) {
+#pragma unroll
+  for (int s2 = 0; s2 < NS; ++s2) {
+    M.m[2 * s2][2 * s2] += c[7 * s2 + 4];
+    M.m[2 * s2][2 * s2 + 1] += c[7 * s2 + 5];
+    M.m[2 * s2 + 1][2 * s2] += c[7 * s2 + 5];
+    M.m[2 * s2 + 1][2 * s2 + 1] += c[7 * s2 + 6];
+  }
+#pragma unroll
+  for (int e2 = 0; e2 < NE; ++e2) M.m[2 * NS + e2][2 * NS + e2] += c[7 * NS + 2 * e2 + 1];
+}
+
+template <int J>
+__device__ __forceinline__ void mat_load(const double* __restrict__ src, Mat<J>& M) {
+#pragma unroll
+  for (int a = 0; a < J; ++a)
+#pragma unroll
+    for (int b = 0; b < J; ++b) M.m[a][b] = src[a * J + b];
+}
+
+template <int J>
+__device__ __forceinline__ void mat_store(const Mat<J>& M, double* __restrict__ dst) {
+#pragma unroll
+  for (int a = 0; a < J; ++a)
+#pragma unroll
+    for (int b = 0; b < J; ++b) dst[a * J + b] = M.m[a][b];
+}
+
+// lower Cholesky factor in place (the upper triangle is left as it is)
+template <int J>
+__device__ __forceinline__ void chol_lower(Mat<J>& M) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    double d = M.m[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d = fma(-M.m[j][k], M.m[j][k], d);
+    d = sqrt(d);
+    M.m[j][j] = d;
+    const double rd = 1.0 / d;
+#pragma unroll
+    for (int i = j + 1; i < J; ++i) {
+      double v = M.m[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v = fma(-M.m[i][k], M.m[j][k], v);
+      M.m[i][j] = v * rd;
+    }
+  }
+}
+
+// One chunk's composed map (A, C, Jm), chunks 0 .. nch - 2 (the last one's is
+// never applied).
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_compose_kernel(const double* __restrict__ step, double rr, int nch,
+                                                        double* __restrict__ elems) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS;
+  const int c = blockIdx.x * 64 + threadIdx.x;
+  if (c >= nch - 1) return;
+  Mat<J> A, C, Jm;
+#pragma unroll
+  for (int a = 0; a < J; ++a)
+#pragma unroll
+    for (int b = 0; b < J; ++b) {
+      A.m[a][b] = a == b ? 1.0 : 0.0;
+      C.m[a][b] = 0.0;
+      Jm.m[a][b] = 0.0;
+    }
+  const int64_t s0 = (int64_t)c * SS_CL;
+  for (int64_t m = s0; m < s0 + SS_CL; ++m) {
+    const double* cs = step + m * TS;
+    double ch[J], ha[J];
+    double sv = rr;
+#pragma unroll
+    for (int a = 0; a < J; ++a) {
+      double v = 0.0, w = 0.0;
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        if (Lt::pos(b)) v += C.m[a][b];
+        if (Lt::pos(b)) w += A.m[b][a];
+      }
+      ch[a] = v;
+      ha[a] = w;
+    }
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+      if (Lt::pos(a)) sv += ch[a];
+    const double rs = 1.0 / sv;
+#pragma unroll
+    for (int a = 0; a < J; ++a) {
+      const double ca = ch[a] * rs, hr = ha[a] * rs;
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        A.m[a][b] = fma(-ca, ha[b], A.m[a][b]);
+        C.m[a][b] = fma(-ca, ch[b], C.m[a][b]);
+        Jm.m[a][b] = fma(hr, ha[b], Jm.m[a][b]);
+      }
+    }
+    rows_phi<NS, NE>(cs, A);
+    rows_phi<NS, NE>(cs, C);
+    cols_phi_t<NS, NE>(cs, C);
+    add_qd<NS, NE>(cs, C);
+  }
+  double* out = elems + (int64_t)c * 3 * J * J;
+  mat_store(A, out);
+  mat_store(C, out + J * J);
+  mat_store(Jm, out + 2 * J * J);
+}
+
+// Every chunk's starting covariance, applying the chunk maps in turn from
+// Pinf (one thread); also clears the failure marker.
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_carry_kernel(const double* __restrict__ elems, nu_kernel kp, int nch,
+                                                      int64_t n, double* __restrict__ pstart,
+                                                      unsigned long long* __restrict__ failmin) {
+  constexpr int J = 2 * NS + NE;
+  if (threadIdx.x != 0) return;
+  *failmin = (unsigned long long)n;
+  Mat<J> P;
+#pragma unroll
+  for (int a = 0; a < J; ++a)
+#pragma unroll
+    for (int b = 0; b < J; ++b) P.m[a][b] = 0.0;
+#pragma unroll
+  for (int s2 = 0; s2 < NS; ++s2) {
+    const double v0 = kp.sho_amp[s2] * kp.sho_amp[s2];
+    P.m[2 * s2][2 * s2] = v0;
+    P.m[2 * s2 + 1][2 * s2 + 1] = v0 * kp.sho_omega[s2] * kp.sho_omega[s2];
+  }
+#pragma unroll
+  for (int e2 = 0; e2 < NE; ++e2) P.m[2 * NS + e2][2 * NS + e2] = kp.exp_sigma[e2] * kp.exp_sigma[e2];
+  mat_store(P, pstart);
+  for (int c = 0; c + 1 < nch; ++c) {
+    const double* el = elems + (int64_t)c * 3 * J * J;
+    Mat<J> L = P;
+    chol_lower(L);  // P = L L^T
+    // Y = I + L^T Jm L, then its lower factor R
+    Mat<J> Jm, T, Y;
+    mat_load(el + 2 * J * J, Jm);
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < J; ++k) v = fma(Jm.m[a][k], (k >= b ? L.m[k][b] : 0.0), v);
+        T.m[a][b] = v;  // Jm L
+      }
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        double v = a == b ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < J; ++k) v = fma((k >= a ? L.m[k][a] : 0.0), T.m[k][b], v);
+        Y.m[a][b] = v;
+      }
+    chol_lower(Y);
+    // Z = L R^-T: row i of Z solves R z^T = (row i of L)^T
+    Mat<J> Z;
+#pragma unroll
+    for (int i = 0; i < J; ++i)
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        double v = j <= i ? L.m[i][j] : 0.0;
+#pragma unroll
+        for (int k = 0; k < j; ++k) v = fma(-Y.m[j][k], Z.m[i][k], v);
+        Z.m[i][j] = v / Y.m[j][j];
+      }
+    // P = (A Z)(A Z)^T + C
+    Mat<J> A, AZ;
+    mat_load(el, A);
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < J; ++k) v = fma(A.m[a][k], Z.m[k][b], v);
+        AZ.m[a][b] = v;
+      }
+    mat_load(el + J * J, P);
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        if (b < a) continue;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < J; ++k) v = fma(AZ.m[a][k], AZ.m[b][k], v);
+        const double cc = 0.5 * (P.m[a][b] + P.m[b][a]);
+        P.m[a][b] = v + cc;
+        P.m[b][a] = v + cc;
+      }
+    mat_store(P, pstart + (int64_t)(c + 1) * J * J);
+  }
+}
+
+// The per-sample filter of each chunk from its starting covariance.
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_chunk_riccati_kernel(const double* __restrict__ step,
+                                                              const double* __restrict__ pstart, int64_t n, int nch,
+                                                              double rr, double* __restrict__ gain,
+                                                              unsigned long long* __restrict__ failmin) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS, GS = Lt::GS;
+  const int c = blockIdx.x * 64 + threadIdx.x;
+  if (c >= nch) return;
+  Mat<J> P;
+  mat_load(pstart + (int64_t)c * J * J, P);
+  const int64_t s0 = (int64_t)c * SS_CL, s1 = min(n, s0 + SS_CL);
+  for (int64_t m = s0; m < s1; ++m) {
+    double ph[J];
+    double S = rr;
+#pragma unroll
+    for (int a = 0; a < J; ++a) {
+      double v = 0.0;
+#pragma unroll
+      for (int b = 0; b < J; ++b)
+        if (Lt::pos(b)) v += P.m[a][b];
+      ph[a] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+      if (Lt::pos(a)) S += ph[a];
+    if (!(S > 0.0 && S < INFINITY)) {
+      atomicMin(failmin, (unsigned long long)m);
+      return;
+    }
+    const double rsq = rsqrt_nr(S);
+    const double rS = rsq * rsq;
+    double* g = gain + m * GS;
+    g[0] = rsq;
+#pragma unroll
+    for (int a = 0; a < J; ++a) g[1 + a] = ph[a] * rS;
+    if (m + 1 == n) break;
+    const double* cs = step + m * TS;
+#pragma unroll
+    for (int a = 0; a < J; ++a) {
+      const double ka = ph[a] * rS;
+#pragma unroll
+      for (int b = 0; b < J; ++b) P.m[a][b] = fma(-ka, ph[b], P.m[a][b]);
+    }
+    rows_phi<NS, NE>(cs, P);
+    cols_phi_t<NS, NE>(cs, P);
+    add_qd<NS, NE>(cs, P);
+  }
+}
+
+// x <- Phi (x + k e) with e = v - h.x; returns e
+template <int NS, int NE>
+__device__ __forceinline__ double filter_step(const double* g, const double* cs, double v, double* x, bool last) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J;
+  double hx = 0.0;
+#pragma unroll
+  for (int b = 0; b < J; ++b)
+    if (Lt::pos(b)) hx += x[b];
+  const double ev = v - hx;
+  if (!last) {
+#pragma unroll
+    for (int b = 0; b < J; ++b) x[b] = fma(g[1 + b], ev, x[b]);
+    apply_phi<NS, NE>(cs, x);
+  }
+  return ev;
+}
+
+// Forward local pass: thread (chunk c < nch - 1, column col < nv + J). Data
+// columns start from 0 with v = V[., col]; column nv + j starts from the unit
+// vector e_j with v = 0 and ends as column j of T_c. xe[c][col] = the state
+// entering chunk c + 1.
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_fwd_local_kernel(const double* __restrict__ step,
+                                                          const double* __restrict__ gain, int64_t n,
+                                                          const double* __restrict__ V, int nv, int nch,
+                                                          double* __restrict__ xe) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS, GS = Lt::GS;
+  const int cw = nv + J;
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  const int c = t / cw, col = t - c * cw;
+  if (c >= nch - 1) return;
+  double x[J];
+#pragma unroll
+  for (int b = 0; b < J; ++b) x[b] = (col >= nv && b == col - nv) ? 1.0 : 0.0;
+  const int64_t s0 = (int64_t)c * SS_CL;
+  for (int64_t m = s0; m < s0 + SS_CL; ++m) {
+    const double v = col < nv ? V[m * YCOLS + col] : 0.0;
+    filter_step<NS, NE>(gain + m * GS, step + m * TS, v, x, false);
+  }
+  double* o = xe + ((int64_t)c * cw + col) * J;
+#pragma unroll
+  for (int b = 0; b < J; ++b) o[b] = x[b];
+}
+
+// Forward carry (one wave, lane = data column): xs[c] = the true state
+// entering chunk c.
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_fwd_carry_kernel(const double* __restrict__ xe, int nv, int nch,
+                                                          double* __restrict__ xs) {
+  constexpr int J = 2 * NS + NE;
+  const int col = threadIdx.x;
+  if (col >= nv) return;
+  const int cw = nv + J;
+  double x[J];
+#pragma unroll
+  for (int b = 0; b < J; ++b) x[b] = 0.0;
+  for (int c = 0; c < nch; ++c) {
+    double* o = xs + ((int64_t)c * YCOLS + col) * J;
+#pragma unroll
+    for (int b = 0; b < J; ++b) o[b] = x[b];
+    if (c + 1 == nch) break;
+    const double* e = xe + (int64_t)c * cw * J;
+    double y[J];
+#pragma unroll
+    for (int a = 0; a < J; ++a) {
+      double v = e[col * J + a];
+#pragma unroll
+      for (int j = 0; j < J; ++j) v = fma(e[(nv + j) * J + a], x[j], v);
+      y[a] = v;
+    }
+#pragma unroll
+    for (int b = 0; b < J; ++b) x[b] = y[b];
+  }
+}
+
+// Forward final pass: thread (chunk, data column) from the true entering
+// state, writing Y = L^-1 V.
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_fwd_final_kernel(const double* __restrict__ step,
+                                                          const double* __restrict__ gain, int64_t n,
+                                                          const double* __restrict__ V, int nv, int nch,
+                                                          const double* __restrict__ xs, double* __restrict__ Y) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS, GS = Lt::GS;
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  const int c = t / nv, col = t - c * nv;
+  if (c >= nch) return;
+  double x[J];
+  const double* xi = xs + ((int64_t)c * YCOLS + col) * J;
+#pragma unroll
+  for (int b = 0; b < J; ++b) x[b] = xi[b];
+  const int64_t s0 = (int64_t)c * SS_CL, s1 = min(n, s0 + SS_CL);
+  for (int64_t m = s0; m < s1; ++m) {
+    const double* g = gain + m * GS;
+    const double ev = filter_step<NS, NE>(g, step + m * TS, V[m * YCOLS + col], x, m + 1 == n);
+    Y[m * YCOLS + col] = ev * g[0];
+  }
+}
+
+// One backward step of the adjoint: returns u_m, updates lambda.
+template <int NS, int NE>
+__device__ __forceinline__ double adjoint_step(const double* g, const double* cs, double w, double* lam, bool last) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J;
+  if (last) {
+#pragma unroll
+    for (int b = 0; b < J; ++b) lam[b] = 0.0;
+  } else {
+    apply_phi_t<NS, NE>(cs, lam);
+  }
+  double u = w * g[0];
+#pragma unroll
+  for (int b = 0; b < J; ++b) u = fma(g[1 + b], lam[b], u);
+#pragma unroll
+  for (int b = 0; b < J; ++b)
+    if (Lt::pos(b)) lam[b] -= u;
+  return u;
+}
+
+// G_m from G_{m+1}: h h^T / S_m + M_m^T G M_m, M_m = Phi (I - k_m h^T)
+template <int NS, int NE>
+__device__ __forceinline__ void gtail_step(const double* g, const double* cs, Mat<2 * NS + NE>& G, bool last) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J;
+  if (last) {
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int b = 0; b < J; ++b) G.m[a][b] = 0.0;
+  } else {
+    rows_phi_t<NS, NE>(cs, G);
+    cols_phi<NS, NE>(cs, G);
+  }
+  double wk[J];
+#pragma unroll
+  for (int a = 0; a < J; ++a) {
+    double v = 0.0;
+#pragma unroll
+    for (int b = 0; b < J; ++b) v = fma(G.m[a][b], g[1 + b], v);
+    wk[a] = v;
+  }
+  double kwk = 0.0;
+#pragma unroll
+  for (int a = 0; a < J; ++a) kwk = fma(g[1 + a], wk[a], kwk);
+  const double corner = kwk + g[0] * g[0];
+#pragma unroll
+  for (int a = 0; a < J; ++a)
+#pragma unroll
+    for (int b = 0; b < J; ++b) {
+      double v = G.m[a][b];
+      if (Lt::pos(a)) v -= wk[b];
+      if (Lt::pos(b)) v -= wk[a];
+      if (Lt::pos(a) && Lt::pos(b)) v += corner;
+      G.m[a][b] = v;
+    }
+}
+
+// Backward local pass: thread (chunk 1 <= c < nch, role). Roles < nv: the
+// adjoint of column role from lambda = 0 after the chunk, giving
+// ls[c][role] = the local lambda at the chunk's first sample; role nv: G from
+// 0 after the chunk, giving Gl[c].
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_bwd_local_kernel(const double* __restrict__ step,
+                                                          const double* __restrict__ gain, int64_t n,
+                                                          const double* __restrict__ W, int nv, int nch,
+                                                          double* __restrict__ ls, double* __restrict__ Gl) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS, GS = Lt::GS;
+  const int rw = nv + 1;
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  const int c = 1 + t / rw, role = t - (c - 1) * rw;
+  if (c >= nch) return;
+  const int64_t s0 = (int64_t)c * SS_CL, s1 = min(n, s0 + SS_CL);
+  if (role < nv) {
+    double lam[J];
+#pragma unroll
+    for (int b = 0; b < J; ++b) lam[b] = 0.0;
+    for (int64_t m = s1 - 1; m >= s0; --m) {
+      const bool last = m + 1 == n;
+      adjoint_step<NS, NE>(gain + m * GS, step + (last ? 0 : m) * TS, W[m * YCOLS + role], lam, last);
+    }
+    double* o = ls + ((int64_t)c * YCOLS + role) * J;
+#pragma unroll
+    for (int b = 0; b < J; ++b) o[b] = lam[b];
+  } else {
+    Mat<J> G;
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int b = 0; b < J; ++b) G.m[a][b] = 0.0;
+    for (int64_t m = s1 - 1; m >= s0; --m) {
+      const bool last = m + 1 == n;
+      gtail_step<NS, NE>(gain + m * GS, step + (last ? 0 : m) * TS, G, last);
+    }
+    mat_store(G, Gl + (int64_t)c * J * J);
+  }
+}
+
+// Backward carry, from the last chunk down. Workgroup 0, lane = column:
+// le[c][col] = the true lambda entering chunk c from after its end. Workgroup
+// 1, one thread: ge[c] = the true G after chunk c's end. T_c (columns
+// xe[c][nv + j]) is the forward transfer of chunk c.
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_bwd_carry_kernel(const double* __restrict__ xe,
+                                                          const double* __restrict__ ls,
+                                                          const double* __restrict__ Gl, int nv, int nch,
+                                                          double* __restrict__ le, double* __restrict__ ge) {
+  constexpr int J = 2 * NS + NE;
+  const int cw = nv + J;
+  if (blockIdx.x == 0) {
+    const int col = threadIdx.x;
+    if (col >= nv) return;
+    double lam[J];
+#pragma unroll
+    for (int b = 0; b < J; ++b) lam[b] = 0.0;
+    for (int c = nch - 1; c >= 0; --c) {
+      double* o = le + ((int64_t)c * YCOLS + col) * J;
+#pragma unroll
+      for (int b = 0; b < J; ++b) o[b] = lam[b];
+      if (c == 0) break;
+      // lambda at chunk c's first sample = local + T_c^T lambda_after (the
+      // last chunk has nothing after it and no T)
+      const double* e = xe + (int64_t)c * cw * J;
+      const double* l0 = ls + ((int64_t)c * YCOLS + col) * J;
+      const bool tail = c + 1 < nch;
+      double y[J];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        double v = l0[j];
+        if (tail) {
+#pragma unroll
+          for (int a = 0; a < J; ++a) v = fma(e[(nv + j) * J + a], lam[a], v);
+        }
+        y[j] = v;
+      }
+#pragma unroll
+      for (int b = 0; b < J; ++b) lam[b] = y[b];
+    }
+    return;
+  }
+  if (threadIdx.x != 0) return;
+  Mat<J> G;
+#pragma unroll
+  for (int a = 0; a < J; ++a)
+#pragma unroll
+    for (int b = 0; b < J; ++b) G.m[a][b] = 0.0;
+  for (int c = nch - 1; c >= 0; --c) {
+    mat_store(G, ge + (int64_t)c * J * J);
+    if (c == 0) break;
+    if (c + 1 == nch) {  // nothing after the last chunk: G at its start is its local part
+      mat_load(Gl + (int64_t)c * J * J, G);
+      continue;
+    }
+    const double* e = xe + (int64_t)c * cw * J;
+    Mat<J> T, GT;
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int j = 0; j < J; ++j) T.m[a][j] = e[(nv + j) * J + a];
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < J; ++k) v = fma(G.m[a][k], T.m[k][b], v);
+        GT.m[a][b] = v;
+      }
+    const double* gl = Gl + (int64_t)c * J * J;
+#pragma unroll
+    for (int a = 0; a < J; ++a)
+#pragma unroll
+      for (int b = 0; b < J; ++b) {
+        if (b < a) continue;
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < J; ++k) v = fma(T.m[k][a], GT.m[k][b], v);
+        const double cc = 0.5 * (gl[a * J + b] + gl[b * J + a]);
+        G.m[a][b] = v + cc;
+        G.m[b][a] = v + cc;
+      }
+  }
+}
+
+// Backward final pass: thread (chunk, role) from the true state after the
+// chunk: the adjoint columns write Z, the G thread writes Gm (and G_n = 0).
+template <int NS, int NE>
+__global__ __launch_bounds__(64) void ss_bwd_final_kernel(const double* __restrict__ step,
+                                                          const double* __restrict__ gain, int64_t n,
+                                                          const double* __restrict__ W, int nv, int nch,
+                                                          const double* __restrict__ le,
+                                                          const double* __restrict__ ge, double* __restrict__ Z,
+                                                          double* __restrict__ Gm) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J, TS = Lt::TS, GS = Lt::GS;
+  const int rw = nv + 1;
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  const int c = t / rw, role = t - c * rw;
+  if (c >= nch) return;
+  const int64_t s0 = (int64_t)c * SS_CL, s1 = min(n, s0 + SS_CL);
+  if (role < nv) {
+    double lam[J];
+    const double* li = le + ((int64_t)c * YCOLS + role) * J;
+#pragma unroll
+    for (int b = 0; b < J; ++b) lam[b] = li[b];
+    for (int64_t m = s1 - 1; m >= s0; --m) {
+      const bool last = m + 1 == n;
+      Z[m * YCOLS + role] = adjoint_step<NS, NE>(gain + m * GS, step + (last ? 0 : m) * TS, W[m * YCOLS + role],
+                                                 lam, last);
+    }
+  } else {
+    Mat<J> G;
+    mat_load(ge + (int64_t)c * J * J, G);
+    if (s1 == n) mat_store(G, Gm + n * J * J);
+    for (int64_t m = s1 - 1; m >= s0; --m) {
+      const bool last = m + 1 == n;
+      gtail_step<NS, NE>(gain + m * GS, step + (last ? 0 : m) * TS, G, last);
+      mat_store(G, Gm + m * J * J);
+    }
+  }
+}
+
+// chunk buffers inside A.chunk (doubles), for nch chunks
+struct ChunkWs {
+  double *elems, *pstart, *xe, *xs, *ls, *le, *Gl, *ge;
+  unsigned long long* failmin;
+};
+
+inline ChunkWs chunk_layout(double* base, int nch, int J) {
+  ChunkWs w;
+  const int64_t jj = (int64_t)J * J;
+  double* p = base;
+  w.elems = p;  p += (int64_t)nch * 3 * jj;
+  w.pstart = p; p += (int64_t)nch * jj;
+  w.xe = p;     p += (int64_t)nch * (YCOLS + J) * J;
+  w.xs = p;     p += (int64_t)nch * YCOLS * J;
+  w.ls = p;     p += (int64_t)nch * YCOLS * J;
+  w.le = p;     p += (int64_t)nch * YCOLS * J;
+  w.Gl = p;     p += (int64_t)nch * jj;
+  w.ge = p;     p += (int64_t)nch * jj;
+  w.failmin = reinterpret_cast<unsigned long long*>(p);
+  return w;
+}
+
+template <int NS, int NE>
+hipError_t launch_ss_chunked(int phase, hipStream_t s, const SsArgs& A) {
+  using Lt = SsLayout<NS, NE>;
+  constexpr int J = Lt::J;
+  const int nch = (int)((A.n + SS_CL - 1) / SS_CL);
+  const ChunkWs w = chunk_layout(A.chunk, nch, J);
+  const double rr = A.kernel.sigma_w * A.kernel.sigma_w;
+  auto blocks = [](int64_t threads) { return dim3((unsigned)((threads + 63) / 64)); };
+  switch (phase) {
+    case SS_PAR_RICCATI:
+      if (nch > 1) {
+        hipLaunchKernelGGL((ss_compose_kernel<NS, NE>), blocks(nch - 1), dim3(64), 0, s, A.step, rr, nch, w.elems);
+        if (hipPeekAtLastError() != hipSuccess) break;
+      }
+      hipLaunchKernelGGL((ss_carry_kernel<NS, NE>), dim3(1), dim3(64), 0, s, w.elems, A.kernel, nch, A.n, w.pstart,
+                         w.failmin);
+      if (hipPeekAtLastError() != hipSuccess) break;
+      hipLaunchKernelGGL((ss_chunk_riccati_kernel<NS, NE>), blocks(nch), dim3(64), 0, s, A.step, w.pstart, A.n, nch,
+                         rr, A.gain, w.failmin);
+      if (hipPeekAtLastError() != hipSuccess) break;
+      hipLaunchKernelGGL(ss_logdet_kernel, dim3(1), dim3(256), 0, s, A.gain, Lt::GS, A.n,
+                         (const unsigned long long*)w.failmin, A.status, A.logdet);
+      break;
+    case SS_PAR_FORWARD:
+      if (nch > 1) {
+        hipLaunchKernelGGL((ss_fwd_local_kernel<NS, NE>), blocks((int64_t)(nch - 1) * (A.nv + J)), dim3(64), 0, s,
+                           A.step, A.gain, A.n, A.V, A.nv, nch, w.xe);
+        if (hipPeekAtLastError() != hipSuccess) break;
+      }
+      hipLaunchKernelGGL((ss_fwd_carry_kernel<NS, NE>), dim3(1), dim3(64), 0, s, w.xe, A.nv, nch, w.xs);
+      if (hipPeekAtLastError() != hipSuccess) break;
+      hipLaunchKernelGGL((ss_fwd_final_kernel<NS, NE>), blocks((int64_t)nch * A.nv), dim3(64), 0, s, A.step, A.gain,
+                         A.n, A.V, A.nv, nch, w.xs, A.Y);
+      break;
+    case SS_PAR_BACKWARD:
+      if (nch > 1) {
+        hipLaunchKernelGGL((ss_bwd_local_kernel<NS, NE>), blocks((int64_t)(nch - 1) * (A.nv + 1)), dim3(64), 0, s,
+                           A.step, A.gain, A.n, A.Y, A.nv, nch, w.ls, w.Gl);
+        if (hipPeekAtLastError() != hipSuccess) break;
+      }
+      hipLaunchKernelGGL((ss_bwd_carry_kernel<NS, NE>), dim3(2), dim3(64), 0, s, w.xe, w.ls, w.Gl, A.nv, nch, w.le,
+                         w.ge);
+      if (hipPeekAtLastError() != hipSuccess) break;
+      hipLaunchKernelGGL((ss_bwd_final_kernel<NS, NE>), blocks((int64_t)nch * (A.nv + 1)), dim3(64), 0, s, A.step,
+                         A.gain, A.n, A.Y, A.nv, nch, w.le, w.ge, A.Z, A.Gm);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int NS, int NE>
 hipError_t launch_ss_typed(int phase, hipStream_t s, const SsArgs& A) {
   switch (phase) {
@@ -628,8 +1392,8 @@ hipError_t launch_ss_typed(int phase, hipStream_t s, const SsArgs& A) {
       hipLaunchKernelGGL((ss_riccati_kernel<NS, NE>), dim3(1), dim3(64), 0, s, A.step, A.kernel, A.n, A.gain,
                          A.status);
       if (hipPeekAtLastError() != hipSuccess) break;
-      hipLaunchKernelGGL(ss_logdet_kernel, dim3(1), dim3(256), 0, s, A.gain, SsLayout<NS, NE>::GS, A.n, A.status,
-                         A.logdet);
+      hipLaunchKernelGGL(ss_logdet_kernel, dim3(1), dim3(256), 0, s, A.gain, SsLayout<NS, NE>::GS, A.n,
+                         (const unsigned long long*)nullptr, A.status, A.logdet);
       break;
     case SS_FORWARD:
       hipLaunchKernelGGL((ss_forward_kernel<NS, NE>), dim3(1), dim3(64), 0, s, A.step, A.gain, A.n, A.V, A.nv, A.Y);
@@ -668,6 +1432,11 @@ hipError_t launch_ss_typed(int phase, hipStream_t s, const SsArgs& A) {
                          A.shapes, A.qbox);
       break;
     }
+    case SS_PAR_RICCATI:
+    case SS_PAR_FORWARD:
+    case SS_PAR_BACKWARD:
+      if constexpr (2 * NS + NE <= SS_PAR_MAXJ) return launch_ss_chunked<NS, NE>(phase, s, A);
+      return hipErrorInvalidValue;
     default:
       return hipErrorInvalidValue;
   }
@@ -695,6 +1464,21 @@ hipError_t launch_ss_step(hipStream_t s, const double* t, int64_t n, const nu_ke
   const int ts = 7 * k.n_sho + 2 * k.n_exp;
   hipLaunchKernelGGL(ss_step_kernel, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s, t, n, k, ts, step);
   return hipGetLastError();
+}
+
+size_t ss_chunk_ws_doubles(int64_t n, int J) {
+  const int64_t nch = (n + SS_CL - 1) / SS_CL;
+  const int64_t jj = (int64_t)J * J;
+  return (size_t)(nch * (3 * jj + jj + (YCOLS + J) * J + 3 * YCOLS * J + 2 * jj) + 1);
+}
+
+bool ss_chunked_applies(const nu_kernel& k) {
+  if (2 * k.n_sho + k.n_exp > SS_PAR_MAXJ || !(k.sigma_w > 0.0)) return false;
+  for (int i = 0; i < k.n_sho; ++i)
+    if (!(k.sho_amp[i] > 0.0)) return false;
+  for (int i = 0; i < k.n_exp; ++i)
+    if (!(k.exp_sigma[i] > 0.0)) return false;
+  return true;
 }
 
 hipError_t launch_ss(int phase, hipStream_t s, const SsArgs& A) {

@@ -230,3 +230,33 @@ def test_nuance_object_statespace_solver(api):
     assert ra.best[0] == rb.best[0]
     with pytest.raises(ValueError):
         api.Nuance(w.t, w.f, gp=api.SHO.from_dict(w.theta), solver="banded")
+
+
+def test_chunked_and_sequential_filters_agree(api, ctx):
+    """The chunked (parallel-in-time) filter runs for kernels of at most 6 states with white noise and
+    positive term variances, the one-wave sequential filter otherwise. An extra SHO term of zero amplitude
+    leaves K unchanged but sends the search down the sequential path: both must give the same cells."""
+    import torch
+    w = config2()
+    k = api.rotation_kernel(**ROT)
+    k_seq = api.Kernel(sho=list(k.sho) + [(0.0, 5.0, 2.0)], exp=list(k.exp), sigma_w=k.sigma_w)
+    say(f"chunked against sequential filter at N={w.n}")
+    a = _host(api.linear_search_ss(ctx, w.t, k, w.f, w.A, w.lattice, w.n_epochs, w.durations))
+    b_ls = api.linear_search_ss(ctx, w.t, k_seq, w.f, w.A, w.lattice, w.n_epochs, w.durations)
+    b = _host(b_ls)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a["valid"], b["valid"])
+    v = a["valid"].astype(bool)
+    e = float(np.max(np.abs(a["dll"][v] - b["dll"][v]) / np.maximum(np.abs(b["dll"][v]), 1.0)))
+    say(f"chunked vs sequential max dll error {e}")
+    assert e <= 1e-10
+
+
+def test_no_white_noise_sequential_path(api, ctx):
+    """sigma_w = 0 (the chunked filter needs white noise): an exponential kernel is still positive definite."""
+    terms = {"sho": [], "exp": [(0.006, 0.1), (0.002, 0.02)]}
+    w = _curve(500, 73, (240, 11))
+    k = api.Kernel(exp=list(terms["exp"]), sigma_w=0.0)
+    say("state-space exponential kernel without white noise")
+    ls, ref = _run(api, ctx, w, k, terms, 0.0)
+    _close(_host(ls), ref, "ss no white noise")
