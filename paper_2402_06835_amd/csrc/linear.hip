@@ -537,20 +537,22 @@ hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks,
 // q of template cells: q = sum_r (sum_m X[r][m] b_m)^2 with b the shape of the
 // cell on its window. As in q_partial, a wave owns 64 consecutive epoch slots
 // and one chunk of rows; here a row is laid out by lattice slot in the wave's
-// LDS row (zeros on slots without a sample), so a cell's window is a
-// contiguous run of it and the shape value at window offset k is the same for
-// every lane: each lane takes, per duration, the dot product of its window
-// with the shape (staged once per workgroup in LDS). The span of slots a
-// wave's windows cover is 64 + dmax; RUN slots per lane.
-template <int RUN>
+// LDS rows (zeros on slots without a sample), so every window is a contiguous
+// run of it, and the shape value at a window offset is the same for every
+// lane (a broadcast read of the shapes, staged once per workgroup in LDS).
+// RR rows go per pass, so each shape value read serves RR rows; the window
+// loop runs four offsets at a time so neighbouring row reads pair up. The span
+// of slots a wave's windows cover is 64 + dmax; RUN slots per lane.
+template <int RUN, int RR>
 __global__ __launch_bounds__(256) void q_template_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
                                                          const int64_t* __restrict__ lattice,
                                                          const int32_t* __restrict__ T, int64_t n_epochs, DurList dl,
                                                          const double* __restrict__ shapes, int shape_total,
-                                                         int half_max, int rowchunk, double* __restrict__ qpart) {
+                                                         int half_max, int dmax, int rowchunk,
+                                                         double* __restrict__ qpart) {
   constexpr int SPAN = 64 * RUN;
   __shared__ double sh[MAX_SHAPE];
-  __shared__ double row[4][SPAN];
+  __shared__ double rows[4][RR][SPAN];
   for (int t = threadIdx.x; t < shape_total; t += 256) sh[t] = shapes[t];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -578,29 +580,56 @@ __global__ __launch_bounds__(256) void q_template_kernel(const double* __restric
     my_lo = min(my_lo, (int64_t)__shfl_xor(my_lo, off, 64));
     my_hi = max(my_hi, (int64_t)__shfl_xor(my_hi, off, 64));
   }
-  double* P = row[wave];
+  // duration k's window covers offsets [wlo[k], wlo[k] + d_k) from the lane's base position
+  int wlo[MAX_ND];
+#pragma unroll
+  for (int k = 0; k < MAX_ND; ++k) wlo[k] = k < dl.n ? half_max - dl.d[k] / 2 : 0;
   double q[MAX_ND];
 #pragma unroll
   for (int k = 0; k < MAX_ND; ++k) q[k] = 0.0;
   const int64_t r0 = max((int64_t)chunk * rowchunk, my_lo);
   const int64_t r1 = min(n, (int64_t)chunk * rowchunk + rowchunk);
   if (my_hi > my_lo) {
-    for (int64_t r = r0; r < r1; ++r) {
-      const double* x = X + r * ldx;
+    for (int64_t r = r0; r < r1; r += RR) {
 #pragma unroll
-      for (int e = 0; e < RUN; ++e) {
-        const int64_t m = msamp[e];
-        P[lane * RUN + e] = (m >= 0 && m <= r) ? x[m] : 0.0;
+      for (int rr = 0; rr < RR; ++rr) {
+        const int64_t row = r + rr;
+        const double* x = X + row * ldx;
+#pragma unroll
+        for (int e = 0; e < RUN; ++e) {
+          const int64_t m = msamp[e];
+          rows[wave][rr][lane * RUN + e] = (row < r1 && m >= 0 && m <= row) ? x[m] : 0.0;
+        }
       }
       wave_lds_fence();
       if (active) {
-        for (int k = 0; k < dl.n; ++k) {
-          const int d = dl.d[k];
-          const double* shp = sh + dl.off[k];
-          const double* win = P + (slot - d / 2 - base);
-          double acc = 0.0;
-          for (int kk = 0; kk < d; ++kk) acc = fma(shp[kk], win[kk], acc);
-          q[k] = fma(acc, acc, q[k]);
+#pragma unroll
+        for (int k = 0; k < MAX_ND; ++k) {
+          if (k < dl.n) {
+            const double* shp = sh + dl.off[k];
+            const int d = dl.d[k];
+            const int p0 = lane + wlo[k];
+            double acc[RR];
+#pragma unroll
+            for (int rr = 0; rr < RR; ++rr) acc[rr] = 0.0;
+            int i = 0;
+            for (; i + 4 <= d; i += 4) {
+              double w[4];
+#pragma unroll
+              for (int t = 0; t < 4; ++t) w[t] = shp[i + t];
+#pragma unroll
+              for (int rr = 0; rr < RR; ++rr)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[rr] = fma(w[t], rows[wave][rr][p0 + i + t], acc[rr]);
+            }
+            for (; i < d; ++i) {
+              const double w = shp[i];
+#pragma unroll
+              for (int rr = 0; rr < RR; ++rr) acc[rr] = fma(w, rows[wave][rr][p0 + i], acc[rr]);
+            }
+#pragma unroll
+            for (int rr = 0; rr < RR; ++rr) q[k] = fma(acc[rr], acc[rr], q[k]);
+          }
         }
       }
       wave_lds_fence();
@@ -632,11 +661,15 @@ hipError_t launch_q_template(hipStream_t s, const double* X, int64_t ldx, int64_
   const int span = 64 + dmax;
   const int half = dmax / 2;
   const dim3 g((unsigned)((n_epochs + QCH - 1) / QCH), (unsigned)nchunks), b(256);
-  if (span <= 64 * 2) hipLaunchKernelGGL(q_template_kernel<2>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart);
-  else if (span <= 64 * 3) hipLaunchKernelGGL(q_template_kernel<3>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart);
-  else if (span <= 64 * 5) hipLaunchKernelGGL(q_template_kernel<5>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart);
-  else if (span <= 64 * 9) hipLaunchKernelGGL(q_template_kernel<9>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart);
-  else if (span <= 64 * 17) hipLaunchKernelGGL(q_template_kernel<17>, g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart);
+#define NU_QT(RUN, RR)                                                                                            \
+  hipLaunchKernelGGL((q_template_kernel<RUN, RR>), g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, \
+                     half, dmax, rowchunk, qpart)
+  if (span <= 64 * 2) NU_QT(2, 4);
+  else if (span <= 64 * 3) NU_QT(3, 4);
+  else if (span <= 64 * 5) NU_QT(5, 4);
+  else if (span <= 64 * 9) NU_QT(9, 2);
+  else if (span <= 64 * 17) NU_QT(17, 1);
+#undef NU_QT
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
