@@ -45,6 +45,15 @@ def _run(cmd):
     return out
 
 
+# sources whose matrix-core loops keep their accumulators in ordinary VGPRs
+# (without this the compiler copies every accumulator through AGPRs on each
+# step of the template q loop)
+EXTRA_FLAGS = {
+    "linear.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "factor.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
@@ -52,7 +61,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        out = _run([hipcc, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
+        out = _run([hipcc, *FLAGS, *EXTRA_FLAGS.get(src, []), *lang, "-c", os.path.join(CSRC, src), "-o", obj])
         if verbose and out.strip():
             print(out)
         return obj

@@ -640,6 +640,135 @@ __global__ __launch_bounds__(256) void q_template_kernel(const double* __restric
   }
 }
 
+// The same sums on the matrix cores, for windows up to 256 slots. One wave
+// per workgroup owns 64 slots (four 16-slot tiles) and takes 16 rows per pass:
+// for duration k, C[r][l] = sum_m A[r][m] B[m][l] with A the rows laid out by
+// slot (m counted from the tile's first window position) and B the banded
+// Toeplitz matrix B[m][l] = s_k[m - l] (0 outside the shape), so each
+// v_mfma_f64_16x16x4f64 step takes 4 offsets m for 16 rows x 16 slots. The B
+// fragment depends on m - l only, so one read of the shape serves all four
+// tiles; the squares of C summed over the rows give q.
+typedef double qdbl4 __attribute__((ext_vector_type(4)));
+constexpr int QT_ROWS = 16;
+constexpr int QT_SH0 = 16;  // zeros before a staged shape: m - lr >= -15
+constexpr int QT_SH1 = 24;  // zeros after it: m - lr < d + 18
+constexpr int QT_PAD = 9;  // zeros after a row (the last MFMA step may reach past the span); odd, so the 16 rows of a read fall in distinct banks
+
+template <int RUN>
+__global__ __launch_bounds__(64) void q_template_mfma_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
+                                                             const int64_t* __restrict__ lattice,
+                                                             const int32_t* __restrict__ T, int64_t n_epochs,
+                                                             DurList dl, const double* __restrict__ shapes,
+                                                             int shape_total, int half_max, int rowchunk,
+                                                             double* __restrict__ qpart) {
+  constexpr int SPAN = 64 * RUN;
+  constexpr int LDR = SPAN + QT_PAD;
+  // shapes with QT_SH0 zeros before and QT_SH1 after each, so that the B
+  // fragment is one unconditional read (no branch splits the MFMA loop)
+  __shared__ double sh[MAX_SHAPE + (QT_SH0 + QT_SH1) * MAX_ND];
+  __shared__ double rows[QT_ROWS][LDR];
+  const int lane = threadIdx.x;
+  const int padded = shape_total + (QT_SH0 + QT_SH1) * dl.n;
+  for (int t = lane; t < padded; t += 64) sh[t] = 0.0;
+  for (int t = lane; t < QT_ROWS * QT_PAD; t += 64) rows[t / QT_PAD][SPAN + t % QT_PAD] = 0.0;
+  __syncthreads();
+  for (int k = 0; k < dl.n; ++k) {
+    const int po = dl.off[k] + (QT_SH0 + QT_SH1) * dl.perm[k] + QT_SH0;
+    for (int t = lane; t < dl.d[k]; t += 64) sh[po + t] = shapes[dl.off[k] + t];
+  }
+  const int lr = lane & 15, lk = lane >> 4;
+  const int64_t s0 = (int64_t)blockIdx.x * 64;  // first slot of the wave
+  const int64_t slot = s0 + lane;
+  const int chunk = blockIdx.y;
+  const bool active = slot < n_epochs;
+  const int64_t base = s0 - half_max;  // slot of row position 0
+  int64_t msamp[RUN];
+  int64_t my_lo = INT64_MAX, my_hi = INT64_MIN;
+#pragma unroll
+  for (int e = 0; e < RUN; ++e) {
+    const int64_t sl = base + lane * RUN + e;
+    const int64_t m = count_below(lattice, n, T, n_epochs, sl);
+    const bool present = m < n && lattice[m] == sl;
+    msamp[e] = present ? m : -1;
+    if (present) {
+      my_lo = min(my_lo, m);
+      my_hi = max(my_hi, m + 1);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    my_lo = min(my_lo, (int64_t)__shfl_xor(my_lo, off, 64));
+    my_hi = max(my_hi, (int64_t)__shfl_xor(my_hi, off, 64));
+  }
+  double q[MAX_ND];
+#pragma unroll
+  for (int k = 0; k < MAX_ND; ++k) q[k] = 0.0;
+  const int64_t r0 = max((int64_t)chunk * rowchunk, my_lo);
+  const int64_t r1 = min(n, (int64_t)chunk * rowchunk + rowchunk);
+  __syncthreads();
+  if (my_hi > my_lo) {
+    for (int64_t r = r0; r < r1; r += QT_ROWS) {
+#pragma unroll
+      for (int rr = 0; rr < QT_ROWS; ++rr) {
+        const int64_t row = r + rr;
+        const double* x = X + row * ldx;
+#pragma unroll
+        for (int e = 0; e < RUN; ++e) {
+          const int64_t m = msamp[e];
+          rows[rr][lane * RUN + e] = (row < r1 && m >= 0 && m <= row) ? x[m] : 0.0;
+        }
+      }
+      wave_lds_fence();
+#pragma unroll
+      for (int k = 0; k < MAX_ND; ++k) {
+        if (k < dl.n) {
+          const int d = dl.d[k];
+          // B fragment of step st: shape value at m - lr = 4 st + lk - lr, zero outside [0, d)
+          const double* shb = sh + dl.off[k] + (QT_SH0 + QT_SH1) * dl.perm[k] + QT_SH0 + lk - lr;
+          const int w0 = half_max - d / 2;  // window start of tile slot 0, in row positions
+          const double* ar = &rows[lr][w0 + lk];
+          const int steps = (QT_ROWS - 1 + d + 3) / 4;
+          qdbl4 acc[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[t] = qdbl4{0.0, 0.0, 0.0, 0.0};
+          // operands of step st + 1 are read while step st's products run (the
+          // padding keeps the read past the last step inside the arrays)
+          double bv = shb[0], av[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) av[t] = ar[16 * t];
+          for (int st = 0; st < steps; ++st) {
+            const double bn = shb[4 * st + 4];
+            double an[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) an[t] = ar[16 * t + 4 * st + 4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv, acc[t], 0, 0, 0);
+            bv = bn;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) av[t] = an[t];
+          }
+          // column lr of tile t: rows lk + 4v; sum the squares over the 16 rows
+          double mine = 0.0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s2 = fma(acc[t][v], acc[t][v], s2);
+            s2 += __shfl_xor(s2, 16, 64);
+            s2 += __shfl_xor(s2, 32, 64);
+            if (t == lk) mine = s2;  // lane 16 t + lr is slot 16 t + lr
+          }
+          q[k] += mine;
+        }
+      }
+      wave_lds_fence();
+    }
+  }
+  if (active) {
+    for (int k = 0; k < dl.n; ++k) qpart[((int64_t)chunk * dl.n + dl.perm[k]) * n_epochs + slot] = q[k];
+  }
+}
+
 hipError_t launch_q_template(hipStream_t s, const double* X, int64_t ldx, int64_t n, const int64_t* lattice,
                              const int32_t* T, int64_t n_epochs, const int32_t* dur_sorted, const int32_t* dur,
                              int n_d, const double* shapes, int dmax, int rowchunk, int nchunks, double* qpart) {
@@ -664,12 +793,16 @@ hipError_t launch_q_template(hipStream_t s, const double* X, int64_t ldx, int64_
 #define NU_QT(RUN, RR)                                                                                            \
   hipLaunchKernelGGL((q_template_kernel<RUN, RR>), g, b, 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, \
                      half, dmax, rowchunk, qpart)
-  if (span <= 64 * 2) NU_QT(2, 4);
-  else if (span <= 64 * 3) NU_QT(3, 4);
-  else if (span <= 64 * 5) NU_QT(5, 4);
+#define NU_QTM(RUN)                                                                                               \
+  hipLaunchKernelGGL((q_template_mfma_kernel<RUN>), dim3((unsigned)((n_epochs + 63) / 64), (unsigned)nchunks),       \
+                     dim3(64), 0, s, X, ldx, n, lattice, T, n_epochs, dl, shapes, total, half, rowchunk, qpart)
+  if (span <= 64 * 2) NU_QTM(2);
+  else if (span <= 64 * 3) NU_QTM(3);
+  else if (span <= 64 * 5) NU_QTM(5);
   else if (span <= 64 * 9) NU_QT(9, 2);
   else if (span <= 64 * 17) NU_QT(17, 1);
 #undef NU_QT
+#undef NU_QTM
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
