@@ -22,7 +22,11 @@ Readings (the paper is silent on these):
   positive depth; the epoch grid is every lattice slot from the first to
   the last sample (the time array itself when there are no gaps);
 * invalid cells (no sample in the box, or X^T K^-1 X not positive definite):
-  depth = 0, var = +inf, dll = 0, valid = 0;
+  depth = 0, var = +inf, dll = 0, valid = 0. X^T K^-1 X is singular when the
+  box lies in the span of the trend columns (a box over every sample, with a
+  constant trend); in floating point its last pivot is then rounding noise,
+  so a cell counts as singular when the Schur complement of the trend block,
+  S = 1 / var, is at most 1e-12 times q = b^T K^-1 b;
 * var is the variance (the square of the depth uncertainty of Eq. 6).
 """
 from __future__ import annotations
@@ -86,6 +90,8 @@ def _fit_cells(At: np.ndarray, ft: np.ndarray, Bt: np.ndarray):
         w = scipy.linalg.cho_solve(cf, rhs)
         cov_last = scipy.linalg.cho_solve(cf, np.eye(M)[:, m1])[m1]
         if not (cov_last > 0.0 and math.isfinite(cov_last)):
+            continue
+        if not (1.0 / cov_last > 1e-12 * G[m1, m1]):   # box in the span of the trend: singular
             continue
         r = ft - Xt @ w
         depth[c] = w[m1]

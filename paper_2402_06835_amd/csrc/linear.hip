@@ -492,8 +492,9 @@ __global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __rest
       y[r] = 0.0;
     }
   }
+  // a box in the span of the trend columns leaves S at rounding level: singular
   const double S = q - gg;
-  ok = ok && (S > 0.0) && isfinite(S) && isfinite(h);
+  ok = ok && (S > 1e-12 * q) && isfinite(S) && isfinite(h);
   const int64_t o = (int64_t)j * n_epochs + i;
   if (ok) {
     const double dep = h / S;

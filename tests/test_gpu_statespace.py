@@ -266,15 +266,13 @@ def test_no_white_noise_sequential_path(api, ctx):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 191, 192, 193, 384, 385])
 def test_chunk_boundary_sizes(api, ctx, n):
-    """Sizes around the chunk length of the chunked filter (192 samples), and the smallest curves. The
-    smallest ones are exactly or nearly determined (as many parameters as samples), so their samples sit
-    0.3 d apart to keep K well conditioned; at 10-min spacing such a fit amplifies rounding far beyond the
-    FP64 bar in either implementation."""
+    """Sizes around the chunk length of the chunked filter (192 samples), and the smallest curves (where
+    boxes over every sample are collinear with the constant trend: invalid on both sides)."""
     import torch
     terms = _rot_terms()
     k = api.rotation_kernel(**ROT)
     rng = np.random.default_rng(100 + n)
-    t = np.arange(n) * (0.3 if n <= 3 else 10 / 1440)
+    t = np.arange(n) * (10 / 1440)
     lattice = np.arange(n, dtype=np.int64)
     f = 1.0 + rng.normal(0, 2e-3, n)
     A = np.ones((n, 1)) if n >= 2 else np.zeros((n, 0))

@@ -269,3 +269,22 @@ def test_lnl0_is_eq5_of_trend_only_fit():
     _, ld = np.linalg.slogdet(K)
     ref = -0.5 * r @ Ki @ r - 0.5 * ld - 0.5 * 60 * math.log(2 * math.pi)
     assert out["lnl0"] == pytest.approx(ref, rel=1e-9)
+
+
+def test_box_in_the_span_of_the_trend_is_invalid():
+    """A box over every sample equals minus the constant trend column: X^T K^-1 X is singular and the
+    cell is invalid, whatever the rounding of its last pivot. A box that leaves one sample out is not in
+    the span and stays valid, with the exactly determined fit of that case (depth = difference of the
+    two means weighted by K)."""
+    rng = np.random.default_rng(4)
+    n = 6
+    t = np.arange(n) * 0.01
+    theta = {"amp": 0.01, "omega": 8.0, "q": 3.0, "sigma_w": 1e-3}
+    L = gp.cholesky(gp.covariance(t, theta))
+    f = 1.0 + rng.normal(0, 1e-3, n)
+    A = np.ones((n, 1))
+    lattice = np.arange(n)
+    out = linear.linear_search(f, A, L, lattice, [n, n - 1], cells=[(0, n // 2), (1, (n - 1) // 2)])
+    assert out["valid"].tolist() == [0, 1]
+    assert out["var"][0] == np.inf and out["dll"][0] == 0.0 and out["depth"][0] == 0.0
+    assert np.isfinite(out["var"][1]) and out["var"][1] > 0
