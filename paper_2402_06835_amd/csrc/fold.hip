@@ -64,10 +64,11 @@ __global__ __launch_bounds__(256) void fold_pack_kernel(const double* __restrict
   Lp[e] = l;
 }
 
-// lane i receives lane i+1's value (DPP wave shift; lane 63 receives 0)
+// lane i receives lane i+1's value (DPP wave shift; lane 63 receives 0 through
+// the bound control, with no old value to set up)
 __device__ __forceinline__ double from_next_lane(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x130, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
@@ -124,9 +125,16 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
                                            int64_t nph, double p, double sign, double thr, Best& best) {
   const int64_t m = mb + lane;
   const int64_t kmax_base = n_t - 1 - mb;  // events while base_k <= this (uniform)
-  int64_t row[JG];
+  // the rows of the group from the wave's first phase: uniform pointers, so an
+  // event's loads share one 32-bit lane offset
+  const double2* dvr[JG];
+  const double* lpr[JG];
 #pragma unroll
-  for (int g = 0; g < JG; ++g) row[g] = (int64_t)min(j0 + g, n_d - 1) * ld + m;
+  for (int g = 0; g < JG; ++g) {
+    const int64_t r0 = (int64_t)min(j0 + g, n_d - 1) * ld + mb;
+    dvr[g] = DV + r0;
+    lpr[g] = Lp + r0;
+  }
   double s_w[JG], s_wd[JG], s_ll[JG], s_dd[JG];
   double vmin = INFINITY;  // over the group's durations: a smaller v_min only loosens the bound
   int cnt[JG];
@@ -135,29 +143,32 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
     s_w[g] = s_wd[g] = s_ll[g] = s_dd[g] = 0.0;
     cnt[g] = 0;
   }
-  // pass 1
+  // pass 1 (k counts events as an int64 and, exactly, as a double for k p)
   int seg = 0;
-  for (int64_t k = 0;; ++k) {
-    const double kp = (double)k * p;
+  double kd = 0.0;
+  for (int64_t k = 0;; ++k, kd += 1.0) {
+    const double kp = kd * p;
     const double base = floor(kp);
     if (base > (double)kmax_base) break;
-    int64_t b = (int64_t)base;
+    int b = (int)base;
     if constexpr (SEG) {
       int64_t delta, knext;
       if (!seg_event(S, mb, b, k, p, seg, delta, knext)) {
         k = knext - 1;
+        kd = (double)k;
         continue;
       }
-      b += delta;
+      b += (int)delta;
     }
     const double w = kp - base;
     const double u = 1.0 - w;
+    const int idx = lane + b;
     double2 dv[JG];
     double l[JG];
 #pragma unroll
     for (int g = 0; g < JG; ++g) {
-      dv[g] = DV[row[g] + b];
-      l[g] = Lp[row[g] + b];
+      dv[g] = dvr[g][idx];
+      l[g] = lpr[g][idx];
     }
 #pragma unroll
     for (int g = 0; g < JG; ++g) {
@@ -201,25 +212,28 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
   if (!any_need) return;
   // pass 2
   seg = 0;
-  for (int64_t k = 0;; ++k) {
-    const double kp = (double)k * p;
+  kd = 0.0;
+  for (int64_t k = 0;; ++k, kd += 1.0) {
+    const double kp = kd * p;
     const double base = floor(kp);
     if (base > (double)kmax_base) break;
-    int64_t b = (int64_t)base;
+    int b = (int)base;
     if constexpr (SEG) {
       int64_t delta, knext;
       if (!seg_event(S, mb, b, k, p, seg, delta, knext)) {
         k = knext - 1;
+        kd = (double)k;
         continue;
       }
-      b += delta;
+      b += (int)delta;
     }
     const double w = kp - base;
     const double u = 1.0 - w;
+    const int idx = lane + b;
     double2 dv[JG];
 #pragma unroll
     for (int g = 0; g < JG; ++g)
-      if (need[g]) dv[g] = DV[row[g] + b];
+      if (need[g]) dv[g] = dvr[g][idx];
 #pragma unroll
     for (int g = 0; g < JG; ++g) {
       if (!need[g]) continue;
