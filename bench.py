@@ -17,7 +17,11 @@ workload.
 Default precision: FP32_REFINE (FP64 Cholesky, FP32 inverse products with an
 FP64 band Newton step and one refinement step), the fastest path that meets
 the 1e-6 dll bar; its dll error against the FP64 path on the same curve is
-measured after the timed region and reported. Other modes:
+measured after the timed region and reported. The FP32 inverse is started
+inside the factorisation (the context's inverse prefetch: its leading half
+on three quarters of the CUs beside the late, latency-bound Cholesky steps;
+bit-identical results). Other modes:
+  --inverse-prefetch off  the inverse after the factorisation, inside linear_search
   --mode graph          the same step as one captured-graph launch
   --workload batch-64   64 curves of 4000..20000 samples in one batch call per step
                         (--mode loop: the same curves through the single-curve calls)
@@ -440,6 +444,10 @@ def bench_curve(args, api, ctx, torch):
         kernel = api.rotation_kernel(**ROTATION_KERNEL)
     elif args.solver == "statespace":
         kernel = api.SHO.from_dict(w.theta)
+    ctx_prefetch = args.inverse_prefetch == "on" and args.mode == "eager" and args.solver == "dense" \
+        and args.precision != "fp64"
+    if ctx_prefetch:
+        ctx.set_inverse_prefetch(args.precision, args.prefetch_cus)
     if args.mode == "graph":
         g = api.Graph(ctx, dev_in["t"], dev_in["f"], dev_in["A"], dev_in["lattice"], w.n_epochs, w.durations,
                       w.theta, w.dt, dev_in["periods"], precision=args.precision)
@@ -495,6 +503,8 @@ def bench_curve(args, api, ctx, torch):
            "n_periods": int(w.periods.size), "valid_cells": n_valid,
            "precision": args.precision if args.solver == "dense" else "fp64", "mode": args.mode,
            "solver": args.solver, "kernel": args.kernel, "template": args.template}
+    if ctx_prefetch:
+        cfg["inverse_prefetch_cus"] = args.prefetch_cus
     extra = {"best_period_days": float(w.periods[best]) if best >= 0 else None,
              "injected_period_days": w.injection["period"] if w.injection else None}
     if args.planets > 1:
@@ -524,6 +534,11 @@ def main(argv=None):
                     help="candidates per curve: after each periodic search the found transits are masked in the "
                          "linear-search products and the periodic search is repeated (single-curve eager mode)")
     ap.add_argument("--autotune", action="store_true", help="tune the tile policy before warming up")
+    ap.add_argument("--inverse-prefetch", default="on", choices=["on", "off"],
+                    help="compute the reduced-precision inverse inside the factorisation (dense solver, "
+                         "single-curve eager steps)")
+    ap.add_argument("--prefetch-cus", type=int, default=0,
+                    help="compute units of the inverse started inside the factorisation (0: three quarters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dll-check", action="store_true",
                     help="skip the FP64 reference search that measures the dll error of a reduced precision "
@@ -534,7 +549,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); curves shard across GPUs with no "
-              "communication but multi-GPU runs are not part of this build", file=sys.stderr)
+              "communication, and the timed step is one GPU's share", file=sys.stderr)
         return 2
 
     import torch

@@ -116,6 +116,20 @@ nu_status nu_ctx_set_stream(nu_ctx* ctx, void* stream);
  * workspace and the arena of the batch factors (4). Synchronises the stream. */
 nu_status nu_ctx_release_memory(nu_ctx* ctx);
 const char* nu_ctx_last_error(const nu_ctx* ctx);
+/* Inverse prefetch. prec = NU_FP32_REFINE or NU_BF16X3_REFINE: every later
+ * nu_gp_factor / nu_gp_factor_kernel on this context also computes the
+ * factor's triangular inverse L^-1 at that precision (the one the linear
+ * search of Section 2.2 applies to f and the design columns), starting its
+ * leading half (the inverse of the top-left block of L and its product with
+ * the block below) while the Cholesky factors the remaining columns, on
+ * compute_units of the device's compute units (0: three quarters of them;
+ * rounded to whole XCDs of 32), which the late, latency-bound steps leave
+ * idle. A linear search at prec then finds
+ * the inverse made; at another precision it makes its own as without
+ * prefetch. Results are bit-identical to those without prefetch. prec = -1
+ * (the default) turns it off. NU_ERR_ARG for other precisions or
+ * compute_units < 0. */
+nu_status nu_ctx_set_inverse_prefetch(nu_ctx* ctx, int prec, int compute_units);
 
 /* Kernel timing with HIP events recorded on the context's stream around
  * every launch of the library's kernels, accumulated per kernel name.

@@ -37,6 +37,7 @@ SIGNATURES = {
     "nu_ctx_destroy": (None, [c_void_p]),
     "nu_ctx_set_stream": (c_int, [c_void_p, c_void_p]),
     "nu_ctx_release_memory": (c_int, [c_void_p]),
+    "nu_ctx_set_inverse_prefetch": (c_int, [c_void_p, c_int, c_int]),
     "nu_ctx_last_error": (c_char_p, [c_void_p]),
     "nu_ctx_enable_timing": (c_int, [c_void_p, c_int]),
     "nu_ctx_timing_reset": (c_int, [c_void_p]),

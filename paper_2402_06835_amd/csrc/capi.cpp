@@ -187,10 +187,24 @@ nu_status validate_kernel(nu_ctx* ctx, const nu_kernel* k) {
 namespace {
 
 // K build (from the uploaded theta or kernel), blocked Cholesky, ln|K|;
-// synchronises once for the status
+// synchronises once for the status. With an inverse precision set on the
+// context (nu_ctx_set_inverse_prefetch), the factor's reduced-precision
+// inverse for it is computed here too, its leading half inside the
+// factorisation.
 nu_status factor_run(nu_ctx* ctx, nu_factor* F, const double* t, double* logdet_host, int64_t* fail_pivot_host) {
   std::vector<nu_factor*> one{F};
-  nu_status st = run_factor(ctx, one, F->plan64, {t}, {F->theta_dev()});
+  nu_status st = NU_OK;
+  EarlyInverse early;
+  const bool prefetch = ctx->prefetch_prec > 0;
+  if (prefetch) {
+    early.F = F;
+    early.prec = ctx->prefetch_prec;
+    st = ensure_plan32(ctx, F, early.prec);
+  }
+  if (st == NU_OK) st = run_factor(ctx, one, F->plan64, {t}, {F->theta_dev()}, prefetch ? &early : nullptr);
+  if (st == NU_OK && prefetch)
+    st = early.started ? run_inverse_post(ctx, F, F->plan32, early.prec)
+                       : run_inverse_mixed(ctx, one, F->plan32, early.prec);
   std::vector<int64_t> status;
   if (st == NU_OK) st = read_factor_status(ctx, one, status);
   if (st != NU_OK) return st;
@@ -199,6 +213,7 @@ nu_status factor_run(nu_ctx* ctx, nu_factor* F, const double* t, double* logdet_
     return set_error(ctx, NU_ERR_NOT_PD,
                      "gp_factor: covariance not positive definite at pivot " + std::to_string(status[0]));
   }
+  if (prefetch) F->inverse_kind = 1 + early.prec;
   if (logdet_host) *logdet_host = F->logdet;
   return NU_OK;
 }
@@ -285,6 +300,16 @@ nu_status nu_ctx_set_stream(nu_ctx* ctx, void* stream) {
 }
 
 const char* nu_ctx_last_error(const nu_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+nu_status nu_ctx_set_inverse_prefetch(nu_ctx* ctx, int prec, int compute_units) {
+  if (!ctx) return NU_ERR_ARG;
+  if (prec != -1 && prec != NU_FP32_REFINE && prec != NU_BF16X3_REFINE)
+    return set_error(ctx, NU_ERR_ARG, "inverse prefetch: precision must be NU_FP32_REFINE, NU_BF16X3_REFINE or -1");
+  if (compute_units < 0) return set_error(ctx, NU_ERR_ARG, "inverse prefetch: compute_units must be >= 0");
+  ctx->prefetch_prec = prec;
+  ctx->prefetch_cus = compute_units;
+  return NU_OK;
+}
 
 nu_status nu_ctx_enable_timing(nu_ctx* ctx, int enable) {
   if (!ctx) return NU_ERR_ARG;

@@ -180,7 +180,18 @@ void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P)
 // Triangular inverse X = L^-1, bottom-up over a binary tree of the TB blocks:
 // for the node [[A, 0], [L21, C]], T = L21 X_A then X21 = -X_C T. Leaves are
 // the diagonal-block inverses. Level e of every factor runs in one launch.
-void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu, Plan& P) {
+//
+// T layout: the root's T at offset 0 and every other node past it (the nodes
+// of one level side by side; levels run one after another). The root's T then
+// survives from its first product to its second, so a single factor's plan can
+// split (split = true) into the leading half of the tree [0, mid) plus the
+// root's first product, which need only the factor's columns left of mid, and
+// the trailing half plus the root's second product.
+namespace {
+size_t node_elems(const Node& nd) { return (size_t)(nd.mid - nd.a) * TB * (size_t)(nd.b - nd.mid) * TB; }
+}  // namespace
+
+void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu, Plan& P, bool split) {
   const bool f32 = kind != GK_F64;  // the split-BF16 products run on the FP32 copies
   std::vector<std::vector<std::vector<Node>>> lv(Fs.size());
   size_t nlev = 0;
@@ -192,24 +203,58 @@ void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu,
   const int cls = kind == GK_F64 ? TC_INV64 : kind == GK_F32 ? TC_INV32 : TC_INVB;
   P.t1.clear();
   P.t2.clear();
+  P.pre.clear();
+  P.post.clear();
+  P.split = 0;
+  // the products of one node: T = L21 X_A, X21 = -X_C T
+  auto node_probs = [&](nu_factor* F, const Node& nd, size_t off_t, std::vector<GemmProblem>& p1,
+                        std::vector<GemmProblem>& p2) {
+    const int64_t np = F->np;
+    const void* L = f32 ? (const void*)F->L32 : (const void*)F->L;
+    void* X = f32 ? (void*)F->X32 : (void*)F->X;
+    const int64_t a0 = (int64_t)nd.a * TB, m0 = (int64_t)nd.mid * TB;
+    const int na = (nd.mid - nd.a) * TB, nc = (nd.b - nd.mid) * TB;
+    void* Tn = at(F->T, 0, (int64_t)off_t, 0, es);
+    p1.push_back(prob(at(L, m0, a0, np, es), np, at(X, a0, a0, np, es), np, Tn, na, nc, na, na, G_B_LOWER, 1.0, 0.0));
+    p2.push_back(prob(at(X, m0, m0, np, es), np, Tn, na, at(X, m0, a0, np, es), np, nc, na, nc, G_A_LOWER, -1.0,
+                      0.0));
+  };
+  if (split && Fs.size() == 1 && nlev >= 1) {
+    nu_factor* F = Fs[0];
+    const auto& levels = lv[0];
+    const Node root = levels.back()[0];
+    const size_t root_elems = node_elems(root);
+    P.split = root.mid;
+    for (int half = 0; half < 2; ++half) {
+      std::vector<Range>& out = half == 0 ? P.pre : P.post;
+      for (size_t e = 0; e + 1 < levels.size(); ++e) {
+        std::vector<GemmProblem> p1, p2;
+        size_t off_t = root_elems;
+        for (const Node& nd : levels[e]) {
+          const bool lead = nd.b <= root.mid;
+          if (lead == (half == 0)) node_probs(F, nd, off_t, p1, p2);
+          off_t += node_elems(nd);
+        }
+        if (!p1.empty()) {
+          out.push_back(add_launch(P.sched, p1, tu.small_below[cls]));
+          out.push_back(add_launch(P.sched, p2, tu.small_below[cls]));
+        }
+      }
+      std::vector<GemmProblem> r1, r2;
+      node_probs(F, root, 0, r1, r2);
+      out.push_back(add_launch(P.sched, half == 0 ? r1 : r2, tu.small_below[cls]));
+    }
+    return;
+  }
   for (size_t e = 0; e < nlev; ++e) {
     std::vector<GemmProblem> p1, p2;
     for (size_t i = 0; i < Fs.size(); ++i) {
       if (e >= lv[i].size()) continue;
-      nu_factor* F = Fs[i];
-      const int64_t np = F->np;
-      const void* L = f32 ? (const void*)F->L32 : (const void*)F->L;
-      void* X = f32 ? (void*)F->X32 : (void*)F->X;
-      size_t off_t = 0;
+      const bool is_root = e + 1 == lv[i].size();
+      size_t off_t = is_root ? 0 : node_elems(lv[i].back()[0]);
       for (const Node& nd : lv[i][e]) {
-        const int64_t a0 = (int64_t)nd.a * TB, m0 = (int64_t)nd.mid * TB;
-        const int na = (nd.mid - nd.a) * TB, nc = (nd.b - nd.mid) * TB;
-        void* Tn = at(F->T, 0, (int64_t)off_t, 0, es);
-        p1.push_back(prob(at(L, m0, a0, np, es), np, at(X, a0, a0, np, es), np, Tn, na, nc, na, na, G_B_LOWER, 1.0,
-                          0.0));
-        p2.push_back(prob(at(X, m0, m0, np, es), np, Tn, na, at(X, m0, a0, np, es), np, nc, na, nc, G_A_LOWER, -1.0,
-                          0.0));
-        off_t += (size_t)na * nc;
+        node_probs(Fs[i], nd, off_t, p1, p2);
+        off_t += node_elems(nd);
       }
     }
     P.t1.push_back(add_launch(P.sched, p1, tu.small_below[cls]));
@@ -218,13 +263,15 @@ void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu,
 }
 
 size_t inverse_t_elems(int nblk) {
-  size_t tmax = 1;
-  for (const auto& level : inverse_levels(nblk)) {
+  const auto levels = inverse_levels(nblk);
+  if (levels.empty()) return 1;
+  size_t other = 0;
+  for (size_t e = 0; e + 1 < levels.size(); ++e) {
     size_t s = 0;
-    for (const Node& nd : level) s += (size_t)(nd.mid - nd.a) * TB * (size_t)(nd.b - nd.mid) * TB;
-    tmax = std::max(tmax, s);
+    for (const Node& nd : levels[e]) s += node_elems(nd);
+    other = std::max(other, s);
   }
-  return tmax;
+  return node_elems(levels.back()[0]) + other;
 }
 
 // One Newton step X1 = 2 X - X (L X) on the blocks within w of the
@@ -399,7 +446,7 @@ nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F, int prec) {
     plan_release(F->plan32);
   }
   std::vector<nu_factor*> one{F};
-  plan_inverse(one, gemm_kind_of(prec), ctx->tuning, F->plan32);
+  plan_inverse(one, gemm_kind_of(prec), ctx->tuning, F->plan32, true);
   plan_band(one, band_width(prec), ctx->tuning, F->plan32);
   st = plan_upload(ctx, F->plan32);
   if (st == NU_OK) F->plan32_prec = prec;
@@ -450,17 +497,50 @@ nu_status ensure_factor_streams(nu_ctx* ctx) {
   if (st == NU_OK)
     st = check_hip(ctx, hipExtStreamCreateWithCUMask(&ctx->s_rest, (uint32_t)mask.size(), mask.data()),
                    "trailing-update stream");
-  hipEvent_t* evs[] = {&ctx->ev_fork, &ctx->ev_pan, &ctx->ev_rest, &ctx->ev_join};
+  hipEvent_t* evs[] = {&ctx->ev_fork, &ctx->ev_pan, &ctx->ev_rest, &ctx->ev_join, &ctx->ev_split, &ctx->ev_inv};
   for (hipEvent_t* e : evs)
     if (st == NU_OK) st = check_hip(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming), "step-loop event");
   if (st != NU_OK) destroy_factor_streams(ctx);
   return st;
 }
 
+// CUs of one XCD of gfx950; a CU mask selects them XCD by XCD (bits
+// [32 x, 32 x + 32) are XCD x).
+constexpr int XCD_CUS = 32;
+
+// The early inverse's stream on the top `compute_units` CUs (0: three
+// quarters of the chip, the fastest split on the TESS-sector curve), rounded
+// to whole XCDs (at least one, at most all but one): an inverse spread over
+// part of every XCD slows the factorisation's kernels more than one on XCDs
+// of its own. Recreated when the count changes.
+nu_status ensure_inverse_stream(nu_ctx* ctx, int compute_units) {
+  int ncu = 0;
+  nu_status st =
+      check_hip(ctx, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device), "CU count");
+  if (st != NU_OK) return st;
+  if (ncu < 2 * XCD_CUS || ncu % XCD_CUS != 0) return NU_OK;  // no split: the inverse runs after the factorisation
+  int c = compute_units > 0 ? compute_units : ncu / 4 * 3;
+  c = std::max(XCD_CUS, std::min(ncu - XCD_CUS, (c + XCD_CUS / 2) / XCD_CUS * XCD_CUS));
+  if (ctx->s_inv && ctx->s_inv_cus == c) return NU_OK;
+  if (ctx->s_inv) {
+    (void)hipStreamSynchronize(ctx->s_inv);
+    (void)hipStreamDestroy(ctx->s_inv);
+    ctx->s_inv = nullptr;
+  }
+  ctx->s_inv_cus = 0;
+  std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0u);
+  for (int u = ncu - c; u < ncu; ++u) mask[(size_t)u / 32] |= 1u << (u % 32);
+  st = check_hip(ctx, hipExtStreamCreateWithCUMask(&ctx->s_inv, (uint32_t)mask.size(), mask.data()),
+                 "early-inverse stream");
+  if (st == NU_OK) ctx->s_inv_cus = c;
+  return st;
+}
+
 void destroy_factor_streams(nu_ctx* ctx) {
   if (ctx->s_fac) (void)hipStreamSynchronize(ctx->s_fac);
   if (ctx->s_rest) (void)hipStreamSynchronize(ctx->s_rest);
-  hipEvent_t* evs[] = {&ctx->ev_fork, &ctx->ev_pan, &ctx->ev_rest, &ctx->ev_join};
+  if (ctx->s_inv) (void)hipStreamSynchronize(ctx->s_inv);
+  hipEvent_t* evs[] = {&ctx->ev_fork, &ctx->ev_pan, &ctx->ev_rest, &ctx->ev_join, &ctx->ev_split, &ctx->ev_inv};
   for (hipEvent_t* e : evs)
     if (*e) {
       (void)hipEventDestroy(*e);
@@ -468,11 +548,15 @@ void destroy_factor_streams(nu_ctx* ctx) {
     }
   if (ctx->s_fac) (void)hipStreamDestroy(ctx->s_fac);
   if (ctx->s_rest) (void)hipStreamDestroy(ctx->s_rest);
+  if (ctx->s_inv) (void)hipStreamDestroy(ctx->s_inv);
+  ctx->s_inv = nullptr;
+  ctx->s_inv_cus = 0;
   ctx->s_fac = ctx->s_rest = nullptr;
 }
 
 nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P,
-                     const std::vector<const double*>& ts, const std::vector<const nu_sho*>& theta_dev) {
+                     const std::vector<const double*>& ts, const std::vector<const nu_sho*>& theta_dev,
+                     const EarlyInverse* early) {
   nu_status st = NU_OK;
   for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i) {
     nu_factor* F = Fs[i];
@@ -507,6 +591,14 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
   // the null stream's pending work, and that must not enter a capture.
   // A step whose diagonal blocks outnumber the free CUs (a batch: one block
   // per curve) would queue them behind the update's tiles; it stays serial.
+  //
+  // Early inverse (early != nullptr, lookahead only): once step split - 1 has
+  // factored its panel, the columns left of the inverse plan's split point are
+  // final, and the leading half of the reduced-precision inverse runs on
+  // s_inv (part of the chip, see ensure_inverse_stream) beside the remaining steps, which from there
+  // on are bound by the chain of diagonal blocks and leave most of the chip
+  // idle. It writes only the factor's FP32 copies and T, which no step reads.
+  // The join waits for it; the caller then enqueues the rest of the inverse.
   hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
   if (st == NU_OK) st = check_hip(ctx, hipStreamIsCapturing(ctx->stream, &capturing), "capture status");
   int max_jobs = 0;
@@ -514,14 +606,19 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
   const bool want_la = ctx->lookahead && capturing == hipStreamCaptureStatusNone && max_jobs <= LOOKAHEAD_FREE_CUS;
   if (st == NU_OK && want_la) st = ensure_factor_streams(ctx);
   const bool la = st == NU_OK && want_la && ctx->lookahead && ctx->s_rest;
+  if (st == NU_OK && la && early) st = ensure_inverse_stream(ctx, ctx->prefetch_cus);
   hipStream_t sf = ctx->stream;
   if (la) {
     st = check_hip(ctx, hipEventRecord(ctx->ev_fork, ctx->stream), "fork");
     if (st == NU_OK) st = check_hip(ctx, hipStreamWaitEvent(ctx->s_fac, ctx->ev_fork, 0), "fork");
     sf = ctx->s_fac;
   }
-  bool rest_pending = false;
+  bool rest_pending = false, inv_pending = false;
   const int steps = (int)P.job_first.size();
+  const int early_step = la && early && ctx->s_inv && early->F->plan32.built && early->F->plan32_prec == early->prec &&
+                                 early->F->plan32.split > 0 && early->F->plan32.split <= steps
+                             ? early->F->plan32.split - 1
+                             : -1;
   for (int k = 0; st == NU_OK && k < steps; ++k) {
     {
       Timed tm(ctx, sf, "potrf_diag", (double)P.job_count[k] * TB * TB * TB * 2.0 / 3.0);
@@ -529,6 +626,13 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
     }
     if (st == NU_OK) st = launch_range(ctx, P, P.panel[k], "gemm_f64:panel", GK_F64, sf);
     if (st == NU_OK) st = launch_range(ctx, P, P.pupd[k], "gemm_f64:panel_update", GK_F64, sf);
+    if (st == NU_OK && k == early_step) {
+      st = check_hip(ctx, hipEventRecord(ctx->ev_split, sf), "early inverse");
+      if (st == NU_OK) st = check_hip(ctx, hipStreamWaitEvent(ctx->s_inv, ctx->ev_split, 0), "early inverse");
+      if (st == NU_OK) st = run_inverse_pre(ctx, early->F, early->F->plan32, early->prec, ctx->s_inv);
+      if (st == NU_OK) st = check_hip(ctx, hipEventRecord(ctx->ev_inv, ctx->s_inv), "early inverse");
+      inv_pending = st == NU_OK;
+    }
     if (st != NU_OK || (P.next[k].tiles == 0 && P.rest[k].tiles == 0)) continue;
     if (!la) {
       st = launch_range(ctx, P, P.next[k], "gemm_f64:trailing", GK_F64, sf);
@@ -551,8 +655,10 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
     if (rest_pending) sj = check_hip(ctx, hipStreamWaitEvent(sf, ctx->ev_rest, 0), "join");
     if (sj == NU_OK) sj = check_hip(ctx, hipEventRecord(ctx->ev_join, sf), "join");
     if (sj == NU_OK) sj = check_hip(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "join");
+    if (sj == NU_OK && inv_pending) sj = check_hip(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_inv, 0), "join");
     if (st == NU_OK) st = sj;
   }
+  if (early) early->started = st == NU_OK && inv_pending;
   for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i)
     st = check_hip(ctx, launch_logdet_reduce(ctx->stream, Fs[i]->parts(), Fs[i]->nblk, Fs[i]->logdet_dev()),
                    "logdet");
@@ -585,12 +691,60 @@ nu_status run_inverse_fp64(nu_ctx* ctx, const Plan& P) {
   return st;
 }
 
+// Leading half of a split inverse (see plan_inverse) on stream s: the FP32
+// copies of the factor's columns left of the split and of their diagonal
+// blocks, then the leading subtree and the root's first product. It reads
+// only columns the factorisation has finished by its step split - 1.
+nu_status run_inverse_pre(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec, hipStream_t s) {
+  const int kind = gemm_kind_of(prec);
+  const char* level_name = kind == GK_BF16X3 ? "gemm_bf16x3:inverse" : "gemm_f32:inverse";
+  nu_status st;
+  {
+    Timed tm(ctx, s, "convert", 0.0);
+    st = check_hip(ctx, launch_cvt_f64_f32(s, F->L, F->L32, F->np, 0, 0, P.split), "convert L");
+    if (st == NU_OK) st = check_hip(ctx, launch_cvt_f64_f32(s, F->X, F->X32, F->np, 1, 0, P.split), "convert X diag");
+  }
+  for (size_t r = 0; st == NU_OK && r < P.pre.size(); ++r) st = launch_range(ctx, P, P.pre[r], level_name, kind, s);
+  return st;
+}
+
+// The rest of a split inverse on the context's stream: the remaining FP32
+// copies, the trailing subtree and the root's second product, then the FP64
+// copy and the band step.
+nu_status run_inverse_post(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec) {
+  const int kind = gemm_kind_of(prec), w = band_width(prec);
+  const char* level_name = kind == GK_BF16X3 ? "gemm_bf16x3:inverse" : "gemm_f32:inverse";
+  if (F->band_w < w) return set_error(ctx, NU_ERR_ARG, "inverse: band buffers narrower than the precision needs");
+  nu_status st;
+  {
+    Timed tm(ctx, "convert", 0.0);
+    st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->L, F->L32, F->np, 0, P.split, F->nblk), "convert L");
+    if (st == NU_OK)
+      st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->X, F->X32, F->np, 1, P.split, F->nblk),
+                     "convert X diag");
+  }
+  for (size_t r = 0; st == NU_OK && r < P.post.size(); ++r) st = launch_range(ctx, P, P.post[r], level_name, kind);
+  if (st == NU_OK) {
+    Timed tm(ctx, "convert", 0.0);
+    st = check_hip(ctx, launch_cvt_f32_f64(ctx->stream, F->X32, F->X, F->np), "convert X");
+  }
+  if (st == NU_OK) st = check_hip(ctx, launch_band_copy(ctx->stream, F->X, F->np, F->bandX, w, 1), "band copy");
+  if (st == NU_OK) st = launch_range(ctx, P, P.bandp, "gemm_f64:band", GK_F64);
+  if (st == NU_OK) st = launch_range(ctx, P, P.bandx, "gemm_f64:band", GK_F64);
+  if (st == NU_OK) st = check_hip(ctx, launch_band_copy(ctx->stream, F->X, F->np, F->bandX, w, 0), "band copy");
+  return st;
+}
+
 // Reduced-precision doubling levels (FP32, or split BF16 for
 // NU_BF16X3_REFINE), then one FP64 Newton step on the blocks within the
 // precision's band width of the diagonal. P holds the levels and the band
 // products of every factor in Fs (their reduced-precision buffers allocated
-// for prec).
+// for prec); a single factor's split plan runs its two halves in turn.
 nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P, int prec) {
+  if (P.split > 0 && Fs.size() == 1) {
+    nu_status st = run_inverse_pre(ctx, Fs[0], P, prec, ctx->stream);
+    return st == NU_OK ? run_inverse_post(ctx, Fs[0], P, prec) : st;
+  }
   const int kind = gemm_kind_of(prec), w = band_width(prec);
   const char* level_name = kind == GK_BF16X3 ? "gemm_bf16x3:inverse" : "gemm_f32:inverse";
   nu_status st = NU_OK;
@@ -598,8 +752,9 @@ nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, cons
     nu_factor* F = Fs[i];
     if (F->band_w < w) return set_error(ctx, NU_ERR_ARG, "inverse: band buffers narrower than the precision needs");
     Timed tm(ctx, "convert", 0.0);
-    st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->L, F->L32, F->np, 0), "convert L");
-    if (st == NU_OK) st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->X, F->X32, F->np, 1), "convert X diag");
+    st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->L, F->L32, F->np, 0, 0, F->nblk), "convert L");
+    if (st == NU_OK)
+      st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->X, F->X32, F->np, 1, 0, F->nblk), "convert X diag");
   }
   for (size_t l = 0; st == NU_OK && l < P.t1.size(); ++l) {
     st = launch_range(ctx, P, P.t1[l], level_name, kind);

@@ -139,6 +139,13 @@ struct nu_ctx {
   hipStream_t s_fac = nullptr, s_rest = nullptr;
   hipEvent_t ev_fork = nullptr, ev_pan = nullptr, ev_rest = nullptr, ev_join = nullptr;
   bool lookahead = true;
+  // early inverse of a factorisation: its stream (on the top s_inv_cus CUs),
+  // the event that releases it and the event of its end; the precision it is
+  // started for (-1: none) and the CUs asked for (0: three quarters)
+  hipStream_t s_inv = nullptr;
+  int s_inv_cus = 0;
+  hipEvent_t ev_split = nullptr, ev_inv = nullptr;
+  int prefetch_prec = -1, prefetch_cus = 0;
   // pinned host staging of small host-to-device uploads (template shapes); the
   // event marks the last copy out of it
   void* pinned = nullptr;
@@ -179,6 +186,11 @@ struct Plan {
   std::vector<Range> next, rest;          // per step: the trailing update after a panel's last block, split
                                           // into the next panel's columns and the rest
   std::vector<Range> t1, t2;              // per inverse level, deepest first
+  // a single factor's inverse split at the root's middle block `split`: the
+  // launches of the leading half (and the root's first product), then of the
+  // rest (and the root's second product); split = 0: t1/t2 instead
+  std::vector<Range> pre, post;
+  int split = 0;
   Range bandp, bandx;
   bool built = false;
 };
@@ -261,7 +273,7 @@ struct HostTimed {
 
 // engine (engine.cpp)
 void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P);
-void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu, Plan& P);
+void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu, Plan& P, bool split = false);
 void plan_band(const std::vector<nu_factor*>& Fs, int w, const Tuning& tu, Plan& P);
 size_t inverse_t_elems(int nblk);
 nu_status plan_upload(nu_ctx* ctx, Plan& P);
@@ -275,12 +287,24 @@ void factor_free(nu_factor* F);
 nu_status launch_range(nu_ctx* ctx, const Plan& P, const Range& r, const char* name, int kind,
                        hipStream_t s = nullptr);  // s = nullptr: the context's stream
 nu_status ensure_factor_streams(nu_ctx* ctx);
+nu_status ensure_inverse_stream(nu_ctx* ctx, int compute_units);
 void destroy_factor_streams(nu_ctx* ctx);
+// The reduced-precision inverse of a single factor started inside its
+// factorisation: the leading half as soon as the Cholesky has finished the
+// columns it reads, beside the remaining steps, the rest after them.
+struct EarlyInverse {
+  nu_factor* F = nullptr;
+  int prec = 0;                  // NU_FP32_REFINE or NU_BF16X3_REFINE; F->plan32 is built for it
+  mutable bool started = false;  // out: the leading half was enqueued (run_inverse_post is due)
+};
 nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P,
-                     const std::vector<const double*>& ts, const std::vector<const nu_sho*>& theta_dev);
+                     const std::vector<const double*>& ts, const std::vector<const nu_sho*>& theta_dev,
+                     const EarlyInverse* early = nullptr);
 nu_status read_factor_status(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, std::vector<int64_t>& status);
 nu_status run_inverse_fp64(nu_ctx* ctx, const Plan& P);
 nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P, int prec);
+nu_status run_inverse_pre(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec, hipStream_t s);
+nu_status run_inverse_post(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec);
 size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs);
 nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double* A, int m1, const int64_t* lattice,
                           int64_t n_epochs, const int32_t* dur_samples_host, int n_d, nu_precision prec,
@@ -317,7 +341,8 @@ hipError_t launch_fill_invalid_cells(hipStream_t s, int64_t count, double* depth
 hipError_t launch_fill_no_event(hipStream_t s, int64_t n_p, double* q_snr, int64_t* best_phase, int32_t* best_dur,
                                 double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period);
 hipError_t launch_fill_i64(hipStream_t s, int64_t* p, int64_t v);
-hipError_t launch_cvt_f64_f32(hipStream_t s, const double* src, float* dst, int64_t np, int diag_only);
+hipError_t launch_cvt_f64_f32(hipStream_t s, const double* src, float* dst, int64_t np, int diag_only, int cb0,
+                              int cb1);
 hipError_t launch_cvt_f32_f64(hipStream_t s, const float* src, double* dst, int64_t np);
 hipError_t launch_band_copy(hipStream_t s, double* X, int64_t np, double* band, int w, int to_band);
 hipError_t launch_logdet_reduce(hipStream_t s, const double* parts, int nparts, double* out);

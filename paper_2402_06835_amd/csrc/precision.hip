@@ -17,9 +17,9 @@ namespace nu {
 
 // dst = (float) src on the lower blocks (bi >= bj), or on the diagonal blocks only
 __global__ __launch_bounds__(256) void cvt_f64_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
-                                                          int64_t np, int diag_only) {
-  const int bi = blockIdx.y, bj = diag_only ? blockIdx.y : blockIdx.x;
-  if (bj > bi) return;
+                                                          int64_t np, int diag_only, int cb0, int cb1) {
+  const int bi = blockIdx.y, bj = diag_only ? blockIdx.y : cb0 + (int)blockIdx.x;
+  if (bj > bi || bj < cb0 || bj >= cb1) return;
   const double* s = src + (int64_t)bi * TB * np + (int64_t)bj * TB;
   float* d = dst + (int64_t)bi * TB * np + (int64_t)bj * TB;
   for (int idx = threadIdx.x; idx < TB * TB; idx += 256) {
@@ -28,9 +28,16 @@ __global__ __launch_bounds__(256) void cvt_f64_f32_kernel(const double* __restri
   }
 }
 
-hipError_t launch_cvt_f64_f32(hipStream_t s, const double* src, float* dst, int64_t np, int diag_only) {
-  const unsigned nb = (unsigned)(np / TB);
-  hipLaunchKernelGGL(cvt_f64_f32_kernel, dim3(diag_only ? 1u : nb, nb), dim3(256), 0, s, src, dst, np, diag_only);
+// dst = (float) src on the lower blocks (bi >= bj) of block columns [cb0, cb1),
+// or on their diagonal blocks only
+hipError_t launch_cvt_f64_f32(hipStream_t s, const double* src, float* dst, int64_t np, int diag_only, int cb0,
+                              int cb1) {
+  const int nb = (int)(np / TB);
+  cb0 = cb0 < 0 ? 0 : cb0;
+  cb1 = cb1 > nb ? nb : cb1;
+  if (cb1 <= cb0) return hipSuccess;
+  hipLaunchKernelGGL(cvt_f64_f32_kernel, dim3(diag_only ? 1u : (unsigned)(cb1 - cb0), (unsigned)nb), dim3(256), 0, s,
+                     src, dst, np, diag_only, cb0, cb1);
   return hipGetLastError();
 }
 
