@@ -779,8 +779,16 @@ nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, cons
 // Linear search of one factor (the inverse of the requested kind in place)
 
 namespace {
-constexpr int XRC = 1024;  // rows per partial of the transposed products
-constexpr int QRC = 512;   // rows per partial of the box sums of squares (one wave each: latency bound, so many)
+// Partials of the products with X and L (measured at N = 18000): the
+// transposed products take XRC rows per partial (512: 0.96 ms for the three
+// passes; 1024: 1.50; 256: 1.02), the row products RCW columns (2048: 0.89 ms;
+// 1024: 0.95; 512: 1.23). Both share one partial buffer of XRC chunks.
+constexpr int XRC = 512;
+constexpr int RCW = 2048;
+static_assert(RCW % XRC == 0, "row-product partials fit the buffer of the transposed ones");
+// rows per partial of the box sums of squares (one wave each: latency bound,
+// so many; 256: 0.89 ms at N = 18000, 512: 1.02, 1024: 1.31)
+constexpr int QRC = 256;
 }  // namespace
 
 size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs) {
@@ -818,7 +826,7 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
                      const double* shapes_host) {
   const int steps = refine_steps(prec);
   const int64_t n = F->n, np = F->np;
-  const int xchunks = (int)((n + XRC - 1) / XRC);
+  const int xchunks = (int)((n + XRC - 1) / XRC), rchunks = (int)((n + RCW - 1) / RCW);
   const int qchunks = (int)((n + QRC - 1) / QRC);
   const size_t yz = (size_t)np * YCOLS;
   double* V = ws;
@@ -847,11 +855,14 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
   {
     // Y = X V, refined against L when X is a reduced-precision inverse
     Timed tm(ctx, "rows_matvec", gemv_bytes * (1 + 2 * steps));
-    st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->X, np, n, V, nv, nullptr, 1.0, Y), "rows_matvec");
+    st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->X, np, n, np, V, nv, xpart, RCW, rchunks, nullptr, 1.0, Y),
+                   "rows_matvec");
     for (int r = 0; r < steps && st == NU_OK; ++r) {
-      st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->L, np, n, Y, nv, V, -1.0, R), "rows_matvec");
+      st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->L, np, n, np, Y, nv, xpart, RCW, rchunks, V, -1.0, R),
+                     "rows_matvec");
       if (st == NU_OK)
-        st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->X, np, n, R, nv, Y, 1.0, Y), "rows_matvec");
+        st = check_hip(ctx, launch_rows_matvec(ctx->stream, F->X, np, n, np, R, nv, xpart, RCW, rchunks, Y, 1.0, Y),
+                       "rows_matvec");
     }
   }
   if (st != NU_OK) return st;

@@ -348,8 +348,9 @@ hipError_t launch_band_copy(hipStream_t s, double* X, int64_t np, double* band, 
 hipError_t launch_logdet_reduce(hipStream_t s, const double* parts, int nparts, double* out);
 
 hipError_t launch_pack_v(hipStream_t s, const double* A, int m1, const double* f, int64_t n, double* V);
-hipError_t launch_rows_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, const double* V, int nv,
-                              const double* base, double alpha, double* out);
+hipError_t launch_rows_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, int64_t np, const double* V,
+                              int nv, double* partial, int cw, int nchunks, const double* base, double alpha,
+                              double* out);
 hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const double* logdet, NullFit* nf,
                              double* null_out);
 hipError_t launch_cols_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, int64_t np, const double* W,

@@ -63,20 +63,26 @@ hipError_t launch_pack_v(hipStream_t s, const double* A, int m1, const double* f
 }
 
 // out[r] = base[r] + alpha * sum_{m <= r} M[r][m] V[m]   (nv columns, row-major,
-// lower-triangular M; entries above the diagonal are never read). A wave owns
-// RPW consecutive rows and streams 64-column chunks of V once for all of them
-// (each lane: one column of the chunk, its nv values of V, and one element of
-// every row), so V leaves L2 once per RPW rows; fixed-order wave reductions at
-// the end. out may alias base.
+// lower-triangular M; entries above the diagonal are never read), in two
+// launches: partial sums over column chunks of cw columns, then the
+// fixed-order sum of the chunks (cols_reduce_kernel, shared with the
+// transposed product). A wave owns RPW consecutive rows and one column chunk
+// and streams its 64-column pieces of V once for all RPW rows (each lane: one
+// column of the piece, its nv values of V, and one element of every row);
+// fixed-order wave reductions at the end. The chunks keep each wave's chain of
+// dependent loads short and give the long rows at the bottom of the triangle
+// as many waves as they need. Chunks right of a wave's rows write zeros, so
+// every partial is defined. out may alias base.
 constexpr int RPW = 8;
 
 template <int NV>
-__global__ __launch_bounds__(256) void rows_matvec_kernel(const double* __restrict__ M, int64_t ldm, int64_t n,
-                                                          const double* __restrict__ V, const double* base,
-                                                          double alpha, double* out) {
+__global__ __launch_bounds__(256) void rows_partial_kernel(const double* __restrict__ M, int64_t ldm, int64_t n,
+                                                           int64_t np, const double* __restrict__ V, int cw,
+                                                           double* __restrict__ partial) {
   const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
   const int lane = threadIdx.x & 63;
   if (r0 >= n) return;
+  const int chunk = blockIdx.y;
   const int rows = (int)min((int64_t)RPW, n - r0);
   const int64_t rlast = r0 + rows - 1;
   double acc[RPW][NV];
@@ -84,7 +90,8 @@ __global__ __launch_bounds__(256) void rows_matvec_kernel(const double* __restri
   for (int i = 0; i < RPW; ++i)
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[i][c] = 0.0;
-  for (int64_t m0 = 0; m0 <= rlast; m0 += 64) {
+  const int64_t mb = (int64_t)chunk * cw, me = min(rlast + 1, mb + cw);
+  for (int64_t m0 = mb; m0 < me; m0 += 64) {
     const int64_t m = m0 + lane;
     double v[NV];
 #pragma unroll
@@ -101,7 +108,7 @@ __global__ __launch_bounds__(256) void rows_matvec_kernel(const double* __restri
   for (int i = 0; i < RPW; ++i)
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[i][c] = wave_sum(acc[i][c]);
-  // lane i * 8 + c writes row r0 + i, column c
+  // lane i * 8 + c writes row r0 + i, column c of this chunk's partial
   const int wi = lane >> 3, wc = lane & 7;
   double mine = 0.0;
 #pragma unroll
@@ -109,28 +116,7 @@ __global__ __launch_bounds__(256) void rows_matvec_kernel(const double* __restri
 #pragma unroll
     for (int c = 0; c < NV; ++c)
       if (i == wi && c == wc) mine = acc[i][c];
-  if (wi < rows && wc < NV) {
-    const int64_t o = (r0 + wi) * YCOLS + wc;
-    out[o] = (base ? base[o] : 0.0) + alpha * mine;
-  }
-}
-
-hipError_t launch_rows_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, const double* V, int nv,
-                              const double* base, double alpha, double* out) {
-  const int64_t waves = (n + RPW - 1) / RPW;
-  const dim3 g((unsigned)((waves + 3) / 4)), b(256);
-  switch (nv) {
-    case 1: hipLaunchKernelGGL(rows_matvec_kernel<1>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
-    case 2: hipLaunchKernelGGL(rows_matvec_kernel<2>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
-    case 3: hipLaunchKernelGGL(rows_matvec_kernel<3>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
-    case 4: hipLaunchKernelGGL(rows_matvec_kernel<4>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
-    case 5: hipLaunchKernelGGL(rows_matvec_kernel<5>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
-    case 6: hipLaunchKernelGGL(rows_matvec_kernel<6>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
-    case 7: hipLaunchKernelGGL(rows_matvec_kernel<7>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
-    case 8: hipLaunchKernelGGL(rows_matvec_kernel<8>, g, b, 0, s, M, ldm, n, V, base, alpha, out); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (wi < rows) partial[((int64_t)chunk * np + r0 + wi) * YCOLS + wc] = wc < NV ? mine : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -270,14 +256,42 @@ __global__ __launch_bounds__(256) void cols_partial_kernel(const double* __restr
   for (int c = 0; c < YCOLS; ++c) o[c] = acc[c];
 }
 
+// out[e] = base[e] + alpha * sum_c partial[c][e] for e < tot (elements of the
+// np x YCOLS layout), the chunks in order
 __global__ __launch_bounds__(256) void cols_reduce_kernel(const double* __restrict__ partial, int64_t np,
                                                           int nchunks, const double* base, double alpha,
-                                                          double* out) {
+                                                          double* out, int64_t tot) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= np * YCOLS) return;
+  if (e >= tot) return;
   double s = 0.0;
   for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * np * YCOLS + e];
   out[e] = (base ? base[e] : 0.0) + alpha * s;
+}
+
+hipError_t launch_rows_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, int64_t np, const double* V,
+                              int nv, double* partial, int cw, int nchunks, const double* base, double alpha,
+                              double* out) {
+  if (cw <= 0 || cw % 64 != 0 || (int64_t)nchunks * cw < n) return hipErrorInvalidValue;
+  const int64_t waves = (n + RPW - 1) / RPW;
+  const dim3 g((unsigned)((waves + 3) / 4), (unsigned)nchunks), b(256);
+  switch (nv) {
+    case 1: hipLaunchKernelGGL(rows_partial_kernel<1>, g, b, 0, s, M, ldm, n, np, V, cw, partial); break;
+    case 2: hipLaunchKernelGGL(rows_partial_kernel<2>, g, b, 0, s, M, ldm, n, np, V, cw, partial); break;
+    case 3: hipLaunchKernelGGL(rows_partial_kernel<3>, g, b, 0, s, M, ldm, n, np, V, cw, partial); break;
+    case 4: hipLaunchKernelGGL(rows_partial_kernel<4>, g, b, 0, s, M, ldm, n, np, V, cw, partial); break;
+    case 5: hipLaunchKernelGGL(rows_partial_kernel<5>, g, b, 0, s, M, ldm, n, np, V, cw, partial); break;
+    case 6: hipLaunchKernelGGL(rows_partial_kernel<6>, g, b, 0, s, M, ldm, n, np, V, cw, partial); break;
+    case 7: hipLaunchKernelGGL(rows_partial_kernel<7>, g, b, 0, s, M, ldm, n, np, V, cw, partial); break;
+    case 8: hipLaunchKernelGGL(rows_partial_kernel<8>, g, b, 0, s, M, ldm, n, np, V, cw, partial); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // rows n .. np - 1 of the partials are never written; the sum covers rows < n only
+  const int64_t tot = n * YCOLS;
+  hipLaunchKernelGGL(cols_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, np, nchunks,
+                     base, alpha, out, tot);
+  return hipGetLastError();
 }
 
 hipError_t launch_cols_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, int64_t np, const double* W,
@@ -289,7 +303,7 @@ hipError_t launch_cols_matvec(hipStream_t s, const double* M, int64_t ldm, int64
   if (e != hipSuccess) return e;
   const int64_t tot = np * YCOLS;
   hipLaunchKernelGGL(cols_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, np, nchunks,
-                     base, alpha, out);
+                     base, alpha, out, tot);
   return hipGetLastError();
 }
 
