@@ -25,14 +25,15 @@ __device__ __forceinline__ bool beats(const Best& a, const Best& b) {
   return a.val > b.val || (a.val == b.val && a.flat < b.flat);
 }
 
-// 1/x: the hardware reciprocal estimate refined by two Newton-Raphson steps
-// (each step squares the relative error), for positive normal x.
+// 1/x for positive normal x: the hardware reciprocal estimate r with a
+// third-order correction. With e = 1 - x r, 1/x = r (1 + e + e^2 + ...); the
+// estimate has |e| <= 2^-24.4 (measured on gfx950 over 1e-300 .. 1e300), so
+// r (1 + e + e^2) leaves a truncation below 2^-72 and is within 1 ulp: the
+// accuracy of two Newton-Raphson steps with one FMA fewer.
 __device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
 constexpr int FPAD = 64;  // padded slots after the grid (invalid), one wave wide
