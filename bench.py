@@ -44,7 +44,9 @@ if ROOT not in sys.path:
 
 # gemm_bf16x3 counts each product once (FP32-equivalent flops); it takes three BF16 products at the
 # 2.5 PFLOP/s dense BF16 peak
-PEAKS = {"gemm_f64": 78.6, "gemm_f32": 157.3, "gemm_bf16x3": 2500.0 / 3, "hbm_gbs": 8000.0}
+# MI355X peaks: dense MFMA per type (TFLOP/s; split BF16 counts its three products as one), FP64 vector ALU
+# (256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz, TFLOP/s) and HBM (GB/s)
+PEAKS = {"gemm_f64": 78.6, "gemm_f32": 157.3, "gemm_bf16x3": 2500.0 / 3, "fp64_alu": 78.6, "hbm_gbs": 8000.0}
 
 
 # the stellar-variability kernel of Section 3.2 at a 2-d rotation period (variance split between the modes,
@@ -159,6 +161,11 @@ def roofline_of(timings):
         achieved = tk["work"] / (tk["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAKS[name], "unit": "TFLOP/s",
                 "frac": achieved / PEAKS[name], "work_unit": "flop (algorithmic)"}
+    elif name == "fold":
+        # FP64 arithmetic on a cache-resident grid: bound by the vector ALU, not HBM
+        achieved = tk["work"] / (tk["ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAKS["fp64_alu"], "unit": "TFLOP/s",
+                "frac": achieved / PEAKS["fp64_alu"], "work_unit": "flop (algorithmic, FP64)"}
     else:
         achieved = tk["work"] / (tk["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",

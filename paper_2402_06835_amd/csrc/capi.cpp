@@ -583,7 +583,7 @@ nu_status nu_periodic_search_segments(nu_ctx* ctx, const double* depth, const do
   int64_t cells = 0;
   for (int s = 0; s < n_seg; ++s) cells += (int64_t)n_d * seg_len_host[s];
   {
-    Timed tm(ctx, "fold", 24.0 * (double)cells * (double)n_p);
+    Timed tm(ctx, "fold", FOLD_FLOPS_PER_VISIT * (double)cells * (double)n_p);
     st = check_hip(ctx, launch_fold_segments(ctx->stream, depth, var, dll, valid, n_d, n_seg, seg_len_host,
                                              seg_off_host, dt, periods, n_p, log_term_sign, q_snr, best_phase,
                                              best_dur, best_depth, best_sigma, best_lnp, ws),

@@ -946,8 +946,8 @@ nu_status run_periodic(nu_ctx* ctx, const double* depth, const double* var, cons
                        double* best_lnp, int64_t* best_period_index, double* ws) {
   nu_status st;
   {
-    // algorithmic bytes: 24 per event visit (depth, var, dll of one interpolated event), n_d * n_epochs per period
-    Timed tm(ctx, "fold", 24.0 * (double)n_d * (double)n_epochs * (double)n_p);
+    // algorithmic flops: FOLD_FLOPS_PER_VISIT per event visit, n_d * n_epochs visits per period
+    Timed tm(ctx, "fold", FOLD_FLOPS_PER_VISIT * (double)n_d * (double)n_epochs * (double)n_p);
     st = check_hip(ctx, launch_fold(ctx->stream, depth, var, dll, valid, n_d, n_epochs, dt, periods, n_p,
                                     log_term_sign, q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp, ws),
                    "fold");

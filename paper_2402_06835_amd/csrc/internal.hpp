@@ -25,6 +25,12 @@ constexpr int TB = 128;
 #define NU_GLOBAL __attribute__((address_space(1)))
 constexpr int MAX_M1 = 7;        // trend columns
 constexpr int YCOLS = 8;         // row stride of the whitened [A | f] panel
+// Algorithmic FP64 flops of the periodic fold per event visit (one event of
+// one (phase, duration) cell; Eq. 8 with the estimates of Eq. B4): linear
+// interpolation of depth, var and dll (3 flops each), the sums of 1/v, d/v and
+// dll (5), and the terms (d - D)^2 / (v + sigma^2) and 1 + sigma^2 / v of the
+// chi^2 and the log product (8).
+constexpr double FOLD_FLOPS_PER_VISIT = 22.0;
 constexpr int MAX_ND = 16;       // durations per search
 constexpr int MAX_DUR = 1024;    // samples per box
 constexpr int MAX_SEG = 32;      // segments of a segmented periodic search

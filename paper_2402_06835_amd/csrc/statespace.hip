@@ -121,12 +121,15 @@ __device__ __forceinline__ double pair_swap(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// 1 / sqrt(s): the hardware estimate and two Newton steps
+// 1 / sqrt(s) for positive normal s: the hardware estimate r with a
+// third-order correction. With h = 1 - s r^2, 1/sqrt(s) = r (1 + h/2 + 3 h^2/8
+// + ...); the estimate has |h| <= 2^-23.2 (measured on gfx950), so the
+// truncation is below 2^-70 and the result within 1.3 ulp, as with two Newton
+// steps but two operations shorter on the dependent chain.
 __device__ __forceinline__ double rsqrt_nr(double s) {
-  double r = __builtin_amdgcn_rsq(s);
-  const double h = 0.5 * s;
-  r = fma(r, fma(-h * r, r, 0.5), r);
-  return fma(r, fma(-h * r, r, 0.5), r);
+  const double r = __builtin_amdgcn_rsq(s);
+  const double h = fma(-s * r, r, 1.0);
+  return fma(r * h, fma(h, 0.375, 0.5), r);
 }
 
 // The sequential kernels take their per-sample records from LDS, staged one
