@@ -78,6 +78,11 @@ LINEAR_CASES = [
     ("N700-m3-gap", dict(n=700, m1=3, durs=[1, 4, 9, 17], gap=(333, 25))),
     ("N300-m2-Qhalf", dict(n=300, m1=2, durs=[3, 7], q=0.5)),
     ("N300-m3-Qlow", dict(n=300, m1=3, durs=[3, 7], q=0.3)),
+    # one past the column chunk of the row products (2048) and of the row chunks of the
+    # transposed products (512) and of the box sums (256)
+    ("N2049-m3-gap", dict(n=2049, m1=3, durs=[1, 6, 40], gap=(1024, 30), seed=2)),
+    # several chunks of each, with a last chunk of 4 rows / columns
+    ("N4100-m3", dict(n=4100, m1=3, durs=[2, 13, 64], seed=3)),
 ]
 
 
