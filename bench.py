@@ -18,7 +18,7 @@ Default precision: FP32_REFINE (FP64 Cholesky, FP32 inverse products with an
 FP64 band Newton step and one refinement step), the fastest path that meets
 the 1e-6 dll bar; its dll error against the FP64 path on the same curve is
 measured after the timed region and reported. The FP32 inverse is started
-inside the factorisation (the context's inverse prefetch: its leading half
+inside the factorisation (the context's inverse prefetch: its early phases
 on three quarters of the CUs beside the late, latency-bound Cholesky steps;
 bit-identical results). Other modes:
   --inverse-prefetch off  the inverse after the factorisation, inside linear_search

@@ -119,9 +119,10 @@ const char* nu_ctx_last_error(const nu_ctx* ctx);
 /* Inverse prefetch. prec = NU_FP32_REFINE or NU_BF16X3_REFINE: every later
  * nu_gp_factor / nu_gp_factor_kernel on this context also computes the
  * factor's triangular inverse L^-1 at that precision (the one the linear
- * search of Section 2.2 applies to f and the design columns), starting its
- * leading half (the inverse of the top-left block of L and its product with
- * the block below) while the Cholesky factors the remaining columns, on
+ * search of Section 2.2 applies to f and the design columns), starting the
+ * parts that read only finished columns of L (the inverse of its top-left
+ * half and that half's product with the block below, then the same one level
+ * down in the bottom-right half) while the Cholesky factors the rest, on
  * compute_units of the device's compute units (0: three quarters of them;
  * rounded to whole XCDs of 32), which the late, latency-bound steps leave
  * idle. A linear search at prec then finds

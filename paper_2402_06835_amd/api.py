@@ -87,7 +87,7 @@ class Context:
     def set_inverse_prefetch(self, precision: Optional[str], compute_units: int = 0):
         """Compute the factor's reduced-precision inverse inside every later
         ``gp_factor`` ("fp32_refine" or "bf16x3_refine"; None turns it off), its
-        leading half on ``compute_units`` CUs beside the factorisation (0: three quarters of the chip)."""
+        early phases on ``compute_units`` CUs beside the factorisation (0: three quarters of the chip)."""
         if precision is not None and precision not in ("fp32_refine", "bf16x3_refine"):
             raise ValueError("inverse prefetch is for fp32_refine or bf16x3_refine")
         code = -1 if precision is None else PRECISIONS[precision]

@@ -189,7 +189,7 @@ namespace {
 // K build (from the uploaded theta or kernel), blocked Cholesky, ln|K|;
 // synchronises once for the status. With an inverse precision set on the
 // context (nu_ctx_set_inverse_prefetch), the factor's reduced-precision
-// inverse for it is computed here too, its leading half inside the
+// inverse for it is computed here too, its early phases inside the
 // factorisation.
 nu_status factor_run(nu_ctx* ctx, nu_factor* F, const double* t, double* logdet_host, int64_t* fail_pivot_host) {
   std::vector<nu_factor*> one{F};
@@ -202,9 +202,14 @@ nu_status factor_run(nu_ctx* ctx, nu_factor* F, const double* t, double* logdet_
     st = ensure_plan32(ctx, F, early.prec);
   }
   if (st == NU_OK) st = run_factor(ctx, one, F->plan64, {t}, {F->theta_dev()}, prefetch ? &early : nullptr);
-  if (st == NU_OK && prefetch)
-    st = early.started ? run_inverse_post(ctx, F, F->plan32, early.prec)
-                       : run_inverse_mixed(ctx, one, F->plan32, early.prec);
+  if (st == NU_OK && prefetch) {
+    // the phases the factorisation did not start, then the last one
+    for (int k = early.started; st == NU_OK && k + 1 < (int)F->plan32.phases.size(); ++k)
+      st = run_inverse_phase(ctx, F, F->plan32, early.prec, k, ctx->stream);
+    if (st == NU_OK)
+      st = F->plan32.phases.empty() ? run_inverse_mixed(ctx, one, F->plan32, early.prec)
+                                    : run_inverse_post(ctx, F, F->plan32, early.prec);
+  }
   std::vector<int64_t> status;
   if (st == NU_OK) st = read_factor_status(ctx, one, status);
   if (st != NU_OK) return st;

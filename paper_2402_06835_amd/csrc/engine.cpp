@@ -181,14 +181,39 @@ void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P)
 // for the node [[A, 0], [L21, C]], T = L21 X_A then X21 = -X_C T. Leaves are
 // the diagonal-block inverses. Level e of every factor runs in one launch.
 //
-// T layout: the root's T at offset 0 and every other node past it (the nodes
-// of one level side by side; levels run one after another). The root's T then
-// survives from its first product to its second, so a single factor's plan can
-// split (split = true) into the leading half of the tree [0, mid) plus the
-// root's first product, which need only the factor's columns left of mid, and
-// the trailing half plus the root's second product.
+// A single factor's plan can split (split = true) into phases by the columns
+// of L they read. The split path is the root and its trailing children, up to
+// SPLIT_DEPTH nodes P_0, P_1, ...; phase k holds the leading half of P_k's
+// subtree and P_k's first product (columns left of P_k.mid), the last phase
+// the rest: the trailing half of the deepest path node and every path node's
+// second product, deepest first. Phase k can thus start as soon as the
+// factorisation has finished the columns left of P_k.mid.
+//
+// T layout: the path nodes' T first (each survives from its first product to
+// its second), then the other nodes, one level at a time (the nodes of a level
+// side by side). Without a split the root alone takes the first place.
 namespace {
 size_t node_elems(const Node& nd) { return (size_t)(nd.mid - nd.a) * TB * (size_t)(nd.b - nd.mid) * TB; }
+constexpr int SPLIT_DEPTH = 2;
+
+// the split path of a factor's inverse tree (levels deepest first)
+std::vector<Node> split_path(const std::vector<std::vector<Node>>& levels) {
+  std::vector<Node> path;
+  if (levels.empty()) return path;
+  path.push_back(levels.back()[0]);
+  for (int k = 1; k < SPLIT_DEPTH && (int)levels.size() > k; ++k) {
+    const Node cur = path.back();
+    bool found = false;
+    for (const Node& nd : levels[levels.size() - 1 - k])
+      if (nd.a == cur.mid && nd.b == cur.b) {
+        path.push_back(nd);
+        found = true;
+        break;
+      }
+    if (!found) break;
+  }
+  return path;
+}
 }  // namespace
 
 void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu, Plan& P, bool split) {
@@ -203,9 +228,8 @@ void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu,
   const int cls = kind == GK_F64 ? TC_INV64 : kind == GK_F32 ? TC_INV32 : TC_INVB;
   P.t1.clear();
   P.t2.clear();
-  P.pre.clear();
-  P.post.clear();
-  P.split = 0;
+  P.phases.clear();
+  P.cuts.clear();
   // the products of one node: T = L21 X_A, X21 = -X_C T
   auto node_probs = [&](nu_factor* F, const Node& nd, size_t off_t, std::vector<GemmProblem>& p1,
                         std::vector<GemmProblem>& p2) {
@@ -222,27 +246,44 @@ void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu,
   if (split && Fs.size() == 1 && nlev >= 1) {
     nu_factor* F = Fs[0];
     const auto& levels = lv[0];
-    const Node root = levels.back()[0];
-    const size_t root_elems = node_elems(root);
-    P.split = root.mid;
-    for (int half = 0; half < 2; ++half) {
-      std::vector<Range>& out = half == 0 ? P.pre : P.post;
-      for (size_t e = 0; e + 1 < levels.size(); ++e) {
-        std::vector<GemmProblem> p1, p2;
-        size_t off_t = root_elems;
-        for (const Node& nd : levels[e]) {
-          const bool lead = nd.b <= root.mid;
-          if (lead == (half == 0)) node_probs(F, nd, off_t, p1, p2);
-          off_t += node_elems(nd);
+    const std::vector<Node> path = split_path(levels);
+    const int D = (int)path.size();
+    std::vector<size_t> path_off(D);
+    size_t shared = 0;
+    for (int k = 0; k < D; ++k) {
+      path_off[k] = shared;
+      shared += node_elems(path[k]);
+      P.cuts.push_back(path[k].mid);
+    }
+    P.cuts.push_back(F->nblk);
+    P.phases.assign(D + 1, {});
+    for (size_t e = 0; e < levels.size(); ++e) {
+      std::vector<std::vector<GemmProblem>> p1(D + 1), p2(D + 1);
+      size_t off_t = shared;
+      for (const Node& nd : levels[e]) {
+        int pk = -1;
+        for (int k = 0; k < D; ++k)
+          if (nd.a == path[k].a && nd.b == path[k].b) pk = k;
+        if (pk >= 0) {  // first product in phase pk, second in the last phase
+          std::vector<GemmProblem> t1, t2;
+          node_probs(F, nd, path_off[pk], t1, t2);
+          p1[pk].insert(p1[pk].end(), t1.begin(), t1.end());
+          p2[D].insert(p2[D].end(), t2.begin(), t2.end());
+          continue;
         }
-        if (!p1.empty()) {
-          out.push_back(add_launch(P.sched, p1, tu.small_below[cls]));
-          out.push_back(add_launch(P.sched, p2, tu.small_below[cls]));
-        }
+        int ph = D;
+        for (int k = 0; k < D; ++k)
+          if (nd.b <= path[k].mid) {
+            ph = k;
+            break;
+          }
+        node_probs(F, nd, off_t, p1[ph], p2[ph]);
+        off_t += node_elems(nd);
       }
-      std::vector<GemmProblem> r1, r2;
-      node_probs(F, root, 0, r1, r2);
-      out.push_back(add_launch(P.sched, half == 0 ? r1 : r2, tu.small_below[cls]));
+      for (int ph = 0; ph <= D; ++ph) {
+        if (!p1[ph].empty()) P.phases[ph].push_back(add_launch(P.sched, p1[ph], tu.small_below[cls]));
+        if (!p2[ph].empty()) P.phases[ph].push_back(add_launch(P.sched, p2[ph], tu.small_below[cls]));
+      }
     }
     return;
   }
@@ -262,16 +303,29 @@ void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu,
   }
 }
 
+// room for either layout: the root, then the widest other level; or the split
+// path's nodes, then the widest level of the other nodes
 size_t inverse_t_elems(int nblk) {
   const auto levels = inverse_levels(nblk);
   if (levels.empty()) return 1;
-  size_t other = 0;
-  for (size_t e = 0; e + 1 < levels.size(); ++e) {
-    size_t s = 0;
-    for (const Node& nd : levels[e]) s += node_elems(nd);
+  const std::vector<Node> path = split_path(levels);
+  auto on_path = [&](const Node& nd) {
+    for (const Node& p : path)
+      if (p.a == nd.a && p.b == nd.b) return true;
+    return false;
+  };
+  size_t fixed = 0, other = 0, other_split = 0;
+  for (const Node& nd : path) fixed += node_elems(nd);
+  for (size_t e = 0; e < levels.size(); ++e) {
+    size_t s = 0, s_split = 0;
+    for (const Node& nd : levels[e]) {
+      if (e + 1 < levels.size()) s += node_elems(nd);
+      if (!on_path(nd)) s_split += node_elems(nd);
+    }
     other = std::max(other, s);
+    other_split = std::max(other_split, s_split);
   }
-  return node_elems(levels.back()[0]) + other;
+  return std::max(node_elems(levels.back()[0]) + other, fixed + other_split);
 }
 
 // One Newton step X1 = 2 X - X (L X) on the blocks within w of the
@@ -592,13 +646,13 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
   // A step whose diagonal blocks outnumber the free CUs (a batch: one block
   // per curve) would queue them behind the update's tiles; it stays serial.
   //
-  // Early inverse (early != nullptr, lookahead only): once step split - 1 has
-  // factored its panel, the columns left of the inverse plan's split point are
-  // final, and the leading half of the reduced-precision inverse runs on
-  // s_inv (part of the chip, see ensure_inverse_stream) beside the remaining steps, which from there
-  // on are bound by the chain of diagonal blocks and leave most of the chip
-  // idle. It writes only the factor's FP32 copies and T, which no step reads.
-  // The join waits for it; the caller then enqueues the rest of the inverse.
+  // Early inverse (early != nullptr, lookahead only): once step cuts[k] - 1
+  // has factored its panel, the columns left of cuts[k] are final, and phase
+  // k of the split reduced-precision inverse runs on s_inv (part of the chip,
+  // see ensure_inverse_stream) beside the remaining steps, which from the
+  // middle on are bound by the chain of diagonal blocks and leave most of the
+  // chip idle. The phases write only the factor's FP32 copies and T, which no
+  // step reads. The join waits for them; the caller then enqueues the rest.
   hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
   if (st == NU_OK) st = check_hip(ctx, hipStreamIsCapturing(ctx->stream, &capturing), "capture status");
   int max_jobs = 0;
@@ -615,10 +669,12 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
   }
   bool rest_pending = false, inv_pending = false;
   const int steps = (int)P.job_first.size();
-  const int early_step = la && early && ctx->s_inv && early->F->plan32.built && early->F->plan32_prec == early->prec &&
-                                 early->F->plan32.split > 0 && early->F->plan32.split <= steps
-                             ? early->F->plan32.split - 1
-                             : -1;
+  // the early phases of the inverse and the steps that release them
+  const bool early_ok = la && early && ctx->s_inv && early->F->plan32.built && early->F->plan32_prec == early->prec &&
+                        early->F->plan32.phases.size() >= 2;
+  const int early_phases = early_ok ? (int)early->F->plan32.phases.size() - 1 : 0;
+  int next_phase = 0;
+  if (early) early->started = 0;
   for (int k = 0; st == NU_OK && k < steps; ++k) {
     {
       Timed tm(ctx, sf, "potrf_diag", (double)P.job_count[k] * TB * TB * TB * 2.0 / 3.0);
@@ -626,12 +682,15 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
     }
     if (st == NU_OK) st = launch_range(ctx, P, P.panel[k], "gemm_f64:panel", GK_F64, sf);
     if (st == NU_OK) st = launch_range(ctx, P, P.pupd[k], "gemm_f64:panel_update", GK_F64, sf);
-    if (st == NU_OK && k == early_step) {
+    while (st == NU_OK && next_phase < early_phases && k == early->F->plan32.cuts[next_phase] - 1) {
       st = check_hip(ctx, hipEventRecord(ctx->ev_split, sf), "early inverse");
       if (st == NU_OK) st = check_hip(ctx, hipStreamWaitEvent(ctx->s_inv, ctx->ev_split, 0), "early inverse");
-      if (st == NU_OK) st = run_inverse_pre(ctx, early->F, early->F->plan32, early->prec, ctx->s_inv);
+      if (st == NU_OK) st = run_inverse_phase(ctx, early->F, early->F->plan32, early->prec, next_phase, ctx->s_inv);
       if (st == NU_OK) st = check_hip(ctx, hipEventRecord(ctx->ev_inv, ctx->s_inv), "early inverse");
-      inv_pending = st == NU_OK;
+      if (st == NU_OK) {
+        inv_pending = true;
+        early->started = ++next_phase;
+      }
     }
     if (st != NU_OK || (P.next[k].tiles == 0 && P.rest[k].tiles == 0)) continue;
     if (!la) {
@@ -658,7 +717,7 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
     if (sj == NU_OK && inv_pending) sj = check_hip(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_inv, 0), "join");
     if (st == NU_OK) st = sj;
   }
-  if (early) early->started = st == NU_OK && inv_pending;
+  if (early && st != NU_OK) early->started = 0;
   for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i)
     st = check_hip(ctx, launch_logdet_reduce(ctx->stream, Fs[i]->parts(), Fs[i]->nblk, Fs[i]->logdet_dev()),
                    "logdet");
@@ -691,39 +750,31 @@ nu_status run_inverse_fp64(nu_ctx* ctx, const Plan& P) {
   return st;
 }
 
-// Leading half of a split inverse (see plan_inverse) on stream s: the FP32
-// copies of the factor's columns left of the split and of their diagonal
-// blocks, then the leading subtree and the root's first product. It reads
-// only columns the factorisation has finished by its step split - 1.
-nu_status run_inverse_pre(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec, hipStream_t s) {
+// Phase k < last of a split inverse (see plan_inverse) on stream s: the FP32
+// copies of the factor's columns [cuts[k - 1], cuts[k]) and of their diagonal
+// blocks, then the phase's products. It reads only columns left of cuts[k],
+// which the factorisation has finished by its step cuts[k] - 1.
+nu_status run_inverse_phase(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec, int k, hipStream_t s) {
   const int kind = gemm_kind_of(prec);
   const char* level_name = kind == GK_BF16X3 ? "gemm_bf16x3:inverse" : "gemm_f32:inverse";
+  const int c0 = k > 0 ? P.cuts[k - 1] : 0, c1 = P.cuts[k];
   nu_status st;
   {
     Timed tm(ctx, s, "convert", 0.0);
-    st = check_hip(ctx, launch_cvt_f64_f32(s, F->L, F->L32, F->np, 0, 0, P.split), "convert L");
-    if (st == NU_OK) st = check_hip(ctx, launch_cvt_f64_f32(s, F->X, F->X32, F->np, 1, 0, P.split), "convert X diag");
+    st = check_hip(ctx, launch_cvt_f64_f32(s, F->L, F->L32, F->np, 0, c0, c1), "convert L");
+    if (st == NU_OK) st = check_hip(ctx, launch_cvt_f64_f32(s, F->X, F->X32, F->np, 1, c0, c1), "convert X diag");
   }
-  for (size_t r = 0; st == NU_OK && r < P.pre.size(); ++r) st = launch_range(ctx, P, P.pre[r], level_name, kind, s);
+  for (size_t r = 0; st == NU_OK && r < P.phases[k].size(); ++r)
+    st = launch_range(ctx, P, P.phases[k][r], level_name, kind, s);
   return st;
 }
 
-// The rest of a split inverse on the context's stream: the remaining FP32
-// copies, the trailing subtree and the root's second product, then the FP64
-// copy and the band step.
+// The last phase of a split inverse on the context's stream (the phases
+// before it enqueued already), then the FP64 copy and the band step.
 nu_status run_inverse_post(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec) {
-  const int kind = gemm_kind_of(prec), w = band_width(prec);
-  const char* level_name = kind == GK_BF16X3 ? "gemm_bf16x3:inverse" : "gemm_f32:inverse";
+  const int w = band_width(prec);
   if (F->band_w < w) return set_error(ctx, NU_ERR_ARG, "inverse: band buffers narrower than the precision needs");
-  nu_status st;
-  {
-    Timed tm(ctx, "convert", 0.0);
-    st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->L, F->L32, F->np, 0, P.split, F->nblk), "convert L");
-    if (st == NU_OK)
-      st = check_hip(ctx, launch_cvt_f64_f32(ctx->stream, F->X, F->X32, F->np, 1, P.split, F->nblk),
-                     "convert X diag");
-  }
-  for (size_t r = 0; st == NU_OK && r < P.post.size(); ++r) st = launch_range(ctx, P, P.post[r], level_name, kind);
+  nu_status st = run_inverse_phase(ctx, F, P, prec, (int)P.phases.size() - 1, ctx->stream);
   if (st == NU_OK) {
     Timed tm(ctx, "convert", 0.0);
     st = check_hip(ctx, launch_cvt_f32_f64(ctx->stream, F->X32, F->X, F->np), "convert X");
@@ -741,8 +792,10 @@ nu_status run_inverse_post(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec) {
 // products of every factor in Fs (their reduced-precision buffers allocated
 // for prec); a single factor's split plan runs its two halves in turn.
 nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P, int prec) {
-  if (P.split > 0 && Fs.size() == 1) {
-    nu_status st = run_inverse_pre(ctx, Fs[0], P, prec, ctx->stream);
+  if (!P.phases.empty() && Fs.size() == 1) {
+    nu_status st = NU_OK;
+    for (int k = 0; st == NU_OK && k + 1 < (int)P.phases.size(); ++k)
+      st = run_inverse_phase(ctx, Fs[0], P, prec, k, ctx->stream);
     return st == NU_OK ? run_inverse_post(ctx, Fs[0], P, prec) : st;
   }
   const int kind = gemm_kind_of(prec), w = band_width(prec);

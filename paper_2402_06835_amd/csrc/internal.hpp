@@ -192,11 +192,11 @@ struct Plan {
   std::vector<Range> next, rest;          // per step: the trailing update after a panel's last block, split
                                           // into the next panel's columns and the rest
   std::vector<Range> t1, t2;              // per inverse level, deepest first
-  // a single factor's inverse split at the root's middle block `split`: the
-  // launches of the leading half (and the root's first product), then of the
-  // rest (and the root's second product); split = 0: t1/t2 instead
-  std::vector<Range> pre, post;
-  int split = 0;
+  // a single factor's inverse split into phases by the columns they read
+  // (phase k: columns left of cuts[k]; the last: all), each a list of
+  // launches; empty: t1/t2 instead
+  std::vector<std::vector<Range>> phases;
+  std::vector<int> cuts;
   Range bandp, bandx;
   bool built = false;
 };
@@ -296,12 +296,12 @@ nu_status ensure_factor_streams(nu_ctx* ctx);
 nu_status ensure_inverse_stream(nu_ctx* ctx, int compute_units);
 void destroy_factor_streams(nu_ctx* ctx);
 // The reduced-precision inverse of a single factor started inside its
-// factorisation: the leading half as soon as the Cholesky has finished the
-// columns it reads, beside the remaining steps, the rest after them.
+// factorisation: each early phase as soon as the Cholesky has finished the
+// columns it reads, beside the remaining steps, the last phase after them.
 struct EarlyInverse {
   nu_factor* F = nullptr;
-  int prec = 0;                  // NU_FP32_REFINE or NU_BF16X3_REFINE; F->plan32 is built for it
-  mutable bool started = false;  // out: the leading half was enqueued (run_inverse_post is due)
+  int prec = 0;              // NU_FP32_REFINE or NU_BF16X3_REFINE; F->plan32 is built for it
+  mutable int started = 0;   // out: the early phases enqueued (the rest is due)
 };
 nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P,
                      const std::vector<const double*>& ts, const std::vector<const nu_sho*>& theta_dev,
@@ -309,7 +309,7 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
 nu_status read_factor_status(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, std::vector<int64_t>& status);
 nu_status run_inverse_fp64(nu_ctx* ctx, const Plan& P);
 nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P, int prec);
-nu_status run_inverse_pre(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec, hipStream_t s);
+nu_status run_inverse_phase(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec, int k, hipStream_t s);
 nu_status run_inverse_post(nu_ctx* ctx, nu_factor* F, const Plan& P, int prec);
 size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs);
 nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double* A, int m1, const int64_t* lattice,
