@@ -304,6 +304,9 @@ def bench_two_sectors(args, api, ctx, torch):
     per = torch.as_tensor(ws[0].periods, device=dev)
     dt, durs = ws[0].dt, ws[0].durations
     facs = [None, None]
+    prefetch = args.inverse_prefetch == "on" and args.precision != "fp64"
+    if prefetch:
+        ctx.set_inverse_prefetch(args.precision, args.prefetch_cus)
 
     def one_step(precision):
         grids = []
@@ -332,6 +335,7 @@ def bench_two_sectors(args, api, ctx, torch):
     best = int(ps["best_index"].item())
     err = None
     if args.precision != "fp64" and not args.no_dll_check:
+        ctx.set_inverse_prefetch(None)
         ref_grids, ref_ps = one_step("fp64")
         got = {k: torch.cat([g[k].reshape(-1) for g in grids]) for k in ("depth", "var", "dll", "valid")}
         ref = {k: torch.cat([g[k].reshape(-1) for g in ref_grids]) for k in ("depth", "var", "dll", "valid")}
@@ -345,6 +349,8 @@ def bench_two_sectors(args, api, ctx, torch):
     cfg = {"workload": "two-tess-sectors-N2x18000-gap1yr", "sectors": 2, "n_samples": [w.n for w in ws],
            "offsets_slots": offs, "n_durations": int(len(durs)), "n_periods": int(len(ws[0].periods)),
            "valid_cells": n_valid, "precision": args.precision, "mode": "eager"}
+    if prefetch:
+        cfg["inverse_prefetch_cus"] = args.prefetch_cus
     extra = {"best_period_days": float(ws[0].periods[best]) if best >= 0 else None, "injected_period_days": p_true,
              "best_t0_days": float(ps["best_phase"][best].item()) * dt if best >= 0 else None,
              "injected_t0_days": float(ws[0].injection["global_t0"])}
