@@ -360,7 +360,7 @@ def bench_two_sectors(args, api, ctx, torch):
 def bench_learned(args, api, ctx, torch):
     """The learned warm start at the TESS-sector shape: 100000 training curves drawn from the
     GP on the device, the CNN trained on them, then 256 held-out curves fitted by BFGS from the
-    plain start and from the learned one (the judge: the best optimum of those and the true start)."""
+    plain start and from the learned one (the reference: the best optimum of those and of the true start)."""
     import numpy as np
     dt = 2 / 1440
     t = np.arange(18000) * dt

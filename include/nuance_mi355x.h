@@ -40,7 +40,7 @@ typedef enum {
   NU_ERR_NOT_PD = 2,      /* covariance not positive definite (pivot reported) */
   NU_ERR_OOM = 3,         /* device allocation failed */
   NU_ERR_DEVICE = 4,      /* a HIP call or kernel launch failed */
-  NU_ERR_UNSUPPORTED = 5  /* valid request this build does not implement */
+  NU_ERR_UNSUPPORTED = 5  /* valid request the library does not implement */
 } nu_status;
 
 /* Arithmetic of the bulk whitening solve of the linear search (the triangular

@@ -29,7 +29,7 @@ This module writes out, in FP64 and in plain loops:
 * ``nll_dense`` / ``nll_kalman``: the negative log-likelihood of Eq. 5 for
   the trend-only model with the trend profiled, by the dense Cholesky and by
   the Kalman filter's prediction-error decomposition;
-* ``plain_init`` and ``fit_bfgs``: the plain fit that judges the warm start,
+* ``plain_init`` and ``fit_bfgs``: the plain fit that checks the warm start,
   a Lomb-Scargle period with moment estimates, then BFGS (SciPy).
 
 Readings (the paper gives no network or sampler): listed in the design
@@ -372,7 +372,7 @@ def nll_kalman(t, f, A, theta: dict) -> float:
 
 
 # ---------------------------------------------------------------------------
-# The plain fit (fallback and judge)
+# The plain fit (fallback and check)
 # ---------------------------------------------------------------------------
 
 def plain_init(t, f, prot_grid) -> dict:

@@ -256,7 +256,7 @@ def test_cnn_training_reduces_the_loss(api, ctx):
 def test_learned_warm_start_gain(api, ctx):
     """What the trained network gains over the plain start, at the TESS-sector shape:
     the network is trained on the GPU on 100000 curves drawn from the GP, then both
-    starts seed the same BFGS fit on 128 held-out curves. The judge is the best optimum
+    starts seed the same BFGS fit on 128 held-out curves. The reference is the best optimum
     found from the plain, learned and true starts."""
     import torch
     dt = 2 / 1440
