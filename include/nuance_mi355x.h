@@ -247,7 +247,8 @@ nu_status nu_linear_search_template(nu_ctx* ctx, nu_factor* factor, const double
  * best_depth, best_sigma, best_lnp. A period without any event has
  * q_snr = 0, best_phase = best_dur = -1, best_lnp = -inf.
  * best_period_index: device, 1 int64 or NULL: the first period of largest
- * q_snr (-1 if n_p == 0 is impossible; n_p >= 1 is required). */
+ * q_snr (period 0 when no period has an event, all q_snr being 0).
+ * n_p >= 1 is required. */
 nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var, const double* dll,
                              const uint8_t* valid, int n_d, int64_t n_epochs, double dt, const double* periods,
                              int64_t n_p, int log_term_sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,
