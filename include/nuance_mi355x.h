@@ -246,6 +246,9 @@ nu_status nu_linear_search_template(nu_ctx* ctx, nu_factor* factor, const double
  * gives per period: q_snr = depth/sigma, best_phase m, best_dur j,
  * best_depth, best_sigma, best_lnp. A period without any event has
  * q_snr = 0, best_phase = best_dur = -1, best_lnp = -inf.
+ * A period shorter than one cadence (p < 1) or not finite (NaN, +-inf) has
+ * no event: the phase grid steps by one cadence, and several transits would
+ * fall into one lattice step.
  * best_period_index: device, 1 int64 or NULL: the first period of largest
  * q_snr (period 0 when no period has an event, all q_snr being 0).
  * n_p >= 1 is required. */

@@ -34,7 +34,13 @@ Readings (the paper is silent or inconsistent on these):
   of phase m is t_first + m dt;
 * argmax order is phase outer, duration inner, and the first maximum wins
   (strict >); NaN never wins; with no valid cell Q = 0 and indices are -1;
-* sums over events run in increasing k.
+* sums over events run in increasing k;
+* a trial period shorter than one cadence (p < 1), or not finite, has no
+  event: Section 2.3 places one phase grid step of one cadence under every
+  period, and a period below it would put several transits into one
+  lattice step;
+* phases at or beyond the last slot hold no event (their k = 0 event is
+  already past the grid), so only phases below n_T are formed.
 """
 from __future__ import annotations
 
@@ -62,7 +68,11 @@ def fold_period(depth, var, dll, valid, dt: float, period: float, sign: int = 1)
     period. Returns (lnp, dep, sig2, nev) each shaped [n_phase, n_d]."""
     n_d, n_t = depth.shape
     p = period / dt
-    n_ph = int(math.ceil(p))
+    if not (math.isfinite(p) and p >= 1.0):
+        # no phase grid below one cadence: no event, no cell
+        z = np.zeros((0, n_d))
+        return z, z.copy(), z.copy(), np.zeros((0, n_d), dtype=np.int64)
+    n_ph = min(int(math.ceil(p)), n_t)
     m = np.arange(n_ph)
     ok = valid.astype(bool)
     ev = _events(n_t, p)

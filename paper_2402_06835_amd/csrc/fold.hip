@@ -281,8 +281,9 @@ __global__ __launch_bounds__(256, 3) void fold_kernel(const double2* __restrict_
   const double P = periods[ip];
   const double p = P / dt;
   Best best{-INFINITY, -1, 0.0, 0.0};
-  // periods below one cadence or absurdly long are reported as having no event
-  if (p >= 1.0 && p <= 1e15) {
+  // a period below one cadence (p < 1), or not finite, has no event: the
+  // phase grid steps by one cadence (Section 2.3)
+  if (p >= 1.0 && p < INFINITY) {
     const double nph_d = ceil(p);
     const int64_t nph = nph_d < (double)n_t ? (int64_t)nph_d : n_t;  // phases >= n_t hold no event
     for (int64_t mb = (int64_t)wave * WPH; mb < nph; mb += 4 * WPH)

@@ -254,18 +254,30 @@ def test_argument_errors_enqueue_nothing(api, ctx):
         api.periodic_search(ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], w.dt, [1.0], sign=0)
 
 
-def test_periods_below_one_cadence_have_no_event(api, ctx):
+def test_periods_at_and_below_one_cadence_match_the_oracle(api, ctx):
+    """Section 2.3's phase grid at its edge: a period below one cadence (p < 1) or
+    not finite has no event on both sides; p = 1 folds every slot into phase 0;
+    a period far beyond the grid leaves single events."""
     import torch
-    w = _case(n=64, m1=1, durs=[2])
-    say("period below one cadence")
+    w = _case(n=64, m1=1, durs=[2, 3])
+    say("periods at and below one cadence, against the oracle")
     fac = api.gp_factor(ctx, w.t, w.theta)
     ls = api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations)
-    ps = api.periodic_search(ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], w.dt,
-                             [0.5 * w.dt, float("nan"), 3 * w.dt])
-    torch.cuda.synchronize()
-    g = _fold_host(ps)
-    assert g["best_phase"][0] == -1 and g["q_snr"][0] == 0 and g["best_phase"][1] == -1
-    assert g["best_phase"][2] >= 0
+    periods = np.array([0.5 * w.dt, w.dt, float("nan"), float("inf"), -w.dt, 0.0, 1.5 * w.dt, 3 * w.dt,
+                        1e20 * w.dt, 0.999999 * w.dt])
+    for sign in (1, -1):
+        ps = api.periodic_search(ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], w.dt, periods, sign=sign)
+        torch.cuda.synchronize()
+        g = _fold_host(ps)
+        h = _host(ls)
+        ref = oper.periodic_search(h["depth"], h["var"], h["dll"], h["valid"], w.dt, periods, sign)
+        for k in ("best_phase", "best_dur"):
+            np.testing.assert_array_equal(g[k], ref[k], err_msg=k)
+        for k in ("q_snr", "best_depth", "best_sigma", "best_lnp"):
+            np.testing.assert_allclose(g[k], ref[k], rtol=1e-12, atol=0, err_msg=k)
+        none = [0, 2, 3, 4, 5, 9]
+        assert np.all(g["best_phase"][none] == -1) and np.all(g["q_snr"][none] == 0)
+        assert np.all(g["best_phase"][[1, 6, 7, 8]] >= 0)
 
 
 def test_deterministic(api, ctx):

@@ -186,3 +186,63 @@ def test_bfgs_optimum_is_stationary_and_beats_the_truth():
     assert res.fun <= ol.nll_kalman(t, f, A, th) + 1e-9
     g = scipy.optimize.approx_fprime(res.x, lambda x: ol.nll_kalman(t, f, A, ol.theta_from_x(x)), 1e-6)
     assert np.max(np.abs(g)) < 1e-2
+
+
+# ---------------------------------------------------------------------------
+# The plain start (Section 3.3: the rotation period from a Lomb-Scargle
+# periodogram; amp and sigma_w from the curve's moments). Each part is pinned
+# to a closed form or a sampling law, not to the formula it uses.
+
+def test_plain_init_sigma_w_closed_forms():
+    """Second differences of a sampled polynomial on a uniform grid of step h:
+    zero for a line, 2 c h^2 everywhere for c t^2, so the white-noise level is
+    exactly 2 c h^2 / sqrt(6) and 0 (up to rounding)."""
+    h = 2.0 / 1440
+    t = np.arange(5000) * h
+    grid = np.linspace(0.3, 2.0, 50)
+    line = ol.plain_init(t, 1.0 + 3e-3 * t, grid)
+    assert line["sigma_w"] <= 1e-14
+    c = 4e-4
+    quad = ol.plain_init(t, 1.0 + c * t * t, grid)
+    assert quad["sigma_w"] == pytest.approx(2.0 * c * h * h / math.sqrt(6.0), rel=1e-6)
+    assert quad["q"] == 5.0 and line["q"] == 5.0
+
+
+def test_plain_init_amp_of_a_sinusoid_over_whole_cycles():
+    """Discrete orthogonality: N equally spaced samples over c whole cycles
+    (2c not a multiple of N) of a sin(2 pi c n / N + phi) have mean 0 and mean
+    square a^2 / 2, so the amplitude estimate is exactly a / sqrt(2)."""
+    n, cycles, a = 3000, 7, 0.02
+    idx = np.arange(n)
+    t = idx * (10 / 1440)
+    f = 1.0 + a * np.sin(2 * np.pi * cycles * idx / n + 0.4)
+    out = ol.plain_init(t, f, np.linspace(0.3, 5.0, 100))
+    assert out["amp"] == pytest.approx(a / math.sqrt(2.0), rel=1e-12)
+
+
+def test_plain_init_sigma_w_of_white_noise_within_its_sampling_law():
+    """On white noise of sigma, d_n = e_n - 2 e_{n+1} + e_{n+2} has variance
+    6 sigma^2; the squares have variance 72 sigma^4 and lag-1 and lag-2
+    covariances 32 and 2 sigma^4, so mean(d^2) has relative standard error
+    sqrt(140 / N) / 6 and its square root half that. The estimate must lie
+    within five standard errors of sigma."""
+    n, sigma = 200000, 1.3e-3
+    rng = np.random.default_rng(17)
+    t = np.arange(n) * (2 / 1440)
+    f = 1.0 + sigma * rng.standard_normal(n)
+    out = ol.plain_init(t, f, np.linspace(0.3, 2.0, 20))
+    se = 0.5 * math.sqrt(140.0 / (n - 2)) / 6.0
+    assert abs(out["sigma_w"] / sigma - 1.0) < 5.0 * se
+
+
+@pytest.mark.parametrize("p_true", [0.45, 1.2, 3.3])
+def test_plain_init_lomb_scargle_finds_a_noiseless_rotation_on_the_grid(p_true):
+    """A noiseless sinusoid whose period is a grid point, sampled with a gap:
+    the periodogram's first maximum is that grid point."""
+    t = np.arange(9000) * (2 / 1440)
+    t = np.concatenate([t[:4000], t[4700:]])
+    grid = np.linspace(0.3, 4.0, 371)
+    p = grid[np.argmin(np.abs(grid - p_true))]
+    f = 1.0 + 0.01 * np.sin(2 * np.pi * t / p + 1.1)
+    out = ol.plain_init(t, f, grid)
+    assert out["prot"] == p

@@ -109,9 +109,15 @@ def test_fold_matches_scalar_enumeration(P, sign):
     depth, var, dll, valid = _grid(3, 31, seed=2, pvalid=0.8)
     lnp, dep, s2, nev = periodic.fold_period(depth, var, dll, valid, 1.0, P, sign)
     ref = _brute_fold(depth, var, dll, valid, 1.0, P, sign)
-    assert lnp.shape[0] == int(math.ceil(P))
+    if P < 1.0:  # below one cadence: no phase grid, no cell (reading of Section 2.3)
+        assert lnp.shape[0] == 0
+        return
+    # phases at or past the last slot hold no event and are not formed
+    assert lnp.shape[0] == min(int(math.ceil(P)), 31)
     for (m, j), r in ref.items():
-        if r is None:
+        if m >= lnp.shape[0]:
+            assert r is None
+        elif r is None:
             assert nev[m, j] == 0 and math.isnan(lnp[m, j])
         else:
             assert nev[m, j] == r[3]
@@ -223,3 +229,49 @@ def test_principle_dataset_alias_scores_lower():
             lnp, *_ = periodic.fold_period(out["depth"], out["var"], out["dll"], out["valid"], w.dt, float(P), sign)
             best.append(np.nanmax(lnp))
         assert best[1] > best[0], (sign, best)
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+def test_period_of_one_cadence_combines_every_valid_slot(sign):
+    """p = 1 (Section 2.3): one phase, an event on every slot (w_k = 0), so
+    Eq. B4 is the inverse-variance mean over all valid slots of a duration, and
+    Eq. 8's log term is the closed form of K independent events."""
+    depth, var, dll, valid = _grid(2, 40, seed=7, pvalid=0.7)
+    lnp, dep, s2, nev = periodic.fold_period(depth, var, dll, valid, 0.25, 0.25, sign)
+    assert lnp.shape == (1, 2)
+    for j in range(2):
+        ok = valid[j].astype(bool)
+        w = 1.0 / var[j, ok]
+        sig2 = 1.0 / w.sum()
+        d = sig2 * (w * depth[j, ok]).sum()
+        ref = dll[j, ok].sum() - 0.5 * (sign * np.log(var[j, ok] / (sig2 + var[j, ok]))
+                                        + (depth[j, ok] - d) ** 2 / (var[j, ok] + sig2)).sum()
+        assert nev[0, j] == ok.sum()
+        assert s2[0, j] == pytest.approx(sig2, rel=1e-13)
+        assert dep[0, j] == pytest.approx(d, rel=1e-12)
+        assert lnp[0, j] == pytest.approx(ref, rel=1e-12)
+
+
+@pytest.mark.parametrize("period", [0.5, 0.999999, 0.0, -1.0, float("nan"), float("inf"), float("-inf")])
+def test_periods_below_one_cadence_or_not_finite_have_no_event(period):
+    """Reading of Section 2.3's phase grid (one cadence per step): a period
+    shorter than one cadence, or not finite, forms no (phase, duration) cell;
+    the periodogram reports Q = 0 and indices -1 for it."""
+    depth, var, dll, valid = _grid(2, 30, seed=3)
+    lnp, dep, s2, nev = periodic.fold_period(depth, var, dll, valid, 1.0, period, 1)
+    assert lnp.shape == (0, 2) and nev.sum() == 0
+    out = periodic.periodic_search(depth, var, dll, valid, 1.0, [period, 3.0])
+    assert out["best_phase"][0] == -1 and out["best_dur"][0] == -1 and out["q_snr"][0] == 0.0
+    assert out["best_lnp"][0] == -np.inf
+    assert out["best_phase"][1] >= 0
+
+
+def test_period_far_beyond_the_grid_leaves_single_events():
+    """A period longer than the grid by any factor gives one event per phase
+    (k = 0 only); phases past the grid hold none, so only n_T phases form."""
+    depth, var, dll, valid = _grid(1, 12, seed=5)
+    for P in (13.0, 1e6, 1e300):
+        lnp, dep, s2, nev = periodic.fold_period(depth, var, dll, valid, 1.0, P, 1)
+        assert lnp.shape == (12, 1)
+        np.testing.assert_array_equal(nev[:, 0], np.ones(12, dtype=np.int64))
+        np.testing.assert_allclose(dep[:, 0], depth[0], rtol=1e-15)
