@@ -67,7 +67,7 @@ def workload(name: str):
 def run_step(api, ctx, dev_in, w, precision, fac=None, planets=1, solver="dense", kernel=None, shapes=None):
     """gp_factor + linear_search + periodic_search (solver "statespace": the state-space linear search, no
     factor); with planets > 1, the periodic search is repeated on the same linear-search grid with each found
-    candidate's transits masked (Section 4). Returns the factor, the grid, the first periodic search and the
+    candidate's transits masked (Section 3.3). Returns the factor, the grid, the first periodic search and the
     candidates (None for planets == 1)."""
     if solver == "statespace":
         ls = api.linear_search_ss(ctx, dev_in["t"], kernel, dev_in["f"], dev_in["A"], dev_in["lattice"],
@@ -540,7 +540,7 @@ def main(argv=None):
                     help="linear search from the dense factor, or from the state-space (Kalman) form of the "
                          "covariance (FP64; single-curve eager mode)")
     ap.add_argument("--template", default="box", choices=["box", "limb_darkened", "exocomet"],
-                    help="single-event base model in the last column of the design (Section 5 prospects)")
+                    help="single-event base model in the last column of the design (Section 4.4, prospects)")
     ap.add_argument("--kernel", default="sho", choices=["sho", "rotation"],
                     help="covariance: the workload's SHO, or the stellar-variability kernel of Section 3.2")
     ap.add_argument("--planets", type=int, default=1,

@@ -104,6 +104,21 @@ typedef struct {
   double sigma_w;
 } nu_kernel;
 
+/* The stellar-variability kernel of Section 3.2 (the "rotation kernel"),
+ * k = k1 + k2 + k3 + k4, as a nu_kernel (host only; no device work):
+ *   k1: SHO with Q1 = 1/2 + q0 + dq, omega1 = 4 pi Q1 / (period sqrt(4 Q1^2 - 1)),
+ *       power S1 = sigma^2 / ((1 + f) omega1 Q1);
+ *   k2: SHO with Q2 = 1/2 + q0, omega2 = 2 omega1, power S2 = f sigma^2 / ((1 + f) omega2 Q2);
+ *   k3, k4: sigma_short^2 exp(-tau / ell_short), sigma_long^2 exp(-tau / ell_long);
+ * plus sigma_w^2 on the diagonal. An SHO term of power S0 has k(0) = S0 omega Q,
+ * so the amplitudes are sqrt(S1 omega1 Q1) and sqrt(S2 omega2 Q2), and
+ * k1(0) + k2(0) = sigma^2. Requires every argument finite, sigma >= 0,
+ * period > 0, q0 > 0, dq >= 0, f >= 0, sigma_short, sigma_long, sigma_w >= 0,
+ * ell_short, ell_long > 0; NU_ERR_ARG otherwise (out_host untouched). */
+nu_status nu_rotation_kernel(double sigma, double period, double q0, double dq, double f, double sigma_short,
+                             double ell_short, double sigma_long, double ell_long, double sigma_w,
+                             nu_kernel* out_host);
+
 typedef struct nu_ctx nu_ctx;
 typedef struct nu_factor nu_factor;
 
@@ -173,7 +188,9 @@ int64_t nu_factor_n(const nu_factor* factor);
  * (column c at A + c*n), 0 <= m1 <= 7; may be NULL when m1 == 0.
  * lattice: device, n int64, lattice[0] == 0 and strictly increasing: sample
  * s sits at epoch slot lattice[s] (time t_first + lattice[s] * dt).
- * n_epochs == lattice[n-1] + 1 epoch slots are searched. dur_samples_host:
+ * n_epochs == lattice[n-1] + 1 epoch slots are searched. The lattice is
+ * checked on the device (no synchronisation): one that breaks these rules
+ * leaves every cell invalid and ln L_0 = NaN in null_out. dur_samples_host:
  * host, n_d box lengths in slots, 1 <= value <= 1024, 1 <= n_d <= 16.
  * The box of cell (j, i) is -1 on samples whose slot lies in
  * [i - floor(d_j/2), i - floor(d_j/2) + d_j) and 0 elsewhere.
@@ -216,7 +233,7 @@ nu_status nu_linear_search_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_
                               double* var, double* dll, uint8_t* valid, double* null_out, int64_t* fail_index_host);
 
 /* (2c) Linear search with a non-box base model in the last column of the
- * design (Section 5, prospects: limb-darkened transits, exocomets, flares):
+ * design (Section 4.4, prospects: limb-darkened transits, exocomets, flares):
  * as (2), with the box of duration j replaced by its shape. shapes_host:
  * host, the n_d shapes concatenated in the caller's duration order, shape j
  * holding dur_samples_host[j] finite values (one per lattice slot of the
@@ -258,7 +275,7 @@ nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var
                              double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period_index);
 
 /* (3c) Periodic search over segments of one light curve, each with its own
- * linear search (Sections 3.3 and 4: sectors observed apart, one GP and one
+ * linear search (Sections 3.3 and 4.1: sectors observed apart, one GP and one
  * linear search per sector, combined in the fold).
  * Segment s covers the global lattice slots [seg_off_host[s],
  * seg_off_host[s] + seg_len_host[s]) (host arrays, n_seg in 1 .. 32; ascending,
@@ -276,7 +293,7 @@ nu_status nu_periodic_search_segments(nu_ctx* ctx, const double* depth, const do
                                       double* best_depth, double* best_sigma, double* best_lnp,
                                       int64_t* best_period_index);
 
-/* (3b) Search for further candidates (Section 4, the search of TOI-540): mask
+/* (3b) Search for further candidates (Section 3.3, the search of TOI-540): mask
  * a found candidate's transits in the linear-search outputs, in place, so
  * that the next periodic search (3) on them skips those epochs; the linear
  * search is not repeated.

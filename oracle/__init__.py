@@ -21,10 +21,10 @@ Contents (each function cites the passage it follows):
 * ``oracle.segments``  The periodic search over several segments (sectors), each
                        with its own linear search, on one global lattice.
 * ``oracle.templates`` The single-event search with a non-box base model in
-                       the last column (Section 5, prospects: limb-darkened
+                       the last column (Section 4.4, prospects: limb-darkened
                        transits, exocomets): the same fit with a shape per
                        duration in place of the box.
-* ``oracle.multiplanet`` The iterative search for several candidates (Section 4):
+* ``oracle.multiplanet`` The iterative search for several candidates (Section 3.3):
                        mask the found candidate's transit windows in the
                        linear-search products and search again.
 * ``oracle.learned``   The hyperparameter fit the search needs first (Section

@@ -1,4 +1,4 @@
-"""Oracle: the iterative search for several transiting candidates (Section 4,
+"""Oracle: the iterative search for several transiting candidates (Section 3.3,
 the search of TOI-540).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).

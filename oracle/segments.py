@@ -1,5 +1,5 @@
 """Oracle: the periodic search over several segments of a light curve, each
-with its own linear search (Sections 3.3 and 4: sectors observed years apart
+with its own linear search (Sections 3.3 and 4.1: sectors observed years apart
 are searched with one GP and one linear search per sector, and the periodic
 search combines them).
 

@@ -1,4 +1,4 @@
-"""Oracle: the single-event search with a non-box base model (Section 5,
+"""Oracle: the single-event search with a non-box base model (Section 4.4,
 prospects: limb-darkened transits and exocomets in the last column of the
 design matrix).
 

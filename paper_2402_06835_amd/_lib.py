@@ -33,6 +33,7 @@ class NuKernel(ctypes.Structure):
 
 # name -> (restype, argtypes)
 SIGNATURES = {
+    "nu_rotation_kernel": (c_int, [c_double] * 10 + [P(NuKernel)]),
     "nu_ctx_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
     "nu_ctx_destroy": (None, [c_void_p]),
     "nu_ctx_set_stream": (c_int, [c_void_p, c_void_p]),

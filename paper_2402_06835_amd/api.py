@@ -11,8 +11,9 @@ and converts arguments, allocates outputs with torch and passes pointers.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
-import math
+import weakref
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -20,6 +21,28 @@ import numpy as np
 import torch
 
 from ._lib import NU_ERR_NOT_PD, NU_OK, PRECISIONS, TUNE_CLASSES, NuanceError, NuKernel, NuSho, lib
+
+
+# Live library handles. Every handle the binding creates is closed by an exit
+# hook, in dependency order (factors, graphs and networks before the contexts
+# whose streams and events they use), while the HIP runtime is still up: left to
+# __del__, a handle held at module scope is released only during interpreter
+# teardown, after the runtime may have begun to tear down its own state.
+_LIVE = {0: weakref.WeakSet(), 1: weakref.WeakSet()}  # 0: factors, graphs, networks; 1: contexts
+
+
+def _register(obj, rank: int):
+    _LIVE[rank].add(obj)
+
+
+@atexit.register
+def _close_live_handles():
+    for rank in (0, 1):
+        for obj in list(_LIVE[rank]):
+            try:
+                obj.close()
+            except Exception:
+                pass
 
 
 def _check(ctx_ptr, status: int):
@@ -68,6 +91,7 @@ class Context:
         if st != NU_OK:
             raise NuanceError(st, "nu_ctx_create failed")
         self.ptr = p
+        _register(self, 1)
 
     def close(self):
         if getattr(self, "ptr", None):
@@ -140,6 +164,7 @@ class Factor:
         self.ptr = ptr
         self.n = n
         self.logdet = logdet
+        _register(self, 0)
 
     def close(self):
         if getattr(self, "ptr", None):
@@ -178,18 +203,16 @@ class Kernel:
 def rotation_kernel(sigma: float, period: float, q0: float, dq: float, f: float, sigma_short: float,
                     ell_short: float, sigma_long: float, ell_long: float, sigma_w: float) -> Kernel:
     """The stellar-variability kernel of Section 3.2, k = k1 + k2 + k3 + k4 (8 hyperparameters, plus the
-    white-noise diagonal): SHO terms at the rotation period P and at P/2,
-        Q1 = 1/2 + Q0 + dQ, omega1 = 4 pi Q1 / (P sqrt(4 Q1^2 - 1)), S1 = sigma^2 / ((1 + f) omega1 Q1),
-        Q2 = 1/2 + Q0,      omega2 = 2 omega1,                       S2 = f sigma^2 / ((1 + f) omega2 Q2),
-    each with k(0) = S0 omega Q, and the short and long exponential terms."""
-    q1 = 0.5 + q0 + dq
-    w1 = 4.0 * math.pi * q1 / (period * math.sqrt(4.0 * q1 * q1 - 1.0))
-    s1 = sigma * sigma / ((1.0 + f) * w1 * q1)
-    q2 = 0.5 + q0
-    w2 = 2.0 * w1
-    s2 = f * sigma * sigma / ((1.0 + f) * w2 * q2)
-    return Kernel(sho=[(math.sqrt(s1 * w1 * q1), w1, q1), (math.sqrt(s2 * w2 * q2), w2, q2)],
-                  exp=[(sigma_short, ell_short), (sigma_long, ell_long)], sigma_w=sigma_w)
+    white-noise diagonal), parametrised by the library (``nu_rotation_kernel``): SHO terms at the rotation
+    period and at half of it, and the short and long exponential terms."""
+    k = NuKernel()
+    st = lib().nu_rotation_kernel(float(sigma), float(period), float(q0), float(dq), float(f), float(sigma_short),
+                                  float(ell_short), float(sigma_long), float(ell_long), float(sigma_w),
+                                  ctypes.byref(k))
+    if st != NU_OK:
+        raise NuanceError(st, "rotation_kernel: invalid hyperparameters")
+    return Kernel(sho=[(k.sho_amp[i], k.sho_omega[i], k.sho_q[i]) for i in range(k.n_sho)],
+                  exp=[(k.exp_sigma[i], k.exp_ell[i]) for i in range(k.n_exp)], sigma_w=k.sigma_w)
 
 
 def gp_factor(ctx: Context, t, theta, out: Optional[Factor] = None) -> Factor:
@@ -500,7 +523,7 @@ def prepare_batch(ctx: Context, curves) -> dict:
 
 def mask_transit(ctx: Context, ls: dict, dt: float, period: float, phase: int, half_width: int) -> dict:
     """Mask a found candidate's transit windows in the linear-search outputs ``ls`` in place (entry point 3b,
-    Section 4): slots within ``half_width`` of phase + k period/dt, every duration. Returns ``ls``."""
+    Section 3.3): slots within ``half_width`` of phase + k period/dt, every duration. Returns ``ls``."""
     depth, var, dll, valid = ls["depth"], ls["var"], ls["dll"], ls["valid"]
     n_d, n_epochs = depth.shape
     for x, dt_ in ((depth, torch.float64), (var, torch.float64), (dll, torch.float64), (valid, torch.uint8)):
@@ -514,7 +537,7 @@ def mask_transit(ctx: Context, ls: dict, dt: float, period: float, phase: int, h
 
 def search_planets(ctx: Context, ls: dict, dt: float, periods, durations, n_planets: int, sign: int = 1,
                    copy: bool = True) -> list:
-    """Up to ``n_planets`` candidates from one linear search (Section 4): periodic search, mask the best
+    """Up to ``n_planets`` candidates from one linear search (Section 3.3): periodic search, mask the best
     candidate's transits (windows of width 2 D), repeat. ``durations``: the box lengths in slots passed to
     linear_search. With ``copy`` the masking works on copies of the grid, else ``ls`` is masked in place.
     One stream synchronisation per candidate (to read its period, phase and duration)."""
@@ -638,6 +661,7 @@ class Graph:
             ctypes.byref(p))
         _check(ctx.ptr, st)
         self.ptr = p
+        _register(self, 0)
 
     def set_inputs(self, theta=None, f=None, A=None, t=None):
         """Overwrite bound inputs in place (stream-ordered copies)."""
@@ -774,6 +798,7 @@ class CNN:
         p = ctypes.c_void_p()
         _check(ctx.ptr, lib().nu_cnn_create(ctx.ptr, int(half), int(max_batch), ctypes.byref(p)))
         self.ptr = p
+        _register(self, 0)
         self.n_params = int(lib().nu_cnn_param_count())
         if params is not None:
             self.set_params(params)
@@ -923,7 +948,7 @@ class Nuance:
         return SearchResult(periods, raw, self.t_first, self.dt, self._dur_slots)
 
     def search_planets(self, periods, n_planets: int = 2, sign: int = 1) -> list:
-        """Several candidates from the one linear search (Section 4): each periodic search is followed by
+        """Several candidates from the one linear search (Section 3.3): each periodic search is followed by
         masking the found transits (windows of width 2 D) in copies of the linear-search products.
         Returns (period, t0, duration, depth, snr) per candidate."""
         if self._ls is None:

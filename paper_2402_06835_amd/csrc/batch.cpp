@@ -322,7 +322,11 @@ nu_status nu_graph_launch(nu_ctx* ctx, nu_graph* g) {
 
 void nu_graph_destroy(nu_graph* g) {
   if (!g) return;
-  (void)hipSetDevice(g->device);
+  if (hipSetDevice(g->device) != hipSuccess) {  // the runtime has shut down: host side only
+    factor_free(g->F);
+    delete g;
+    return;
+  }
   (void)hipDeviceSynchronize();
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);

@@ -271,7 +271,13 @@ nu_status nu_ctx_create(int device, void* stream, nu_ctx** out) {
 
 void nu_ctx_destroy(nu_ctx* ctx) {
   if (!ctx) return;
-  (void)hipSetDevice(ctx->device);
+  // Called after the HIP runtime has shut down (a context released during
+  // process exit), the device objects went with the runtime: free the host
+  // side only, and touch nothing on the device.
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    delete ctx;
+    return;
+  }
   (void)hipStreamSynchronize(ctx->stream);
   nu::destroy_factor_streams(ctx);
   if (ctx->ws) (void)hipFree(ctx->ws);
@@ -372,6 +378,43 @@ nu_status nu_gp_factor(nu_ctx* ctx, const double* t, int64_t n, const nu_sho* th
     return st;
   }
   *out = F;
+  return NU_OK;
+}
+
+// The stellar-variability kernel of Section 3.2 as terms of a nu_kernel. An
+// SHO term of power S0 has k(0) = S0 omega Q, which is what nu_kernel's
+// amplitude squares; the two modes share the variance sigma^2 in the ratio
+// 1 : f.
+nu_status nu_rotation_kernel(double sigma, double period, double q0, double dq, double f, double sigma_short,
+                             double ell_short, double sigma_long, double ell_long, double sigma_w,
+                             nu_kernel* out_host) {
+  if (!out_host) return NU_ERR_ARG;
+  const double in[] = {sigma, period, q0, dq, f, sigma_short, ell_short, sigma_long, ell_long, sigma_w};
+  for (double v : in)
+    if (!std::isfinite(v)) return NU_ERR_ARG;
+  const double q1 = 0.5 + q0 + dq, q2 = 0.5 + q0;
+  if (!(sigma >= 0.0 && period > 0.0 && q0 > 0.0 && dq >= 0.0 && f >= 0.0 && sigma_short >= 0.0 &&
+        ell_short > 0.0 && sigma_long >= 0.0 && ell_long > 0.0 && sigma_w >= 0.0))
+    return NU_ERR_ARG;
+  const double w1 = 4.0 * M_PI * q1 / (period * std::sqrt(4.0 * q1 * q1 - 1.0));
+  const double w2 = 2.0 * w1;
+  const double s1 = sigma * sigma / ((1.0 + f) * w1 * q1);
+  const double s2 = f * sigma * sigma / ((1.0 + f) * w2 * q2);
+  nu_kernel k{};
+  k.n_sho = 2;
+  k.n_exp = 2;
+  k.sho_amp[0] = std::sqrt(s1 * w1 * q1);
+  k.sho_omega[0] = w1;
+  k.sho_q[0] = q1;
+  k.sho_amp[1] = std::sqrt(s2 * w2 * q2);
+  k.sho_omega[1] = w2;
+  k.sho_q[1] = q2;
+  k.exp_sigma[0] = sigma_short;
+  k.exp_ell[0] = ell_short;
+  k.exp_sigma[1] = sigma_long;
+  k.exp_ell[1] = ell_long;
+  k.sigma_w = sigma_w;
+  *out_host = k;
   return NU_OK;
 }
 

@@ -517,7 +517,10 @@ nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F, int prec) {
 
 void factor_free(nu_factor* F) {
   if (!F) return;
-  (void)hipSetDevice(F->device);
+  if (hipSetDevice(F->device) != hipSuccess) {  // the runtime has shut down: host side only
+    delete F;
+    return;
+  }
   (void)hipDeviceSynchronize();
   void* bufs[] = {F->L, F->X, F->T, F->small, F->nullfit, F->L32, F->X32, F->bandP, F->bandX};
   if (F->owns_memory)
@@ -858,7 +861,9 @@ size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs) {
   const size_t yz = (size_t)np * YCOLS;
   const size_t slots = ((size_t)n_epochs + 2) / 2;  // the int32 slot-count table, in doubles
   // template shapes after the slot table
-  return (5 * yz + xchunks * yz + qchunks * (size_t)n_d * (size_t)n_epochs + slots + MAX_SHAPE) * sizeof(double);
+  // the lattice flag after the shapes
+  return (5 * yz + xchunks * yz + qchunks * (size_t)n_d * (size_t)n_epochs + slots + MAX_SHAPE + 1) *
+         sizeof(double);
 }
 
 nu_status validate_linear(nu_ctx* ctx, int64_t n, const double* f, const double* A, int m1, const int64_t* lattice,
@@ -899,6 +904,7 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
   double* qpart = xpart + (size_t)xchunks * yz;
   int32_t* slot_count = reinterpret_cast<int32_t*>(qpart + (size_t)qchunks * n_d * n_epochs);
   double* shapes = qpart + (size_t)qchunks * n_d * n_epochs + ((size_t)n_epochs + 2) / 2;
+  int* lattice_ok = reinterpret_cast<int*>(shapes + MAX_SHAPE);
   const int nv = m1 + 1;
   const double gemv_bytes = (double)n * (double)(n + 1) / 2.0 * 8.0;
   int dmax = 0;
@@ -911,7 +917,8 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
     st = ctx_upload(ctx, shapes_host, total * sizeof(double), shapes);
     if (st != NU_OK) return st;
   }
-  st = check_hip(ctx, launch_pack_v(ctx->stream, A, m1, f, n, V), "pack_v");
+  st = check_hip(ctx, launch_lattice_check(ctx->stream, lattice, n, n_epochs, lattice_ok), "lattice_check");
+  if (st == NU_OK) st = check_hip(ctx, launch_pack_v(ctx->stream, A, m1, f, n, V), "pack_v");
   if (st != NU_OK) return st;
   {
     // Y = X V, refined against L when X is a reduced-precision inverse
@@ -929,7 +936,7 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
   if (st != NU_OK) return st;
   {
     Timed tm(ctx, "null_solve", 0.0);
-    st = check_hip(ctx, launch_null_solve(ctx->stream, Y, n, m1, F->logdet_dev(), F->nullfit, null_out),
+    st = check_hip(ctx, launch_null_solve(ctx->stream, Y, n, m1, F->logdet_dev(), lattice_ok, F->nullfit, null_out),
                    "null_solve");
   }
   if (st != NU_OK) return st;

@@ -426,7 +426,7 @@ hipError_t launch_fold_segments(hipStream_t s, const double* depth, const double
 size_t fold_workspace_doubles(int n_d, int64_t n_epochs) { return (size_t)3 * n_d * (size_t)(n_epochs + FPAD); }
 
 // ---------------------------------------------------------------------------
-// Search for further candidates (Section 4, the search of TOI-540): the trial
+// Search for further candidates (Section 3.3, the search of TOI-540): the trial
 // epochs in windows of width 2 D centred on a found candidate's transits are
 // masked in the linear-search products, which the next periodic search then
 // skips. Transit k of the candidate sits at slot m + k p (any integer k), the

@@ -357,8 +357,10 @@ hipError_t launch_pack_v(hipStream_t s, const double* A, int m1, const double* f
 hipError_t launch_rows_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, int64_t np, const double* V,
                               int nv, double* partial, int cw, int nchunks, const double* base, double alpha,
                               double* out);
-hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const double* logdet, NullFit* nf,
-                             double* null_out);
+// lattice_ok: device flag from launch_lattice_check (NULL: not checked)
+hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const double* logdet,
+                             const int* lattice_ok, NullFit* nf, double* null_out);
+hipError_t launch_lattice_check(hipStream_t s, const int64_t* lattice, int64_t n, int64_t n_epochs, int* ok);
 hipError_t launch_cols_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, int64_t np, const double* W,
                               int nv, double* partial, int rowchunk, int nchunks, const double* base, double alpha,
                               double* out);

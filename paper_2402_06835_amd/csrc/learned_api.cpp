@@ -372,7 +372,10 @@ nu_status nu_cnn_create(nu_ctx* ctx, int half_precision, int max_batch, nu_cnn**
 
 void nu_cnn_destroy(nu_cnn* M) {
   if (!M) return;
-  (void)hipSetDevice(M->device);
+  if (hipSetDevice(M->device) != hipSuccess) {  // the runtime has shut down: host side only
+    delete M;
+    return;
+  }
   (void)hipDeviceSynchronize();
   if (M->arena) (void)hipFree(M->arena);
   delete M;

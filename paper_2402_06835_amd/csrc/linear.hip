@@ -39,6 +39,28 @@ hipError_t launch_slot_count(hipStream_t s, const int64_t* lattice, int64_t n, i
   return hipGetLastError();
 }
 
+// The lattice the searches assume: lattice[0] == 0, strictly increasing,
+// lattice[n - 1] == n_epochs - 1. One workgroup; *ok = 1 if it holds, else 0.
+// The trend fit reads the flag, so a lattice that breaks it leaves every cell
+// invalid and ln L_0 = NaN (the call itself does not synchronise to report it).
+__global__ __launch_bounds__(256) void lattice_check_kernel(const int64_t* __restrict__ lattice, int64_t n,
+                                                            int64_t n_epochs, int* __restrict__ ok) {
+  bool bad = false;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const int64_t v = lattice[i];
+    if (i == 0) bad = bad || v != 0;
+    else bad = bad || v <= lattice[i - 1];
+    if (i == n - 1) bad = bad || v != n_epochs - 1;
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) *ok = bad ? 0 : 1;
+}
+
+hipError_t launch_lattice_check(hipStream_t s, const int64_t* lattice, int64_t n, int64_t n_epochs, int* ok) {
+  hipLaunchKernelGGL(lattice_check_kernel, dim3(1), dim3(256), 0, s, lattice, n, n_epochs, ok);
+  return hipGetLastError();
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -132,7 +154,8 @@ __device__ double block_sum(double v, double* red) {
 }
 
 __global__ __launch_bounds__(256) void null_solve_kernel(double* __restrict__ Y, int64_t n, int m1,
-                                                         const double* __restrict__ logdet, NullFit* __restrict__ nf,
+                                                         const double* __restrict__ logdet,
+                                                         const int* __restrict__ lattice_ok, NullFit* __restrict__ nf,
                                                          double* __restrict__ null_out) {
   __shared__ double red[4];
   __shared__ double S[MAX_M1 + 1][MAX_M1 + 1];
@@ -177,8 +200,10 @@ __global__ __launch_bounds__(256) void null_solve_kernel(double* __restrict__ Y,
     for (int i = 0; i < MAX_M1; ++i)
       for (int j = 0; j < MAX_M1; ++j) nf->G0chol[i * MAX_M1 + j] = (i < m1 && j <= i) ? Lg[i][j] : 0.0;
     for (int i = 0; i < m1; ++i) nf->w0[i] = w0s[i];
-    // a failed factorisation leaves ln|K| non-finite: no cell is valid then
+    // a failed factorisation leaves ln|K| non-finite: no cell is valid then;
+    // nor with a lattice the searches cannot use
     if (!isfinite(*logdet)) ok = 0;
+    if (lattice_ok && !*lattice_ok) ok = 0;
     nf->ok = ok;
     ok_s = ok;
   }
@@ -206,9 +231,9 @@ __global__ __launch_bounds__(256) void null_solve_kernel(double* __restrict__ Y,
   }
 }
 
-hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const double* logdet, NullFit* nf,
-                             double* null_out) {
-  hipLaunchKernelGGL(null_solve_kernel, dim3(1), dim3(256), 0, s, Y, n, m1, logdet, nf, null_out);
+hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const double* logdet,
+                             const int* lattice_ok, NullFit* nf, double* null_out) {
+  hipLaunchKernelGGL(null_solve_kernel, dim3(1), dim3(256), 0, s, Y, n, m1, logdet, lattice_ok, nf, null_out);
   return hipGetLastError();
 }
 
@@ -484,7 +509,11 @@ __global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __rest
   if (ok) {
     for (int64_t r = lo; r < hi; ++r) {
       const double* zr = Z + r * YCOLS;
-      const double wgt = TPL ? shapes[dl.off[j] + (int)(lattice[r] - a)] : 1.0;
+      double wgt = 1.0;
+      if (TPL) {  // the sample's window offset; in [0, d) for a lattice the searches accept
+        const int64_t o = lattice[r] - a;
+        wgt = (o >= 0 && o < d) ? shapes[dl.off[j] + (int)o] : 0.0;
+      }
 #pragma unroll
       for (int c = 0; c < MAX_M1; ++c)
         if (c < m1) g[c] = fma(-wgt, zr[c], g[c]);

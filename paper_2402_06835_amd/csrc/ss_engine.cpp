@@ -14,6 +14,7 @@ namespace {
 struct SsWs {
   double *V, *Y, *Z, *step, *gain, *Gm, *qbox, *shapes, *chunk, *logdet;
   int64_t* status;
+  int* lattice_ok;
   NullFit* nf;
   int32_t* slot_count;
 };
@@ -38,6 +39,7 @@ size_t ss_layout(int64_t n, int J, int ts, int n_d, int64_t n_epochs, double* ba
   l.chunk = take(ss_chunk_ws_doubles(n, J));
   l.logdet = take(2);
   l.status = reinterpret_cast<int64_t*>(l.logdet + 1);
+  l.lattice_ok = reinterpret_cast<int*>(take(1));
   l.nf = reinterpret_cast<NullFit*>(take((sizeof(NullFit) + 7) / 8));
   l.slot_count = reinterpret_cast<int32_t*>(take(((size_t)n_epochs + 2) / 2));
   if (w) *w = l;
@@ -98,7 +100,8 @@ nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel
     st = ctx_upload(ctx, shapes_host, total * sizeof(double), w.shapes);
     if (st != NU_OK) return st;
   }
-  st = check_hip(ctx, launch_pack_v(ctx->stream, A, m1, f, n, w.V), "pack_v");
+  st = check_hip(ctx, launch_lattice_check(ctx->stream, lattice, n, n_epochs, w.lattice_ok), "lattice_check");
+  if (st == NU_OK) st = check_hip(ctx, launch_pack_v(ctx->stream, A, m1, f, n, w.V), "pack_v");
   if (st != NU_OK) return st;
   {
     Timed tm(ctx, "ss_step", 0.0);
@@ -117,7 +120,7 @@ nu_status run_linear_ss(nu_ctx* ctx, const double* t, int64_t n, const nu_kernel
   if (st != NU_OK) return st;
   {
     Timed tm(ctx, "null_solve", 0.0);
-    st = check_hip(ctx, launch_null_solve(ctx->stream, w.Y, n, m1, w.logdet, w.nf, null_out), "null_solve");
+    st = check_hip(ctx, launch_null_solve(ctx->stream, w.Y, n, m1, w.logdet, w.lattice_ok, w.nf, null_out), "null_solve");
   }
   if (st != NU_OK) return st;
   {

@@ -608,7 +608,8 @@ __global__ __launch_bounds__(256) void ss_template_kernel(const double* __restri
 #pragma unroll
     for (int b = 0; b < J; ++b)
       if (Lt::pos(b)) hx += x[b];
-    const double ev = shp[lattice[m] - a] - hx;
+    const int64_t o = lattice[m] - a;  // in [0, d) for a lattice the searches accept
+    const double ev = ((o >= 0 && o < d) ? shp[o] : 0.0) - hx;
     const double z = ev * g[0];
     q = fma(z, z, q);
     if (m + 1 < n) {

@@ -2,7 +2,7 @@
 
 The paper proposes replacing the box in the last column of the design
 matrix by other base models: limb-darkened transits and the asymmetric dips
-of transiting exocomets (Section 5, prospects). It gives no formula for
+of transiting exocomets (Section 4.4, prospects). It gives no formula for
 either, so the shapes here are stated choices. Each is a vector of d values,
 one per lattice slot of the event window (slot k of the window sits at
 u = (k + 1/2) / d of its duration), with peak value 1, so the fitted depth is

@@ -71,6 +71,23 @@ def _close(gpu, ref, tol, tag):
     assert max(e.values()) <= tol, (tag, e)
 
 
+def test_rotation_kernel_parametrisation_matches_the_oracle(api):
+    """The library's Section 3.2 parametrisation (nu_rotation_kernel) against the oracle's terms, and its
+    argument checks."""
+    from paper_2402_06835_amd._lib import NuanceError
+    say("rotation kernel parametrisation")
+    k = api.rotation_kernel(**ROT)
+    terms, sw = _oracle_terms()
+    assert len(k.sho) == 2 and len(k.exp) == 2 and k.sigma_w == sw
+    for got, ref in zip(k.sho, terms["sho"]):
+        np.testing.assert_allclose(got, ref, rtol=1e-15, atol=0)
+    for got, ref in zip(k.exp, terms["exp"]):
+        assert tuple(got) == tuple(ref)
+    for bad in (dict(period=0.0), dict(q0=-1.0), dict(sigma=float("nan")), dict(ell_long=0.0)):
+        with pytest.raises(NuanceError):
+            api.rotation_kernel(**{**ROT, **bad})
+
+
 @pytest.mark.parametrize("n,gap", [(300, None), (900, (450, 30))])
 def test_rotation_kernel_logdet(api, ctx, n, gap):
     w = _curve(n, 31, gap)

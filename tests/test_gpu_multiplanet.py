@@ -1,5 +1,5 @@
 """GPU: the search for further candidates (mask a found candidate's transits in
-the linear-search products, search again; Section 4) through the C ABI,
+the linear-search products, search again; Section 3.3) through the C ABI,
 against the oracle (``oracle.multiplanet``).
 
 * The mask kernel equals the oracle's mask bit for bit, including a slot at

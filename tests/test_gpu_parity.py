@@ -254,6 +254,39 @@ def test_argument_errors_enqueue_nothing(api, ctx):
         api.periodic_search(ctx, ls["depth"], ls["var"], ls["dll"], ls["valid"], w.dt, [1.0], sign=0)
 
 
+def test_lattice_that_breaks_the_rules_gives_no_cell(api, ctx):
+    """The lattice is checked on the device: lattice[0] == 0, strictly increasing, lattice[-1] ==
+    n_epochs - 1. One that breaks a rule leaves every cell invalid and ln L_0 = NaN (dense and
+    state-space searches, boxes and templates); a good lattice afterwards gives the oracle's cells."""
+    import torch
+    w = _case(n=300, m1=2, durs=[2, 5], gap=(150, 9))
+    say("lattice check")
+    fac = api.gp_factor(ctx, w.t, w.theta)
+    kern = api.Kernel(sho=[(w.theta["amp"], w.theta["omega"], w.theta["q"])], sigma_w=w.theta["sigma_w"])
+    shapes = [np.ones(2), np.linspace(0.2, 1.0, 5)]
+    swapped = w.lattice.copy()
+    swapped[[40, 41]] = swapped[[41, 40]]
+    repeated = w.lattice.copy()
+    repeated[100] = repeated[99]
+    shifted = w.lattice + 1
+    short_end = w.lattice.copy()
+    short_end[-1] -= 1  # n_epochs then exceeds lattice[-1] + 1
+    for tag, lat in (("swapped", swapped), ("repeated", repeated), ("shifted", shifted), ("short end", short_end)):
+        outs = [api.linear_search(ctx, fac, w.f, w.A, lat, w.n_epochs, w.durations),
+                api.linear_search(ctx, fac, w.f, w.A, lat, w.n_epochs, w.durations, shapes=shapes),
+                api.linear_search_ss(ctx, w.t, kern, w.f, w.A, lat, w.n_epochs, w.durations, check=False)]
+        torch.cuda.synchronize()
+        for ls in outs:
+            h = _host(ls)
+            assert not h["valid"].any(), tag
+            assert np.all(h["var"] == np.inf) and np.all(h["depth"] == 0) and np.all(h["dll"] == 0), tag
+            assert math.isnan(float(ls["null"][0].item())), tag
+    ls = api.linear_search(ctx, fac, w.f, w.A, w.lattice, w.n_epochs, w.durations)
+    torch.cuda.synchronize()
+    ref = olin.linear_search(w.f, w.A, ogp.cholesky(ogp.covariance(w.t, w.theta)), w.lattice, w.durations)
+    assert_linear_close(_host(ls), ref, "after a bad lattice")
+
+
 def test_periods_at_and_below_one_cadence_match_the_oracle(api, ctx):
     """Section 2.3's phase grid at its edge: a period below one cadence (p < 1) or
     not finite has no event on both sides; p = 1 folds every slot into phase 0;
