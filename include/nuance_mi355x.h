@@ -274,6 +274,25 @@ nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var
                              int64_t n_p, int log_term_sign, double* q_snr, int64_t* best_phase, int32_t* best_dur,
                              double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period_index);
 
+/* (3d) The periodic search (3) for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments, kernels and outputs (bitwise equal to
+ * (3)), with its one scratch buffer, the packed copy of the grid (24 n_d
+ * (n_epochs + 64) bytes), in a fixed device array of NU_PERIODIC_SCRATCH_BYTES
+ * per device instead of the context's workspace. The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine) and does not
+ * synchronise. A grid needing more than the array returns NU_ERR_ARG before
+ * any launch (e.g. 10 durations x 139 000 slots fit). Every call on one device
+ * shares that device's array: calls that overlap on a device (other streams,
+ * other contexts, other host threads) race, and must be ordered by the caller.
+ * The library's kernel timing does not cover this call. */
+#define NU_PERIODIC_SCRATCH_BYTES ((size_t)32 << 20)
+nu_status nu_periodic_search_noalloc(nu_ctx* ctx, const double* depth, const double* var, const double* dll,
+                                     const uint8_t* valid, int n_d, int64_t n_epochs, double dt,
+                                     const double* periods, int64_t n_p, int log_term_sign, double* q_snr,
+                                     int64_t* best_phase, int32_t* best_dur, double* best_depth, double* best_sigma,
+                                     double* best_lnp, int64_t* best_period_index);
+
 /* (3c) Periodic search over segments of one light curve, each with its own
  * linear search (Sections 3.3 and 4.1: sectors observed apart, one GP and one
  * linear search per sector, combined in the fold).

@@ -261,7 +261,7 @@ nu_status nu_ctx_create(int device, void* stream, nu_ctx** out) {
   if (!ctx) return NU_ERR_OOM;
   ctx->device = device;
   ctx->stream = (hipStream_t)stream;
-  if (hipSetDevice(device) != hipSuccess) {
+  if (hipSetDevice(device) != hipSuccess || nu::fold_scratch_ptr(device, &ctx->scratch) != hipSuccess) {
     delete ctx;
     return NU_ERR_DEVICE;
   }
@@ -598,6 +598,37 @@ nu_status nu_periodic_search(nu_ctx* ctx, const double* depth, const double* var
   if (!ws) return st;
   return run_periodic(ctx, depth, var, dll, valid, n_d, n_epochs, dt, periods, n_p, log_term_sign, q_snr,
                       best_phase, best_dur, best_depth, best_sigma, best_lnp, best_period_index, ws);
+}
+
+// ---------------------------------------------------------------------------
+// The periodic search of nu_periodic_search without any allocation: the
+// packed grid goes to the device's fixed scratch array (looked up in
+// nu_ctx_create), and the kernels are the same, so the outputs are bitwise
+// those of nu_periodic_search. No kernel timing is recorded for it.
+nu_status nu_periodic_search_noalloc(nu_ctx* ctx, const double* depth, const double* var, const double* dll,
+                                     const uint8_t* valid, int n_d, int64_t n_epochs, double dt,
+                                     const double* periods, int64_t n_p, int log_term_sign, double* q_snr,
+                                     int64_t* best_phase, int32_t* best_dur, double* best_depth, double* best_sigma,
+                                     double* best_lnp, int64_t* best_period_index) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!depth || !var || !dll || !valid || !periods || !q_snr || !best_phase || !best_dur || !best_depth ||
+      !best_sigma || !best_lnp)
+    return set_error(ctx, NU_ERR_ARG, "periodic_search_noalloc: null argument");
+  nu_status st = validate_periodic(ctx, n_d, n_epochs, dt, n_p, log_term_sign);
+  if (st != NU_OK) return st;
+  if (fold_workspace_doubles(n_d, n_epochs) > FOLD_SCRATCH_DOUBLES)
+    return set_error(ctx, NU_ERR_ARG,
+                     "periodic_search_noalloc: 24 n_d (n_epochs + 64) bytes exceed the scratch of " +
+                         std::to_string(NU_PERIODIC_SCRATCH_BYTES) + " bytes");
+  if (!ctx->scratch) return set_error(ctx, NU_ERR_DEVICE, "periodic_search_noalloc: no scratch on this device");
+  st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+  st = check_hip(ctx, launch_fold(ctx->stream, depth, var, dll, valid, n_d, n_epochs, dt, periods, n_p, log_term_sign,
+                                  q_snr, best_phase, best_dur, best_depth, best_sigma, best_lnp, ctx->scratch),
+                 "fold");
+  if (st == NU_OK && best_period_index)
+    st = check_hip(ctx, launch_best_period(ctx->stream, q_snr, n_p, best_period_index), "best_period");
+  return st;
 }
 
 // ---------------------------------------------------------------------------

@@ -8,6 +8,9 @@
 // event gather is one coalesced segment per wave. Interpolation is evaluated
 // as written (this file is compiled without floating-point contraction); the
 // sums run in increasing k.
+#include <mutex>
+#include <vector>
+
 #include "internal.hpp"
 
 namespace nu {
@@ -424,6 +427,42 @@ hipError_t launch_fold_segments(hipStream_t s, const double* depth, const double
 }
 
 size_t fold_workspace_doubles(int n_d, int64_t n_epochs) { return (size_t)3 * n_d * (size_t)(n_epochs + FPAD); }
+
+// ---------------------------------------------------------------------------
+// The allocation-free periodic search keeps its packed grid in a fixed device
+// array instead of the context's workspace. Each GPU the library runs on holds
+// its own copy of the array until the process ends; in host code its name
+// stands for no device address, so the host takes each device's address once
+// (hipGetSymbolAddress with that device current) and passes that pointer to
+// the kernels. Every call on a device shares its array: calls that overlap on
+// one device race. The fold's pack kernel writes every element of the part a
+// call uses, so nothing needs clearing between calls.
+static __device__ __align__(256) double scratch[FOLD_SCRATCH_DOUBLES];
+
+namespace {
+std::mutex scratch_mu;
+std::vector<double*> scratch_dev;  // per device; nullptr until looked up
+}  // namespace
+
+hipError_t fold_scratch_ptr(int device, double** out) {
+  *out = nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((size_t)device >= scratch_dev.size()) scratch_dev.resize((size_t)device + 1, nullptr);
+  if (!scratch_dev[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current
+    double* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_dev[device] = p;
+  }
+  *out = scratch_dev[device];
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // Search for further candidates (Section 3.3, the search of TOI-540): the trial

@@ -157,6 +157,8 @@ struct nu_ctx {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t pinned_ev = nullptr;
+  // this device's fixed scratch array of the allocation-free periodic search
+  double* scratch = nullptr;
 };
 
 namespace nu {
@@ -382,6 +384,11 @@ hipError_t launch_fold(hipStream_t s, const double* depth, const double* var, co
                        int sign, double* q_snr, int64_t* best_phase, int32_t* best_dur, double* best_depth,
                        double* best_sigma, double* best_lnp, double* packed);
 size_t fold_workspace_doubles(int n_d, int64_t n_epochs);
+// The fixed device array of the allocation-free periodic search (fold.hip):
+// its size, and its address on `device` (looked up once per device, with that
+// device current; the same pointer afterwards).
+constexpr size_t FOLD_SCRATCH_DOUBLES = NU_PERIODIC_SCRATCH_BYTES / sizeof(double);
+hipError_t fold_scratch_ptr(int device, double** out);
 size_t fold_segments_workspace_doubles(int n_d, const int64_t* len, int n_seg);
 hipError_t launch_fold_segments(hipStream_t s, const double* depth, const double* var, const double* dll,
                                 const uint8_t* valid, int n_d, int n_seg, const int64_t* seg_len,
