@@ -241,8 +241,15 @@ def bench_batch(args, api, ctx, torch):
     dev_in = [{"t": torch.as_tensor(w.t, device=ctx.device), "f": torch.as_tensor(w.f, device=ctx.device),
                "A": torch.as_tensor(w.A, device=ctx.device), "lattice": torch.as_tensor(w.lattice, device=ctx.device),
                "periods": per} for w in ws] if args.mode == "loop" else None
+    graph = None
+    if args.mode == "graph":
+        t0 = time.perf_counter()
+        graph = api.BatchGraph(ctx, batch, durs, per, precision=args.precision)
+        log(f"batch graph captured in {time.perf_counter() - t0:.1f} s")
 
     def one_step():
+        if graph is not None:
+            return graph.launch()
         if dev_in is None:
             return api.search_batch(ctx, batch, durs, per, precision=args.precision)
         # the same curves one by one through the single-curve entry points
@@ -277,6 +284,8 @@ def bench_batch(args, api, ctx, torch):
         return elapsed, n_valid, len(ws), timings, None, cfg, {}
     dll_err = None
     if args.precision != "fp64" and not args.no_dll_check:
+        if graph is not None:
+            graph.close()
         ref = api.search_batch(ctx, batch, durs, per, precision="fp64")
         dll_err = output_errors(res, ref)
         log(f"errors vs fp64: {dll_err}")
@@ -289,7 +298,7 @@ def bench_batch(args, api, ctx, torch):
     cfg = {"workload": "uneven-batch-64x(4000..20000)", "n_curves": len(ws),
            "n_samples_total": int(sum(w.n for w in ws)), "n_durations": int(len(durs)),
            "n_periods": int(len(periods)), "valid_cells": n_valid, "precision": args.precision,
-           "mode": "batch call"}
+           "mode": "batch graph launch" if graph is not None else "batch call"}
     return elapsed, n_valid, len(ws), timings, dll_err, cfg, {"injected_recovered": f"{found}/{n_inj}"}
 
 
@@ -526,6 +535,75 @@ def bench_curve(args, api, ctx, torch):
     return elapsed, n_valid, 1, timings, dll_err, cfg, extra, w
 
 
+def bench_extras(args, api, ctx, torch):
+    """Beside the headline curve: the uneven 64-curve batch, FP32_REFINE against FP64, each one captured
+    batch graph per step (seconds per batch, curves/s, fits/s, and the FP32_REFINE errors against the FP64
+    batch over every cell); and the 1440-sample curve in FP64 with its per-stage microseconds."""
+    import numpy as np
+
+    from synth import config1, config3
+    out = {}
+    t0 = time.perf_counter()
+    ws = config3()
+    curves = [{"t": w.t, "f": w.f, "A": w.A, "lattice": w.lattice, "n_epochs": w.n_epochs, "theta": w.theta,
+               "dt": w.dt} for w in ws]
+    durs, per = ws[0].durations, torch.as_tensor(ws[0].periods, device=ctx.device)
+    batch = api.prepare_batch(ctx, curves)
+    log(f"extras: 64-curve batch generated in {time.perf_counter() - t0:.1f} s")
+    ctx.release_memory()
+    res = {}
+    for prec in ("fp32_refine", "fp64"):
+        g = api.BatchGraph(ctx, batch, durs, per, precision=prec)
+        g.launch()
+        torch.cuda.synchronize()
+        steps = args.extra_steps
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            o = g.launch()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        n_valid = int(o["valid"].sum().item())
+        res[prec] = {k: (o[k].clone() if hasattr(o[k], "clone") else o[k]) for k in
+                     ("depth", "var", "dll", "valid", "q_snr", "best_phase", "best_dur")}
+        out[prec] = {"s_per_batch": el, "curves_per_s": len(ws) / el, "fits_per_s": n_valid / el,
+                     "valid_cells": n_valid, "mode": "one captured batch graph launch per step", "steps": steps}
+        log(f"extras: batch-64 {prec}: {el:.3f} s per batch, {n_valid / el:.4g} fits/s")
+        g.close()
+        del g
+    out["errors_fp32_refine_vs_fp64"] = output_errors(res["fp32_refine"], res["fp64"])
+    out["fp32_refine_speedup_vs_fp64"] = out["fp64"]["s_per_batch"] / out["fp32_refine"]["s_per_batch"]
+    del res, batch
+    ctx.release_memory()
+    # the 1440-sample curve, FP64: per-stage microseconds (kernel time per step, HIP events)
+    w = config1()
+    dev_in = {"t": torch.as_tensor(w.t, device=ctx.device), "f": torch.as_tensor(w.f, device=ctx.device),
+              "A": torch.as_tensor(w.A, device=ctx.device), "lattice": torch.as_tensor(w.lattice, device=ctx.device),
+              "periods": torch.as_tensor(w.periods, device=ctx.device)}
+    run_step(api, ctx, dev_in, w, "fp64")
+    torch.cuda.synchronize()
+    steps = 10
+    ctx.enable_timing(True)
+    ctx.reset_timing()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fac, ls, ps, _ = run_step(api, ctx, dev_in, w, "fp64")
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    tm = ctx.timings()
+    ctx.enable_timing(False)
+    stages = {"K build": ["kbuild"], "Cholesky": ["potrf_diag", "gemm_f64:panel", "gemm_f64:panel_update",
+                                                  "gemm_f64:trailing"],
+              "inverse": ["gemm_f64:inverse"], "trend fit and passes": ["rows_matvec", "null_solve", "cols_matvec"],
+              "box sums": ["q_partial"], "cell normal equations": ["cell_epilogue"], "fold": ["fold"],
+              "best period": ["best_period"]}
+    out["plain_1440_fp64"] = {
+        "workload": "plain-fp64-N1440", "us_per_step": el * 1e6,
+        "stage_kernel_us": {k: sum(tm[n]["ms"] for n in v if n in tm) / steps * 1e3 for k, v in stages.items()},
+        "launches_per_step": sum(v["launches"] for v in tm.values()) / steps}
+    log(f"extras: plain-1440 fp64 {el * 1e6:.0f} us per step")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -553,6 +631,10 @@ def main(argv=None):
     ap.add_argument("--prefetch-cus", type=int, default=0,
                     help="compute units of the inverse started inside the factorisation (0: three quarters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline curve only: skip the 64-curve batch (FP32_REFINE and FP64) and the "
+                         "1440-sample per-stage timings")
+    ap.add_argument("--extra-steps", type=int, default=2, help="timed batch launches per precision in the extras")
     ap.add_argument("--no-dll-check", action="store_true",
                     help="skip the FP64 reference search that measures the dll error of a reduced precision "
                          "(keeps a profiled run to the timed kernels)")
@@ -599,8 +681,6 @@ def main(argv=None):
         print(json.dumps(out), flush=True)
         return 0
     if args.workload == "batch-64":
-        if args.mode == "graph":
-            raise SystemExit("the batch runs through its own entry point (--mode eager, or loop)")
         elapsed, n_valid, curves, timings, dll_err, cfg, extra = bench_batch(args, api, ctx, torch)
     elif args.workload == "two-sectors":
         if args.mode != "eager" or args.planets > 1:
@@ -636,6 +716,10 @@ def main(argv=None):
         "tuning": tuning,
     }
     out.update(extra)
+    if (not args.no_extras and args.workload == "tess-sector" and args.mode == "eager" and args.solver == "dense"
+            and args.kernel == "sho" and args.template == "box" and args.planets == 1):
+        out["batch_64"] = bench_extras(args, api, ctx, torch)
+        out["plain_1440_fp64"] = out["batch_64"].pop("plain_1440_fp64")
     if not args.no_cpu_baseline and w is not None:
         shapes = None
         if args.template != "box":

@@ -343,14 +343,20 @@ nu_status nu_mask_transit(nu_ctx* ctx, double* depth, double* var, double* dll, 
  * NULL): ln|K| and -1 or the failing pivot.
  * The curves are processed longest first in waves whose factors fit in
  * memory_budget_bytes of device memory (0: 90 % of the free memory counting
- * the arena the context already holds as free); each dense stage of a wave is one launch
- * over all its curves. The factors live in a device arena of the size of the
- * largest wave, which the context keeps for later calls (released by
- * nu_ctx_release_memory or nu_ctx_destroy). The call synchronises the stream
- * once per wave and once before it returns. A curve whose covariance is not
- * positive definite gets invalid cells and no event at any period; the call
- * then finishes the other curves and returns NU_ERR_NOT_PD. A single curve
- * larger than the budget gives NU_ERR_OOM before any work. */
+ * the arena the context already holds as free). Every stage of a wave is one
+ * launch for all its curves: the covariance build, each Cholesky step's
+ * diagonal blocks and grouped GEMMs, each level of the inverse, each pass of
+ * the linear search, the fold over (period, curve) and the best periods, so
+ * a call issues a number of launches set by the stages and the waves, not by
+ * the curves. The factors and each curve's search workspace live in a device
+ * arena of the size of the largest wave, which the context keeps for later
+ * calls (released by nu_ctx_release_memory or nu_ctx_destroy). The call
+ * synchronises the stream once, before it returns. A curve whose covariance
+ * is not positive definite gets invalid cells, no event at any period and
+ * best_period_index -1; the call finishes the other curves and returns
+ * NU_ERR_NOT_PD. A single curve larger than the budget gives NU_ERR_OOM
+ * before any work. Each curve's outputs equal those of (1)-(3) on that curve
+ * alone, bit for bit. */
 nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_host, const int64_t* epoch_off_host,
                           const double* t, const double* f, const double* A, int m1, const int64_t* lattice,
                           const nu_sho* theta_host, const double* dt_host, const int32_t* dur_samples_host, int n_d,
@@ -359,6 +365,32 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
                           double* null_out, double* q_snr, int64_t* best_phase, int32_t* best_dur,
                           double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period_index,
                           double* logdet_host, int64_t* fail_pivot_host);
+
+/* (4b) Captured graph of the batch search (4): every stage of every wave of
+ * (4), recorded once into a HIP graph bound to these device buffers, with its
+ * own device arena (allocated here, before the capture; memory_budget_bytes
+ * as in (4), 0: 90 % of the free memory). Each nu_batch_graph_launch replays
+ * the whole batch on the context's stream in one graph launch and reads the
+ * current contents of t, f, A, lattice, periods and theta_dev (device,
+ * n_curves nu_sho: the caller may rewrite them between launches, in stream
+ * order). Nothing synchronises: status_dev (device, n_curves int64) receives
+ * -1 or the failing pivot of each curve, logdet_dev (device, n_curves, may be
+ * NULL) its ln|K|. Other arguments and outputs as in (4); the outputs of a
+ * launch equal those of (4) on the same inputs, bit for bit. Launches of one
+ * graph must not overlap. theta_dev is not validated: it must satisfy (1)'s
+ * bounds. */
+typedef struct nu_batch_graph nu_batch_graph;
+nu_status nu_batch_graph_create(nu_ctx* ctx, int n_curves, const int64_t* sample_off_host,
+                                const int64_t* epoch_off_host, const double* t, const double* f, const double* A,
+                                int m1, const int64_t* lattice, const nu_sho* theta_dev, const double* dt_host,
+                                const int32_t* dur_samples_host, int n_d, const double* periods, int64_t n_p,
+                                nu_precision prec, int log_term_sign, size_t memory_budget_bytes, double* depth,
+                                double* var, double* dll, uint8_t* valid, double* null_out, double* q_snr,
+                                int64_t* best_phase, int32_t* best_dur, double* best_depth, double* best_sigma,
+                                double* best_lnp, int64_t* best_period_index, int64_t* status_dev,
+                                double* logdet_dev, nu_batch_graph** out);
+nu_status nu_batch_graph_launch(nu_ctx* ctx, nu_batch_graph* graph);
+void nu_batch_graph_destroy(nu_batch_graph* graph);
 
 /* (5) Captured graph of the whole search of one light curve: K build,
  * Cholesky, inverse, linear search, periodic search and best period, as

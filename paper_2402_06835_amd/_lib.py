@@ -73,6 +73,13 @@ SIGNATURES = {
                                 ctypes.c_size_t, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(c_double),
                                 P(c_int64)]),
+    "nu_batch_graph_create": (c_int, [c_void_p, c_int, P(c_int64), P(c_int64), c_void_p, c_void_p, c_void_p, c_int,
+                                      c_void_p, c_void_p, P(c_double), P(c_int32), c_int, c_void_p, c_int64, c_int,
+                                      c_int, ctypes.c_size_t, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, P(c_void_p)]),
+    "nu_batch_graph_launch": (c_int, [c_void_p, c_void_p]),
+    "nu_batch_graph_destroy": (None, [c_void_p]),
     "nu_graph_create": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int, c_void_p,
                                 c_int64, P(c_int32), c_int, c_int, c_double, c_void_p, c_int64, c_int, c_void_p,
                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,

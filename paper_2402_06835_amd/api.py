@@ -614,6 +614,81 @@ def search_batch(ctx: Context, curves, durations, periods, precision: str = "fp3
     return out
 
 
+class BatchGraph:
+    """Captured graph of the batch search (entry point 4b): every stage of every wave of ``search_batch``
+    recorded once; ``launch()`` replays the whole batch in one graph launch on the context's stream, with no
+    synchronisation. Inputs are read from the prepared batch's device arrays and ``theta`` (device, one SHO per
+    curve; ``set_theta`` rewrites it); ``status`` receives -1 or the failing pivot per curve, ``logdet`` ln|K|.
+    Outputs as in ``search_batch``."""
+
+    def __init__(self, ctx: Context, curves, durations, periods, precision: str = "fp32_refine", sign: int = 1,
+                 memory_budget: int = 0):
+        dev = ctx.device
+        self.ctx = ctx
+        b = curves if isinstance(curves, dict) else prepare_batch(ctx, curves)
+        self.batch = b
+        nc, nes, soff, eoff = b["n_curves"], b["n_epochs"], b["sample_off"], b["epoch_off"]
+        self.durs = np.ascontiguousarray(np.asarray(durations, dtype=np.int32))
+        n_d = int(self.durs.size)
+        self.per = _dev_tensor(periods, torch.float64, dev)
+        n_p = self.per.numel()
+        cells = n_d * int(eoff[-1])
+        out = {k: torch.empty(cells, dtype=dt_, device=dev)
+               for k, dt_ in (("depth", torch.float64), ("var", torch.float64), ("dll", torch.float64),
+                              ("valid", torch.uint8))}
+        out["null"] = torch.empty((nc, 3), dtype=torch.float64, device=dev)
+        for k, dt_ in zip(_PERIOD_KEYS, _PERIOD_DTYPES):
+            out[k] = torch.empty((nc, n_p), dtype=dt_, device=dev)
+        out["best_index"] = torch.empty(nc, dtype=torch.int64, device=dev)
+        self.status = torch.empty(nc, dtype=torch.int64, device=dev)
+        self.logdet = torch.empty(nc, dtype=torch.float64, device=dev)
+        self.theta = torch.empty((nc, 4), dtype=torch.float64, device=dev)
+        self.theta.copy_(torch.tensor([[t.amp, t.omega, t.q, t.sigma_w] for t in b["theta"]], dtype=torch.float64))
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        P64 = ctypes.POINTER(ctypes.c_int64)
+        A = b["A"]
+        p = ctypes.c_void_p()
+        st = lib().nu_batch_graph_create(
+            ctx.ptr, nc, soff.ctypes.data_as(P64), eoff.ctypes.data_as(P64), ctypes.c_void_p(b["t"].data_ptr()),
+            ctypes.c_void_p(b["f"].data_ptr()), ctypes.c_void_p(A.data_ptr() if A is not None else 0), b["m1"],
+            ctypes.c_void_p(b["lattice"].data_ptr()), ctypes.c_void_p(self.theta.data_ptr()),
+            b["dt"].ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            self.durs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), n_d, ctypes.c_void_p(self.per.data_ptr()), n_p,
+            PRECISIONS[precision], int(sign), int(memory_budget),
+            *[ctypes.c_void_p(out[k].data_ptr()) for k in ("depth", "var", "dll", "valid", "null")],
+            *[ctypes.c_void_p(out[k].data_ptr()) for k in _PERIOD_KEYS],
+            ctypes.c_void_p(out["best_index"].data_ptr()), ctypes.c_void_p(self.status.data_ptr()),
+            ctypes.c_void_p(self.logdet.data_ptr()), ctypes.byref(p))
+        _check(ctx.ptr, st)
+        self.ptr = p
+        _register(self, 0)
+        out["cells"] = [{k: out[k][n_d * int(eoff[c]):n_d * int(eoff[c + 1])].view(n_d, nes[c])
+                         for k in ("depth", "var", "dll", "valid")} for c in range(nc)]
+        out["periods"] = [{k: out[k][c] for k in _PERIOD_KEYS} for c in range(nc)]
+        self.out = out
+
+    def set_theta(self, thetas):
+        """Rewrite the per-curve hyperparameters the next launch reads (stream-ordered copy)."""
+        rows = [t if isinstance(t, SHO) else SHO.from_dict(t) for t in thetas]
+        self.theta.copy_(torch.tensor([[t.amp, t.omega, t.q, t.sigma_w] for t in rows], dtype=torch.float64))
+
+    def launch(self) -> dict:
+        _check(self.ctx.ptr, lib().nu_batch_graph_launch(self.ctx.ptr, self.ptr))
+        return self.out
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().nu_batch_graph_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Graph:
     """Captured graph of the whole search of one light curve (entry point 5).
 

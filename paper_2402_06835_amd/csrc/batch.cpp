@@ -1,17 +1,23 @@
-// Batched search of light curves of uneven length, captured graphs of the
-// whole single-curve search, and the tile autotuner.
+// Batched search of light curves of uneven length, its captured graph, captured
+// graphs of the whole single-curve search, and the tile autotuner.
 //
 // Batch: the curves are ordered by length (longest first) and cut into waves
-// whose factors fit the device-memory budget; the factors of a wave are carved
+// whose factors fit the device-memory budget; the factors of a wave (and each
+// curve's search workspace, inside its factor's inverse workspace) are carved
 // from one device arena that the context keeps for later calls (allocating
-// and freeing hundreds of GB per call costs seconds). Within a wave every dense stage
-// is one launch for all curves: the diagonal blocks of Cholesky step k are
-// one launch of one workgroup per curve that has a block k, and the panel,
-// panel-update, trailing and inverse-level products of all curves form the
-// problem list of one grouped GEMM launch. The linear and periodic searches
-// then run curve by curve (each of their launches already covers the chip).
+// and freeing hundreds of GB per call costs seconds). Every stage of a wave is
+// one launch for all its curves: the covariance build, the diagonal blocks of
+// each Cholesky step (one workgroup per curve) and the grouped GEMMs of its
+// panel, panel-update and trailing products, each level of the inverse, every
+// pass of the linear search, the fold over (period, curve) and the best
+// periods. The per-curve records (CurveJob) and stage tables are built and
+// uploaded before anything is enqueued, and a failed factorisation is handled
+// on the device (its cells come out invalid), so the enqueue sequence neither
+// allocates nor synchronises: the eager call waits once, at its end, and the
+// same sequence is captured as one graph for replay.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <new>
 #include <numeric>
 
@@ -29,15 +35,6 @@ struct nu_graph {
 
 namespace {
 
-nu_status fail_batch(nu_ctx* ctx, std::vector<nu_factor*>& Fs, Plan* P, Plan* Q, nu_status st) {
-  (void)hipStreamSynchronize(ctx->stream);
-  if (P) plan_release(*P);
-  if (Q) plan_release(*Q);
-  for (nu_factor* F : Fs) factor_free(F);
-  Fs.clear();
-  return st;
-}
-
 const char* class_timing_name(int c) {
   static const char* names[TC_COUNT] = {"gemm_f64:panel",   "gemm_f64:panel_update", "gemm_f64:trailing",
                                         "gemm_f64:inverse", "gemm_f32:inverse",      "gemm_f64:band",
@@ -45,7 +42,342 @@ const char* class_timing_name(int c) {
   return names[c];
 }
 
+// ---------------------------------------------------------------------------
+// A batch cut into waves whose factors fit the memory budget; every wave is
+// searched by one launch per stage for all its curves (see CurveJob), its
+// factors carved from one arena reused wave after wave. Built on the host
+// before anything is enqueued (plans and tables uploaded), so that the
+// enqueue sequence itself allocates and synchronises nothing and can be
+// captured into a graph.
+struct BatchWave {
+  std::vector<int> curves;       // caller indices, longest first
+  std::vector<nu_factor*> Fs;    // placed in the arena
+  std::vector<CurveJob> jobs;    // host copies of the device records
+  std::vector<int> begin;        // [BS_COUNT][n + 1]
+  std::vector<int> total;        // workgroups per stage
+  Plan P, Q;                     // Cholesky; inverse (+ band)
+  CurveJob* djobs = nullptr;
+  int* dbegin = nullptr;
+  int n() const { return (int)curves.size(); }
+  const int* b(int stage) const { return dbegin + (size_t)stage * (n() + 1); }
+};
+
+struct BatchInputs {
+  int n_curves = 0;
+  const int64_t *sample_off = nullptr, *epoch_off = nullptr;
+  const double *t = nullptr, *f = nullptr, *A = nullptr;
+  int m1 = 0;
+  const int64_t* lattice = nullptr;
+  const nu_sho* theta_dev = nullptr;  // device, one per curve
+  const double* dt_host = nullptr;
+  const int32_t* dur = nullptr;       // host, caller order
+  int n_d = 0;
+  const double* periods = nullptr;
+  int64_t n_p = 0;
+  int prec = 0, sign = 1;
+  double *depth = nullptr, *var = nullptr, *dll = nullptr;
+  uint8_t* valid = nullptr;
+  double *null_out = nullptr, *q_snr = nullptr, *best_depth = nullptr, *best_sigma = nullptr, *best_lnp = nullptr;
+  int64_t* best_phase = nullptr;
+  int32_t* best_dur = nullptr;
+  int64_t* best_index = nullptr;
+  int64_t* status_out = nullptr;  // device, one per curve
+  double* logdet_out = nullptr;   // device, one per curve
+};
+
+struct BatchRun {
+  std::vector<BatchWave> waves;
+  void* tables = nullptr;  // device: every wave's jobs and begin tables
+  ~BatchRun() {
+    for (auto& w : waves) {
+      plan_release(w.P);
+      plan_release(w.Q);
+      for (nu_factor* F : w.Fs) factor_free(F);
+    }
+    if (tables) (void)hipFree(tables);
+  }
+};
+
+int64_t curve_n(const BatchInputs& in, int c) { return in.sample_off[c + 1] - in.sample_off[c]; }
+int64_t curve_ne(const BatchInputs& in, int c) { return in.epoch_off[c + 1] - in.epoch_off[c]; }
+size_t curve_t_min(const BatchInputs& in, int c) { return batch_search_ws_doubles(curve_n(in, c), in.n_d, curve_ne(in, c)); }
+size_t curve_bytes(const BatchInputs& in, int c) { return factor_bytes(curve_n(in, c), in.prec, curve_t_min(in, c)); }
+
+// waves of curves (longest first) whose factors fit `budget` bytes; the arena size they need
+nu_status plan_waves(nu_ctx* ctx, const BatchInputs& in, size_t budget, std::vector<std::vector<int>>& waves,
+                     size_t& arena_need) {
+  std::vector<int> order(in.n_curves);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return curve_n(in, a) > curve_n(in, b); });
+  size_t used = 0;
+  for (int c : order) {
+    const size_t need = curve_bytes(in, c);
+    if (need > budget)
+      return set_error(ctx, NU_ERR_OOM,
+                       "search_batch: curve " + std::to_string(c) + " does not fit the device-memory budget");
+    if (waves.empty() || used + need > budget) {
+      waves.emplace_back();
+      used = 0;
+    }
+    waves.back().push_back(c);
+    used += need;
+  }
+  arena_need = 0;
+  for (const auto& w : waves) {
+    size_t b = 0;
+    for (int c : w) b += curve_bytes(in, c);
+    arena_need = std::max(arena_need, b);
+  }
+  return NU_OK;
+}
+
+// factors, records, stage tables and schedules of every wave; uploads them
+nu_status build_batch(nu_ctx* ctx, const BatchInputs& in, const std::vector<std::vector<int>>& waves, char* arena,
+                      BatchRun& run) {
+  const bool mixed = in.prec != NU_FP64;
+  const int bw = mixed ? band_width(in.prec) : 0;
+  size_t table_bytes = 0;
+  run.waves.resize(waves.size());
+  for (size_t wi = 0; wi < waves.size(); ++wi) {
+    BatchWave& W = run.waves[wi];
+    W.curves = waves[wi];
+    char* cursor = arena;
+    for (int c : W.curves) {
+      nu_factor* F = nullptr;
+      nu_status st = factor_place(ctx, curve_n(in, c), in.prec, &cursor, &F, curve_t_min(in, c));
+      if (st != NU_OK) return st;
+      W.Fs.push_back(F);
+      CurveJob J{};
+      const int64_t s0 = in.sample_off[c], e0 = in.epoch_off[c], cells = (int64_t)in.n_d * e0;
+      J.t = in.t + s0;
+      J.theta = in.theta_dev + c;
+      J.L = F->L;
+      J.X = F->X;
+      J.L32 = F->L32;
+      J.X32 = F->X32;
+      J.bandX = F->bandX;
+      J.parts = F->parts();
+      J.logdet = F->logdet_dev();
+      J.status = F->status_dev();
+      J.nf = F->nullfit;
+      J.n = F->n;
+      J.np = F->np;
+      J.nblk = F->nblk;
+      J.f = in.f + s0;
+      J.A = in.m1 > 0 ? in.A + (int64_t)in.m1 * s0 : nullptr;
+      J.lattice = in.lattice + s0;
+      J.n_epochs = curve_ne(in, c);
+      batch_carve_search_ws(J, F->T, in.n_d);
+      J.depth = in.depth + cells;
+      J.var = in.var + cells;
+      J.dll = in.dll + cells;
+      J.valid = in.valid + cells;
+      J.null_out = in.null_out ? in.null_out + 3 * (int64_t)c : nullptr;
+      J.dt = in.dt_host[c];
+      J.q_snr = in.q_snr + (int64_t)c * in.n_p;
+      J.best_phase = in.best_phase + (int64_t)c * in.n_p;
+      J.best_dur = in.best_dur + (int64_t)c * in.n_p;
+      J.best_depth = in.best_depth + (int64_t)c * in.n_p;
+      J.best_sigma = in.best_sigma + (int64_t)c * in.n_p;
+      J.best_lnp = in.best_lnp + (int64_t)c * in.n_p;
+      J.best_index = in.best_index ? in.best_index + c : nullptr;
+      J.curve = c;
+      W.jobs.push_back(J);
+    }
+    const int n = W.n();
+    W.begin.assign((size_t)BS_COUNT * (n + 1), 0);
+    W.total.assign(BS_COUNT, 0);
+    for (int stg = 0; stg < BS_COUNT; ++stg) {
+      int64_t acc = 0;
+      for (int i = 0; i < n; ++i) {
+        W.begin[(size_t)stg * (n + 1) + i] = (int)acc;
+        acc += batch_stage_blocks(stg, W.jobs[i], in.n_d, bw);
+      }
+      if (acc > INT32_MAX) return set_error(ctx, NU_ERR_ARG, "search_batch: a stage exceeds 2^31 workgroups");
+      W.begin[(size_t)stg * (n + 1) + n] = (int)acc;
+      W.total[stg] = (int)acc;
+    }
+    table_bytes += (size_t)n * sizeof(CurveJob) + W.begin.size() * sizeof(int) + 256;
+    plan_cholesky(W.Fs, ctx->tuning, W.P);
+    nu_status st = plan_upload(ctx, W.P);
+    if (st != NU_OK) return st;
+    if (mixed) {
+      plan_inverse(W.Fs, gemm_kind_of(in.prec), ctx->tuning, W.Q);
+      plan_band(W.Fs, bw, ctx->tuning, W.Q);
+    } else {
+      plan_inverse(W.Fs, GK_F64, ctx->tuning, W.Q);
+    }
+    st = plan_upload(ctx, W.Q);
+    if (st != NU_OK) return st;
+  }
+  nu_status st = check_hip(ctx, hipMalloc(&run.tables, table_bytes), "alloc batch tables");
+  if (st != NU_OK) return st;
+  std::vector<char> host(table_bytes);
+  size_t off = 0;
+  for (BatchWave& W : run.waves) {
+    const size_t jb = (size_t)W.n() * sizeof(CurveJob);
+    std::memcpy(host.data() + off, W.jobs.data(), jb);
+    W.djobs = reinterpret_cast<CurveJob*>(static_cast<char*>(run.tables) + off);
+    off += jb;
+    const size_t bb = W.begin.size() * sizeof(int);
+    std::memcpy(host.data() + off, W.begin.data(), bb);
+    W.dbegin = reinterpret_cast<int*>(static_cast<char*>(run.tables) + off);
+    off = (off + bb + 255) / 256 * 256;
+  }
+  return check_hip(ctx, hipMemcpy(run.tables, host.data(), table_bytes, hipMemcpyHostToDevice),
+                   "upload batch tables");
+}
+
+// the stages of one wave, each one launch for all its curves
+nu_status enqueue_wave(nu_ctx* ctx, const BatchInputs& in, const BatchWave& W) {
+  hipStream_t s = ctx->stream;
+  const int n = W.n(), m1 = in.m1, nv = m1 + 1, n_d = in.n_d;
+  const bool mixed = in.prec != NU_FP64;
+  const int kind = gemm_kind_of(in.prec), steps = refine_steps(in.prec), bw = mixed ? band_width(in.prec) : 0;
+  double kflops = 0.0;
+  for (const CurveJob& J : W.jobs) kflops += (double)J.n * (double)(J.n + 1) / 2.0;
+  nu_status st = check_hip(ctx, launch_batch_init(s, W.djobs, n), "batch init");
+  if (st == NU_OK) {
+    Timed tm(ctx, "kbuild", kflops);
+    st = check_hip(ctx, launch_batch_kbuild(s, W.djobs, W.b(BS_KBUILD), n, W.total[BS_KBUILD]), "kbuild");
+  }
+  if (st == NU_OK) st = run_factor_steps(ctx, W.P);
+  if (st == NU_OK) st = check_hip(ctx, launch_batch_logdet(s, W.djobs, n), "logdet");
+  // the triangular inverse
+  if (st == NU_OK && mixed) {
+    const char* level_name = kind == GK_BF16X3 ? "gemm_bf16x3:inverse" : "gemm_f32:inverse";
+    {
+      Timed tm(ctx, "convert", 0.0);
+      st = check_hip(ctx, launch_batch_cvt_l(s, W.djobs, W.b(BS_CVT_L), n, W.total[BS_CVT_L]), "convert L");
+      if (st == NU_OK)
+        st = check_hip(ctx, launch_batch_cvt_xd(s, W.djobs, W.b(BS_CVT_XD), n, W.total[BS_CVT_XD]), "convert X");
+    }
+    for (size_t l = 0; st == NU_OK && l < W.Q.t1.size(); ++l) {
+      st = launch_range(ctx, W.Q, W.Q.t1[l], level_name, kind);
+      if (st == NU_OK) st = launch_range(ctx, W.Q, W.Q.t2[l], level_name, kind);
+    }
+    if (st == NU_OK) {
+      Timed tm(ctx, "convert", 0.0);
+      st = check_hip(ctx, launch_batch_cvt_back(s, W.djobs, W.b(BS_CVT_BACK), n, W.total[BS_CVT_BACK]), "convert X");
+    }
+    if (st == NU_OK)
+      st = check_hip(ctx, launch_batch_band_copy(s, W.djobs, W.b(BS_BAND), n, W.total[BS_BAND], bw, 1), "band copy");
+    if (st == NU_OK) st = launch_range(ctx, W.Q, W.Q.bandp, "gemm_f64:band", GK_F64);
+    if (st == NU_OK) st = launch_range(ctx, W.Q, W.Q.bandx, "gemm_f64:band", GK_F64);
+    if (st == NU_OK)
+      st = check_hip(ctx, launch_batch_band_copy(s, W.djobs, W.b(BS_BAND), n, W.total[BS_BAND], bw, 0), "band copy");
+  } else if (st == NU_OK) {
+    st = run_inverse_fp64(ctx, W.Q);
+  }
+  // the linear search
+  double gemv_bytes = 0.0;
+  for (const CurveJob& J : W.jobs) gemv_bytes += (double)J.n * (double)(J.n + 1) / 2.0 * 8.0;
+  if (st == NU_OK) st = check_hip(ctx, launch_batch_lattice_check(s, W.djobs, n), "lattice_check");
+  if (st == NU_OK) st = check_hip(ctx, launch_batch_pack_v(s, W.djobs, W.b(BS_PACKV), n, W.total[BS_PACKV], m1), "pack_v");
+  auto rows = [&](int mat, int vin, int base, double alpha, int out) {
+    return check_hip(ctx, launch_batch_rows(s, W.djobs, W.b(BS_ROWS), W.b(BS_ROWS_RED), n, W.total[BS_ROWS],
+                                            W.total[BS_ROWS_RED], nv, mat, vin, base, alpha, out),
+                     "rows_matvec");
+  };
+  auto cols = [&](int mat, int win, int base, double alpha, int out) {
+    return check_hip(ctx, launch_batch_cols(s, W.djobs, W.b(BS_COLS), W.b(BS_COLS_RED), n, W.total[BS_COLS],
+                                            W.total[BS_COLS_RED], nv, mat, win, base, alpha, out),
+                     "cols_matvec");
+  };
+  if (st == NU_OK) {
+    Timed tm(ctx, "rows_matvec", gemv_bytes * (1 + 2 * steps));
+    st = rows(MS_X, PS_V, PS_NONE, 1.0, PS_Y);
+    for (int r = 0; r < steps && st == NU_OK; ++r) {
+      st = rows(MS_L, PS_Y, PS_V, -1.0, PS_R);
+      if (st == NU_OK) st = rows(MS_X, PS_R, PS_Y, 1.0, PS_Y);
+    }
+  }
+  if (st == NU_OK) {
+    Timed tm(ctx, "null_solve", 0.0);
+    st = check_hip(ctx, launch_batch_null(s, W.djobs, n, m1), "null_solve");
+  }
+  if (st == NU_OK) {
+    Timed tm(ctx, "cols_matvec", gemv_bytes * (1 + 2 * steps));
+    st = cols(MS_X, PS_Y, PS_NONE, 1.0, PS_Z);
+    for (int r = 0; r < steps && st == NU_OK; ++r) {
+      st = cols(MS_L, PS_Z, PS_Y, -1.0, PS_RZ);
+      if (st == NU_OK) st = cols(MS_X, PS_RZ, PS_Z, 1.0, PS_Z);
+    }
+  }
+  std::vector<int32_t> order(n_d), sorted(2 * n_d);
+  for (int j = 0; j < n_d; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return in.dur[a] < in.dur[b]; });
+  int dmax = 0;
+  for (int k = 0; k < n_d; ++k) {
+    sorted[k] = in.dur[order[k]];
+    sorted[n_d + k] = order[k];
+    dmax = std::max(dmax, (int)in.dur[k]);
+  }
+  if (st == NU_OK) {
+    Timed tm(ctx, "q_partial", 0.0);
+    st = check_hip(ctx, launch_batch_slot_count(s, W.djobs, W.b(BS_SLOTS), n, W.total[BS_SLOTS]), "slot_count");
+    if (st == NU_OK)
+      st = check_hip(ctx, launch_batch_q_partial(s, W.djobs, W.b(BS_QPART), n, W.total[BS_QPART], sorted.data(), n_d,
+                                                 dmax),
+                     "q_partial");
+  }
+  if (st == NU_OK) {
+    Timed tm(ctx, "cell_epilogue", 0.0);
+    st = check_hip(ctx, launch_batch_epilogue(s, W.djobs, W.b(BS_EPI), n, W.total[BS_EPI], in.dur, n_d, m1),
+                   "cell_epilogue");
+  }
+  // the periodic search
+  if (st == NU_OK) {
+    double visits = 0.0;
+    for (const CurveJob& J : W.jobs) visits += (double)n_d * (double)J.n_epochs * (double)in.n_p;
+    Timed tm(ctx, "fold", FOLD_FLOPS_PER_VISIT * visits);
+    st = check_hip(ctx, launch_batch_fold(s, W.djobs, W.b(BS_FOLD_PACK), n, W.total[BS_FOLD_PACK], n_d, in.periods,
+                                          in.n_p, in.sign),
+                   "fold");
+  }
+  if (st == NU_OK) {
+    Timed tm(ctx, "best_period", 0.0);
+    st = check_hip(ctx, launch_batch_best(s, W.djobs, n, in.n_p), "best_period");
+  }
+  if (st == NU_OK)
+    st = check_hip(ctx, launch_batch_collect(s, W.djobs, n, in.status_out, in.logdet_out), "batch collect");
+  return st;
+}
+
+nu_status validate_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_host, const int64_t* epoch_off_host,
+                         const double* t, const double* f, const double* A, int m1, const int64_t* lattice,
+                         const double* dt_host, const int32_t* dur_samples_host, int n_d, const double* periods,
+                         int64_t n_p, nu_precision prec, int log_term_sign, double* depth, double* var, double* dll,
+                         uint8_t* valid, const void* q_snr, const void* best_phase, const void* best_dur,
+                         const void* best_depth, const void* best_sigma, const void* best_lnp) {
+  if (n_curves < 1) return set_error(ctx, NU_ERR_ARG, "search_batch: n_curves must be >= 1");
+  if (!sample_off_host || !epoch_off_host || !t || !dt_host || !periods || !q_snr || !best_phase || !best_dur ||
+      !best_depth || !best_sigma || !best_lnp)
+    return set_error(ctx, NU_ERR_ARG, "search_batch: null argument");
+  if (sample_off_host[0] != 0 || epoch_off_host[0] != 0)
+    return set_error(ctx, NU_ERR_ARG, "search_batch: offsets must start at 0");
+  for (int c = 0; c < n_curves; ++c) {
+    const int64_t n = sample_off_host[c + 1] - sample_off_host[c];
+    const int64_t ne = epoch_off_host[c + 1] - epoch_off_host[c];
+    if (n < 1 || n > (int64_t)1 << 17)
+      return set_error(ctx, NU_ERR_ARG, "search_batch: every curve needs 1 .. 131072 samples");
+    nu_status st = validate_linear(ctx, n, f, A, m1, lattice, ne, dur_samples_host, n_d, prec, depth, var, dll, valid);
+    if (st == NU_OK) st = validate_periodic(ctx, n_d, ne, dt_host[c], n_p, log_term_sign);
+    if (st != NU_OK) return set_error(ctx, st, ctx->last_error + " (curve " + std::to_string(c) + ")");
+  }
+  return NU_OK;
+}
+
 }  // namespace
+
+struct nu_batch_graph {
+  int device = 0;
+  void* arena = nullptr;    // the graph's own factors
+  double* logdet = nullptr;  // ln|K| per curve when the caller passes none
+  BatchRun run;              // schedules, tables, placed factors
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -59,36 +391,56 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
                           double* best_depth, double* best_sigma, double* best_lnp, int64_t* best_period_index,
                           double* logdet_host, int64_t* fail_pivot_host) {
   if (!ctx) return NU_ERR_ARG;
-  if (n_curves < 1) return set_error(ctx, NU_ERR_ARG, "search_batch: n_curves must be >= 1");
-  if (!sample_off_host || !epoch_off_host || !t || !theta_host || !dt_host || !periods || !q_snr || !best_phase ||
-      !best_dur || !best_depth || !best_sigma || !best_lnp)
-    return set_error(ctx, NU_ERR_ARG, "search_batch: null argument");
-  if (sample_off_host[0] != 0 || epoch_off_host[0] != 0)
-    return set_error(ctx, NU_ERR_ARG, "search_batch: offsets must start at 0");
+  if (!theta_host) return set_error(ctx, NU_ERR_ARG, "search_batch: null argument");
+  nu_status st = validate_batch(ctx, n_curves, sample_off_host, epoch_off_host, t, f, A, m1, lattice, dt_host,
+                                dur_samples_host, n_d, periods, n_p, prec, log_term_sign, depth, var, dll, valid, q_snr,
+                                best_phase, best_dur, best_depth, best_sigma, best_lnp);
+  if (st != NU_OK) return st;
   for (int c = 0; c < n_curves; ++c) {
-    const int64_t n = sample_off_host[c + 1] - sample_off_host[c];
-    const int64_t ne = epoch_off_host[c + 1] - epoch_off_host[c];
-    if (n < 1 || n > (int64_t)1 << 17)
-      return set_error(ctx, NU_ERR_ARG, "search_batch: every curve needs 1 .. 131072 samples");
-    nu_status st = validate_theta(ctx, &theta_host[c]);
-    if (st == NU_OK)
-      st = validate_linear(ctx, n, f, A, m1, lattice, ne, dur_samples_host, n_d, prec, depth, var, dll, valid);
-    if (st == NU_OK) st = validate_periodic(ctx, n_d, ne, dt_host[c], n_p, log_term_sign);
+    st = validate_theta(ctx, &theta_host[c]);
     if (st != NU_OK) return set_error(ctx, st, ctx->last_error + " (curve " + std::to_string(c) + ")");
   }
-  nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (st != NU_OK) return st;
-  const bool mixed = prec != NU_FP64;
 
-  // shared workspace of the per-curve searches, sized for the largest curve
-  size_t ws_need = 0;
-  for (int c = 0; c < n_curves; ++c) {
-    const int64_t n = sample_off_host[c + 1] - sample_off_host[c];
-    const int64_t ne = epoch_off_host[c + 1] - epoch_off_host[c];
-    ws_need = std::max({ws_need, linear_ws_bytes(n, n_d, ne), periodic_ws_bytes(n_d, ne)});
-  }
-  double* ws = (double*)ctx_workspace(ctx, ws_need, &st);
-  if (!ws) return st;
+  BatchInputs in;
+  in.n_curves = n_curves;
+  in.sample_off = sample_off_host;
+  in.epoch_off = epoch_off_host;
+  in.t = t;
+  in.f = f;
+  in.A = A;
+  in.m1 = m1;
+  in.lattice = lattice;
+  in.dt_host = dt_host;
+  in.dur = dur_samples_host;
+  in.n_d = n_d;
+  in.periods = periods;
+  in.n_p = n_p;
+  in.prec = prec;
+  in.sign = log_term_sign;
+  in.depth = depth;
+  in.var = var;
+  in.dll = dll;
+  in.valid = valid;
+  in.null_out = null_out;
+  in.q_snr = q_snr;
+  in.best_phase = best_phase;
+  in.best_dur = best_dur;
+  in.best_depth = best_depth;
+  in.best_sigma = best_sigma;
+  in.best_lnp = best_lnp;
+  in.best_index = best_period_index;
+
+  // per-curve hyperparameters, statuses and ln|K| in the context's workspace
+  const size_t small_bytes = (size_t)n_curves * (sizeof(nu_sho) + sizeof(int64_t) + sizeof(double));
+  char* small = (char*)ctx_workspace(ctx, small_bytes, &st);
+  if (!small) return st;
+  in.theta_dev = reinterpret_cast<const nu_sho*>(small);
+  in.status_out = reinterpret_cast<int64_t*>(small + (size_t)n_curves * sizeof(nu_sho));
+  in.logdet_out = reinterpret_cast<double*>(small + (size_t)n_curves * (sizeof(nu_sho) + sizeof(int64_t)));
+  st = ctx_upload(ctx, theta_host, (size_t)n_curves * sizeof(nu_sho), small);
+  if (st != NU_OK) return st;
 
   // the budget counts the arena this context already holds as available
   size_t budget = memory_budget_bytes;
@@ -98,148 +450,188 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
     if (st != NU_OK) return st;
     budget = (free_b + ctx->arena_bytes) / 10 * 9;
   }
-
-  // longest curves first, cut into waves that fit the budget
-  std::vector<int> order(n_curves);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return sample_off_host[a + 1] - sample_off_host[a] > sample_off_host[b + 1] - sample_off_host[b];
-  });
   std::vector<std::vector<int>> waves;
-  size_t used = 0;
-  for (int c : order) {
-    const size_t need = factor_bytes(sample_off_host[c + 1] - sample_off_host[c], prec);
-    if (need > budget)
-      return set_error(ctx, NU_ERR_OOM, "search_batch: curve " + std::to_string(c) +
-                                            " does not fit the device-memory budget");
-    if (waves.empty() || used + need > budget) {
-      waves.emplace_back();
-      used = 0;
-    }
-    waves.back().push_back(c);
-    used += need;
-  }
   size_t arena_need = 0;
-  for (const auto& wave : waves) {
-    size_t b = 0;
-    for (int c : wave) b += factor_bytes(sample_off_host[c + 1] - sample_off_host[c], prec);
-    arena_need = std::max(arena_need, b);
-  }
+  st = plan_waves(ctx, in, budget, waves, arena_need);
+  if (st != NU_OK) return st;
   char* arena = nullptr;
   {
     HostTimed ht(ctx, "batch_arena");
     arena = (char*)ctx_arena(ctx, arena_need, &st);
   }
   if (!arena) return st;
-
-  int n_failed = 0;
-  int first_failed = -1;
-  for (const auto& wave : waves) {
-    std::vector<nu_factor*> Fs;
-    {
-      HostTimed ht(ctx, "batch_place");
-      char* cursor = arena;
-      for (int c : wave) {
-        nu_factor* F = nullptr;
-        st = factor_place(ctx, sample_off_host[c + 1] - sample_off_host[c], prec, &cursor, &F);
-        if (st != NU_OK) break;
-        Fs.push_back(F);
-        F->theta_host = theta_host[c];
-        st = check_hip(ctx, hipMemcpyAsync(F->theta_dev(), &F->theta_host, sizeof(nu_sho), hipMemcpyHostToDevice,
-                                           ctx->stream),
-                       "upload theta");
-        if (st != NU_OK) break;
-      }
+  BatchRun run;
+  {
+    HostTimed ht(ctx, "batch_plan");
+    st = build_batch(ctx, in, waves, arena, run);
+  }
+  for (size_t w = 0; st == NU_OK && w < run.waves.size(); ++w) st = enqueue_wave(ctx, in, run.waves[w]);
+  std::vector<int64_t> status(n_curves, -1);
+  std::vector<double> logdet(n_curves, 0.0);
+  if (st == NU_OK) {
+    HostTimed ht(ctx, "batch_wait");
+    st = check_hip(ctx, hipMemcpyAsync(status.data(), in.status_out, (size_t)n_curves * sizeof(int64_t),
+                                       hipMemcpyDeviceToHost, ctx->stream),
+                   "read statuses");
+    if (st == NU_OK)
+      st = check_hip(ctx, hipMemcpyAsync(logdet.data(), in.logdet_out, (size_t)n_curves * sizeof(double),
+                                         hipMemcpyDeviceToHost, ctx->stream),
+                     "read logdets");
+    if (st == NU_OK) st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "batch sync");
+  } else {
+    (void)hipStreamSynchronize(ctx->stream);  // nothing of the run may be freed while it is queued
+  }
+  if (st != NU_OK) return st;
+  int n_failed = 0, first_failed = -1;
+  for (int c = 0; c < n_curves; ++c) {
+    if (logdet_host) logdet_host[c] = logdet[c];
+    if (fail_pivot_host) fail_pivot_host[c] = status[c];
+    if (status[c] >= 0) {
+      if (first_failed < 0) first_failed = c;
+      ++n_failed;
     }
-    if (st != NU_OK) return fail_batch(ctx, Fs, nullptr, nullptr, st);
-    Plan P, Q;
-    {
-      HostTimed ht(ctx, "batch_plan");
-      plan_cholesky(Fs, ctx->tuning, P);
-      st = plan_upload(ctx, P);
-    }
-    std::vector<const double*> ts;
-    std::vector<const nu_sho*> th;
-    for (size_t i = 0; i < wave.size(); ++i) {
-      ts.push_back(t + sample_off_host[wave[i]]);
-      th.push_back(Fs[i]->theta_dev());
-    }
-    if (st == NU_OK) st = run_factor(ctx, Fs, P, ts, th);
-    std::vector<int64_t> status;
-    if (st == NU_OK) {
-      HostTimed ht(ctx, "batch_factor_wait");
-      st = read_factor_status(ctx, Fs, status);
-    }
-    if (st != NU_OK) return fail_batch(ctx, Fs, &P, &Q, st);
-
-    std::vector<nu_factor*> ok;
-    for (size_t i = 0; i < wave.size(); ++i) {
-      const int c = wave[i];
-      if (logdet_host) logdet_host[c] = Fs[i]->logdet;
-      if (fail_pivot_host) fail_pivot_host[c] = status[i];
-      if (status[i] < 0) {
-        ok.push_back(Fs[i]);
-      } else {
-        if (first_failed < 0) first_failed = c;
-        ++n_failed;
-      }
-    }
-    if (!ok.empty()) {
-      HostTimed ht(ctx, "batch_inverse_setup");
-      if (mixed) {
-        if (st == NU_OK) {
-          plan_inverse(ok, gemm_kind_of(prec), ctx->tuning, Q);
-          plan_band(ok, band_width(prec), ctx->tuning, Q);
-          st = plan_upload(ctx, Q);
-        }
-        if (st == NU_OK) st = run_inverse_mixed(ctx, ok, Q, prec);
-      } else {
-        plan_inverse(ok, GK_F64, ctx->tuning, Q);
-        st = plan_upload(ctx, Q);
-        if (st == NU_OK) st = run_inverse_fp64(ctx, Q);
-      }
-    }
-    for (size_t i = 0; st == NU_OK && i < wave.size(); ++i) {
-      const int c = wave[i];
-      const int64_t s0 = sample_off_host[c], e0 = epoch_off_host[c];
-      const int64_t ne = epoch_off_host[c + 1] - e0;
-      const int64_t cells = (int64_t)n_d * e0;
-      double* qs = q_snr + (int64_t)c * n_p;
-      int64_t* bp = best_phase + (int64_t)c * n_p;
-      int32_t* bd = best_dur + (int64_t)c * n_p;
-      double* bdep = best_depth + (int64_t)c * n_p;
-      double* bsig = best_sigma + (int64_t)c * n_p;
-      double* blnp = best_lnp + (int64_t)c * n_p;
-      int64_t* bpi = best_period_index ? best_period_index + c : nullptr;
-      if (status[i] >= 0) {
-        st = check_hip(ctx, launch_fill_invalid_cells(ctx->stream, (int64_t)n_d * ne, depth + cells, var + cells,
-                                                      dll + cells, valid + cells),
-                       "fill invalid");
-        if (st == NU_OK)
-          st = check_hip(ctx, launch_fill_no_event(ctx->stream, n_p, qs, bp, bd, bdep, bsig, blnp, bpi),
-                         "fill no event");
-        continue;
-      }
-      st = run_linear(ctx, Fs[i], f + s0, m1 > 0 ? A + (int64_t)m1 * s0 : nullptr, m1, lattice + s0, ne,
-                      dur_samples_host, n_d, prec, depth + cells, var + cells, dll + cells, valid + cells,
-                      null_out ? null_out + 3 * (int64_t)c : nullptr, ws);
-      if (st == NU_OK)
-        st = run_periodic(ctx, depth + cells, var + cells, dll + cells, valid + cells, n_d, ne, dt_host[c],
-                          periods, n_p, log_term_sign, qs, bp, bd, bdep, bsig, blnp, bpi, ws);
-    }
-    // the factors go before the next wave is allocated
-    nu_status st2;
-    {
-      HostTimed ht(ctx, "batch_wait_free");
-      st2 = fail_batch(ctx, Fs, &P, &Q, st);
-    }
-    if (st2 != NU_OK) return st2;
   }
   if (n_failed > 0)
     return set_error(ctx, NU_ERR_NOT_PD,
                      "search_batch: " + std::to_string(n_failed) + " covariance(s) not positive definite (first: curve " +
                          std::to_string(first_failed) + "); their outputs hold no candidate");
   return NU_OK;
+}
+
+// ---------------------------------------------------------------------------
+nu_status nu_batch_graph_create(nu_ctx* ctx, int n_curves, const int64_t* sample_off_host,
+                                const int64_t* epoch_off_host, const double* t, const double* f, const double* A,
+                                int m1, const int64_t* lattice, const nu_sho* theta_dev, const double* dt_host,
+                                const int32_t* dur_samples_host, int n_d, const double* periods, int64_t n_p,
+                                nu_precision prec, int log_term_sign, size_t memory_budget_bytes, double* depth,
+                                double* var, double* dll, uint8_t* valid, double* null_out, double* q_snr,
+                                int64_t* best_phase, int32_t* best_dur, double* best_depth, double* best_sigma,
+                                double* best_lnp, int64_t* best_period_index, int64_t* status_dev,
+                                double* logdet_dev, nu_batch_graph** out) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!out || !theta_dev || !status_dev) return set_error(ctx, NU_ERR_ARG, "batch_graph_create: null argument");
+  *out = nullptr;
+  nu_status st = validate_batch(ctx, n_curves, sample_off_host, epoch_off_host, t, f, A, m1, lattice, dt_host,
+                                dur_samples_host, n_d, periods, n_p, prec, log_term_sign, depth, var, dll, valid, q_snr,
+                                best_phase, best_dur, best_depth, best_sigma, best_lnp);
+  if (st != NU_OK) return st;
+  st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+  nu_batch_graph* g = new (std::nothrow) nu_batch_graph();
+  if (!g) return set_error(ctx, NU_ERR_OOM, "batch_graph_create: host allocation");
+  g->device = ctx->device;
+  auto fail = [&](nu_status e) {
+    nu_batch_graph_destroy(g);
+    return e;
+  };
+  BatchInputs in;
+  in.n_curves = n_curves;
+  in.sample_off = sample_off_host;
+  in.epoch_off = epoch_off_host;
+  in.t = t;
+  in.f = f;
+  in.A = A;
+  in.m1 = m1;
+  in.lattice = lattice;
+  in.theta_dev = theta_dev;
+  in.dt_host = dt_host;
+  in.dur = dur_samples_host;
+  in.n_d = n_d;
+  in.periods = periods;
+  in.n_p = n_p;
+  in.prec = prec;
+  in.sign = log_term_sign;
+  in.depth = depth;
+  in.var = var;
+  in.dll = dll;
+  in.valid = valid;
+  in.null_out = null_out;
+  in.q_snr = q_snr;
+  in.best_phase = best_phase;
+  in.best_dur = best_dur;
+  in.best_depth = best_depth;
+  in.best_sigma = best_sigma;
+  in.best_lnp = best_lnp;
+  in.best_index = best_period_index;
+  in.status_out = status_dev;
+  if (!logdet_dev) {
+    st = check_hip(ctx, hipMalloc(&g->logdet, (size_t)n_curves * sizeof(double)), "alloc logdet");
+    if (st != NU_OK) return fail(st);
+    logdet_dev = g->logdet;
+  }
+  in.logdet_out = logdet_dev;
+  // every allocation happens before the capture: the graph's own arena, schedules and tables
+  size_t budget = memory_budget_bytes;
+  if (budget == 0) {
+    size_t free_b = 0, total_b = 0;
+    st = check_hip(ctx, hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    if (st != NU_OK) return fail(st);
+    budget = free_b / 10 * 9;
+  }
+  std::vector<std::vector<int>> waves;
+  size_t arena_need = 0;
+  st = plan_waves(ctx, in, budget, waves, arena_need);
+  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&g->arena, std::max<size_t>(arena_need, 256)), "alloc graph arena");
+  if (st == NU_OK) st = build_batch(ctx, in, waves, (char*)g->arena, g->run);
+  if (st != NU_OK) return fail(st);
+
+  hipStream_t cs = nullptr;
+  st = check_hip(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+  if (st != NU_OK) return fail(st);
+  const hipStream_t saved_stream = ctx->stream;
+  const bool saved_timing = ctx->timing;
+  ctx->stream = cs;
+  ctx->timing = false;
+  st = check_hip(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (st == NU_OK) {
+    nu_status cst = NU_OK;
+    for (size_t w = 0; cst == NU_OK && w < g->run.waves.size(); ++w) cst = enqueue_wave(ctx, in, g->run.waves[w]);
+    st = check_hip(ctx, hipStreamEndCapture(cs, &g->graph), "end capture");
+    if (cst != NU_OK) st = cst;
+  }
+  ctx->stream = saved_stream;
+  ctx->timing = saved_timing;
+  (void)hipStreamDestroy(cs);
+  if (st == NU_OK) st = check_hip(ctx, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0), "instantiate");
+  if (st != NU_OK) return fail(st);
+  *out = g;
+  return NU_OK;
+}
+
+nu_status nu_batch_graph_launch(nu_ctx* ctx, nu_batch_graph* g) {
+  if (!ctx) return NU_ERR_ARG;
+  if (!g || !g->exec) return set_error(ctx, NU_ERR_ARG, "batch_graph_launch: null graph");
+  if (g->device != ctx->device) return set_error(ctx, NU_ERR_ARG, "batch_graph_launch: graph on another device");
+  nu_status st = check_hip(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != NU_OK) return st;
+  return check_hip(ctx, hipGraphLaunch(g->exec, ctx->stream), "batch graph launch");
+}
+
+void nu_batch_graph_destroy(nu_batch_graph* g) {
+  if (!g) return;
+  if (hipSetDevice(g->device) != hipSuccess) {  // the runtime has shut down: host side only
+    for (auto& w : g->run.waves) {
+      w.P = Plan();
+      w.Q = Plan();
+      for (nu_factor*& F : w.Fs) {
+        F->plan64 = Plan();
+        F->plan32 = Plan();
+        delete F;
+        F = nullptr;
+      }
+      w.Fs.clear();
+    }
+    g->run.waves.clear();
+    g->run.tables = nullptr;
+    delete g;
+    return;
+  }
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->arena) (void)hipFree(g->arena);
+  if (g->logdet) (void)hipFree(g->logdet);
+  delete g;  // the schedules, tables and factor records go with g->run
 }
 
 // ---------------------------------------------------------------------------

@@ -392,12 +392,13 @@ constexpr size_t ARENA_ALIGN = 256;
 size_t aligned(size_t b) { return (b + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN; }
 
 // device bytes of each buffer of a factor of n samples, in carving order
-// (prec != NU_FP64: with the reduced-precision buffers, band sized for prec)
-std::vector<size_t> factor_buffer_bytes(int64_t n, int prec) {
+// (prec != NU_FP64: with the reduced-precision buffers, band sized for prec;
+// the T workspace holds at least t_min doubles)
+std::vector<size_t> factor_buffer_bytes(int64_t n, int prec, size_t t_min) {
   const int64_t np = round_up(n, TB);
   const int nblk = (int)(np / TB);
   std::vector<size_t> b = {(size_t)np * np * sizeof(double), (size_t)np * np * sizeof(double),
-                           inverse_t_elems(nblk) * sizeof(double),
+                           std::max(inverse_t_elems(nblk), t_min) * sizeof(double),
                            (size_t)(nblk + FACTOR_SMALL_EXTRA) * sizeof(double), sizeof(NullFit)};
   if (prec != NU_FP64) {
     const size_t band = (size_t)nblk * (band_width(prec) + 1) * TB * TB * sizeof(double);
@@ -418,9 +419,9 @@ nu_factor* new_factor(nu_ctx* ctx, int64_t n) {
 }
 }  // namespace
 
-size_t factor_bytes(int64_t n, int prec) {
+size_t factor_bytes(int64_t n, int prec, size_t t_min) {
   size_t s = 0;
-  for (size_t b : factor_buffer_bytes(n, prec)) s += aligned(b);
+  for (size_t b : factor_buffer_bytes(n, prec, t_min)) s += aligned(b);
   return s;
 }
 
@@ -453,12 +454,13 @@ nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out) {
 // A factor whose buffers (and, for prec != NU_FP64, its reduced-precision buffers) are
 // carved from caller-owned device memory at *cursor (factor_bytes(n, prec)
 // bytes, 256-byte aligned); the factor does not free them.
-nu_status factor_place(nu_ctx* ctx, int64_t n, int prec, char** cursor, nu_factor** out) {
+nu_status factor_place(nu_ctx* ctx, int64_t n, int prec, char** cursor, nu_factor** out, size_t t_min) {
   *out = nullptr;
   nu_factor* F = new_factor(ctx, n);
   if (!F) return set_error(ctx, NU_ERR_OOM, "factor: host allocation");
   F->owns_memory = false;
-  const std::vector<size_t> sz = factor_buffer_bytes(n, prec);
+  const std::vector<size_t> sz = factor_buffer_bytes(n, prec, t_min);
+  F->t_elems = std::max(F->t_elems, t_min);
   if (prec != NU_FP64) F->band_w = band_width(prec);
   void** slots[] = {(void**)&F->L,  (void**)&F->X,   (void**)&F->T,     (void**)&F->small, (void**)&F->nullfit,
                     (void**)&F->L32, (void**)&F->X32, (void**)&F->bandP, (void**)&F->bandX};
@@ -635,6 +637,15 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
                      "kbuild");
     }
   }
+  if (st == NU_OK) st = run_factor_steps(ctx, P, early);
+  for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i)
+    st = check_hip(ctx, launch_logdet_reduce(ctx->stream, Fs[i]->parts(), Fs[i]->nblk, Fs[i]->logdet_dev()),
+                   "logdet");
+  return st;
+}
+
+nu_status run_factor_steps(nu_ctx* ctx, const Plan& P, const EarlyInverse* early) {
+  nu_status st = NU_OK;
   // Blocked right-looking Cholesky, two levels: within a panel of PANEL
   // blocks, diagonal block -> its column (times the diagonal block's inverse)
   // -> update of the panel's remaining columns; after the panel, one trailing
@@ -729,9 +740,6 @@ nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan&
     if (st == NU_OK) st = sj;
   }
   if (early && st != NU_OK) early->started = 0;
-  for (size_t i = 0; st == NU_OK && i < Fs.size(); ++i)
-    st = check_hip(ctx, launch_logdet_reduce(ctx->stream, Fs[i]->parts(), Fs[i]->nblk, Fs[i]->logdet_dev()),
-                   "logdet");
   return st;
 }
 
@@ -847,12 +855,12 @@ namespace {
 // transposed products take XRC rows per partial (512: 0.96 ms for the three
 // passes; 1024: 1.50; 256: 1.02), the row products RCW columns (2048: 0.89 ms;
 // 1024: 0.95; 512: 1.23). Both share one partial buffer of XRC chunks.
-constexpr int XRC = 512;
-constexpr int RCW = 2048;
+constexpr int XRC = LIN_XRC;
+constexpr int RCW = LIN_RCW;
 static_assert(RCW % XRC == 0, "row-product partials fit the buffer of the transposed ones");
 // rows per partial of the box sums of squares (one wave each: latency bound,
 // so many; 256: 0.89 ms at N = 18000, 512: 1.02, 1024: 1.31)
-constexpr int QRC = 256;
+constexpr int QRC = LIN_QRC;
 }  // namespace
 
 size_t linear_ws_bytes(int64_t n, int n_d, int64_t n_epochs) {
@@ -988,6 +996,60 @@ nu_status run_linear(nu_ctx* ctx, nu_factor* F, const double* f, const double* A
                    "cell_epilogue");
   }
   return st;
+}
+
+// ---------------------------------------------------------------------------
+// Per-curve search workspace of a batch (inside the factor's T region, which
+// the inverse no longer needs once the linear search starts): the linear
+// search's panels, partials and slot table, and the fold's packed grid.
+
+size_t batch_search_ws_doubles(int64_t n, int n_d, int64_t n_epochs) {
+  const int64_t np = round_up(n, TB);
+  const size_t xchunks = (size_t)((n + XRC - 1) / XRC), qchunks = (size_t)((n + QRC - 1) / QRC);
+  const size_t yz = (size_t)np * YCOLS;
+  return 5 * yz + xchunks * yz + qchunks * (size_t)n_d * (size_t)n_epochs + ((size_t)n_epochs + 2) / 2 + 1 +
+         fold_workspace_doubles(n_d, n_epochs);
+}
+
+void batch_carve_search_ws(CurveJob& J, double* ws, int n_d) {
+  const int64_t n = J.n, np = J.np;
+  J.xchunks = (int)((n + XRC - 1) / XRC);
+  J.rchunks = (int)((n + RCW - 1) / RCW);
+  J.qchunks = (int)((n + QRC - 1) / QRC);
+  const size_t yz = (size_t)np * YCOLS;
+  J.V = ws;
+  J.Y = J.V + yz;
+  J.R = J.Y + yz;
+  J.Z = J.R + yz;
+  J.Rz = J.Z + yz;
+  J.xpart = J.Rz + yz;
+  J.qpart = J.xpart + (size_t)J.xchunks * yz;
+  double* slots = J.qpart + (size_t)J.qchunks * n_d * J.n_epochs;
+  J.slot_count = reinterpret_cast<int32_t*>(slots);
+  double* flag = slots + ((size_t)J.n_epochs + 2) / 2;
+  J.lattice_ok = reinterpret_cast<int*>(flag);
+  J.packed = flag + 1;
+}
+
+int64_t linear_stage_blocks(int stage, const CurveJob& J, int n_d);  // linear.hip
+
+int64_t batch_stage_blocks(int stage, const CurveJob& J, int n_d, int band_w) {
+  const int64_t nb = J.nblk;
+  switch (stage) {
+    case BS_INIT: return 0;  // one thread per curve
+    case BS_KBUILD: {
+      const int64_t T = J.np / 64;
+      return T * (T + 1) / 2;
+    }
+    case BS_LOGDET: return 1;
+    case BS_CVT_L: return nb * (nb + 1) / 2;
+    case BS_CVT_XD: return nb;
+    case BS_CVT_BACK: return nb * (nb - 1) / 2;
+    case BS_BAND: return nb > 1 ? nb * band_w : 0;
+    case BS_FOLD_PACK: return ((int64_t)n_d * (J.n_epochs + 64) + 255) / 256;
+    case BS_BEST: return 1;
+    default: return linear_stage_blocks(stage, J, n_d);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -5,6 +5,7 @@
 // Appendix A; ln|K| = 2 sum ln L_nn enters Eq. 5.
 #include <algorithm>
 
+#include "batch_dev.hpp"
 #include "internal.hpp"
 
 namespace nu {
@@ -25,11 +26,10 @@ __device__ __forceinline__ double sho_cov(double tau, double amp, double omega, 
 }
 
 // Lower triangle of K, padded: rows/columns n >= N hold the identity.
-// Grid: (np/64, np/64) blocks of 64 x 64; upper blocks exit at once.
-__global__ __launch_bounds__(256) void kbuild_kernel(const double* __restrict__ t, int64_t n, int64_t np,
-                                                     const nu_sho* __restrict__ th, double* __restrict__ K) {
-  const int64_t br = blockIdx.y, bc = blockIdx.x;
-  if (bc > br) return;
+// One 64 x 64 block (br, bc), bc <= br, per workgroup.
+__device__ __forceinline__ void kbuild_block(const double* __restrict__ t, int64_t n, int64_t np,
+                                             const nu_sho* __restrict__ th, double* __restrict__ K, int64_t br,
+                                             int64_t bc) {
   const double amp = th->amp, omega = th->omega, q = th->q, s2w = th->sigma_w * th->sigma_w;
   const int64_t r0 = br * 64, c0 = bc * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 columns x 4 rows per pass
@@ -47,6 +47,14 @@ __global__ __launch_bounds__(256) void kbuild_kernel(const double* __restrict__ 
     }
     K[row * np + col] = v;
   }
+}
+
+// Grid: (np/64, np/64) blocks; upper blocks exit at once.
+__global__ __launch_bounds__(256) void kbuild_kernel(const double* __restrict__ t, int64_t n, int64_t np,
+                                                     const nu_sho* __restrict__ th, double* __restrict__ K) {
+  const int64_t br = blockIdx.y, bc = blockIdx.x;
+  if (bc > br) return;
+  kbuild_block(t, n, np, th, K, br, bc);
 }
 
 // Lower triangle of K for a sum-of-terms covariance (nu_kernel), same layout.
@@ -439,6 +447,71 @@ __global__ void logdet_reduce_kernel(const double* __restrict__ parts, int npart
 
 hipError_t launch_logdet_reduce(hipStream_t s, const double* parts, int nparts, double* out) {
   hipLaunchKernelGGL(logdet_reduce_kernel, dim3(1), dim3(64), 0, s, parts, nparts, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched stages of the factorisation (one launch for every curve of a batch)
+
+// status = -1 of every curve (one thread per curve)
+__global__ __launch_bounds__(64) void batch_init_kernel(const CurveJob* __restrict__ jobs, int n_curves) {
+  const int c = blockIdx.x * 64 + threadIdx.x;
+  if (c < n_curves) *jobs[c].status = -1;
+}
+
+hipError_t launch_batch_init(hipStream_t s, const CurveJob* jobs, int n_curves) {
+  hipLaunchKernelGGL(batch_init_kernel, dim3((unsigned)((n_curves + 63) / 64)), dim3(64), 0, s, jobs, n_curves);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(64) void batch_collect_kernel(const CurveJob* __restrict__ jobs, int n_curves,
+                                                           int64_t* __restrict__ status_out,
+                                                           double* __restrict__ logdet_out) {
+  const int c = blockIdx.x * 64 + threadIdx.x;
+  if (c >= n_curves) return;
+  const CurveJob& J = jobs[c];
+  status_out[J.curve] = *J.status;
+  logdet_out[J.curve] = *J.logdet;
+}
+
+hipError_t launch_batch_collect(hipStream_t s, const CurveJob* jobs, int n_curves, int64_t* status_out,
+                                double* logdet_out) {
+  hipLaunchKernelGGL(batch_collect_kernel, dim3((unsigned)((n_curves + 63) / 64)), dim3(64), 0, s, jobs, n_curves,
+                     status_out, logdet_out);
+  return hipGetLastError();
+}
+
+// lower 64 x 64 blocks of every curve's K, numbered row by row within a curve
+__global__ __launch_bounds__(256) void batch_kbuild_kernel(const CurveJob* __restrict__ jobs,
+                                                           const int* __restrict__ begin, int n_curves) {
+  int u;
+  const int c = batch_find(begin, n_curves, (int)blockIdx.x, u);
+  const CurveJob& J = jobs[c];
+  int64_t br = (int64_t)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+  while ((br + 1) * (br + 2) / 2 <= u) ++br;
+  while (br * (br + 1) / 2 > u) --br;
+  const int64_t bc = u - br * (br + 1) / 2;
+  kbuild_block(J.t, J.n, J.np, J.theta, J.L, br, bc);
+}
+
+hipError_t launch_batch_kbuild(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_kbuild_kernel, dim3((unsigned)total), dim3(256), 0, s, jobs, begin, n_curves);
+  return hipGetLastError();
+}
+
+// ln|K| of every curve (one workgroup per curve; the same order as logdet_reduce_kernel)
+__global__ __launch_bounds__(64) void batch_logdet_kernel(const CurveJob* __restrict__ jobs) {
+  const CurveJob& J = jobs[blockIdx.x];
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+    for (int i = 0; i < J.nblk; ++i) sum += J.parts[i];
+    *J.logdet = sum;
+  }
+}
+
+hipError_t launch_batch_logdet(hipStream_t s, const CurveJob* jobs, int n_curves) {
+  hipLaunchKernelGGL(batch_logdet_kernel, dim3((unsigned)n_curves), dim3(64), 0, s, jobs);
   return hipGetLastError();
 }
 

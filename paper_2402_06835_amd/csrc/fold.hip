@@ -11,6 +11,7 @@
 #include <mutex>
 #include <vector>
 
+#include "batch_dev.hpp"
 #include "internal.hpp"
 
 namespace nu {
@@ -45,13 +46,11 @@ constexpr int WPH = 63;   // phases per wave: lane 63 only supplies its neighbou
 // Packed copy of the single-event grid for the fold: rows of n_t + FPAD slots
 // holding (depth, var) pairs and dll; var = NaN where the cell is invalid or
 // past the grid, so "valid and inside the grid" is var == var.
-__global__ __launch_bounds__(256) void fold_pack_kernel(const double* __restrict__ depth,
-                                                        const double* __restrict__ var,
-                                                        const double* __restrict__ dll,
-                                                        const uint8_t* __restrict__ valid, int n_d, int64_t n_t,
-                                                        double2* __restrict__ DV, double* __restrict__ Lp) {
+__device__ __forceinline__ void fold_pack_at(const double* __restrict__ depth, const double* __restrict__ var,
+                                             const double* __restrict__ dll, const uint8_t* __restrict__ valid,
+                                             int n_d, int64_t n_t, double2* __restrict__ DV, double* __restrict__ Lp,
+                                             int64_t e) {
   const int64_t ld = n_t + FPAD;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)n_d * ld) return;
   const int j = (int)(e / ld);
   const int64_t i = e - (int64_t)j * ld;
@@ -66,6 +65,14 @@ __global__ __launch_bounds__(256) void fold_pack_kernel(const double* __restrict
   }
   DV[e] = make_double2(d, v);
   Lp[e] = l;
+}
+
+__global__ __launch_bounds__(256) void fold_pack_kernel(const double* __restrict__ depth,
+                                                        const double* __restrict__ var,
+                                                        const double* __restrict__ dll,
+                                                        const uint8_t* __restrict__ valid, int n_d, int64_t n_t,
+                                                        double2* __restrict__ DV, double* __restrict__ Lp) {
+  fold_pack_at(depth, var, dll, valid, n_d, n_t, DV, Lp, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 // lane i receives lane i+1's value (DPP wave shift; lane 63 receives 0 through
@@ -268,15 +275,15 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
 }
 
 template <int JG, bool SEG>
-__global__ __launch_bounds__(256, 3) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
-                                                   int n_d, int64_t n_t, int64_t ld, const Segs S, double dt,
-                                                   const double* __restrict__ periods, double sign,
-                                                   double* __restrict__ q_snr, int64_t* __restrict__ best_phase,
-                                                   int32_t* __restrict__ best_dur, double* __restrict__ best_depth,
-                                                   double* __restrict__ best_sigma, double* __restrict__ best_lnp) {
+__device__ __forceinline__ void fold_period_block(const double2* __restrict__ DV, const double* __restrict__ Lp,
+                                                  int n_d, int64_t n_t, int64_t ld, const Segs& S, double dt,
+                                                  const double* __restrict__ periods, double sign,
+                                                  double* __restrict__ q_snr, int64_t* __restrict__ best_phase,
+                                                  int32_t* __restrict__ best_dur, double* __restrict__ best_depth,
+                                                  double* __restrict__ best_sigma, double* __restrict__ best_lnp,
+                                                  int64_t ip) {
   __shared__ Best red[256];
   __shared__ double wave_best[4];  // best lnP found so far by each wave (only rises)
-  const int64_t ip = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid < 4) wave_best[tid] = -INFINITY;
   __syncthreads();
@@ -325,6 +332,17 @@ __global__ __launch_bounds__(256, 3) void fold_kernel(const double2* __restrict_
       best_lnp[ip] = -INFINITY;
     }
   }
+}
+
+template <int JG, bool SEG>
+__global__ __launch_bounds__(256, 3) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
+                                                   int n_d, int64_t n_t, int64_t ld, const Segs S, double dt,
+                                                   const double* __restrict__ periods, double sign,
+                                                   double* __restrict__ q_snr, int64_t* __restrict__ best_phase,
+                                                   int32_t* __restrict__ best_dur, double* __restrict__ best_depth,
+                                                   double* __restrict__ best_sigma, double* __restrict__ best_lnp) {
+  fold_period_block<JG, SEG>(DV, Lp, n_d, n_t, ld, S, dt, periods, sign, q_snr, best_phase, best_dur, best_depth,
+                             best_sigma, best_lnp, (int64_t)blockIdx.x);
 }
 
 // durations per pass: 5 when that pads fewer cells than 4 (10 durations: 10 rather than 12)
@@ -500,8 +518,8 @@ hipError_t launch_mask_transit(hipStream_t s, double* depth, double* var, double
 }
 
 // First period of largest Q (NaN never wins).
-__global__ __launch_bounds__(1024) void best_period_kernel(const double* __restrict__ q, int64_t n_p,
-                                                           int64_t* __restrict__ out) {
+__device__ __forceinline__ void best_period_block(const double* __restrict__ q, int64_t n_p,
+                                                  int64_t* __restrict__ out) {
   __shared__ double rv[1024];
   __shared__ int64_t ri[1024];
   const int tid = threadIdx.x;
@@ -531,8 +549,70 @@ __global__ __launch_bounds__(1024) void best_period_kernel(const double* __restr
   if (tid == 0) *out = ri[0];
 }
 
+__global__ __launch_bounds__(1024) void best_period_kernel(const double* __restrict__ q, int64_t n_p,
+                                                           int64_t* __restrict__ out) {
+  best_period_block(q, n_p, out);
+}
+
 hipError_t launch_best_period(hipStream_t s, const double* q_snr, int64_t n_p, int64_t* out) {
   hipLaunchKernelGGL(best_period_kernel, dim3(1), dim3(1024), 0, s, q_snr, n_p, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms of the periodic search: the packed grids of every curve, the
+// fold over (period, curve) and the best period of every curve, one launch
+// each (workgroups of the pack numbered curve after curve, see CurveJob).
+
+__global__ __launch_bounds__(256) void batch_fold_pack_kernel(const CurveJob* __restrict__ jobs,
+                                                              const int* __restrict__ begin, int n_curves, int n_d) {
+  int u;
+  const CurveJob& J = jobs[batch_find(begin, n_curves, (int)blockIdx.x, u)];
+  const int64_t ld = J.n_epochs + FPAD;
+  fold_pack_at(J.depth, J.var, J.dll, J.valid, n_d, J.n_epochs, reinterpret_cast<double2*>(J.packed),
+               J.packed + 2 * (int64_t)n_d * ld, (int64_t)u * 256 + threadIdx.x);
+}
+
+template <int JG>
+__global__ __launch_bounds__(256, 3) void batch_fold_kernel(const CurveJob* __restrict__ jobs, int n_d,
+                                                         const double* __restrict__ periods, double sign) {
+  const CurveJob& J = jobs[blockIdx.y];
+  const int64_t ld = J.n_epochs + FPAD;
+  fold_period_block<JG, false>(reinterpret_cast<const double2*>(J.packed), J.packed + 2 * (int64_t)n_d * ld, n_d,
+                               J.n_epochs, ld, Segs{}, J.dt, periods, sign, J.q_snr, J.best_phase, J.best_dur,
+                               J.best_depth, J.best_sigma, J.best_lnp, (int64_t)blockIdx.x);
+}
+
+// the best period of every curve; -1 for a curve whose factorisation failed
+__global__ __launch_bounds__(1024) void batch_best_kernel(const CurveJob* __restrict__ jobs, int64_t n_p) {
+  const CurveJob& J = jobs[blockIdx.x];
+  if (!J.best_index) return;
+  if (*J.status >= 0) {
+    if (threadIdx.x == 0) *J.best_index = -1;
+    return;
+  }
+  best_period_block(J.q_snr, n_p, J.best_index);
+}
+
+hipError_t launch_batch_fold(hipStream_t s, const CurveJob* jobs, const int* begin_pack, int n_curves,
+                             int total_pack, int n_d, const double* periods, int64_t n_p, int sign) {
+  if (total_pack > 0) {
+    hipLaunchKernelGGL(batch_fold_pack_kernel, dim3((unsigned)total_pack), dim3(256), 0, s, jobs, begin_pack,
+                       n_curves, n_d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int pad4 = (n_d + 3) / 4 * 4, pad5 = (n_d + 4) / 5 * 5;
+  const dim3 g((unsigned)n_p, (unsigned)n_curves);
+  if (pad5 < pad4)
+    hipLaunchKernelGGL(batch_fold_kernel<5>, g, dim3(256), 0, s, jobs, n_d, periods, (double)sign);
+  else
+    hipLaunchKernelGGL(batch_fold_kernel<4>, g, dim3(256), 0, s, jobs, n_d, periods, (double)sign);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_best(hipStream_t s, const CurveJob* jobs, int n_curves, int64_t n_p) {
+  hipLaunchKernelGGL(batch_best_kernel, dim3((unsigned)n_curves), dim3(1024), 0, s, jobs, n_p);
   return hipGetLastError();
 }
 

@@ -35,6 +35,12 @@ constexpr int MAX_ND = 16;       // durations per search
 constexpr int MAX_DUR = 1024;    // samples per box
 constexpr int MAX_SEG = 32;      // segments of a segmented periodic search
 constexpr int MAX_SHAPE = 2048;  // values of all shapes of a template search together
+// Partials of the linear search's passes over X and L: rows per partial of the
+// transposed products, columns per partial of the row products, rows per
+// partial of the box sums of squares (measured choices, see run_linear)
+constexpr int LIN_XRC = 512;
+constexpr int LIN_RCW = 2048;
+constexpr int LIN_QRC = 256;
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -285,9 +291,9 @@ void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu,
 void plan_band(const std::vector<nu_factor*>& Fs, int w, const Tuning& tu, Plan& P);
 size_t inverse_t_elems(int nblk);
 nu_status plan_upload(nu_ctx* ctx, Plan& P);
-size_t factor_bytes(int64_t n, int prec);
+size_t factor_bytes(int64_t n, int prec, size_t t_min = 0);
 nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out);
-nu_status factor_place(nu_ctx* ctx, int64_t n, int prec, char** cursor, nu_factor** out);
+nu_status factor_place(nu_ctx* ctx, int64_t n, int prec, char** cursor, nu_factor** out, size_t t_min = 0);
 void* ctx_arena(nu_ctx* ctx, size_t bytes, nu_status* st);
 nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F, int prec);
 nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F, int prec);
@@ -308,6 +314,8 @@ struct EarlyInverse {
 nu_status run_factor(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P,
                      const std::vector<const double*>& ts, const std::vector<const nu_sho*>& theta_dev,
                      const EarlyInverse* early = nullptr);
+// the Cholesky's step loop alone (diagonal blocks, panels, trailing updates of P)
+nu_status run_factor_steps(nu_ctx* ctx, const Plan& P, const EarlyInverse* early = nullptr);
 nu_status read_factor_status(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, std::vector<int64_t>& status);
 nu_status run_inverse_fp64(nu_ctx* ctx, const Plan& P);
 nu_status run_inverse_mixed(nu_ctx* ctx, const std::vector<nu_factor*>& Fs, const Plan& P, int prec);
@@ -435,5 +443,94 @@ size_t ss_chunk_ws_doubles(int64_t n, int J);
 bool ss_chunked_applies(const nu_kernel& k);
 hipError_t launch_ss_step(hipStream_t s, const double* t, int64_t n, const nu_kernel& k, double* step);
 hipError_t launch_ss(int phase, hipStream_t s, const SsArgs& A);
+
+// ---------------------------------------------------------------------------
+// Batched stages: one launch runs a stage of the search for every curve of a
+// batch. Each curve's record holds its sizes and the device pointers of its
+// factor, search workspace, inputs and outputs; a launch's workgroups are
+// numbered curve after curve, and begin[c] (per stage kind) is the first
+// workgroup of curve c (begin[n_curves] the total), so a workgroup finds its
+// curve by binary search and its own index within that curve's grid.
+struct CurveJob {
+  // factor
+  const double* t;
+  const nu_sho* theta;
+  double *L, *X;
+  float *L32, *X32;
+  double* bandX;
+  double* parts;    // per-block ln|L_kk| terms
+  double* logdet;   // then the status word (int64) right after it
+  int64_t* status;
+  NullFit* nf;
+  int64_t n, np;
+  int nblk, xchunks, rchunks, qchunks;
+  // linear search: inputs, workspace (inside the factor's T region), outputs
+  const double* f;
+  const double* A;  // n x m1 column-major, or null
+  const int64_t* lattice;
+  int64_t n_epochs;
+  double *V, *Y, *R, *Z, *Rz, *xpart, *qpart;
+  int32_t* slot_count;
+  int* lattice_ok;
+  double *depth, *var, *dll;
+  uint8_t* valid;
+  double* null_out;  // 3 doubles or null
+  // periodic search
+  double* packed;
+  double dt;
+  double *q_snr, *best_depth, *best_sigma, *best_lnp;
+  int64_t* best_phase;
+  int32_t* best_dur;
+  int64_t* best_index;  // or null
+  // the caller's index of the curve (where its status and ln|K| are collected)
+  int64_t curve;
+};
+
+// stage kinds (rows of the begin table)
+enum BatchStage {
+  BS_INIT = 0, BS_KBUILD, BS_LOGDET, BS_CVT_L, BS_CVT_XD, BS_CVT_BACK, BS_BAND, BS_CHECK, BS_PACKV, BS_ROWS,
+  BS_ROWS_RED, BS_NULL, BS_COLS, BS_COLS_RED, BS_SLOTS, BS_QPART, BS_EPI, BS_FOLD_PACK, BS_BEST, BS_COUNT
+};
+// workgroups of stage `stage` for one curve (n_d durations, band width w, n_p periods)
+int64_t batch_stage_blocks(int stage, const CurveJob& J, int n_d, int band_w);
+// doubles of one curve's search workspace: linear search + packed fold grid
+size_t batch_search_ws_doubles(int64_t n, int n_d, int64_t n_epochs);
+// carve a curve's search workspace (linear search + packed grid) from ws
+void batch_carve_search_ws(CurveJob& J, double* ws, int n_d);
+
+// GEMV passes of the linear search: the matrix (X or L), the vector panel
+// read, the base added and the panel written (fields of CurveJob)
+enum PanelSel { PS_NONE = -1, PS_V = 0, PS_Y, PS_R, PS_Z, PS_RZ };
+enum MatSel { MS_X = 0, MS_L = 1 };
+
+hipError_t launch_batch_init(hipStream_t s, const CurveJob* jobs, int n_curves);
+// status_out[J.curve] = status, logdet_out[J.curve] = ln|K| of every curve of the launch
+hipError_t launch_batch_collect(hipStream_t s, const CurveJob* jobs, int n_curves, int64_t* status_out,
+                                double* logdet_out);
+hipError_t launch_batch_kbuild(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total);
+hipError_t launch_batch_logdet(hipStream_t s, const CurveJob* jobs, int n_curves);
+hipError_t launch_batch_cvt_l(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total);
+hipError_t launch_batch_cvt_xd(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total);
+hipError_t launch_batch_cvt_back(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total);
+hipError_t launch_batch_band_copy(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total,
+                                  int w, int to_band);
+hipError_t launch_batch_lattice_check(hipStream_t s, const CurveJob* jobs, int n_curves);
+hipError_t launch_batch_pack_v(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total,
+                               int m1);
+hipError_t launch_batch_rows(hipStream_t s, const CurveJob* jobs, const int* begin, const int* begin_red,
+                             int n_curves, int total, int total_red, int nv, int mat, int vin, int base, double alpha,
+                             int out);
+hipError_t launch_batch_null(hipStream_t s, const CurveJob* jobs, int n_curves, int m1);
+hipError_t launch_batch_cols(hipStream_t s, const CurveJob* jobs, const int* begin, const int* begin_red,
+                             int n_curves, int total, int total_red, int nv, int mat, int win, int base, double alpha,
+                             int out);
+hipError_t launch_batch_slot_count(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total);
+hipError_t launch_batch_q_partial(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total,
+                                  const int32_t* dur_sorted, int n_d, int dmax);
+hipError_t launch_batch_epilogue(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total,
+                                 const int32_t* dur, int n_d, int m1);
+hipError_t launch_batch_fold(hipStream_t s, const CurveJob* jobs, const int* begin_pack, int n_curves,
+                             int total_pack, int n_d, const double* periods, int64_t n_p, int sign);
+hipError_t launch_batch_best(hipStream_t s, const CurveJob* jobs, int n_curves, int64_t n_p);
 
 }  // namespace nu

@@ -22,15 +22,20 @@
 //   cell_epilogue per cell: g, h from window sums of Z, Schur complement, outputs
 #include <algorithm>
 
+#include "batch_dev.hpp"
 #include "cells.hpp"
 #include "internal.hpp"
 
 namespace nu {
 
+__device__ __forceinline__ void slot_count_at(const int64_t* __restrict__ lattice, int64_t n, int64_t n_epochs,
+                                              int32_t* __restrict__ T, int64_t s) {
+  if (s <= n_epochs) T[s] = (int32_t)lower_bound_i64(lattice, n, s);
+}
+
 __global__ __launch_bounds__(256) void slot_count_kernel(const int64_t* __restrict__ lattice, int64_t n,
                                                          int64_t n_epochs, int32_t* __restrict__ T) {
-  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (s <= n_epochs) T[s] = (int32_t)lower_bound_i64(lattice, n, s);
+  slot_count_at(lattice, n, n_epochs, T, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 hipError_t launch_slot_count(hipStream_t s, const int64_t* lattice, int64_t n, int64_t n_epochs, int32_t* T) {
@@ -43,8 +48,8 @@ hipError_t launch_slot_count(hipStream_t s, const int64_t* lattice, int64_t n, i
 // lattice[n - 1] == n_epochs - 1. One workgroup; *ok = 1 if it holds, else 0.
 // The trend fit reads the flag, so a lattice that breaks it leaves every cell
 // invalid and ln L_0 = NaN (the call itself does not synchronise to report it).
-__global__ __launch_bounds__(256) void lattice_check_kernel(const int64_t* __restrict__ lattice, int64_t n,
-                                                            int64_t n_epochs, int* __restrict__ ok) {
+__device__ __forceinline__ void lattice_check_block(const int64_t* __restrict__ lattice, int64_t n, int64_t n_epochs,
+                                                    int* __restrict__ ok) {
   bool bad = false;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
     const int64_t v = lattice[i];
@@ -54,6 +59,11 @@ __global__ __launch_bounds__(256) void lattice_check_kernel(const int64_t* __res
   }
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0) *ok = bad ? 0 : 1;
+}
+
+__global__ __launch_bounds__(256) void lattice_check_kernel(const int64_t* __restrict__ lattice, int64_t n,
+                                                            int64_t n_epochs, int* __restrict__ ok) {
+  lattice_check_block(lattice, n, n_epochs, ok);
 }
 
 hipError_t launch_lattice_check(hipStream_t s, const int64_t* lattice, int64_t n, int64_t n_epochs, int* ok) {
@@ -70,13 +80,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ---------------------------------------------------------------------------
 // V = [A | f] packed row-major (np x YCOLS): column c < m1 is trend column c,
 // column m1 is the flux.
-__global__ __launch_bounds__(256) void pack_v_kernel(const double* __restrict__ A, int m1,
-                                                     const double* __restrict__ f, int64_t n,
-                                                     double* __restrict__ V) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void pack_v_at(const double* __restrict__ A, int m1, const double* __restrict__ f,
+                                          int64_t n, double* __restrict__ V, int64_t r) {
   if (r >= n) return;
 #pragma unroll
   for (int c = 0; c < YCOLS; ++c) V[r * YCOLS + c] = c < m1 ? A[c * n + r] : (c == m1 ? f[r] : 0.0);
+}
+
+__global__ __launch_bounds__(256) void pack_v_kernel(const double* __restrict__ A, int m1,
+                                                     const double* __restrict__ f, int64_t n,
+                                                     double* __restrict__ V) {
+  pack_v_at(A, m1, f, n, V, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 hipError_t launch_pack_v(hipStream_t s, const double* A, int m1, const double* f, int64_t n, double* V) {
@@ -98,13 +112,12 @@ hipError_t launch_pack_v(hipStream_t s, const double* A, int m1, const double* f
 constexpr int RPW = 8;
 
 template <int NV>
-__global__ __launch_bounds__(256) void rows_partial_kernel(const double* __restrict__ M, int64_t ldm, int64_t n,
-                                                           int64_t np, const double* __restrict__ V, int cw,
-                                                           double* __restrict__ partial) {
-  const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
+__device__ __forceinline__ void rows_partial_block(const double* __restrict__ M, int64_t ldm, int64_t n, int64_t np,
+                                                   const double* __restrict__ V, int cw, double* __restrict__ partial,
+                                                   int bx, int chunk) {
+  const int64_t r0 = ((int64_t)bx * 4 + (threadIdx.x >> 6)) * RPW;
   const int lane = threadIdx.x & 63;
   if (r0 >= n) return;
-  const int chunk = blockIdx.y;
   const int rows = (int)min((int64_t)RPW, n - r0);
   const int64_t rlast = r0 + rows - 1;
   double acc[RPW][NV];
@@ -141,6 +154,13 @@ __global__ __launch_bounds__(256) void rows_partial_kernel(const double* __restr
   if (wi < rows) partial[((int64_t)chunk * np + r0 + wi) * YCOLS + wc] = wc < NV ? mine : 0.0;
 }
 
+template <int NV>
+__global__ __launch_bounds__(256) void rows_partial_kernel(const double* __restrict__ M, int64_t ldm, int64_t n,
+                                                           int64_t np, const double* __restrict__ V, int cw,
+                                                           double* __restrict__ partial) {
+  rows_partial_block<NV>(M, ldm, n, np, V, cw, partial, (int)blockIdx.x, (int)blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // Block-wide sum of one double per thread; fixed order (wave butterflies, then
 // the four wave totals in order). All threads get the result.
@@ -153,10 +173,11 @@ __device__ double block_sum(double v, double* red) {
   return ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-__global__ __launch_bounds__(256) void null_solve_kernel(double* __restrict__ Y, int64_t n, int m1,
-                                                         const double* __restrict__ logdet,
-                                                         const int* __restrict__ lattice_ok, NullFit* __restrict__ nf,
-                                                         double* __restrict__ null_out) {
+// status: the factor's status word (a failed factorisation: >= 0), or null
+__device__ __forceinline__ void null_solve_block(double* __restrict__ Y, int64_t n, int m1,
+                                                 const double* __restrict__ logdet, const int* __restrict__ lattice_ok,
+                                                 const int64_t* __restrict__ status, NullFit* __restrict__ nf,
+                                                 double* __restrict__ null_out) {
   __shared__ double red[4];
   __shared__ double S[MAX_M1 + 1][MAX_M1 + 1];
   __shared__ double w0s[MAX_M1];
@@ -204,6 +225,7 @@ __global__ __launch_bounds__(256) void null_solve_kernel(double* __restrict__ Y,
     // nor with a lattice the searches cannot use
     if (!isfinite(*logdet)) ok = 0;
     if (lattice_ok && !*lattice_ok) ok = 0;
+    if (status && *status >= 0) ok = 0;
     nf->ok = ok;
     ok_s = ok;
   }
@@ -231,6 +253,13 @@ __global__ __launch_bounds__(256) void null_solve_kernel(double* __restrict__ Y,
   }
 }
 
+__global__ __launch_bounds__(256) void null_solve_kernel(double* __restrict__ Y, int64_t n, int m1,
+                                                         const double* __restrict__ logdet,
+                                                         const int* __restrict__ lattice_ok, NullFit* __restrict__ nf,
+                                                         double* __restrict__ null_out) {
+  null_solve_block(Y, n, m1, logdet, lattice_ok, nullptr, nf, null_out);
+}
+
 hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const double* logdet,
                              const int* lattice_ok, NullFit* nf, double* null_out) {
   hipLaunchKernelGGL(null_solve_kernel, dim3(1), dim3(256), 0, s, Y, n, m1, logdet, lattice_ok, nf, null_out);
@@ -241,18 +270,17 @@ hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const 
 // out[m] = base[m] + alpha * sum_{n >= m} M[n][m] W[n]   (nv columns,
 // row-major, lower-triangular M). Workgroup = 256 columns x a chunk of rows;
 // partials per chunk, then a fixed-order reduction. out may alias base.
-__global__ __launch_bounds__(256) void cols_partial_kernel(const double* __restrict__ M, int64_t ldm, int64_t n,
-                                                           int64_t np, const double* __restrict__ W, int nv,
-                                                           int rowchunk, double* __restrict__ partial) {
-  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void cols_partial_block(const double* __restrict__ M, int64_t ldm, int64_t n, int64_t np,
+                                                   const double* __restrict__ W, int nv, int rowchunk,
+                                                   double* __restrict__ partial, int bx, int chunk) {
+  const int64_t m = (int64_t)bx * 256 + threadIdx.x;
   if (m >= np) return;
-  const int chunk = blockIdx.y;
   const int64_t r0 = (int64_t)chunk * rowchunk;
   const int64_t r1 = min(n, r0 + rowchunk);
   double acc[YCOLS];
 #pragma unroll
   for (int c = 0; c < YCOLS; ++c) acc[c] = 0.0;
-  const int64_t c0 = (int64_t)blockIdx.x * 256;
+  const int64_t c0 = (int64_t)bx * 256;
   if (m < n) {
     // eight rows per step: eight independent loads in flight per thread
     int64_t r = max(r0, c0);
@@ -281,16 +309,27 @@ __global__ __launch_bounds__(256) void cols_partial_kernel(const double* __restr
   for (int c = 0; c < YCOLS; ++c) o[c] = acc[c];
 }
 
+__global__ __launch_bounds__(256) void cols_partial_kernel(const double* __restrict__ M, int64_t ldm, int64_t n,
+                                                           int64_t np, const double* __restrict__ W, int nv,
+                                                           int rowchunk, double* __restrict__ partial) {
+  cols_partial_block(M, ldm, n, np, W, nv, rowchunk, partial, (int)blockIdx.x, (int)blockIdx.y);
+}
+
 // out[e] = base[e] + alpha * sum_c partial[c][e] for e < tot (elements of the
 // np x YCOLS layout), the chunks in order
-__global__ __launch_bounds__(256) void cols_reduce_kernel(const double* __restrict__ partial, int64_t np,
-                                                          int nchunks, const double* base, double alpha,
-                                                          double* out, int64_t tot) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void cols_reduce_at(const double* __restrict__ partial, int64_t np, int nchunks,
+                                               const double* base, double alpha, double* out, int64_t tot,
+                                               int64_t e) {
   if (e >= tot) return;
   double s = 0.0;
   for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * np * YCOLS + e];
   out[e] = (base ? base[e] : 0.0) + alpha * s;
+}
+
+__global__ __launch_bounds__(256) void cols_reduce_kernel(const double* __restrict__ partial, int64_t np,
+                                                          int nchunks, const double* base, double alpha,
+                                                          double* out, int64_t tot) {
+  cols_reduce_at(partial, np, nchunks, base, alpha, out, tot, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 hipError_t launch_rows_matvec(hipStream_t s, const double* M, int64_t ldm, int64_t n, int64_t np, const double* V,
@@ -350,15 +389,14 @@ hipError_t launch_cols_matvec(hipStream_t s, const double* M, int64_t ldm, int64
 constexpr int QCH = 256;  // slots per workgroup (4 waves x 64)
 
 template <int RUN>
-__global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
-                                                        const int64_t* __restrict__ lattice,
-                                                        const int32_t* __restrict__ T, int64_t n_epochs,
-                                                        DurList dl, int rowchunk, double* __restrict__ qpart) {
+__device__ __forceinline__ void q_partial_block(const double* __restrict__ X, int64_t ldx, int64_t n,
+                                                const int64_t* __restrict__ lattice, const int32_t* __restrict__ T,
+                                                int64_t n_epochs, const DurList& dl, int rowchunk,
+                                                double* __restrict__ qpart, int bx, int chunk) {
   constexpr int SEG = 64 * RUN;  // segment capacity of a wave
   __shared__ double prefix[4][2][SEG + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t slot = (int64_t)blockIdx.x * QCH + wave * 64 + lane;
-  const int chunk = blockIdx.y;
+  const int64_t slot = (int64_t)bx * QCH + wave * 64 + lane;
   const bool active = slot < n_epochs;
   int64_t lo[MAX_ND], hi[MAX_ND];
   int64_t my_lo = INT64_MAX, my_hi = INT64_MIN;
@@ -455,6 +493,14 @@ __global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict
   }
 }
 
+template <int RUN>
+__global__ __launch_bounds__(256) void q_partial_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
+                                                        const int64_t* __restrict__ lattice,
+                                                        const int32_t* __restrict__ T, int64_t n_epochs,
+                                                        DurList dl, int rowchunk, double* __restrict__ qpart) {
+  q_partial_block<RUN>(X, ldx, n, lattice, T, n_epochs, dl, rowchunk, qpart, (int)blockIdx.x, (int)blockIdx.y);
+}
+
 hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t n, const int64_t* lattice,
                             const int32_t* T, int64_t n_epochs, const int32_t* dur_sorted, int n_d, int dmax,
                             int rowchunk, int nchunks, double* qpart) {
@@ -483,16 +529,13 @@ hipError_t launch_q_partial(hipStream_t s, const double* X, int64_t ldx, int64_t
 // the outputs. With TPL the box is the duration's shape: sample r of the
 // window weighs shapes[off_j + lattice[r] - a].
 template <bool TPL>
-__global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __restrict__ qpart, int nchunks,
-                                                            const int64_t* __restrict__ lattice,
-                                                            const int32_t* __restrict__ T, int64_t n,
-                                                            int64_t n_epochs, DurList dl,
-                                                            const double* __restrict__ Z, int m1,
-                                                            const NullFit* __restrict__ nf,
-                                                            const double* __restrict__ shapes,
-                                                            double* __restrict__ depth, double* __restrict__ var,
-                                                            double* __restrict__ dll, uint8_t* __restrict__ valid) {
-  const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void cell_epilogue_at(const double* __restrict__ qpart, int nchunks,
+                                                 const int64_t* __restrict__ lattice, const int32_t* __restrict__ T,
+                                                 int64_t n, int64_t n_epochs, const DurList& dl,
+                                                 const double* __restrict__ Z, int m1, const NullFit* __restrict__ nf,
+                                                 const double* __restrict__ shapes, double* __restrict__ depth,
+                                                 double* __restrict__ var, double* __restrict__ dll,
+                                                 uint8_t* __restrict__ valid, int64_t cell) {
   if (cell >= (int64_t)dl.n * n_epochs) return;
   const int j = (int)(cell / n_epochs);
   const int64_t i = cell - (int64_t)j * n_epochs;
@@ -551,6 +594,20 @@ __global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __rest
     dll[o] = 0.0;
     valid[o] = 0;
   }
+}
+
+template <bool TPL>
+__global__ __launch_bounds__(256) void cell_epilogue_kernel(const double* __restrict__ qpart, int nchunks,
+                                                            const int64_t* __restrict__ lattice,
+                                                            const int32_t* __restrict__ T, int64_t n,
+                                                            int64_t n_epochs, DurList dl,
+                                                            const double* __restrict__ Z, int m1,
+                                                            const NullFit* __restrict__ nf,
+                                                            const double* __restrict__ shapes,
+                                                            double* __restrict__ depth, double* __restrict__ var,
+                                                            double* __restrict__ dll, uint8_t* __restrict__ valid) {
+  cell_epilogue_at<TPL>(qpart, nchunks, lattice, T, n, n_epochs, dl, Z, m1, nf, shapes, depth, var, dll, valid,
+                        (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 hipError_t launch_cell_epilogue(hipStream_t s, const double* qpart, int nchunks, const int64_t* lattice,
@@ -849,6 +906,211 @@ hipError_t launch_q_template(hipStream_t s, const double* X, int64_t ldx, int64_
 #undef NU_QTM
   else return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms of the linear search (one launch for every curve of a batch;
+// workgroups numbered curve after curve, see CurveJob). The bodies are those
+// of the single-curve kernels, so each curve's outputs are bitwise the same.
+
+__device__ __forceinline__ double* job_panel(const CurveJob& J, int sel) {
+  switch (sel) {
+    case PS_V: return J.V;
+    case PS_Y: return J.Y;
+    case PS_R: return J.R;
+    case PS_Z: return J.Z;
+    case PS_RZ: return J.Rz;
+    default: return nullptr;
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_lattice_check_kernel(const CurveJob* __restrict__ jobs) {
+  const CurveJob& J = jobs[blockIdx.x];
+  lattice_check_block(J.lattice, J.n, J.n_epochs, J.lattice_ok);
+}
+
+__global__ __launch_bounds__(256) void batch_pack_v_kernel(const CurveJob* __restrict__ jobs,
+                                                           const int* __restrict__ begin, int n_curves, int m1) {
+  int u;
+  const CurveJob& J = jobs[batch_find(begin, n_curves, (int)blockIdx.x, u)];
+  pack_v_at(J.A, m1, J.f, J.n, J.V, (int64_t)u * 256 + threadIdx.x);
+}
+
+// workgroups of the row products of one curve: row groups x column chunks
+__host__ __device__ inline int rows_groups(int64_t n) { return (int)(((n + RPW - 1) / RPW + 3) / 4); }
+
+template <int NV>
+__global__ __launch_bounds__(256) void batch_rows_partial_kernel(const CurveJob* __restrict__ jobs,
+                                                                 const int* __restrict__ begin, int n_curves,
+                                                                 int mat, int vin) {
+  int u;
+  const CurveJob& J = jobs[batch_find(begin, n_curves, (int)blockIdx.x, u)];
+  const int gx = rows_groups(J.n);
+  rows_partial_block<NV>(mat == MS_L ? J.L : J.X, J.np, J.n, J.np, job_panel(J, vin), LIN_RCW, J.xpart, u % gx,
+                         u / gx);
+}
+
+// out = base + alpha * (sum of the chunks), over tot(J) elements; rows: n YCOLS, columns: np YCOLS
+template <bool ROWS>
+__global__ __launch_bounds__(256) void batch_reduce_kernel(const CurveJob* __restrict__ jobs,
+                                                           const int* __restrict__ begin, int n_curves, int base,
+                                                           double alpha, int out) {
+  int u;
+  const CurveJob& J = jobs[batch_find(begin, n_curves, (int)blockIdx.x, u)];
+  const int64_t tot = (ROWS ? J.n : J.np) * YCOLS;
+  cols_reduce_at(J.xpart, J.np, ROWS ? J.rchunks : J.xchunks, job_panel(J, base), alpha, job_panel(J, out), tot,
+                 (int64_t)u * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void batch_null_kernel(const CurveJob* __restrict__ jobs, int m1) {
+  const CurveJob& J = jobs[blockIdx.x];
+  null_solve_block(J.Y, J.n, m1, J.logdet, J.lattice_ok, J.status, J.nf, J.null_out);
+}
+
+__global__ __launch_bounds__(256) void batch_cols_partial_kernel(const CurveJob* __restrict__ jobs,
+                                                                 const int* __restrict__ begin, int n_curves, int nv,
+                                                                 int mat, int win) {
+  int u;
+  const CurveJob& J = jobs[batch_find(begin, n_curves, (int)blockIdx.x, u)];
+  const int gx = (int)((J.np + 255) / 256);
+  cols_partial_block(mat == MS_L ? J.L : J.X, J.np, J.n, J.np, job_panel(J, win), nv, LIN_XRC, J.xpart, u % gx,
+                     u / gx);
+}
+
+__global__ __launch_bounds__(256) void batch_slot_count_kernel(const CurveJob* __restrict__ jobs,
+                                                               const int* __restrict__ begin, int n_curves) {
+  int u;
+  const CurveJob& J = jobs[batch_find(begin, n_curves, (int)blockIdx.x, u)];
+  slot_count_at(J.lattice, J.n, J.n_epochs, J.slot_count, (int64_t)u * 256 + threadIdx.x);
+}
+
+template <int RUN>
+__global__ __launch_bounds__(256) void batch_q_partial_kernel(const CurveJob* __restrict__ jobs,
+                                                              const int* __restrict__ begin, int n_curves,
+                                                              DurList dl) {
+  int u;
+  const CurveJob& J = jobs[batch_find(begin, n_curves, (int)blockIdx.x, u)];
+  const int gx = (int)((J.n_epochs + QCH - 1) / QCH);
+  q_partial_block<RUN>(J.X, J.np, J.n, J.lattice, J.slot_count, J.n_epochs, dl, LIN_QRC, J.qpart, u % gx, u / gx);
+}
+
+__global__ __launch_bounds__(256) void batch_epilogue_kernel(const CurveJob* __restrict__ jobs,
+                                                             const int* __restrict__ begin, int n_curves, DurList dl,
+                                                             int m1) {
+  int u;
+  const CurveJob& J = jobs[batch_find(begin, n_curves, (int)blockIdx.x, u)];
+  cell_epilogue_at<false>(J.qpart, J.qchunks, J.lattice, J.slot_count, J.n, J.n_epochs, dl, J.Z, m1, J.nf, nullptr,
+                          J.depth, J.var, J.dll, J.valid, (int64_t)u * 256 + threadIdx.x);
+}
+
+hipError_t launch_batch_lattice_check(hipStream_t s, const CurveJob* jobs, int n_curves) {
+  hipLaunchKernelGGL(batch_lattice_check_kernel, dim3((unsigned)n_curves), dim3(256), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_pack_v(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total,
+                               int m1) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_pack_v_kernel, dim3((unsigned)total), dim3(256), 0, s, jobs, begin, n_curves, m1);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_rows(hipStream_t s, const CurveJob* jobs, const int* begin, const int* begin_red,
+                             int n_curves, int total, int total_red, int nv, int mat, int vin, int base, double alpha,
+                             int out) {
+  if (total <= 0) return hipSuccess;
+  const dim3 g((unsigned)total), b(256);
+  switch (nv) {
+    case 1: hipLaunchKernelGGL(batch_rows_partial_kernel<1>, g, b, 0, s, jobs, begin, n_curves, mat, vin); break;
+    case 2: hipLaunchKernelGGL(batch_rows_partial_kernel<2>, g, b, 0, s, jobs, begin, n_curves, mat, vin); break;
+    case 3: hipLaunchKernelGGL(batch_rows_partial_kernel<3>, g, b, 0, s, jobs, begin, n_curves, mat, vin); break;
+    case 4: hipLaunchKernelGGL(batch_rows_partial_kernel<4>, g, b, 0, s, jobs, begin, n_curves, mat, vin); break;
+    case 5: hipLaunchKernelGGL(batch_rows_partial_kernel<5>, g, b, 0, s, jobs, begin, n_curves, mat, vin); break;
+    case 6: hipLaunchKernelGGL(batch_rows_partial_kernel<6>, g, b, 0, s, jobs, begin, n_curves, mat, vin); break;
+    case 7: hipLaunchKernelGGL(batch_rows_partial_kernel<7>, g, b, 0, s, jobs, begin, n_curves, mat, vin); break;
+    case 8: hipLaunchKernelGGL(batch_rows_partial_kernel<8>, g, b, 0, s, jobs, begin, n_curves, mat, vin); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || total_red <= 0) return e;
+  hipLaunchKernelGGL(batch_reduce_kernel<true>, dim3((unsigned)total_red), b, 0, s, jobs, begin_red, n_curves, base,
+                     alpha, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_null(hipStream_t s, const CurveJob* jobs, int n_curves, int m1) {
+  hipLaunchKernelGGL(batch_null_kernel, dim3((unsigned)n_curves), dim3(256), 0, s, jobs, m1);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_cols(hipStream_t s, const CurveJob* jobs, const int* begin, const int* begin_red,
+                             int n_curves, int total, int total_red, int nv, int mat, int win, int base, double alpha,
+                             int out) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_cols_partial_kernel, dim3((unsigned)total), dim3(256), 0, s, jobs, begin, n_curves, nv, mat,
+                     win);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || total_red <= 0) return e;
+  hipLaunchKernelGGL(batch_reduce_kernel<false>, dim3((unsigned)total_red), dim3(256), 0, s, jobs, begin_red, n_curves,
+                     base, alpha, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_slot_count(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_slot_count_kernel, dim3((unsigned)total), dim3(256), 0, s, jobs, begin, n_curves);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_q_partial(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total,
+                                  const int32_t* dur_sorted, int n_d, int dmax) {
+  if (total <= 0) return hipSuccess;
+  DurList dl{};
+  dl.n = n_d;
+  for (int k = 0; k < n_d; ++k) {
+    dl.d[k] = dur_sorted[k];
+    dl.perm[k] = dur_sorted[n_d + k];
+  }
+  const int seg = 64 + dmax;
+  const dim3 g((unsigned)total), b(256);
+  if (seg <= 64 * 2) hipLaunchKernelGGL(batch_q_partial_kernel<2>, g, b, 0, s, jobs, begin, n_curves, dl);
+  else if (seg <= 64 * 3) hipLaunchKernelGGL(batch_q_partial_kernel<3>, g, b, 0, s, jobs, begin, n_curves, dl);
+  else if (seg <= 64 * 5) hipLaunchKernelGGL(batch_q_partial_kernel<5>, g, b, 0, s, jobs, begin, n_curves, dl);
+  else if (seg <= 64 * 9) hipLaunchKernelGGL(batch_q_partial_kernel<9>, g, b, 0, s, jobs, begin, n_curves, dl);
+  else if (seg <= 64 * 17) hipLaunchKernelGGL(batch_q_partial_kernel<17>, g, b, 0, s, jobs, begin, n_curves, dl);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_epilogue(hipStream_t s, const CurveJob* jobs, const int* begin, int n_curves, int total,
+                                 const int32_t* dur, int n_d, int m1) {
+  if (total <= 0) return hipSuccess;
+  DurList dl{};
+  dl.n = n_d;
+  for (int k = 0; k < n_d; ++k) {
+    dl.d[k] = dur[k];
+    dl.perm[k] = k;
+    dl.off[k] = 0;
+  }
+  hipLaunchKernelGGL(batch_epilogue_kernel, dim3((unsigned)total), dim3(256), 0, s, jobs, begin, n_curves, dl, m1);
+  return hipGetLastError();
+}
+
+// workgroups of a linear-search stage for one curve (the grids of the single-curve launches)
+int64_t linear_stage_blocks(int stage, const CurveJob& J, int n_d) {
+  switch (stage) {
+    case BS_CHECK: return 1;
+    case BS_PACKV: return (J.n + 255) / 256;
+    case BS_ROWS: return (int64_t)rows_groups(J.n) * J.rchunks;
+    case BS_ROWS_RED: return (J.n * YCOLS + 255) / 256;
+    case BS_NULL: return 1;
+    case BS_COLS: return (J.np + 255) / 256 * J.xchunks;
+    case BS_COLS_RED: return (J.np * YCOLS + 255) / 256;
+    case BS_SLOTS: return (J.n_epochs + 1 + 255) / 256;
+    case BS_QPART: return (J.n_epochs + QCH - 1) / QCH * J.qchunks;
+    case BS_EPI: return ((int64_t)n_d * J.n_epochs + 255) / 256;
+    default: return 0;
+  }
 }
 
 }  // namespace nu

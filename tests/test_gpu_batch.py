@@ -168,6 +168,68 @@ def test_batch_not_positive_definite_curve(api, ctx):
         np.testing.assert_array_equal(res["periods"][c]["q_snr"].cpu().numpy(), single["q_snr"])
 
 
+def _batch_host(out, nc):
+    got = {k: out[k].cpu().numpy() for k in CELL_KEYS + PERIOD_KEYS + ("null", "best_index")}
+    return got
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_batch_graph_replays_match_eager(api, ctx, precision):
+    """The captured batch (one graph launch per batch) against the eager batch call, bit for bit, over three
+    replays with new hyperparameters, with eager batches and synchronisations between the replays; a
+    small budget forces several waves into the graph."""
+    import torch
+    ws = _curves()
+    curves = [_as_batch_input(w) for w in ws]
+    say(f"batch graph of {len(ws)} curves, N={[w.n for w in ws]}, {precision}, three replays")
+    batch = api.prepare_batch(ctx, curves)
+    # room for the largest factor (N = 1000) and a little more: several waves
+    budget = (20 if precision == "fp64" else 48) << 20
+    g = api.BatchGraph(ctx, batch, DURS, PERIODS, precision=precision, memory_budget=budget)
+    for rep in range(3):
+        thetas = []
+        for c, w in enumerate(ws):
+            th = dict(w.theta)
+            th["amp"] = w.theta["amp"] * (1.0 + 0.25 * rep + 0.05 * c)
+            th["sigma_w"] = w.theta["sigma_w"] * (1.0 + 0.1 * rep)
+            thetas.append(th)
+        g.set_theta(thetas)
+        out = g.launch()
+        torch.cuda.synchronize()
+        assert np.all(g.status.cpu().numpy() == -1)
+        got = _batch_host(out, len(ws))
+        eager_curves = [dict(cv, theta=th) for cv, th in zip(curves, thetas)]
+        ref = api.search_batch(ctx, eager_curves, DURS, PERIODS, precision=precision)
+        torch.cuda.synchronize()
+        for k in got:
+            np.testing.assert_array_equal(got[k], ref[k].cpu().numpy(), err_msg=f"replay {rep}: {k}")
+        np.testing.assert_array_equal(g.logdet.cpu().numpy(), ref["logdet"])
+    g.close()
+
+
+def test_batch_graph_reports_not_pd_without_sync(api, ctx):
+    import torch
+    ws = [_curve(300, 31, 0.9), _curve(200, 32, 1.1), _curve(150, 33, 0.7)]
+    curves = [_as_batch_input(w) for w in ws]
+    say("batch graph with a zero covariance in the middle on the second launch")
+    g = api.BatchGraph(ctx, curves, DURS, PERIODS, precision="fp64")
+    g.launch()
+    torch.cuda.synchronize()
+    assert list(g.status.cpu().numpy()) == [-1, -1, -1]
+    g.set_theta([ws[0].theta, {"amp": 0.0, "omega": 3.0, "q": 5.0, "sigma_w": 0.0}, ws[2].theta])
+    out = g.launch()
+    torch.cuda.synchronize()
+    assert list(g.status.cpu().numpy()) == [-1, 0, -1]
+    bad = out["cells"][1]
+    assert not bad["valid"].any().item() and bool(torch.isinf(bad["var"]).all().item())
+    assert bool((out["periods"][1]["best_phase"] == -1).all().item())
+    assert int(out["best_index"][1].item()) == -1
+    for c in (0, 2):
+        single = _single(api, ctx, ws[c], "fp64")
+        np.testing.assert_array_equal(out["cells"][c]["dll"].cpu().numpy(), single["dll"])
+    g.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine", "bf16x3_refine"])
 @pytest.mark.parametrize("n", [700, 2000])
 def test_graph_replays_match_eager(api, ctx, precision, n):
