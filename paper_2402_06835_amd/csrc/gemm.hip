@@ -19,6 +19,11 @@
 // triangular inverse X = L^-1 that whitens the box design of the linear search.
 #include "internal.hpp"
 
+// LDS stores of the next k-slice interleaved with the MFMAs of the current one
+#ifndef NU_GEMM_INTERLEAVE
+#define NU_GEMM_INTERLEAVE 1
+#endif
+
 // Accumulator layout of v_mfma_f32_16x16x4_f32 (set from the lane probe)
 #ifndef MFMA_F32_ROW_INTERLEAVED
 #define MFMA_F32_ROW_INTERLEAVED 0
@@ -184,7 +189,23 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
 #pragma unroll
     for (int j = 0; j < NBN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  auto compute = [&](int buf) {
+  // part q of 4 of the LDS store of a slice (a quarter of each thread's A and B
+  // elements). The B element i of a thread goes to Bs[k0 + i dk][n0 + i dn]:
+  // along k for B stored transposed, along n otherwise (no branch in the loop).
+  const int bs_k0 = bt ? bkh : bk, bs_n0 = bt ? br : bnc, bs_step = bt ? BN + LPAD : 1;
+  auto lstore_part = [&](int q, int buf, const T (&ra)[EA], const T (&rb)[EB]) {
+    constexpr int QA = (EA + 3) / 4, QB = (EB + 3) / 4;
+#pragma unroll
+    for (int i = q * QA; i < (q + 1) * QA && i < EA; ++i) As[buf][akh + i][ar] = ra[i];
+    T* bb = &Bs[buf][bs_k0][bs_n0];
+#pragma unroll
+    for (int i = q * QB; i < (q + 1) * QB && i < EB; ++i) bb[i * bs_step] = rb[i];
+  };
+  // slice it from buffer buf; with `store`, the next slice goes into the other
+  // buffer a quarter after each k-step, so the LDS stores issue among the MFMAs
+  // instead of after them (the other buffer was last read before the previous
+  // barrier)
+  auto compute = [&](int buf, const T (&ran)[EA], const T (&rbn)[EB]) {
 #pragma unroll
     for (int kk = 0; kk < GBK / 4; ++kk) {
       T a[NBM], b[NBN];
@@ -196,20 +217,30 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
       for (int mi = 0; mi < NBM; ++mi)
 #pragma unroll
         for (int ni = 0; ni < NBN; ++ni) acc[mi][ni] = Mfma<T>::op(a[mi], b[ni], acc[mi][ni]);
+#if NU_GEMM_INTERLEAVE
+      lstore_part(kk, buf ^ 1, ran, rbn);
+#endif
     }
+#if !NU_GEMM_INTERLEAVE
+    lstore(buf ^ 1, ran, rbn);
+#endif
   };
   // one slice: compute buffer it & 1 (slice it), refill the register set
-  // that held slice it with slice it + 2, store slice it + 1 from the other
+  // that held slice it with slice it + 2, store slice it + 1 from the other.
+  // The loads and stores are unconditional (near the end of the k range the
+  // last slice is loaded again, and a store goes to a buffer no one reads any
+  // more), so the loop body has no branch: the compiler then counts the loads
+  // in flight exactly (a conditional load forced a wait for all of them) and
+  // schedules the LDS reads of a k-step among the MFMAs of the previous one.
   auto step = [&](int it, T (&rac)[EA], T (&rbc)[EB], T (&ran)[EA], T (&rbn)[EB]) {
-    if (it + 2 < nk) gload(kb + (it + 2) * GBK, rac, rbc);
-    compute(it & 1);
-    if (it + 1 < nk) lstore((it + 1) & 1, ran, rbn);
+    gload(kb + min(it + 2, nk - 1) * GBK, rac, rbc);
+    compute(it & 1, ran, rbn);
     __syncthreads();
   };
 
   if (nk > 0) {
     gload(kb, ra0, rb0);
-    if (nk > 1) gload(kb + GBK, ra1, rb1);
+    gload(kb + min(1, nk - 1) * GBK, ra1, rb1);
     lstore(0, ra0, rb0);
     __syncthreads();
     for (int it = 0; it < nk; it += 2) {
