@@ -251,6 +251,7 @@ nu_status nu_linear_search_template(nu_ctx* ctx, nu_factor* factor, const double
 /* (3) Periodic search (Sections 2.3-2.4, Eqs. 8, 9, B4).
  * depth/var/dll/valid: device, [n_d][n_epochs] as produced by (2).
  * periods: device, n_p doubles in the time unit of dt (dt > 0).
+ * 1 <= n_epochs <= 2^27 (the global extent for (3c)).
  * For period P, p = P / dt; phases m = 0 .. ceil(p) - 1 (slot units from the
  * first sample); events k >= 0 at slot position m + k p, linearly
  * interpolated between slots floor and floor+1 (a single slot when k p is

@@ -1059,8 +1059,9 @@ size_t periodic_ws_bytes(int n_d, int64_t n_epochs) { return fold_workspace_doub
 
 nu_status validate_periodic(nu_ctx* ctx, int n_d, int64_t n_epochs, double dt, int64_t n_p, int log_term_sign) {
   if (n_d < 1 || n_d > MAX_ND) return set_error(ctx, NU_ERR_ARG, "periodic_search: n_d must be in [1, 16]");
-  if (n_epochs < 1 || n_epochs > ((int64_t)1 << 31))
-    return set_error(ctx, NU_ERR_ARG, "periodic_search: n_epochs must be in [1, 2^31]");
+  // the fold addresses a row of the packed grid with 32-bit byte offsets
+  if (n_epochs < 1 || n_epochs > ((int64_t)1 << 27))
+    return set_error(ctx, NU_ERR_ARG, "periodic_search: n_epochs must be in [1, 2^27]");
   if (!(std::isfinite(dt) && dt > 0.0))
     return set_error(ctx, NU_ERR_ARG, "periodic_search: dt must be finite and > 0");
   if (n_p < 1 || n_p > ((int64_t)1 << 31) - 1)

@@ -83,6 +83,19 @@ __device__ __forceinline__ double from_next_lane(double x) {
   return __hiloint2double(hi, lo);
 }
 
+// Element idx (>= 0, within 2^32 bytes of the row start: the periodic search
+// accepts at most 2^27 epoch slots) of a row whose start is wave-uniform: a
+// 32-bit byte offset from a scalar base, so the load takes the scalar-base
+// form with no per-lane 64-bit address arithmetic.
+__device__ __forceinline__ double row_at(const double* row, int idx) {
+  return *(const NU_GLOBAL double*)((const NU_GLOBAL char*)row + 8u * (uint32_t)idx);
+}
+__device__ __forceinline__ double2 row_at(const double2* row, int idx) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  const d2v v = *(const NU_GLOBAL d2v*)((const NU_GLOBAL char*)row + 16u * (uint32_t)idx);
+  return make_double2(v.x, v.y);
+}
+
 // Segments of one global lattice (sectors with their own linear searches):
 // segment s covers global slots [off[s], off[s] + len[s]); the packed grid
 // holds each segment's slots at [pstart[s], pstart[s] + len[s]) of a row,
@@ -178,8 +191,13 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
     double l[JG];
 #pragma unroll
     for (int g = 0; g < JG; ++g) {
-      dv[g] = dvr[g][idx];
-      l[g] = lpr[g][idx];
+      if constexpr (SEG) {  // idx may be negative there (the window's packed offset)
+        dv[g] = dvr[g][idx];
+        l[g] = lpr[g][idx];
+      } else {
+        dv[g] = row_at(dvr[g], idx);
+        l[g] = row_at(lpr[g], idx);
+      }
     }
 #pragma unroll
     for (int g = 0; g < JG; ++g) {
@@ -244,7 +262,7 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
     double2 dv[JG];
 #pragma unroll
     for (int g = 0; g < JG; ++g)
-      if (need[g]) dv[g] = dvr[g][idx];
+      if (need[g]) dv[g] = SEG ? dvr[g][idx] : row_at(dvr[g], idx);
 #pragma unroll
     for (int g = 0; g < JG; ++g) {
       if (!need[g]) continue;
@@ -284,7 +302,10 @@ __device__ __forceinline__ void fold_period_block(const double2* __restrict__ DV
                                                   int64_t ip) {
   __shared__ Best red[256];
   __shared__ double wave_best[4];  // best lnP found so far by each wave (only rises)
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform within a wave: read it into a scalar register, so
+  // that the phase base and the per-duration row pointers derived from it stay
+  // scalar and each event's loads share one 32-bit lane offset
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid < 4) wave_best[tid] = -INFINITY;
   __syncthreads();
   volatile double* wb = wave_best;
