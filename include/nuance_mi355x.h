@@ -123,13 +123,22 @@ typedef struct nu_ctx nu_ctx;
 typedef struct nu_factor nu_factor;
 
 /* Context: device, stream, growable workspace, optional kernel timing.
- * stream == NULL means the device's null stream. */
-nu_status nu_ctx_create(int device, void* stream, nu_ctx** out);
+ * stream == NULL means the device's null stream. workspace_limit_bytes (0: no
+ * limit) caps the device memory the library allocates on this context: the
+ * search workspace, the batch arena (4) and per-call fold grids and records,
+ * and the buffers of the factors, graphs and networks made on it, counted
+ * while they live (the small launch schedules are not counted). A call that
+ * would exceed it allocates nothing more and returns NU_ERR_OOM (the caller
+ * may retry with a smaller problem or batch); the batch (4, 4b) plans its
+ * waves within it. */
+nu_status nu_ctx_create(int device, void* stream, size_t workspace_limit_bytes, nu_ctx** out);
 void nu_ctx_destroy(nu_ctx* ctx);
 nu_status nu_ctx_set_stream(nu_ctx* ctx, void* stream);
 /* Frees the device memory the context keeps between calls: the search
  * workspace and the arena of the batch factors (4). Synchronises the stream. */
 nu_status nu_ctx_release_memory(nu_ctx* ctx);
+/* Device bytes counted against the workspace limit right now (0 for NULL). */
+size_t nu_ctx_device_bytes(const nu_ctx* ctx);
 const char* nu_ctx_last_error(const nu_ctx* ctx);
 /* Inverse prefetch. prec = NU_FP32_REFINE or NU_BF16X3_REFINE: every later
  * nu_gp_factor / nu_gp_factor_kernel on this context also computes the

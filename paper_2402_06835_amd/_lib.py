@@ -11,8 +11,9 @@ import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnuance_mi355x.so")
 
-c_int, c_int32, c_int64, c_double, c_void_p, c_char_p = (
-    ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_char_p)
+c_int, c_int32, c_int64, c_double, c_void_p, c_char_p, c_size_t = (
+    ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_char_p,
+    ctypes.c_size_t)
 P = ctypes.POINTER
 
 NU_OK, NU_ERR_ARG, NU_ERR_NOT_PD, NU_ERR_OOM, NU_ERR_DEVICE, NU_ERR_UNSUPPORTED = range(6)
@@ -34,7 +35,8 @@ class NuKernel(ctypes.Structure):
 # name -> (restype, argtypes)
 SIGNATURES = {
     "nu_rotation_kernel": (c_int, [c_double] * 10 + [P(NuKernel)]),
-    "nu_ctx_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
+    "nu_ctx_create": (c_int, [c_int, c_void_p, c_size_t, P(c_void_p)]),
+    "nu_ctx_device_bytes": (c_size_t, [c_void_p]),
     "nu_ctx_destroy": (None, [c_void_p]),
     "nu_ctx_set_stream": (c_int, [c_void_p, c_void_p]),
     "nu_ctx_release_memory": (c_int, [c_void_p]),

@@ -79,7 +79,10 @@ class SHO:
 class Context:
     """Library context bound to one device and (by default) torch's current stream."""
 
-    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, workspace_limit: int = 0):
+        """workspace_limit: bytes of device memory the library may allocate on this
+        context (0: no limit); a call that would exceed it raises NuanceError
+        with NU_ERR_OOM."""
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the transit-search library runs on the device only")
         self.device = torch.device("cuda", device)
@@ -87,7 +90,7 @@ class Context:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         p = ctypes.c_void_p()
-        st = lib().nu_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(p))
+        st = lib().nu_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), int(workspace_limit), ctypes.byref(p))
         if st != NU_OK:
             raise NuanceError(st, "nu_ctx_create failed")
         self.ptr = p
@@ -107,6 +110,10 @@ class Context:
     def release_memory(self):
         """Free the device memory the context keeps between calls (workspace, batch arena)."""
         _check(self.ptr, lib().nu_ctx_release_memory(self.ptr))
+
+    def device_bytes(self) -> int:
+        """Device bytes counted against the workspace limit right now."""
+        return int(lib().nu_ctx_device_bytes(self.ptr))
 
     def set_inverse_prefetch(self, precision: Optional[str], compute_units: int = 0):
         """Compute the factor's reduced-precision inverse inside every later

@@ -10,7 +10,9 @@
 // each Cholesky step (one workgroup per curve) and the grouped GEMMs of its
 // panel, panel-update and trailing products, each level of the inverse, every
 // pass of the linear search, the fold over (period, curve) and the best
-// periods. The per-curve records (CurveJob) and stage tables are built and
+// periods. A wave's fold and best periods run on a second stream beside the
+// next wave's factorisation (vector work beside matrix-core work), reading
+// grids kept outside the arena. The per-curve records (CurveJob) and stage tables are built and
 // uploaded before anything is enqueued, and a failed factorisation is handled
 // on the device (its cells come out invalid), so the enqueue sequence neither
 // allocates nor synchronises: the eager call waits once, at its end, and the
@@ -29,6 +31,7 @@ struct nu_graph {
   int device = 0;
   nu_factor* F = nullptr;
   double* ws = nullptr;
+  MemHold hold;  // ws against the context's limit
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -87,14 +90,21 @@ struct BatchInputs {
 
 struct BatchRun {
   std::vector<BatchWave> waves;
-  void* tables = nullptr;  // device: every wave's jobs and begin tables
+  void* tables = nullptr;    // device: every wave's jobs and begin tables
+  double* packed = nullptr;  // device: every curve's packed fold grid (outside the arena)
+  std::vector<hipEvent_t> ev_lin, ev_fold;  // per wave: linear search done, fold done
+  MemHold hold;                             // tables and grids against the context's limit
   ~BatchRun() {
+    hold.release();
     for (auto& w : waves) {
       plan_release(w.P);
       plan_release(w.Q);
       for (nu_factor* F : w.Fs) factor_free(F);
     }
     if (tables) (void)hipFree(tables);
+    if (packed) (void)hipFree(packed);
+    for (hipEvent_t e : ev_lin) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_fold) (void)hipEventDestroy(e);
   }
 };
 
@@ -109,6 +119,13 @@ nu_status plan_waves(nu_ctx* ctx, const BatchInputs& in, size_t budget, std::vec
   std::vector<int> order(in.n_curves);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return curve_n(in, a) > curve_n(in, b); });
+  // every curve's packed fold grid and record are held for the whole call,
+  // outside the waves (the records' bound: one wave per curve at most)
+  size_t grids = (size_t)in.n_curves * (sizeof(CurveJob) + 2 * BS_COUNT * sizeof(int) + 512);
+  for (int c = 0; c < in.n_curves; ++c) grids += fold_workspace_doubles(in.n_d, curve_ne(in, c)) * sizeof(double);
+  if (grids >= budget)
+    return set_error(ctx, NU_ERR_OOM, "search_batch: the fold grids do not fit the device-memory budget");
+  budget -= grids;
   size_t used = 0;
   for (int c : order) {
     const size_t need = curve_bytes(in, c);
@@ -210,7 +227,31 @@ nu_status build_batch(nu_ctx* ctx, const BatchInputs& in, const std::vector<std:
     st = plan_upload(ctx, W.Q);
     if (st != NU_OK) return st;
   }
-  nu_status st = check_hip(ctx, hipMalloc(&run.tables, table_bytes), "alloc batch tables");
+  // the packed fold grids live outside the arena, so a wave's fold can run
+  // while the next wave's factors overwrite the arena
+  size_t packed_doubles = 0;
+  for (const BatchWave& W : run.waves)
+    for (const CurveJob& J : W.jobs) packed_doubles += fold_workspace_doubles(in.n_d, J.n_epochs);
+  nu_status st = ctx_malloc(ctx, (void**)&run.packed, std::max<size_t>(packed_doubles, 1) * sizeof(double), run.hold,
+                            "alloc batch fold grids");
+  if (st != NU_OK) return st;
+  size_t poff = 0;
+  for (BatchWave& W : run.waves)
+    for (CurveJob& J : W.jobs) {
+      J.packed = run.packed + poff;
+      poff += fold_workspace_doubles(in.n_d, J.n_epochs);
+    }
+  if (!ctx->s_fold)  // created here, never under a capture
+    st = check_hip(ctx, hipStreamCreateWithFlags(&ctx->s_fold, hipStreamNonBlocking), "fold stream");
+  if (st != NU_OK) return st;
+  run.ev_lin.assign(run.waves.size(), nullptr);
+  run.ev_fold.assign(run.waves.size(), nullptr);
+  for (size_t w = 0; st == NU_OK && w < run.waves.size(); ++w) {
+    st = check_hip(ctx, hipEventCreateWithFlags(&run.ev_lin[w], hipEventDisableTiming), "batch event");
+    if (st == NU_OK) st = check_hip(ctx, hipEventCreateWithFlags(&run.ev_fold[w], hipEventDisableTiming), "batch event");
+  }
+  if (st != NU_OK) return st;
+  st = ctx_malloc(ctx, &run.tables, table_bytes, run.hold, "alloc batch tables");
   if (st != NU_OK) return st;
   std::vector<char> host(table_bytes);
   size_t off = 0;
@@ -326,21 +367,54 @@ nu_status enqueue_wave(nu_ctx* ctx, const BatchInputs& in, const BatchWave& W) {
     st = check_hip(ctx, launch_batch_epilogue(s, W.djobs, W.b(BS_EPI), n, W.total[BS_EPI], in.dur, n_d, m1),
                    "cell_epilogue");
   }
-  // the periodic search
-  if (st == NU_OK) {
+  // statuses and ln|K| by curve index, before the next wave overwrites the arena
+  if (st == NU_OK)
+    st = check_hip(ctx, launch_batch_collect(s, W.djobs, n, in.status_out, in.logdet_out), "batch collect");
+  return st;
+}
+
+// the periodic search of one wave on stream s (its grids outside the arena)
+nu_status enqueue_wave_fold(nu_ctx* ctx, const BatchInputs& in, const BatchWave& W, hipStream_t s) {
+  const int n = W.n(), n_d = in.n_d;
+  nu_status st;
+  {
     double visits = 0.0;
     for (const CurveJob& J : W.jobs) visits += (double)n_d * (double)J.n_epochs * (double)in.n_p;
-    Timed tm(ctx, "fold", FOLD_FLOPS_PER_VISIT * visits);
+    Timed tm(ctx, s, "fold", FOLD_FLOPS_PER_VISIT * visits);
     st = check_hip(ctx, launch_batch_fold(s, W.djobs, W.b(BS_FOLD_PACK), n, W.total[BS_FOLD_PACK], n_d, in.periods,
                                           in.n_p, in.sign),
                    "fold");
   }
   if (st == NU_OK) {
-    Timed tm(ctx, "best_period", 0.0);
-    st = check_hip(ctx, launch_batch_best(s, W.djobs, n, in.n_p), "best_period");
+    Timed tm(ctx, s, "best_period", 0.0);
+    st = check_hip(ctx, launch_batch_best(s, W.djobs, n, in.n_p, in.status_out), "best_period");
   }
-  if (st == NU_OK)
-    st = check_hip(ctx, launch_batch_collect(s, W.djobs, n, in.status_out, in.logdet_out), "batch collect");
+  return st;
+}
+
+// Every wave: factorisation, inverse and linear search on the context's
+// stream; then its periodic search on the fold stream, which runs beside the
+// next wave's factorisation (the fold is VALU work, the factorisation matrix-
+// core work). The context's stream joins the fold stream at the end.
+nu_status enqueue_batch(nu_ctx* ctx, const BatchInputs& in, BatchRun& run) {
+  nu_status st = NU_OK;
+  bool forked = false;
+  for (size_t w = 0; st == NU_OK && w < run.waves.size(); ++w) {
+    st = enqueue_wave(ctx, in, run.waves[w]);
+    if (st == NU_OK) st = check_hip(ctx, hipEventRecord(run.ev_lin[w], ctx->stream), "batch fork");
+    if (st == NU_OK) st = check_hip(ctx, hipStreamWaitEvent(ctx->s_fold, run.ev_lin[w], 0), "batch fork");
+    if (st == NU_OK) {
+      forked = true;
+      st = enqueue_wave_fold(ctx, in, run.waves[w], ctx->s_fold);
+    }
+    if (st == NU_OK) st = check_hip(ctx, hipEventRecord(run.ev_fold[w], ctx->s_fold), "batch join");
+  }
+  if (forked) {  // join (also after an error: the caller's stream must not run ahead of the fold stream)
+    const size_t last = run.waves.size() - 1;
+    nu_status sj = check_hip(ctx, hipEventRecord(run.ev_fold[last], ctx->s_fold), "batch join");
+    if (sj == NU_OK) sj = check_hip(ctx, hipStreamWaitEvent(ctx->stream, run.ev_fold[last], 0), "batch join");
+    if (st == NU_OK) st = sj;
+  }
   return st;
 }
 
@@ -372,6 +446,7 @@ nu_status validate_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_ho
 
 struct nu_batch_graph {
   int device = 0;
+  MemHold hold;             // arena and logdet against the context's limit
   void* arena = nullptr;    // the graph's own factors
   double* logdet = nullptr;  // ln|K| per curve when the caller passes none
   BatchRun run;              // schedules, tables, placed factors
@@ -450,6 +525,7 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
     if (st != NU_OK) return st;
     budget = (free_b + ctx->arena_bytes) / 10 * 9;
   }
+  budget = std::min(budget, mem_headroom(ctx, ctx->arena_bytes));  // the arena is replaced
   std::vector<std::vector<int>> waves;
   size_t arena_need = 0;
   st = plan_waves(ctx, in, budget, waves, arena_need);
@@ -465,7 +541,7 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
     HostTimed ht(ctx, "batch_plan");
     st = build_batch(ctx, in, waves, arena, run);
   }
-  for (size_t w = 0; st == NU_OK && w < run.waves.size(); ++w) st = enqueue_wave(ctx, in, run.waves[w]);
+  if (st == NU_OK) st = enqueue_batch(ctx, in, run);
   std::vector<int64_t> status(n_curves, -1);
   std::vector<double> logdet(n_curves, 0.0);
   if (st == NU_OK) {
@@ -555,7 +631,7 @@ nu_status nu_batch_graph_create(nu_ctx* ctx, int n_curves, const int64_t* sample
   in.best_index = best_period_index;
   in.status_out = status_dev;
   if (!logdet_dev) {
-    st = check_hip(ctx, hipMalloc(&g->logdet, (size_t)n_curves * sizeof(double)), "alloc logdet");
+    st = ctx_malloc(ctx, (void**)&g->logdet, (size_t)n_curves * sizeof(double), g->hold, "alloc logdet");
     if (st != NU_OK) return fail(st);
     logdet_dev = g->logdet;
   }
@@ -568,10 +644,11 @@ nu_status nu_batch_graph_create(nu_ctx* ctx, int n_curves, const int64_t* sample
     if (st != NU_OK) return fail(st);
     budget = free_b / 10 * 9;
   }
+  budget = std::min(budget, mem_headroom(ctx, 0));
   std::vector<std::vector<int>> waves;
   size_t arena_need = 0;
   st = plan_waves(ctx, in, budget, waves, arena_need);
-  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&g->arena, std::max<size_t>(arena_need, 256)), "alloc graph arena");
+  if (st == NU_OK) st = ctx_malloc(ctx, &g->arena, std::max<size_t>(arena_need, 256), g->hold, "alloc graph arena");
   if (st == NU_OK) st = build_batch(ctx, in, waves, (char*)g->arena, g->run);
   if (st != NU_OK) return fail(st);
 
@@ -584,8 +661,7 @@ nu_status nu_batch_graph_create(nu_ctx* ctx, int n_curves, const int64_t* sample
   ctx->timing = false;
   st = check_hip(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
   if (st == NU_OK) {
-    nu_status cst = NU_OK;
-    for (size_t w = 0; cst == NU_OK && w < g->run.waves.size(); ++w) cst = enqueue_wave(ctx, in, g->run.waves[w]);
+    const nu_status cst = enqueue_batch(ctx, in, g->run);
     st = check_hip(ctx, hipStreamEndCapture(cs, &g->graph), "end capture");
     if (cst != NU_OK) st = cst;
   }
@@ -609,6 +685,7 @@ nu_status nu_batch_graph_launch(nu_ctx* ctx, nu_batch_graph* g) {
 
 void nu_batch_graph_destroy(nu_batch_graph* g) {
   if (!g) return;
+  g->hold.release();
   if (hipSetDevice(g->device) != hipSuccess) {  // the runtime has shut down: host side only
     for (auto& w : g->run.waves) {
       w.P = Plan();
@@ -623,6 +700,9 @@ void nu_batch_graph_destroy(nu_batch_graph* g) {
     }
     g->run.waves.clear();
     g->run.tables = nullptr;
+    g->run.packed = nullptr;
+    g->run.ev_lin.clear();
+    g->run.ev_fold.clear();
     delete g;
     return;
   }
@@ -667,8 +747,9 @@ nu_status nu_graph_create(nu_ctx* ctx, const double* t, int64_t n, const nu_sho*
   st = factor_alloc(ctx, n, true, &g->F);
   if (st == NU_OK && mixed) st = ensure_plan32(ctx, g->F, prec);
   if (st == NU_OK)
-    st = check_hip(ctx, hipMalloc(&g->ws, std::max(linear_ws_bytes(n, n_d, n_epochs), periodic_ws_bytes(n_d, n_epochs))),
-                   "alloc graph workspace");
+    st = ctx_malloc(ctx, (void**)&g->ws,
+                    std::max(linear_ws_bytes(n, n_d, n_epochs), periodic_ws_bytes(n_d, n_epochs)), g->hold,
+                    "alloc graph workspace");
   if (st != NU_OK) return fail(st);
 
   hipStream_t cs = nullptr;
@@ -714,6 +795,7 @@ nu_status nu_graph_launch(nu_ctx* ctx, nu_graph* g) {
 
 void nu_graph_destroy(nu_graph* g) {
   if (!g) return;
+  g->hold.release();
   if (hipSetDevice(g->device) != hipSuccess) {  // the runtime has shut down: host side only
     factor_free(g->F);
     delete g;
@@ -755,7 +837,8 @@ nu_status nu_ctx_autotune(nu_ctx* ctx, int64_t n, nu_precision prec) {
   for (int64_t i = 0; i < n; ++i) th[i] = (double)i;
   double* t_dev = nullptr;
   nu_factor* F = nullptr;
-  st = check_hip(ctx, hipMalloc(&t_dev, n * sizeof(double)), "autotune alloc");
+  MemHold hold;
+  st = ctx_malloc(ctx, (void**)&t_dev, n * sizeof(double), hold, "autotune alloc");
   if (st == NU_OK) st = check_hip(ctx, hipMemcpy(t_dev, th.data(), n * sizeof(double), hipMemcpyHostToDevice), "copy");
   if (st == NU_OK) st = factor_alloc(ctx, n, false, &F);
   if (st == NU_OK && mixed) st = alloc_mixed(ctx, F, prec);
@@ -817,6 +900,7 @@ nu_status nu_ctx_autotune(nu_ctx* ctx, int64_t n, nu_precision prec) {
   ctx->timing_names = saved_names;
   factor_free(F);
   if (t_dev) (void)hipFree(t_dev);
+  hold.release();
   if (st != NU_OK) return st;
   for (int c = 0; c < TC_COUNT; ++c) ctx->tuning.small_below[c] = best_thr[c];
   return NU_OK;

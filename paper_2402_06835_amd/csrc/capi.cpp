@@ -24,22 +24,63 @@ nu_status check_hip(nu_ctx* ctx, hipError_t e, const char* what) {
                    std::string(what) + ": " + hipGetErrorString(e));
 }
 
-void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st) {
+nu_status mem_check(nu_ctx* ctx, size_t bytes, size_t replaced, const char* what) {
+  const MemCount& m = *ctx->mem;
+  const size_t live = m.live.load() - replaced;
+  if (m.limit && (bytes > m.limit || live > m.limit - bytes))
+    return set_error(ctx, NU_ERR_OOM,
+                     std::string(what) + ": " + std::to_string(bytes) + " bytes would exceed the context's limit of " +
+                         std::to_string(m.limit) + " bytes (" + std::to_string(live) + " in use)");
+  return NU_OK;
+}
+
+nu_status ctx_malloc(nu_ctx* ctx, void** p, size_t bytes, MemHold& hold, const char* what) {
+  *p = nullptr;
+  nu_status st = mem_check(ctx, bytes, 0, what);
+  if (st == NU_OK) st = check_hip(ctx, hipMalloc(p, bytes), what);
+  if (st != NU_OK) {
+    *p = nullptr;
+    return st;
+  }
+  if (!hold.count) hold.count = ctx->mem;
+  ctx->mem->live += bytes;
+  hold.bytes += bytes;
+  return NU_OK;
+}
+
+size_t mem_headroom(const nu_ctx* ctx, size_t replaced) {
+  const MemCount& m = *ctx->mem;
+  if (!m.limit) return SIZE_MAX;
+  const size_t live = m.live.load() - replaced;
+  return live >= m.limit ? 0 : m.limit - live;
+}
+
+// the context's own growable buffer (workspace or arena): grown to `bytes`
+// when smaller, counted against the limit
+static void* ctx_grow(nu_ctx* ctx, void** buf, size_t* have, size_t bytes, const char* what, nu_status* st) {
   *st = NU_OK;
-  if (bytes <= ctx->ws_bytes) return ctx->ws;
+  if (bytes <= *have) return *buf;
+  *st = mem_check(ctx, bytes, *have, what);
+  if (*st != NU_OK) return nullptr;
   // the old buffer may still be in use by enqueued work
   hipError_t e = hipStreamSynchronize(ctx->stream);
-  if (e == hipSuccess && ctx->ws) e = hipFree(ctx->ws);
-  ctx->ws = nullptr;
-  ctx->ws_bytes = 0;
-  if (e == hipSuccess) e = hipMalloc(&ctx->ws, bytes);
+  if (e == hipSuccess && *buf) e = hipFree(*buf);
+  ctx->mem->live -= *have;
+  *buf = nullptr;
+  *have = 0;
+  if (e == hipSuccess) e = hipMalloc(buf, bytes);
   if (e != hipSuccess) {
-    *st = check_hip(ctx, e, "workspace allocation");
-    ctx->ws = nullptr;
+    *st = check_hip(ctx, e, what);
+    *buf = nullptr;
     return nullptr;
   }
-  ctx->ws_bytes = bytes;
-  return ctx->ws;
+  ctx->mem->live += bytes;
+  *have = bytes;
+  return *buf;
+}
+
+void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st) {
+  return ctx_grow(ctx, &ctx->ws, &ctx->ws_bytes, bytes, "workspace allocation", st);
 }
 
 nu_status ctx_upload(nu_ctx* ctx, const void* host, size_t bytes, void* dev) {
@@ -78,20 +119,7 @@ nu_status validate_shapes(nu_ctx* ctx, const double* shapes_host, const int32_t*
 }
 
 void* ctx_arena(nu_ctx* ctx, size_t bytes, nu_status* st) {
-  *st = NU_OK;
-  if (bytes <= ctx->arena_bytes) return ctx->arena;
-  hipError_t e = hipStreamSynchronize(ctx->stream);
-  if (e == hipSuccess && ctx->arena) e = hipFree(ctx->arena);
-  ctx->arena = nullptr;
-  ctx->arena_bytes = 0;
-  if (e == hipSuccess) e = hipMalloc(&ctx->arena, bytes);
-  if (e != hipSuccess) {
-    *st = check_hip(ctx, e, "arena allocation");
-    ctx->arena = nullptr;
-    return nullptr;
-  }
-  ctx->arena_bytes = bytes;
-  return ctx->arena;
+  return ctx_grow(ctx, &ctx->arena, &ctx->arena_bytes, bytes, "arena allocation", st);
 }
 
 void timing_begin(nu_ctx* ctx, hipStream_t s, hipEvent_t* start) {
@@ -251,7 +279,7 @@ nu_status factor_compute(nu_ctx* ctx, nu_factor* F, const double* t, const nu_sh
 // ===========================================================================
 extern "C" {
 
-nu_status nu_ctx_create(int device, void* stream, nu_ctx** out) {
+nu_status nu_ctx_create(int device, void* stream, size_t workspace_limit_bytes, nu_ctx** out) {
   if (!out) return NU_ERR_ARG;
   *out = nullptr;
   int ndev = 0;
@@ -261,6 +289,7 @@ nu_status nu_ctx_create(int device, void* stream, nu_ctx** out) {
   if (!ctx) return NU_ERR_OOM;
   ctx->device = device;
   ctx->stream = (hipStream_t)stream;
+  ctx->mem->limit = workspace_limit_bytes;
   if (hipSetDevice(device) != hipSuccess || nu::fold_scratch_ptr(device, &ctx->scratch) != hipSuccess) {
     delete ctx;
     return NU_ERR_DEVICE;
@@ -280,6 +309,10 @@ void nu_ctx_destroy(nu_ctx* ctx) {
   }
   (void)hipStreamSynchronize(ctx->stream);
   nu::destroy_factor_streams(ctx);
+  if (ctx->s_fold) {
+    (void)hipStreamSynchronize(ctx->s_fold);
+    (void)hipStreamDestroy(ctx->s_fold);
+  }
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -299,10 +332,13 @@ nu_status nu_ctx_release_memory(nu_ctx* ctx) {
   if (st != NU_OK) return st;
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->arena) (void)hipFree(ctx->arena);
+  ctx->mem->live -= ctx->ws_bytes + ctx->arena_bytes;
   ctx->ws = ctx->arena = nullptr;
   ctx->ws_bytes = ctx->arena_bytes = 0;
   return NU_OK;
 }
+
+size_t nu_ctx_device_bytes(const nu_ctx* ctx) { return ctx ? ctx->mem->live.load() : 0; }
 
 nu_status nu_ctx_set_stream(nu_ctx* ctx, void* stream) {
   if (!ctx) return NU_ERR_ARG;

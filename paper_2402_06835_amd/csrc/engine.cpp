@@ -430,13 +430,13 @@ nu_status factor_alloc(nu_ctx* ctx, int64_t n, bool own_plan, nu_factor** out) {
   nu_factor* F = new_factor(ctx, n);
   if (!F) return set_error(ctx, NU_ERR_OOM, "factor: host allocation");
   const int64_t np = F->np;
-  nu_status st = check_hip(ctx, hipMalloc(&F->L, (size_t)np * np * sizeof(double)), "alloc L");
-  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->X, (size_t)np * np * sizeof(double)), "alloc X");
-  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->T, F->t_elems * sizeof(double)), "alloc T");
+  nu_status st = ctx_malloc(ctx, (void**)&F->L, (size_t)np * np * sizeof(double), F->hold, "alloc L");
+  if (st == NU_OK) st = ctx_malloc(ctx, (void**)&F->X, (size_t)np * np * sizeof(double), F->hold, "alloc X");
+  if (st == NU_OK) st = ctx_malloc(ctx, (void**)&F->T, F->t_elems * sizeof(double), F->hold, "alloc T");
   if (st == NU_OK)
-    st = check_hip(ctx, hipMalloc(&F->small, (size_t)(F->nblk + FACTOR_SMALL_EXTRA) * sizeof(double)),
-                   "alloc small");
-  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->nullfit, sizeof(NullFit)), "alloc nullfit");
+    st = ctx_malloc(ctx, (void**)&F->small, (size_t)(F->nblk + FACTOR_SMALL_EXTRA) * sizeof(double), F->hold,
+                    "alloc small");
+  if (st == NU_OK) st = ctx_malloc(ctx, (void**)&F->nullfit, sizeof(NullFit), F->hold, "alloc nullfit");
   if (st == NU_OK && own_plan) {
     std::vector<nu_factor*> one{F};
     plan_cholesky(one, ctx->tuning, F->plan64);
@@ -481,19 +481,24 @@ nu_status alloc_mixed(nu_ctx* ctx, nu_factor* F, int prec) {
   const int64_t np = F->np;
   nu_status st = NU_OK;
   if (!F->L32) {
-    st = check_hip(ctx, hipMalloc(&F->L32, (size_t)np * np * sizeof(float)), "alloc L32");
-    if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->X32, (size_t)np * np * sizeof(float)), "alloc X32");
+    st = ctx_malloc(ctx, (void**)&F->L32, (size_t)np * np * sizeof(float), F->hold, "alloc L32");
+    if (st == NU_OK) st = ctx_malloc(ctx, (void**)&F->X32, (size_t)np * np * sizeof(float), F->hold, "alloc X32");
   }
   if (st == NU_OK && F->bandP) {
     st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "band realloc sync");
     (void)hipFree(F->bandP);
     (void)hipFree(F->bandX);
+    F->hold.count->live -= F->band_bytes;
+    F->hold.bytes -= F->band_bytes;
+    F->band_bytes = 0;
     F->bandP = F->bandX = nullptr;
     F->band_w = 0;
   }
   const size_t band_elems = (size_t)F->nblk * (w + 1) * TB * TB;
-  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->bandP, band_elems * sizeof(double)), "alloc band");
-  if (st == NU_OK) st = check_hip(ctx, hipMalloc(&F->bandX, band_elems * sizeof(double)), "alloc band");
+  if (st == NU_OK) st = ctx_malloc(ctx, (void**)&F->bandP, band_elems * sizeof(double), F->hold, "alloc band");
+  if (st == NU_OK) F->band_bytes += band_elems * sizeof(double);
+  if (st == NU_OK) st = ctx_malloc(ctx, (void**)&F->bandX, band_elems * sizeof(double), F->hold, "alloc band");
+  if (st == NU_OK) F->band_bytes += band_elems * sizeof(double);
   if (st == NU_OK) F->band_w = w;
   return st;
 }
@@ -519,6 +524,7 @@ nu_status ensure_plan32(nu_ctx* ctx, nu_factor* F, int prec) {
 
 void factor_free(nu_factor* F) {
   if (!F) return;
+  F->hold.release();
   if (hipSetDevice(F->device) != hipSuccess) {  // the runtime has shut down: host side only
     delete F;
     return;
@@ -1007,8 +1013,7 @@ size_t batch_search_ws_doubles(int64_t n, int n_d, int64_t n_epochs) {
   const int64_t np = round_up(n, TB);
   const size_t xchunks = (size_t)((n + XRC - 1) / XRC), qchunks = (size_t)((n + QRC - 1) / QRC);
   const size_t yz = (size_t)np * YCOLS;
-  return 5 * yz + xchunks * yz + qchunks * (size_t)n_d * (size_t)n_epochs + ((size_t)n_epochs + 2) / 2 + 1 +
-         fold_workspace_doubles(n_d, n_epochs);
+  return 5 * yz + xchunks * yz + qchunks * (size_t)n_d * (size_t)n_epochs + ((size_t)n_epochs + 2) / 2 + 1;
 }
 
 void batch_carve_search_ws(CurveJob& J, double* ws, int n_d) {
@@ -1028,7 +1033,7 @@ void batch_carve_search_ws(CurveJob& J, double* ws, int n_d) {
   J.slot_count = reinterpret_cast<int32_t*>(slots);
   double* flag = slots + ((size_t)J.n_epochs + 2) / 2;
   J.lattice_ok = reinterpret_cast<int*>(flag);
-  J.packed = flag + 1;
+  J.packed = nullptr;  // the packed fold grid lives outside the workspace
 }
 
 int64_t linear_stage_blocks(int stage, const CurveJob& J, int n_d);  // linear.hip

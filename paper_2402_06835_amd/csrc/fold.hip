@@ -605,10 +605,12 @@ __global__ __launch_bounds__(256, 3) void batch_fold_kernel(const CurveJob* __re
 }
 
 // the best period of every curve; -1 for a curve whose factorisation failed
-__global__ __launch_bounds__(1024) void batch_best_kernel(const CurveJob* __restrict__ jobs, int64_t n_p) {
+// (status_out: the statuses collected by curve index, see launch_batch_collect)
+__global__ __launch_bounds__(1024) void batch_best_kernel(const CurveJob* __restrict__ jobs, int64_t n_p,
+                                                          const int64_t* __restrict__ status_out) {
   const CurveJob& J = jobs[blockIdx.x];
   if (!J.best_index) return;
-  if (*J.status >= 0) {
+  if (status_out[J.curve] >= 0) {
     if (threadIdx.x == 0) *J.best_index = -1;
     return;
   }
@@ -632,8 +634,9 @@ hipError_t launch_batch_fold(hipStream_t s, const CurveJob* jobs, const int* beg
   return hipGetLastError();
 }
 
-hipError_t launch_batch_best(hipStream_t s, const CurveJob* jobs, int n_curves, int64_t n_p) {
-  hipLaunchKernelGGL(batch_best_kernel, dim3((unsigned)n_curves), dim3(1024), 0, s, jobs, n_p);
+hipError_t launch_batch_best(hipStream_t s, const CurveJob* jobs, int n_curves, int64_t n_p,
+                             const int64_t* status_out) {
+  hipLaunchKernelGGL(batch_best_kernel, dim3((unsigned)n_curves), dim3(1024), 0, s, jobs, n_p, status_out);
   return hipGetLastError();
 }
 

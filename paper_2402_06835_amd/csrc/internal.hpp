@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
+#include <memory>
 #include <map>
 #include <string>
 #include <vector>
@@ -115,6 +117,26 @@ struct NullFit {
 
 }  // namespace nu
 
+namespace nu {
+// Device bytes counted against a context's workspace limit (0: none): its
+// search workspace and batch arena, and the buffers of the factors, graphs,
+// networks and batch calls made on it. Every object holding such buffers
+// shares the count, since it may outlive its context.
+struct MemCount {
+  std::atomic<size_t> live{0};
+  size_t limit = 0;
+};
+// the part of its context's count one object holds
+struct MemHold {
+  std::shared_ptr<MemCount> count;
+  size_t bytes = 0;
+  void release() {
+    if (count) count->live -= bytes;
+    bytes = 0;
+  }
+};
+}  // namespace nu
+
 struct nu_timing_slot {
   int64_t launches = 0;
   double ms = 0.0;
@@ -137,6 +159,8 @@ struct nu_ctx {
   // device arena of the batch factors, kept between calls
   void* arena = nullptr;
   size_t arena_bytes = 0;
+  // device memory counted against the workspace limit
+  std::shared_ptr<nu::MemCount> mem = std::make_shared<nu::MemCount>();
   // kernel timing
   bool timing = false;
   std::vector<nu_pending_event> pending;
@@ -149,6 +173,9 @@ struct nu_ctx {
   // panels and lookahead updates on s_fac; the rest of each trailing update
   // on s_rest, which leaves LOOKAHEAD_FREE_CUS compute units to s_fac
   hipStream_t s_fac = nullptr, s_rest = nullptr;
+  // the periodic search of a batch wave, beside the next wave's factorisation
+  // (created on first use; default priority, non-blocking)
+  hipStream_t s_fold = nullptr;
   hipEvent_t ev_fork = nullptr, ev_pan = nullptr, ev_rest = nullptr, ev_join = nullptr;
   bool lookahead = true;
   // early inverse of a factorisation: its stream (on the top s_inv_cus CUs),
@@ -233,11 +260,13 @@ struct nu_factor {
   double* bandP = nullptr;   // (I, d) blocks of L X on the band, stored by column block
   double* bandX = nullptr;   // refined band blocks
   int band_w = 0;            // widest band the band buffers hold
+  size_t band_bytes = 0;     // device bytes of the band buffers it allocated
   nu::Plan plan32;           // reduced-precision inverse + FP64 band step
   int plan32_prec = 0;       // the nu_precision plan32 was built for
   int inverse_kind = 0;  // 0 none, else 1 + the nu_precision X was formed in
   double logdet = 0.0;
   bool owns_memory = true;   // false: buffers carved from the context's arena
+  nu::MemHold hold;          // its buffers' share of the context's memory count
   double* parts() const { return small; }
   double* logdet_dev() const { return small + nblk; }
   int64_t* status_dev() const { return reinterpret_cast<int64_t*>(small + nblk + 1); }
@@ -253,6 +282,12 @@ namespace nu {
 nu_status set_error(nu_ctx* ctx, nu_status st, const std::string& msg);
 nu_status check_hip(nu_ctx* ctx, hipError_t e, const char* what);
 void* ctx_workspace(nu_ctx* ctx, size_t bytes, nu_status* st);
+// NU_ERR_OOM if the context's count, less `replaced`, plus `bytes` exceeds its limit
+nu_status mem_check(nu_ctx* ctx, size_t bytes, size_t replaced, const char* what);
+// hipMalloc counted against the context's limit, on behalf of `hold`
+nu_status ctx_malloc(nu_ctx* ctx, void** p, size_t bytes, MemHold& hold, const char* what);
+// what a batch call may still place (the limit less what is held outside the arena; SIZE_MAX: no limit)
+size_t mem_headroom(const nu_ctx* ctx, size_t replaced);
 // host -> device copy on the context's stream through the pinned staging buffer
 nu_status ctx_upload(nu_ctx* ctx, const void* host, size_t bytes, void* dev);
 // template shapes: validates n_d shapes of dur_samples_host[j] values each (finite, total <= MAX_SHAPE)
@@ -493,9 +528,10 @@ enum BatchStage {
 };
 // workgroups of stage `stage` for one curve (n_d durations, band width w, n_p periods)
 int64_t batch_stage_blocks(int stage, const CurveJob& J, int n_d, int band_w);
-// doubles of one curve's search workspace: linear search + packed fold grid
+// doubles of one curve's linear-search workspace (the packed fold grid is kept
+// apart, so a wave's fold can run while the next wave reuses the workspace)
 size_t batch_search_ws_doubles(int64_t n, int n_d, int64_t n_epochs);
-// carve a curve's search workspace (linear search + packed grid) from ws
+// carve a curve's linear-search workspace from ws
 void batch_carve_search_ws(CurveJob& J, double* ws, int n_d);
 
 // GEMV passes of the linear search: the matrix (X or L), the vector panel
@@ -531,6 +567,7 @@ hipError_t launch_batch_epilogue(hipStream_t s, const CurveJob* jobs, const int*
                                  const int32_t* dur, int n_d, int m1);
 hipError_t launch_batch_fold(hipStream_t s, const CurveJob* jobs, const int* begin_pack, int n_curves,
                              int total_pack, int n_d, const double* periods, int64_t n_p, int sign);
-hipError_t launch_batch_best(hipStream_t s, const CurveJob* jobs, int n_curves, int64_t n_p);
+hipError_t launch_batch_best(hipStream_t s, const CurveJob* jobs, int n_curves, int64_t n_p,
+                             const int64_t* status_out);
 
 }  // namespace nu

@@ -34,6 +34,7 @@ struct nu_cnn {
   float* loss = nullptr;     // device scalar of the last step
   CnnBuffers buf{};
   void* arena = nullptr;     // activations and scratch
+  MemHold hold;              // the arena against the context's limit
   int64_t step = 0;
 };
 
@@ -340,7 +341,7 @@ nu_status nu_cnn_create(nu_ctx* ctx, int half_precision, int max_batch, nu_cnn**
     sz = (sz + 255) / 256 * 256;
     total += sz;
   }
-  st = check_hip(ctx, hipMalloc(&M->arena, total), "alloc cnn");
+  st = ctx_malloc(ctx, &M->arena, total, M->hold, "alloc cnn");
   if (st == NU_OK) st = check_hip(ctx, hipMemset(M->arena, 0, total), "clear cnn");
   if (st != NU_OK) {
     nu_cnn_destroy(M);
@@ -372,6 +373,7 @@ nu_status nu_cnn_create(nu_ctx* ctx, int half_precision, int max_batch, nu_cnn**
 
 void nu_cnn_destroy(nu_cnn* M) {
   if (!M) return;
+  M->hold.release();
   if (hipSetDevice(M->device) != hipSuccess) {  // the runtime has shut down: host side only
     delete M;
     return;

@@ -94,7 +94,8 @@ def test_null_context_is_rejected_without_a_gpu(libpath):
     assert L.nu_graph_launch(None, None) == _lib.NU_ERR_ARG
     assert L.nu_ctx_autotune(None, 1024, 0) == _lib.NU_ERR_ARG
     assert L.nu_ctx_set_tuning(None, 0, 0) == _lib.NU_ERR_ARG
-    assert L.nu_ctx_create(0, None, None) == _lib.NU_ERR_ARG
+    assert L.nu_ctx_create(0, None, 0, None) == _lib.NU_ERR_ARG
+    assert L.nu_ctx_device_bytes(None) == 0
     assert L.nu_ctx_last_error(None) == b"null context"
     assert L.nu_factor_n(None) == -1
 
