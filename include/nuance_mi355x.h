@@ -162,6 +162,10 @@ nu_status nu_ctx_set_inverse_prefetch(nu_ctx* ctx, int prec, int compute_units);
  * launches (flops for the dense kernels, bytes for the fold). Reading the
  * entries synchronises the stream. */
 nu_status nu_ctx_enable_timing(nu_ctx* ctx, int enable);
+/* Restricts the timing to the launches whose kernel name starts with prefix
+ * (NULL or "": every launch), so that the events of a measurement do not
+ * delay the other launches. The prefix is copied. */
+nu_status nu_ctx_set_timing_filter(nu_ctx* ctx, const char* prefix);
 nu_status nu_ctx_timing_reset(nu_ctx* ctx);
 int nu_ctx_timing_count(nu_ctx* ctx);
 nu_status nu_ctx_timing_entry(nu_ctx* ctx, int index, const char** name_host, int64_t* launches_host,

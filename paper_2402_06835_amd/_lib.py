@@ -43,6 +43,7 @@ SIGNATURES = {
     "nu_ctx_set_inverse_prefetch": (c_int, [c_void_p, c_int, c_int]),
     "nu_ctx_last_error": (c_char_p, [c_void_p]),
     "nu_ctx_enable_timing": (c_int, [c_void_p, c_int]),
+    "nu_ctx_set_timing_filter": (c_int, [c_void_p, c_char_p]),
     "nu_ctx_timing_reset": (c_int, [c_void_p]),
     "nu_ctx_timing_count": (c_int, [c_void_p]),
     "nu_ctx_timing_entry": (c_int, [c_void_p, c_int, P(c_char_p), P(c_int64), P(c_double), P(c_double)]),

@@ -127,6 +127,10 @@ class Context:
     def enable_timing(self, on: bool = True):
         _check(self.ptr, lib().nu_ctx_enable_timing(self.ptr, int(on)))
 
+    def set_timing_filter(self, prefix: str = ""):
+        """Time only the launches whose kernel name starts with prefix ("" for all)."""
+        _check(self.ptr, lib().nu_ctx_set_timing_filter(self.ptr, prefix.encode()))
+
     def reset_timing(self):
         _check(self.ptr, lib().nu_ctx_timing_reset(self.ptr))
 

@@ -122,9 +122,10 @@ void* ctx_arena(nu_ctx* ctx, size_t bytes, nu_status* st) {
   return ctx_grow(ctx, &ctx->arena, &ctx->arena_bytes, bytes, "arena allocation", st);
 }
 
-void timing_begin(nu_ctx* ctx, hipStream_t s, hipEvent_t* start) {
+void timing_begin(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t* start) {
   *start = nullptr;
   if (!ctx->timing) return;
+  if (!ctx->timing_only.empty() && std::strncmp(name, ctx->timing_only.c_str(), ctx->timing_only.size()) != 0) return;
   if (ctx->free_events.empty()) {
     hipEvent_t ev;
     if (hipEventCreate(&ev) != hipSuccess) return;
@@ -361,6 +362,12 @@ nu_status nu_ctx_set_inverse_prefetch(nu_ctx* ctx, int prec, int compute_units) 
 nu_status nu_ctx_enable_timing(nu_ctx* ctx, int enable) {
   if (!ctx) return NU_ERR_ARG;
   ctx->timing = enable != 0;
+  return NU_OK;
+}
+
+nu_status nu_ctx_set_timing_filter(nu_ctx* ctx, const char* prefix) {
+  if (!ctx) return NU_ERR_ARG;
+  ctx->timing_only = prefix ? prefix : "";
   return NU_OK;
 }
 

@@ -149,65 +149,69 @@ __device__ __forceinline__ dbl4 mfma64(double av, double bv, dbl4 acc) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
 }
 
-// One doubling level of the in-block inverse: NODES nodes of edge 2*BS, the
-// A part at a0 = node*2*BS, the C part at c0 = a0 + BS. Work unit = one 16 x 16
-// output piece per wave.
+// X[r][c] of the in-LDS inverse when r > c is known to hold (a block strictly
+// below the diagonal)
+__device__ __forceinline__ double xlow(const double (*a)[DPAD], int r, int c) { return a[c][r]; }
+
+// One doubling level of the in-block inverse: NODES nodes of edge 2*BS (the
+// A part at a0 = node*2*BS, the C part at c0 = a0 + BS), NB = BS/16 pieces a
+// side. The NB waves of a node each take one piece row (first product) or one
+// piece column (second product), so every wave does the same number of
+// 16 x 16 x 16 products, and every loop bound is a compile-time constant
+// (straight-line code whose LDS reads the compiler issues ahead of the
+// MFMAs). The sums run over the same k in the same order as a plain loop.
 template <int BS, int NODES>
 __device__ void inverse_level(double (*a)[DPAD], const double* xd) {
   constexpr int NB = BS / SB;
-  constexpr int TT = NODES * NB * NB;
-  constexpr int PER = (TT + 3) / 4;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  static_assert(NB * NODES == 4, "one wave per piece row of a node");
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
-  // T = L21 X_A, kept at a[a0 + j][c0 + i] until overwritten by X21
+  const int node = wave / NB, wi = wave % NB;
+  const int a0 = node * 2 * BS, c0 = a0 + BS;
+  // T = L21 X_A: this wave's piece row bi = wi, pieces bj = 0..NB-1, k over
+  // blocks bj..NB-1 (X_A is lower); kept at a[a0 + j][c0 + i] until X21 replaces it
+  {
+    const int bi = wi;
+    dbl4 acc[NB];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int t = wave + 4 * u;
-    if (t < TT) {
-      const int node = t / (NB * NB), e = t % (NB * NB), bi = e / NB, bj = e % NB;
-      const int a0 = node * 2 * BS, c0 = a0 + BS;
-      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int bj = 0; bj < NB; ++bj) {
+      acc[bj] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
       for (int bk = bj; bk < NB; ++bk)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int k = bk * SB + q * 4 + lk;
-          acc = mfma64(a[c0 + bi * SB + lr][a0 + k], xget(a, xd, a0 + k, a0 + bj * SB + lr), acc);
+          const int k = a0 + bk * SB + q * 4 + lk, col = a0 + bj * SB + lr;
+          const double xa = bk > bj ? xlow(a, k, col) : xget(a, xd, k, col);
+          acc[bj] = mfma64(a[c0 + bi * SB + lr][k], xa, acc[bj]);
         }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) a[a0 + bj * SB + lr][c0 + bi * SB + lk + 4 * v] = acc[v];
     }
+#pragma unroll
+    for (int bj = 0; bj < NB; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[a0 + bj * SB + lr][c0 + bi * SB + lk + 4 * v] = acc[bj][v];
   }
   __syncthreads();
-  // X21 = -X_C T
-  dbl4 res[PER];
+  // X21 = -X_C T: this wave's piece column bj = wi, pieces bi = 0..NB-1, k over
+  // blocks 0..bi (X_C is lower)
+  const int bj = wi;
+  dbl4 res[NB];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int t = wave + 4 * u;
-    res[u] = dbl4{0.0, 0.0, 0.0, 0.0};
-    if (t < TT) {
-      const int node = t / (NB * NB), e = t % (NB * NB), bi = e / NB, bj = e % NB;
-      const int a0 = node * 2 * BS, c0 = a0 + BS;
-      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-      for (int bk = 0; bk <= bi; ++bk)
+  for (int bi = 0; bi < NB; ++bi) {
+    res[bi] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k = bk * SB + q * 4 + lk;
-          acc = mfma64(-xget(a, xd, c0 + bi * SB + lr, c0 + k), a[a0 + bj * SB + lr][c0 + k], acc);
-        }
-      res[u] = acc;
-    }
+    for (int bk = 0; bk <= bi; ++bk)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = c0 + bi * SB + lr, k = c0 + bk * SB + q * 4 + lk;
+        const double xc = bk < bi ? xlow(a, row, k) : xget(a, xd, row, k);
+        res[bi] = mfma64(-xc, a[a0 + bj * SB + lr][k], res[bi]);
+      }
   }
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int t = wave + 4 * u;
-    if (t < TT) {
-      const int node = t / (NB * NB), e = t % (NB * NB), bi = e / NB, bj = e % NB;
-      const int a0 = node * 2 * BS, c0 = a0 + BS;
+  for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) a[a0 + bj * SB + lr][c0 + bi * SB + lk + 4 * v] = res[u][v];
-    }
-  }
+    for (int v = 0; v < 4; ++v) a[a0 + bj * SB + lr][c0 + bi * SB + lk + 4 * v] = res[bi][v];
   __syncthreads();
 }
 
@@ -223,22 +227,16 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __re
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  // load the block: 64 values per thread, 16 loads in flight at a time
-  // (the whole 128 x 128 block lies inside the matrix; the upper part is
-  // discarded)
-  for (int u0 = 0; u0 < DB * DB / 256; u0 += 16) {
-    double v[16];
+  // load the lower triangle: up to 64 values per thread, all loads in flight
+  // at once (thread tid reads column tid & 127 of rows tid >> 7, +2, +4, ...)
+  {
+    const int c = tid & 127, r0 = tid >> 7;
+    const NU_GLOBAL double* src = L + (off + r0) * ld + off + c;
+    double v[DB * DB / 256];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = tid + 256 * (u0 + u);
-      v[u] = L[(off + (idx >> 7)) * ld + off + (idx & 127)];
-    }
+    for (int u = 0; u < DB * DB / 256; ++u) v[u] = c <= r0 + 2 * u ? src[2 * u * ld] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = tid + 256 * (u0 + u);
-      const int r = idx >> 7, c = idx & 127;
-      a[r][c] = c <= r ? v[u] : 0.0;
-    }
+    for (int u = 0; u < DB * DB / 256; ++u) a[r0 + 2 * u][c] = v[u];
   }
   __syncthreads();
   const int pr = tid >> 4, ps = tid & 15;  // (row, column) of a 16 x 16 piece owned by this thread
@@ -335,26 +333,23 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __re
     const int r = idx / DB, c = idx - (idx / DB) * DB;
     L[(off + r) * ld + off + c] = c <= r ? a[r][c] : 0.0;
   }
-  // inverses of the eight 16 x 16 diagonal pieces: wave w takes pieces w and
-  // w + 4, lane j < 16 forms column j by forward substitution
+  // inverses of the eight 16 x 16 diagonal pieces, all at once: wave w takes
+  // pieces w (lanes 0-15) and w + 4 (lanes 16-31), lane j forms column j by
+  // forward substitution
+  if (lane < 2 * SB) {
+    const int o = (wave + 4 * (lane >> 4)) * SB, j = lane & 15;
+    double x[SB];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int o = (wave + 4 * h) * SB;
-    if (lane < SB) {
-      const int j = lane;
-      double x[SB];
+    for (int i = 0; i < SB; ++i) {
+      double acc = (i == j) ? 1.0 : 0.0;
 #pragma unroll
-      for (int i = 0; i < SB; ++i) {
-        double acc = (i == j) ? 1.0 : 0.0;
+      for (int s2 = 0; s2 < i; ++s2) acc = fma(-a[o + i][o + s2], x[s2], acc);
+      x[i] = (i >= j) ? acc * rdg[o + i] : 0.0;
+    }
 #pragma unroll
-        for (int s2 = 0; s2 < i; ++s2) acc = fma(-a[o + i][o + s2], x[s2], acc);
-        x[i] = (i >= j) ? acc * rdg[o + i] : 0.0;
-      }
-#pragma unroll
-      for (int i = 0; i < SB; ++i) {
-        if (i > j) a[o + j][o + i] = x[i];
-        if (i == j) xd[o + j] = x[i];
-      }
+    for (int i = 0; i < SB; ++i) {
+      if (i > j) a[o + j][o + i] = x[i];
+      if (i == j) xd[o + j] = x[i];
     }
   }
   __syncthreads();

@@ -161,8 +161,9 @@ struct nu_ctx {
   size_t arena_bytes = 0;
   // device memory counted against the workspace limit
   std::shared_ptr<nu::MemCount> mem = std::make_shared<nu::MemCount>();
-  // kernel timing
+  // kernel timing (only of the launches whose name starts with timing_only, when set)
   bool timing = false;
+  std::string timing_only;
   std::vector<nu_pending_event> pending;
   std::vector<hipEvent_t> free_events;
   std::map<std::string, nu_timing_slot> timings;
@@ -294,7 +295,7 @@ nu_status ctx_upload(nu_ctx* ctx, const void* host, size_t bytes, void* dev);
 nu_status validate_shapes(nu_ctx* ctx, const double* shapes_host, const int32_t* dur_samples_host, int n_d);
 
 // kernel timing (capi.cpp): events on the context's stream around a launch
-void timing_begin(nu_ctx* ctx, hipStream_t s, hipEvent_t* start);
+void timing_begin(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t* start);
 void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, double work);
 void resolve_timing(nu_ctx* ctx);  // synchronises the stream, folds pending events into the totals
 struct Timed {
@@ -305,7 +306,7 @@ struct Timed {
   hipEvent_t start;
   Timed(nu_ctx* c, const char* n, double w) : Timed(c, c->stream, n, w) {}
   Timed(nu_ctx* c, hipStream_t s, const char* n, double w) : ctx(c), stream(s), name(n), work(w) {
-    timing_begin(c, s, &start);
+    timing_begin(c, s, n, &start);
   }
   ~Timed() { timing_end(ctx, stream, name, start, work); }
 };
