@@ -121,6 +121,7 @@ constexpr int SB = 16;       // piece edge
 constexpr int NSB = DB / SB; // 8
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 // 1/x: the hardware estimate r with a third-order correction (e = 1 - x r,
 // 1/x = r (1 + e + e^2 + ...); measured |e| <= 2^-24.4, result within 1 ulp)
@@ -329,9 +330,11 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __re
     for (int offs = 32; offs > 0; offs >>= 1) v += __shfl_xor(v, offs, 64);
     if (lane == 0) ((NU_GLOBAL double*)J.parts)[J.step] = 2.0 * v;
   }
-  for (int idx = tid; idx < DB * DB; idx += 256) {
-    const int r = idx / DB, c = idx - (idx / DB) * DB;
-    L[(off + r) * ld + off + c] = c <= r ? a[r][c] : 0.0;
+  // the block of L (zeros above the diagonal), two columns per 16-byte store
+  for (int idx = tid; idx < DB * DB / 2; idx += 256) {
+    const int r = idx >> 6, c = 2 * (idx & 63);
+    const dbl2 v = {c <= r ? a[r][c] : 0.0, c < r ? a[r][c + 1] : 0.0};
+    *(NU_GLOBAL dbl2*)(L + (off + r) * ld + off + c) = v;
   }
   // inverses of the eight 16 x 16 diagonal pieces, all at once: wave w takes
   // pieces w (lanes 0-15) and w + 4 (lanes 16-31), lane j forms column j by
@@ -356,9 +359,10 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __re
   inverse_level<16, 4>(a, xd);
   inverse_level<32, 2>(a, xd);
   inverse_level<64, 1>(a, xd);
-  for (int idx = tid; idx < DB * DB; idx += 256) {
-    const int r = idx / DB, c = idx - (idx / DB) * DB;
-    X[(off + r) * ldx + off + c] = xget(a, xd, r, c);
+  for (int idx = tid; idx < DB * DB / 2; idx += 256) {
+    const int r = idx >> 6, c = 2 * (idx & 63);
+    const dbl2 v = {xget(a, xd, r, c), xget(a, xd, r, c + 1)};
+    *(NU_GLOBAL dbl2*)(X + (off + r) * ldx + off + c) = v;
   }
 }
 

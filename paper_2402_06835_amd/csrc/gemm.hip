@@ -36,7 +36,18 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef float flt2 __attribute__((ext_vector_type(2)));
 
 constexpr int GBK = 16;
-constexpr int LPAD = 4;
+// LDS row padding of the staged slices, per element type
+#ifndef NU_LPAD_F32
+#define NU_LPAD_F32 4
+#endif
+template <typename T>
+struct Lpad {
+  static constexpr int v = 4;
+};
+template <>
+struct Lpad<float> {
+  static constexpr int v = NU_LPAD_F32;
+};
 
 // Tile order within a problem: groups of GROUP tile-rows, column-major inside
 // a group, so any run of consecutive tiles covers a compact block of rows and
@@ -69,6 +80,24 @@ __device__ __forceinline__ void tile_of(const GemmProblem& P, int t, int& tm, in
       tn = g0 + c;
       tm = g0 + c + u;
     }
+  } else if (P.flags & G_A_LOWER) {
+    // a lower A gives row group g about g + 1 slices of k per tile: the
+    // heaviest groups go first, so the launch ends on light tiles
+    const int Tm = P.M / BM, Tn = P.tiles_n;
+    const int G = (Tm + GROUP - 1) / GROUP, Rl = Tm - (G - 1) * GROUP;
+    int g, u, R;
+    if (t < Rl * Tn) {
+      g = G - 1;
+      u = t;
+      R = Rl;
+    } else {
+      const int t2 = t - Rl * Tn;
+      g = G - 2 - t2 / (GROUP * Tn);
+      u = t2 - (t2 / (GROUP * Tn)) * GROUP * Tn;
+      R = GROUP;
+    }
+    tn = u / R;
+    tm = g * GROUP + u % R;
   } else {
     const int Tm = P.M / BM, Tn = P.tiles_n;
     const int g = t / (GROUP * Tn);
@@ -124,6 +153,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
   constexpr int EB = BN * GBK / 256;  // elements per thread of a B slice
   constexpr int NBM = BM / 32;        // MFMA blocks per wave sub-tile, rows
   constexpr int NBN = BN / 32;        // and columns
+  constexpr int LPAD = Lpad<T>::v;
   __shared__ T As[2][GBK][BM + LPAD];
   __shared__ T Bs[2][GBK][BN + LPAD];
   typedef typename Mfma<T>::acc_t acc_t;
