@@ -228,18 +228,36 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __re
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  // load the lower triangle: up to 64 values per thread, all loads in flight
-  // at once (thread tid reads column tid & 127 of rows tid >> 7, +2, +4, ...)
+  // load the lower triangle, two columns per 16-byte load, all loads in
+  // flight at once (thread tid reads columns 2 (tid & 63), +1 of rows
+  // tid >> 6, +4, +8, ...); the upper triangle is set to zero
   {
-    const int c = tid & 127, r0 = tid >> 7;
+    const int c = 2 * (tid & 63), r0 = tid >> 6;
     const NU_GLOBAL double* src = L + (off + r0) * ld + off + c;
-    double v[DB * DB / 256];
+    dbl2 v[DB * DB / 512];
 #pragma unroll
-    for (int u = 0; u < DB * DB / 256; ++u) v[u] = c <= r0 + 2 * u ? src[2 * u * ld] : 0.0;
+    for (int u = 0; u < DB * DB / 512; ++u)
+      v[u] = c <= r0 + 4 * u ? *(const NU_GLOBAL dbl2*)(src + 4 * u * ld) : dbl2{0.0, 0.0};
 #pragma unroll
-    for (int u = 0; u < DB * DB / 256; ++u) a[r0 + 2 * u][c] = v[u];
+    for (int u = 0; u < DB * DB / 512; ++u) {
+      const int r = r0 + 4 * u;
+      a[r][c] = v[u][0];
+      a[r][c + 1] = c + 1 <= r ? v[u][1] : 0.0;
+    }
   }
   __syncthreads();
+  // 16-byte stores of rows [r0, r1) x columns [c0, c1) of a block of L or X
+  // (columns an even count), value(r, c) from LDS
+  auto store_rect = [&](NU_GLOBAL double* dst, int64_t ldd, int r0, int r1, int c0, int c1, auto value) {
+    const int w = (c1 - c0) / 2, cnt = (r1 - r0) * w;
+    for (int idx = tid; idx < cnt; idx += 256) {
+      const int r = r0 + idx / w, c = c0 + 2 * (idx % w);
+      const dbl2 v = {value(r, c), value(r, c + 1)};
+      *(NU_GLOBAL dbl2*)(dst + (off + r) * ldd + off + c) = v;
+    }
+  };
+  auto lval = [&](int r, int c) { return c <= r ? a[r][c] : 0.0; };
+  auto xval = [&](int r, int c) { return xget(a, xd, r, c); };
   const int pr = tid >> 4, ps = tid & 15;  // (row, column) of a 16 x 16 piece owned by this thread
   for (int kb = 0; kb < NSB; ++kb) {
     const int o = kb * SB;
@@ -302,6 +320,9 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __re
       for (int c = 0; c < SB; ++c) a[r][o + c] = x[c];
     }
     __syncthreads();
+    // columns [o, o + 16) of L are final: store them (zeros above the
+    // diagonal) while the rest of the block is factored
+    store_rect(L, ld, 0, DB, o, o + SB, lval);
     // (c) trailing pieces (i, j), kb < j <= i: A_ij -= P_i P_j^T on the matrix cores
     const int m = NSB - 1 - kb;
     for (int t = wave; t < m * (m + 1) / 2; t += 4) {
@@ -330,12 +351,6 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __re
     for (int offs = 32; offs > 0; offs >>= 1) v += __shfl_xor(v, offs, 64);
     if (lane == 0) ((NU_GLOBAL double*)J.parts)[J.step] = 2.0 * v;
   }
-  // the block of L (zeros above the diagonal), two columns per 16-byte store
-  for (int idx = tid; idx < DB * DB / 2; idx += 256) {
-    const int r = idx >> 6, c = 2 * (idx & 63);
-    const dbl2 v = {c <= r ? a[r][c] : 0.0, c < r ? a[r][c + 1] : 0.0};
-    *(NU_GLOBAL dbl2*)(L + (off + r) * ld + off + c) = v;
-  }
   // inverses of the eight 16 x 16 diagonal pieces, all at once: wave w takes
   // pieces w (lanes 0-15) and w + 4 (lanes 16-31), lane j forms column j by
   // forward substitution
@@ -358,12 +373,12 @@ __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __re
   __syncthreads();
   inverse_level<16, 4>(a, xd);
   inverse_level<32, 2>(a, xd);
+  // the two 64 x 64 diagonal blocks of X and the zeros right of the first are
+  // final (the last level only reads them): stored while it runs
+  store_rect(X, ldx, 0, DB / 2, 0, DB, xval);
+  store_rect(X, ldx, DB / 2, DB, DB / 2, DB, xval);
   inverse_level<64, 1>(a, xd);
-  for (int idx = tid; idx < DB * DB / 2; idx += 256) {
-    const int r = idx >> 6, c = 2 * (idx & 63);
-    const dbl2 v = {xget(a, xd, r, c), xget(a, xd, r, c + 1)};
-    *(NU_GLOBAL dbl2*)(X + (off + r) * ldx + off + c) = v;
-  }
+  store_rect(X, ldx, DB / 2, DB, 0, DB / 2, xval);
 }
 
 // one workgroup per job (one diagonal block per factor of a batch)

@@ -40,6 +40,12 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, fma(e, e, e), r);
 }
 
+#ifndef NU_FOLD_PIPE
+#define NU_FOLD_PIPE 0
+#endif
+#ifndef NU_FOLD_WAVES
+#define NU_FOLD_WAVES 3
+#endif
 constexpr int FPAD = 64;  // padded slots after the grid (invalid), one wave wide
 constexpr int WPH = 63;   // phases per wave: lane 63 only supplies its neighbour
 
@@ -81,6 +87,17 @@ __device__ __forceinline__ double from_next_lane(double x) {
   const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x130, 0xF, 0xF, true);
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x130, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
+}
+
+// (1 - w) x + w y with u = 1 - w, the second product rounded into the sum
+__device__ __forceinline__ double interp(double u, double w, double x, double y) { return fma(w, y, u * x); }
+
+// min of two doubles that are not NaN: one v_min_f64 (fmin would first quiet
+// both operands, as a signalling NaN could reach it as far as the compiler knows)
+__device__ __forceinline__ double min_num(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
 }
 
 // Element idx (>= 0, within 2^32 bytes of the row start: the periodic search
@@ -128,15 +145,19 @@ __device__ __forceinline__ bool seg_event(const Segs& S, int64_t mb, int64_t b, 
 
 // Eq. 8 with the estimates of Eq. B4, for the durations j0 .. j0+JG-1 and the
 // phases m = mb + lane of one wave. All lanes share base_k = floor(k p) and
-// w_k, so an event's right-hand slot is the next lane's left-hand slot.
+// w_k, so an event's right-hand slot is the next lane's left-hand slot; the
+// interpolation (1 - w) V_i + w V_i+1 rounds the second product into the sum
+// (one FMA), within an ulp of the separately rounded form.
 // The sum of log ratios is taken as one logarithm of a product:
-//   sum_k [ln var_k - ln(sigma^2 + var_k)] = -ln prod_k (1 + sigma^2 / var_k),
-// where the product lies in (1, e] because sigma^2 sum_k 1/var_k = 1.
+//   sum_k [ln var_k - ln(sigma^2 + var_k)] = ln prod_k var_k / (var_k + sigma^2),
+// where the product lies in [1/e, 1) because sigma^2 sum_k 1/var_k = 1; one
+// reciprocal r = 1 / (var_k + sigma^2) per event gives both the factor
+// var_k r and the chi^2 term (d_k - D)^2 r.
 //
 // Pass 2 (the chi^2 and log terms, which need the combined depth and sigma^2
 // of pass 1) is skipped for a group of durations when no cell of the wave can
 // reach the best lnP found so far for this period (thr, from any wave of the
-// workgroup). The bound, from pass-1 sums alone: with L = ln prod in [0, 1],
+// workgroup). The bound, from pass-1 sums alone: with L = -ln prod in [0, 1],
 //   lnP = S_ll - (-s L + chi^2) / 2 <= S_ll + [s > 0] / 2 - chi^2 / 2,
 // and, since sigma^2 <= v_min (the smallest var_k) and sum_k (d_k - D) / v_k = 0,
 //   chi^2 >= sum_k (d_k - D)^2 / (v_k (1 + sigma^2 / v_min))
@@ -159,23 +180,43 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
     dvr[g] = DV + r0;
     lpr[g] = Lp + r0;
   }
+  // s_w > 0 once a cell has an event (every valid var is positive and finite)
   double s_w[JG], s_wd[JG], s_ll[JG], s_dd[JG];
   double vmin = INFINITY;  // over the group's durations: a smaller v_min only loosens the bound
-  int cnt[JG];
 #pragma unroll
-  for (int g = 0; g < JG; ++g) {
-    s_w[g] = s_wd[g] = s_ll[g] = s_dd[g] = 0.0;
-    cnt[g] = 0;
-  }
+  for (int g = 0; g < JG; ++g) s_w[g] = s_wd[g] = s_ll[g] = s_dd[g] = 0.0;
+  // one event of pass 1 for every duration of the group, from its loaded slots
+  auto event1 = [&](const double2 (&dv)[JG], const double (&l)[JG], double w) {
+    const double u = 1.0 - w;
+#pragma unroll
+    for (int g = 0; g < JG; ++g) {
+      double d = dv[g].x, v = dv[g].y, ll = l[g];
+      if (w != 0.0) {
+        d = interp(u, w, d, from_next_lane(d));
+        v = interp(u, w, v, from_next_lane(v));
+        ll = interp(u, w, ll, from_next_lane(ll));
+      }
+      if (v == v && j0 + g < n_d) {
+        const double iv = rcp_nr(v);
+        const double dw = d * iv;
+        s_w[g] = s_w[g] + iv;
+        s_wd[g] = s_wd[g] + dw;
+        s_dd[g] = fma(d, dw, s_dd[g]);  // enters only the skipping bound, which has a margin
+        s_ll[g] = s_ll[g] + ll;
+        vmin = min_num(vmin, v);
+      }
+    }
+  };
   // pass 1 (k counts events as an int64 and, exactly, as a double for k p)
-  int seg = 0;
-  double kd = 0.0;
-  for (int64_t k = 0;; ++k, kd += 1.0) {
-    const double kp = kd * p;
-    const double base = floor(kp);
-    if (base > (double)kmax_base) break;
-    int b = (int)base;
-    if constexpr (SEG) {
+  if constexpr (SEG || !NU_FOLD_PIPE) {
+    int seg = 0;
+    double kd = 0.0;
+    for (int64_t k = 0;; ++k, kd += 1.0) {
+      const double kp = kd * p;
+      const double base = floor(kp);
+      if (base > (double)kmax_base) break;
+      int b = (int)base;
+      if constexpr (SEG) {
       int64_t delta, knext;
       if (!seg_event(S, mb, b, k, p, seg, delta, knext)) {
         k = knext - 1;
@@ -183,40 +224,53 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
         continue;
       }
       b += (int)delta;
-    }
-    const double w = kp - base;
-    const double u = 1.0 - w;
-    const int idx = lane + b;
-    double2 dv[JG];
-    double l[JG];
+      }
+      const int idx = lane + b;  // may be negative (the window's packed offset)
+      double2 dv[JG];
+      double l[JG];
 #pragma unroll
-    for (int g = 0; g < JG; ++g) {
-      if constexpr (SEG) {  // idx may be negative there (the window's packed offset)
+      for (int g = 0; g < JG; ++g) {
+        if constexpr (SEG) {
         dv[g] = dvr[g][idx];
         l[g] = lpr[g][idx];
-      } else {
+        } else {
+        dv[g] = row_at(dvr[g], idx);
+        l[g] = row_at(lpr[g], idx);
+        }
+      }
+      event1(dv, l, kp - base);
+    }
+  } else {
+    // software pipelined over two register sets: the slots of event k + 1 are
+    // loaded while event k is combined (past the last event the current
+    // event's slots are loaded again, so every load stays inside the grid)
+    auto load1 = [&](int b, double2 (&dv)[JG], double (&l)[JG]) {
+      const int idx = lane + b;
+#pragma unroll
+      for (int g = 0; g < JG; ++g) {
         dv[g] = row_at(dvr[g], idx);
         l[g] = row_at(lpr[g], idx);
       }
-    }
-#pragma unroll
-    for (int g = 0; g < JG; ++g) {
-      double d = dv[g].x, v = dv[g].y, ll = l[g];
-      if (w != 0.0) {
-        d = u * d + w * from_next_lane(d);
-        v = u * v + w * from_next_lane(v);
-        ll = u * ll + w * from_next_lane(ll);
-      }
-      if (v == v && j0 + g < n_d) {
-        const double iv = rcp_nr(v);
-        const double dw = d * iv;
-        s_w[g] = s_w[g] + iv;
-        s_wd[g] = s_wd[g] + dw;
-        s_dd[g] = s_dd[g] + d * dw;
-        s_ll[g] = s_ll[g] + ll;
-        vmin = fmin(vmin, v);
-        ++cnt[g];
-      }
+    };
+    const double kmax = (double)kmax_base;  // >= 0: event 0 (slot m) always exists
+    double2 dva[JG], dvb[JG];
+    double la[JG], lb[JG];
+    double kda = 0.0, kpa = 0.0, basea = 0.0;
+    load1(0, dva, la);
+    for (;;) {
+      const double kdb = kda + 1.0, kpb = kdb * p, baseb = floor(kpb);
+      const bool hasb = baseb <= kmax;
+      load1(hasb ? (int)baseb : (int)basea, dvb, lb);
+      event1(dva, la, kpa - basea);
+      if (!hasb) break;
+      kda = kdb + 1.0;
+      kpa = kda * p;
+      const double basen = floor(kpa);
+      const bool hasa = basen <= kmax;
+      load1(hasa ? (int)basen : (int)baseb, dva, la);
+      event1(dvb, lb, kpb - baseb);
+      if (!hasa) break;
+      basea = basen;
     }
   }
   double s2[JG], dc[JG], prod[JG], chi[JG];
@@ -229,7 +283,7 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
     prod[g] = 1.0;
     chi[g] = 0.0;
     bool mine = false;
-    if (j0 + g < n_d && cnt[g] > 0 && m < nph && lane < WPH) {
+    if (j0 + g < n_d && s_w[g] > 0.0 && m < nph && lane < WPH) {
       const double chi_lb = fmax(s_dd[g] - dc[g] * dc[g] * s_w[g], 0.0) / (1.0 + s2[g] / vmin);
       const double ub = s_ll[g] + (sign > 0.0 ? 0.5 : 0.0) - 0.5 * chi_lb;
       const double margin = 1e-9 * (1.0 + fabs(s_ll[g]) + s_dd[g]);
@@ -239,15 +293,35 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
     any_need = any_need || need[g];
   }
   if (!any_need) return;
+  // one event of pass 2 for the durations that need it
+  auto event2 = [&](const double2 (&dv)[JG], double w) {
+    const double u = 1.0 - w;
+#pragma unroll
+    for (int g = 0; g < JG; ++g) {
+      if (!need[g]) continue;
+      double d = dv[g].x, v = dv[g].y;
+      if (w != 0.0) {
+        d = interp(u, w, d, from_next_lane(d));
+        v = interp(u, w, v, from_next_lane(v));
+      }
+      if (v == v && s_w[g] > 0.0) {
+        const double r = rcp_nr(v + s2[g]);  // 1 / (var_k + sigma^2)
+        prod[g] = prod[g] * (v * r);
+        const double dd = d - dc[g];
+        chi[g] = fma(dd * dd, r, chi[g]);  // (d_k - d)^2 / (var_k + sigma^2)
+      }
+    }
+  };
   // pass 2
-  seg = 0;
-  kd = 0.0;
-  for (int64_t k = 0;; ++k, kd += 1.0) {
-    const double kp = kd * p;
-    const double base = floor(kp);
-    if (base > (double)kmax_base) break;
-    int b = (int)base;
-    if constexpr (SEG) {
+  if constexpr (SEG || NU_FOLD_PIPE < 2) {
+    int seg = 0;
+    double kd = 0.0;
+    for (int64_t k = 0;; ++k, kd += 1.0) {
+      const double kp = kd * p;
+      const double base = floor(kp);
+      if (base > (double)kmax_base) break;
+      int b = (int)base;
+      if constexpr (SEG) {
       int64_t delta, knext;
       if (!seg_event(S, mb, b, k, p, seg, delta, knext)) {
         k = knext - 1;
@@ -255,36 +329,47 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
         continue;
       }
       b += (int)delta;
+      }
+      const int idx = lane + b;
+      double2 dv[JG];
+#pragma unroll
+      for (int g = 0; g < JG; ++g)
+        if (need[g]) dv[g] = SEG ? dvr[g][idx] : row_at(dvr[g], idx);
+      event2(dv, kp - base);
     }
-    const double w = kp - base;
-    const double u = 1.0 - w;
-    const int idx = lane + b;
-    double2 dv[JG];
+  } else {
+    // pipelined as pass 1; every duration's slots are loaded (no branch
+    // around a load), only the needed ones are combined
+    auto load2 = [&](int b, double2 (&dv)[JG]) {
+      const int idx = lane + b;
 #pragma unroll
-    for (int g = 0; g < JG; ++g)
-      if (need[g]) dv[g] = SEG ? dvr[g][idx] : row_at(dvr[g], idx);
-#pragma unroll
-    for (int g = 0; g < JG; ++g) {
-      if (!need[g]) continue;
-      double d = dv[g].x, v = dv[g].y;
-      if (w != 0.0) {
-        d = u * d + w * from_next_lane(d);
-        v = u * v + w * from_next_lane(v);
-      }
-      if (v == v && cnt[g] > 0) {
-        const double iv = rcp_nr(v);
-        const double x1 = fma(s2[g], iv, 1.0);  // 1 + sigma^2 / var_k
-        prod[g] = prod[g] * x1;
-        const double dd = d - dc[g];
-        chi[g] = fma(dd * dd * iv, rcp_nr(x1), chi[g]);  // (d_k - d)^2 / (var_k + sigma^2)
-      }
+      for (int g = 0; g < JG; ++g) dv[g] = row_at(dvr[g], idx);
+    };
+    const double kmax = (double)kmax_base;
+    double2 dva[JG], dvb[JG];
+    double kda = 0.0, kpa = 0.0, basea = 0.0;
+    load2(0, dva);
+    for (;;) {
+      const double kdb = kda + 1.0, kpb = kdb * p, baseb = floor(kpb);
+      const bool hasb = baseb <= kmax;
+      load2(hasb ? (int)baseb : (int)basea, dvb);
+      event2(dva, kpa - basea);
+      if (!hasb) break;
+      kda = kdb + 1.0;
+      kpa = kda * p;
+      const double basen = floor(kpa);
+      const bool hasa = basen <= kmax;
+      load2(hasa ? (int)basen : (int)baseb, dva);
+      event2(dvb, kpb - baseb);
+      if (!hasa) break;
+      basea = basen;
     }
   }
 #pragma unroll
   for (int g = 0; g < JG; ++g) {
     const int j = j0 + g;
-    if (need[g] && j < n_d && cnt[g] > 0 && m < nph && lane < WPH) {
-      const double corr = -sign * log(prod[g]) + chi[g];
+    if (need[g] && j < n_d && s_w[g] > 0.0 && m < nph && lane < WPH) {
+      const double corr = sign * log(prod[g]) + chi[g];
       const double lnp = s_ll[g] - 0.5 * corr;
       Best cand{lnp, m * (int64_t)n_d + j, dc[g], s2[g]};
       if (lnp == lnp && lnp > -INFINITY && beats(cand, best)) best = cand;
@@ -356,7 +441,7 @@ __device__ __forceinline__ void fold_period_block(const double2* __restrict__ DV
 }
 
 template <int JG, bool SEG>
-__global__ __launch_bounds__(256, 3) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
+__global__ __launch_bounds__(256, NU_FOLD_WAVES) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
                                                    int n_d, int64_t n_t, int64_t ld, const Segs S, double dt,
                                                    const double* __restrict__ periods, double sign,
                                                    double* __restrict__ q_snr, int64_t* __restrict__ best_phase,
@@ -595,7 +680,7 @@ __global__ __launch_bounds__(256) void batch_fold_pack_kernel(const CurveJob* __
 }
 
 template <int JG>
-__global__ __launch_bounds__(256, 3) void batch_fold_kernel(const CurveJob* __restrict__ jobs, int n_d,
+__global__ __launch_bounds__(256, NU_FOLD_WAVES) void batch_fold_kernel(const CurveJob* __restrict__ jobs, int n_d,
                                                          const double* __restrict__ periods, double sign) {
   const CurveJob& J = jobs[blockIdx.y];
   const int64_t ld = J.n_epochs + FPAD;
