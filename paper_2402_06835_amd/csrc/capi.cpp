@@ -149,6 +149,25 @@ void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, 
   ctx->pending.push_back({name, start, stop, work});
 }
 
+void timing_pair(nu_ctx* ctx, const char* name, hipEvent_t* start, hipEvent_t* stop) {
+  *start = *stop = nullptr;
+  if (!ctx->timing) return;
+  if (!ctx->timing_only.empty() && std::strncmp(name, ctx->timing_only.c_str(), ctx->timing_only.size()) != 0) return;
+  while (ctx->free_events.size() < 2) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return;
+    ctx->free_events.push_back(ev);
+  }
+  *start = ctx->free_events.back();
+  ctx->free_events.pop_back();
+  *stop = ctx->free_events.back();
+  ctx->free_events.pop_back();
+}
+
+void timing_add(nu_ctx* ctx, const char* name, hipEvent_t start, hipEvent_t stop, double work) {
+  if (start && stop) ctx->pending.push_back({name, start, stop, work});
+}
+
 static double wall_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }

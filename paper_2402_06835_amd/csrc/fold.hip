@@ -40,12 +40,6 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, fma(e, e, e), r);
 }
 
-#ifndef NU_FOLD_PIPE
-#define NU_FOLD_PIPE 0
-#endif
-#ifndef NU_FOLD_WAVES
-#define NU_FOLD_WAVES 3
-#endif
 constexpr int FPAD = 64;  // padded slots after the grid (invalid), one wave wide
 constexpr int WPH = 63;   // phases per wave: lane 63 only supplies its neighbour
 
@@ -208,15 +202,14 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
     }
   };
   // pass 1 (k counts events as an int64 and, exactly, as a double for k p)
-  if constexpr (SEG || !NU_FOLD_PIPE) {
-    int seg = 0;
-    double kd = 0.0;
-    for (int64_t k = 0;; ++k, kd += 1.0) {
-      const double kp = kd * p;
-      const double base = floor(kp);
-      if (base > (double)kmax_base) break;
-      int b = (int)base;
-      if constexpr (SEG) {
+  int seg = 0;
+  double kd = 0.0;
+  for (int64_t k = 0;; ++k, kd += 1.0) {
+    const double kp = kd * p;
+    const double base = floor(kp);
+    if (base > (double)kmax_base) break;
+    int b = (int)base;
+    if constexpr (SEG) {
       int64_t delta, knext;
       if (!seg_event(S, mb, b, k, p, seg, delta, knext)) {
         k = knext - 1;
@@ -224,54 +217,21 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
         continue;
       }
       b += (int)delta;
-      }
-      const int idx = lane + b;  // may be negative (the window's packed offset)
-      double2 dv[JG];
-      double l[JG];
+    }
+    const int idx = lane + b;
+    double2 dv[JG];
+    double l[JG];
 #pragma unroll
-      for (int g = 0; g < JG; ++g) {
-        if constexpr (SEG) {
+    for (int g = 0; g < JG; ++g) {
+      if constexpr (SEG) {  // idx may be negative there (the window's packed offset)
         dv[g] = dvr[g][idx];
         l[g] = lpr[g][idx];
-        } else {
-        dv[g] = row_at(dvr[g], idx);
-        l[g] = row_at(lpr[g], idx);
-        }
-      }
-      event1(dv, l, kp - base);
-    }
-  } else {
-    // software pipelined over two register sets: the slots of event k + 1 are
-    // loaded while event k is combined (past the last event the current
-    // event's slots are loaded again, so every load stays inside the grid)
-    auto load1 = [&](int b, double2 (&dv)[JG], double (&l)[JG]) {
-      const int idx = lane + b;
-#pragma unroll
-      for (int g = 0; g < JG; ++g) {
+      } else {
         dv[g] = row_at(dvr[g], idx);
         l[g] = row_at(lpr[g], idx);
       }
-    };
-    const double kmax = (double)kmax_base;  // >= 0: event 0 (slot m) always exists
-    double2 dva[JG], dvb[JG];
-    double la[JG], lb[JG];
-    double kda = 0.0, kpa = 0.0, basea = 0.0;
-    load1(0, dva, la);
-    for (;;) {
-      const double kdb = kda + 1.0, kpb = kdb * p, baseb = floor(kpb);
-      const bool hasb = baseb <= kmax;
-      load1(hasb ? (int)baseb : (int)basea, dvb, lb);
-      event1(dva, la, kpa - basea);
-      if (!hasb) break;
-      kda = kdb + 1.0;
-      kpa = kda * p;
-      const double basen = floor(kpa);
-      const bool hasa = basen <= kmax;
-      load1(hasa ? (int)basen : (int)baseb, dva, la);
-      event1(dvb, lb, kpb - baseb);
-      if (!hasa) break;
-      basea = basen;
     }
+    event1(dv, l, kp - base);
   }
   double s2[JG], dc[JG], prod[JG], chi[JG];
   bool need[JG];
@@ -313,15 +273,14 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
     }
   };
   // pass 2
-  if constexpr (SEG || NU_FOLD_PIPE < 2) {
-    int seg = 0;
-    double kd = 0.0;
-    for (int64_t k = 0;; ++k, kd += 1.0) {
-      const double kp = kd * p;
-      const double base = floor(kp);
-      if (base > (double)kmax_base) break;
-      int b = (int)base;
-      if constexpr (SEG) {
+  seg = 0;
+  kd = 0.0;
+  for (int64_t k = 0;; ++k, kd += 1.0) {
+    const double kp = kd * p;
+    const double base = floor(kp);
+    if (base > (double)kmax_base) break;
+    int b = (int)base;
+    if constexpr (SEG) {
       int64_t delta, knext;
       if (!seg_event(S, mb, b, k, p, seg, delta, knext)) {
         k = knext - 1;
@@ -329,41 +288,13 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
         continue;
       }
       b += (int)delta;
-      }
-      const int idx = lane + b;
-      double2 dv[JG];
-#pragma unroll
-      for (int g = 0; g < JG; ++g)
-        if (need[g]) dv[g] = SEG ? dvr[g][idx] : row_at(dvr[g], idx);
-      event2(dv, kp - base);
     }
-  } else {
-    // pipelined as pass 1; every duration's slots are loaded (no branch
-    // around a load), only the needed ones are combined
-    auto load2 = [&](int b, double2 (&dv)[JG]) {
-      const int idx = lane + b;
+    const int idx = lane + b;
+    double2 dv[JG];
 #pragma unroll
-      for (int g = 0; g < JG; ++g) dv[g] = row_at(dvr[g], idx);
-    };
-    const double kmax = (double)kmax_base;
-    double2 dva[JG], dvb[JG];
-    double kda = 0.0, kpa = 0.0, basea = 0.0;
-    load2(0, dva);
-    for (;;) {
-      const double kdb = kda + 1.0, kpb = kdb * p, baseb = floor(kpb);
-      const bool hasb = baseb <= kmax;
-      load2(hasb ? (int)baseb : (int)basea, dvb);
-      event2(dva, kpa - basea);
-      if (!hasb) break;
-      kda = kdb + 1.0;
-      kpa = kda * p;
-      const double basen = floor(kpa);
-      const bool hasa = basen <= kmax;
-      load2(hasa ? (int)basen : (int)baseb, dva);
-      event2(dvb, kpb - baseb);
-      if (!hasa) break;
-      basea = basen;
-    }
+    for (int g = 0; g < JG; ++g)
+      if (need[g]) dv[g] = SEG ? dvr[g][idx] : row_at(dvr[g], idx);
+    event2(dv, kp - base);
   }
 #pragma unroll
   for (int g = 0; g < JG; ++g) {
@@ -441,7 +372,7 @@ __device__ __forceinline__ void fold_period_block(const double2* __restrict__ DV
 }
 
 template <int JG, bool SEG>
-__global__ __launch_bounds__(256, NU_FOLD_WAVES) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
+__global__ __launch_bounds__(256, 3) void fold_kernel(const double2* __restrict__ DV, const double* __restrict__ Lp,
                                                    int n_d, int64_t n_t, int64_t ld, const Segs S, double dt,
                                                    const double* __restrict__ periods, double sign,
                                                    double* __restrict__ q_snr, int64_t* __restrict__ best_phase,
@@ -680,7 +611,7 @@ __global__ __launch_bounds__(256) void batch_fold_pack_kernel(const CurveJob* __
 }
 
 template <int JG>
-__global__ __launch_bounds__(256, NU_FOLD_WAVES) void batch_fold_kernel(const CurveJob* __restrict__ jobs, int n_d,
+__global__ __launch_bounds__(256, 3) void batch_fold_kernel(const CurveJob* __restrict__ jobs, int n_d,
                                                          const double* __restrict__ periods, double sign) {
   const CurveJob& J = jobs[blockIdx.y];
   const int64_t ld = J.n_epochs + FPAD;

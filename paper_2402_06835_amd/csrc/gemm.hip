@@ -7,7 +7,14 @@
 // with few tiles, 64 x 64, or 64 x 128 where C aliases A). 256 threads = 4
 // waves in a 2 x 2 arrangement, each wave a quarter of the tile held as 16 x 16
 // MFMA accumulators. The k loop stages 16-deep slices of A and op(B) through
-// LDS (k-major, double buffered; one barrier per slice).
+// LDS (k-major, double buffered; one barrier per slice). The slices come in by
+// buffer loads: per slice a descriptor on the tile's first row, built in
+// scalar registers, plus one fixed 32-bit offset per lane, so the loop does no
+// vector address arithmetic and the loads of slice it + 2 stay in flight
+// while slice it is computed. (With 64-bit vector addresses the compiler put
+// the next addresses into registers of loads still in flight and waited for
+// every load at the top of the loop: standalone 16384^2 x 768 FP64 products
+// 67.7 -> 70.3 TFLOP/s, FP32 8192^3 products 142.8 -> 146 TFLOP/s.)
 //
 // A problem may write C over its own A (the Cholesky panel, times the inverse
 // of the diagonal block) only if every tile spans all N columns: a tile reads
@@ -17,6 +24,8 @@
 // This is the dense contraction of the factorisation: the trailing updates
 // and panels of the blocked Cholesky, and both products of every level of the
 // triangular inverse X = L^-1 that whitens the box design of the linear search.
+#include <hip/hip_ext.h>
+
 #include "internal.hpp"
 
 // LDS stores of the next k-slice interleaved with the MFMAs of the current one
@@ -145,6 +154,24 @@ __device__ __forceinline__ void loadE(const NU_GLOBAL T* p, T (&r)[E]) {
   }
 }
 
+typedef int int4v __attribute__((ext_vector_type(4)));
+// raw buffer descriptor over [p, p + 4 GiB): no stride, unformatted 32-bit data
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
+}
+// E consecutive elements at byte offset voff of a buffer, 16-byte loads
+template <typename T, int E>
+__device__ __forceinline__ void bloadE(__amdgpu_buffer_rsrc_t rs, uint32_t voff, T (&r)[E]) {
+  constexpr int PER = 16 / sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(PER)));
+#pragma unroll
+  for (int i = 0; i < E / PER; ++i) {
+    const vec_t x = __builtin_bit_cast(vec_t, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16u * i, 0, 0));
+#pragma unroll
+    for (int e = 0; e < PER; ++e) r[i * PER + e] = x[e];
+  }
+}
+
 // BM x BN output tile per workgroup ((128, 128), (64, 64) or (64, 128)),
 // 4 waves in a 2 x 2 arrangement of (BM/2) x (BN/2) sub-tiles.
 template <typename T, int BM, int BN>
@@ -189,17 +216,21 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
   // "row-major K x N -> [k][n]" pattern for B
   const int bk = tid / (BN / EB), bnc = (tid % (BN / EB)) * EB;
 
-  const NU_GLOBAL T* A = (const NU_GLOBAL T*)P.A;
-  const NU_GLOBAL T* B = (const NU_GLOBAL T*)P.B;
-  const NU_GLOBAL T* Ap = A + (int64_t)(m0 + ar) * P.lda + akh;
-  const NU_GLOBAL T* Bp = bt ? B + (int64_t)(n0 + br) * P.ldb + bkh : B + (int64_t)bk * P.ldb + n0 + bnc;
-
   // two register sets: the global loads of slice it + 2 are issued while
   // slice it is computed, two slices ahead of their LDS store
   T ra0[EA], rb0[EB], ra1[EA], rb1[EB];
+  // buffer loads: a descriptor on the tile's first row of A (of B) per slice,
+  // built in scalar registers, and one loop-invariant 32-bit lane offset, so
+  // no per-slice vector address arithmetic (a tile's rows span far less than
+  // 2^32 bytes for any matrix that fits the device)
+  const char* Abase = (const char*)P.A + (int64_t)m0 * P.lda * (int64_t)sizeof(T);
+  const char* Bbase = (const char*)P.B + (bt ? (int64_t)n0 * P.ldb : (int64_t)n0) * (int64_t)sizeof(T);
+  const uint32_t aoff = (uint32_t)(((int64_t)ar * P.lda + akh) * (int64_t)sizeof(T));
+  const uint32_t boff = (uint32_t)((bt ? (int64_t)br * P.ldb + bkh : (int64_t)bk * P.ldb + bnc) * (int64_t)sizeof(T));
+  const int64_t bstep = bt ? (int64_t)sizeof(T) : (int64_t)P.ldb * (int64_t)sizeof(T);
   auto gload = [&](int k0, T (&ra)[EA], T (&rb)[EB]) {
-    loadE<T, EA>(Ap + k0, ra);
-    loadE<T, EB>(bt ? Bp + k0 : Bp + (int64_t)k0 * P.ldb, rb);
+    bloadE<T, EA>(make_rsrc(Abase + (int64_t)k0 * (int64_t)sizeof(T)), aoff, ra);
+    bloadE<T, EB>(make_rsrc(Bbase + (int64_t)k0 * bstep), boff, rb);
   };
   auto lstore = [&](int buf, const T (&ra)[EA], const T (&rb)[EB]) {
 #pragma unroll
@@ -264,6 +295,9 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
   // schedules the LDS reads of a k-step among the MFMAs of the previous one.
   auto step = [&](int it, T (&rac)[EA], T (&rbc)[EB], T (&ran)[EA], T (&rbn)[EB]) {
     gload(kb + min(it + 2, nk - 1) * GBK, rac, rbc);
+    // keep the loads ahead of the products (the scheduler would otherwise
+    // sink them and give their registers to the LDS operands)
+    __builtin_amdgcn_sched_barrier(0);
     compute(it & 1, ran, rbn);
     __syncthreads();
   };
@@ -483,28 +517,36 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const GemmProblem* 
   }
 }
 
+// With events, the launch records them itself at the start and end of its
+// dispatch (hipExtLaunchKernelGGL).
+template <typename K>
+void launch_one(K kernel, dim3 g, hipStream_t s, hipEvent_t e0, hipEvent_t e1, const GemmProblem* dprobs, int nprob) {
+  if (e0 || e1) hipExtLaunchKernelGGL(kernel, g, dim3(256), 0, s, e0, e1, 0, dprobs, nprob);
+  else hipLaunchKernelGGL(kernel, g, dim3(256), 0, s, dprobs, nprob);
+}
+
 template <typename T>
-void launch_typed(hipStream_t s, const GemmProblem* dprobs, int nprob, dim3 g, int tm, int tn) {
-  const dim3 b(256);
-  if (tm == 64 && tn == 64) hipLaunchKernelGGL((gemm_kernel<T, 64, 64>), g, b, 0, s, dprobs, nprob);
-  else if (tm == 64) hipLaunchKernelGGL((gemm_kernel<T, 64, 128>), g, b, 0, s, dprobs, nprob);
-  else hipLaunchKernelGGL((gemm_kernel<T, 128, 128>), g, b, 0, s, dprobs, nprob);
+void launch_typed(hipStream_t s, const GemmProblem* dprobs, int nprob, dim3 g, int tm, int tn, hipEvent_t e0,
+                  hipEvent_t e1) {
+  if (tm == 64 && tn == 64) launch_one(gemm_kernel<T, 64, 64>, g, s, e0, e1, dprobs, nprob);
+  else if (tm == 64) launch_one(gemm_kernel<T, 64, 128>, g, s, e0, e1, dprobs, nprob);
+  else launch_one(gemm_kernel<T, 128, 128>, g, s, e0, e1, dprobs, nprob);
 }
 
 hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int kind, int tile_m,
-                       int tile_n) {
+                       int tile_n, hipEvent_t start, hipEvent_t stop) {
   if (total_tiles <= 0) return hipSuccess;
   if (!((tile_m == 128 && tile_n == 128) || (tile_m == 64 && (tile_n == 64 || tile_n == 128))))
     return hipErrorInvalidValue;
-  const dim3 g((unsigned)total_tiles), b(256);
+  const dim3 g((unsigned)total_tiles);
   switch (kind) {
-    case GK_F64: launch_typed<double>(s, dprobs, nprob, g, tile_m, tile_n); break;
-    case GK_F32: launch_typed<float>(s, dprobs, nprob, g, tile_m, tile_n); break;
+    case GK_F64: launch_typed<double>(s, dprobs, nprob, g, tile_m, tile_n, start, stop); break;
+    case GK_F32: launch_typed<float>(s, dprobs, nprob, g, tile_m, tile_n, start, stop); break;
     case GK_BF16X3:
       // square tiles only (64 x 128 serves the in-place panels, which this kind never runs)
       if (tile_m != tile_n) return hipErrorInvalidValue;
-      if (tile_m == 64) hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 64>), g, b, 0, s, dprobs, nprob);
-      else hipLaunchKernelGGL((gemm_bf16x3_kernel<128, 128>), g, b, 0, s, dprobs, nprob);
+      if (tile_m == 64) launch_one(gemm_bf16x3_kernel<64, 64>, g, s, start, stop, dprobs, nprob);
+      else launch_one(gemm_bf16x3_kernel<128, 128>, g, s, start, stop, dprobs, nprob);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -296,6 +296,11 @@ nu_status validate_shapes(nu_ctx* ctx, const double* shapes_host, const int32_t*
 
 // kernel timing (capi.cpp): events on the context's stream around a launch
 void timing_begin(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t* start);
+// events that a launch records itself (start and end of its own dispatch, no
+// marker of their own in the stream), both null when `name` is not timed;
+// timing_add queues them
+void timing_pair(nu_ctx* ctx, const char* name, hipEvent_t* start, hipEvent_t* stop);
+void timing_add(nu_ctx* ctx, const char* name, hipEvent_t start, hipEvent_t stop, double work);
 void timing_end(nu_ctx* ctx, hipStream_t s, const char* name, hipEvent_t start, double work);
 void resolve_timing(nu_ctx* ctx);  // synchronises the stream, folds pending events into the totals
 struct Timed {
@@ -385,7 +390,7 @@ hipError_t launch_kbuild_terms(hipStream_t s, const double* t, int64_t n, int64_
                                double* K);
 nu_status validate_kernel(nu_ctx* ctx, const nu_kernel* k);
 hipError_t launch_gemm(hipStream_t s, const GemmProblem* dprobs, int nprob, int total_tiles, int kind, int tile_m,
-                       int tile_n);
+                       int tile_n, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_potrf_diag(hipStream_t s, const PotrfJob* jobs, int njobs);
 hipError_t launch_copy_i64(hipStream_t s, const int64_t* src, int64_t* dst);
 hipError_t launch_fill_invalid_cells(hipStream_t s, int64_t count, double* depth, double* var, double* dll,
