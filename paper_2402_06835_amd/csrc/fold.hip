@@ -238,16 +238,18 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
   bool any_need = false;
 #pragma unroll
   for (int g = 0; g < JG; ++g) {
-    s2[g] = 1.0 / s_w[g];
+    s2[g] = rcp_nr(s_w[g]);  // used only where s_w > 0
     dc[g] = s2[g] * s_wd[g];
     prod[g] = 1.0;
     chi[g] = 0.0;
     bool mine = false;
     if (j0 + g < n_d && s_w[g] > 0.0 && m < nph && lane < WPH) {
-      const double chi_lb = fmax(s_dd[g] - dc[g] * dc[g] * s_w[g], 0.0) / (1.0 + s2[g] / vmin);
-      const double ub = s_ll[g] + (sign > 0.0 ? 0.5 : 0.0) - 0.5 * chi_lb;
+      // ub + margin < thr with chi_lb = chi_ub v_min / (v_min + sigma^2), multiplied
+      // out by v_min + sigma^2 > 0 (no division)
+      const double chi_ub = fmax(s_dd[g] - dc[g] * dc[g] * s_w[g], 0.0);
       const double margin = 1e-9 * (1.0 + fabs(s_ll[g]) + s_dd[g]);
-      mine = !(ub + margin < thr);  // NaN: evaluated
+      const double x = s_ll[g] + (sign > 0.0 ? 0.5 : 0.0) + margin - thr;
+      mine = !(x * (vmin + s2[g]) < 0.5 * chi_ub * vmin);  // NaN: evaluated
     }
     need[g] = __ballot(mine) != 0;
     any_need = any_need || need[g];
@@ -300,10 +302,15 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
   for (int g = 0; g < JG; ++g) {
     const int j = j0 + g;
     if (need[g] && j < n_d && s_w[g] > 0.0 && m < nph && lane < WPH) {
-      const double corr = sign * log(prod[g]) + chi[g];
-      const double lnp = s_ll[g] - 0.5 * corr;
-      Best cand{lnp, m * (int64_t)n_d + j, dc[g], s2[g]};
-      if (lnp == lnp && lnp > -INFINITY && beats(cand, best)) best = cand;
+      // ln prod lies in [-1, 0): a cell whose bound stays below the lane's best
+      // (with a margin for rounding) cannot win, and skips the logarithm
+      const double ubx = s_ll[g] - 0.5 * chi[g] + (sign > 0.0 ? 0.5 : 0.0);
+      if (!(ubx + 1e-9 * (1.0 + fabs(s_ll[g]) + chi[g]) < best.val)) {
+        const double corr = sign * log(prod[g]) + chi[g];
+        const double lnp = s_ll[g] - 0.5 * corr;
+        Best cand{lnp, m * (int64_t)n_d + j, dc[g], s2[g]};
+        if (lnp == lnp && lnp > -INFINITY && beats(cand, best)) best = cand;
+      }
     }
   }
 }
@@ -337,11 +344,16 @@ __device__ __forceinline__ void fold_period_block(const double2* __restrict__ DV
       for (int j0 = 0; j0 < n_d; j0 += JG) {
         // read without synchronisation: a stale value only prunes less
         const double thr = fmax(fmax(wb[0], wb[1]), fmax(wb[2], wb[3]));
+        const double before = best.val;
         fold_cells<JG, SEG>(DV, Lp, n_d, n_t, ld, S, j0, mb, lane, nph, p, sign, thr, best);
-        double v = best.flat >= 0 ? best.val : -INFINITY;
+        // the wave's best, published for the other waves' skipping, only when
+        // some lane found a better cell in this call
+        if (__ballot(best.val != before) != 0) {
+          double v = best.flat >= 0 ? best.val : -INFINITY;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-        if (lane == 0 && v > wb[wave]) wb[wave] = v;
+          for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+          if (lane == 0 && v > wb[wave]) wb[wave] = v;
+        }
       }
   }
   red[tid] = best;
