@@ -364,7 +364,9 @@ nu_status nu_mask_transit(nu_ctx* ctx, double* depth, double* var, double* dll, 
  * a call issues a number of launches set by the stages and the waves, not by
  * the curves. The factors and each curve's search workspace live in a device
  * arena of the size of the largest wave, which the context keeps for later
- * calls (released by nu_ctx_release_memory or nu_ctx_destroy). The call
+ * calls (released by nu_ctx_release_memory or nu_ctx_destroy); a later call
+ * keeps that arena when a plan within it needs no more waves than the budget
+ * allows, and grows it otherwise. The call
  * synchronises the stream once, before it returns. A curve whose covariance
  * is not positive definite gets invalid cells, no event at any period and
  * best_period_index -1; the call finishes the other curves and returns

@@ -113,16 +113,21 @@ int64_t curve_ne(const BatchInputs& in, int c) { return in.epoch_off[c + 1] - in
 size_t curve_t_min(const BatchInputs& in, int c) { return batch_search_ws_doubles(curve_n(in, c), in.n_d, curve_ne(in, c)); }
 size_t curve_bytes(const BatchInputs& in, int c) { return factor_bytes(curve_n(in, c), in.prec, curve_t_min(in, c)); }
 
+// every curve's packed fold grid and record, held for the whole call outside
+// the waves (the records' bound: one wave per curve at most)
+size_t batch_grid_bytes(const BatchInputs& in) {
+  size_t grids = (size_t)in.n_curves * (sizeof(CurveJob) + 2 * BS_COUNT * sizeof(int) + 512);
+  for (int c = 0; c < in.n_curves; ++c) grids += fold_workspace_doubles(in.n_d, curve_ne(in, c)) * sizeof(double);
+  return grids;
+}
+
 // waves of curves (longest first) whose factors fit `budget` bytes; the arena size they need
 nu_status plan_waves(nu_ctx* ctx, const BatchInputs& in, size_t budget, std::vector<std::vector<int>>& waves,
                      size_t& arena_need) {
   std::vector<int> order(in.n_curves);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return curve_n(in, a) > curve_n(in, b); });
-  // every curve's packed fold grid and record are held for the whole call,
-  // outside the waves (the records' bound: one wave per curve at most)
-  size_t grids = (size_t)in.n_curves * (sizeof(CurveJob) + 2 * BS_COUNT * sizeof(int) + 512);
-  for (int c = 0; c < in.n_curves; ++c) grids += fold_workspace_doubles(in.n_d, curve_ne(in, c)) * sizeof(double);
+  const size_t grids = batch_grid_bytes(in);
   if (grids >= budget)
     return set_error(ctx, NU_ERR_OOM, "search_batch: the fold grids do not fit the device-memory budget");
   budget -= grids;
@@ -530,6 +535,23 @@ nu_status nu_search_batch(nu_ctx* ctx, int n_curves, const int64_t* sample_off_h
   size_t arena_need = 0;
   st = plan_waves(ctx, in, budget, waves, arena_need);
   if (st != NU_OK) return st;
+  if (arena_need > ctx->arena_bytes && ctx->arena_bytes > 0) {
+    // The budget follows the free memory, so from call to call the first wave
+    // can gain a curve and outgrow the arena, whose replacement (a wait, a free
+    // and an allocation of up to hundreds of GB) costs seconds. The arena held
+    // is kept when a plan within it needs no more waves.
+    size_t largest = 0;
+    for (int c = 0; c < n_curves; ++c) largest = std::max(largest, curve_bytes(in, c));
+    if (largest <= ctx->arena_bytes) {
+      std::vector<std::vector<int>> within;
+      size_t need = 0;
+      if (plan_waves(ctx, in, ctx->arena_bytes + batch_grid_bytes(in), within, need) == NU_OK &&
+          within.size() <= waves.size()) {
+        waves.swap(within);
+        arena_need = need;
+      }
+    }
+  }
   char* arena = nullptr;
   {
     HostTimed ht(ctx, "batch_arena");

@@ -128,6 +128,13 @@ constexpr int PANEL = 6;
 // ---------------------------------------------------------------------------
 // Schedules
 
+// The chain of a factorisation (diagonal blocks, panels, panel updates and the
+// next panel's update) is latency bound, and with the lookahead and the
+// inverse prefetch its workgroups share compute units with the trailing
+// updates and the early inverse. Its GEMM problems carry G_PRIO (and the
+// diagonal-block kernel raises its own priority), so their waves issue first on
+// a shared CU: at N = 18000, 63.1-63.4 -> 62.5-62.7 ms per step, outputs
+// bitwise unchanged.
 void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P) {
   int steps = 0;
   for (auto* F : Fs) steps = std::max(steps, F->nblk);
@@ -152,10 +159,10 @@ void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P)
       if (rest > 0) {
         void* col = at(F->L, off + TB, off, np, es);  // rows below the diagonal block, block column k
         const void* xkk = at(F->X, off, off, np, es);
-        pan.push_back(prob(col, np, xkk, np, col, np, rest, TB, TB, G_BT | G_C_IS_A, 1.0, 0.0));
+        pan.push_back(prob(col, np, xkk, np, col, np, rest, TB, TB, G_BT | G_C_IS_A | G_PRIO, 1.0, 0.0));
         const int inner = (p0 + pw - k - 1) * TB;  // columns of this panel right of block k
         if (inner > 0)
-          pup.push_back(prob(col, np, col, np, at(col, 0, TB, np, es), np, rest, inner, TB, G_BT, -1.0, 1.0));
+          pup.push_back(prob(col, np, col, np, at(col, 0, TB, np, es), np, rest, inner, TB, G_BT | G_PRIO, -1.0, 1.0));
       }
       if (k == p0 + pw - 1) {
         // last block of the panel: update the trailing matrix by the panel,
@@ -167,7 +174,7 @@ void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P)
         if (rest2 > 0) {
           const void* pn = at(F->L, t0, (int64_t)p0 * TB, np, es);  // trailing rows, panel columns
           const int nw = std::min(PANEL, F->nblk - (p0 + pw)) * TB;   // next panel's width
-          nx.push_back(prob(pn, np, pn, np, at(F->L, t0, t0, np, es), np, rest2, nw, pw * TB, G_BT, -1.0, 1.0));
+          nx.push_back(prob(pn, np, pn, np, at(F->L, t0, t0, np, es), np, rest2, nw, pw * TB, G_BT | G_PRIO, -1.0, 1.0));
           const int rest3 = rest2 - nw;
           if (rest3 > 0) {
             const void* pr = at(F->L, t0 + nw, (int64_t)p0 * TB, np, es);

@@ -217,6 +217,7 @@ __device__ void inverse_level(double (*a)[DPAD], const double* xd) {
 }
 
 __global__ __launch_bounds__(256, 1) void potrf_diag_kernel(const PotrfJob* __restrict__ jobs) {
+  __builtin_amdgcn_s_setprio(2);  // on the factorisation's critical chain: issue ahead of co-resident waves
   const PotrfJob J = jobs[blockIdx.x];
   NU_GLOBAL double* __restrict__ L = (NU_GLOBAL double*)J.L;
   NU_GLOBAL double* __restrict__ X = (NU_GLOBAL double*)J.X;

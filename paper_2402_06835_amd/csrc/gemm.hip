@@ -198,6 +198,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(const GemmProblem* __restr
   int tm, tn;
   tile_of<BM>(P, tile - P.tile_begin, tm, tn);
   const int m0 = tm * BM, n0 = tn * BN;
+  if (P.flags & G_PRIO) __builtin_amdgcn_s_setprio(2);
   int kb = 0, ke = P.K;
   if (P.flags & G_A_LOWER) ke = min(ke, m0 + BM);
   if (P.flags & G_B_LOWER) kb = max(kb, n0);

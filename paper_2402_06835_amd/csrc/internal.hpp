@@ -57,7 +57,8 @@ enum GemmFlags : int {
   G_B_LOWER = 4,        // op(B) lower triangular: k >= n0
   G_B_UPPER = 8,        // op(B) upper triangular: k < n0 + TB
   G_C_LOWER_TILES = 16,  // only tiles with row block >= column block (square tiles)
-  G_C_IS_A = 32          // C overwrites A's rows: every tile must span all N columns
+  G_C_IS_A = 32,         // C overwrites A's rows: every tile must span all N columns
+  G_PRIO = 64            // the tile's waves take issue priority over other kernels' waves on their CU
 };
 
 struct GemmProblem {

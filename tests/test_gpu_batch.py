@@ -135,6 +135,22 @@ def test_batch_waves_under_a_small_budget(api, ctx):
         np.testing.assert_array_equal(one[k].cpu().numpy(), many[k].cpu().numpy(), err_msg=k)
 
 
+def test_batch_arena_kept_across_budgets(api, ctx):
+    """Budgets that grow a little from call to call: a later call may plan its waves within the arena the
+    context already holds instead of growing it; every call's outputs equal the single-wave call's."""
+    import torch
+    ws = _curves()
+    say("batch under growing budgets on one context")
+    one = api.search_batch(ctx, [_as_batch_input(w) for w in ws], DURS, PERIODS, precision="fp64")
+    ctx.release_memory()
+    for budget in ((20 << 20), (21 << 20), (23 << 20), (26 << 20), (30 << 20)):
+        got = api.search_batch(ctx, [_as_batch_input(w) for w in ws], DURS, PERIODS, precision="fp64",
+                               memory_budget=budget)
+        torch.cuda.synchronize()
+        for k in CELL_KEYS + PERIOD_KEYS + ("null", "best_index"):
+            np.testing.assert_array_equal(one[k].cpu().numpy(), got[k].cpu().numpy(), err_msg=f"{k} {budget}")
+
+
 def test_batch_budget_too_small_is_oom(api, ctx):
     from paper_2402_06835_amd._lib import NU_ERR_OOM, NuanceError
     ws = _curves()[:2]
