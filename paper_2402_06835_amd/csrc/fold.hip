@@ -331,7 +331,10 @@ __device__ __forceinline__ void fold_period_block(const double2* __restrict__ DV
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid < 4) wave_best[tid] = -INFINITY;
   __syncthreads();
-  volatile double* wb = wave_best;
+  // the waves' best values are read and written as relaxed workgroup-scope
+  // atomics on the LDS array: plain ds operations (a volatile generic pointer
+  // made each read a serialised flat access)
+  auto wb_get = [&](int w) { return __hip_atomic_load(&wave_best[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
   const double P = periods[ip];
   const double p = P / dt;
   Best best{-INFINITY, -1, 0.0, 0.0};
@@ -343,7 +346,7 @@ __device__ __forceinline__ void fold_period_block(const double2* __restrict__ DV
     for (int64_t mb = (int64_t)wave * WPH; mb < nph; mb += 4 * WPH)
       for (int j0 = 0; j0 < n_d; j0 += JG) {
         // read without synchronisation: a stale value only prunes less
-        const double thr = fmax(fmax(wb[0], wb[1]), fmax(wb[2], wb[3]));
+        const double thr = fmax(fmax(wb_get(0), wb_get(1)), fmax(wb_get(2), wb_get(3)));
         const double before = best.val;
         fold_cells<JG, SEG>(DV, Lp, n_d, n_t, ld, S, j0, mb, lane, nph, p, sign, thr, best);
         // the wave's best, published for the other waves' skipping, only when
@@ -352,7 +355,8 @@ __device__ __forceinline__ void fold_period_block(const double2* __restrict__ DV
           double v = best.flat >= 0 ? best.val : -INFINITY;
 #pragma unroll
           for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-          if (lane == 0 && v > wb[wave]) wb[wave] = v;
+          if (lane == 0 && v > wb_get(wave))
+            __hip_atomic_store(&wave_best[wave], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
   }
