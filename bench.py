@@ -555,8 +555,9 @@ def bench_curve(args, api, ctx, torch):
 
 def bench_extras(args, api, ctx, torch):
     """Beside the headline curve: the uneven 64-curve batch, FP32_REFINE against FP64, each one captured
-    batch graph per step (seconds per batch, curves/s, fits/s, and the FP32_REFINE errors against the FP64
-    batch over every cell); and the 1440-sample curve in FP64 with its per-stage microseconds."""
+    batch graph per step and one eager batch call per step (seconds per batch, curves/s, fits/s, the
+    per-kernel time and dominant-kernel roofline of one timed eager call, and the FP32_REFINE errors against
+    the FP64 batch over every cell); and the 1440-sample curve in FP64 with its per-stage microseconds."""
     import numpy as np
 
     from synth import config1, config3
@@ -588,17 +589,29 @@ def bench_extras(args, api, ctx, torch):
         log(f"extras: batch-64 {prec}: {el:.3f} s per batch, {n_valid / el:.4g} fits/s")
         g.close()
         del g
-        if prec == "fp32_refine":
-            # the same batch through the eager batch call (one wait at its end)
+        # the same batch through the eager batch call (one wait at its end)
+        api.search_batch(ctx, batch, durs, per, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
             api.search_batch(ctx, batch, durs, per, precision=prec)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                api.search_batch(ctx, batch, durs, per, precision=prec)
-            torch.cuda.synchronize()
-            out[prec]["eager_call_s_per_batch"] = (time.perf_counter() - t0) / steps
-            log(f"extras: batch-64 {prec}, eager call: {out[prec]['eager_call_s_per_batch']:.3f} s per batch")
-            ctx.release_memory()  # the eager call's arena, before the next graph takes its own
+        torch.cuda.synchronize()
+        out[prec]["eager_call_s_per_batch"] = (time.perf_counter() - t0) / steps
+        log(f"extras: batch-64 {prec}, eager call: {out[prec]['eager_call_s_per_batch']:.3f} s per batch")
+        # one more eager call with every launch timed (HIP events on the launch streams): the batch's
+        # per-kernel time and the roofline of its dominant kernel (durations overlapped, as in the headline)
+        ctx.enable_timing(True)
+        ctx.reset_timing()
+        api.search_batch(ctx, batch, durs, per, precision=prec)
+        torch.cuda.synchronize()
+        tm = ctx.timings()
+        ctx.enable_timing(False)
+        roof, _ = roofline_of(tm)
+        out[prec]["roofline"] = {k: roof[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac",
+                                                      "launches", "avg_launch_ms")}
+        out[prec]["kernels_ms_per_batch"] = {k: v["ms"] for k, v in sorted(tm.items(), key=lambda kv: -kv[1]["ms"])
+                                             if not k.startswith("host:")}
+        ctx.release_memory()  # the eager call's arena, before the next graph takes its own
     out["errors_fp32_refine_vs_fp64"] = output_errors(res["fp32_refine"], res["fp64"])
     out["fp32_refine_speedup_vs_fp64"] = out["fp64"]["s_per_batch"] / out["fp32_refine"]["s_per_batch"]
     del res, batch
