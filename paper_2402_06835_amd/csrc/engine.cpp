@@ -206,7 +206,10 @@ void plan_cholesky(const std::vector<nu_factor*>& Fs, const Tuning& tu, Plan& P)
 //
 // T layout: the path nodes' T first (each survives from its first product to
 // its second), then the other nodes, one level at a time (the nodes of a level
-// side by side). Without a split the root alone takes the first place.
+// side by side). With a split the early phases run at the same time on two
+// streams, so each early phase has a region of its own for its other nodes;
+// the last phase, which follows them all, reuses the first. Without a split
+// the root alone takes the first place.
 namespace {
 size_t node_elems(const Node& nd) { return (size_t)(nd.mid - nd.a) * TB * (size_t)(nd.b - nd.mid) * TB; }
 constexpr int SPLIT_DEPTH = 2;
@@ -228,6 +231,43 @@ std::vector<Node> split_path(const std::vector<std::vector<Node>>& levels) {
     if (!found) break;
   }
   return path;
+}
+
+bool on_path(const Node& nd, const std::vector<Node>& path) {
+  for (const Node& p : path)
+    if (p.a == nd.a && p.b == nd.b) return true;
+  return false;
+}
+
+// phase of a node off the split path: the first path node whose leading half
+// holds it, else the last phase
+int node_phase(const Node& nd, const std::vector<Node>& path) {
+  for (int k = 0; k < (int)path.size(); ++k)
+    if (nd.b <= path[k].mid) return k;
+  return (int)path.size();
+}
+
+// the split layout of T: base[k] = the start of phase k's region (k = 0..D);
+// returns the elements it takes
+size_t split_t_layout(const std::vector<std::vector<Node>>& levels, const std::vector<Node>& path,
+                      std::vector<size_t>& base) {
+  const int D = (int)path.size();
+  size_t fixed = 0;
+  for (const Node& nd : path) fixed += node_elems(nd);
+  std::vector<size_t> need(D + 1, 0);  // per phase: the widest level of its other nodes
+  for (const auto& lev : levels) {
+    std::vector<size_t> s(D + 1, 0);
+    for (const Node& nd : lev)
+      if (!on_path(nd, path)) s[node_phase(nd, path)] += node_elems(nd);
+    for (int k = 0; k <= D; ++k) need[k] = std::max(need[k], s[k]);
+  }
+  base.assign(D + 1, fixed);
+  size_t end = fixed + std::max(need[0], need[D]);
+  for (int k = 1; k < D; ++k) {
+    base[k] = end;
+    end += need[k];
+  }
+  return end;
 }
 }  // namespace
 
@@ -272,9 +312,11 @@ void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu,
     }
     P.cuts.push_back(F->nblk);
     P.phases.assign(D + 1, {});
+    std::vector<size_t> base;
+    split_t_layout(levels, path, base);
     for (size_t e = 0; e < levels.size(); ++e) {
       std::vector<std::vector<GemmProblem>> p1(D + 1), p2(D + 1);
-      size_t off_t = shared;
+      std::vector<size_t> off_t = base;  // each phase's nodes of this level side by side in its region
       for (const Node& nd : levels[e]) {
         int pk = -1;
         for (int k = 0; k < D; ++k)
@@ -286,14 +328,9 @@ void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu,
           p2[D].insert(p2[D].end(), t2.begin(), t2.end());
           continue;
         }
-        int ph = D;
-        for (int k = 0; k < D; ++k)
-          if (nd.b <= path[k].mid) {
-            ph = k;
-            break;
-          }
-        node_probs(F, nd, off_t, p1[ph], p2[ph]);
-        off_t += node_elems(nd);
+        const int ph = node_phase(nd, path);
+        node_probs(F, nd, off_t[ph], p1[ph], p2[ph]);
+        off_t[ph] += node_elems(nd);
       }
       for (int ph = 0; ph <= D; ++ph) {
         if (!p1[ph].empty()) P.phases[ph].push_back(add_launch(P.sched, p1[ph], tu.small_below[cls]));
@@ -319,28 +356,18 @@ void plan_inverse(const std::vector<nu_factor*>& Fs, int kind, const Tuning& tu,
 }
 
 // room for either layout: the root, then the widest other level; or the split
-// path's nodes, then the widest level of the other nodes
+// layout (the path's nodes, then a region per early phase)
 size_t inverse_t_elems(int nblk) {
   const auto levels = inverse_levels(nblk);
   if (levels.empty()) return 1;
-  const std::vector<Node> path = split_path(levels);
-  auto on_path = [&](const Node& nd) {
-    for (const Node& p : path)
-      if (p.a == nd.a && p.b == nd.b) return true;
-    return false;
-  };
-  size_t fixed = 0, other = 0, other_split = 0;
-  for (const Node& nd : path) fixed += node_elems(nd);
-  for (size_t e = 0; e < levels.size(); ++e) {
-    size_t s = 0, s_split = 0;
-    for (const Node& nd : levels[e]) {
-      if (e + 1 < levels.size()) s += node_elems(nd);
-      if (!on_path(nd)) s_split += node_elems(nd);
-    }
+  size_t other = 0;
+  for (size_t e = 0; e + 1 < levels.size(); ++e) {
+    size_t s = 0;
+    for (const Node& nd : levels[e]) s += node_elems(nd);
     other = std::max(other, s);
-    other_split = std::max(other_split, s_split);
   }
-  return std::max(node_elems(levels.back()[0]) + other, fixed + other_split);
+  std::vector<size_t> base;
+  return std::max(node_elems(levels.back()[0]) + other, split_t_layout(levels, split_path(levels), base));
 }
 
 // One Newton step X1 = 2 X - X (L X) on the blocks within w of the
@@ -582,7 +609,8 @@ nu_status ensure_factor_streams(nu_ctx* ctx) {
   if (st == NU_OK)
     st = check_hip(ctx, hipExtStreamCreateWithCUMask(&ctx->s_rest, (uint32_t)mask.size(), mask.data()),
                    "trailing-update stream");
-  hipEvent_t* evs[] = {&ctx->ev_fork, &ctx->ev_pan, &ctx->ev_rest, &ctx->ev_join, &ctx->ev_split, &ctx->ev_inv};
+  hipEvent_t* evs[] = {&ctx->ev_fork, &ctx->ev_pan,   &ctx->ev_rest,   &ctx->ev_join,
+                       &ctx->ev_split, &ctx->ev_inv[0], &ctx->ev_inv[1]};
   for (hipEvent_t* e : evs)
     if (st == NU_OK) st = check_hip(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming), "step-loop event");
   if (st != NU_OK) destroy_factor_streams(ctx);
@@ -593,11 +621,11 @@ nu_status ensure_factor_streams(nu_ctx* ctx) {
 // [32 x, 32 x + 32) are XCD x).
 constexpr int XCD_CUS = 32;
 
-// The early inverse's stream on the top `compute_units` CUs (0: three
-// quarters of the chip, the fastest split on the TESS-sector curve), rounded
-// to whole XCDs (at least one, at most all but one): an inverse spread over
-// part of every XCD slows the factorisation's kernels more than one on XCDs
-// of its own. Recreated when the count changes.
+// The early inverse's streams: the first on the top `compute_units` CUs (0:
+// three quarters of the chip, the fastest split on the TESS-sector curve),
+// rounded to whole XCDs (at least one, at most all but one): an inverse spread
+// over part of every XCD slows the factorisation's kernels more than one on
+// XCDs of its own. Recreated when the count changes.
 nu_status ensure_inverse_stream(nu_ctx* ctx, int compute_units) {
   int ncu = 0;
   nu_status st =
@@ -606,17 +634,26 @@ nu_status ensure_inverse_stream(nu_ctx* ctx, int compute_units) {
   if (ncu < 2 * XCD_CUS || ncu % XCD_CUS != 0) return NU_OK;  // no split: the inverse runs after the factorisation
   int c = compute_units > 0 ? compute_units : ncu / 4 * 3;
   c = std::max(XCD_CUS, std::min(ncu - XCD_CUS, (c + XCD_CUS / 2) / XCD_CUS * XCD_CUS));
-  if (ctx->s_inv && ctx->s_inv_cus == c) return NU_OK;
-  if (ctx->s_inv) {
-    (void)hipStreamSynchronize(ctx->s_inv);
-    (void)hipStreamDestroy(ctx->s_inv);
-    ctx->s_inv = nullptr;
-  }
+  if (ctx->s_inv[0] && ctx->s_inv[1] && ctx->s_inv_cus == c) return NU_OK;
+  for (hipStream_t& si : ctx->s_inv)
+    if (si) {
+      (void)hipStreamSynchronize(si);
+      (void)hipStreamDestroy(si);
+      si = nullptr;
+    }
   ctx->s_inv_cus = 0;
-  std::vector<uint32_t> mask((size_t)(ncu + 31) / 32, 0u);
-  for (int u = ncu - c; u < ncu; ++u) mask[(size_t)u / 32] |= 1u << (u % 32);
-  st = check_hip(ctx, hipExtStreamCreateWithCUMask(&ctx->s_inv, (uint32_t)mask.size(), mask.data()),
-                 "early-inverse stream");
+  // the first stream (phase 0, whose products are the largest) on the top c
+  // CUs; the second (phase 1, released late, small products) on every CU but
+  // the ones the lookahead keeps free for the diagonal blocks, so that it also
+  // uses what the chain of the last steps leaves idle on the other XCDs
+  std::vector<uint32_t> mask0((size_t)(ncu + 31) / 32, 0u), mask1(mask0);
+  for (int u = ncu - c; u < ncu; ++u) mask0[(size_t)u / 32] |= 1u << (u % 32);
+  for (int u = LOOKAHEAD_FREE_CUS; u < ncu; ++u) mask1[(size_t)u / 32] |= 1u << (u % 32);
+  for (int i = 0; i < 2 && st == NU_OK; ++i) {
+    std::vector<uint32_t>& m = i == 0 ? mask0 : mask1;
+    st = check_hip(ctx, hipExtStreamCreateWithCUMask(&ctx->s_inv[i], (uint32_t)m.size(), m.data()),
+                   "early-inverse stream");
+  }
   if (st == NU_OK) ctx->s_inv_cus = c;
   return st;
 }
@@ -624,8 +661,10 @@ nu_status ensure_inverse_stream(nu_ctx* ctx, int compute_units) {
 void destroy_factor_streams(nu_ctx* ctx) {
   if (ctx->s_fac) (void)hipStreamSynchronize(ctx->s_fac);
   if (ctx->s_rest) (void)hipStreamSynchronize(ctx->s_rest);
-  if (ctx->s_inv) (void)hipStreamSynchronize(ctx->s_inv);
-  hipEvent_t* evs[] = {&ctx->ev_fork, &ctx->ev_pan, &ctx->ev_rest, &ctx->ev_join, &ctx->ev_split, &ctx->ev_inv};
+  for (hipStream_t si : ctx->s_inv)
+    if (si) (void)hipStreamSynchronize(si);
+  hipEvent_t* evs[] = {&ctx->ev_fork, &ctx->ev_pan,   &ctx->ev_rest,   &ctx->ev_join,
+                       &ctx->ev_split, &ctx->ev_inv[0], &ctx->ev_inv[1]};
   for (hipEvent_t* e : evs)
     if (*e) {
       (void)hipEventDestroy(*e);
@@ -633,8 +672,10 @@ void destroy_factor_streams(nu_ctx* ctx) {
     }
   if (ctx->s_fac) (void)hipStreamDestroy(ctx->s_fac);
   if (ctx->s_rest) (void)hipStreamDestroy(ctx->s_rest);
-  if (ctx->s_inv) (void)hipStreamDestroy(ctx->s_inv);
-  ctx->s_inv = nullptr;
+  for (hipStream_t& si : ctx->s_inv) {
+    if (si) (void)hipStreamDestroy(si);
+    si = nullptr;
+  }
   ctx->s_inv_cus = 0;
   ctx->s_fac = ctx->s_rest = nullptr;
 }
@@ -688,8 +729,8 @@ nu_status run_factor_steps(nu_ctx* ctx, const Plan& P, const EarlyInverse* early
   //
   // Early inverse (early != nullptr, lookahead only): once step cuts[k] - 1
   // has factored its panel, the columns left of cuts[k] are final, and phase
-  // k of the split reduced-precision inverse runs on s_inv (part of the chip,
-  // see ensure_inverse_stream) beside the remaining steps, which from the
+  // k of the split reduced-precision inverse runs on s_inv[k % 2] (part of the
+  // chip, see ensure_inverse_stream) beside the remaining steps, which from the
   // middle on are bound by the chain of diagonal blocks and leave most of the
   // chip idle. The phases write only the factor's FP32 copies and T, which no
   // step reads. The join waits for them; the caller then enqueues the rest.
@@ -707,11 +748,11 @@ nu_status run_factor_steps(nu_ctx* ctx, const Plan& P, const EarlyInverse* early
     if (st == NU_OK) st = check_hip(ctx, hipStreamWaitEvent(ctx->s_fac, ctx->ev_fork, 0), "fork");
     sf = ctx->s_fac;
   }
-  bool rest_pending = false, inv_pending = false;
+  bool rest_pending = false, inv_pending[2] = {false, false};
   const int steps = (int)P.job_first.size();
   // the early phases of the inverse and the steps that release them
-  const bool early_ok = la && early && ctx->s_inv && early->F->plan32.built && early->F->plan32_prec == early->prec &&
-                        early->F->plan32.phases.size() >= 2;
+  const bool early_ok = la && early && ctx->s_inv[0] && ctx->s_inv[1] && early->F->plan32.built &&
+                        early->F->plan32_prec == early->prec && early->F->plan32.phases.size() >= 2;
   const int early_phases = early_ok ? (int)early->F->plan32.phases.size() - 1 : 0;
   int next_phase = 0;
   if (early) early->started = 0;
@@ -723,12 +764,16 @@ nu_status run_factor_steps(nu_ctx* ctx, const Plan& P, const EarlyInverse* early
     if (st == NU_OK) st = launch_range(ctx, P, P.panel[k], "gemm_f64:panel", GK_F64, sf);
     if (st == NU_OK) st = launch_range(ctx, P, P.pupd[k], "gemm_f64:panel_update", GK_F64, sf);
     while (st == NU_OK && next_phase < early_phases && k == early->F->plan32.cuts[next_phase] - 1) {
+      // the phases share no buffer (each has its own T region), so phase k
+      // does not wait for phase k - 1
+      const int si = next_phase % 2;
       st = check_hip(ctx, hipEventRecord(ctx->ev_split, sf), "early inverse");
-      if (st == NU_OK) st = check_hip(ctx, hipStreamWaitEvent(ctx->s_inv, ctx->ev_split, 0), "early inverse");
-      if (st == NU_OK) st = run_inverse_phase(ctx, early->F, early->F->plan32, early->prec, next_phase, ctx->s_inv);
-      if (st == NU_OK) st = check_hip(ctx, hipEventRecord(ctx->ev_inv, ctx->s_inv), "early inverse");
+      if (st == NU_OK) st = check_hip(ctx, hipStreamWaitEvent(ctx->s_inv[si], ctx->ev_split, 0), "early inverse");
+      if (st == NU_OK)
+        st = run_inverse_phase(ctx, early->F, early->F->plan32, early->prec, next_phase, ctx->s_inv[si]);
+      if (st == NU_OK) st = check_hip(ctx, hipEventRecord(ctx->ev_inv[si], ctx->s_inv[si]), "early inverse");
       if (st == NU_OK) {
-        inv_pending = true;
+        inv_pending[si] = true;
         early->started = ++next_phase;
       }
     }
@@ -754,7 +799,8 @@ nu_status run_factor_steps(nu_ctx* ctx, const Plan& P, const EarlyInverse* early
     if (rest_pending) sj = check_hip(ctx, hipStreamWaitEvent(sf, ctx->ev_rest, 0), "join");
     if (sj == NU_OK) sj = check_hip(ctx, hipEventRecord(ctx->ev_join, sf), "join");
     if (sj == NU_OK) sj = check_hip(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "join");
-    if (sj == NU_OK && inv_pending) sj = check_hip(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_inv, 0), "join");
+    for (int si = 0; si < 2; ++si)
+      if (sj == NU_OK && inv_pending[si]) sj = check_hip(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_inv[si], 0), "join");
     if (st == NU_OK) st = sj;
   }
   if (early && st != NU_OK) early->started = 0;

@@ -180,12 +180,14 @@ struct nu_ctx {
   hipStream_t s_fold = nullptr;
   hipEvent_t ev_fork = nullptr, ev_pan = nullptr, ev_rest = nullptr, ev_join = nullptr;
   bool lookahead = true;
-  // early inverse of a factorisation: its stream (on the top s_inv_cus CUs),
-  // the event that releases it and the event of its end; the precision it is
+  // early inverse of a factorisation: its streams (both on the top s_inv_cus
+  // CUs; early phases alternate between them, so a phase released late does
+  // not queue behind an earlier phase's products), the event that releases a
+  // phase and the event of each stream's last phase; the precision it is
   // started for (-1: none) and the CUs asked for (0: three quarters)
-  hipStream_t s_inv = nullptr;
+  hipStream_t s_inv[2] = {nullptr, nullptr};
   int s_inv_cus = 0;
-  hipEvent_t ev_split = nullptr, ev_inv = nullptr;
+  hipEvent_t ev_split = nullptr, ev_inv[2] = {nullptr, nullptr};
   int prefetch_prec = -1, prefetch_cus = 0;
   // pinned host staging of small host-to-device uploads (template shapes); the
   // event marks the last copy out of it

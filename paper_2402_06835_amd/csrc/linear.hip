@@ -270,9 +270,15 @@ hipError_t launch_null_solve(hipStream_t s, double* Y, int64_t n, int m1, const 
 // out[m] = base[m] + alpha * sum_{n >= m} M[n][m] W[n]   (nv columns,
 // row-major, lower-triangular M). Workgroup = 256 columns x a chunk of rows;
 // partials per chunk, then a fixed-order reduction. out may alias base.
-__device__ __forceinline__ void cols_partial_block(const double* __restrict__ M, int64_t ldm, int64_t n, int64_t np,
-                                                   const double* __restrict__ W, int nv, int rowchunk,
+// The operands are read through global-address-space views: a batch passes
+// pointers read from its job records, generic to the compiler, and the row of
+// W shared by a wave then came in by per-lane flat loads instead of scalar
+// loads.
+__device__ __forceinline__ void cols_partial_block(const double* __restrict__ M_, int64_t ldm, int64_t n, int64_t np,
+                                                   const double* __restrict__ W_, int nv, int rowchunk,
                                                    double* __restrict__ partial, int bx, int chunk) {
+  const NU_GLOBAL double* __restrict__ M = (const NU_GLOBAL double*)M_;
+  const NU_GLOBAL double* __restrict__ W = (const NU_GLOBAL double*)W_;
   const int64_t m = (int64_t)bx * 256 + threadIdx.x;
   if (m >= np) return;
   const int64_t r0 = (int64_t)chunk * rowchunk;
@@ -290,7 +296,7 @@ __device__ __forceinline__ void cols_partial_block(const double* __restrict__ M,
       for (int u = 0; u < 8; ++u) x[u] = (m <= r + u) ? M[(r + u) * ldm + m] : 0.0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const double* wr = W + (r + u) * YCOLS;
+        const NU_GLOBAL double* wr = W + (r + u) * YCOLS;
 #pragma unroll
         for (int c = 0; c < YCOLS; ++c)
           if (c < nv) acc[c] = fma(x[u], wr[c], acc[c]);
@@ -298,13 +304,13 @@ __device__ __forceinline__ void cols_partial_block(const double* __restrict__ M,
     }
     for (; r < r1; ++r) {
       const double x = (m <= r) ? M[r * ldm + m] : 0.0;
-      const double* wr = W + r * YCOLS;
+      const NU_GLOBAL double* wr = W + r * YCOLS;
 #pragma unroll
       for (int c = 0; c < YCOLS; ++c)
         if (c < nv) acc[c] = fma(x, wr[c], acc[c]);
     }
   }
-  double* o = partial + ((int64_t)chunk * np + m) * YCOLS;
+  NU_GLOBAL double* o = (NU_GLOBAL double*)partial + ((int64_t)chunk * np + m) * YCOLS;
 #pragma unroll
   for (int c = 0; c < YCOLS; ++c) o[c] = acc[c];
 }
@@ -433,8 +439,10 @@ __device__ __forceinline__ void q_partial_block(const double* __restrict__ X, in
     if (lane == 0) P0[0] = P1[0] = 0.0;
     const int64_t m0 = seg_lo + lane * RUN;  // this lane's first column
     // row r restricted to the segment; rows at or past r1 read as 0
+    // global loads (a batch's X is a generic pointer read from its job record,
+    // and flat loads would also hold up the waits for the LDS prefix)
     auto load_row = [&](int64_t r, double (&v)[RUN]) {
-      const double* x = X + r * ldx;
+      const NU_GLOBAL double* x = (const NU_GLOBAL double*)X + r * ldx;
 #pragma unroll
       for (int e = 0; e < RUN; ++e) {
         const int64_t m = m0 + e;
