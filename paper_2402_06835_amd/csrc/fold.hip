@@ -292,10 +292,17 @@ __device__ __forceinline__ void fold_cells(const double2* __restrict__ DV, const
       b += (int)delta;
     }
     const int idx = lane + b;
+    // every group's slots, needed or not: conditional loads made the compiler
+    // wait for each one before issuing the next
     double2 dv[JG];
 #pragma unroll
-    for (int g = 0; g < JG; ++g)
-      if (need[g]) dv[g] = SEG ? dvr[g][idx] : row_at(dvr[g], idx);
+    for (int g = 0; g < JG; ++g) {
+      if constexpr (SEG) {
+        dv[g] = dvr[g][idx];
+      } else {
+        dv[g] = row_at(dvr[g], idx);
+      }
+    }
     event2(dv, kp - base);
   }
 #pragma unroll
