@@ -643,12 +643,14 @@ nu_status ensure_inverse_stream(nu_ctx* ctx, int compute_units) {
     }
   ctx->s_inv_cus = 0;
   // the first stream (phase 0, whose products are the largest) on the top c
-  // CUs; the second (phase 1, released late, small products) on every CU but
-  // the ones the lookahead keeps free for the diagonal blocks, so that it also
-  // uses what the chain of the last steps leaves idle on the other XCDs
+  // CUs; the second (phase 1, released late, small products) on every XCD but
+  // the first, so that it also uses what the chain of the last steps leaves
+  // idle there. A dispatch of one workgroup (a diagonal block) always starts
+  // on the first XCD (workgroup i of a dispatch goes to XCD i mod 8, measured
+  // with the XCC_ID register), which the second stream leaves to the chain.
   std::vector<uint32_t> mask0((size_t)(ncu + 31) / 32, 0u), mask1(mask0);
   for (int u = ncu - c; u < ncu; ++u) mask0[(size_t)u / 32] |= 1u << (u % 32);
-  for (int u = LOOKAHEAD_FREE_CUS; u < ncu; ++u) mask1[(size_t)u / 32] |= 1u << (u % 32);
+  for (int u = XCD_CUS; u < ncu; ++u) mask1[(size_t)u / 32] |= 1u << (u % 32);
   for (int i = 0; i < 2 && st == NU_OK; ++i) {
     std::vector<uint32_t>& m = i == 0 ? mask0 : mask1;
     st = check_hip(ctx, hipExtStreamCreateWithCUMask(&ctx->s_inv[i], (uint32_t)m.size(), m.data()),
